@@ -1,0 +1,313 @@
+#!/usr/bin/env python3
+"""Benchmark of the heterodyned MBHB likelihood on one MI355X.
+
+Workload (one step): heterodyned lnL of 8 sources x (8 temperatures x 64
+walkers) = 4096 walkers against their references, (2,2) IMR-lite + LISA TDI
+A/E/T, 1 yr at dt = 10 s (1 577 880 Fourier bins, 3 channels), 128 bins,
+SNR log-uniform in [100, 1000], seeded synthetic noise; evaluated as one
+persistent graph-captured launch (mbh_batch).  The timed value is the
+mixed-precision path; the plain-FP64 path is timed the same way and reported
+beside it, together with the largest |dlnL| between the two.
+
+Also measured (not part of the step): the full-grid likelihood on a prior-draw
+sweep, the reference build, a higher-mode ragged 16-source batch, and a
+Poisson request stream through the continuous-batching server (p50/p99).
+The CPU baseline is the FP64 oracle timed on a bounded sample on the host.
+
+Prints ONE JSON line on stdout.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import threading
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2111_01064_amd import inputs as I  # noqa: E402
+
+METRIC = "heterodyned lnL evals/s (mixed vs FP64, |ΔlnL|≤1e-3); p50/p99 request latency"
+PEAK_ALU_TFLOPS = 78.6   # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, unpacked FP32 and FP64 alike
+PEAK_HBM_GBS = 8000.0
+N_SOURCES, TEMPS, PER_TEMP, N_BINS = 8, tuple(2.0 ** k for k in range(8)), 64, 128
+# algorithmic flop count per (walker, edge) of the heterodyned step with one
+# mode and three channels, and per (walker, frequency) of the full grid; the
+# itemisation is in the design notes (transcendentals count 1, FMA 2)
+FLOPS_PER_EDGE = 711.0
+FLOPS_PER_BIN = 81.0
+FLOPS_PER_FULL_POINT = 720.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+class Sources:
+    """Synthetic LISA sources built through the library (no oracle)."""
+
+    def __init__(self, M, ctx, grid, n_sources, modes_list=None, n_bins_list=None, snr_cap=None, cfg=2):
+        import torch
+
+        self.M, self.ctx, self.grid = M, ctx, grid
+        f = grid.freqs
+        self.psd = torch.as_tensor(I.psd_lisa_aet(f), device="cuda")
+        zeros = torch.zeros((3, grid.n_f), dtype=torch.complex128, device="cuda")
+        grid_data = M.data_create(ctx, zeros, self.psd, grid.f0, grid.df, grid.t_obs)
+        self.items = []
+        for s in range(n_sources):
+            rng = I.rng_for(cfg, s)
+            th, snr = I.draw_mbhb_source(rng, grid.t_obs)
+            if snr_cap:
+                snr = min(snr, snr_cap)
+            modes = modes_list[s] if modes_list else M.MODE_22
+            nb = n_bins_list[s] if n_bins_list else N_BINS
+            h = M.template_full(ctx, grid_data, M.MODEL_IMR, modes, th)
+            # <h|h> at D_L = 1 Gpc through the library's own full-grid kernel
+            dsig = M.data_create(ctx, h, self.psd, grid.f0, grid.df, grid.t_obs)
+            dh = torch.empty((1, 2), dtype=torch.float64, device="cuda")
+            M.loglike_full(ctx, dsig, M.MODEL_IMR, modes, torch.as_tensor(th[None, :], device="cuda"), M.FP64,
+                           dh_hh=dh)
+            hh1 = float(dh[0, 1])
+            dsig.close()
+            th[4] = I.distance_for_snr(hh1, snr)
+            noise = torch.as_tensor(I.noise(I.psd_lisa_aet(f), grid.df, rng), device="cuda")
+            d = h * (1.0 / th[4]) + noise
+            del h, noise
+            data = M.data_create(ctx, d, self.psd, grid.f0, grid.df, grid.t_obs)
+            ref = M.build_reference_coeffs(ctx, data, M.MODEL_IMR, modes, th, nb)
+            self.items.append(dict(th=th, snr=snr, data=data, ref=ref, modes=modes, nb=nb, rng=rng, d=d))
+        grid_data.close()
+
+    def walkers(self, item, temps, per_temp):
+        import torch
+
+        M, ctx = self.M, self.ctx
+
+        def het(x):
+            return M.loglike_heterodyned(ctx, item["ref"], torch.as_tensor(x, device="cuda"), M.FP64).cpu().numpy()
+
+        sig = I.curvature_sigma(het, item["th"])
+        w = I.walker_cloud(item["th"], sig, temps, per_temp, item["rng"])
+        return w
+
+
+def time_batch(M, ctx, batch, steps, warmup, stream):
+    import torch
+
+    for _ in range(warmup):
+        batch.launch(stream)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        for a, b in ev:
+            a.record(stream)
+            batch.launch(stream)
+            b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = [a.elapsed_time(b) * 1e-3 for a, b in ev]
+    return wall, float(np.mean(per)), per
+
+
+def cpu_baseline(budget_s: float = 15.0):
+    """The FP64 oracle (OpenMP over walkers) on one source of the same
+    workload: its own data, reference and walker cloud, timed on the host."""
+    import oracle as O
+
+    g = I.grid_lisa()
+    rng = I.rng_for(2, 0)
+    th, snr = I.draw_mbhb_source(rng, g.t_obs)
+    f = g.freqs
+    psd = I.psd_lisa_aet(f)
+    t0 = time.perf_counter()
+    h = O.template(O.MODEL_IMR, O.MODE_22, th, f, g.t_obs)
+    th[4] = I.distance_for_snr(O.inner(h, h, psd, g.df), snr)
+    d = h / th[4] + I.noise(psd, g.df, rng)
+    data = O.Data(d, psd, g.f0, g.df, g.t_obs)
+    ref = O.Reference(O.MODEL_IMR, O.MODE_22, th, data, N_BINS)
+    sig = I.curvature_sigma(lambda x: ref.loglike(x)[0], th)
+    w = I.walker_cloud(th, sig, TEMPS, PER_TEMP, rng)
+    setup_s = time.perf_counter() - t0
+    n_done, t_start = 0, time.perf_counter()
+    while time.perf_counter() - t_start < budget_s:
+        ref.loglike(w)
+        n_done += len(w)
+    el = time.perf_counter() - t_start
+    # one full-grid evaluation for the per-evaluation cost of the direct likelihood
+    t1 = time.perf_counter()
+    O.loglike_full(O.MODEL_IMR, O.MODE_22, w[: O.max_threads()], data)
+    full_s = (time.perf_counter() - t1) / O.max_threads()
+    return dict(value=n_done / el, unit="evals/s", cores=O.max_threads(), kind="oracle",
+                sample=f"1 source, {len(w)} walkers (8 temps x 64) x {n_done // len(w)} passes, "
+                       f"1.58e6-bin grid, 128 bins, {el:.1f} s",
+                full_grid_s_per_eval_per_core=full_s * O.max_threads(), setup_s=setup_s)
+
+
+def serve_run(M, ctx, refs, pools, prec, rate_hz, n_req, warm):
+    rng = I.rng_for(5, 1)
+    reqs = I.poisson_requests(rng, n_req + warm, rate_hz, 64, len(refs), 4096)
+    srv = M.Server(ctx, refs, max_inflight=3, max_batch_walkers=65536, hbm_budget_bytes=2 << 30, prec=prec)
+    lat = [None] * len(reqs)
+    ids = [None] * len(reqs)
+    done = threading.Event()
+
+    def collector():
+        for i in range(len(reqs)):
+            while ids[i] is None:
+                time.sleep(0.0001)
+            _, l = srv.wait(ids[i], reqs[i][3])
+            lat[i] = l
+        done.set()
+
+    th = threading.Thread(target=collector, daemon=True)
+    th.start()
+    t0 = time.perf_counter()
+    for i, (t_arr, sampler, src, W) in enumerate(reqs):
+        while time.perf_counter() - t0 < t_arr:
+            time.sleep(0.0002)
+        pool = pools[src]
+        sel = rng.integers(0, len(pool), W)
+        ids[i] = srv.submit(src, pool[sel])
+    done.wait()
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    l = np.array(lat[warm:]) * 1e3
+    walkers = sum(r[3] for r in reqs)
+    return dict(p50_ms=float(np.percentile(l, 50)), p99_ms=float(np.percentile(l, 99)),
+                throughput_evals_s=walkers / wall, requests=n_req, rate_hz=rate_hz, batches=st["batches"],
+                mean_walkers_per_batch=st["walkers"] / max(1, st["batches"]))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--quick", action="store_true", help="skip the side measurements")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: every walker batch fits one MI355X and this build has no "
+              "multi-GPU path (see the sharding notes in the design document)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2111_01064_amd import mbh as M
+
+    ctx = M.Context(0)
+    grid = I.grid_lisa()
+    t0 = time.perf_counter()
+    S = Sources(M, ctx, grid, N_SOURCES)
+    log(f"[bench] built {N_SOURCES} sources on {grid.n_f} bins in {time.perf_counter() - t0:.1f} s")
+    walkers = [S.walkers(it, TEMPS, PER_TEMP) for it in S.items]
+    thetas = [torch.as_tensor(w, device="cuda") for w in walkers]
+    W_total = sum(len(w) for w in walkers)
+    stream = torch.cuda.Stream()
+    res = {}
+    for name, prec in (("fp64", M.FP64), ("mixed", M.MIXED)):
+        for it in S.items:  # autotune lanes per walker for this shape once
+            M.autotune_heterodyned(ctx, it["ref"], W_total, prec)
+            break
+        lnls = [torch.empty(len(w), dtype=torch.float64, device="cuda") for w in walkers]
+        batch = M.Batch(ctx, [it["ref"] for it in S.items], thetas, lnls, prec=prec)
+        wall, mean_s, per = time_batch(M, ctx, batch, args.steps, args.warmup, stream)
+        res[name] = dict(wall=wall, kernel_s=mean_s, lnl=np.concatenate([l.cpu().numpy() for l in lnls]),
+                         lanes=M.lanes_for(ctx, N_BINS, 1, prec))
+        batch.close()
+        log(f"[bench] {name}: {W_total} walkers/step, {mean_s * 1e6:.1f} us/step (events), wall {wall:.3f} s, "
+            f"lanes {res[name]['lanes']}")
+    dmix = float(np.max(np.abs(res["mixed"]["lnl"] - res["fp64"]["lnl"])))
+    ms_per_step = res["mixed"]["wall"] / args.steps * 1e3
+    value = W_total * args.steps / res["mixed"]["wall"]
+    fp64_value = W_total * args.steps / res["fp64"]["wall"]
+    E = N_BINS + 1
+    flops = W_total * (E * FLOPS_PER_EDGE + N_BINS * FLOPS_PER_BIN)
+    achieved = flops / res["mixed"]["kernel_s"] / 1e12
+    out = {
+        "metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64 (mixed)", "data": "synthetic",
+        "config": {"workload": "8 sources x (8 temps x 64 walkers), (2,2) IMR-lite + TDI A/E/T, "
+                               "1 yr dt=10 s (1577880 bins x 3 ch), 128 bins, SNR 100-1000, noisy",
+                   "walkers_per_step": W_total, "n_bins": N_BINS, "launch": "mbh_batch graph replay"},
+        "fp64_evals_per_s": fp64_value, "fp64_ms_per_step": res["fp64"]["wall"] / args.steps * 1e3,
+        "mixed_speedup_vs_fp64": value / fp64_value, "max_abs_dlnL_mixed_vs_fp64": dmix,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_ALU_TFLOPS, "traffic": None,
+                     "kernel": "k_het_work<float>", "kernel_us": res["mixed"]["kernel_s"] * 1e6,
+                     "flops_per_launch": flops},
+        "paper_context": {"het_evals_per_s": 2e5, "note": "~5 us per heterodyned lnL, unnamed GPU, PhenomD"},
+    }
+    if not args.quick:
+        out.update(side_measurements(M, ctx, S, walkers, grid))
+    if not args.no_cpu:
+        log("[bench] cpu baseline (oracle) ...")
+        cb = cpu_baseline()
+        out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+        out["cpu_baseline_full_grid_s_per_eval_per_core"] = cb["full_grid_s_per_eval_per_core"]
+    print(json.dumps(out), flush=True)
+
+
+def side_measurements(M, ctx, S, walkers, grid):
+    import torch
+
+    out = {}
+    # full-grid likelihood: brute-force prior draws on the 1.58e6-bin grid
+    it = S.items[0]
+    draws = I.prior_draws(I.rng_for(3, 0), 2048, grid.t_obs)
+    td = torch.as_tensor(draws, device="cuda")
+    for name, prec in (("fp64", M.FP64), ("mixed", M.MIXED)):
+        M.loglike_full(ctx, it["data"], M.MODEL_IMR, M.MODE_22, td[:64], prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        M.loglike_full(ctx, it["data"], M.MODEL_IMR, M.MODE_22, td, prec)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[f"full_grid_{name}_evals_per_s"] = len(draws) / dt
+        log(f"[bench] full grid {name}: {len(draws) / dt:.1f} evals/s")
+    # reference build (a9)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = M.build_reference_coeffs(ctx, it["data"], M.MODEL_IMR, M.MODE_22, it["th"], N_BINS)
+    out["reference_build_ms"] = (time.perf_counter() - t0) * 1e3
+    r.close()
+    # ragged higher-mode batch: 16 sources, modes 1-6, N_b 64-512, W 128-4096
+    shapes = I.batch_shapes(I.rng_for(4, 0), 16)
+    S4 = Sources(M, ctx, grid, 16, modes_list=[s[0] for s in shapes], n_bins_list=[s[1] for s in shapes], cfg=4)
+    th4 = []
+    for item, (_, _, W) in zip(S4.items, shapes):
+        th4.append(torch.as_tensor(S4.walkers(item, (1, 4, 16, 64), (W + 3) // 4)[:W], device="cuda"))
+    for it4 in S4.items:
+        M.autotune_heterodyned(ctx, it4["ref"], len(th4[0]), M.MIXED)
+    ln4 = [torch.empty(len(t), dtype=torch.float64, device="cuda") for t in th4]
+    b4 = M.Batch(ctx, [x["ref"] for x in S4.items], th4, ln4, prec=M.MIXED)
+    st = torch.cuda.Stream()
+    wall, mean_s, _ = time_batch(M, ctx, b4, 50, 5, st)
+    W4 = sum(len(t) for t in th4)
+    out["hm_batch"] = {"sources": 16, "walkers": W4, "evals_per_s": W4 * 50 / wall, "us_per_launch": mean_s * 1e6,
+                       "shapes": [[int(m), int(nb), int(w)] for (m, nb, w) in shapes]}
+    b4.close()
+    log(f"[bench] HM batch: {W4} walkers, {W4 * 50 / wall:.3g} evals/s")
+    # serving: Poisson stream over 4 resident sources at a fraction of capacity
+    refs = [x["ref"] for x in S.items[:4]]
+    pools = walkers[:4]
+    serve = {}
+    for name, prec in (("mixed", M.MIXED), ("fp64", M.FP64)):
+        serve[name] = serve_run(M, ctx, refs, pools, prec, rate_hz=2000.0, n_req=4000, warm=400)
+        log(f"[bench] serve {name}: {serve[name]}")
+    out["serving"] = serve
+    return out
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,240 @@
+/*
+ * mbh.h -- C ABI of libmbh, the MI355X (gfx950) library for the batched
+ * heterodyned ("relative binning") and full-grid log-likelihoods of massive
+ * black hole binaries with the LISA A/E/T response (Katz 2021,
+ * arXiv:2111.01064).
+ *
+ * Conventions for every entry point:
+ *  - Return value: mbh_status, MBH_OK (0) on success, a negative code on
+ *    failure.  No entry point aborts, throws or exits; mbh_last_error()
+ *    gives a human-readable message for the calling thread's last failure.
+ *  - Pointers marked _dev are device (HBM) pointers owned by the caller,
+ *    e.g. torch.cuda tensors' data_ptr(); pointers marked _host are host
+ *    memory owned by the caller.  Everything behind an opaque handle is
+ *    owned by the library and freed by the matching *_release / destroy.
+ *  - Layouts are row-major.  Complex arrays are interleaved (re, im) FP64.
+ *  - Work is enqueued on the given stream and is asynchronous unless stated;
+ *    outputs are valid after the stream is synchronised.  Handles are
+ *    immutable after creation, so concurrent calls on different streams may
+ *    share them.
+ *  - Walker parameters theta[W][11] follow Sec. 2.1 of the paper:
+ *      {M_T [Msun], q = m2/m1, a1, a2, D_L [Gpc], phi_ref, iota,
+ *       lambda, beta, psi, t_ref [s]}  (SSB frame).
+ *    For MBH_MODEL_TF2 (single-channel 0PN chirp) the slots are
+ *      {Mc [Msun], amplitude, t_c [s], phi_c, unused...}.
+ *    A walker outside the model domain (non-finite entries, M_T <= 0,
+ *    q outside [0.05, 1], |a_i| > 0.99, D_L <= 0; Mc <= 0 for TF2) gets
+ *    lnL = -inf (never NaN) and <d|h> = <h|h> = 0; the call still succeeds.
+ */
+#ifndef MBH_H
+#define MBH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mbh_status;
+#define MBH_OK 0
+#define MBH_EINVAL (-1)   /* bad argument, shape or null pointer           */
+#define MBH_ENOMEM (-2)   /* device allocation failed or HBM budget exceeded */
+#define MBH_EBAND (-3)    /* reference template empty or zero at a bin edge  */
+#define MBH_EDEVICE (-4)  /* a HIP runtime call failed                       */
+#define MBH_EAGAIN (-5)   /* serving: request not finished / queue full      */
+#define MBH_ENOTFOUND (-6)/* serving: unknown request id                     */
+
+/* waveform models */
+#define MBH_MODEL_IMR 0   /* IMR-lite harmonics + LISA TDI A/E/T, 3 channels */
+#define MBH_MODEL_TF2 1   /* 0PN chirp, 1 channel, no response             */
+
+/* harmonic modes (bit mask, MBH_MODEL_IMR only); (2,2) is Sec. 2.1's dominant mode */
+#define MBH_MODE_22 (1u << 0)
+#define MBH_MODE_33 (1u << 1)
+#define MBH_MODE_44 (1u << 2)
+#define MBH_MODE_21 (1u << 3)
+#define MBH_MODE_32 (1u << 4)
+#define MBH_MODE_43 (1u << 5)
+#define MBH_MODES_ALL 0x3Fu
+
+typedef enum { MBH_FP64 = 0, MBH_MIXED = 1 } mbh_precision;
+
+typedef struct mbh_ctx mbh_ctx;
+typedef struct mbh_data mbh_data;
+typedef struct mbh_ref mbh_ref;
+typedef struct mbh_batch mbh_batch;
+typedef struct mbh_server mbh_server;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes caps the device
+ * memory the context's handles and scratch may hold (0 = no cap).
+ * Errors: MBH_EINVAL (bad device / null out), MBH_EDEVICE. */
+mbh_status mbh_create(int device, size_t hbm_budget_bytes, mbh_ctx **out);
+mbh_status mbh_destroy(mbh_ctx *ctx);
+
+/* Message of the calling thread's last failed call ("" if none). */
+const char *mbh_last_error(void);
+const char *mbh_strerror(mbh_status s);
+
+/* Device memory currently held by the context's handles and scratch. */
+mbh_status mbh_memory_in_use(const mbh_ctx *ctx, size_t *bytes_out);
+
+/* ------------------------------------------------------------------- data */
+
+/* Frequency-domain data d(f) and noise PSD S_n(f) of n_chan channels on the
+ * uniform grid f_k = f0 + k*df, k = 0..n_freq-1 (eq. inner of Sec. 2: the
+ * PSDs are known analytic inputs).
+ *   d_reim_dev [n_chan][n_freq][2] FP64, psd_dev [n_chan][n_freq] FP64 > 0.
+ * n_chan is 3 (A, E, T) for MBH_MODEL_IMR and 1 for MBH_MODEL_TF2.
+ * t_obs is the observation time bounding the template support.
+ * The library copies (whitened) data; the caller may free its inputs once
+ * the stream is synchronised.  Also computes <d|d>.
+ * Errors: MBH_EINVAL, MBH_ENOMEM, MBH_EDEVICE. */
+mbh_status mbh_data_create(mbh_ctx *ctx, int n_chan, int64_t n_freq, double f0, double df,
+                           double t_obs, const double *d_reim_dev, const double *psd_dev,
+                           hipStream_t stream, mbh_data **out);
+mbh_status mbh_data_release(mbh_data *data);
+/* <d|d> (synchronises the creation stream on first use). */
+mbh_status mbh_data_inner_dd(mbh_data *data, double *dd_out);
+
+/* Template h^c(f_k) of one parameter vector on the data grid (eq. response
+ * of Sec. 2.1), FP64, written to h_dev [n_chan][n_freq][2].  For synthetic
+ * signal injection and tests.  Errors: MBH_EINVAL (incl. invalid theta). */
+mbh_status mbh_template_full(mbh_ctx *ctx, const mbh_data *data, int model, uint32_t modes,
+                             const double *theta_host, double *h_dev, hipStream_t stream);
+
+/* ------------------------------------------------------- reference (a9) */
+
+/* Heterodyne precompute of Sec. 2.2 / Sec. 3.2: the band [F_0, F_Nb] is the
+ * first and last grid frequency where the reference h0 = h(theta0) is non
+ * zero; n_bins log-spaced bins (half-open, the last closed); per bin and
+ * channel the sums A0, A1, B0, B1 of eqs. (d_h_rel_bin) and (h_h_rel_bin)
+ * over the grid, lnL(h0) = -1/2 <d-h0|d-h0>, and h0 at the bin edges.
+ * Synchronises `stream` (the band must be known on the host).
+ * Errors: MBH_EINVAL (bad args, invalid theta0, n_bins outside [1, 4096]),
+ * MBH_EBAND (h0 empty on the grid or exactly zero at an edge), MBH_ENOMEM. */
+mbh_status mbh_build_reference_coeffs(mbh_ctx *ctx, const mbh_data *data, int model,
+                                      uint32_t modes, const double *theta0_host, int n_bins,
+                                      hipStream_t stream, mbh_ref **out);
+mbh_status mbh_ref_release(mbh_ref *ref);
+
+typedef struct {
+  int32_t model, n_chan, n_bins;
+  uint32_t modes;
+  int64_t k_lo, k_hi;  /* band in grid indices                           */
+  double lnL0;         /* lnL(h0) = -1/2 <d-h0|d-h0>                      */
+  double dd, dh0, hh0; /* <d|d>, <d|h0>, <h0|h0>                          */
+} mbh_ref_info;
+mbh_status mbh_ref_get_info(const mbh_ref *ref, mbh_ref_info *out);
+
+/* Copy the reference out to host buffers, in the paper's form:
+ *   edges [n_bins+1], kb [n_bins+1] (first grid index of bin b;
+ *   kb[n_bins] = k_hi + 1), A0, A1 [n_chan][n_bins][2], B0, B1
+ *   [n_chan][n_bins], h0_edges [n_chan][n_bins+1][2].  Any pointer may be
+ *   NULL.  Synchronous. */
+mbh_status mbh_ref_export(const mbh_ref *ref, double *edges, int64_t *kb, double *A0, double *A1,
+                          double *B0, double *B1, double *h0_edges);
+
+/* ---------------------------------------------------- likelihoods (a1-a8) */
+
+/* Heterodyned log-likelihood of W walkers against a reference (Sec. 2.2):
+ * the template at the N_b+1 bin edges, r = h/h0, the complex line across
+ * each bin (r0 at the bin centre, slope r1) and the contraction with the
+ * per-bin coefficients, evaluated in the algebraically identical residual
+ * form lnL(h0) + sum_b {...} so that FP32 terms stay small.
+ *   theta_dev [W][11] FP64; lnL_dev [W] FP64; dh_hh_dev [W][2] (Z[d,h],
+ *   Z[h,h]) or NULL.  MBH_FP64 runs every step in FP64; MBH_MIXED keeps
+ *   phases, times and the time/phase shifts in FP64 and runs amplitudes,
+ *   response factors, ratios and bin terms in FP32 with FP64 accumulation.
+ * Errors: MBH_EINVAL, MBH_ENOMEM, MBH_EDEVICE. */
+mbh_status mbh_loglike_heterodyned(mbh_ctx *ctx, const mbh_ref *ref, const double *theta_dev,
+                                   int64_t W, mbh_precision prec, double *lnL_dev,
+                                   double *dh_hh_dev, hipStream_t stream);
+
+/* Full-grid log-likelihood -1/2 <d-h|d-h> (eqs. like and inner, Sec. 2) of W
+ * walkers: the template is generated on every grid frequency on the fly and
+ * never stored.  Same argument conventions as above.
+ * Errors: MBH_EINVAL, MBH_ENOMEM, MBH_EDEVICE. */
+mbh_status mbh_loglike_full(mbh_ctx *ctx, const mbh_data *data, int model, uint32_t modes,
+                            const double *theta_dev, int64_t W, mbh_precision prec,
+                            double *lnL_dev, double *dh_hh_dev, hipStream_t stream);
+
+/* ------------------------------------------------------ batching (a10) */
+
+/* One persistent launch over many (reference, walker batch) items with
+ * ragged modes, bin counts and walker counts.  Items are packed into a
+ * device work list of tiles (longest first) that the workgroups of a
+ * persistent grid claim through one atomic counter; the launch is captured
+ * once into a HIP graph and replayed by mbh_batch_launch.  Lanes per walker
+ * come from the autotuner table (per bin count and mode count), so a walker's
+ * result does not depend on the rest of the batch.
+ *   refs[n], theta_dev[n] ([W_i][11]), W[n], lnL_dev[n] ([W_i]),
+ *   dh_hh_dev[n] (each [W_i][2] or NULL; the array itself may be NULL).
+ * Caller buffers must stay valid while the batch exists.
+ * Errors: MBH_EINVAL, MBH_ENOMEM, MBH_EDEVICE. */
+mbh_status mbh_batch_create(mbh_ctx *ctx, int n, const mbh_ref *const *refs,
+                            const double *const *theta_dev, const int64_t *W,
+                            double *const *lnL_dev, double *const *dh_hh_dev,
+                            mbh_precision prec, mbh_batch **out);
+mbh_status mbh_batch_launch(mbh_batch *batch, hipStream_t stream);
+mbh_status mbh_batch_release(mbh_batch *batch);
+
+/* --------------------------------------------------------- autotuner */
+
+/* Time the heterodyned kernel for every lanes-per-walker choice at this
+ * reference's shape and record the fastest in the context's table (and in
+ * the cache file given to mbh_autotune_load/save).  Synchronous.
+ * lanes_out may be NULL. */
+mbh_status mbh_autotune_heterodyned(mbh_ctx *ctx, const mbh_ref *ref, int64_t W,
+                                    mbh_precision prec, int *lanes_out);
+/* Lanes per walker the library uses for this shape (table or heuristic). */
+mbh_status mbh_lanes_for(const mbh_ctx *ctx, int n_bins, int n_modes, mbh_precision prec,
+                         int *lanes_out);
+/* Force lanes per walker for a shape (1..64, power of two); for tests. */
+mbh_status mbh_set_lanes(mbh_ctx *ctx, int n_bins, int n_modes, mbh_precision prec, int lanes);
+mbh_status mbh_autotune_save(const mbh_ctx *ctx, const char *path);
+mbh_status mbh_autotune_load(mbh_ctx *ctx, const char *path);
+
+/* --------------------------------------------------------- serving (a11) */
+
+typedef struct {
+  int32_t max_inflight;      /* batches in flight on the device (>= 1)           */
+  int32_t max_batch_walkers; /* walkers packed into one launch                    */
+  size_t hbm_budget_bytes;   /* device memory for in-flight request buffers       */
+  mbh_precision prec;
+} mbh_server_config;
+
+/* Continuous-batching request server over resident references.  A
+ * scheduler thread packs queued requests into batches as walker slots and
+ * HBM budget free up, launches them on its own streams (several in flight),
+ * and completes each request when its batch's event fires.
+ * Errors: MBH_EINVAL, MBH_ENOMEM, MBH_EDEVICE. */
+mbh_status mbh_server_create(mbh_ctx *ctx, int n_refs, const mbh_ref *const *refs,
+                             const mbh_server_config *cfg, mbh_server **out);
+/* Enqueue W walkers (host memory, copied) for reference ref_index.
+ * Returns MBH_EAGAIN if the request alone exceeds the batch or budget caps. */
+mbh_status mbh_server_submit(mbh_server *srv, int ref_index, const double *theta_host,
+                             int64_t W, uint64_t *request_id);
+/* Copy results of a finished request to host buffers (lnL [W], dh_hh [W][2]
+ * or NULL) and forget it.  timeout_ms < 0 waits forever, 0 polls.
+ * MBH_EAGAIN if not finished in time; MBH_ENOTFOUND for an unknown id.
+ * latency_s_out (may be NULL) = completion time - submit time. */
+mbh_status mbh_server_wait(mbh_server *srv, uint64_t request_id, int timeout_ms,
+                           double *lnL_host, double *dh_hh_host, double *latency_s_out);
+typedef struct {
+  uint64_t submitted, completed, batches, walkers;
+  uint64_t max_walkers_in_flight;
+  uint64_t max_bytes_in_flight;
+  uint64_t admission_waits; /* times the scheduler held work back for budget/slots */
+} mbh_server_stats;
+mbh_status mbh_server_get_stats(const mbh_server *srv, mbh_server_stats *out);
+mbh_status mbh_server_destroy(mbh_server *srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MBH_H */

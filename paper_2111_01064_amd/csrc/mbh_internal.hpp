@@ -1,0 +1,59 @@
+// mbh_internal.hpp -- handle layouts shared by the translation units of libmbh.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "mbh.h"
+
+struct mbh_ctx {
+  int device = 0;
+  size_t budget = 0;
+  std::atomic<size_t> in_use{0};
+  int n_cu = 256;
+  std::string arch;
+  mutable std::mutex mu;
+  // lanes per walker of the heterodyned kernel, keyed by (n_bins, n_modes, precision)
+  std::map<std::tuple<int, int, int>, int> lanes;
+};
+
+struct mbh_data {
+  mbh_ctx *ctx = nullptr;
+  int n_chan = 0;
+  int64_t n_f = 0;
+  double f0 = 0, df = 0, t_obs = 0;
+  double2 *dw64 = nullptr;  // whitened data d sqrt(4 df / S)         [C][N]
+  double *sw64 = nullptr;   // sqrt(4 df / S) / amplitude scale        [C][N]
+  float2 *dw32 = nullptr;
+  float *sw32 = nullptr;
+  double *dd_dev = nullptr;
+  double dd_host = 0;
+  bool dd_ready = false;
+  hipEvent_t ready = nullptr;
+  size_t bytes = 0;
+  std::mutex mu;
+};
+
+struct mbh_ref {
+  mbh_ctx *ctx = nullptr;
+  int model = 0;
+  uint32_t modes = 0;
+  int n_chan = 0, n_bins = 0;
+  int64_t k_lo = 0, k_hi = 0;
+  double t_obs = 0, lnL0 = 0, dd = 0, dh0 = 0, hh0 = 0;
+  double *F = nullptr, *psi0 = nullptr, *is064 = nullptr, *coef = nullptr;
+  std::vector<double> edges, A0, A1, B0, B1, h0_edges;
+  std::vector<int64_t> kb;
+};
+
+mbh_status mbh_fail(mbh_status s, const char *fmt, ...);
+mbh_status ctx_alloc(mbh_ctx *ctx, void **p, size_t bytes);
+void ctx_free(mbh_ctx *ctx, void *p, size_t bytes);
+mbh_status ctx_alloc_async(mbh_ctx *ctx, void **p, size_t bytes, hipStream_t st);
+void ctx_free_async(mbh_ctx *ctx, void *p, size_t bytes, hipStream_t st);

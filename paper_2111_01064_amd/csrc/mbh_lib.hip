@@ -1,0 +1,777 @@
+// mbh_lib.hip -- host runtime and C ABI of libmbh (see include/mbh.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "mbh.h"
+#include "mbh_internal.hpp"
+#include "mbh_kernels.hpp"
+
+using namespace mbh;
+
+// ---------------------------------------------------------------- errors
+static thread_local std::string g_last_error;
+
+mbh_status mbh_fail(mbh_status s, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+
+extern "C" const char *mbh_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" const char *mbh_strerror(mbh_status s) {
+  switch (s) {
+    case MBH_OK: return "ok";
+    case MBH_EINVAL: return "invalid argument";
+    case MBH_ENOMEM: return "out of device memory or over the HBM budget";
+    case MBH_EBAND: return "reference template empty or zero at a bin edge";
+    case MBH_EDEVICE: return "HIP runtime error";
+    case MBH_EAGAIN: return "not ready";
+    case MBH_ENOTFOUND: return "unknown request";
+  }
+  return "unknown status";
+}
+
+// ---------------------------------------------------------------- memory
+mbh_status ctx_alloc(mbh_ctx *ctx, void **p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) return MBH_OK;
+  size_t cur = ctx->in_use.fetch_add(bytes);
+  if (ctx->budget && cur + bytes > ctx->budget) {
+    ctx->in_use.fetch_sub(bytes);
+    return mbh_fail(MBH_ENOMEM, "HBM budget exceeded: %zu + %zu > %zu bytes", cur, bytes, ctx->budget);
+  }
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    ctx->in_use.fetch_sub(bytes);
+    *p = nullptr;
+    return mbh_fail(MBH_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+  }
+  return MBH_OK;
+}
+
+void ctx_free(mbh_ctx *ctx, void *p, size_t bytes) {
+  if (!p) return;
+  (void)hipFree(p);
+  ctx->in_use.fetch_sub(bytes);
+}
+
+mbh_status ctx_alloc_async(mbh_ctx *ctx, void **p, size_t bytes, hipStream_t st) {
+  *p = nullptr;
+  if (bytes == 0) return MBH_OK;
+  size_t cur = ctx->in_use.fetch_add(bytes);
+  if (ctx->budget && cur + bytes > ctx->budget) {
+    ctx->in_use.fetch_sub(bytes);
+    return mbh_fail(MBH_ENOMEM, "HBM budget exceeded: %zu + %zu > %zu bytes", cur, bytes, ctx->budget);
+  }
+  hipError_t e = hipMallocAsync(p, bytes, st);
+  if (e != hipSuccess) {
+    ctx->in_use.fetch_sub(bytes);
+    *p = nullptr;
+    return mbh_fail(MBH_ENOMEM, "hipMallocAsync(%zu): %s", bytes, hipGetErrorString(e));
+  }
+  return MBH_OK;
+}
+
+void ctx_free_async(mbh_ctx *ctx, void *p, size_t bytes, hipStream_t st) {
+  if (!p) return;
+  (void)hipFreeAsync(p, st);
+  ctx->in_use.fetch_sub(bytes);
+}
+
+// RAII scratch for one call
+struct Scratch {
+  mbh_ctx *ctx;
+  hipStream_t st;
+  std::vector<std::pair<void *, size_t>> bufs;
+  explicit Scratch(mbh_ctx *c, hipStream_t s) : ctx(c), st(s) {}
+  ~Scratch() {
+    for (auto &b : bufs) ctx_free_async(ctx, b.first, b.second, st);
+  }
+  template <typename T>
+  mbh_status get(T **p, size_t n) {
+    void *v = nullptr;
+    mbh_status s = ctx_alloc_async(ctx, &v, n * sizeof(T), st);
+    if (s != MBH_OK) return s;
+    bufs.emplace_back(v, n * sizeof(T));
+    *p = (T *)v;
+    return MBH_OK;
+  }
+};
+
+#define HIP_TRY(x)                                                                          \
+  do {                                                                                      \
+    hipError_t e_ = (x);                                                                    \
+    if (e_ != hipSuccess) return mbh_fail(MBH_EDEVICE, "%s: %s", #x, hipGetErrorString(e_)); \
+  } while (0)
+
+#define MBH_TRY(x)                  \
+  do {                              \
+    mbh_status s_ = (x);            \
+    if (s_ != MBH_OK) return s_;    \
+  } while (0)
+
+// ---------------------------------------------------------------- context
+extern "C" mbh_status mbh_create(int device, size_t hbm_budget_bytes, mbh_ctx **out) {
+  if (!out) return mbh_fail(MBH_EINVAL, "null out");
+  *out = nullptr;
+  int n = 0;
+  HIP_TRY(hipGetDeviceCount(&n));
+  if (device < 0 || device >= n) return mbh_fail(MBH_EINVAL, "device %d of %d", device, n);
+  HIP_TRY(hipSetDevice(device));
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, device));
+  mbh_ctx *c = new mbh_ctx();
+  c->device = device;
+  c->budget = hbm_budget_bytes;
+  c->n_cu = prop.multiProcessorCount;
+  c->arch = prop.gcnArchName;
+  *out = c;
+  return MBH_OK;
+}
+
+extern "C" mbh_status mbh_destroy(mbh_ctx *ctx) {
+  if (!ctx) return MBH_OK;
+  delete ctx;
+  return MBH_OK;
+}
+
+extern "C" mbh_status mbh_memory_in_use(const mbh_ctx *ctx, size_t *bytes_out) {
+  if (!ctx || !bytes_out) return mbh_fail(MBH_EINVAL, "null argument");
+  *bytes_out = ctx->in_use.load();
+  return MBH_OK;
+}
+
+// ---------------------------------------------------------------- data
+static int grid_blocks(int64_t n, int cap) {
+  int64_t b = (n + kBlock - 1) / kBlock;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(b, cap));
+}
+
+extern "C" mbh_status mbh_data_create(mbh_ctx *ctx, int n_chan, int64_t n_freq, double f0, double df,
+                                      double t_obs, const double *d_reim_dev, const double *psd_dev,
+                                      hipStream_t st, mbh_data **out) {
+  if (!ctx || !out || !d_reim_dev || !psd_dev) return mbh_fail(MBH_EINVAL, "null argument");
+  *out = nullptr;
+  if (n_chan != 1 && n_chan != 3) return mbh_fail(MBH_EINVAL, "n_chan must be 1 or 3 (got %d)", n_chan);
+  if (n_freq < 2) return mbh_fail(MBH_EINVAL, "n_freq must be >= 2");
+  if (!(df > 0.0) || !(f0 > 0.0) || !std::isfinite(f0) || !std::isfinite(df))
+    return mbh_fail(MBH_EINVAL, "grid needs f0 > 0 and df > 0");
+  if (!(t_obs > 0.0)) return mbh_fail(MBH_EINVAL, "t_obs must be > 0");
+  HIP_TRY(hipSetDevice(ctx->device));
+  mbh_data *d = new mbh_data();
+  d->ctx = ctx;
+  d->n_chan = n_chan;
+  d->n_f = n_freq;
+  d->f0 = f0;
+  d->df = df;
+  d->t_obs = t_obs;
+  const int64_t n = (int64_t)n_chan * n_freq;
+  auto fail_free = [&](mbh_status s) {
+    mbh_data_release(d);
+    return s;
+  };
+  mbh_status s;
+  if ((s = ctx_alloc(ctx, (void **)&d->dw64, n * sizeof(double2))) != MBH_OK) return fail_free(s);
+  d->bytes += n * sizeof(double2);
+  if ((s = ctx_alloc(ctx, (void **)&d->sw64, n * sizeof(double))) != MBH_OK) return fail_free(s);
+  d->bytes += n * sizeof(double);
+  if ((s = ctx_alloc(ctx, (void **)&d->dw32, n * sizeof(float2))) != MBH_OK) return fail_free(s);
+  d->bytes += n * sizeof(float2);
+  if ((s = ctx_alloc(ctx, (void **)&d->sw32, n * sizeof(float))) != MBH_OK) return fail_free(s);
+  d->bytes += n * sizeof(float);
+  if ((s = ctx_alloc(ctx, (void **)&d->dd_dev, sizeof(double))) != MBH_OK) return fail_free(s);
+  d->bytes += sizeof(double);
+  const int nb = grid_blocks(n, 2048);
+  double *part = nullptr;
+  if ((s = ctx_alloc_async(ctx, (void **)&part, nb * sizeof(double), st)) != MBH_OK) return fail_free(s);
+  hipLaunchKernelGGL(k_whiten, dim3(nb), dim3(kBlock), 0, st, d_reim_dev, psd_dev, n, df, d->dw64, d->sw64,
+                     d->dw32, d->sw32, part);
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, st, part, nb, 1, 1, d->dd_dev);
+  ctx_free_async(ctx, part, nb * sizeof(double), st);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail_free(mbh_fail(MBH_EDEVICE, "whitening launch: %s", hipGetErrorString(e)));
+  if (hipEventCreateWithFlags(&d->ready, hipEventDisableTiming) != hipSuccess ||
+      hipEventRecord(d->ready, st) != hipSuccess)
+    return fail_free(mbh_fail(MBH_EDEVICE, "event"));
+  *out = d;
+  return MBH_OK;
+}
+
+extern "C" mbh_status mbh_data_release(mbh_data *d) {
+  if (!d) return MBH_OK;
+  (void)hipSetDevice(d->ctx->device);
+  (void)hipDeviceSynchronize();
+  ctx_free(d->ctx, d->dw64, d->n_chan * d->n_f * sizeof(double2));
+  ctx_free(d->ctx, d->sw64, d->n_chan * d->n_f * sizeof(double));
+  ctx_free(d->ctx, d->dw32, d->n_chan * d->n_f * sizeof(float2));
+  ctx_free(d->ctx, d->sw32, d->n_chan * d->n_f * sizeof(float));
+  ctx_free(d->ctx, d->dd_dev, sizeof(double));
+  if (d->ready) (void)hipEventDestroy(d->ready);
+  delete d;
+  return MBH_OK;
+}
+
+static mbh_status data_dd(mbh_data *d, double *out) {
+  std::lock_guard<std::mutex> g(d->mu);
+  if (!d->dd_ready) {
+    HIP_TRY(hipSetDevice(d->ctx->device));
+    HIP_TRY(hipEventSynchronize(d->ready));
+    HIP_TRY(hipMemcpy(&d->dd_host, d->dd_dev, sizeof(double), hipMemcpyDeviceToHost));
+    d->dd_ready = true;
+  }
+  *out = d->dd_host;
+  return MBH_OK;
+}
+
+extern "C" mbh_status mbh_data_inner_dd(mbh_data *d, double *dd_out) {
+  if (!d || !dd_out) return mbh_fail(MBH_EINVAL, "null argument");
+  return data_dd(d, dd_out);
+}
+
+static mbh_status check_model(const mbh_data *d, int model, uint32_t modes) {
+  if (model == MBH_MODEL_IMR) {
+    if (d->n_chan != 3) return mbh_fail(MBH_EINVAL, "IMR model needs 3 channels");
+    if (modes == 0 || (modes & ~MBH_MODES_ALL)) return mbh_fail(MBH_EINVAL, "bad mode mask 0x%x", modes);
+    double fmax = d->f0 + (double)(d->n_f - 1) * d->df;
+    if (fmax > kMaxFreq * (1.0 + 1e-12))
+      return mbh_fail(MBH_EINVAL, "grid reaches %.4g Hz; the response series covers f <= %.3g Hz", fmax, kMaxFreq);
+  } else if (model == MBH_MODEL_TF2) {
+    if (d->n_chan != 1) return mbh_fail(MBH_EINVAL, "chirp model needs 1 channel");
+  } else {
+    return mbh_fail(MBH_EINVAL, "unknown model %d", model);
+  }
+  return MBH_OK;
+}
+
+// walker constants of one host parameter vector, on the device
+static mbh_status setup_one(Scratch &sc, const double *theta_host, int model, WalkerC **wc_out, bool *valid) {
+  double *th = nullptr;
+  MBH_TRY(sc.get(&th, 11));
+  WalkerC *wc = nullptr;
+  MBH_TRY(sc.get(&wc, 1));
+  HIP_TRY(hipMemcpyAsync(th, theta_host, 11 * sizeof(double), hipMemcpyHostToDevice, sc.st));
+  hipLaunchKernelGGL(k_walker_setup, dim3(1), dim3(64), 0, sc.st, th, (int64_t)1, model, wc);
+  int32_t v = 0;
+  HIP_TRY(hipMemcpyAsync(&v, &wc->valid, sizeof(int32_t), hipMemcpyDeviceToHost, sc.st));
+  HIP_TRY(hipStreamSynchronize(sc.st));
+  *valid = v != 0;
+  *wc_out = wc;
+  return MBH_OK;
+}
+
+extern "C" mbh_status mbh_template_full(mbh_ctx *ctx, const mbh_data *data, int model, uint32_t modes,
+                                        const double *theta_host, double *h_dev, hipStream_t st) {
+  if (!ctx || !data || !theta_host || !h_dev) return mbh_fail(MBH_EINVAL, "null argument");
+  MBH_TRY(check_model(data, model, modes));
+  HIP_TRY(hipSetDevice(ctx->device));
+  Scratch sc(ctx, st);
+  WalkerC *wc = nullptr;
+  bool valid = false;
+  MBH_TRY(setup_one(sc, theta_host, model, &wc, &valid));
+  if (!valid) return mbh_fail(MBH_EINVAL, "theta outside the model domain");
+  hipLaunchKernelGGL(k_template_grid, dim3((unsigned)((data->n_f + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
+                     wc, modes, data->n_chan, data->n_f, data->f0, data->df, data->t_obs, (double2 *)h_dev);
+  HIP_TRY(hipGetLastError());
+  return MBH_OK;
+}
+
+// ---------------------------------------------------------------- reference
+static void release_ref_dev(mbh_ref *r) {
+  mbh_ctx *c = r->ctx;
+  const int E = r->n_bins + 1;
+  ctx_free(c, r->F, E * sizeof(double));
+  ctx_free(c, r->psi0, E * sizeof(double));
+  ctx_free(c, r->is064, (size_t)r->n_chan * E * 2 * sizeof(double));
+  ctx_free(c, r->coef, (size_t)r->n_chan * r->n_bins * 6 * sizeof(double));
+  r->F = r->psi0 = r->is064 = r->coef = nullptr;
+}
+
+extern "C" mbh_status mbh_ref_release(mbh_ref *r) {
+  if (!r) return MBH_OK;
+  (void)hipSetDevice(r->ctx->device);
+  (void)hipDeviceSynchronize();
+  release_ref_dev(r);
+  delete r;
+  return MBH_OK;
+}
+
+// grid frequency on the host with the same two roundings as the device
+#pragma clang fp contract(off)
+static double host_grid_freq(double f0, double df, int64_t k) {
+  volatile double t = (double)k * df;
+  return f0 + t;
+}
+static void host_edges(double F0, double FN, int n_bins, std::vector<double> &edges) {
+  edges.assign(n_bins + 1, 0.0);
+  edges[0] = F0;
+  edges[n_bins] = FN;
+  for (int j = 1; j < n_bins; ++j) edges[j] = std::exp(std::log(F0) + j * (std::log(FN) - std::log(F0)) / n_bins);
+}
+#pragma clang fp contract(on)
+
+extern "C" mbh_status mbh_build_reference_coeffs(mbh_ctx *ctx, const mbh_data *data_c, int model,
+                                                 uint32_t modes, const double *theta0_host, int n_bins,
+                                                 hipStream_t st, mbh_ref **out) {
+  mbh_data *data = const_cast<mbh_data *>(data_c);
+  if (!ctx || !data || !theta0_host || !out) return mbh_fail(MBH_EINVAL, "null argument");
+  *out = nullptr;
+  if (n_bins < 1 || n_bins > 4096) return mbh_fail(MBH_EINVAL, "n_bins %d outside [1, 4096]", n_bins);
+  MBH_TRY(check_model(data, model, modes));
+  HIP_TRY(hipSetDevice(ctx->device));
+  const int C = data->n_chan, E = n_bins + 1;
+  const int64_t N = data->n_f;
+  Scratch sc(ctx, st);
+  WalkerC *wc = nullptr;
+  bool valid = false;
+  MBH_TRY(setup_one(sc, theta0_host, model, &wc, &valid));
+  if (!valid) return mbh_fail(MBH_EINVAL, "theta0 outside the model domain");
+
+  // pass 1: h0 on the grid, band, lnL(h0) pieces
+  double2 *h0w = nullptr;
+  MBH_TRY(sc.get(&h0w, (size_t)C * N));
+  unsigned long long *band = nullptr;
+  MBH_TRY(sc.get(&band, 2));
+  const int nb1 = grid_blocks(N, 4 * ctx->n_cu);
+  double *part1 = nullptr, *sums1 = nullptr;
+  MBH_TRY(sc.get(&part1, (size_t)nb1 * 3));
+  MBH_TRY(sc.get(&sums1, 3));
+  hipLaunchKernelGGL(k_init_band, dim3(1), dim3(1), 0, st, band);
+  hipLaunchKernelGGL(k_ref_grid, dim3(nb1), dim3(kBlock), 0, st, wc, modes, C, N, data->f0, data->df,
+                     data->t_obs, data->dw64, data->sw64, h0w, band, part1);
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, st, part1, nb1, 3, 3, sums1);
+  HIP_TRY(hipGetLastError());
+  unsigned long long hb[2];
+  double s1[3];
+  HIP_TRY(hipMemcpyAsync(hb, band, sizeof(hb), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(s1, sums1, sizeof(s1), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (hb[0] == ~0ull || hb[1] <= hb[0]) return mbh_fail(MBH_EBAND, "reference template is empty on the grid");
+  const int64_t k_lo = (int64_t)hb[0], k_hi = (int64_t)hb[1];
+
+  // band, log-spaced edges and the first grid index of each bin (host, FP64)
+  std::vector<double> edges;
+  host_edges(host_grid_freq(data->f0, data->df, k_lo), host_grid_freq(data->f0, data->df, k_hi), n_bins, edges);
+  std::vector<int64_t> kb(E);
+  kb[0] = k_lo;
+  kb[n_bins] = k_hi + 1;
+  for (int b = 1; b < n_bins; ++b) {
+    int64_t lo = k_lo, hi = k_hi;  // smallest k with f_k >= edges[b]
+    while (lo < hi) {
+      int64_t mid = lo + (hi - lo) / 2;
+      if (host_grid_freq(data->f0, data->df, mid) >= edges[b]) hi = mid;
+      else lo = mid + 1;
+    }
+    kb[b] = lo;
+  }
+  int64_t max_len = 0;
+  for (int b = 0; b < n_bins; ++b) max_len = std::max(max_len, kb[b + 1] - kb[b]);
+  const int n_sub = (int)std::max<int64_t>(1, (max_len + kRefChunk - 1) / kRefChunk);
+
+  mbh_ref *r = new mbh_ref();
+  r->ctx = ctx;
+  r->model = model;
+  r->modes = model == MBH_MODEL_IMR ? modes : 0u;
+  r->n_chan = C;
+  r->n_bins = n_bins;
+  r->k_lo = k_lo;
+  r->k_hi = k_hi;
+  r->t_obs = data->t_obs;
+  r->edges = edges;
+  r->kb = kb;
+  auto fail_free = [&](mbh_status s) {
+    release_ref_dev(r);
+    delete r;
+    return s;
+  };
+  mbh_status s;
+  if ((s = ctx_alloc(ctx, (void **)&r->F, E * sizeof(double))) != MBH_OK) return fail_free(s);
+  if ((s = ctx_alloc(ctx, (void **)&r->psi0, E * sizeof(double))) != MBH_OK) return fail_free(s);
+  if ((s = ctx_alloc(ctx, (void **)&r->is064, (size_t)C * E * 2 * sizeof(double))) != MBH_OK) return fail_free(s);
+  if ((s = ctx_alloc(ctx, (void **)&r->coef, (size_t)C * n_bins * 6 * sizeof(double))) != MBH_OK)
+    return fail_free(s);
+  int64_t *kb_dev = nullptr;
+  double *part2 = nullptr, *sums2 = nullptr;
+  double2 *s0 = nullptr;
+  if ((s = sc.get(&kb_dev, E)) != MBH_OK) return fail_free(s);
+  if ((s = sc.get(&part2, (size_t)n_bins * n_sub * 18)) != MBH_OK) return fail_free(s);
+  if ((s = sc.get(&sums2, (size_t)n_bins * 18)) != MBH_OK) return fail_free(s);
+  if ((s = sc.get(&s0, (size_t)C * E)) != MBH_OK) return fail_free(s);
+  if (hipMemcpyAsync(r->F, edges.data(), E * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(kb_dev, kb.data(), E * sizeof(int64_t), hipMemcpyHostToDevice, st) != hipSuccess)
+    return fail_free(mbh_fail(MBH_EDEVICE, "upload edges"));
+  hipLaunchKernelGGL(k_ref_bins, dim3(n_bins, n_sub), dim3(kBlock), 0, st, kb_dev, r->F, n_bins, n_sub, C, N,
+                     data->f0, data->df, data->dw64, h0w, part2);
+  // sum the n_sub chunks of each bin in order: part2 is [Nb][n_sub][18]
+  hipLaunchKernelGGL(k_sum_bins, dim3(n_bins), dim3(64), 0, st, part2, n_sub, sums2);
+  hipLaunchKernelGGL(k_ref_edges, dim3((E + 63) / 64), dim3(64), 0, st, wc, r->modes, C, E, r->F, data->t_obs,
+                     r->psi0, s0);
+  if (hipGetLastError() != hipSuccess) return fail_free(mbh_fail(MBH_EDEVICE, "reference kernels"));
+  std::vector<double> hs2((size_t)n_bins * 18), hs0((size_t)C * E * 2);
+  if (hipMemcpyAsync(hs2.data(), sums2, hs2.size() * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipMemcpyAsync(hs0.data(), s0, hs0.size() * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return fail_free(mbh_fail(MBH_EDEVICE, "download reference sums"));
+
+  // the ratio h/h0 must exist at every edge
+  for (int c = 0; c < C; ++c)
+    for (int j = 0; j < E; ++j) {
+      double re = hs0[2 * (c * E + j)], im = hs0[2 * (c * E + j) + 1];
+      if (!(re != 0.0 || im != 0.0) || !std::isfinite(re) || !std::isfinite(im))
+        return fail_free(mbh_fail(MBH_EBAND, "reference is zero at edge %d (f = %.6g Hz), channel %d", j, edges[j], c));
+    }
+  double dd = 0.0;
+  if ((s = data_dd(data, &dd)) != MBH_OK) return fail_free(s);
+  r->dd = dd;
+  r->lnL0 = -0.5 * s1[0];
+  r->dh0 = s1[1];
+  r->hh0 = s1[2];
+
+  // paper-form coefficients (A0 = sum d h0* / S df, ...) and the kernel's
+  // residual-form coefficients, scaled by 1/dF_b for the slope terms
+  r->A0.assign((size_t)C * n_bins * 2, 0.0);
+  r->A1.assign((size_t)C * n_bins * 2, 0.0);
+  r->B0.assign((size_t)C * n_bins, 0.0);
+  r->B1.assign((size_t)C * n_bins, 0.0);
+  std::vector<double> coef((size_t)C * n_bins * 6);
+  for (int c = 0; c < C; ++c)
+    for (int b = 0; b < n_bins; ++b) {
+      const double *q = &hs2[(size_t)b * 18 + c * 6];
+      // the grid sums carry w = 4 df / S; the coefficients carry df / S
+      double amb0r = 0.25 * q[0], amb0i = 0.25 * q[1], amb1r = 0.25 * q[2], amb1i = 0.25 * q[3];
+      double b0 = 0.25 * q[4], b1 = 0.25 * q[5];
+      size_t o = (size_t)c * n_bins + b;
+      r->A0[2 * o] = amb0r + b0;
+      r->A0[2 * o + 1] = amb0i;
+      r->A1[2 * o] = amb1r + b1;
+      r->A1[2 * o + 1] = amb1i;
+      r->B0[o] = b0;
+      r->B1[o] = b1;
+      double idf = 1.0 / (edges[b + 1] - edges[b]);
+      coef[6 * o + 0] = amb0r;
+      coef[6 * o + 1] = amb0i;
+      coef[6 * o + 2] = amb1r * idf;
+      coef[6 * o + 3] = amb1i * idf;
+      coef[6 * o + 4] = b0;
+      coef[6 * o + 5] = b1 * idf;
+    }
+  std::vector<double> is64((size_t)C * E * 2);
+  r->h0_edges.assign((size_t)C * E * 2, 0.0);
+  for (size_t i = 0; i < (size_t)C * E; ++i) {
+    double re = hs0[2 * i], im = hs0[2 * i + 1];
+    double den = re * re + im * im;
+    is64[2 * i] = re / den;
+    is64[2 * i + 1] = -im / den;
+  }
+  // h0 at the edges in the paper's units (for export): s0 e^{-i psi0} / scale
+  {
+    std::vector<double> psi(E);
+    if (hipMemcpy(psi.data(), r->psi0, E * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+      return fail_free(mbh_fail(MBH_EDEVICE, "download psi0"));
+    for (int c = 0; c < C; ++c)
+      for (int j = 0; j < E; ++j) {
+        double re = hs0[2 * (c * E + j)], im = hs0[2 * (c * E + j) + 1];
+        double p = std::remainder(psi[j], 2.0 * M_PI);
+        double cp = std::cos(p), sp = std::sin(p);
+        r->h0_edges[2 * (c * E + j)] = (re * cp + im * sp) / kAmpScale;
+        r->h0_edges[2 * (c * E + j) + 1] = (im * cp - re * sp) / kAmpScale;
+      }
+  }
+  if (hipMemcpyAsync(r->coef, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(r->is064, is64.data(), is64.size() * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return fail_free(mbh_fail(MBH_EDEVICE, "upload coefficients"));
+  *out = r;
+  return MBH_OK;
+}
+
+extern "C" mbh_status mbh_ref_get_info(const mbh_ref *r, mbh_ref_info *o) {
+  if (!r || !o) return mbh_fail(MBH_EINVAL, "null argument");
+  o->model = r->model;
+  o->n_chan = r->n_chan;
+  o->n_bins = r->n_bins;
+  o->modes = r->modes;
+  o->k_lo = r->k_lo;
+  o->k_hi = r->k_hi;
+  o->lnL0 = r->lnL0;
+  o->dd = r->dd;
+  o->dh0 = r->dh0;
+  o->hh0 = r->hh0;
+  return MBH_OK;
+}
+
+extern "C" mbh_status mbh_ref_export(const mbh_ref *r, double *edges, int64_t *kb, double *A0, double *A1,
+                                     double *B0, double *B1, double *h0_edges) {
+  if (!r) return mbh_fail(MBH_EINVAL, "null reference");
+  if (edges) std::memcpy(edges, r->edges.data(), r->edges.size() * sizeof(double));
+  if (kb) std::memcpy(kb, r->kb.data(), r->kb.size() * sizeof(int64_t));
+  if (A0) std::memcpy(A0, r->A0.data(), r->A0.size() * sizeof(double));
+  if (A1) std::memcpy(A1, r->A1.data(), r->A1.size() * sizeof(double));
+  if (B0) std::memcpy(B0, r->B0.data(), r->B0.size() * sizeof(double));
+  if (B1) std::memcpy(B1, r->B1.data(), r->B1.size() * sizeof(double));
+  if (h0_edges) std::memcpy(h0_edges, r->h0_edges.data(), r->h0_edges.size() * sizeof(double));
+  return MBH_OK;
+}
+
+HetRef ref_view(const mbh_ref *r) {
+  HetRef h;
+  h.F = r->F;
+  h.psi0 = r->psi0;
+  h.is064 = r->is064;
+  h.coef = r->coef;
+  h.lnL0 = r->lnL0;
+  h.dh0 = r->dh0;
+  h.hh0 = r->hh0;
+  h.t_obs = r->t_obs;
+  h.n_bins = r->n_bins;
+  h.n_chan = r->n_chan;
+  h.modes = r->modes;
+  h.pad = 0;
+  return h;
+}
+
+// ---------------------------------------------------------------- lanes per walker
+int popcount_modes(uint32_t m) { return __builtin_popcount(m); }
+
+int default_lanes(int n_bins, int n_modes) {
+  // enough edges per lane to amortise the group reduction, few idle lanes
+  int E = n_bins + 1;
+  (void)n_modes;
+  if (E <= 40) return 8;
+  if (E <= 80) return 16;
+  if (E <= 300) return 32;
+  return 64;
+}
+
+int lanes_lookup(const mbh_ctx *ctx, int n_bins, int n_modes, int prec) {
+  std::lock_guard<std::mutex> g(ctx->mu);
+  auto it = ctx->lanes.find(std::make_tuple(n_bins, n_modes, prec));
+  if (it != ctx->lanes.end()) return it->second;
+  return default_lanes(n_bins, n_modes);
+}
+
+template <typename R, bool DH>
+static void launch_het_g(int G, const HetRef &h, const WalkerC *wc, int64_t W, double *lnL, double *dhhh,
+                         hipStream_t st) {
+  const int wpb = kBlock / G;
+  dim3 grid((unsigned)((W + wpb - 1) / wpb));
+  switch (G) {
+    case 1: hipLaunchKernelGGL((k_het<R, 1, DH>), grid, dim3(kBlock), 0, st, h, wc, W, lnL, dhhh); break;
+    case 2: hipLaunchKernelGGL((k_het<R, 2, DH>), grid, dim3(kBlock), 0, st, h, wc, W, lnL, dhhh); break;
+    case 4: hipLaunchKernelGGL((k_het<R, 4, DH>), grid, dim3(kBlock), 0, st, h, wc, W, lnL, dhhh); break;
+    case 8: hipLaunchKernelGGL((k_het<R, 8, DH>), grid, dim3(kBlock), 0, st, h, wc, W, lnL, dhhh); break;
+    case 16: hipLaunchKernelGGL((k_het<R, 16, DH>), grid, dim3(kBlock), 0, st, h, wc, W, lnL, dhhh); break;
+    case 32: hipLaunchKernelGGL((k_het<R, 32, DH>), grid, dim3(kBlock), 0, st, h, wc, W, lnL, dhhh); break;
+    default: hipLaunchKernelGGL((k_het<R, 64, DH>), grid, dim3(kBlock), 0, st, h, wc, W, lnL, dhhh); break;
+  }
+}
+
+void launch_het(int prec, int G, const HetRef &h, const WalkerC *wc, int64_t W, double *lnL, double *dhhh,
+                hipStream_t st) {
+  if (prec == MBH_FP64) {
+    if (dhhh) launch_het_g<double, true>(G, h, wc, W, lnL, dhhh, st);
+    else launch_het_g<double, false>(G, h, wc, W, lnL, dhhh, st);
+  } else {
+    if (dhhh) launch_het_g<float, true>(G, h, wc, W, lnL, dhhh, st);
+    else launch_het_g<float, false>(G, h, wc, W, lnL, dhhh, st);
+  }
+}
+
+extern "C" mbh_status mbh_loglike_heterodyned(mbh_ctx *ctx, const mbh_ref *ref, const double *theta_dev,
+                                              int64_t W, mbh_precision prec, double *lnL_dev,
+                                              double *dh_hh_dev, hipStream_t st) {
+  if (!ctx || !ref || (W > 0 && (!theta_dev || !lnL_dev))) return mbh_fail(MBH_EINVAL, "null argument");
+  if (W < 0 || W > (int64_t)1 << 30) return mbh_fail(MBH_EINVAL, "W = %lld out of range", (long long)W);
+  if (prec != MBH_FP64 && prec != MBH_MIXED) return mbh_fail(MBH_EINVAL, "bad precision");
+  if (W == 0) return MBH_OK;
+  HIP_TRY(hipSetDevice(ctx->device));
+  Scratch sc(ctx, st);
+  WalkerC *wc = nullptr;
+  MBH_TRY(sc.get(&wc, (size_t)W));
+  hipLaunchKernelGGL(k_walker_setup, dim3((unsigned)((W + 127) / 128)), dim3(128), 0, st, theta_dev, W,
+                     ref->model, wc);
+  int G = lanes_lookup(ctx, ref->n_bins, popcount_modes(ref->modes ? ref->modes : 1u), prec);
+  launch_het(prec, G, ref_view(ref), wc, W, lnL_dev, dh_hh_dev, st);
+  HIP_TRY(hipGetLastError());
+  return MBH_OK;
+}
+
+// ---------------------------------------------------------------- full grid
+template <typename R, bool DH>
+static mbh_status full_impl(mbh_ctx *ctx, const mbh_data *d, uint32_t modes, const WalkerC *wc, int64_t W,
+                            double *lnL, double *dhhh, hipStream_t st, Scratch &sc) {
+  constexpr int KF = 2;
+  const int64_t fpb = (int64_t)kBlock * KF;
+  const int64_t n_fc = (d->n_f + fpb - 1) / fpb;
+  if (n_fc > 65535 * 32) return mbh_fail(MBH_EINVAL, "grid too large");
+  // walkers per block: keep >= ~4 blocks per CU in total
+  int64_t target = (int64_t)ctx->n_cu * 8;
+  int64_t n_wc = std::max<int64_t>(1, std::min<int64_t>(W, target / std::max<int64_t>(1, n_fc)));
+  int64_t wpb = (W + n_wc - 1) / n_wc;
+  n_wc = (W + wpb - 1) / wpb;
+  const int nv = DH ? 3 : 1;
+  double *part = nullptr;
+  MBH_TRY(sc.get(&part, (size_t)nv * n_fc * W));
+  dim3 grid((unsigned)n_fc, (unsigned)n_wc);
+  if constexpr (sizeof(R) == 8)
+    hipLaunchKernelGGL((k_full<double, KF, DH>), grid, dim3(kBlock), 0, st, d->dw64, d->sw64, d->n_chan, d->n_f,
+                       d->f0, d->df, d->t_obs, modes, wc, W, (int)wpb, part);
+  else
+    hipLaunchKernelGGL((k_full<float, KF, DH>), grid, dim3(kBlock), 0, st, d->dw32, d->sw32, d->n_chan, d->n_f,
+                       d->f0, d->df, d->t_obs, modes, wc, W, (int)wpb, part);
+  hipLaunchKernelGGL(k_full_reduce, dim3((unsigned)((W + 127) / 128)), dim3(128), 0, st, part, (int)n_fc, W, nv,
+                     wc, lnL, dhhh);
+  HIP_TRY(hipGetLastError());
+  return MBH_OK;
+}
+
+extern "C" mbh_status mbh_loglike_full(mbh_ctx *ctx, const mbh_data *data, int model, uint32_t modes,
+                                       const double *theta_dev, int64_t W, mbh_precision prec, double *lnL_dev,
+                                       double *dh_hh_dev, hipStream_t st) {
+  if (!ctx || !data || (W > 0 && (!theta_dev || !lnL_dev))) return mbh_fail(MBH_EINVAL, "null argument");
+  if (W < 0 || W > (int64_t)1 << 24) return mbh_fail(MBH_EINVAL, "W = %lld out of range", (long long)W);
+  if (prec != MBH_FP64 && prec != MBH_MIXED) return mbh_fail(MBH_EINVAL, "bad precision");
+  MBH_TRY(check_model(data, model, modes));
+  if (W == 0) return MBH_OK;
+  HIP_TRY(hipSetDevice(ctx->device));
+  Scratch sc(ctx, st);
+  WalkerC *wc = nullptr;
+  MBH_TRY(sc.get(&wc, (size_t)W));
+  hipLaunchKernelGGL(k_walker_setup, dim3((unsigned)((W + 127) / 128)), dim3(128), 0, st, theta_dev, W, model, wc);
+  uint32_t m = model == MBH_MODEL_IMR ? modes : 0u;
+  if (prec == MBH_FP64)
+    return dh_hh_dev ? full_impl<double, true>(ctx, data, m, wc, W, lnL_dev, dh_hh_dev, st, sc)
+                     : full_impl<double, false>(ctx, data, m, wc, W, lnL_dev, nullptr, st, sc);
+  return dh_hh_dev ? full_impl<float, true>(ctx, data, m, wc, W, lnL_dev, dh_hh_dev, st, sc)
+                   : full_impl<float, false>(ctx, data, m, wc, W, lnL_dev, nullptr, st, sc);
+}
+
+// ---------------------------------------------------------------- autotuner
+static bool valid_lanes(int g) { return g == 1 || g == 2 || g == 4 || g == 8 || g == 16 || g == 32 || g == 64; }
+
+extern "C" mbh_status mbh_lanes_for(const mbh_ctx *ctx, int n_bins, int n_modes, mbh_precision prec,
+                                    int *lanes_out) {
+  if (!ctx || !lanes_out) return mbh_fail(MBH_EINVAL, "null argument");
+  *lanes_out = lanes_lookup(ctx, n_bins, n_modes, prec);
+  return MBH_OK;
+}
+
+extern "C" mbh_status mbh_set_lanes(mbh_ctx *ctx, int n_bins, int n_modes, mbh_precision prec, int lanes) {
+  if (!ctx || !valid_lanes(lanes)) return mbh_fail(MBH_EINVAL, "lanes must be a power of two in [1, 64]");
+  std::lock_guard<std::mutex> g(ctx->mu);
+  ctx->lanes[std::make_tuple(n_bins, n_modes, (int)prec)] = lanes;
+  return MBH_OK;
+}
+
+// Times every lanes-per-walker choice on the reference's shape with W
+// walkers at the reference point (plus small offsets), keeps the fastest.
+extern "C" mbh_status mbh_autotune_heterodyned(mbh_ctx *ctx, const mbh_ref *ref, int64_t W, mbh_precision prec,
+                                               int *lanes_out) {
+  if (!ctx || !ref || W < 1) return mbh_fail(MBH_EINVAL, "bad argument");
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t st;
+  HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+  mbh_status rc = MBH_OK;
+  {
+    Scratch sc(ctx, st);
+    double *th = nullptr, *lnL = nullptr;
+    WalkerC *wc = nullptr;
+    if ((rc = sc.get(&th, (size_t)W * 11)) != MBH_OK || (rc = sc.get(&lnL, (size_t)W)) != MBH_OK ||
+        (rc = sc.get(&wc, (size_t)W)) != MBH_OK) {
+      (void)hipStreamSynchronize(st);
+      (void)hipStreamDestroy(st);
+      return rc;
+    }
+    // walkers: a valid parameter vector of the reference's model
+    std::vector<double> h((size_t)W * 11);
+    for (int64_t w = 0; w < W; ++w) {
+      double *t = &h[(size_t)w * 11];
+      const double base[11] = {2e6, 0.5, 0.3, -0.2, 50.0, 1.0, 1.1, 2.0, 0.3, 0.7, ref->t_obs * 0.5};
+      for (int i = 0; i < 11; ++i) t[i] = base[i];
+      if (ref->model == MBH_MODEL_TF2) {
+        t[0] = 3e5;
+        t[1] = 1e-21;
+        t[2] = 1e4;
+        t[3] = 0.5;
+      }
+      t[0] *= 1.0 + 1e-6 * (double)(w % 7);
+    }
+    std::vector<std::pair<float, int>> res;
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    if (hipMemcpyAsync(th, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, st) == hipSuccess) {
+      hipLaunchKernelGGL(k_walker_setup, dim3((unsigned)((W + 127) / 128)), dim3(128), 0, st, th, W, ref->model,
+                         wc);
+      HetRef hv = ref_view(ref);
+      for (int G : {4, 8, 16, 32, 64}) {
+        launch_het(prec, G, hv, wc, W, lnL, nullptr, st);  // warm-up
+        (void)hipEventRecord(e0, st);
+        const int reps = 20;
+        for (int r = 0; r < reps; ++r) launch_het(prec, G, hv, wc, W, lnL, nullptr, st);
+        (void)hipEventRecord(e1, st);
+        (void)hipEventSynchronize(e1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        res.emplace_back(ms / reps, G);
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (hipGetLastError() != hipSuccess || res.empty()) rc = mbh_fail(MBH_EDEVICE, "autotune launches failed");
+    if (rc == MBH_OK) {
+      std::sort(res.begin(), res.end());
+      int best = res.front().second;
+      std::lock_guard<std::mutex> g(ctx->mu);
+      ctx->lanes[std::make_tuple(ref->n_bins, popcount_modes(ref->modes ? ref->modes : 1u), (int)prec)] = best;
+      if (lanes_out) *lanes_out = best;
+    }
+  }
+  (void)hipStreamSynchronize(st);
+  (void)hipStreamDestroy(st);
+  return rc;
+}
+
+// cache file: one line per entry "arch n_bins n_modes prec lanes"
+extern "C" mbh_status mbh_autotune_save(const mbh_ctx *ctx, const char *path) {
+  if (!ctx || !path) return mbh_fail(MBH_EINVAL, "null argument");
+  FILE *f = fopen(path, "w");
+  if (!f) return mbh_fail(MBH_EINVAL, "cannot write %s", path);
+  std::lock_guard<std::mutex> g(ctx->mu);
+  for (auto &kv : ctx->lanes)
+    fprintf(f, "%s %d %d %d %d\n", ctx->arch.c_str(), std::get<0>(kv.first), std::get<1>(kv.first),
+            std::get<2>(kv.first), kv.second);
+  fclose(f);
+  return MBH_OK;
+}
+
+extern "C" mbh_status mbh_autotune_load(mbh_ctx *ctx, const char *path) {
+  if (!ctx || !path) return mbh_fail(MBH_EINVAL, "null argument");
+  FILE *f = fopen(path, "r");
+  if (!f) return mbh_fail(MBH_EINVAL, "cannot read %s", path);
+  char arch[128];
+  int nb, nm, pr, g;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  while (fscanf(f, "%127s %d %d %d %d", arch, &nb, &nm, &pr, &g) == 5) {
+    // entries measured on another architecture are ignored
+    if (ctx->arch.rfind(arch, 0) == 0 || std::string(arch).rfind(ctx->arch, 0) == 0)
+      if (valid_lanes(g)) ctx->lanes[std::make_tuple(nb, nm, pr)] = g;
+  }
+  fclose(f);
+  return MBH_OK;
+}

@@ -1,0 +1,533 @@
+// mbh_serve.hip -- ragged multi-source batching in one persistent,
+// graph-captured launch (mbh_batch_*) and a continuous-batching request
+// server on top of the same work-list kernel (mbh_server_*).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "mbh.h"
+#include "mbh_internal.hpp"
+#include "mbh_work.hpp"
+
+using namespace mbh;
+
+HetRef ref_view(const mbh_ref *r);
+int lanes_lookup(const mbh_ctx *ctx, int n_bins, int n_modes, int prec);
+int popcount_modes(uint32_t m);
+
+#define HIP_TRY(x)                                                                          \
+  do {                                                                                      \
+    hipError_t e_ = (x);                                                                    \
+    if (e_ != hipSuccess) return mbh_fail(MBH_EDEVICE, "%s: %s", #x, hipGetErrorString(e_)); \
+  } while (0)
+
+// ---------------------------------------------------------------- shared helpers
+static int item_lanes(const mbh_ctx *ctx, const mbh_ref *r, int prec) {
+  return lanes_lookup(ctx, r->n_bins, popcount_modes(r->modes ? r->modes : 1u), prec);
+}
+
+// tiles of one item: kBlock / G walkers each; cost ~ edge iterations x modes
+static void append_tiles(std::vector<WorkTile> &tiles, std::vector<double> &cost, int item, const mbh_ref *r,
+                         int G, int64_t W) {
+  const int64_t wpb = kBlock / G;
+  const int E = r->n_bins + 1;
+  const double c = (double)((E + G - 1) / G) * popcount_modes(r->modes ? r->modes : 1u);
+  for (int64_t w = 0; w < W; w += wpb) {
+    tiles.push_back(WorkTile{item, G, w});
+    cost.push_back(c);
+  }
+}
+
+// longest tiles first; ties keep item order (stable)
+static void order_tiles(std::vector<WorkTile> &tiles, const std::vector<double> &cost) {
+  std::vector<size_t> idx(tiles.size());
+  for (size_t i = 0; i < idx.size(); ++i) idx[i] = i;
+  std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+  std::vector<WorkTile> out(tiles.size());
+  for (size_t i = 0; i < idx.size(); ++i) out[i] = tiles[idx[i]];
+  tiles.swap(out);
+}
+
+static int persistent_blocks(const mbh_ctx *ctx, int prec, bool dh) {
+  int per_cu = 0;
+  hipError_t e;
+  if (prec == MBH_FP64)
+    e = dh ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_het_work<double, true>, kBlock, 0)
+           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_het_work<double, false>, kBlock, 0);
+  else
+    e = dh ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_het_work<float, true>, kBlock, 0)
+           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_het_work<float, false>, kBlock, 0);
+  if (e != hipSuccess || per_cu < 1) per_cu = 1;
+  return per_cu * ctx->n_cu;
+}
+
+static void launch_work(int prec, bool dh, int n_blocks, int setup_blocks, const WorkHeader *hdr,
+                        const WorkItem *items, const WorkTile *tiles, unsigned *counters, hipStream_t st) {
+  hipLaunchKernelGGL(k_setup_work, dim3(setup_blocks), dim3(128), 0, st, hdr, items);
+  if (prec == MBH_FP64) {
+    if (dh) hipLaunchKernelGGL((k_het_work<double, true>), dim3(n_blocks), dim3(kBlock), 0, st, hdr, items, tiles, counters);
+    else hipLaunchKernelGGL((k_het_work<double, false>), dim3(n_blocks), dim3(kBlock), 0, st, hdr, items, tiles, counters);
+  } else {
+    if (dh) hipLaunchKernelGGL((k_het_work<float, true>), dim3(n_blocks), dim3(kBlock), 0, st, hdr, items, tiles, counters);
+    else hipLaunchKernelGGL((k_het_work<float, false>), dim3(n_blocks), dim3(kBlock), 0, st, hdr, items, tiles, counters);
+  }
+}
+
+// ---------------------------------------------------------------- batch
+struct mbh_batch {
+  mbh_ctx *ctx = nullptr;
+  int prec = 0;
+  bool dh = false;
+  WorkHeader *hdr = nullptr;
+  WorkItem *items = nullptr;
+  WorkTile *tiles = nullptr;
+  unsigned *counters = nullptr;
+  WalkerC *wc = nullptr;
+  size_t bytes[5] = {0, 0, 0, 0, 0};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+static void batch_free(mbh_batch *b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  ctx_free(b->ctx, b->hdr, b->bytes[0]);
+  ctx_free(b->ctx, b->items, b->bytes[1]);
+  ctx_free(b->ctx, b->tiles, b->bytes[2]);
+  ctx_free(b->ctx, b->counters, b->bytes[3]);
+  ctx_free(b->ctx, b->wc, b->bytes[4]);
+  delete b;
+}
+
+extern "C" mbh_status mbh_batch_create(mbh_ctx *ctx, int n, const mbh_ref *const *refs, const double *const *theta_dev,
+                                       const int64_t *W, double *const *lnL_dev, double *const *dh_hh_dev,
+                                       mbh_precision prec, mbh_batch **out) {
+  if (!ctx || !refs || !theta_dev || !W || !lnL_dev || !out || n < 1) return mbh_fail(MBH_EINVAL, "bad argument");
+  *out = nullptr;
+  if (prec != MBH_FP64 && prec != MBH_MIXED) return mbh_fail(MBH_EINVAL, "bad precision");
+  int64_t total = 0;
+  bool dh = false;
+  for (int i = 0; i < n; ++i) {
+    if (!refs[i] || W[i] < 0 || (W[i] > 0 && (!theta_dev[i] || !lnL_dev[i])))
+      return mbh_fail(MBH_EINVAL, "item %d: null reference or buffers", i);
+    if (refs[i]->ctx != ctx) return mbh_fail(MBH_EINVAL, "item %d: reference of another context", i);
+    total += W[i];
+    if (dh_hh_dev && dh_hh_dev[i]) dh = true;
+  }
+  HIP_TRY(hipSetDevice(ctx->device));
+  mbh_batch *b = new mbh_batch();
+  b->ctx = ctx;
+  b->prec = prec;
+  b->dh = dh;
+  auto fail = [&](mbh_status s) {
+    batch_free(b);
+    return s;
+  };
+  std::vector<WorkItem> items(n);
+  std::vector<WorkTile> tiles;
+  std::vector<double> cost;
+  mbh_status s;
+  b->bytes[4] = (size_t)std::max<int64_t>(total, 1) * sizeof(WalkerC);
+  if ((s = ctx_alloc(ctx, (void **)&b->wc, b->bytes[4])) != MBH_OK) return fail(s);
+  int64_t off = 0;
+  for (int i = 0; i < n; ++i) {
+    WorkItem &it = items[i];
+    it.ref = ref_view(refs[i]);
+    it.theta = theta_dev[i];
+    it.wc = b->wc + off;
+    it.lnL = lnL_dev[i];
+    it.dhhh = dh_hh_dev ? dh_hh_dev[i] : nullptr;
+    it.W = W[i];
+    it.offset = off;
+    it.G = item_lanes(ctx, refs[i], prec);
+    it.model = refs[i]->model;
+    append_tiles(tiles, cost, i, refs[i], it.G, W[i]);
+    off += W[i];
+  }
+  order_tiles(tiles, cost);
+  WorkHeader h{n, (int32_t)tiles.size(), total};
+  b->bytes[0] = sizeof(WorkHeader);
+  b->bytes[1] = n * sizeof(WorkItem);
+  b->bytes[2] = std::max<size_t>(1, tiles.size()) * sizeof(WorkTile);
+  b->bytes[3] = 2 * sizeof(unsigned);
+  if ((s = ctx_alloc(ctx, (void **)&b->hdr, b->bytes[0])) != MBH_OK) return fail(s);
+  if ((s = ctx_alloc(ctx, (void **)&b->items, b->bytes[1])) != MBH_OK) return fail(s);
+  if ((s = ctx_alloc(ctx, (void **)&b->tiles, b->bytes[2])) != MBH_OK) return fail(s);
+  if ((s = ctx_alloc(ctx, (void **)&b->counters, b->bytes[3])) != MBH_OK) return fail(s);
+  unsigned zero[2] = {0u, 0u};
+  if (hipMemcpy(b->hdr, &h, sizeof(h), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b->items, items.data(), b->bytes[1], hipMemcpyHostToDevice) != hipSuccess ||
+      (!tiles.empty() && hipMemcpy(b->tiles, tiles.data(), tiles.size() * sizeof(WorkTile), hipMemcpyHostToDevice) != hipSuccess) ||
+      hipMemcpy(b->counters, zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess)
+    return fail(mbh_fail(MBH_EDEVICE, "upload work list"));
+  // capture the setup + persistent launch once
+  const int nblk = std::max(1, std::min<int>(persistent_blocks(ctx, prec, dh), (int)tiles.size()));
+  const int sblk = (int)std::max<int64_t>(1, std::min<int64_t>((total + 127) / 128, 4 * ctx->n_cu));
+  hipStream_t cs;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return fail(mbh_fail(MBH_EDEVICE, "stream"));
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    launch_work(prec, dh, nblk, sblk, b->hdr, b->items, b->tiles, b->counters, cs);
+    e = hipStreamEndCapture(cs, &b->graph);
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+  (void)hipStreamDestroy(cs);
+  if (e != hipSuccess) return fail(mbh_fail(MBH_EDEVICE, "graph capture: %s", hipGetErrorString(e)));
+  *out = b;
+  return MBH_OK;
+}
+
+extern "C" mbh_status mbh_batch_launch(mbh_batch *b, hipStream_t st) {
+  if (!b) return mbh_fail(MBH_EINVAL, "null batch");
+  HIP_TRY(hipSetDevice(b->ctx->device));
+  HIP_TRY(hipGraphLaunch(b->exec, st));
+  return MBH_OK;
+}
+
+extern "C" mbh_status mbh_batch_release(mbh_batch *b) {
+  if (!b) return MBH_OK;
+  (void)hipSetDevice(b->ctx->device);
+  (void)hipDeviceSynchronize();
+  batch_free(b);
+  return MBH_OK;
+}
+
+// ---------------------------------------------------------------- server
+namespace {
+using Clock = std::chrono::steady_clock;
+
+struct Request {
+  uint64_t id = 0;
+  int ref = 0;
+  int64_t W = 0;
+  std::vector<double> theta;
+  std::vector<double> lnL, dhhh;
+  Clock::time_point t_submit, t_done;
+  bool done = false;
+};
+
+// one in-flight batch: device buffers, pinned host staging, stream, event
+struct Slot {
+  hipStream_t st = nullptr;
+  hipEvent_t ev = nullptr;
+  double *theta_h = nullptr, *res_h = nullptr;  // pinned
+  WorkHeader *hdr_h = nullptr;
+  WorkItem *items_h = nullptr;
+  WorkTile *tiles_h = nullptr;
+  double *theta_d = nullptr, *res_d = nullptr;
+  WorkHeader *hdr_d = nullptr;
+  WorkItem *items_d = nullptr;
+  WorkTile *tiles_d = nullptr;
+  unsigned *counters_d = nullptr;
+  WalkerC *wc_d = nullptr;
+  std::vector<std::pair<std::shared_ptr<Request>, int64_t>> members;  // request, first walker in the slot
+  int64_t walkers = 0;
+  bool busy = false;
+};
+}  // namespace
+
+struct mbh_server {
+  mbh_ctx *ctx = nullptr;
+  std::vector<const mbh_ref *> refs;
+  mbh_server_config cfg{};
+  int64_t cap_walkers = 0;  // per slot
+  int max_items = 0, max_tiles = 0;
+  size_t bytes_per_walker = 0;
+  std::vector<Slot> slots;
+  std::vector<std::pair<void *, size_t>> dev_allocs;
+  int nblk = 1;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<std::shared_ptr<Request>> queue;
+  std::unordered_map<uint64_t, std::shared_ptr<Request>> live;
+  uint64_t next_id = 1;
+  std::atomic<bool> stop{false};
+  std::thread thr;
+  mbh_server_stats stats{};
+  size_t bytes_in_flight = 0;
+  int64_t walkers_in_flight = 0;
+  std::string thread_error;
+};
+
+static void server_free(mbh_server *s) {
+  for (auto &sl : s->slots) {
+    if (sl.st) (void)hipStreamSynchronize(sl.st);
+    if (sl.ev) (void)hipEventDestroy(sl.ev);
+    if (sl.st) (void)hipStreamDestroy(sl.st);
+    if (sl.theta_h) (void)hipHostFree(sl.theta_h);
+    if (sl.res_h) (void)hipHostFree(sl.res_h);
+    if (sl.hdr_h) (void)hipHostFree(sl.hdr_h);
+    if (sl.items_h) (void)hipHostFree(sl.items_h);
+    if (sl.tiles_h) (void)hipHostFree(sl.tiles_h);
+  }
+  for (auto &a : s->dev_allocs) ctx_free(s->ctx, a.first, a.second);
+  delete s;
+}
+
+// pack queued requests into a free slot (FIFO, as walker capacity allows)
+static bool server_pack(mbh_server *s, Slot &sl) {
+  sl.members.clear();
+  sl.walkers = 0;
+  int n_items = 0, n_tiles = 0;
+  std::vector<WorkTile> tiles;
+  std::vector<double> cost;
+  while (!s->queue.empty()) {
+    auto &r = s->queue.front();
+    const mbh_ref *ref = s->refs[r->ref];
+    int G = item_lanes(s->ctx, ref, s->cfg.prec);
+    int nt = (int)((r->W + kBlock / G - 1) / (kBlock / G));
+    if (sl.walkers + r->W > s->cap_walkers || n_items + 1 > s->max_items || n_tiles + nt > s->max_tiles) break;
+    WorkItem &it = sl.items_h[n_items];
+    it.ref = ref_view(ref);
+    it.theta = sl.theta_d + sl.walkers * 11;
+    it.wc = sl.wc_d + sl.walkers;
+    it.lnL = sl.res_d + sl.walkers * 3;
+    it.dhhh = nullptr;
+    it.W = r->W;
+    it.offset = sl.walkers;
+    it.G = G;
+    it.model = ref->model;
+    std::memcpy(sl.theta_h + sl.walkers * 11, r->theta.data(), r->W * 11 * sizeof(double));
+    append_tiles(tiles, cost, n_items, ref, G, r->W);
+    n_tiles += nt;
+    sl.members.emplace_back(r, sl.walkers);
+    sl.walkers += r->W;
+    ++n_items;
+    s->queue.pop_front();
+  }
+  if (n_items == 0) return false;
+  // results of item i: lnL at res_d + 3 off (W entries), then dh/hh pairs after the lnL block
+  for (int i = 0; i < n_items; ++i) {
+    WorkItem &it = sl.items_h[i];
+    it.lnL = sl.res_d + it.offset;
+    it.dhhh = sl.res_d + sl.walkers + 2 * it.offset;
+  }
+  order_tiles(tiles, cost);
+  std::memcpy(sl.tiles_h, tiles.data(), tiles.size() * sizeof(WorkTile));
+  *sl.hdr_h = WorkHeader{n_items, (int32_t)tiles.size(), sl.walkers};
+  return true;
+}
+
+static bool server_launch(mbh_server *s, Slot &sl) {
+  const WorkHeader &h = *sl.hdr_h;
+  hipStream_t st = sl.st;
+  bool ok = hipMemcpyAsync(sl.theta_d, sl.theta_h, sl.walkers * 11 * sizeof(double), hipMemcpyHostToDevice, st) == hipSuccess &&
+            hipMemcpyAsync(sl.items_d, sl.items_h, h.n_items * sizeof(WorkItem), hipMemcpyHostToDevice, st) == hipSuccess &&
+            hipMemcpyAsync(sl.tiles_d, sl.tiles_h, h.n_tiles * sizeof(WorkTile), hipMemcpyHostToDevice, st) == hipSuccess &&
+            hipMemcpyAsync(sl.hdr_d, sl.hdr_h, sizeof(WorkHeader), hipMemcpyHostToDevice, st) == hipSuccess;
+  if (!ok) return false;
+  const int nblk = std::max(1, std::min(s->nblk, h.n_tiles));
+  const int sblk = (int)std::max<int64_t>(1, std::min<int64_t>((sl.walkers + 127) / 128, 4 * s->ctx->n_cu));
+  launch_work(s->cfg.prec, true, nblk, sblk, sl.hdr_d, sl.items_d, sl.tiles_d, sl.counters_d, st);
+  ok = hipGetLastError() == hipSuccess &&
+       hipMemcpyAsync(sl.res_h, sl.res_d, sl.walkers * 3 * sizeof(double), hipMemcpyDeviceToHost, st) == hipSuccess &&
+       hipEventRecord(sl.ev, st) == hipSuccess;
+  return ok;
+}
+
+static void server_complete(mbh_server *s, Slot &sl) {
+  const double *lnL = sl.res_h;
+  const double *dh = sl.res_h + sl.walkers;
+  auto now = Clock::now();
+  for (auto &m : sl.members) {
+    Request &r = *m.first;
+    r.lnL.assign(lnL + m.second, lnL + m.second + r.W);
+    r.dhhh.assign(dh + 2 * m.second, dh + 2 * (m.second + r.W));
+    r.t_done = now;
+    r.done = true;
+  }
+  s->stats.completed += sl.members.size();
+  s->walkers_in_flight -= sl.walkers;
+  s->bytes_in_flight -= (size_t)sl.walkers * s->bytes_per_walker;
+  sl.members.clear();
+  sl.busy = false;
+}
+
+static void server_loop(mbh_server *s) {
+  (void)hipSetDevice(s->ctx->device);
+  std::unique_lock<std::mutex> lk(s->mu);
+  while (!s->stop.load()) {
+    bool progressed = false;
+    // 1. retire finished batches
+    for (auto &sl : s->slots) {
+      if (sl.busy && hipEventQuery(sl.ev) == hipSuccess) {
+        server_complete(s, sl);
+        progressed = true;
+      }
+    }
+    if (progressed) s->cv_done.notify_all();
+    // 2. admit queued work into free slots (continuous batching)
+    for (auto &sl : s->slots) {
+      if (sl.busy || s->queue.empty()) continue;
+      if (!server_pack(s, sl)) continue;
+      sl.busy = true;
+      s->walkers_in_flight += sl.walkers;
+      s->bytes_in_flight += (size_t)sl.walkers * s->bytes_per_walker;
+      s->stats.max_walkers_in_flight = std::max<uint64_t>(s->stats.max_walkers_in_flight, s->walkers_in_flight);
+      s->stats.max_bytes_in_flight = std::max<uint64_t>(s->stats.max_bytes_in_flight, s->bytes_in_flight);
+      s->stats.batches += 1;
+      s->stats.walkers += sl.walkers;
+      lk.unlock();
+      bool ok = server_launch(s, sl);
+      lk.lock();
+      if (!ok) {
+        s->thread_error = "launch failed";
+        for (auto &m : sl.members) m.first->done = true;
+        sl.busy = false;
+      }
+      progressed = true;
+    }
+    bool any_busy = false;
+    for (auto &sl : s->slots) any_busy |= sl.busy;
+    if (!s->queue.empty() && !progressed) s->stats.admission_waits += 1;
+    if (progressed) continue;
+    if (any_busy) {
+      // poll the oldest batch without holding the lock
+      lk.unlock();
+      std::this_thread::yield();
+      lk.lock();
+    } else {
+      s->cv_work.wait_for(lk, std::chrono::milliseconds(50));
+    }
+  }
+}
+
+extern "C" mbh_status mbh_server_create(mbh_ctx *ctx, int n_refs, const mbh_ref *const *refs,
+                                        const mbh_server_config *cfg, mbh_server **out) {
+  if (!ctx || !refs || !cfg || !out || n_refs < 1) return mbh_fail(MBH_EINVAL, "bad argument");
+  *out = nullptr;
+  if (cfg->max_inflight < 1 || cfg->max_inflight > 8 || cfg->max_batch_walkers < 1)
+    return mbh_fail(MBH_EINVAL, "max_inflight in [1, 8] and max_batch_walkers >= 1 required");
+  if (cfg->prec != MBH_FP64 && cfg->prec != MBH_MIXED) return mbh_fail(MBH_EINVAL, "bad precision");
+  for (int i = 0; i < n_refs; ++i)
+    if (!refs[i] || refs[i]->ctx != ctx) return mbh_fail(MBH_EINVAL, "reference %d invalid", i);
+  HIP_TRY(hipSetDevice(ctx->device));
+  mbh_server *s = new mbh_server();
+  s->ctx = ctx;
+  s->refs.assign(refs, refs + n_refs);
+  s->cfg = *cfg;
+  s->bytes_per_walker = 11 * sizeof(double) + 3 * sizeof(double) + sizeof(WalkerC);
+  int64_t cap = cfg->max_batch_walkers;
+  if (cfg->hbm_budget_bytes) {
+    int64_t by_budget = (int64_t)(cfg->hbm_budget_bytes / (cfg->max_inflight * s->bytes_per_walker));
+    cap = std::min(cap, by_budget);
+  }
+  if (cap < 1) {
+    delete s;
+    return mbh_fail(MBH_ENOMEM, "HBM budget too small for one walker per slot");
+  }
+  s->cap_walkers = cap;
+  s->max_items = (int)std::min<int64_t>(cap, 4096);
+  s->max_tiles = (int)(cap + s->max_items);
+  s->nblk = persistent_blocks(ctx, cfg->prec, true);
+  s->slots.resize(cfg->max_inflight);
+  auto dalloc = [&](void **p, size_t bytes) {
+    mbh_status st = ctx_alloc(ctx, p, bytes);
+    if (st == MBH_OK) s->dev_allocs.emplace_back(*p, bytes);
+    return st;
+  };
+  for (auto &sl : s->slots) {
+    mbh_status st;
+    if (hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming) != hipSuccess ||
+        hipHostMalloc((void **)&sl.theta_h, cap * 11 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&sl.res_h, cap * 3 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&sl.hdr_h, sizeof(WorkHeader), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&sl.items_h, s->max_items * sizeof(WorkItem), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&sl.tiles_h, s->max_tiles * sizeof(WorkTile), hipHostMallocDefault) != hipSuccess) {
+      server_free(s);
+      return mbh_fail(MBH_EDEVICE, "server host resources");
+    }
+    if ((st = dalloc((void **)&sl.theta_d, cap * 11 * sizeof(double))) != MBH_OK ||
+        (st = dalloc((void **)&sl.res_d, cap * 3 * sizeof(double))) != MBH_OK ||
+        (st = dalloc((void **)&sl.hdr_d, sizeof(WorkHeader))) != MBH_OK ||
+        (st = dalloc((void **)&sl.items_d, s->max_items * sizeof(WorkItem))) != MBH_OK ||
+        (st = dalloc((void **)&sl.tiles_d, s->max_tiles * sizeof(WorkTile))) != MBH_OK ||
+        (st = dalloc((void **)&sl.counters_d, 2 * sizeof(unsigned))) != MBH_OK ||
+        (st = dalloc((void **)&sl.wc_d, cap * sizeof(WalkerC))) != MBH_OK) {
+      server_free(s);
+      return st;
+    }
+    unsigned zero[2] = {0u, 0u};
+    if (hipMemcpy(sl.counters_d, zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess) {
+      server_free(s);
+      return mbh_fail(MBH_EDEVICE, "counter init");
+    }
+  }
+  s->thr = std::thread(server_loop, s);
+  *out = s;
+  return MBH_OK;
+}
+
+extern "C" mbh_status mbh_server_submit(mbh_server *s, int ref_index, const double *theta_host, int64_t W,
+                                        uint64_t *request_id) {
+  if (!s || !theta_host || !request_id || W < 1) return mbh_fail(MBH_EINVAL, "bad argument");
+  if (ref_index < 0 || ref_index >= (int)s->refs.size()) return mbh_fail(MBH_EINVAL, "reference index %d", ref_index);
+  if (W > s->cap_walkers)
+    return mbh_fail(MBH_EAGAIN, "request of %lld walkers exceeds the per-batch capacity %lld", (long long)W,
+                    (long long)s->cap_walkers);
+  auto r = std::make_shared<Request>();
+  r->ref = ref_index;
+  r->W = W;
+  r->theta.assign(theta_host, theta_host + W * 11);
+  r->t_submit = Clock::now();
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    r->id = s->next_id++;
+    s->live[r->id] = r;
+    s->queue.push_back(r);
+    s->stats.submitted += 1;
+  }
+  s->cv_work.notify_one();
+  *request_id = r->id;
+  return MBH_OK;
+}
+
+extern "C" mbh_status mbh_server_wait(mbh_server *s, uint64_t id, int timeout_ms, double *lnL_host,
+                                      double *dh_hh_host, double *latency_s_out) {
+  if (!s) return mbh_fail(MBH_EINVAL, "null server");
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->live.find(id);
+  if (it == s->live.end()) return mbh_fail(MBH_ENOTFOUND, "request %llu", (unsigned long long)id);
+  std::shared_ptr<Request> r = it->second;
+  auto ready = [&] { return r->done; };
+  if (timeout_ms < 0) s->cv_done.wait(lk, ready);
+  else if (!s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), ready))
+    return MBH_EAGAIN;
+  if (!s->thread_error.empty() && r->lnL.empty()) return mbh_fail(MBH_EDEVICE, "server: %s", s->thread_error.c_str());
+  if (lnL_host) std::memcpy(lnL_host, r->lnL.data(), r->W * sizeof(double));
+  if (dh_hh_host) std::memcpy(dh_hh_host, r->dhhh.data(), r->W * 2 * sizeof(double));
+  if (latency_s_out) *latency_s_out = std::chrono::duration<double>(r->t_done - r->t_submit).count();
+  s->live.erase(it);
+  return MBH_OK;
+}
+
+extern "C" mbh_status mbh_server_get_stats(const mbh_server *s, mbh_server_stats *out) {
+  if (!s || !out) return mbh_fail(MBH_EINVAL, "null argument");
+  std::lock_guard<std::mutex> g(const_cast<mbh_server *>(s)->mu);
+  *out = s->stats;
+  return MBH_OK;
+}
+
+extern "C" mbh_status mbh_server_destroy(mbh_server *s) {
+  if (!s) return MBH_OK;
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    s->stop.store(true);
+  }
+  s->cv_work.notify_all();
+  if (s->thr.joinable()) s->thr.join();
+  (void)hipSetDevice(s->ctx->device);
+  server_free(s);
+  return MBH_OK;
+}

@@ -1,0 +1,367 @@
+"""Thin ctypes binding of libmbh (include/mbh.h): argument marshalling only.
+
+Every function here forwards to the C entry point of the same name (without
+the ``mbh_`` prefix); all computation happens in the HIP kernels of
+``libmbh.so``.  PyTorch is used only for device memory and streams: device
+arguments are ``torch`` CUDA tensors whose ``data_ptr()`` is passed through,
+and the work is enqueued on ``torch.cuda.current_stream()``.
+
+If ``libmbh.so`` has not been built this module raises on import: there is no
+CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmbh.so")
+
+MBH_OK, MBH_EINVAL, MBH_ENOMEM, MBH_EBAND, MBH_EDEVICE, MBH_EAGAIN, MBH_ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
+MODEL_IMR, MODEL_TF2 = 0, 1
+MODE_22, MODE_33, MODE_44, MODE_21, MODE_32, MODE_43 = (1 << i for i in range(6))
+MODES_ALL = 0x3F
+FP64, MIXED = 0, 1
+NPARAM = 11
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'` "
+                      "(the likelihoods have no CPU fallback)")
+_L = ct.CDLL(LIB_PATH)
+
+
+class MbhError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = _L.mbh_last_error().decode()
+        super().__init__(f"{where}: {_L.mbh_strerror(status).decode()} ({status}): {msg}")
+        self.status = status
+
+
+class _RefInfo(ct.Structure):
+    _fields_ = [("model", ct.c_int32), ("n_chan", ct.c_int32), ("n_bins", ct.c_int32), ("modes", ct.c_uint32),
+                ("k_lo", ct.c_int64), ("k_hi", ct.c_int64), ("lnL0", ct.c_double), ("dd", ct.c_double),
+                ("dh0", ct.c_double), ("hh0", ct.c_double)]
+
+
+class ServerConfig(ct.Structure):
+    _fields_ = [("max_inflight", ct.c_int32), ("max_batch_walkers", ct.c_int32),
+                ("hbm_budget_bytes", ct.c_size_t), ("prec", ct.c_int)]
+
+
+class ServerStats(ct.Structure):
+    _fields_ = [("submitted", ct.c_uint64), ("completed", ct.c_uint64), ("batches", ct.c_uint64),
+                ("walkers", ct.c_uint64), ("max_walkers_in_flight", ct.c_uint64),
+                ("max_bytes_in_flight", ct.c_uint64), ("admission_waits", ct.c_uint64)]
+
+
+_vp, _dp, _i64, _u32, _i32, _d, _sz = ct.c_void_p, ct.POINTER(ct.c_double), ct.c_int64, ct.c_uint32, ct.c_int, ct.c_double, ct.c_size_t
+_pp = ct.POINTER(ct.c_void_p)
+_SIGS = {
+    "mbh_create": [_i32, _sz, _pp],
+    "mbh_destroy": [_vp],
+    "mbh_memory_in_use": [_vp, ct.POINTER(ct.c_size_t)],
+    "mbh_data_create": [_vp, _i32, _i64, _d, _d, _d, _vp, _vp, _vp, _pp],
+    "mbh_data_release": [_vp],
+    "mbh_data_inner_dd": [_vp, _dp],
+    "mbh_template_full": [_vp, _vp, _i32, _u32, _dp, _vp, _vp],
+    "mbh_build_reference_coeffs": [_vp, _vp, _i32, _u32, _dp, _i32, _vp, _pp],
+    "mbh_ref_release": [_vp],
+    "mbh_ref_get_info": [_vp, ct.POINTER(_RefInfo)],
+    "mbh_ref_export": [_vp, _dp, ct.POINTER(ct.c_int64), _dp, _dp, _dp, _dp, _dp],
+    "mbh_loglike_heterodyned": [_vp, _vp, _vp, _i64, _i32, _vp, _vp, _vp],
+    "mbh_loglike_full": [_vp, _vp, _i32, _u32, _vp, _i64, _i32, _vp, _vp, _vp],
+    "mbh_batch_create": [_vp, _i32, _pp, _pp, ct.POINTER(ct.c_int64), _pp, _pp, _i32, _pp],
+    "mbh_batch_launch": [_vp, _vp],
+    "mbh_batch_release": [_vp],
+    "mbh_autotune_heterodyned": [_vp, _vp, _i64, _i32, ct.POINTER(ct.c_int)],
+    "mbh_lanes_for": [_vp, _i32, _i32, _i32, ct.POINTER(ct.c_int)],
+    "mbh_set_lanes": [_vp, _i32, _i32, _i32, _i32],
+    "mbh_autotune_save": [_vp, ct.c_char_p],
+    "mbh_autotune_load": [_vp, ct.c_char_p],
+    "mbh_server_create": [_vp, _i32, _pp, ct.POINTER(ServerConfig), _pp],
+    "mbh_server_submit": [_vp, _i32, _dp, _i64, ct.POINTER(ct.c_uint64)],
+    "mbh_server_wait": [_vp, ct.c_uint64, _i32, _dp, _dp, _dp],
+    "mbh_server_get_stats": [_vp, ct.POINTER(ServerStats)],
+    "mbh_server_destroy": [_vp],
+}
+for _name, _args in _SIGS.items():
+    _f = getattr(_L, _name)
+    _f.argtypes = _args
+    _f.restype = ct.c_int32
+_L.mbh_last_error.restype = ct.c_char_p
+_L.mbh_last_error.argtypes = []
+_L.mbh_strerror.restype = ct.c_char_p
+_L.mbh_strerror.argtypes = [ct.c_int32]
+
+
+def _check(status: int, where: str):
+    if status != MBH_OK:
+        raise MbhError(status, where)
+
+
+def _stream(stream=None) -> int:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+def _dev_ptr(t: torch.Tensor, dtype, shape=None) -> int:
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"expected a contiguous CUDA tensor of {dtype}, got {t.dtype} on {t.device}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"expected shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t.data_ptr()
+
+
+def _host_theta(theta) -> np.ndarray:
+    th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).reshape(-1))
+    if th.size != NPARAM:
+        raise ValueError("theta must have 11 entries")
+    return th
+
+
+# ------------------------------------------------------------------ handles
+class Context:
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        h = ct.c_void_p()
+        _check(_L.mbh_create(device, hbm_budget_bytes, ct.byref(h)), "mbh_create")
+        self.h = h
+        self.device = device
+
+    def memory_in_use(self) -> int:
+        v = ct.c_size_t()
+        _check(_L.mbh_memory_in_use(self.h, ct.byref(v)), "mbh_memory_in_use")
+        return v.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            _L.mbh_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Data:
+    def __init__(self, ctx: Context, h, n_chan, n_f, f0, df, t_obs, keep):
+        self.ctx, self.h = ctx, h
+        self.n_chan, self.n_f, self.f0, self.df, self.t_obs = n_chan, n_f, f0, df, t_obs
+        self._keep = keep
+
+    def inner_dd(self) -> float:
+        v = ct.c_double()
+        _check(_L.mbh_data_inner_dd(self.h, ct.byref(v)), "mbh_data_inner_dd")
+        return v.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            _L.mbh_data_release(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Reference:
+    def __init__(self, ctx: Context, h):
+        self.ctx, self.h = ctx, h
+        info = _RefInfo()
+        _check(_L.mbh_ref_get_info(h, ct.byref(info)), "mbh_ref_get_info")
+        self.info = {k: getattr(info, k) for k, _ in _RefInfo._fields_}
+        self.n_bins, self.n_chan = info.n_bins, info.n_chan
+
+    def export(self) -> dict:
+        nb, nc = self.n_bins, self.n_chan
+        edges = np.zeros(nb + 1)
+        kb = np.zeros(nb + 1, dtype=np.int64)
+        A0, A1 = np.zeros((nc, nb, 2)), np.zeros((nc, nb, 2))
+        B0, B1 = np.zeros((nc, nb)), np.zeros((nc, nb))
+        h0 = np.zeros((nc, nb + 1, 2))
+        P = lambda a: a.ctypes.data_as(_dp)
+        _check(_L.mbh_ref_export(self.h, P(edges), kb.ctypes.data_as(ct.POINTER(ct.c_int64)), P(A0), P(A1),
+                                 P(B0), P(B1), P(h0)), "mbh_ref_export")
+        return dict(edges=edges, kb=kb, A0=A0[..., 0] + 1j * A0[..., 1], A1=A1[..., 0] + 1j * A1[..., 1],
+                    B0=B0, B1=B1, h0_edges=h0[..., 0] + 1j * h0[..., 1])
+
+    def close(self):
+        if getattr(self, "h", None):
+            _L.mbh_ref_release(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------ entry points
+def data_create(ctx: Context, d: torch.Tensor, psd: torch.Tensor, f0: float, df: float, t_obs: float,
+                stream=None) -> Data:
+    """mbh_data_create: d complex128 [C][N] and psd float64 [C][N] on the device."""
+    if d.dtype != torch.complex128:
+        raise ValueError("d must be complex128")
+    d = d.contiguous()
+    dr = torch.view_as_real(d)
+    C, N = d.shape
+    h = ct.c_void_p()
+    _check(_L.mbh_data_create(ctx.h, C, N, f0, df, t_obs, _dev_ptr(dr, torch.float64, (C, N, 2)),
+                              _dev_ptr(psd, torch.float64, (C, N)), _stream(stream), ct.byref(h)),
+           "mbh_data_create")
+    return Data(ctx, h, C, N, f0, df, t_obs, keep=(d, psd))
+
+
+def template_full(ctx: Context, data: Data, model: int, modes: int, theta, stream=None) -> torch.Tensor:
+    """mbh_template_full: complex128 [C][N] template on the data grid."""
+    th = _host_theta(theta)
+    out = torch.empty((data.n_chan, data.n_f), dtype=torch.complex128, device=f"cuda:{ctx.device}")
+    _check(_L.mbh_template_full(ctx.h, data.h, model, modes, th.ctypes.data_as(_dp),
+                                torch.view_as_real(out).data_ptr(), _stream(stream)), "mbh_template_full")
+    return out
+
+
+def build_reference_coeffs(ctx: Context, data: Data, model: int, modes: int, theta0, n_bins: int,
+                           stream=None) -> Reference:
+    th = _host_theta(theta0)
+    h = ct.c_void_p()
+    _check(_L.mbh_build_reference_coeffs(ctx.h, data.h, model, modes, th.ctypes.data_as(_dp), n_bins,
+                                         _stream(stream), ct.byref(h)), "mbh_build_reference_coeffs")
+    return Reference(ctx, h)
+
+
+def loglike_heterodyned(ctx: Context, ref: Reference, theta: torch.Tensor, prec: int = FP64,
+                        lnL: torch.Tensor | None = None, dh_hh: torch.Tensor | None = None, stream=None):
+    W = theta.shape[0]
+    tp = _dev_ptr(theta, torch.float64, (W, NPARAM))
+    if lnL is None:
+        lnL = torch.empty(W, dtype=torch.float64, device=theta.device)
+    dp = _dev_ptr(dh_hh, torch.float64, (W, 2)) if dh_hh is not None else None
+    _check(_L.mbh_loglike_heterodyned(ctx.h, ref.h, tp, W, prec, _dev_ptr(lnL, torch.float64, (W,)), dp,
+                                      _stream(stream)), "mbh_loglike_heterodyned")
+    return lnL
+
+
+def loglike_full(ctx: Context, data: Data, model: int, modes: int, theta: torch.Tensor, prec: int = FP64,
+                 lnL: torch.Tensor | None = None, dh_hh: torch.Tensor | None = None, stream=None):
+    W = theta.shape[0]
+    tp = _dev_ptr(theta, torch.float64, (W, NPARAM))
+    if lnL is None:
+        lnL = torch.empty(W, dtype=torch.float64, device=theta.device)
+    dp = _dev_ptr(dh_hh, torch.float64, (W, 2)) if dh_hh is not None else None
+    _check(_L.mbh_loglike_full(ctx.h, data.h, model, modes, tp, W, prec, _dev_ptr(lnL, torch.float64, (W,)), dp,
+                               _stream(stream)), "mbh_loglike_full")
+    return lnL
+
+
+def lanes_for(ctx: Context, n_bins: int, n_modes: int, prec: int) -> int:
+    v = ct.c_int()
+    _check(_L.mbh_lanes_for(ctx.h, n_bins, n_modes, prec, ct.byref(v)), "mbh_lanes_for")
+    return v.value
+
+
+def set_lanes(ctx: Context, n_bins: int, n_modes: int, prec: int, lanes: int):
+    _check(_L.mbh_set_lanes(ctx.h, n_bins, n_modes, prec, lanes), "mbh_set_lanes")
+
+
+def autotune_heterodyned(ctx: Context, ref: Reference, W: int, prec: int) -> int:
+    v = ct.c_int()
+    _check(_L.mbh_autotune_heterodyned(ctx.h, ref.h, W, prec, ct.byref(v)), "mbh_autotune_heterodyned")
+    return v.value
+
+
+def autotune_save(ctx: Context, path: str):
+    _check(_L.mbh_autotune_save(ctx.h, path.encode()), "mbh_autotune_save")
+
+
+def autotune_load(ctx: Context, path: str):
+    _check(_L.mbh_autotune_load(ctx.h, path.encode()), "mbh_autotune_load")
+
+
+class Batch:
+    """mbh_batch_*: one persistent, graph-captured launch over many items."""
+
+    def __init__(self, ctx: Context, refs, thetas, lnLs, dh_hhs=None, prec: int = FP64):
+        n = len(refs)
+        self.ctx = ctx
+        arr = lambda xs: (ct.c_void_p * n)(*xs)
+        Ws = (ct.c_int64 * n)(*[t.shape[0] for t in thetas])
+        tp = arr([_dev_ptr(t, torch.float64, (t.shape[0], NPARAM)) for t in thetas])
+        lp = arr([_dev_ptr(l, torch.float64, (t.shape[0],)) for l, t in zip(lnLs, thetas)])
+        dp = None
+        if dh_hhs is not None:
+            dp = arr([_dev_ptr(x, torch.float64, (t.shape[0], 2)) if x is not None else None
+                      for x, t in zip(dh_hhs, thetas)])
+        h = ct.c_void_p()
+        _check(_L.mbh_batch_create(ctx.h, n, arr([r.h for r in refs]), tp, Ws, lp, dp, prec, ct.byref(h)),
+               "mbh_batch_create")
+        self.h = h
+        self._keep = (refs, thetas, lnLs, dh_hhs)
+
+    def launch(self, stream=None):
+        _check(_L.mbh_batch_launch(self.h, _stream(stream)), "mbh_batch_launch")
+
+    def close(self):
+        if getattr(self, "h", None):
+            _L.mbh_batch_release(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """mbh_server_*: continuous-batching request server over resident references."""
+
+    def __init__(self, ctx: Context, refs, max_inflight=2, max_batch_walkers=65536, hbm_budget_bytes=1 << 30,
+                 prec: int = MIXED):
+        cfg = ServerConfig(max_inflight, max_batch_walkers, hbm_budget_bytes, prec)
+        n = len(refs)
+        h = ct.c_void_p()
+        _check(_L.mbh_server_create(ctx.h, n, (ct.c_void_p * n)(*[r.h for r in refs]), ct.byref(cfg),
+                                    ct.byref(h)), "mbh_server_create")
+        self.h, self.ctx, self._refs = h, ctx, refs
+
+    def submit(self, ref_index: int, theta: np.ndarray) -> int:
+        th = np.ascontiguousarray(theta, dtype=np.float64).reshape(-1, NPARAM)
+        rid = ct.c_uint64()
+        _check(_L.mbh_server_submit(self.h, ref_index, th.ctypes.data_as(_dp), th.shape[0], ct.byref(rid)),
+               "mbh_server_submit")
+        return rid.value
+
+    def wait(self, rid: int, W: int, timeout_ms: int = -1, want_dh_hh: bool = False):
+        lnL = np.zeros(W)
+        dh = np.zeros((W, 2)) if want_dh_hh else None
+        lat = ct.c_double()
+        st = _L.mbh_server_wait(self.h, rid, timeout_ms, lnL.ctypes.data_as(_dp),
+                                dh.ctypes.data_as(_dp) if dh is not None else None, ct.byref(lat))
+        if st == MBH_EAGAIN:
+            return None
+        _check(st, "mbh_server_wait")
+        return (lnL, dh, lat.value) if want_dh_hh else (lnL, lat.value)
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        _check(_L.mbh_server_get_stats(self.h, ct.byref(s)), "mbh_server_get_stats")
+        return {k: getattr(s, k) for k, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            _L.mbh_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
