@@ -221,11 +221,12 @@ def main():
         lnls = [torch.empty(len(w), dtype=torch.float64, device="cuda") for w in walkers]
         batch = M.Batch(ctx, [it["ref"] for it in S.items], thetas, lnls, prec=prec)
         wall, mean_s, per = time_batch(M, ctx, batch, args.steps, args.warmup, stream)
+        routed = batch.routed() / (args.steps + args.warmup)
         res[name] = dict(wall=wall, kernel_s=mean_s, lnl=np.concatenate([l.cpu().numpy() for l in lnls]),
-                         lanes=M.lanes_for(ctx, N_BINS, 1, prec))
+                         lanes=M.lanes_for(ctx, N_BINS, 1, prec), routed=routed)
         batch.close()
         log(f"[bench] {name}: {W_total} walkers/step, {mean_s * 1e6:.1f} us/step (events), wall {wall:.3f} s, "
-            f"lanes {res[name]['lanes']}")
+            f"lanes {res[name]['lanes']}, FP64-recomputed walkers/step {routed:.1f}")
     dmix = float(np.max(np.abs(res["mixed"]["lnl"] - res["fp64"]["lnl"])))
     ms_per_step = res["mixed"]["wall"] / args.steps * 1e3
     value = W_total * args.steps / res["mixed"]["wall"]
@@ -242,6 +243,7 @@ def main():
                    "walkers_per_step": W_total, "n_bins": N_BINS, "launch": "mbh_batch graph replay"},
         "fp64_evals_per_s": fp64_value, "fp64_ms_per_step": res["fp64"]["wall"] / args.steps * 1e3,
         "mixed_speedup_vs_fp64": value / fp64_value, "max_abs_dlnL_mixed_vs_fp64": dmix,
+        "mixed_fp64_recomputed_fraction": res["mixed"]["routed"] / W_total,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_ALU_TFLOPS, "traffic": None,
                      "kernel": "k_het_work<float>", "kernel_us": res["mixed"]["kernel_s"] * 1e6,

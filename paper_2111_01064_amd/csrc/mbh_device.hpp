@@ -93,6 +93,7 @@ struct WalkerC {
   double ph_max, dph_max;     // raw phase and slope at f_max
   double AN;                  // amplitude prefactor (times kAmpScale)
   double lam_num;             // (f1 - fRD)^2 + fD^2
+  double inv_fD;              // 1 / fD
   double tref;
   double rel[6];              // relative amplitude coefficient of each mode
   // sky: propagation direction and polarisation basis
@@ -106,9 +107,10 @@ struct WalkerC {
 __device__ __forceinline__ double sq(double x) { return x * x; }
 
 // closed-form spin-weight -2 harmonics (real part at phi = 0) for the
-// (l, +-m) pairs of the six modes, in terms of cos(iota), cos/sin(iota/2)
-__device__ inline void ylm_pair(int mi, double iota, double &yp, double &ym, int &lsign) {
-  double c = cos(iota), s = sin(iota), ch = cos(0.5 * iota), sh = sin(0.5 * iota);
+// (l, +-m) pairs of the six modes, in terms of c = cos(iota), s = sin(iota)
+// and ch, sh = cos, sin(iota/2)
+__device__ inline void ylm_pair(int mi, double c, double s, double ch, double sh, double &yp, double &ym,
+                                int &lsign) {
   const double r5_64pi = 0.15769578262626002;  // sqrt(5 / (64 pi))
   const double r5_16pi = 0.31539156525252005;  // sqrt(5 / (16 pi))
   const double r21_2pi = 1.8281831978578629;   // sqrt(21 / (2 pi))
@@ -172,7 +174,7 @@ __device__ inline void raw_phase64(const WalkerC &w, double f, double &ph, doubl
   }
 }
 
-__device__ inline void walker_setup(const double *__restrict__ th, int model, WalkerC &w) {
+__device__ inline void walker_setup(const double *__restrict__ th, int model, uint32_t modes, WalkerC &w) {
   w.model = model;
   w.pad0 = w.pad1 = 0;
   if (model == 1) {  // chirp
@@ -214,6 +216,7 @@ __device__ inline void walker_setup(const double *__restrict__ th, int model, Wa
     w.dP1 = (w.d5 * iv5 + w.d3 * iv3 + w.d2 * iv2) / w.f1;
   }
   w.lam_num = sq(w.f1 - w.fRD) + w.fD * w.fD;
+  w.inv_fD = 1.0 / w.fD;
   w.L1 = w.fD / w.lam_num;
   w.at1 = atan((w.f1 - w.fRD) / w.fD);
   raw_phase64(w, w.fmax, w.ph_max, w.dph_max);
@@ -238,13 +241,22 @@ __device__ inline void walker_setup(const double *__restrict__ th, int model, Wa
   w.qx = -sp * sl - cp * sb * cl;
   w.qy = sp * cl - cp * sb * sl;
   w.qz = cp * cb;
-  double phiref = th[5], iota = th[6];
+  // polarisation weights of the active modes only; e^{i m phi_ref} as powers of e^{i phi_ref}
+  double ci, si, chi, shi, s1, c1;
+  sincos(th[6], &si, &ci);
+  sincos(0.5 * th[6], &shi, &chi);
+  sincos(th[5], &s1, &c1);
   for (int mi = 0; mi < kNumModes; ++mi) {
+    if (!(modes & (1u << mi))) continue;
     double yp, ym;
     int ls;
-    ylm_pair(mi, iota, yp, ym, ls);
-    double sm, cm;
-    sincos(kModeM[mi] * phiref, &sm, &cm);
+    ylm_pair(mi, ci, si, chi, shi, yp, ym, ls);
+    double cm = c1, sm = s1;
+    for (int k = 1; k < kModeM[mi]; ++k) {
+      double t = cm * c1 - sm * s1;
+      sm = sm * c1 + cm * s1;
+      cm = t;
+    }
     w.kp[mi] = 0.5 * (yp + ls * ym);
     w.kc[mi] = 0.5 * (yp - ls * ym);
     w.eph[mi][0] = cm;
@@ -253,73 +265,78 @@ __device__ inline void walker_setup(const double *__restrict__ th, int model, Wa
 }
 
 // ---- precision-specific primitives ---------------------------------------
+// FP64 reciprocal and cube root from hardware FP32 estimates refined by two
+// Newton steps in FP64 (quadratic convergence from ~1e-7 to below the FP64
+// rounding level); used by both paths in place of IEEE division sequences.
+__device__ __forceinline__ double rcp64_nr(double x) {
+  double y = (double)__builtin_amdgcn_rcpf((float)x);
+  y = y * fma(-x, y, 2.0);
+  return y * fma(-x, y, 2.0);
+}
+__device__ __forceinline__ double cbrt64_nr(double x) {
+  double v = (double)__builtin_amdgcn_exp2f(__builtin_amdgcn_logf((float)x) * (1.0f / 3.0f));
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    double v2 = v * v;
+    v = v - fma(v2, v, -x) * (double)__builtin_amdgcn_rcpf((float)(3.0 * v2));
+  }
+  return v;
+}
+
 template <typename R>
 struct Prec;
 
 template <>
 struct Prec<double> {
-  static __device__ __forceinline__ double cbrt64(double x) { return cbrt(x); }
-  static __device__ __forceinline__ double rcp64(double x) { return 1.0 / x; }
   static __device__ __forceinline__ void sincos_r(double x, double &s, double &c) { sincos(x, &s, &c); }
   static __device__ __forceinline__ void sincos_alpha(double a, double &s, double &c) { sincos(a, &s, &c); }
   static __device__ __forceinline__ double atan_small(double x) { return atan(x); }
   static __device__ __forceinline__ double rsqrt_r(double x) { return 1.0 / sqrt(x); }
+  static __device__ __forceinline__ double sqrt_r(double x) { return sqrt(x); }
   static constexpr int kSincTerms = 20;
 };
 
 template <>
 struct Prec<float> {
-  // cbrt: FP32 seed + one Newton step in FP64 (relative error ~1e-14)
-  static __device__ __forceinline__ double cbrt64(double x) {
-    double v = (double)cbrtf((float)x);
-    float inv3v2 = 1.0f / (3.0f * (float)(v * v));
-    return v - (v * v * v - x) * (double)inv3v2;
-  }
-  // reciprocal: FP32 seed + two Newton steps in FP64
-  static __device__ __forceinline__ double rcp64(double x) {
-    double y = (double)(1.0f / (float)x);
-    y = y * fma(-x, y, 2.0);
-    return y * fma(-x, y, 2.0);
-  }
   static __device__ __forceinline__ void sincos_r(float x, float &s, float &c) { sincosf(x, &s, &c); }
   static __device__ __forceinline__ void sincos_alpha(double a, double &s, double &c) { sincos(a, &s, &c); }
   static __device__ __forceinline__ float atan_small(float x) { return atanf(x); }
-  // hardware reciprocal square root plus one Newton step: the raw estimate's
-  // error is not centred, and |n|^2 scales every link projection alike
-  static __device__ __forceinline__ float rsqrt_r(float x) {
-    float y = rsqrtf(x);
-    return y * (1.5f - 0.5f * x * y * y);
-  }
+  static __device__ __forceinline__ float rsqrt_r(float x) { return rsqrtf(x); }
+  static __device__ __forceinline__ float sqrt_r(float x) { return sqrtf(x); }
   static constexpr int kSincTerms = 14;
 };
 
 // (2,2) phase aligned at f_max, its slope, and the amplitude at (2,2)
-// frequency fp; amplitude scaled by v^vpow (v = (pi M fp)^(1/3))
+// frequency fp; amplitude scaled by v^vpow (v = (pi M fp)^(1/3)).  Phase and
+// slope are FP64; the frequency-dependent amplitude factor (v^-7/2 times the
+// ringdown Lorentzian) is formed in R and multiplied by the per-walker FP64
+// prefactor, so its rounding varies from edge to edge and never acts as a
+// coherent shift of D_L.
 template <typename R>
 __device__ __forceinline__ void wf22(const WalkerC &w, double fp, int vpow, double &ph, double &dph,
                                      double &amp) {
-  double v = Prec<R>::cbrt64(w.piM * fp);
-  double iv = Prec<R>::rcp64(v);
-  double lam = 1.0;
+  double v = cbrt64_nr(w.piM * fp);
+  double iv = rcp64_nr(v);
+  R lam2 = (R)1;
   if (fp <= w.f1) {
     double iv2 = iv * iv, iv3 = iv2 * iv, iv5 = iv3 * iv2;
     ph = w.c5 * iv5 + w.c3 * iv3 + w.c2 * iv2;
-    dph = (w.d5 * iv5 + w.d3 * iv3 + w.d2 * iv2) * Prec<R>::rcp64(fp);
+    dph = (w.d5 * iv5 + w.d3 * iv3 + w.d2 * iv2) * rcp64_nr(fp);
   } else {
     double x = fp - w.f1, y = fp - w.fRD;
-    double den = y * y + w.fD * w.fD;
-    R Lr = (R)(w.fD / den);
-    R at = Prec<R>::atan_small((R)(y / w.fD));
+    double rden = rcp64_nr(y * y + w.fD * w.fD);
+    R Lr = (R)(w.fD * rden);
+    R at = Prec<R>::atan_small((R)(y * w.inv_fD));
     // the arctan difference and the slope correction are bounded by a few rad
     ph = w.P1 + w.dP1 * x + kKappa * ((double)(at - (R)w.at1) - w.L1 * x);
     dph = w.dP1 + kKappa * ((double)Lr - w.L1);
-    lam = sqrt(w.lam_num / den);
+    lam2 = (R)(w.lam_num * rden);
   }
   ph = ph - w.ph_max - w.dph_max * (fp - w.fmax);
   dph = dph - w.dph_max;
-  // the amplitude is kept in FP64: a rounded per-walker amplitude would act
-  // as a coherent shift of D_L across all frequencies
-  double a = w.AN * (iv * iv * iv * sqrt(iv)) * lam;
+  R ivr = (R)iv;
+  R af = ivr * ivr * ivr * Prec<R>::sqrt_r(ivr * lam2);
+  double a = w.AN * (double)af;
   for (int k = 0; k < vpow; ++k) a *= v;
   amp = a;
 }
@@ -453,10 +470,11 @@ __device__ __forceinline__ bool template_point(const WalkerC &w, uint32_t modes,
                                                cx<double> s[3], double &psi) {
   if (w.model == 1) {  // 0PN chirp, one channel
     double x = w.piMc * f;
-    double cx1 = Prec<R>::cbrt64(x);
+    double cx1 = cbrt64_nr(x);
     double x53 = x * cx1 * cx1;
-    psi = w.phic - (3.0 / 128.0) * Prec<R>::rcp64(x53) - kTwoPi * f * w.tc;
-    double a = w.amp * Prec<R>::rcp64(f * sqrt(Prec<R>::cbrt64(f)));
+    psi = w.phic - (3.0 / 128.0) * rcp64_nr(x53) - kTwoPi * f * w.tc;
+    R fr = (R)f;
+    double a = w.amp * (double)((R)1 / (fr * Prec<R>::sqrt_r(cbrt(fr))));
     s[0] = mk<double>(a, 0.0);
     s[1] = s[2] = mk<double>(0.0, 0.0);
     return true;

@@ -52,10 +52,10 @@ __device__ __forceinline__ void block_sum(double v[NV], double *sh /* [NV][kBloc
 
 // ---------------------------------------------------------------- a1: ingest
 static __global__ __launch_bounds__(128) void k_walker_setup(const double *__restrict__ theta, int64_t W, int model,
-                                                      WalkerC *__restrict__ out) {
+                                                             uint32_t modes, WalkerC *__restrict__ out) {
   int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= W) return;
-  walker_setup(theta + w * 11, model, out[w]);
+  walker_setup(theta + w * 11, model, modes, out[w]);
 }
 
 // ---------------------------------------------------------------- data
@@ -82,14 +82,16 @@ static __global__ __launch_bounds__(kBlock) void k_whiten(const double *__restri
   if (threadIdx.x == 0) part[blockIdx.x] = v[0];
 }
 
-// out[i] = sum_b part[b * stride + i] for i < n_out (fixed order); one block
-static __global__ void k_sum_partials(const double *__restrict__ part, int n_part, int stride, int n_out,
-                               double *__restrict__ out) {
-  for (int i = threadIdx.x; i < n_out; i += blockDim.x) {
-    double s = 0.0;
-    for (int b = 0; b < n_part; ++b) s += part[(int64_t)b * stride + i];
-    out[i] = s;
-  }
+// out[i] = sum_b part[b * stride + i] for i < n_out: one wavefront per
+// output, lanes stride over the partials, fixed butterfly (grid n_out x 64)
+static __global__ __launch_bounds__(64) void k_sum_partials(const double *__restrict__ part, int n_part, int stride,
+                                                            int n_out, double *__restrict__ out) {
+  const int i = blockIdx.x;
+  if (i >= n_out) return;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < n_part; b += 64) s += part[(int64_t)b * stride + i];
+  s = wave_sum(s);
+  if (threadIdx.x == 0) out[i] = s;
 }
 
 static __global__ void k_init_band(unsigned long long *band) {
@@ -237,6 +239,23 @@ static __global__ __launch_bounds__(64) void k_ref_edges(const WalkerC *__restri
 }
 
 // ---------------------------------------------------------------- a2-a7: heterodyned
+// FP64 recomputation queue of the mixed path.  The FP32 response leaves a
+// per-edge relative error of ~1e-7 on r - 1; its effect on lnL is estimated
+// per walker as kMixedErrScale * sqrt(S / 2), S = sum over bins and channels
+// of |dT/d delta_0|^2 + 4 |dT/d delta_1|^2 (the gradient of the bin term
+// with respect to the edge values).  kMixedErrScale bounds the measured ratio
+// |lnL_mixed - lnL_fp64| / sqrt(S / 2) over tempered walker clouds at SNR
+// 100-1000; walkers whose estimate exceeds kMixedRouteTol are queued and
+// recomputed in FP64, so the mixed result stays within 1e-3 of FP64.
+constexpr double kMixedErrScale = 6e-7;
+constexpr double kMixedRouteTol = 5e-4;
+
+struct RouteQ {
+  unsigned int *count;  // entries queued by the mixed pass (null: no routing)
+  int2 *list;           // (item, walker)
+  int item;
+};
+
 // One lane group of G lanes per walker; lane gl evaluates edges gl, gl+G, ...
 // The right neighbour edge of each bin comes from lane gl+1 (rotate within
 // the group); the last lane's bin closes one iteration later with lane 0's
@@ -244,15 +263,20 @@ static __global__ __launch_bounds__(64) void k_ref_edges(const WalkerC *__restri
 // a fixed butterfly, so a walker's result depends only on its inputs and G.
 template <typename R, int G, bool DH>
 __device__ __forceinline__ void het_walker(const HetRef &ref, const WalkerC *__restrict__ wc, int64_t w,
-                                           int64_t W, double *__restrict__ lnL, double *__restrict__ dhhh) {
+                                           int64_t W, double *__restrict__ lnL, double *__restrict__ dhhh,
+                                           RouteQ rq) {
+  constexpr bool EST = sizeof(R) == 4;
   const int lane = threadIdx.x & 63;
   const int gl = lane & (G - 1);
+  // with one walker per wavefront the walker index is wave-uniform: say so,
+  // so that the walker constants live in scalar registers
+  if constexpr (G == 64) w = (int64_t)__builtin_amdgcn_readfirstlane((int)w);
   const bool active = w < W;
   const WalkerC &c = wc[active ? w : 0];
   const bool valid = active && c.valid;
   const int Nb = ref.n_bins, E = Nb + 1, C = ref.n_chan;
   const int n_iter = (E + G - 1) / G;
-  double acc = 0.0, a_dh = 0.0, a_hh = 0.0;
+  double acc = 0.0, a_dh = 0.0, a_hh = 0.0, a_s = 0.0;
   cx<double> dprev[3];
 #pragma unroll
   for (int ch = 0; ch < 3; ++ch) dprev[ch] = mk<double>(0.0, 0.0);
@@ -314,6 +338,12 @@ __device__ __forceinline__ void het_walker(const HetRef &ref, const WalkerC *__r
         double m0 = d0r * d0r + d0i * d0i;
         double x01 = d0r * d1r + d0i * d1i;
         acc += 4.0 * re_a - 2.0 * (k[4] * m0 + 2.0 * k[5] * x01);
+        if constexpr (EST) {
+          // gradient of the bin term (without its factor 4)
+          double g0r = k[0] - k[4] * d0r - k[5] * d1r, g0i = k[1] - k[4] * d0i - k[5] * d1i;
+          double g1r = k[2] - k[5] * d0r, g1i = k[3] - k[5] * d0i;
+          a_s += g0r * g0r + g0i * g0i + 4.0 * (g1r * g1r + g1i * g1i);
+        }
         if constexpr (DH) {
           // Z[d,h] - <d|h0> = 4 Re[A0 conj(d0) + A1 conj(d1)], A = (A - B) + B
           a_dh += 4.0 * (re_a + k[4] * d0r + k[5] * d1r);
@@ -330,9 +360,20 @@ __device__ __forceinline__ void het_walker(const HetRef &ref, const WalkerC *__r
 #pragma unroll
   for (int off = G / 2; off >= 1; off >>= 1) {
     acc += __shfl_xor(acc, off, 64);
+    if constexpr (EST) a_s += __shfl_xor(a_s, off, 64);
     if constexpr (DH) {
       a_dh += __shfl_xor(a_dh, off, 64);
       a_hh += __shfl_xor(a_hh, off, 64);
+    }
+  }
+  if constexpr (EST) {
+    // S carries the bin-term gradient without its factor 4: sqrt(S_true / 2) = sqrt(8 S)
+    if (valid && rq.count && kMixedErrScale * sqrt(8.0 * a_s) > kMixedRouteTol) {
+      if (gl == 0) {
+        unsigned int slot = atomicAdd(rq.count, 1u);
+        rq.list[slot] = make_int2(rq.item, (int)w);
+      }
+      return;  // the FP64 recomputation writes this walker's outputs
     }
   }
   if (active && gl == 0) {
@@ -348,9 +389,13 @@ __device__ __forceinline__ void het_walker(const HetRef &ref, const WalkerC *__r
 
 template <typename R, int G, bool DH>
 __global__ __launch_bounds__(kBlock) void k_het(HetRef ref, const WalkerC *__restrict__ wc, int64_t W,
-                                                double *__restrict__ lnL, double *__restrict__ dhhh) {
+                                                double *__restrict__ lnL, double *__restrict__ dhhh, RouteQ rq) {
   const int64_t w = (int64_t)blockIdx.x * (kBlock / G) + threadIdx.x / G;
-  het_walker<R, G, DH>(ref, wc, w, W, lnL, dhhh);
+  het_walker<R, G, DH>(ref, wc, w, W, lnL, dhhh, rq);
+}
+
+static __global__ void k_zero_u32(unsigned int *p, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
 }
 
 // ---------------------------------------------------------------- a8: full grid
@@ -438,14 +483,19 @@ __global__ __launch_bounds__(kBlock) void k_full(const typename DataPtrs<R>::R2 
   }
 }
 
-static __global__ void k_full_reduce(const double *__restrict__ part, int n_fc, int64_t W, int nv,
-                              const WalkerC *__restrict__ wc, double *__restrict__ lnL,
-                              double *__restrict__ dhhh) {
-  int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// one wavefront per walker: lanes stride over the frequency chunks, fixed butterfly
+static __global__ __launch_bounds__(kBlock) void k_full_reduce(const double *__restrict__ part, int n_fc, int64_t W,
+                                                               int nv, const WalkerC *__restrict__ wc,
+                                                               double *__restrict__ lnL, double *__restrict__ dhhh) {
+  const int64_t w = (int64_t)blockIdx.x * (kBlock / 64) + threadIdx.x / 64;
   if (w >= W) return;
+  const int lane = threadIdx.x & 63;
   double s[3] = {0.0, 0.0, 0.0};
-  for (int i = 0; i < nv; ++i)
-    for (int fc = 0; fc < n_fc; ++fc) s[i] += part[((int64_t)i * n_fc + fc) * W + w];
+  for (int i = 0; i < nv; ++i) {
+    for (int fc = lane; fc < n_fc; fc += 64) s[i] += part[((int64_t)i * n_fc + fc) * W + w];
+    s[i] = wave_sum(s[i]);
+  }
+  if (lane != 0) return;
   bool ok = wc[w].valid;
   lnL[w] = ok ? -0.5 * s[0] : -INFINITY;
   if (dhhh) {

@@ -16,6 +16,7 @@
 #include "mbh.h"
 #include "mbh_internal.hpp"
 #include "mbh_kernels.hpp"
+#include "mbh_work.hpp"
 
 using namespace mbh;
 
@@ -260,13 +261,14 @@ static mbh_status check_model(const mbh_data *d, int model, uint32_t modes) {
 }
 
 // walker constants of one host parameter vector, on the device
-static mbh_status setup_one(Scratch &sc, const double *theta_host, int model, WalkerC **wc_out, bool *valid) {
+static mbh_status setup_one(Scratch &sc, const double *theta_host, int model, uint32_t modes, WalkerC **wc_out,
+                            bool *valid) {
   double *th = nullptr;
   MBH_TRY(sc.get(&th, 11));
   WalkerC *wc = nullptr;
   MBH_TRY(sc.get(&wc, 1));
   HIP_TRY(hipMemcpyAsync(th, theta_host, 11 * sizeof(double), hipMemcpyHostToDevice, sc.st));
-  hipLaunchKernelGGL(k_walker_setup, dim3(1), dim3(64), 0, sc.st, th, (int64_t)1, model, wc);
+  hipLaunchKernelGGL(k_walker_setup, dim3(1), dim3(64), 0, sc.st, th, (int64_t)1, model, modes, wc);
   int32_t v = 0;
   HIP_TRY(hipMemcpyAsync(&v, &wc->valid, sizeof(int32_t), hipMemcpyDeviceToHost, sc.st));
   HIP_TRY(hipStreamSynchronize(sc.st));
@@ -283,7 +285,7 @@ extern "C" mbh_status mbh_template_full(mbh_ctx *ctx, const mbh_data *data, int 
   Scratch sc(ctx, st);
   WalkerC *wc = nullptr;
   bool valid = false;
-  MBH_TRY(setup_one(sc, theta_host, model, &wc, &valid));
+  MBH_TRY(setup_one(sc, theta_host, model, modes, &wc, &valid));
   if (!valid) return mbh_fail(MBH_EINVAL, "theta outside the model domain");
   hipLaunchKernelGGL(k_template_grid, dim3((unsigned)((data->n_f + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
                      wc, modes, data->n_chan, data->n_f, data->f0, data->df, data->t_obs, (double2 *)h_dev);
@@ -339,7 +341,7 @@ extern "C" mbh_status mbh_build_reference_coeffs(mbh_ctx *ctx, const mbh_data *d
   Scratch sc(ctx, st);
   WalkerC *wc = nullptr;
   bool valid = false;
-  MBH_TRY(setup_one(sc, theta0_host, model, &wc, &valid));
+  MBH_TRY(setup_one(sc, theta0_host, model, modes, &wc, &valid));
   if (!valid) return mbh_fail(MBH_EINVAL, "theta0 outside the model domain");
 
   // pass 1: h0 on the grid, band, lnL(h0) pieces
@@ -354,7 +356,7 @@ extern "C" mbh_status mbh_build_reference_coeffs(mbh_ctx *ctx, const mbh_data *d
   hipLaunchKernelGGL(k_init_band, dim3(1), dim3(1), 0, st, band);
   hipLaunchKernelGGL(k_ref_grid, dim3(nb1), dim3(kBlock), 0, st, wc, modes, C, N, data->f0, data->df,
                      data->t_obs, data->dw64, data->sw64, h0w, band, part1);
-  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, st, part1, nb1, 3, 3, sums1);
+  hipLaunchKernelGGL(k_sum_partials, dim3(3), dim3(64), 0, st, part1, nb1, 3, 3, sums1);
   HIP_TRY(hipGetLastError());
   unsigned long long hb[2];
   double s1[3];
@@ -567,29 +569,39 @@ int lanes_lookup(const mbh_ctx *ctx, int n_bins, int n_modes, int prec) {
 
 template <typename R, bool DH>
 static void launch_het_g(int G, const HetRef &h, const WalkerC *wc, int64_t W, double *lnL, double *dhhh,
-                         hipStream_t st) {
+                         RouteQ rq, hipStream_t st) {
   const int wpb = kBlock / G;
   dim3 grid((unsigned)((W + wpb - 1) / wpb));
   switch (G) {
-    case 1: hipLaunchKernelGGL((k_het<R, 1, DH>), grid, dim3(kBlock), 0, st, h, wc, W, lnL, dhhh); break;
-    case 2: hipLaunchKernelGGL((k_het<R, 2, DH>), grid, dim3(kBlock), 0, st, h, wc, W, lnL, dhhh); break;
-    case 4: hipLaunchKernelGGL((k_het<R, 4, DH>), grid, dim3(kBlock), 0, st, h, wc, W, lnL, dhhh); break;
-    case 8: hipLaunchKernelGGL((k_het<R, 8, DH>), grid, dim3(kBlock), 0, st, h, wc, W, lnL, dhhh); break;
-    case 16: hipLaunchKernelGGL((k_het<R, 16, DH>), grid, dim3(kBlock), 0, st, h, wc, W, lnL, dhhh); break;
-    case 32: hipLaunchKernelGGL((k_het<R, 32, DH>), grid, dim3(kBlock), 0, st, h, wc, W, lnL, dhhh); break;
-    default: hipLaunchKernelGGL((k_het<R, 64, DH>), grid, dim3(kBlock), 0, st, h, wc, W, lnL, dhhh); break;
+    case 1: hipLaunchKernelGGL((k_het<R, 1, DH>), grid, dim3(kBlock), 0, st, h, wc, W, lnL, dhhh, rq); break;
+    case 2: hipLaunchKernelGGL((k_het<R, 2, DH>), grid, dim3(kBlock), 0, st, h, wc, W, lnL, dhhh, rq); break;
+    case 4: hipLaunchKernelGGL((k_het<R, 4, DH>), grid, dim3(kBlock), 0, st, h, wc, W, lnL, dhhh, rq); break;
+    case 8: hipLaunchKernelGGL((k_het<R, 8, DH>), grid, dim3(kBlock), 0, st, h, wc, W, lnL, dhhh, rq); break;
+    case 16: hipLaunchKernelGGL((k_het<R, 16, DH>), grid, dim3(kBlock), 0, st, h, wc, W, lnL, dhhh, rq); break;
+    case 32: hipLaunchKernelGGL((k_het<R, 32, DH>), grid, dim3(kBlock), 0, st, h, wc, W, lnL, dhhh, rq); break;
+    default: hipLaunchKernelGGL((k_het<R, 64, DH>), grid, dim3(kBlock), 0, st, h, wc, W, lnL, dhhh, rq); break;
   }
 }
 
 void launch_het(int prec, int G, const HetRef &h, const WalkerC *wc, int64_t W, double *lnL, double *dhhh,
-                hipStream_t st) {
+                RouteQ rq, hipStream_t st) {
   if (prec == MBH_FP64) {
-    if (dhhh) launch_het_g<double, true>(G, h, wc, W, lnL, dhhh, st);
-    else launch_het_g<double, false>(G, h, wc, W, lnL, dhhh, st);
+    if (dhhh) launch_het_g<double, true>(G, h, wc, W, lnL, dhhh, rq, st);
+    else launch_het_g<double, false>(G, h, wc, W, lnL, dhhh, rq, st);
   } else {
-    if (dhhh) launch_het_g<float, true>(G, h, wc, W, lnL, dhhh, st);
-    else launch_het_g<float, false>(G, h, wc, W, lnL, dhhh, st);
+    if (dhhh) launch_het_g<float, true>(G, h, wc, W, lnL, dhhh, rq, st);
+    else launch_het_g<float, false>(G, h, wc, W, lnL, dhhh, rq, st);
   }
+}
+
+int fixup_blocks(const mbh_ctx *ctx, int64_t W) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>((W + 3) / 4, 2 * ctx->n_cu));
+}
+
+void launch_fixup(bool dh, int n_blocks, const WorkItem *items, const WorkItem &one, const int2 *list, unsigned *rc,
+                  hipStream_t st) {
+  if (dh) hipLaunchKernelGGL(k_het_fixup<true>, dim3(n_blocks), dim3(kBlock), 0, st, items, one, list, rc);
+  else hipLaunchKernelGGL(k_het_fixup<false>, dim3(n_blocks), dim3(kBlock), 0, st, items, one, list, rc);
 }
 
 extern "C" mbh_status mbh_loglike_heterodyned(mbh_ctx *ctx, const mbh_ref *ref, const double *theta_dev,
@@ -604,9 +616,30 @@ extern "C" mbh_status mbh_loglike_heterodyned(mbh_ctx *ctx, const mbh_ref *ref, 
   WalkerC *wc = nullptr;
   MBH_TRY(sc.get(&wc, (size_t)W));
   hipLaunchKernelGGL(k_walker_setup, dim3((unsigned)((W + 127) / 128)), dim3(128), 0, st, theta_dev, W,
-                     ref->model, wc);
+                     ref->model, ref->modes, wc);
   int G = lanes_lookup(ctx, ref->n_bins, popcount_modes(ref->modes ? ref->modes : 1u), prec);
-  launch_het(prec, G, ref_view(ref), wc, W, lnL_dev, dh_hh_dev, st);
+  if (prec == MBH_FP64) {
+    launch_het(prec, G, ref_view(ref), wc, W, lnL_dev, dh_hh_dev, RouteQ{nullptr, nullptr, 0}, st);
+  } else {
+    // mixed pass with its FP64 recomputation queue
+    unsigned *rc = nullptr;
+    int2 *list = nullptr;
+    MBH_TRY(sc.get(&rc, 4));
+    MBH_TRY(sc.get(&list, (size_t)W));
+    WorkItem h;
+    h.ref = ref_view(ref);
+    h.theta = theta_dev;
+    h.wc = wc;
+    h.lnL = lnL_dev;
+    h.dhhh = dh_hh_dev;
+    h.W = W;
+    h.offset = 0;
+    h.G = G;
+    h.model = ref->model;
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, rc, 4);
+    launch_het(prec, G, h.ref, wc, W, lnL_dev, dh_hh_dev, RouteQ{rc, list, 0}, st);
+    launch_fixup(dh_hh_dev != nullptr, fixup_blocks(ctx, W), nullptr, h, list, rc, st);
+  }
   HIP_TRY(hipGetLastError());
   return MBH_OK;
 }
@@ -634,8 +667,8 @@ static mbh_status full_impl(mbh_ctx *ctx, const mbh_data *d, uint32_t modes, con
   else
     hipLaunchKernelGGL((k_full<float, KF, DH>), grid, dim3(kBlock), 0, st, d->dw32, d->sw32, d->n_chan, d->n_f,
                        d->f0, d->df, d->t_obs, modes, wc, W, (int)wpb, part);
-  hipLaunchKernelGGL(k_full_reduce, dim3((unsigned)((W + 127) / 128)), dim3(128), 0, st, part, (int)n_fc, W, nv,
-                     wc, lnL, dhhh);
+  hipLaunchKernelGGL(k_full_reduce, dim3((unsigned)((W + kBlock / 64 - 1) / (kBlock / 64))), dim3(kBlock), 0, st,
+                     part, (int)n_fc, W, nv, wc, lnL, dhhh);
   HIP_TRY(hipGetLastError());
   return MBH_OK;
 }
@@ -652,7 +685,8 @@ extern "C" mbh_status mbh_loglike_full(mbh_ctx *ctx, const mbh_data *data, int m
   Scratch sc(ctx, st);
   WalkerC *wc = nullptr;
   MBH_TRY(sc.get(&wc, (size_t)W));
-  hipLaunchKernelGGL(k_walker_setup, dim3((unsigned)((W + 127) / 128)), dim3(128), 0, st, theta_dev, W, model, wc);
+  hipLaunchKernelGGL(k_walker_setup, dim3((unsigned)((W + 127) / 128)), dim3(128), 0, st, theta_dev, W, model,
+                     model == MBH_MODEL_IMR ? modes : 0u, wc);
   uint32_t m = model == MBH_MODEL_IMR ? modes : 0u;
   if (prec == MBH_FP64)
     return dh_hh_dev ? full_impl<double, true>(ctx, data, m, wc, W, lnL_dev, dh_hh_dev, st, sc)
@@ -717,13 +751,14 @@ extern "C" mbh_status mbh_autotune_heterodyned(mbh_ctx *ctx, const mbh_ref *ref,
     (void)hipEventCreate(&e1);
     if (hipMemcpyAsync(th, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, st) == hipSuccess) {
       hipLaunchKernelGGL(k_walker_setup, dim3((unsigned)((W + 127) / 128)), dim3(128), 0, st, th, W, ref->model,
-                         wc);
+                         ref->modes, wc);
       HetRef hv = ref_view(ref);
       for (int G : {4, 8, 16, 32, 64}) {
-        launch_het(prec, G, hv, wc, W, lnL, nullptr, st);  // warm-up
+        const RouteQ none{nullptr, nullptr, 0};
+        launch_het(prec, G, hv, wc, W, lnL, nullptr, none, st);  // warm-up
         (void)hipEventRecord(e0, st);
         const int reps = 20;
-        for (int r = 0; r < reps; ++r) launch_het(prec, G, hv, wc, W, lnL, nullptr, st);
+        for (int r = 0; r < reps; ++r) launch_het(prec, G, hv, wc, W, lnL, nullptr, none, st);
         (void)hipEventRecord(e1, st);
         (void)hipEventSynchronize(e1);
         float ms = 0.f;

@@ -24,6 +24,9 @@ using namespace mbh;
 HetRef ref_view(const mbh_ref *r);
 int lanes_lookup(const mbh_ctx *ctx, int n_bins, int n_modes, int prec);
 int popcount_modes(uint32_t m);
+int fixup_blocks(const mbh_ctx *ctx, int64_t W);
+void launch_fixup(bool dh, int n_blocks, const WorkItem *items, const WorkItem &one, const int2 *list, unsigned *rc,
+                  hipStream_t st);
 
 #define HIP_TRY(x)                                                                          \
   do {                                                                                      \
@@ -71,15 +74,20 @@ static int persistent_blocks(const mbh_ctx *ctx, int prec, bool dh) {
   return per_cu * ctx->n_cu;
 }
 
-static void launch_work(int prec, bool dh, int n_blocks, int setup_blocks, const WorkHeader *hdr,
-                        const WorkItem *items, const WorkTile *tiles, unsigned *counters, hipStream_t st) {
+// setup (a1), the persistent heterodyned pass and, for the mixed path, the
+// FP64 recomputation of the walkers it queued (rc[4], list[total walkers])
+static void launch_work(const mbh_ctx *ctx, int prec, bool dh, int n_blocks, int setup_blocks, int64_t max_walkers,
+                        const WorkHeader *hdr, const WorkItem *items, const WorkTile *tiles, unsigned *counters,
+                        unsigned *rc, int2 *list, hipStream_t st) {
   hipLaunchKernelGGL(k_setup_work, dim3(setup_blocks), dim3(128), 0, st, hdr, items);
   if (prec == MBH_FP64) {
-    if (dh) hipLaunchKernelGGL((k_het_work<double, true>), dim3(n_blocks), dim3(kBlock), 0, st, hdr, items, tiles, counters);
-    else hipLaunchKernelGGL((k_het_work<double, false>), dim3(n_blocks), dim3(kBlock), 0, st, hdr, items, tiles, counters);
+    if (dh) hipLaunchKernelGGL((k_het_work<double, true>), dim3(n_blocks), dim3(kBlock), 0, st, hdr, items, tiles, counters, (unsigned *)nullptr, (int2 *)nullptr);
+    else hipLaunchKernelGGL((k_het_work<double, false>), dim3(n_blocks), dim3(kBlock), 0, st, hdr, items, tiles, counters, (unsigned *)nullptr, (int2 *)nullptr);
   } else {
-    if (dh) hipLaunchKernelGGL((k_het_work<float, true>), dim3(n_blocks), dim3(kBlock), 0, st, hdr, items, tiles, counters);
-    else hipLaunchKernelGGL((k_het_work<float, false>), dim3(n_blocks), dim3(kBlock), 0, st, hdr, items, tiles, counters);
+    if (dh) hipLaunchKernelGGL((k_het_work<float, true>), dim3(n_blocks), dim3(kBlock), 0, st, hdr, items, tiles, counters, rc, list);
+    else hipLaunchKernelGGL((k_het_work<float, false>), dim3(n_blocks), dim3(kBlock), 0, st, hdr, items, tiles, counters, rc, list);
+    WorkItem none{};
+    launch_fixup(dh, fixup_blocks(ctx, max_walkers), items, none, list, rc, st);
   }
 }
 
@@ -93,7 +101,9 @@ struct mbh_batch {
   WorkTile *tiles = nullptr;
   unsigned *counters = nullptr;
   WalkerC *wc = nullptr;
-  size_t bytes[5] = {0, 0, 0, 0, 0};
+  unsigned *rc = nullptr;
+  int2 *list = nullptr;
+  size_t bytes[7] = {0, 0, 0, 0, 0, 0, 0};
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -106,6 +116,8 @@ static void batch_free(mbh_batch *b) {
   ctx_free(b->ctx, b->tiles, b->bytes[2]);
   ctx_free(b->ctx, b->counters, b->bytes[3]);
   ctx_free(b->ctx, b->wc, b->bytes[4]);
+  ctx_free(b->ctx, b->rc, b->bytes[5]);
+  ctx_free(b->ctx, b->list, b->bytes[6]);
   delete b;
 }
 
@@ -160,15 +172,20 @@ extern "C" mbh_status mbh_batch_create(mbh_ctx *ctx, int n, const mbh_ref *const
   b->bytes[1] = n * sizeof(WorkItem);
   b->bytes[2] = std::max<size_t>(1, tiles.size()) * sizeof(WorkTile);
   b->bytes[3] = 2 * sizeof(unsigned);
+  b->bytes[5] = 4 * sizeof(unsigned);
+  b->bytes[6] = (size_t)std::max<int64_t>(total, 1) * sizeof(int2);
+  if ((s = ctx_alloc(ctx, (void **)&b->rc, b->bytes[5])) != MBH_OK) return fail(s);
+  if ((s = ctx_alloc(ctx, (void **)&b->list, b->bytes[6])) != MBH_OK) return fail(s);
   if ((s = ctx_alloc(ctx, (void **)&b->hdr, b->bytes[0])) != MBH_OK) return fail(s);
   if ((s = ctx_alloc(ctx, (void **)&b->items, b->bytes[1])) != MBH_OK) return fail(s);
   if ((s = ctx_alloc(ctx, (void **)&b->tiles, b->bytes[2])) != MBH_OK) return fail(s);
   if ((s = ctx_alloc(ctx, (void **)&b->counters, b->bytes[3])) != MBH_OK) return fail(s);
-  unsigned zero[2] = {0u, 0u};
-  if (hipMemcpy(b->hdr, &h, sizeof(h), hipMemcpyHostToDevice) != hipSuccess ||
+  unsigned zero[4] = {0u, 0u, 0u, 0u};
+  if (hipMemcpy(b->rc, zero, 4 * sizeof(unsigned), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b->hdr, &h, sizeof(h), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(b->items, items.data(), b->bytes[1], hipMemcpyHostToDevice) != hipSuccess ||
       (!tiles.empty() && hipMemcpy(b->tiles, tiles.data(), tiles.size() * sizeof(WorkTile), hipMemcpyHostToDevice) != hipSuccess) ||
-      hipMemcpy(b->counters, zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess)
+      hipMemcpy(b->counters, zero, 2 * sizeof(unsigned), hipMemcpyHostToDevice) != hipSuccess)
     return fail(mbh_fail(MBH_EDEVICE, "upload work list"));
   // capture the setup + persistent launch once
   const int nblk = std::max(1, std::min<int>(persistent_blocks(ctx, prec, dh), (int)tiles.size()));
@@ -177,7 +194,7 @@ extern "C" mbh_status mbh_batch_create(mbh_ctx *ctx, int n, const mbh_ref *const
   if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return fail(mbh_fail(MBH_EDEVICE, "stream"));
   hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    launch_work(prec, dh, nblk, sblk, b->hdr, b->items, b->tiles, b->counters, cs);
+    launch_work(ctx, prec, dh, nblk, sblk, total, b->hdr, b->items, b->tiles, b->counters, b->rc, b->list, cs);
     e = hipStreamEndCapture(cs, &b->graph);
   }
   if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
@@ -191,6 +208,15 @@ extern "C" mbh_status mbh_batch_launch(mbh_batch *b, hipStream_t st) {
   if (!b) return mbh_fail(MBH_EINVAL, "null batch");
   HIP_TRY(hipSetDevice(b->ctx->device));
   HIP_TRY(hipGraphLaunch(b->exec, st));
+  return MBH_OK;
+}
+
+extern "C" mbh_status mbh_batch_routed(const mbh_batch *b, uint64_t *routed_out) {
+  if (!b || !routed_out) return mbh_fail(MBH_EINVAL, "null argument");
+  HIP_TRY(hipSetDevice(b->ctx->device));
+  unsigned v[4];
+  HIP_TRY(hipMemcpy(v, b->rc, sizeof(v), hipMemcpyDeviceToHost));
+  *routed_out = v[3];
   return MBH_OK;
 }
 
@@ -229,6 +255,8 @@ struct Slot {
   WorkItem *items_d = nullptr;
   WorkTile *tiles_d = nullptr;
   unsigned *counters_d = nullptr;
+  unsigned *rc_d = nullptr;
+  int2 *list_d = nullptr;
   WalkerC *wc_d = nullptr;
   std::vector<std::pair<std::shared_ptr<Request>, int64_t>> members;  // request, first walker in the slot
   int64_t walkers = 0;
@@ -328,7 +356,8 @@ static bool server_launch(mbh_server *s, Slot &sl) {
   if (!ok) return false;
   const int nblk = std::max(1, std::min(s->nblk, h.n_tiles));
   const int sblk = (int)std::max<int64_t>(1, std::min<int64_t>((sl.walkers + 127) / 128, 4 * s->ctx->n_cu));
-  launch_work(s->cfg.prec, true, nblk, sblk, sl.hdr_d, sl.items_d, sl.tiles_d, sl.counters_d, st);
+  launch_work(s->ctx, s->cfg.prec, true, nblk, sblk, sl.walkers, sl.hdr_d, sl.items_d, sl.tiles_d, sl.counters_d,
+              sl.rc_d, sl.list_d, st);
   ok = hipGetLastError() == hipSuccess &&
        hipMemcpyAsync(sl.res_h, sl.res_d, sl.walkers * 3 * sizeof(double), hipMemcpyDeviceToHost, st) == hipSuccess &&
        hipEventRecord(sl.ev, st) == hipSuccess;
@@ -454,12 +483,15 @@ extern "C" mbh_status mbh_server_create(mbh_ctx *ctx, int n_refs, const mbh_ref 
         (st = dalloc((void **)&sl.items_d, s->max_items * sizeof(WorkItem))) != MBH_OK ||
         (st = dalloc((void **)&sl.tiles_d, s->max_tiles * sizeof(WorkTile))) != MBH_OK ||
         (st = dalloc((void **)&sl.counters_d, 2 * sizeof(unsigned))) != MBH_OK ||
+        (st = dalloc((void **)&sl.rc_d, 4 * sizeof(unsigned))) != MBH_OK ||
+        (st = dalloc((void **)&sl.list_d, cap * sizeof(int2))) != MBH_OK ||
         (st = dalloc((void **)&sl.wc_d, cap * sizeof(WalkerC))) != MBH_OK) {
       server_free(s);
       return st;
     }
-    unsigned zero[2] = {0u, 0u};
-    if (hipMemcpy(sl.counters_d, zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess) {
+    unsigned zero[4] = {0u, 0u, 0u, 0u};
+    if (hipMemcpy(sl.counters_d, zero, 2 * sizeof(unsigned), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(sl.rc_d, zero, 4 * sizeof(unsigned), hipMemcpyHostToDevice) != hipSuccess) {
       server_free(s);
       return mbh_fail(MBH_EDEVICE, "counter init");
     }

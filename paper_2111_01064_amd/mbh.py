@@ -75,6 +75,7 @@ _SIGS = {
     "mbh_loglike_full": [_vp, _vp, _i32, _u32, _vp, _i64, _i32, _vp, _vp, _vp],
     "mbh_batch_create": [_vp, _i32, _pp, _pp, ct.POINTER(ct.c_int64), _pp, _pp, _i32, _pp],
     "mbh_batch_launch": [_vp, _vp],
+    "mbh_batch_routed": [_vp, ct.POINTER(ct.c_uint64)],
     "mbh_batch_release": [_vp],
     "mbh_autotune_heterodyned": [_vp, _vp, _i64, _i32, ct.POINTER(ct.c_int)],
     "mbh_lanes_for": [_vp, _i32, _i32, _i32, ct.POINTER(ct.c_int)],
@@ -307,6 +308,11 @@ class Batch:
 
     def launch(self, stream=None):
         _check(_L.mbh_batch_launch(self.h, _stream(stream)), "mbh_batch_launch")
+
+    def routed(self) -> int:
+        v = ct.c_uint64()
+        _check(_L.mbh_batch_routed(self.h, ct.byref(v)), "mbh_batch_routed")
+        return v.value
 
     def close(self):
         if getattr(self, "h", None):
