@@ -215,9 +215,8 @@ def main():
     stream = torch.cuda.Stream()
     res = {}
     for name, prec in (("fp64", M.FP64), ("mixed", M.MIXED)):
-        for it in S.items:  # autotune lanes per walker for this shape once
-            M.autotune_heterodyned(ctx, it["ref"], W_total, prec)
-            break
+        # autotune the mapping for this shape once, on the step's own walkers
+        M.autotune_heterodyned(ctx, S.items[0]["ref"], torch.cat(thetas), prec)
         lnls = [torch.empty(len(w), dtype=torch.float64, device="cuda") for w in walkers]
         batch = M.Batch(ctx, [it["ref"] for it in S.items], thetas, lnls, prec=prec)
         wall, mean_s, per = time_batch(M, ctx, batch, args.steps, args.warmup, stream)
@@ -289,8 +288,8 @@ def side_measurements(M, ctx, S, walkers, grid):
     th4 = []
     for item, (_, _, W) in zip(S4.items, shapes):
         th4.append(torch.as_tensor(S4.walkers(item, (1, 4, 16, 64), (W + 3) // 4)[:W], device="cuda"))
-    for it4 in S4.items:
-        M.autotune_heterodyned(ctx, it4["ref"], len(th4[0]), M.MIXED)
+    for it4, t4 in zip(S4.items, th4):
+        M.autotune_heterodyned(ctx, it4["ref"], t4, M.MIXED)
     ln4 = [torch.empty(len(t), dtype=torch.float64, device="cuda") for t in th4]
     b4 = M.Batch(ctx, [x["ref"] for x in S4.items], th4, ln4, prec=M.MIXED)
     st = torch.cuda.Stream()

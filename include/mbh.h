@@ -173,9 +173,10 @@ mbh_status mbh_loglike_full(mbh_ctx *ctx, const mbh_data *data, int model, uint3
  * ragged modes, bin counts and walker counts.  Items are packed into a
  * device work list of tiles (longest first) that the workgroups of a
  * persistent grid claim through one atomic counter; the launch is captured
- * once into a HIP graph and replayed by mbh_batch_launch.  Lanes per walker
- * come from the autotuner table (per bin count and mode count), so a walker's
- * result does not depend on the rest of the batch.
+ * once into a HIP graph and replayed by mbh_batch_launch.  The mapping of
+ * each item (see mbh_set_lanes) comes from the autotuner table (per bin count
+ * and mode count), so a walker's result depends only on its inputs, its
+ * reference and its index within its item, never on the rest of the batch.
  *   refs[n], theta_dev[n] ([W_i][11]), W[n], lnL_dev[n] ([W_i]),
  *   dh_hh_dev[n] (each [W_i][2] or NULL; the array itself may be NULL).
  * Caller buffers must stay valid while the batch exists.
@@ -192,16 +193,21 @@ mbh_status mbh_batch_release(mbh_batch *batch);
 
 /* --------------------------------------------------------- autotuner */
 
-/* Time the heterodyned kernel for every lanes-per-walker choice at this
- * reference's shape and record the fastest in the context's table (and in
- * the cache file given to mbh_autotune_load/save).  Synchronous.
- * lanes_out may be NULL. */
-mbh_status mbh_autotune_heterodyned(mbh_ctx *ctx, const mbh_ref *ref, int64_t W,
-                                    mbh_precision prec, int *lanes_out);
-/* Lanes per walker the library uses for this shape (table or heuristic). */
+/* Time the heterodyned kernel for each mapping (flattened, and lane groups
+ * of 16, 32 and 64 lanes per walker) at this reference's shape and record the
+ * fastest in the context's table (saved and restored by
+ * mbh_autotune_save/load).  theta_dev [W][11] (device) are representative
+ * walkers, e.g. the sampler's current ensemble; if NULL, W copies of a fixed
+ * valid parameter point are used.  Synchronous.  lanes_out may be NULL. */
+mbh_status mbh_autotune_heterodyned(mbh_ctx *ctx, const mbh_ref *ref, const double *theta_dev,
+                                    int64_t W, mbh_precision prec, int *lanes_out);
+/* Mapping the library uses for this shape (table, else 0). */
 mbh_status mbh_lanes_for(const mbh_ctx *ctx, int n_bins, int n_modes, mbh_precision prec,
                          int *lanes_out);
-/* Force lanes per walker for a shape (1..64, power of two); for tests. */
+/* Set the mapping of the heterodyned pass for a shape: 0 = flattened (one
+ * lane per walker and bin edge, 63 bins per wavefront; the default), or
+ * 1..64 (power of two) lanes per walker.  Results differ between mappings
+ * only by rounding. */
 mbh_status mbh_set_lanes(mbh_ctx *ctx, int n_bins, int n_modes, mbh_precision prec, int lanes);
 mbh_status mbh_autotune_save(const mbh_ctx *ctx, const char *path);
 mbh_status mbh_autotune_load(mbh_ctx *ctx, const char *path);

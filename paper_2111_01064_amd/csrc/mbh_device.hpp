@@ -283,60 +283,108 @@ __device__ __forceinline__ double cbrt64_nr(double x) {
   return v;
 }
 
+// Taylor coefficients of sin(x)/x and cos(x) in y = x^2:
+// s_n = (-1)^n / (2n+1)!, c_n = (-1)^n / (2n)!
+struct TrigCoef {
+  double s[24], c[24];
+  constexpr TrigCoef() : s(), c() {
+    double sn = 1.0, cn = 1.0;
+    s[0] = 1.0;
+    c[0] = 1.0;
+    for (int n = 1; n < 24; ++n) {
+      cn = -cn / ((2.0 * n - 1.0) * (2.0 * n));
+      sn = -sn / ((2.0 * n) * (2.0 * n + 1.0));
+      s[n] = sn;
+      c[n] = cn;
+    }
+  }
+};
+constexpr TrigCoef kTrig{};
+
+// sin and cos for the bounded arguments of this library (|x| <= ~1e4): one
+// Cody-Waite reduction by pi/2 (two-constant split, exact FMA products), then
+// Taylor polynomials on [-pi/4, pi/4] truncated where the next term is below
+// the format's rounding (x^17 / x^16 for FP64, x^11 / x^10 for FP32).
+template <typename R>
+struct TrigConst;
+template <>
+struct TrigConst<double> {
+  static constexpr double kTwoOverPi = 0.636619772367581343075535053490057448;
+  static constexpr double kPio2Hi = 1.5707963267948965579989817342720925807952880859375;  // nearest double
+  static constexpr double kPio2Lo = 6.123233995736766035868820147291818e-17;            // pi/2 - hi
+  static constexpr int kSin = 9, kCos = 9;
+};
+template <>
+struct TrigConst<float> {
+  static constexpr float kTwoOverPi = 0.636619772367581343f;
+  static constexpr float kPio2Hi = 1.57079637050628662109375f;   // nearest float
+  static constexpr float kPio2Lo = -4.37113900018624283e-8f;     // pi/2 - hi
+  static constexpr int kSin = 6, kCos = 6;
+};
+
+template <typename R>
+__device__ __forceinline__ void sincos_red(R x, R &s, R &c) {
+  using T = TrigConst<R>;
+  const R kq = rint(x * T::kTwoOverPi);
+  R r = fma(-kq, T::kPio2Hi, x);
+  r = fma(-kq, T::kPio2Lo, r);
+  const int q = (int)kq;
+  const R r2 = r * r;
+  R ps = (R)kTrig.s[T::kSin - 1], pc = (R)kTrig.c[T::kCos - 1];
+#pragma unroll
+  for (int n = T::kSin - 2; n >= 0; --n) ps = fma(ps, r2, (R)kTrig.s[n]);
+#pragma unroll
+  for (int n = T::kCos - 2; n >= 0; --n) pc = fma(pc, r2, (R)kTrig.c[n]);
+  const R sr = r * ps;
+  // x = q pi/2 + r
+  R so = (q & 1) ? pc : sr;
+  R co = (q & 1) ? -sr : pc;
+  if (q & 2) {
+    so = -so;
+    co = -co;
+  }
+  s = so;
+  c = co;
+}
+
 template <typename R>
 struct Prec;
 
 template <>
 struct Prec<double> {
-  static __device__ __forceinline__ void sincos_r(double x, double &s, double &c) { sincos(x, &s, &c); }
-  static __device__ __forceinline__ void sincos_alpha(double a, double &s, double &c) { sincos(a, &s, &c); }
-  static __device__ __forceinline__ double atan_small(double x) { return atan(x); }
-  static __device__ __forceinline__ double rsqrt_r(double x) { return 1.0 / sqrt(x); }
+  static __device__ __forceinline__ void sincos_r(double x, double &s, double &c) { sincos_red<double>(x, s, c); }
   static __device__ __forceinline__ double sqrt_r(double x) { return sqrt(x); }
-  static constexpr int kSincTerms = 20;
 };
 
 template <>
 struct Prec<float> {
-  static __device__ __forceinline__ void sincos_r(float x, float &s, float &c) { sincosf(x, &s, &c); }
-  static __device__ __forceinline__ void sincos_alpha(double a, double &s, double &c) { sincos(a, &s, &c); }
-  static __device__ __forceinline__ float atan_small(float x) { return atanf(x); }
-  static __device__ __forceinline__ float rsqrt_r(float x) { return rsqrtf(x); }
+  static __device__ __forceinline__ void sincos_r(float x, float &s, float &c) { sincos_red<float>(x, s, c); }
   static __device__ __forceinline__ float sqrt_r(float x) { return sqrtf(x); }
-  static constexpr int kSincTerms = 14;
 };
 
 // (2,2) phase aligned at f_max, its slope, and the amplitude at (2,2)
-// frequency fp; amplitude scaled by v^vpow (v = (pi M fp)^(1/3)).  Phase and
-// slope are FP64; the frequency-dependent amplitude factor (v^-7/2 times the
-// ringdown Lorentzian) is formed in R and multiplied by the per-walker FP64
-// prefactor, so its rounding varies from edge to edge and never acts as a
-// coherent shift of D_L.
-template <typename R>
-__device__ __forceinline__ void wf22(const WalkerC &w, double fp, int vpow, double &ph, double &dph,
-                                     double &amp) {
-  double v = cbrt64_nr(w.piM * fp);
-  double iv = rcp64_nr(v);
-  R lam2 = (R)1;
+// frequency fp; amplitude scaled by v^vpow (v = (pi M fp)^(1/3)).  All FP64:
+// the arctan of the merger-ringdown continuation and the amplitude factor
+// would otherwise carry FP32 roundings of per-walker constants (arctan at
+// f1) into every edge alike, i.e. coherent phase and amplitude shifts.
+__device__ __forceinline__ void wf22(const WalkerC &w, double fp, int vpow, double &ph, double &dph, double &amp) {
+  const double v = cbrt64_nr(w.piM * fp);
+  const double iv = rcp64_nr(v);
+  double lam2 = 1.0;
   if (fp <= w.f1) {
-    double iv2 = iv * iv, iv3 = iv2 * iv, iv5 = iv3 * iv2;
+    const double iv2 = iv * iv, iv3 = iv2 * iv, iv5 = iv3 * iv2;
     ph = w.c5 * iv5 + w.c3 * iv3 + w.c2 * iv2;
     dph = (w.d5 * iv5 + w.d3 * iv3 + w.d2 * iv2) * rcp64_nr(fp);
   } else {
-    double x = fp - w.f1, y = fp - w.fRD;
-    double rden = rcp64_nr(y * y + w.fD * w.fD);
-    R Lr = (R)(w.fD * rden);
-    R at = Prec<R>::atan_small((R)(y * w.inv_fD));
-    // the arctan difference and the slope correction are bounded by a few rad
-    ph = w.P1 + w.dP1 * x + kKappa * ((double)(at - (R)w.at1) - w.L1 * x);
-    dph = w.dP1 + kKappa * ((double)Lr - w.L1);
-    lam2 = (R)(w.lam_num * rden);
+    const double x = fp - w.f1, y = fp - w.fRD;
+    const double rden = rcp64_nr(y * y + w.fD * w.fD);
+    ph = w.P1 + w.dP1 * x + kKappa * ((atan(y * w.inv_fD) - w.at1) - w.L1 * x);
+    dph = w.dP1 + kKappa * (w.fD * rden - w.L1);
+    lam2 = w.lam_num * rden;
   }
   ph = ph - w.ph_max - w.dph_max * (fp - w.fmax);
   dph = dph - w.dph_max;
-  R ivr = (R)iv;
-  R af = ivr * ivr * ivr * Prec<R>::sqrt_r(ivr * lam2);
-  double a = w.AN * (double)af;
+  double a = w.AN * (iv * iv * iv) * sqrt(iv * lam2);
   for (int k = 0; k < vpow; ++k) a *= v;
   amp = a;
 }
@@ -355,109 +403,167 @@ struct SincCoef {
 };
 constexpr SincCoef kSinc{};
 
-// sinc series S(y) = sum c_n y^n and its divided difference
-// S[y1, y2] = (S(y1) - S(y2)) / (y1 - y2), in one downward Horner pass:
+// Number N of sinc coefficients beyond c_0 that reach the format's rounding
+// level for y <= y_max: the truncated terms are below 2^-53 (FP64) or 2^-24
+// (FP32) relative to the divided difference (whose leading coefficient is
+// -1/6).  ylim[N] is the largest y for which N suffices.
+__host__ __device__ inline int sinc_terms(double y_max, bool fp64) {
+  constexpr double ylim64[21] = {0, 0, 0, 1.1e-3, 1.08e-2, 5.17e-2, 0.166, 0.412, 0.857, 1.58, 2.64,
+                                 4.12, 6.08, 8.58, 11.7, 15.4, 19.8, 25.0, 30.9, 37.5, 45.0};
+  constexpr double ylim32[21] = {0, 0, 0, 0.173, 0.602, 1.48, 2.93, 5.08, 8.0, 11.8, 16.4,
+                                 22.0, 28.5, 36.1, 44.6, 54.1, 64.7, 76.3, 88.9, 103.0, 117.0};
+  const double *lim = fp64 ? ylim64 : ylim32;
+  for (int n = 3; n < 20; ++n)
+    if (y_max <= lim[n]) return n;
+  return 20;
+}
+
+// the sinc coefficients in each format, in constant memory (read with
+// scalar loads, the loop index being uniform)
+struct SincCoef32 {
+  float c[24];
+  constexpr SincCoef32() : c() {
+    for (int n = 0; n < 24; ++n) c[n] = (float)kSinc.c[n];
+  }
+};
+__device__ __constant__ const SincCoef kSincDev64 = SincCoef{};
+__device__ __constant__ const SincCoef32 kSincDev32 = SincCoef32{};
+
+// sinc series S(y) = sum_{n<=N} c_n y^n and its divided difference
+// S[y1, y2] = (S(y1) - S(y2)) / (y1 - y2) in one downward Horner pass:
 // with P_n(y) = sum_{k>=n} c_k y^(k-n), P_n = c_n + y P_{n+1} and
-// P_n[y1, y2] = P_{n+1}(y1) + y2 P_{n+1}[y1, y2].
+// P_n[y1, y2] = P_{n+1}(y1) + y2 P_{n+1}[y1, y2].  N (<= 20) is uniform
+// across the wavefront, so the loop is scalar-controlled.
 template <typename R>
-__device__ __forceinline__ void sinc_pair(R y1, R y2, R &s1, R &dd) {
-  constexpr int N = Prec<R>::kSincTerms;
-  R p = (R)kSinc.c[N];
-  R d = (R)0;
-#pragma unroll
-  for (int n = N - 1; n >= 0; --n) {
+__device__ __forceinline__ void sinc_pair(R y1, R y2, int N, R &s1, R &dd) {
+  const R *c;
+  if constexpr (sizeof(R) == 8) c = (const R *)kSincDev64.c;
+  else c = (const R *)kSincDev32.c;
+  R p = (R)0, d = (R)0;
+#pragma unroll 2
+  for (int n = N; n >= 0; --n) {
     d = p + y2 * d;
-    p = (R)kSinc.c[n] + y1 * p;
+    p = c[n] + y1 * p;
   }
   s1 = p;
   dd = d;
 }
 
-// A, E, T transfer of a plus-only (Tp) and a cross-only (Tc) wave, without
-// the guiding-centre Doppler and the common e^{4 i pi f L}, for spacecraft
-// offsets at orbital phase (ca, sa).  Only geometry enters here; the mode's
-// polarisation weights are applied by the caller in FP64.
+// Frequency-only response factors for a = pi f L:
+// Cp = 4 a sin(2a) cos(a), Cm = 2 a sin(2a) sin(a); ns = sinc terms for the
+// precision in use over the frequencies that share this value (uniform)
+struct FreqC {
+  double a, Cp, Cm;
+  int ns;
+};
+__device__ __forceinline__ void freq_consts64(double f, double &a, double &Cp, double &Cm) {
+  a = kPi * f * kArmS;
+  double s, c;
+  sincos_red<double>(a, s, c);
+  const double s2 = 2.0 * s * c;
+  Cp = 4.0 * a * s2 * c;
+  Cm = 2.0 * a * s2 * s;
+}
+// sinc terms for frequencies up to f_max (the sinc arguments are a (1 +- k.n) <= 2a)
 template <typename R>
-__device__ __forceinline__ void response_pol(const WalkerC &w, R f, R a, R Cp, R Cm, R ca, R sa, cx<R> Tp[3],
-                                             cx<R> Tc[3]) {
-  const R eR = (R)kEccR;
-  R c2a = ca * ca - sa * sa, s2a = (R)2 * sa * ca;
-  // beta_k = 0, 2pi/3, 4pi/3
-  const R cbk[3] = {(R)1, (R)-0.5, (R)-0.5};
-  const R sbk[3] = {(R)0, (R)(0.5 * kSqrt3), (R)(-0.5 * kSqrt3)};
-  R dp[3][3];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    dp[k][0] = eR * ((R)0.5 * (c2a * cbk[k] + s2a * sbk[k]) - (R)1.5 * cbk[k]);
-    dp[k][1] = eR * ((R)0.5 * (s2a * cbk[k] - c2a * sbk[k]) - (R)1.5 * sbk[k]);
-    dp[k][2] = -(R)kSqrt3 * eR * (ca * cbk[k] + sa * sbk[k]);
-  }
-  // projections on the source frame use the FP64 sky vectors: rounding p, q
-  // or k to FP32 would change |p|^2 - |q|^2 and act as a coherent amplitude
-  // error at every frequency of the walker
-  double kdp[3];
-#pragma unroll
-  for (int k = 0; k < 3; ++k)
-    kdp[k] = w.kx * (double)dp[k][0] + w.ky * (double)dp[k][1] + w.kz * (double)dp[k][2];
-  const double pif = kPi * (double)f;
-  cx<R> Up[3], Vp[3], Uc[3], Vc[3];
-  const int li[3] = {0, 1, 2}, lj[3] = {1, 2, 0};
-#pragma unroll
-  for (int l = 0; l < 3; ++l) {
-    int i = li[l], j = lj[l];
-    R nx = dp[j][0] - dp[i][0], ny = dp[j][1] - dp[i][1], nz = dp[j][2] - dp[i][2];
-    R inv = Prec<R>::rsqrt_r(nx * nx + ny * ny + nz * nz);
-    nx *= inv;
-    ny *= inv;
-    nz *= inv;
-    const double ndx = nx, ndy = ny, ndz = nz;
-    R kn = (R)(w.kx * ndx + w.ky * ndy + w.kz * ndz);
-    double np = w.px * ndx + w.py * ndy + w.pz * ndz;
-    double nq = w.qx * ndx + w.qy * ndy + w.qz * ndz;
-    R Fp = (R)((np - nq) * (np + nq)), Fc = (R)(2.0 * np * nq);  // n e+ n, n ex n
-    R sph, cph;
-    Prec<R>::sincos_r((R)(pif * (kdp[i] + kdp[j])), sph, cph);
-    R am = a * ((R)1 - kn), ap = a * ((R)1 + kn);
-    R s1, dd;
-    sinc_pair<R>(am * am, ap * ap, s1, dd);
-    R delta = (R)-4 * a * a * kn * dd;  // sinc(x_ij) - sinc(x_ji)
-    R sigma = s1 - (R)0.5 * delta;      // (sinc(x_ij) + sinc(x_ji)) / 2
-    R us = sigma * Fp, vs = delta * Fp, uc = sigma * Fc, vc = delta * Fc;
-    Up[l] = mk<R>(us * cph, us * sph);
-    Vp[l] = mk<R>(vs * cph, vs * sph);
-    Uc[l] = mk<R>(uc * cph, uc * sph);
-    Vc[l] = mk<R>(vc * cph, vc * sph);
-  }
-  // sqrt2 A = Cp (U1 + U2 - 2 U3) - i Cm (V2 - V1)
-  // sqrt6 E = 3 Cp (U2 - U1) - i Cm (2 V3 - V1 - V2)
-  // sqrt3 T = -2 i Cm (V1 + V2 + V3)
-  // (the 1/sqrt2, 1/sqrt6, 1/sqrt3 normalisations are applied by the caller in FP64)
-  Tp[0] = Cp * (Up[0] + Up[1] - (R)2 * Up[2]) + Cm * mul_mi(Vp[1] - Vp[0]);
-  Tp[1] = ((R)3 * Cp) * (Up[1] - Up[0]) + Cm * mul_mi((R)2 * Vp[2] - Vp[0] - Vp[1]);
-  Tp[2] = ((R)2 * Cm) * mul_mi(Vp[0] + Vp[1] + Vp[2]);
-  Tc[0] = Cp * (Uc[0] + Uc[1] - (R)2 * Uc[2]) + Cm * mul_mi(Vc[1] - Vc[0]);
-  Tc[1] = ((R)3 * Cp) * (Uc[1] - Uc[0]) + Cm * mul_mi((R)2 * Vc[2] - Vc[0] - Vc[1]);
-  Tc[2] = ((R)2 * Cm) * mul_mi(Vc[0] + Vc[1] + Vc[2]);
+__host__ __device__ inline int sinc_terms_for(double f_max) {
+  const double x = 2.0 * kPi * f_max * kArmS;
+  return sinc_terms(x * x, sizeof(R) == 8);
+}
+template <typename R>
+__device__ __forceinline__ FreqC freq_consts(double f, int ns) {
+  FreqC fc;
+  freq_consts64(f, fc.a, fc.Cp, fc.Cm);
+  fc.ns = ns;
+  return fc;
 }
 
-// Frequency-only response factors for a = pi f L:
-// Cp = 4 a sin(2a) cos(a), Cm = 2 a sin(2a) sin(a)
+// A, E, T transfer of one mode (unnormalised: sqrt2 A, sqrt6 E, sqrt3 T),
+// without the guiding-centre Doppler and the common e^{4 i pi f L}, for
+// spacecraft offsets at orbital phase (ca, sa).  The geometry (offsets,
+// link vectors, projections, polarisation weights w_l = kp F+_l + i kc Fx_l)
+// is FP64 in both paths: on this hardware an FP32 operation issues at the
+// FP64 rate, so FP32 is used only where it shortens the work (the sinc
+// series and the link phase sine/cosine, precision R), and constant-like
+// FP32 roundings that would act coherently on every edge never arise.
+// In this orbit model every arm has length L exactly, so the link unit
+// vectors are offset differences in units of L, and the three offsets sum to
+// zero, so the third link phase factor is the conjugate product of the other
+// two.
+// spacecraft offset k (beta_k = 2 pi k / 3) from the guiding centre in
+// units of L at orbital phase a: (cos a, sin a) = (ca, sa),
+// (cos 2a, sin 2a) = (c2a, s2a); e R / L = 1 / (2 sqrt3)
+__device__ __forceinline__ void sc_offset(int k, double ca, double sa, double c2a, double s2a, double o[3]) {
+  constexpr double e = 0.5 / kSqrt3;
+  const double cb = k == 0 ? 1.0 : -0.5;
+  const double sb = k == 0 ? 0.0 : (k == 1 ? 0.5 * kSqrt3 : -0.5 * kSqrt3);
+  o[0] = e * (0.5 * (c2a * cb + s2a * sb) - 1.5 * cb);
+  o[1] = e * (0.5 * (s2a * cb - c2a * sb) - 1.5 * sb);
+  o[2] = -kSqrt3 * e * (ca * cb + sa * sb);
+}
+
 template <typename R>
-struct FreqC {
-  R f, a, Cp, Cm;
-};
-template <typename R>
-__device__ __forceinline__ FreqC<R> freq_consts(double f) {
-  FreqC<R> fc;
-  double a64 = kPi * f * kArmS;
-  fc.f = (R)f;
-  fc.a = (R)a64;
-  R s, c;
-  Prec<R>::sincos_r((R)a64, s, c);
-  R s2 = (R)2 * s * c;
-  fc.Cp = (R)4 * fc.a * s2 * c;
-  fc.Cm = (R)2 * fc.a * s2 * s;
-  return fc;
+__device__ __forceinline__ void response_mode(const WalkerC &w, double kp, double kc, const FreqC &fc, double ca,
+                                              double sa, cx<double> T[3]) {
+  const double c2a = ca * ca - sa * sa, s2a = 2.0 * sa * ca;
+  // link phase factors z_l = e^{i a k.(p_i + p_j)}: link (0,1) has phase
+  // -a k.p_2, link (1,2) -a k.p_0 (the offsets sum to zero), and z_2 closes
+  cx<double> z[3];
+  {
+    double o[3];
+    sc_offset(0, ca, sa, c2a, s2a, o);
+    const double kd0 = w.kx * o[0] + w.ky * o[1] + w.kz * o[2];
+    sc_offset(2, ca, sa, c2a, s2a, o);
+    const double kd2 = w.kx * o[0] + w.ky * o[1] + w.kz * o[2];
+    R s0, c0, s1, c1;
+    Prec<R>::sincos_r((R)(-fc.a * kd2), s0, c0);
+    Prec<R>::sincos_r((R)(-fc.a * kd0), s1, c1);
+    z[0] = mk<double>((double)c0, (double)s0);
+    z[1] = mk<double>((double)c1, (double)s1);
+    z[2] = z[0] * z[1];
+    z[2].im = -z[2].im;
+  }
+  // sqrt2 A = Cp SAU - i Cm SAV, sqrt6 E = 3 Cp SEU - i Cm SEV, sqrt3 T = -2 i Cm STV
+  cx<double> SAU = mk<double>(0, 0), SEU = mk<double>(0, 0), SAV = mk<double>(0, 0), SEV = mk<double>(0, 0),
+             STV = mk<double>(0, 0);
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    // unit vector of link l from spacecraft l to spacecraft (l + 1) mod 3
+    double oi[3], oj[3];
+    sc_offset(l, ca, sa, c2a, s2a, oi);
+    sc_offset(l == 2 ? 0 : l + 1, ca, sa, c2a, s2a, oj);
+    const double nx = oj[0] - oi[0], ny = oj[1] - oi[1], nz = oj[2] - oi[2];
+    const double kn = w.kx * nx + w.ky * ny + w.kz * nz;
+    const double am = fc.a * (1.0 - kn), ap = fc.a * (1.0 + kn);
+    R s1r, ddr;
+    sinc_pair<R>((R)(am * am), (R)(ap * ap), fc.ns, s1r, ddr);
+    const double np = w.px * nx + w.py * ny + w.pz * nz;
+    const double nq = w.qx * nx + w.qy * ny + w.qz * nz;
+    // n e+ n = np^2 - nq^2, n ex n = 2 np nq
+    const cx<double> wl = mk<double>(kp * ((np - nq) * (np + nq)), kc * (2.0 * np * nq));
+    const double delta = -4.0 * fc.a * fc.a * kn * (double)ddr;  // sinc(x_ij) - sinc(x_ji)
+    const double sigma = (double)s1r - 0.5 * delta;             // (sinc(x_ij) + sinc(x_ji)) / 2
+    const cx<double> wz = wl * z[l];
+    const cx<double> U = sigma * wz, V = delta * wz;
+    if (l == 0) {
+      SAU = SAU + U;
+      SEU = SEU - U;
+      SAV = SAV - V;
+      SEV = SEV - V;
+    } else if (l == 1) {
+      SAU = SAU + U;
+      SEU = SEU + U;
+      SAV = SAV + V;
+      SEV = SEV - V;
+    } else {
+      SAU = SAU - 2.0 * U;
+      SEV = SEV + 2.0 * V;
+    }
+    STV = STV + V;
+  }
+  T[0] = fc.Cp * SAU + fc.Cm * mul_mi(SAV);
+  T[1] = (3.0 * fc.Cp) * SEU + fc.Cm * mul_mi(SEV);
+  T[2] = (2.0 * fc.Cm) * mul_mi(STV);
 }
 
 // Template of one walker at frequency f: small factors s[c] (FP64) and the
@@ -466,8 +572,8 @@ __device__ __forceinline__ FreqC<R> freq_consts(double f) {
 // mode phase) is applied in FP64, so FP32 rounding cannot act as a coherent
 // shift of D_L or phi_ref.  Returns true if any mode is inside its support.
 template <typename R>
-__device__ __forceinline__ bool template_point(const WalkerC &w, uint32_t modes, double f, double t_obs,
-                                               cx<double> s[3], double &psi) {
+__device__ __forceinline__ bool template_point(const WalkerC &w, uint32_t modes, double f, const FreqC &fc,
+                                               double t_obs, cx<double> s[3], double &psi) {
   if (w.model == 1) {  // 0PN chirp, one channel
     double x = w.piMc * f;
     double cx1 = cbrt64_nr(x);
@@ -481,15 +587,14 @@ __device__ __forceinline__ bool template_point(const WalkerC &w, uint32_t modes,
   }
   // carrier: (2,2) phase, t_ref shift, guiding-centre Doppler at t_22, arm phase
   double ph22, dph22, amp22;
-  wf22<R>(w, f, 0, ph22, dph22, amp22);
+  wf22(w, f, 0, ph22, dph22, amp22);
   double t22 = w.tref - dph22 * kInvTwoPi;
   double al22 = reduce_2pi(t22 * (kTwoPi / kYearS));
   double sa22, ca22;
-  Prec<R>::sincos_alpha(al22, sa22, ca22);
+  sincos_red<double>(al22, sa22, ca22);
   double dop22 = kTwoPi * f * kOrbR * (w.kx * ca22 + w.ky * sa22);
   psi = ph22 - kTwoPi * f * w.tref - dop22 - 4.0 * kPi * f * kArmS;
 
-  FreqC<R> fc = freq_consts<R>(f);
   s[0] = s[1] = s[2] = mk<double>(0.0, 0.0);
   bool any = false;
 #pragma unroll 1
@@ -507,32 +612,26 @@ __device__ __forceinline__ bool template_point(const WalkerC &w, uint32_t modes,
       fm = mk<double>(amp * w.eph[0][0], amp * w.eph[0][1]);
     } else {
       double ph, dph;
-      wf22<R>(w, fp, kModeVPow[mi], ph, dph, amp);
+      wf22(w, fp, kModeVPow[mi], ph, dph, amp);
       amp *= w.rel[mi];
       tlm = w.tref - dph * kInvTwoPi;
       double al = reduce_2pi(tlm * (kTwoPi / kYearS));
-      Prec<R>::sincos_alpha(al, sa, ca);
+      sincos_red<double>(al, sa, ca);
       double dop = kTwoPi * f * kOrbR * (w.kx * ca + w.ky * sa);
       // Psi_lm - Psi = (m/2 phi_22(2f/m) - phi_22(f)) - (Doppler_lm - Doppler_22)
       double dlt = reduce_2pi((0.5 * m * ph - ph22) - (dop - dop22));
-      R sd, cd;
-      Prec<R>::sincos_r((R)dlt, sd, cd);
-      cx<double> e = mk<double>((double)cd, -(double)sd);
+      double sd, cd;
+      sincos_red<double>(dlt, sd, cd);
+      cx<double> e = mk<double>(cd, -sd);
       fm = e * mk<double>(amp * w.eph[mi][0], amp * w.eph[mi][1]);
     }
     if (!(fp <= w.fcut && tlm >= 0.0 && tlm <= t_obs)) continue;
     any = true;
-    cx<R> Tp[3], Tc[3];
-    response_pol<R>(w, fc.f, fc.a, fc.Cp, fc.Cm, (R)ca, (R)sa, Tp, Tc);
-    const double kp = w.kp[mi], kc = w.kc[mi];
+    cx<double> T[3];
+    response_mode<R>(w, w.kp[mi], w.kc[mi], fc, ca, sa, T);
     const double nrm[3] = {1.0 / kSqrt2, 1.0 / kSqrt6, 1.0 / kSqrt3};
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      // K+ T+ + Kx Tx = e^{i m phi} (kp T+ + i kc Tx)
-      cx<double> t = mk<double>(nrm[c] * (kp * (double)Tp[c].re - kc * (double)Tc[c].im),
-                                nrm[c] * (kp * (double)Tp[c].im + kc * (double)Tc[c].re));
-      s[c] = s[c] + fm * t;
-    }
+    for (int c = 0; c < 3; ++c) s[c] = s[c] + fm * (nrm[c] * T[c]);
   }
   return any;
 }

@@ -47,7 +47,9 @@ struct mbh_ref {
   int n_chan = 0, n_bins = 0;
   int64_t k_lo = 0, k_hi = 0;
   double t_obs = 0, lnL0 = 0, dd = 0, dh0 = 0, hh0 = 0;
-  double *F = nullptr, *psi0 = nullptr, *is064 = nullptr, *coef = nullptr;
+  // device: edges [E], response factors [E][3], carrier phase of h0 [E],
+  // 1/s0 [C][E][2], residual-form coefficients [C][Nb][6]
+  double *F = nullptr, *fq = nullptr, *psi0 = nullptr, *is064 = nullptr, *coef = nullptr;
   std::vector<double> edges, A0, A1, B0, B1, h0_edges;
   std::vector<int64_t> kb;
 };

@@ -13,13 +13,14 @@ constexpr int kBlock = 256;
 // B1/dF_b, where dF_b = F_{b+1} - F_b.
 struct HetRef {
   const double *F;      // [E] bin edges
+  const double *fq;     // [E][3] response factors a, Cp, Cm of each edge
   const double *psi0;   // [E] carrier phase of h0
   const double *is064;  // [C][E][2] 1/s0
   const double *coef;   // [C][Nb][6]
   double lnL0, dh0, hh0, t_obs;
   int32_t n_bins, n_chan;
   uint32_t modes;
-  int32_t pad;
+  int32_t ns64, ns32;   // sinc terms over the edges for FP64 / FP32
 };
 
 // ---------------------------------------------------------------- utilities
@@ -110,9 +111,10 @@ static __global__ __launch_bounds__(kBlock) void k_template_grid(const WalkerC *
   double f = grid_freq(f0, df, k);
   cx<double> s[3];
   double psi;
-  bool any = template_point<double>(w, modes, f, t_obs, s, psi);
+  const int ns = sinc_terms_for<double>(grid_freq(f0, df, n_f - 1));
+  bool any = template_point<double>(w, modes, f, freq_consts<double>(f, ns), t_obs, s, psi);
   double sp = 0.0, cp = 1.0;
-  if (any) sincos(reduce_2pi(psi), &sp, &cp);
+  if (any) sincos_red<double>(reduce_2pi(psi), sp, cp);
   for (int c = 0; c < n_chan; ++c) {
     cx<double> v = any ? s[c] * mk<double>(cp, -sp) : mk<double>(0.0, 0.0);
     h[c * n_f + k] = make_double2(v.re / kAmpScale, v.im / kAmpScale);
@@ -132,13 +134,14 @@ static __global__ __launch_bounds__(kBlock) void k_ref_grid(const WalkerC *__res
   double a_res = 0.0, a_dh = 0.0, a_hh = 0.0;
   unsigned long long lo = ~0ull, hi = 0ull;
   bool seen = false;
+  const int ns = sinc_terms_for<double>(grid_freq(f0, df, n_f - 1));
   for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < n_f; k += (int64_t)gridDim.x * kBlock) {
     double f = grid_freq(f0, df, k);
     cx<double> s[3];
     double psi;
-    bool any = template_point<double>(w, modes, f, t_obs, s, psi);
+    bool any = template_point<double>(w, modes, f, freq_consts<double>(f, ns), t_obs, s, psi);
     double sp = 0.0, cp = 1.0;
-    if (any) sincos(reduce_2pi(psi), &sp, &cp);
+    if (any) sincos_red<double>(reduce_2pi(psi), sp, cp);
     bool nz = false;
     for (int c = 0; c < n_chan; ++c) {
       int64_t i = c * n_f + k;
@@ -225,173 +228,400 @@ static __global__ void k_sum_bins(const double *__restrict__ part, int n_sub, do
   }
 }
 
-// pass 3: carrier phase and small factors of h0 at the edges
-static __global__ __launch_bounds__(64) void k_ref_edges(const WalkerC *__restrict__ wc, uint32_t modes, int n_chan, int E,
-                            const double *__restrict__ F, double t_obs, double *__restrict__ psi0,
-                            double2 *__restrict__ s0) {
+// pass 3: response factors of the edges, carrier phase and small factors of
+// h0 at the edges
+static __global__ __launch_bounds__(64) void k_ref_edges(const WalkerC *__restrict__ wc, uint32_t modes, int n_chan,
+                                                         int E, const double *__restrict__ F, double t_obs,
+                                                         double *__restrict__ fq, double *__restrict__ psi0,
+                                                         double2 *__restrict__ s0) {
   int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= E) return;
+  FreqC fc;
+  freq_consts64(F[j], fc.a, fc.Cp, fc.Cm);
+  fc.ns = sinc_terms_for<double>(F[E - 1]);
+  fq[3 * j] = fc.a;
+  fq[3 * j + 1] = fc.Cp;
+  fq[3 * j + 2] = fc.Cm;
   cx<double> s[3];
   double psi;
-  bool any = template_point<double>(wc[0], modes, F[j], t_obs, s, psi);
+  bool any = template_point<double>(wc[0], modes, F[j], fc, t_obs, s, psi);
   psi0[j] = psi;
   for (int c = 0; c < n_chan; ++c) s0[c * E + j] = any ? make_double2(s[c].re, s[c].im) : make_double2(0.0, 0.0);
 }
 
 // ---------------------------------------------------------------- a2-a7: heterodyned
-// FP64 recomputation queue of the mixed path.  The FP32 response leaves a
-// per-edge relative error of ~1e-7 on r - 1; its effect on lnL is estimated
-// per walker as kMixedErrScale * sqrt(S / 2), S = sum over bins and channels
-// of |dT/d delta_0|^2 + 4 |dT/d delta_1|^2 (the gradient of the bin term
-// with respect to the edge values).  kMixedErrScale bounds the measured ratio
+// Residual form of the heterodyned likelihood (Sec. 2.2): with delta = r - 1
+// at the bin edges, delta_0 its value at the bin centre and delta_1 its slope,
+//   lnL = lnL(h0) + sum_b,c { 4 Re[(A0 - B0) delta_0* + (A1 - B1) delta_1*]
+//                             - 2 [B0 |delta_0|^2 + 2 B1 Re(delta_0 delta_1*)] },
+// which equals -(1/2)(<d|d> + Z[h,h] - 2 Z[d,h]) up to the second-order
+// B2 term that the piecewise-linear ratio drops.
+//
+// Mixed precision: the FP32 parts of the response (sinc series, link phase
+// factors) leave a per-edge relative error of ~1e-7 on r - 1, random from
+// edge to edge; its effect on lnL is estimated per walker as
+// kMixedErrScale * sqrt(S / 2), S = sum over bins and channels of
+// |dT/d delta_0|^2 + 4 |dT/d delta_1|^2 (the gradient of the bin term T with
+// respect to the edge values).  kMixedErrScale bounds the measured ratio
 // |lnL_mixed - lnL_fp64| / sqrt(S / 2) over tempered walker clouds at SNR
 // 100-1000; walkers whose estimate exceeds kMixedRouteTol are queued and
 // recomputed in FP64, so the mixed result stays within 1e-3 of FP64.
-constexpr double kMixedErrScale = 6e-7;
-constexpr double kMixedRouteTol = 5e-4;
+constexpr double kMixedErrScale = 2.5e-7;
+constexpr double kMixedRouteTol = 9e-4;
 
-struct RouteQ {
-  unsigned int *count;  // entries queued by the mixed pass (null: no routing)
-  int2 *list;           // (item, walker)
-  int item;
+// Flattened mapping: task t = w E + j is (walker w, edge j).  A wavefront
+// takes the 64 tasks 63 c .. 63 c + 63 of chunk c: every lane evaluates its
+// edge, and lanes 0..62 close the bin that starts at their edge with the
+// value of lane + 1, so each bin is formed exactly once and no lane idles.
+constexpr int kChunk = 63;
+constexpr int kWaves = kBlock / 64;
+
+// One heterodyned work item: a reference, a walker batch, its outputs and
+// per-walker scratch.  G is the number of lanes per walker of the lane-group
+// mapping, or 0 for the flattened mapping.
+struct WorkItem {
+  HetRef ref;
+  const double *theta;   // [W][11]
+  WalkerC *wc;           // [W] walker constants
+  double *lnL;           // [W]
+  double *dhhh;          // [W][2] or null
+  double *part;          // [W][K][4] per-walker partial sums of the main pass
+  int *rlist;            // [W] walkers queued for FP64 (mixed path)
+  unsigned int *rcount;  // queue length, or null (no routing)
+  int64_t W;
+  int64_t offset;        // first walker of this item in its batch
+  int32_t E, K, G, model;
 };
 
-// One lane group of G lanes per walker; lane gl evaluates edges gl, gl+G, ...
-// The right neighbour edge of each bin comes from lane gl+1 (rotate within
-// the group); the last lane's bin closes one iteration later with lane 0's
-// next edge.  Bin terms accumulate in FP64 and are summed over the group with
-// a fixed butterfly, so a walker's result depends only on its inputs and G.
-template <typename R, int G, bool DH>
-__device__ __forceinline__ void het_walker(const HetRef &ref, const WalkerC *__restrict__ wc, int64_t w,
-                                           int64_t W, double *__restrict__ lnL, double *__restrict__ dhhh,
-                                           RouteQ rq) {
-  constexpr bool EST = sizeof(R) == 4;
+// chunks of the flattened main pass (the last bin sits at task W E - 2)
+__host__ __device__ inline int64_t flat_chunks(int64_t W, int E) { return (W * E - 2) / kChunk + 1; }
+// partial slots per walker: chunks that one walker's bins can touch
+__host__ __device__ inline int flat_slots(int E) { return (E - 2) / kChunk + 2; }
+
+// delta = r - 1 at edge j of walker c
+template <typename R>
+__device__ __forceinline__ void het_edge(const HetRef &ref, const WalkerC &c, int j, cx<double> dl[3]) {
+  cx<double> s[3];
+  double psi;
+  const FreqC fc{ref.fq[3 * j], ref.fq[3 * j + 1], ref.fq[3 * j + 2], sizeof(R) == 8 ? ref.ns64 : ref.ns32};
+  template_point<R>(c, ref.modes, ref.F[j], fc, ref.t_obs, s, psi);
+  // the carrier difference enters every channel of the edge at once: FP64
+  // in both paths
+  const double dpsi = reduce_2pi(psi - ref.psi0[j]);
+  double hs, hc;
+  sincos_red<double>(0.5 * dpsi, hs, hc);
+  // e^{-i dpsi} - 1 = -2 sin^2(dpsi/2) - i sin(dpsi)
+  const cx<double> em1 = mk<double>(-2.0 * hs * hs, -2.0 * hs * hc);
+  const cx<double> e = mk<double>(1.0 + em1.re, em1.im);
+  const int E = ref.n_bins + 1;
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) {
+    if (ch >= ref.n_chan) break;
+    cx<double> is0 = mk<double>(ref.is064[2 * (ch * E + j)], ref.is064[2 * (ch * E + j) + 1]);
+    cx<double> q = s[ch] * is0;
+    q.re -= 1.0;
+    dl[ch] = q * e + em1;  // r - 1 without cancellation
+  }
+}
+
+// bin term of bin b from delta at its left (L) and right (Rt) edges:
+// v[0] += lnL - lnL(h0), v[1] += Z[d,h] - <d|h0>, v[2] += Z[h,h] - <h0|h0>,
+// v[3] += squared gradient (without its factor 4) for the FP32 error estimate
+template <bool EST, bool DH>
+__device__ __forceinline__ void bin_terms(const HetRef &ref, int b, const cx<double> L[3], const cx<double> Rt[3],
+                                          double v[4]) {
+  const int Nb = ref.n_bins;
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) {
+    if (ch >= ref.n_chan) break;
+    const double *k = ref.coef + ((int64_t)ch * Nb + b) * 6;
+    // delta_0 at the bin centre and the edge difference delta_1 dF_b
+    const double d0r = 0.5 * (L[ch].re + Rt[ch].re), d0i = 0.5 * (L[ch].im + Rt[ch].im);
+    const double d1r = Rt[ch].re - L[ch].re, d1i = Rt[ch].im - L[ch].im;
+    const double re_a = k[0] * d0r + k[1] * d0i + k[2] * d1r + k[3] * d1i;
+    const double m0 = d0r * d0r + d0i * d0i;
+    const double x01 = d0r * d1r + d0i * d1i;
+    v[0] += 4.0 * re_a - 2.0 * (k[4] * m0 + 2.0 * k[5] * x01);
+    if constexpr (DH) {
+      // Z[d,h] - <d|h0> = 4 Re[A0 conj(d0) + A1 conj(d1)], A = (A - B) + B
+      v[1] += 4.0 * (re_a + k[4] * d0r + k[5] * d1r);
+      // Z[h,h] - <h0|h0> = 4 {B0 (2 Re d0 + |d0|^2) + 2 B1 (Re d1 + Re d0 conj d1)}
+      v[2] += 4.0 * (k[4] * (2.0 * d0r + m0) + 2.0 * k[5] * (d1r + x01));
+    }
+    if constexpr (EST) {
+      const double g0r = k[0] - k[4] * d0r - k[5] * d1r, g0i = k[1] - k[4] * d0i - k[5] * d1i;
+      const double g1r = k[2] - k[5] * d0r, g1i = k[3] - k[5] * d0i;
+      v[3] += g0r * g0r + g0i * g0i + 4.0 * (g1r * g1r + g1i * g1i);
+    }
+  }
+}
+
+// Lane-group mapping: G lanes per walker, lane gl takes edges gl, gl + G, ...
+// The right edge of each bin comes from lane gl + 1 (rotation within the
+// group); the last lane's bin closes one iteration later with lane 0's next
+// edge.  The group's sums are the walker's single slot (main pass) or, for
+// the FP64 recomputation of a queued walker (FIX), its outputs.
+template <typename R, int G, bool DH, bool FIX = false>
+__device__ __forceinline__ void het_walker(const WorkItem &it, int64_t w) {
+  constexpr bool EST = !FIX && sizeof(R) == 4;
   const int lane = threadIdx.x & 63;
   const int gl = lane & (G - 1);
-  // with one walker per wavefront the walker index is wave-uniform: say so,
-  // so that the walker constants live in scalar registers
+  // with one walker per wavefront its constants are wave-uniform
   if constexpr (G == 64) w = (int64_t)__builtin_amdgcn_readfirstlane((int)w);
-  const bool active = w < W;
-  const WalkerC &c = wc[active ? w : 0];
+  const bool active = w < it.W;
+  const WalkerC &c = it.wc[active ? w : 0];
   const bool valid = active && c.valid;
-  const int Nb = ref.n_bins, E = Nb + 1, C = ref.n_chan;
+  const int Nb = it.ref.n_bins, E = Nb + 1;
   const int n_iter = (E + G - 1) / G;
-  double acc = 0.0, a_dh = 0.0, a_hh = 0.0, a_s = 0.0;
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
   cx<double> dprev[3];
 #pragma unroll
   for (int ch = 0; ch < 3; ++ch) dprev[ch] = mk<double>(0.0, 0.0);
   const int src = (lane & ~(G - 1)) | ((gl + 1) & (G - 1));
-
-  for (int it = 0; it < n_iter; ++it) {
-    const int j = it * G + gl;
+  for (int itr = 0; itr < n_iter; ++itr) {
+    const int j = itr * G + gl;
     cx<double> dl[3];
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) dl[ch] = mk<double>(0.0, 0.0);
-    if (valid && j < E) {
-      cx<double> s[3];
-      double psi;
-      template_point<R>(c, ref.modes, ref.F[j], ref.t_obs, s, psi);
-      double dpsi = reduce_2pi(psi - ref.psi0[j]);
-      R hs_r, hc_r;
-      Prec<R>::sincos_r((R)(0.5 * dpsi), hs_r, hc_r);
-      const double hs = hs_r, hc = hc_r;
-      // e^{-i dpsi} - 1 = -2 sin^2(dpsi/2) - i sin(dpsi)
-      cx<double> em1 = mk<double>(-2.0 * hs * hs, -2.0 * hs * hc);
-      cx<double> e = mk<double>(1.0 + em1.re, em1.im);
-#pragma unroll
-      for (int ch = 0; ch < 3; ++ch) {
-        if (ch >= C) break;
-        cx<double> is0 = mk<double>(ref.is064[2 * (ch * E + j)], ref.is064[2 * (ch * E + j) + 1]);
-        cx<double> q = s[ch] * is0;
-        q.re -= 1.0;
-        dl[ch] = q * e + em1;  // r - 1 without cancellation
-      }
-    }
-    cx<double> nb[3];
+    if (valid && j < E) het_edge<R>(it.ref, c, j, dl);
+    cx<double> nb[3], lft[3];
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
       nb[ch].re = __shfl(dl[ch].re, src, 64);
       nb[ch].im = __shfl(dl[ch].im, src, 64);
+      lft[ch] = gl < G - 1 ? dl[ch] : dprev[ch];
     }
-    int b;
-    cx<double> Lft[3];
-    if (gl < G - 1) {
-      b = j;
-#pragma unroll
-      for (int ch = 0; ch < 3; ++ch) Lft[ch] = dl[ch];
-    } else {
-      b = it * G - 1;
-#pragma unroll
-      for (int ch = 0; ch < 3; ++ch) Lft[ch] = dprev[ch];
-    }
-    if (valid && b >= 0 && b < Nb) {
-#pragma unroll
-      for (int ch = 0; ch < 3; ++ch) {
-        if (ch >= C) break;
-        const double *k = ref.coef + ((int64_t)ch * Nb + b) * 6;
-        // delta_0 at the bin centre and the edge difference delta_1 dF_b, in FP64
-        double d0r = 0.5 * (Lft[ch].re + nb[ch].re);
-        double d0i = 0.5 * (Lft[ch].im + nb[ch].im);
-        double d1r = nb[ch].re - Lft[ch].re;
-        double d1i = nb[ch].im - Lft[ch].im;
-        double re_a = k[0] * d0r + k[1] * d0i + k[2] * d1r + k[3] * d1i;
-        double m0 = d0r * d0r + d0i * d0i;
-        double x01 = d0r * d1r + d0i * d1i;
-        acc += 4.0 * re_a - 2.0 * (k[4] * m0 + 2.0 * k[5] * x01);
-        if constexpr (EST) {
-          // gradient of the bin term (without its factor 4)
-          double g0r = k[0] - k[4] * d0r - k[5] * d1r, g0i = k[1] - k[4] * d0i - k[5] * d1i;
-          double g1r = k[2] - k[5] * d0r, g1i = k[3] - k[5] * d0i;
-          a_s += g0r * g0r + g0i * g0i + 4.0 * (g1r * g1r + g1i * g1i);
-        }
-        if constexpr (DH) {
-          // Z[d,h] - <d|h0> = 4 Re[A0 conj(d0) + A1 conj(d1)], A = (A - B) + B
-          a_dh += 4.0 * (re_a + k[4] * d0r + k[5] * d1r);
-          // Z[h,h] - <h0|h0> = 4 {B0 (2 Re d0 + |d0|^2) + 2 B1 (Re d1 + Re d0 conj d1)}
-          a_hh += 4.0 * (k[4] * (2.0 * d0r + m0) + 2.0 * k[5] * (d1r + x01));
-        }
-      }
-    }
+    const int b = gl < G - 1 ? j : itr * G - 1;
+    if (valid && b >= 0 && b < Nb) bin_terms<EST, DH>(it.ref, b, lft, nb, v);
     if (gl == G - 1) {
 #pragma unroll
       for (int ch = 0; ch < 3; ++ch) dprev[ch] = dl[ch];
     }
   }
 #pragma unroll
-  for (int off = G / 2; off >= 1; off >>= 1) {
-    acc += __shfl_xor(acc, off, 64);
-    if constexpr (EST) a_s += __shfl_xor(a_s, off, 64);
-    if constexpr (DH) {
-      a_dh += __shfl_xor(a_dh, off, 64);
-      a_hh += __shfl_xor(a_hh, off, 64);
-    }
-  }
-  if constexpr (EST) {
-    // S carries the bin-term gradient without its factor 4: sqrt(S_true / 2) = sqrt(8 S)
-    if (valid && rq.count && kMixedErrScale * sqrt(8.0 * a_s) > kMixedRouteTol) {
-      if (gl == 0) {
-        unsigned int slot = atomicAdd(rq.count, 1u);
-        rq.list[slot] = make_int2(rq.item, (int)w);
-      }
-      return;  // the FP64 recomputation writes this walker's outputs
-    }
-  }
+  for (int off = G / 2; off >= 1; off >>= 1)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] += __shfl_xor(v[q], off, 64);
   if (active && gl == 0) {
-    lnL[w] = valid ? ref.lnL0 + acc : -INFINITY;
-    if constexpr (DH) {
-      if (dhhh) {
-        dhhh[2 * w] = valid ? ref.dh0 + a_dh : 0.0;
-        dhhh[2 * w + 1] = valid ? ref.hh0 + a_hh : 0.0;
+    if constexpr (FIX) {
+      it.lnL[w] = it.ref.lnL0 + v[0];
+      if (it.dhhh) {
+        it.dhhh[2 * w] = it.ref.dh0 + v[1];
+        it.dhhh[2 * w + 1] = it.ref.hh0 + v[2];
       }
+    } else {
+      double *o = it.part + w * it.K * 4;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) o[q] = v[q];
     }
   }
 }
 
+// Flattened mapping, one chunk per wavefront: the tasks of the item's W
+// walkers, E per walker.  For every walker with bins in the chunk, the
+// chunk's sums go to the walker's slot (chunk - first chunk of the walker).
+template <typename R, bool DH>
+__device__ __forceinline__ void het_chunk(const WorkItem &it, int64_t chunk) {
+  constexpr bool EST = sizeof(R) == 4;
+  const int lane = threadIdx.x & 63;
+  const int E = it.E;
+  // chunk is wave-uniform: the first task's walker and edge are scalars, the
+  // lanes' offsets from them need only a 32-bit division
+  const int64_t t0 = chunk * kChunk;
+  const int64_t v0 = t0 / E;
+  const int j0 = (int)(t0 - v0 * E);
+  const unsigned jl = (unsigned)(j0 + lane);
+  const unsigned qv = jl / (unsigned)E;
+  const int64_t v = v0 + qv;
+  const int j = (int)(jl - qv * (unsigned)E);
+  const bool act = v < it.W;
+  const WalkerC &c = it.wc[act ? v : 0];
+  const bool valid = act && c.valid;
+  cx<double> dl[3];
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) dl[ch] = mk<double>(0.0, 0.0);
+  if (valid) het_edge<R>(it.ref, c, j, dl);
+  cx<double> nb[3];
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) {
+    nb[ch].re = __shfl_down(dl[ch].re, 1, 64);
+    nb[ch].im = __shfl_down(dl[ch].im, 1, 64);
+  }
+  double val[4] = {0.0, 0.0, 0.0, 0.0};
+  const bool is_bin = valid && lane < kChunk && j < E - 1;
+  if (is_bin) bin_terms<EST, DH>(it.ref, j, dl, nb, val);
+  // per-walker sums over the lanes of this chunk, fixed butterfly order
+  const int64_t v_hi = min(v0 + (j0 + kChunk - 1) / E, it.W - 1);
+  for (int64_t vs = v0; vs <= v_hi; ++vs) {
+    const bool mine = is_bin && v == vs;
+    double s[4];
+    s[0] = wave_sum(mine ? val[0] : 0.0);
+    s[1] = DH ? wave_sum(mine ? val[1] : 0.0) : 0.0;
+    s[2] = DH ? wave_sum(mine ? val[2] : 0.0) : 0.0;
+    s[3] = EST ? wave_sum(mine ? val[3] : 0.0) : 0.0;
+    if (lane == 0) {
+      double *o = it.part + (vs * it.K + (chunk - (vs * E) / kChunk)) * 4;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) o[q] = s[q];
+    }
+  }
+}
+
+// item of flattened walker t: the last item whose offset is <= t
+__device__ __forceinline__ int item_of(const WorkItem *__restrict__ items, int n_items, int64_t t) {
+  int lo = 0, hi = n_items - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (items[mid].offset <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Exclusive prefix sums of the per-item queue lengths (total in
+// fix_off[n_items]); adds the number of queued walkers to *routed_total.
+// Run by one whole workgroup once every walker has been finished.
+__device__ __forceinline__ void fix_plan(const WorkItem *__restrict__ items, const WorkItem &one, int n_items,
+                                         int64_t *__restrict__ fix_off,
+                                         unsigned long long *__restrict__ routed_total) {
+  __shared__ int64_t sh_c[kBlock];
+  const int per = (n_items + kBlock - 1) / kBlock;
+  const int i0 = threadIdx.x * per, i1 = min(n_items, i0 + per);
+  int64_t c = 0;
+  for (int i = i0; i < i1; ++i) {
+    const WorkItem &it = items ? items[i] : one;
+    c += it.rcount ? (int64_t)atomicAdd(it.rcount, 0u) : 0;
+  }
+  sh_c[threadIdx.x] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t acc = 0;
+    for (int k = 0; k < kBlock; ++k) {
+      const int64_t x = sh_c[k];
+      sh_c[k] = acc;
+      acc += x;
+    }
+    fix_off[n_items] = acc;
+    if (routed_total) *routed_total += (unsigned long long)acc;
+  }
+  __syncthreads();
+  int64_t acc = sh_c[threadIdx.x];
+  for (int i = i0; i < i1; ++i) {
+    const WorkItem &it = items ? items[i] : one;
+    fix_off[i] = acc;
+    acc += it.rcount ? (int64_t)atomicAdd(it.rcount, 0u) : 0;
+  }
+}
+
+// Per-walker totals of the main pass: the walker's slots are added in slot
+// order, then the outputs are written or (EST, mixed path) the walker is
+// queued for FP64 when its error estimate is above tolerance (one atomic per
+// wavefront and item).  On the mixed path the last workgroup to finish (done
+// counter, zeroed by the setup kernel; device-scope atomics only) builds the
+// plan of the FP64 recomputation.  A single item may be passed by value in
+// `one` with items == nullptr.
+template <bool EST>
+static __global__ __launch_bounds__(kBlock) void k_het_final(const WorkItem *__restrict__ items, WorkItem one,
+                                                             int n_items, int64_t total, unsigned int *done,
+                                                             int64_t *fix_off, unsigned long long *routed_total) {
+  const int lane = threadIdx.x & 63;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  // grid-stride in whole wavefronts: every lane takes part in the queue appends
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < total; base += stride) {
+    const int64_t t = base + lane;
+    const bool in = t < total;
+    const int ii = (in && items) ? item_of(items, n_items, t) : 0;
+    const WorkItem &it = items ? items[ii] : one;
+    const int64_t w = t - it.offset;
+    const bool act = in && w < it.W;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    bool valid = false;
+    if (act) {
+      int n_slot = 1;
+      if (it.G == 0) n_slot = (int)((w * it.E + it.E - 2) / kChunk - (w * it.E) / kChunk) + 1;
+      const double *p = it.part + w * it.K * 4;
+      for (int k = 0; k < n_slot; ++k)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s[q] += p[4 * k + q];
+      valid = it.wc[w].valid;
+    }
+    // s[3] lacks the gradient's factor 4: sqrt(S / 2) = sqrt(8 s[3])
+    const bool route = EST && act && valid && it.rcount && kMixedErrScale * sqrt(8.0 * s[3]) > kMixedRouteTol;
+    if (EST) {
+      uint64_t pending = __ballot(route);
+      while (pending) {
+        const int leader = __ffsll((unsigned long long)pending) - 1;
+        const int il = __shfl(ii, leader, 64);
+        const bool mine = route && ii == il;
+        const uint64_t m = __ballot(mine);
+        unsigned int slot0 = 0;
+        if (lane == leader) slot0 = atomicAdd(it.rcount, (unsigned int)__popcll(m));
+        slot0 = __shfl(slot0, leader, 64);
+        if (mine) it.rlist[slot0 + __popcll(m & ((1ull << lane) - 1ull))] = (int)w;
+        pending &= ~m;
+      }
+    }
+    if (act && !route) {
+      it.lnL[w] = valid ? it.ref.lnL0 + s[0] : -INFINITY;
+      if (it.dhhh) {
+        it.dhhh[2 * w] = valid ? it.ref.dh0 + s[1] : 0.0;
+        it.dhhh[2 * w + 1] = valid ? it.ref.hh0 + s[2] : 0.0;
+      }
+    }
+  }
+  if (EST) {
+    __shared__ int s_last;
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = atomicAdd(done, 1u) == gridDim.x - 1;
+    __syncthreads();
+    if (s_last) fix_plan(items, one, n_items, fix_off, routed_total);
+  }
+}
+
+// FP64 recomputation of the queued walkers, one wavefront per walker (the
+// 64-lane group mapping, so that the walker's sums never leave the
+// wavefront); the grid covers the largest possible queue and wavefronts past
+// the actual total fix_off[n_items] return at once
+template <bool DH>
+__global__ __launch_bounds__(kBlock) void k_het_fix(const WorkItem *__restrict__ items, WorkItem one, int n_items,
+                                                       const int64_t *__restrict__ fix_off) {
+  const int64_t g = (int64_t)blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (g >= fix_off[n_items]) return;
+  int lo = 0;
+  if (items) {
+    int hi = n_items - 1;  // last item whose first queue entry is <= g
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (fix_off[mid] <= g) lo = mid;
+      else hi = mid - 1;
+    }
+    lo = __builtin_amdgcn_readfirstlane(lo);
+  }
+  const WorkItem &it = items ? items[lo] : one;
+  const int64_t w = __builtin_amdgcn_readfirstlane(it.rlist[g - fix_off[lo]]);
+  het_walker<double, 64, DH, true>(it, w);
+}
+
+// single-item path: walker constants and cleared queue
+static __global__ __launch_bounds__(128) void k_setup_one(WorkItem one, unsigned int *done) {
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w == 0) {
+    if (one.rcount) *one.rcount = 0u;
+    if (done) *done = 0u;
+  }
+  if (w < one.W) walker_setup(one.theta + w * 11, one.model, one.ref.modes, one.wc[w]);
+}
+
+// single-item launches of the main pass
 template <typename R, int G, bool DH>
-__global__ __launch_bounds__(kBlock) void k_het(HetRef ref, const WalkerC *__restrict__ wc, int64_t W,
-                                                double *__restrict__ lnL, double *__restrict__ dhhh, RouteQ rq) {
-  const int64_t w = (int64_t)blockIdx.x * (kBlock / G) + threadIdx.x / G;
-  het_walker<R, G, DH>(ref, wc, w, W, lnL, dhhh, rq);
+__global__ __launch_bounds__(kBlock, 2) void k_het_lane(WorkItem one) {
+  het_walker<R, G, DH>(one, (int64_t)blockIdx.x * (kBlock / G) + threadIdx.x / G);
+}
+
+template <typename R, bool DH>
+__global__ __launch_bounds__(kBlock, 2) void k_het_flat(WorkItem one, int64_t n_chunks) {
+  const int64_t c = (int64_t)blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (c < n_chunks) het_chunk<R, DH>(one, c);
 }
 
 static __global__ void k_zero_u32(unsigned int *p, int n) {
@@ -415,7 +645,7 @@ struct DataPtrs<float> {
 };
 
 template <typename R, int KF, bool DH>
-__global__ __launch_bounds__(kBlock) void k_full(const typename DataPtrs<R>::R2 *__restrict__ dw,
+__global__ __launch_bounds__(kBlock, 2) void k_full(const typename DataPtrs<R>::R2 *__restrict__ dw,
                                                  const R *__restrict__ sw, int n_chan, int64_t n_f, double f0,
                                                  double df, double t_obs, uint32_t modes,
                                                  const WalkerC *__restrict__ wc, int64_t W, int w_per_block,
@@ -427,12 +657,17 @@ __global__ __launch_bounds__(kBlock) void k_full(const typename DataPtrs<R>::R2 
   R2 d[KF][3];
   R s_w[KF][3];
   double fq[KF];
+  FreqC fcs[KF];
   bool inr[KF];
+  // sinc terms for the highest frequency of this workgroup (uniform)
+  const int ns = sinc_terms_for<R>(
+      grid_freq(f0, df, min(n_f - 1, (int64_t)blockIdx.x * (kBlock * KF) + kBlock * KF - 1)));
 #pragma unroll
   for (int i = 0; i < KF; ++i) {
     int64_t k = (int64_t)blockIdx.x * (kBlock * KF) + i * kBlock + threadIdx.x;
     inr[i] = k < n_f;
     fq[i] = grid_freq(f0, df, inr[i] ? k : 0);
+    fcs[i] = freq_consts<R>(fq[i], ns);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       if (c < n_chan && inr[i]) {
@@ -458,7 +693,7 @@ __global__ __launch_bounds__(kBlock) void k_full(const typename DataPtrs<R>::R2 
         if (!inr[i]) continue;
         cx<double> s[3];
         double psi;
-        bool any = template_point<R>(c, modes, fq[i], t_obs, s, psi);
+        bool any = template_point<R>(c, modes, fq[i], fcs[i], t_obs, s, psi);
         R sp = (R)0, cp = (R)1;
         if (any) Prec<R>::sincos_r((R)reduce_2pi(psi), sp, cp);
 #pragma unroll

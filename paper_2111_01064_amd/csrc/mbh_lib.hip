@@ -299,9 +299,10 @@ static void release_ref_dev(mbh_ref *r) {
   const int E = r->n_bins + 1;
   ctx_free(c, r->F, E * sizeof(double));
   ctx_free(c, r->psi0, E * sizeof(double));
+  ctx_free(c, r->fq, (size_t)E * 3 * sizeof(double));
   ctx_free(c, r->is064, (size_t)r->n_chan * E * 2 * sizeof(double));
   ctx_free(c, r->coef, (size_t)r->n_chan * r->n_bins * 6 * sizeof(double));
-  r->F = r->psi0 = r->is064 = r->coef = nullptr;
+  r->F = r->psi0 = r->fq = r->is064 = r->coef = nullptr;
 }
 
 extern "C" mbh_status mbh_ref_release(mbh_ref *r) {
@@ -404,6 +405,7 @@ extern "C" mbh_status mbh_build_reference_coeffs(mbh_ctx *ctx, const mbh_data *d
   mbh_status s;
   if ((s = ctx_alloc(ctx, (void **)&r->F, E * sizeof(double))) != MBH_OK) return fail_free(s);
   if ((s = ctx_alloc(ctx, (void **)&r->psi0, E * sizeof(double))) != MBH_OK) return fail_free(s);
+  if ((s = ctx_alloc(ctx, (void **)&r->fq, (size_t)E * 3 * sizeof(double))) != MBH_OK) return fail_free(s);
   if ((s = ctx_alloc(ctx, (void **)&r->is064, (size_t)C * E * 2 * sizeof(double))) != MBH_OK) return fail_free(s);
   if ((s = ctx_alloc(ctx, (void **)&r->coef, (size_t)C * n_bins * 6 * sizeof(double))) != MBH_OK)
     return fail_free(s);
@@ -422,7 +424,7 @@ extern "C" mbh_status mbh_build_reference_coeffs(mbh_ctx *ctx, const mbh_data *d
   // sum the n_sub chunks of each bin in order: part2 is [Nb][n_sub][18]
   hipLaunchKernelGGL(k_sum_bins, dim3(n_bins), dim3(64), 0, st, part2, n_sub, sums2);
   hipLaunchKernelGGL(k_ref_edges, dim3((E + 63) / 64), dim3(64), 0, st, wc, r->modes, C, E, r->F, data->t_obs,
-                     r->psi0, s0);
+                     r->fq, r->psi0, s0);
   if (hipGetLastError() != hipSuccess) return fail_free(mbh_fail(MBH_EDEVICE, "reference kernels"));
   std::vector<double> hs2((size_t)n_bins * 18), hs0((size_t)C * E * 2);
   if (hipMemcpyAsync(hs2.data(), sums2, hs2.size() * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -534,6 +536,7 @@ HetRef ref_view(const mbh_ref *r) {
   HetRef h;
   h.F = r->F;
   h.psi0 = r->psi0;
+  h.fq = r->fq;
   h.is064 = r->is064;
   h.coef = r->coef;
   h.lnL0 = r->lnL0;
@@ -543,21 +546,20 @@ HetRef ref_view(const mbh_ref *r) {
   h.n_bins = r->n_bins;
   h.n_chan = r->n_chan;
   h.modes = r->modes;
-  h.pad = 0;
+  h.ns64 = sinc_terms_for<double>(r->edges.back());
+  h.ns32 = sinc_terms_for<float>(r->edges.back());
   return h;
 }
 
-// ---------------------------------------------------------------- lanes per walker
+// ---------------------------------------------------------------- heterodyned launches
 int popcount_modes(uint32_t m) { return __builtin_popcount(m); }
 
+// mapping of the heterodyned pass: 0 = flattened (one lane per walker and
+// edge), else lanes per walker of the lane-group mapping
 int default_lanes(int n_bins, int n_modes) {
-  // enough edges per lane to amortise the group reduction, few idle lanes
-  int E = n_bins + 1;
+  (void)n_bins;
   (void)n_modes;
-  if (E <= 40) return 8;
-  if (E <= 80) return 16;
-  if (E <= 300) return 32;
-  return 64;
+  return 0;
 }
 
 int lanes_lookup(const mbh_ctx *ctx, int n_bins, int n_modes, int prec) {
@@ -567,41 +569,69 @@ int lanes_lookup(const mbh_ctx *ctx, int n_bins, int n_modes, int prec) {
   return default_lanes(n_bins, n_modes);
 }
 
+// a work item for reference r with mapping G; buffers are set by the caller
+WorkItem make_item(const mbh_ref *r, int G) {
+  WorkItem it;
+  std::memset(&it, 0, sizeof(it));
+  it.ref = ref_view(r);
+  it.E = r->n_bins + 1;
+  it.K = flat_slots(it.E);
+  it.G = G;
+  it.model = r->model;
+  return it;
+}
+
 template <typename R, bool DH>
-static void launch_het_g(int G, const HetRef &h, const WalkerC *wc, int64_t W, double *lnL, double *dhhh,
-                         RouteQ rq, hipStream_t st) {
-  const int wpb = kBlock / G;
-  dim3 grid((unsigned)((W + wpb - 1) / wpb));
-  switch (G) {
-    case 1: hipLaunchKernelGGL((k_het<R, 1, DH>), grid, dim3(kBlock), 0, st, h, wc, W, lnL, dhhh, rq); break;
-    case 2: hipLaunchKernelGGL((k_het<R, 2, DH>), grid, dim3(kBlock), 0, st, h, wc, W, lnL, dhhh, rq); break;
-    case 4: hipLaunchKernelGGL((k_het<R, 4, DH>), grid, dim3(kBlock), 0, st, h, wc, W, lnL, dhhh, rq); break;
-    case 8: hipLaunchKernelGGL((k_het<R, 8, DH>), grid, dim3(kBlock), 0, st, h, wc, W, lnL, dhhh, rq); break;
-    case 16: hipLaunchKernelGGL((k_het<R, 16, DH>), grid, dim3(kBlock), 0, st, h, wc, W, lnL, dhhh, rq); break;
-    case 32: hipLaunchKernelGGL((k_het<R, 32, DH>), grid, dim3(kBlock), 0, st, h, wc, W, lnL, dhhh, rq); break;
-    default: hipLaunchKernelGGL((k_het<R, 64, DH>), grid, dim3(kBlock), 0, st, h, wc, W, lnL, dhhh, rq); break;
+static void launch_main_t(const WorkItem &it, hipStream_t st) {
+  if (it.G == 0) {
+    const int64_t nc = flat_chunks(it.W, it.E);
+    hipLaunchKernelGGL((k_het_flat<R, DH>), dim3((unsigned)((nc + kWaves - 1) / kWaves)), dim3(kBlock), 0, st, it,
+                       nc);
+    return;
+  }
+  const int wpb = kBlock / it.G;
+  const dim3 grid((unsigned)((it.W + wpb - 1) / wpb)), blk(kBlock);
+  switch (it.G) {
+    case 1: hipLaunchKernelGGL((k_het_lane<R, 1, DH>), grid, blk, 0, st, it); break;
+    case 2: hipLaunchKernelGGL((k_het_lane<R, 2, DH>), grid, blk, 0, st, it); break;
+    case 4: hipLaunchKernelGGL((k_het_lane<R, 4, DH>), grid, blk, 0, st, it); break;
+    case 8: hipLaunchKernelGGL((k_het_lane<R, 8, DH>), grid, blk, 0, st, it); break;
+    case 16: hipLaunchKernelGGL((k_het_lane<R, 16, DH>), grid, blk, 0, st, it); break;
+    case 32: hipLaunchKernelGGL((k_het_lane<R, 32, DH>), grid, blk, 0, st, it); break;
+    default: hipLaunchKernelGGL((k_het_lane<R, 64, DH>), grid, blk, 0, st, it); break;
   }
 }
 
-void launch_het(int prec, int G, const HetRef &h, const WalkerC *wc, int64_t W, double *lnL, double *dhhh,
-                RouteQ rq, hipStream_t st) {
+// main heterodyned pass of one item (partial sums only)
+static void launch_main(int prec, bool dh, const WorkItem &it, hipStream_t st) {
   if (prec == MBH_FP64) {
-    if (dhhh) launch_het_g<double, true>(G, h, wc, W, lnL, dhhh, rq, st);
-    else launch_het_g<double, false>(G, h, wc, W, lnL, dhhh, rq, st);
+    if (dh) launch_main_t<double, true>(it, st);
+    else launch_main_t<double, false>(it, st);
   } else {
-    if (dhhh) launch_het_g<float, true>(G, h, wc, W, lnL, dhhh, rq, st);
-    else launch_het_g<float, false>(G, h, wc, W, lnL, dhhh, rq, st);
+    if (dh) launch_main_t<float, true>(it, st);
+    else launch_main_t<float, false>(it, st);
   }
 }
 
-int fixup_blocks(const mbh_ctx *ctx, int64_t W) {
-  return (int)std::max<int64_t>(1, std::min<int64_t>((W + 3) / 4, 2 * ctx->n_cu));
-}
-
-void launch_fixup(bool dh, int n_blocks, const WorkItem *items, const WorkItem &one, const int2 *list, unsigned *rc,
-                  hipStream_t st) {
-  if (dh) hipLaunchKernelGGL(k_het_fixup<true>, dim3(n_blocks), dim3(kBlock), 0, st, items, one, list, rc);
-  else hipLaunchKernelGGL(k_het_fixup<false>, dim3(n_blocks), dim3(kBlock), 0, st, items, one, list, rc);
+// Totals of the main pass and, for the mixed path, the FP64 recomputation of
+// the queued walkers (k_het_final, which also plans the recomputation, then
+// k_het_fix over the largest possible queue, max_fix walkers).
+// done: the finishing grid's counter (zero before the launch); fix_off:
+// n_items + 1 entries; routed: running total (64-bit) or null.
+void launch_finish(const mbh_ctx *ctx, int prec, bool dh, const WorkItem *items, const WorkItem &one, int n_items,
+                   int64_t total, int64_t max_fix, unsigned *done, int64_t *fix_off, unsigned long long *routed,
+                   hipStream_t st) {
+  const unsigned fb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + kBlock - 1) / kBlock, 4 * ctx->n_cu));
+  if (prec == MBH_FP64) {
+    hipLaunchKernelGGL(k_het_final<false>, dim3(fb), dim3(kBlock), 0, st, items, one, n_items, total,
+                       (unsigned *)nullptr, (int64_t *)nullptr, (unsigned long long *)nullptr);
+    return;
+  }
+  hipLaunchKernelGGL(k_het_final<true>, dim3(fb), dim3(kBlock), 0, st, items, one, n_items, total, done, fix_off,
+                     routed);
+  const unsigned nb = (unsigned)std::max<int64_t>(1, (max_fix + kWaves - 1) / kWaves);
+  if (dh) hipLaunchKernelGGL(k_het_fix<true>, dim3(nb), dim3(kBlock), 0, st, items, one, n_items, (const int64_t *)fix_off);
+  else hipLaunchKernelGGL(k_het_fix<false>, dim3(nb), dim3(kBlock), 0, st, items, one, n_items, (const int64_t *)fix_off);
 }
 
 extern "C" mbh_status mbh_loglike_heterodyned(mbh_ctx *ctx, const mbh_ref *ref, const double *theta_dev,
@@ -613,33 +643,28 @@ extern "C" mbh_status mbh_loglike_heterodyned(mbh_ctx *ctx, const mbh_ref *ref, 
   if (W == 0) return MBH_OK;
   HIP_TRY(hipSetDevice(ctx->device));
   Scratch sc(ctx, st);
-  WalkerC *wc = nullptr;
-  MBH_TRY(sc.get(&wc, (size_t)W));
-  hipLaunchKernelGGL(k_walker_setup, dim3((unsigned)((W + 127) / 128)), dim3(128), 0, st, theta_dev, W,
-                     ref->model, ref->modes, wc);
-  int G = lanes_lookup(ctx, ref->n_bins, popcount_modes(ref->modes ? ref->modes : 1u), prec);
-  if (prec == MBH_FP64) {
-    launch_het(prec, G, ref_view(ref), wc, W, lnL_dev, dh_hh_dev, RouteQ{nullptr, nullptr, 0}, st);
-  } else {
-    // mixed pass with its FP64 recomputation queue
-    unsigned *rc = nullptr;
-    int2 *list = nullptr;
-    MBH_TRY(sc.get(&rc, 4));
-    MBH_TRY(sc.get(&list, (size_t)W));
-    WorkItem h;
-    h.ref = ref_view(ref);
-    h.theta = theta_dev;
-    h.wc = wc;
-    h.lnL = lnL_dev;
-    h.dhhh = dh_hh_dev;
-    h.W = W;
-    h.offset = 0;
-    h.G = G;
-    h.model = ref->model;
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, rc, 4);
-    launch_het(prec, G, h.ref, wc, W, lnL_dev, dh_hh_dev, RouteQ{rc, list, 0}, st);
-    launch_fixup(dh_hh_dev != nullptr, fixup_blocks(ctx, W), nullptr, h, list, rc, st);
+  const int G = lanes_lookup(ctx, ref->n_bins, popcount_modes(ref->modes ? ref->modes : 1u), prec);
+  WorkItem it = make_item(ref, G);
+  it.theta = theta_dev;
+  it.lnL = lnL_dev;
+  it.dhhh = dh_hh_dev;
+  it.W = W;
+  it.offset = 0;
+  MBH_TRY(sc.get(&it.wc, (size_t)W));
+  MBH_TRY(sc.get(&it.part, (size_t)W * it.K * 4));
+  const bool mixed = prec == MBH_MIXED;
+  unsigned *done = nullptr;
+  int64_t *fix_off = nullptr;
+  if (mixed) {
+    MBH_TRY(sc.get(&it.rlist, (size_t)W));
+    MBH_TRY(sc.get(&it.rcount, 1));
+    MBH_TRY(sc.get(&done, 1));
+    MBH_TRY(sc.get(&fix_off, 2));
   }
+  hipLaunchKernelGGL(k_setup_one, dim3((unsigned)((W + 127) / 128)), dim3(128), 0, st, it, done);
+  const bool dh = dh_hh_dev != nullptr;
+  launch_main(prec, dh, it, st);
+  launch_finish(ctx, prec, dh, nullptr, it, 1, W, W, done, fix_off, nullptr, st);
   HIP_TRY(hipGetLastError());
   return MBH_OK;
 }
@@ -696,7 +721,8 @@ extern "C" mbh_status mbh_loglike_full(mbh_ctx *ctx, const mbh_data *data, int m
 }
 
 // ---------------------------------------------------------------- autotuner
-static bool valid_lanes(int g) { return g == 1 || g == 2 || g == 4 || g == 8 || g == 16 || g == 32 || g == 64; }
+// 0 (flattened mapping) or a power of two in [1, 64] (lanes per walker)
+static bool valid_lanes(int g) { return g == 0 || g == 1 || g == 2 || g == 4 || g == 8 || g == 16 || g == 32 || g == 64; }
 
 extern "C" mbh_status mbh_lanes_for(const mbh_ctx *ctx, int n_bins, int n_modes, mbh_precision prec,
                                     int *lanes_out) {
@@ -706,32 +732,38 @@ extern "C" mbh_status mbh_lanes_for(const mbh_ctx *ctx, int n_bins, int n_modes,
 }
 
 extern "C" mbh_status mbh_set_lanes(mbh_ctx *ctx, int n_bins, int n_modes, mbh_precision prec, int lanes) {
-  if (!ctx || !valid_lanes(lanes)) return mbh_fail(MBH_EINVAL, "lanes must be a power of two in [1, 64]");
+  if (!ctx || !valid_lanes(lanes)) return mbh_fail(MBH_EINVAL, "lanes must be 0 or a power of two in [1, 64]");
   std::lock_guard<std::mutex> g(ctx->mu);
   ctx->lanes[std::make_tuple(n_bins, n_modes, (int)prec)] = lanes;
   return MBH_OK;
 }
 
-// Times every lanes-per-walker choice on the reference's shape with W
-// walkers at the reference point (plus small offsets), keeps the fastest.
-extern "C" mbh_status mbh_autotune_heterodyned(mbh_ctx *ctx, const mbh_ref *ref, int64_t W, mbh_precision prec,
-                                               int *lanes_out) {
+// Times each mapping of the main heterodyned pass (flattened, and lane groups
+// of 16, 32 and 64 lanes per walker) on the reference's shape with W walkers, the
+// caller's (theta_dev) or, if null, copies of a fixed valid parameter point
+// with small offsets; keeps the fastest.
+extern "C" mbh_status mbh_autotune_heterodyned(mbh_ctx *ctx, const mbh_ref *ref, const double *theta_dev,
+                                               int64_t W, mbh_precision prec, int *lanes_out) {
   if (!ctx || !ref || W < 1) return mbh_fail(MBH_EINVAL, "bad argument");
+  if (prec != MBH_FP64 && prec != MBH_MIXED) return mbh_fail(MBH_EINVAL, "bad precision");
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t st;
   HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
   mbh_status rc = MBH_OK;
   {
     Scratch sc(ctx, st);
+    WorkItem it = make_item(ref, 0);
     double *th = nullptr, *lnL = nullptr;
-    WalkerC *wc = nullptr;
+    it.W = W;
     if ((rc = sc.get(&th, (size_t)W * 11)) != MBH_OK || (rc = sc.get(&lnL, (size_t)W)) != MBH_OK ||
-        (rc = sc.get(&wc, (size_t)W)) != MBH_OK) {
+        (rc = sc.get(&it.wc, (size_t)W)) != MBH_OK || (rc = sc.get(&it.part, (size_t)W * it.K * 4)) != MBH_OK) {
       (void)hipStreamSynchronize(st);
       (void)hipStreamDestroy(st);
       return rc;
     }
-    // walkers: a valid parameter vector of the reference's model
+    it.theta = theta_dev ? theta_dev : th;
+    it.lnL = lnL;
+    // default walkers: a valid parameter vector of the reference's model
     std::vector<double> h((size_t)W * 11);
     for (int64_t w = 0; w < W; ++w) {
       double *t = &h[(size_t)w * 11];
@@ -750,15 +782,13 @@ extern "C" mbh_status mbh_autotune_heterodyned(mbh_ctx *ctx, const mbh_ref *ref,
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
     if (hipMemcpyAsync(th, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, st) == hipSuccess) {
-      hipLaunchKernelGGL(k_walker_setup, dim3((unsigned)((W + 127) / 128)), dim3(128), 0, st, th, W, ref->model,
-                         ref->modes, wc);
-      HetRef hv = ref_view(ref);
-      for (int G : {4, 8, 16, 32, 64}) {
-        const RouteQ none{nullptr, nullptr, 0};
-        launch_het(prec, G, hv, wc, W, lnL, nullptr, none, st);  // warm-up
+      hipLaunchKernelGGL(k_setup_one, dim3((unsigned)((W + 127) / 128)), dim3(128), 0, st, it, (unsigned *)nullptr);
+      for (int G : {0, 16, 32, 64}) {
+        it.G = G;
+        launch_main(prec, false, it, st);  // warm-up
         (void)hipEventRecord(e0, st);
         const int reps = 20;
-        for (int r = 0; r < reps; ++r) launch_het(prec, G, hv, wc, W, lnL, nullptr, none, st);
+        for (int r = 0; r < reps; ++r) launch_main(prec, false, it, st);
         (void)hipEventRecord(e1, st);
         (void)hipEventSynchronize(e1);
         float ms = 0.f;

@@ -1,6 +1,6 @@
-// mbh_serve.hip -- ragged multi-source batching in one persistent,
-// graph-captured launch (mbh_batch_*) and a continuous-batching request
-// server on top of the same work-list kernel (mbh_server_*).
+// mbh_serve.hip -- ragged multi-source batching in one graph-captured launch
+// (mbh_batch_*) and a continuous-batching request server on top of the same
+// work-list kernels (mbh_server_*).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -24,9 +24,10 @@ using namespace mbh;
 HetRef ref_view(const mbh_ref *r);
 int lanes_lookup(const mbh_ctx *ctx, int n_bins, int n_modes, int prec);
 int popcount_modes(uint32_t m);
-int fixup_blocks(const mbh_ctx *ctx, int64_t W);
-void launch_fixup(bool dh, int n_blocks, const WorkItem *items, const WorkItem &one, const int2 *list, unsigned *rc,
-                  hipStream_t st);
+WorkItem make_item(const mbh_ref *r, int G);
+void launch_finish(const mbh_ctx *ctx, int prec, bool dh, const WorkItem *items, const WorkItem &one, int n_items,
+                   int64_t total, int64_t max_fix, unsigned *done, int64_t *fix_off, unsigned long long *routed,
+                   hipStream_t st);
 
 #define HIP_TRY(x)                                                                          \
   do {                                                                                      \
@@ -39,56 +40,101 @@ static int item_lanes(const mbh_ctx *ctx, const mbh_ref *r, int prec) {
   return lanes_lookup(ctx, r->n_bins, popcount_modes(r->modes ? r->modes : 1u), prec);
 }
 
-// tiles of one item: kBlock / G walkers each; cost ~ edge iterations x modes
+// tiles of one item: kWaves chunks (G = 0) or kBlock / G walkers each; cost ~
+// edge evaluations per lane x modes
+static int64_t tiles_of(int G, int64_t W, int E) {
+  if (W <= 0) return 0;
+  if (G == 0) return (flat_chunks(W, E) + kWaves - 1) / kWaves;
+  const int64_t wpb = kBlock / G;
+  return (W + wpb - 1) / wpb;
+}
+
 static void append_tiles(std::vector<WorkTile> &tiles, std::vector<double> &cost, int item, const mbh_ref *r,
                          int G, int64_t W) {
-  const int64_t wpb = kBlock / G;
   const int E = r->n_bins + 1;
-  const double c = (double)((E + G - 1) / G) * popcount_modes(r->modes ? r->modes : 1u);
+  const int nm = popcount_modes(r->modes ? r->modes : 1u);
+  if (W <= 0) return;
+  if (G == 0) {
+    const int64_t nc = flat_chunks(W, E);
+    for (int64_t c = 0; c < nc; c += kWaves) {
+      tiles.push_back(WorkTile{item, 0, c});
+      cost.push_back((double)nm);
+    }
+    return;
+  }
+  const int64_t wpb = kBlock / G;
+  const double c = (double)((E + G - 1) / G) * nm;
   for (int64_t w = 0; w < W; w += wpb) {
     tiles.push_back(WorkTile{item, G, w});
     cost.push_back(c);
   }
 }
 
-// longest tiles first; ties keep item order (stable)
-static void order_tiles(std::vector<WorkTile> &tiles, const std::vector<double> &cost) {
+// tiles grouped by mapping, longest first within a group (stable), and the
+// group ranges (G, first tile, count)
+struct TileGroup {
+  int G;
+  int64_t begin, count;
+};
+
+static std::vector<TileGroup> order_tiles(std::vector<WorkTile> &tiles, const std::vector<double> &cost) {
   std::vector<size_t> idx(tiles.size());
   for (size_t i = 0; i < idx.size(); ++i) idx[i] = i;
-  std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+  std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) {
+    if (tiles[a].G != tiles[b].G) return tiles[a].G < tiles[b].G;
+    return cost[a] > cost[b];
+  });
   std::vector<WorkTile> out(tiles.size());
   for (size_t i = 0; i < idx.size(); ++i) out[i] = tiles[idx[i]];
   tiles.swap(out);
-}
-
-static int persistent_blocks(const mbh_ctx *ctx, int prec, bool dh) {
-  int per_cu = 0;
-  hipError_t e;
-  if (prec == MBH_FP64)
-    e = dh ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_het_work<double, true>, kBlock, 0)
-           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_het_work<double, false>, kBlock, 0);
-  else
-    e = dh ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_het_work<float, true>, kBlock, 0)
-           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_het_work<float, false>, kBlock, 0);
-  if (e != hipSuccess || per_cu < 1) per_cu = 1;
-  return per_cu * ctx->n_cu;
-}
-
-// setup (a1), the persistent heterodyned pass and, for the mixed path, the
-// FP64 recomputation of the walkers it queued (rc[4], list[total walkers])
-static void launch_work(const mbh_ctx *ctx, int prec, bool dh, int n_blocks, int setup_blocks, int64_t max_walkers,
-                        const WorkHeader *hdr, const WorkItem *items, const WorkTile *tiles, unsigned *counters,
-                        unsigned *rc, int2 *list, hipStream_t st) {
-  hipLaunchKernelGGL(k_setup_work, dim3(setup_blocks), dim3(128), 0, st, hdr, items);
-  if (prec == MBH_FP64) {
-    if (dh) hipLaunchKernelGGL((k_het_work<double, true>), dim3(n_blocks), dim3(kBlock), 0, st, hdr, items, tiles, counters, (unsigned *)nullptr, (int2 *)nullptr);
-    else hipLaunchKernelGGL((k_het_work<double, false>), dim3(n_blocks), dim3(kBlock), 0, st, hdr, items, tiles, counters, (unsigned *)nullptr, (int2 *)nullptr);
-  } else {
-    if (dh) hipLaunchKernelGGL((k_het_work<float, true>), dim3(n_blocks), dim3(kBlock), 0, st, hdr, items, tiles, counters, rc, list);
-    else hipLaunchKernelGGL((k_het_work<float, false>), dim3(n_blocks), dim3(kBlock), 0, st, hdr, items, tiles, counters, rc, list);
-    WorkItem none{};
-    launch_fixup(dh, fixup_blocks(ctx, max_walkers), items, none, list, rc, st);
+  std::vector<TileGroup> groups;
+  for (size_t i = 0; i < tiles.size(); ++i) {
+    if (groups.empty() || groups.back().G != tiles[i].G) groups.push_back(TileGroup{tiles[i].G, (int64_t)i, 0});
+    groups.back().count += 1;
   }
+  return groups;
+}
+
+template <typename R, bool DH>
+static void launch_group(const TileGroup &g, const WorkItem *items, const WorkTile *tiles, hipStream_t st) {
+  const dim3 grid((unsigned)g.count), blk(kBlock);
+  const WorkTile *t = tiles + g.begin;
+  switch (g.G) {
+    case 0: hipLaunchKernelGGL((k_het_tiles<R, DH, 0>), grid, blk, 0, st, items, t); break;
+    case 1: hipLaunchKernelGGL((k_het_tiles<R, DH, 1>), grid, blk, 0, st, items, t); break;
+    case 2: hipLaunchKernelGGL((k_het_tiles<R, DH, 2>), grid, blk, 0, st, items, t); break;
+    case 4: hipLaunchKernelGGL((k_het_tiles<R, DH, 4>), grid, blk, 0, st, items, t); break;
+    case 8: hipLaunchKernelGGL((k_het_tiles<R, DH, 8>), grid, blk, 0, st, items, t); break;
+    case 16: hipLaunchKernelGGL((k_het_tiles<R, DH, 16>), grid, blk, 0, st, items, t); break;
+    case 32: hipLaunchKernelGGL((k_het_tiles<R, DH, 32>), grid, blk, 0, st, items, t); break;
+    default: hipLaunchKernelGGL((k_het_tiles<R, DH, 64>), grid, blk, 0, st, items, t); break;
+  }
+}
+
+// Counters of one work list (zero at creation): [0..1] running total of the
+// walkers recomputed in FP64 (64-bit), [2] workgroups of the finishing grid
+// that have finished (cleared by the setup kernel of every launch).
+constexpr int kCounterWords = 4;
+
+// setup (a1), one grid per mapping group, the per-walker totals and, for the
+// mixed path, the FP64 recomputation of the walkers the totals queued
+static void launch_work(const mbh_ctx *ctx, int prec, bool dh, int setup_blocks, int n_items, int64_t total,
+                        const std::vector<TileGroup> &groups, const WorkHeader *hdr, const WorkItem *items,
+                        const WorkTile *tiles, unsigned *counters, int64_t *fix_off, hipStream_t st) {
+  unsigned *done = counters + 2;
+  hipLaunchKernelGGL(k_setup_work, dim3(setup_blocks), dim3(128), 0, st, hdr, items, done);
+  for (const TileGroup &g : groups) {
+    if (prec == MBH_FP64) {
+      if (dh) launch_group<double, true>(g, items, tiles, st);
+      else launch_group<double, false>(g, items, tiles, st);
+    } else {
+      if (dh) launch_group<float, true>(g, items, tiles, st);
+      else launch_group<float, false>(g, items, tiles, st);
+    }
+  }
+  WorkItem none;
+  std::memset(&none, 0, sizeof(none));
+  launch_finish(ctx, prec, dh, items, none, n_items, total, total, done, fix_off, (unsigned long long *)counters, st);
 }
 
 // ---------------------------------------------------------------- batch
@@ -100,10 +146,8 @@ struct mbh_batch {
   WorkItem *items = nullptr;
   WorkTile *tiles = nullptr;
   unsigned *counters = nullptr;
-  WalkerC *wc = nullptr;
-  unsigned *rc = nullptr;
-  int2 *list = nullptr;
-  size_t bytes[7] = {0, 0, 0, 0, 0, 0, 0};
+  std::vector<std::pair<void *, size_t>> allocs;
+  std::vector<TileGroup> groups;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -111,14 +155,16 @@ struct mbh_batch {
 static void batch_free(mbh_batch *b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
-  ctx_free(b->ctx, b->hdr, b->bytes[0]);
-  ctx_free(b->ctx, b->items, b->bytes[1]);
-  ctx_free(b->ctx, b->tiles, b->bytes[2]);
-  ctx_free(b->ctx, b->counters, b->bytes[3]);
-  ctx_free(b->ctx, b->wc, b->bytes[4]);
-  ctx_free(b->ctx, b->rc, b->bytes[5]);
-  ctx_free(b->ctx, b->list, b->bytes[6]);
+  for (auto &a : b->allocs) ctx_free(b->ctx, a.first, a.second);
   delete b;
+}
+
+template <typename T>
+static mbh_status batch_alloc(mbh_batch *b, T **p, size_t n) {
+  const size_t bytes = std::max<size_t>(1, n) * sizeof(T);
+  mbh_status s = ctx_alloc(b->ctx, (void **)p, bytes);
+  if (s == MBH_OK) b->allocs.emplace_back((void *)*p, bytes);
+  return s;
 }
 
 extern "C" mbh_status mbh_batch_create(mbh_ctx *ctx, int n, const mbh_ref *const *refs, const double *const *theta_dev,
@@ -129,12 +175,14 @@ extern "C" mbh_status mbh_batch_create(mbh_ctx *ctx, int n, const mbh_ref *const
   if (prec != MBH_FP64 && prec != MBH_MIXED) return mbh_fail(MBH_EINVAL, "bad precision");
   int64_t total = 0;
   bool dh = false;
+  int Kmax = 1;
   for (int i = 0; i < n; ++i) {
     if (!refs[i] || W[i] < 0 || (W[i] > 0 && (!theta_dev[i] || !lnL_dev[i])))
       return mbh_fail(MBH_EINVAL, "item %d: null reference or buffers", i);
     if (refs[i]->ctx != ctx) return mbh_fail(MBH_EINVAL, "item %d: reference of another context", i);
     total += W[i];
     if (dh_hh_dev && dh_hh_dev[i]) dh = true;
+    Kmax = std::max(Kmax, flat_slots(refs[i]->n_bins + 1));
   }
   HIP_TRY(hipSetDevice(ctx->device));
   mbh_batch *b = new mbh_batch();
@@ -145,56 +193,56 @@ extern "C" mbh_status mbh_batch_create(mbh_ctx *ctx, int n, const mbh_ref *const
     batch_free(b);
     return s;
   };
+  const bool mixed = prec == MBH_MIXED;
+  WalkerC *wc = nullptr;
+  double *part = nullptr;
+  int *rlist = nullptr;
+  unsigned *rcount = nullptr;
+  int64_t *fix_off = nullptr;
+  mbh_status s;
+  if ((s = batch_alloc(b, &wc, (size_t)total)) != MBH_OK || (s = batch_alloc(b, &part, (size_t)total * Kmax * 4)) != MBH_OK ||
+      (mixed && (s = batch_alloc(b, &rlist, (size_t)total)) != MBH_OK) ||
+      (mixed && (s = batch_alloc(b, &rcount, (size_t)n)) != MBH_OK) ||
+      (s = batch_alloc(b, &fix_off, (size_t)n + 1)) != MBH_OK || (s = batch_alloc(b, &b->counters, kCounterWords)) != MBH_OK)
+    return fail(s);
   std::vector<WorkItem> items(n);
   std::vector<WorkTile> tiles;
   std::vector<double> cost;
-  mbh_status s;
-  b->bytes[4] = (size_t)std::max<int64_t>(total, 1) * sizeof(WalkerC);
-  if ((s = ctx_alloc(ctx, (void **)&b->wc, b->bytes[4])) != MBH_OK) return fail(s);
   int64_t off = 0;
   for (int i = 0; i < n; ++i) {
     WorkItem &it = items[i];
-    it.ref = ref_view(refs[i]);
+    it = make_item(refs[i], item_lanes(ctx, refs[i], prec));
     it.theta = theta_dev[i];
-    it.wc = b->wc + off;
+    it.wc = wc + off;
     it.lnL = lnL_dev[i];
     it.dhhh = dh_hh_dev ? dh_hh_dev[i] : nullptr;
+    it.part = part + off * Kmax * 4;
+    it.rlist = mixed ? rlist + off : nullptr;
+    it.rcount = mixed ? rcount + i : nullptr;
     it.W = W[i];
     it.offset = off;
-    it.G = item_lanes(ctx, refs[i], prec);
-    it.model = refs[i]->model;
     append_tiles(tiles, cost, i, refs[i], it.G, W[i]);
     off += W[i];
   }
-  order_tiles(tiles, cost);
+  b->groups = order_tiles(tiles, cost);
   WorkHeader h{n, (int32_t)tiles.size(), total};
-  b->bytes[0] = sizeof(WorkHeader);
-  b->bytes[1] = n * sizeof(WorkItem);
-  b->bytes[2] = std::max<size_t>(1, tiles.size()) * sizeof(WorkTile);
-  b->bytes[3] = 2 * sizeof(unsigned);
-  b->bytes[5] = 4 * sizeof(unsigned);
-  b->bytes[6] = (size_t)std::max<int64_t>(total, 1) * sizeof(int2);
-  if ((s = ctx_alloc(ctx, (void **)&b->rc, b->bytes[5])) != MBH_OK) return fail(s);
-  if ((s = ctx_alloc(ctx, (void **)&b->list, b->bytes[6])) != MBH_OK) return fail(s);
-  if ((s = ctx_alloc(ctx, (void **)&b->hdr, b->bytes[0])) != MBH_OK) return fail(s);
-  if ((s = ctx_alloc(ctx, (void **)&b->items, b->bytes[1])) != MBH_OK) return fail(s);
-  if ((s = ctx_alloc(ctx, (void **)&b->tiles, b->bytes[2])) != MBH_OK) return fail(s);
-  if ((s = ctx_alloc(ctx, (void **)&b->counters, b->bytes[3])) != MBH_OK) return fail(s);
-  unsigned zero[4] = {0u, 0u, 0u, 0u};
-  if (hipMemcpy(b->rc, zero, 4 * sizeof(unsigned), hipMemcpyHostToDevice) != hipSuccess ||
+  if ((s = batch_alloc(b, &b->hdr, 1)) != MBH_OK || (s = batch_alloc(b, &b->items, (size_t)n)) != MBH_OK ||
+      (s = batch_alloc(b, &b->tiles, tiles.size())) != MBH_OK)
+    return fail(s);
+  std::vector<unsigned> zero(std::max(n, kCounterWords), 0u);
+  if ((mixed && hipMemcpy(rcount, zero.data(), n * sizeof(unsigned), hipMemcpyHostToDevice) != hipSuccess) ||
+      hipMemcpy(b->counters, zero.data(), kCounterWords * sizeof(unsigned), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(b->hdr, &h, sizeof(h), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(b->items, items.data(), b->bytes[1], hipMemcpyHostToDevice) != hipSuccess ||
-      (!tiles.empty() && hipMemcpy(b->tiles, tiles.data(), tiles.size() * sizeof(WorkTile), hipMemcpyHostToDevice) != hipSuccess) ||
-      hipMemcpy(b->counters, zero, 2 * sizeof(unsigned), hipMemcpyHostToDevice) != hipSuccess)
+      hipMemcpy(b->items, items.data(), n * sizeof(WorkItem), hipMemcpyHostToDevice) != hipSuccess ||
+      (!tiles.empty() && hipMemcpy(b->tiles, tiles.data(), tiles.size() * sizeof(WorkTile), hipMemcpyHostToDevice) != hipSuccess))
     return fail(mbh_fail(MBH_EDEVICE, "upload work list"));
-  // capture the setup + persistent launch once
-  const int nblk = std::max(1, std::min<int>(persistent_blocks(ctx, prec, dh), (int)tiles.size()));
+  // capture the whole pass once
   const int sblk = (int)std::max<int64_t>(1, std::min<int64_t>((total + 127) / 128, 4 * ctx->n_cu));
   hipStream_t cs;
   if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return fail(mbh_fail(MBH_EDEVICE, "stream"));
   hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    launch_work(ctx, prec, dh, nblk, sblk, total, b->hdr, b->items, b->tiles, b->counters, b->rc, b->list, cs);
+    launch_work(ctx, prec, dh, sblk, n, total, b->groups, b->hdr, b->items, b->tiles, b->counters, fix_off, cs);
     e = hipStreamEndCapture(cs, &b->graph);
   }
   if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
@@ -214,9 +262,9 @@ extern "C" mbh_status mbh_batch_launch(mbh_batch *b, hipStream_t st) {
 extern "C" mbh_status mbh_batch_routed(const mbh_batch *b, uint64_t *routed_out) {
   if (!b || !routed_out) return mbh_fail(MBH_EINVAL, "null argument");
   HIP_TRY(hipSetDevice(b->ctx->device));
-  unsigned v[4];
-  HIP_TRY(hipMemcpy(v, b->rc, sizeof(v), hipMemcpyDeviceToHost));
-  *routed_out = v[3];
+  unsigned long long v = 0;
+  HIP_TRY(hipMemcpy(&v, b->counters, sizeof(v), hipMemcpyDeviceToHost));
+  *routed_out = v;
   return MBH_OK;
 }
 
@@ -254,12 +302,16 @@ struct Slot {
   WorkHeader *hdr_d = nullptr;
   WorkItem *items_d = nullptr;
   WorkTile *tiles_d = nullptr;
-  unsigned *counters_d = nullptr;
-  unsigned *rc_d = nullptr;
-  int2 *list_d = nullptr;
+  unsigned *counters_d = nullptr;  // kCounterWords
+  unsigned *rcount_d = nullptr;    // [max_items]
+  int64_t *fix_off_d = nullptr;    // [max_items + 1]
+  int *rlist_d = nullptr;          // [cap]
+
+  double *part_d = nullptr;        // [cap][Kmax][4]
   WalkerC *wc_d = nullptr;
   std::vector<std::pair<std::shared_ptr<Request>, int64_t>> members;  // request, first walker in the slot
   int64_t walkers = 0;
+  std::vector<TileGroup> groups;
   bool busy = false;
 };
 }  // namespace
@@ -269,11 +321,10 @@ struct mbh_server {
   std::vector<const mbh_ref *> refs;
   mbh_server_config cfg{};
   int64_t cap_walkers = 0;  // per slot
-  int max_items = 0, max_tiles = 0;
+  int max_items = 0, max_tiles = 0, Kmax = 1;
   size_t bytes_per_walker = 0;
   std::vector<Slot> slots;
   std::vector<std::pair<void *, size_t>> dev_allocs;
-  int nblk = 1;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<std::shared_ptr<Request>> queue;
@@ -306,25 +357,26 @@ static void server_free(mbh_server *s) {
 static bool server_pack(mbh_server *s, Slot &sl) {
   sl.members.clear();
   sl.walkers = 0;
-  int n_items = 0, n_tiles = 0;
+  int n_items = 0;
+  int64_t n_tiles = 0;
+  const bool mixed = s->cfg.prec == MBH_MIXED;
   std::vector<WorkTile> tiles;
   std::vector<double> cost;
   while (!s->queue.empty()) {
     auto &r = s->queue.front();
     const mbh_ref *ref = s->refs[r->ref];
-    int G = item_lanes(s->ctx, ref, s->cfg.prec);
-    int nt = (int)((r->W + kBlock / G - 1) / (kBlock / G));
+    const int G = item_lanes(s->ctx, ref, s->cfg.prec);
+    const int64_t nt = tiles_of(G, r->W, ref->n_bins + 1);
     if (sl.walkers + r->W > s->cap_walkers || n_items + 1 > s->max_items || n_tiles + nt > s->max_tiles) break;
     WorkItem &it = sl.items_h[n_items];
-    it.ref = ref_view(ref);
+    it = make_item(ref, G);
     it.theta = sl.theta_d + sl.walkers * 11;
     it.wc = sl.wc_d + sl.walkers;
-    it.lnL = sl.res_d + sl.walkers * 3;
-    it.dhhh = nullptr;
+    it.part = sl.part_d + sl.walkers * s->Kmax * 4;
+    it.rlist = mixed ? sl.rlist_d + sl.walkers : nullptr;
+    it.rcount = mixed ? sl.rcount_d + n_items : nullptr;
     it.W = r->W;
     it.offset = sl.walkers;
-    it.G = G;
-    it.model = ref->model;
     std::memcpy(sl.theta_h + sl.walkers * 11, r->theta.data(), r->W * 11 * sizeof(double));
     append_tiles(tiles, cost, n_items, ref, G, r->W);
     n_tiles += nt;
@@ -340,7 +392,7 @@ static bool server_pack(mbh_server *s, Slot &sl) {
     it.lnL = sl.res_d + it.offset;
     it.dhhh = sl.res_d + sl.walkers + 2 * it.offset;
   }
-  order_tiles(tiles, cost);
+  sl.groups = order_tiles(tiles, cost);
   std::memcpy(sl.tiles_h, tiles.data(), tiles.size() * sizeof(WorkTile));
   *sl.hdr_h = WorkHeader{n_items, (int32_t)tiles.size(), sl.walkers};
   return true;
@@ -354,10 +406,9 @@ static bool server_launch(mbh_server *s, Slot &sl) {
             hipMemcpyAsync(sl.tiles_d, sl.tiles_h, h.n_tiles * sizeof(WorkTile), hipMemcpyHostToDevice, st) == hipSuccess &&
             hipMemcpyAsync(sl.hdr_d, sl.hdr_h, sizeof(WorkHeader), hipMemcpyHostToDevice, st) == hipSuccess;
   if (!ok) return false;
-  const int nblk = std::max(1, std::min(s->nblk, h.n_tiles));
   const int sblk = (int)std::max<int64_t>(1, std::min<int64_t>((sl.walkers + 127) / 128, 4 * s->ctx->n_cu));
-  launch_work(s->ctx, s->cfg.prec, true, nblk, sblk, sl.walkers, sl.hdr_d, sl.items_d, sl.tiles_d, sl.counters_d,
-              sl.rc_d, sl.list_d, st);
+  launch_work(s->ctx, s->cfg.prec, true, sblk, h.n_items, sl.walkers, sl.groups, sl.hdr_d, sl.items_d, sl.tiles_d,
+              sl.counters_d, sl.fix_off_d, st);
   ok = hipGetLastError() == hipSuccess &&
        hipMemcpyAsync(sl.res_h, sl.res_d, sl.walkers * 3 * sizeof(double), hipMemcpyDeviceToHost, st) == hipSuccess &&
        hipEventRecord(sl.ev, st) == hipSuccess;
@@ -445,7 +496,12 @@ extern "C" mbh_status mbh_server_create(mbh_ctx *ctx, int n_refs, const mbh_ref 
   s->ctx = ctx;
   s->refs.assign(refs, refs + n_refs);
   s->cfg = *cfg;
-  s->bytes_per_walker = 11 * sizeof(double) + 3 * sizeof(double) + sizeof(WalkerC);
+  for (int i = 0; i < n_refs; ++i) {
+    s->Kmax = std::max(s->Kmax, flat_slots(refs[i]->n_bins + 1));
+  }
+  // inputs, outputs, walker constants and the per-walker partial sums
+  s->bytes_per_walker = 11 * sizeof(double) + 3 * sizeof(double) + sizeof(WalkerC) +
+                        4 * sizeof(double) * s->Kmax + sizeof(int);
   int64_t cap = cfg->max_batch_walkers;
   if (cfg->hbm_budget_bytes) {
     int64_t by_budget = (int64_t)(cfg->hbm_budget_bytes / (cfg->max_inflight * s->bytes_per_walker));
@@ -457,8 +513,14 @@ extern "C" mbh_status mbh_server_create(mbh_ctx *ctx, int n_refs, const mbh_ref 
   }
   s->cap_walkers = cap;
   s->max_items = (int)std::min<int64_t>(cap, 4096);
-  s->max_tiles = (int)(cap + s->max_items);
-  s->nblk = persistent_blocks(ctx, cfg->prec, true);
+  {
+    // tiles of a full slot: flattened chunks (E / (63 kWaves) per walker) or
+    // lane groups (at most one walker per lane), plus one partial tile per item
+    int Emax = 2;
+    for (int i = 0; i < n_refs; ++i) Emax = std::max(Emax, refs[i]->n_bins + 1);
+    const int64_t per_walker_x = std::max<int64_t>(kBlock, (Emax + kChunk * kWaves - 1) / (kChunk * kWaves) * kBlock);
+    s->max_tiles = (int)std::min<int64_t>(cap * per_walker_x / kBlock + 2 * s->max_items, INT32_MAX / 2);
+  }
   s->slots.resize(cfg->max_inflight);
   auto dalloc = [&](void **p, size_t bytes) {
     mbh_status st = ctx_alloc(ctx, p, bytes);
@@ -482,16 +544,19 @@ extern "C" mbh_status mbh_server_create(mbh_ctx *ctx, int n_refs, const mbh_ref 
         (st = dalloc((void **)&sl.hdr_d, sizeof(WorkHeader))) != MBH_OK ||
         (st = dalloc((void **)&sl.items_d, s->max_items * sizeof(WorkItem))) != MBH_OK ||
         (st = dalloc((void **)&sl.tiles_d, s->max_tiles * sizeof(WorkTile))) != MBH_OK ||
-        (st = dalloc((void **)&sl.counters_d, 2 * sizeof(unsigned))) != MBH_OK ||
-        (st = dalloc((void **)&sl.rc_d, 4 * sizeof(unsigned))) != MBH_OK ||
-        (st = dalloc((void **)&sl.list_d, cap * sizeof(int2))) != MBH_OK ||
+        (st = dalloc((void **)&sl.counters_d, kCounterWords * sizeof(unsigned))) != MBH_OK ||
+        (st = dalloc((void **)&sl.rcount_d, s->max_items * sizeof(unsigned))) != MBH_OK ||
+        (st = dalloc((void **)&sl.fix_off_d, (s->max_items + 1) * sizeof(int64_t))) != MBH_OK ||
+        (st = dalloc((void **)&sl.rlist_d, cap * sizeof(int))) != MBH_OK ||
+
+        (st = dalloc((void **)&sl.part_d, cap * s->Kmax * 4 * sizeof(double))) != MBH_OK ||
+
         (st = dalloc((void **)&sl.wc_d, cap * sizeof(WalkerC))) != MBH_OK) {
       server_free(s);
       return st;
     }
-    unsigned zero[4] = {0u, 0u, 0u, 0u};
-    if (hipMemcpy(sl.counters_d, zero, 2 * sizeof(unsigned), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(sl.rc_d, zero, 4 * sizeof(unsigned), hipMemcpyHostToDevice) != hipSuccess) {
+    std::vector<unsigned> zero(kCounterWords, 0u);
+    if (hipMemcpy(sl.counters_d, zero.data(), kCounterWords * sizeof(unsigned), hipMemcpyHostToDevice) != hipSuccess) {
       server_free(s);
       return mbh_fail(MBH_EDEVICE, "counter init");
     }

@@ -77,7 +77,7 @@ _SIGS = {
     "mbh_batch_launch": [_vp, _vp],
     "mbh_batch_routed": [_vp, ct.POINTER(ct.c_uint64)],
     "mbh_batch_release": [_vp],
-    "mbh_autotune_heterodyned": [_vp, _vp, _i64, _i32, ct.POINTER(ct.c_int)],
+    "mbh_autotune_heterodyned": [_vp, _vp, _vp, _i64, _i32, ct.POINTER(ct.c_int)],
     "mbh_lanes_for": [_vp, _i32, _i32, _i32, ct.POINTER(ct.c_int)],
     "mbh_set_lanes": [_vp, _i32, _i32, _i32, _i32],
     "mbh_autotune_save": [_vp, ct.c_char_p],
@@ -272,9 +272,17 @@ def set_lanes(ctx: Context, n_bins: int, n_modes: int, prec: int, lanes: int):
     _check(_L.mbh_set_lanes(ctx.h, n_bins, n_modes, prec, lanes), "mbh_set_lanes")
 
 
-def autotune_heterodyned(ctx: Context, ref: Reference, W: int, prec: int) -> int:
+def autotune_heterodyned(ctx: Context, ref: Reference, walkers, prec: int) -> int:
+    """Time every mapping on ``walkers`` (a [W, 11] float64 CUDA tensor of
+    representative walkers) or, if ``walkers`` is an int W, on W copies of a
+    fixed parameter point; records and returns the fastest (0 = flattened)."""
     v = ct.c_int()
-    _check(_L.mbh_autotune_heterodyned(ctx.h, ref.h, W, prec, ct.byref(v)), "mbh_autotune_heterodyned")
+    if isinstance(walkers, int):
+        ptr, W = None, walkers
+    else:
+        W = walkers.shape[0]
+        ptr = _dev_ptr(walkers, torch.float64, (W, NPARAM))
+    _check(_L.mbh_autotune_heterodyned(ctx.h, ref.h, ptr, W, prec, ct.byref(v)), "mbh_autotune_heterodyned")
     return v.value
 
 
