@@ -37,12 +37,27 @@ METRIC = "heterodyned lnL evals/s (mixed vs FP64, |ΔlnL|≤1e-3); p50/p99 reque
 PEAK_ALU_TFLOPS = 78.6   # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, unpacked FP32 and FP64 alike
 PEAK_HBM_GBS = 8000.0
 N_SOURCES, TEMPS, PER_TEMP, N_BINS = 8, tuple(2.0 ** k for k in range(8)), 64, 128
-# algorithmic flop count per (walker, edge) of the heterodyned step with one
-# mode and three channels, and per (walker, frequency) of the full grid; the
-# itemisation is in the design notes (transcendentals count 1, FMA 2)
-FLOPS_PER_EDGE = 711.0
-FLOPS_PER_BIN = 81.0
-FLOPS_PER_FULL_POINT = 720.0
+# Floating-point work of one (walker, bin edge) of the heterodyned main pass
+# with the (2,2) mode and three channels, its bin included (FMA = 2 flops,
+# other arithmetic and transcendental instructions 1), as counted by the VALU
+# FLOP counters (SQ_INSTS_VALU_FLOPS_FP64, _FP32, _FP64_TRANS, _FP32_TRANS,
+# x 64 lanes) over a divergence-free launch of 4096 walkers x 129 edges: the
+# same 905 in both precisions (the mixed path moves ~16 % of it to FP32).
+FLOPS_PER_EDGE = 905.0
+# HBM traffic of the dominant kernel (bytes per launch) from the FETCH_SIZE and
+# WRITE_SIZE counters, scaled by the same counters' reading for a plain copy
+# of known size; valid only for the kernel sources it was measured on.
+TRAFFIC = {"src_sha256": None, "bytes_per_launch": None}
+
+
+def kernel_sources_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2111_01064_amd", "csrc")
+    for fn in sorted(os.listdir(d)):
+        with open(os.path.join(d, fn), "rb") as f:
+            h.update(fn.encode() + b"\0" + f.read())
+    return h.hexdigest()
 
 
 def log(*a):
@@ -115,6 +130,38 @@ def time_batch(M, ctx, batch, steps, warmup, stream):
     wall = time.perf_counter() - t0
     per = [a.elapsed_time(b) * 1e-3 for a, b in ev]
     return wall, float(np.mean(per)), per
+
+
+def time_stage(batch, stage, steps, stream):
+    """Mean duration of one stage of the batch (a graph of its own): `steps`
+    launches queued back to back between two events on the launch stream, so
+    that the host-side launch latency overlaps the device work; the stage's
+    inputs come from a preceding full launch."""
+    import torch
+
+    batch.launch(stream)
+    for _ in range(3):
+        batch.launch_stage(stage, stream)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        a.record(stream)
+        for _ in range(steps):
+            batch.launch_stage(stage, stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) * 1e-3 / steps
+
+
+def copy_calibration():
+    """A plain device copy of 64 MiB (read 64 MiB, write 64 MiB), run so that
+    HBM byte counters can be scaled against a kernel of known traffic."""
+    import torch
+
+    src = torch.ones(8 << 20, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
 
 
 def cpu_baseline(budget_s: float = 15.0):
@@ -194,6 +241,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--quick", action="store_true", help="skip the side measurements")
+    ap.add_argument("--mapping", type=int, default=None,
+                    help="fix the heterodyned mapping (0 = flattened, or lanes per walker) instead of autotuning; "
+                         "for profiler runs, whose timings would mislead the autotuner")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: every walker batch fits one MI355X and this build has no "
@@ -216,23 +266,32 @@ def main():
     res = {}
     for name, prec in (("fp64", M.FP64), ("mixed", M.MIXED)):
         # autotune the mapping for this shape once, on the step's own walkers
-        M.autotune_heterodyned(ctx, S.items[0]["ref"], torch.cat(thetas), prec)
+        if args.mapping is None:
+            M.autotune_heterodyned(ctx, S.items[0]["ref"], torch.cat(thetas), prec)
+        else:
+            M.set_lanes(ctx, N_BINS, 1, prec, args.mapping)
         lnls = [torch.empty(len(w), dtype=torch.float64, device="cuda") for w in walkers]
         batch = M.Batch(ctx, [it["ref"] for it in S.items], thetas, lnls, prec=prec)
         wall, mean_s, per = time_batch(M, ctx, batch, args.steps, args.warmup, stream)
         routed = batch.routed() / (args.steps + args.warmup)
         res[name] = dict(wall=wall, kernel_s=mean_s, lnl=np.concatenate([l.cpu().numpy() for l in lnls]),
                          lanes=M.lanes_for(ctx, N_BINS, 1, prec), routed=routed)
+        stages = [time_stage(batch, st, max(20, args.steps // 4), stream)
+                  for st in (M.STAGE_SETUP, M.STAGE_MAIN, M.STAGE_FINISH)]
+        res[name]["stages_s"] = stages
         batch.close()
         log(f"[bench] {name}: {W_total} walkers/step, {mean_s * 1e6:.1f} us/step (events), wall {wall:.3f} s, "
-            f"lanes {res[name]['lanes']}, FP64-recomputed walkers/step {routed:.1f}")
+            f"lanes {res[name]['lanes']}, FP64-recomputed walkers/step {routed:.1f}, stages (us) "
+            + " / ".join(f"{x * 1e6:.1f}" for x in stages))
     dmix = float(np.max(np.abs(res["mixed"]["lnl"] - res["fp64"]["lnl"])))
     ms_per_step = res["mixed"]["wall"] / args.steps * 1e3
     value = W_total * args.steps / res["mixed"]["wall"]
     fp64_value = W_total * args.steps / res["fp64"]["wall"]
     E = N_BINS + 1
-    flops = W_total * (E * FLOPS_PER_EDGE + N_BINS * FLOPS_PER_BIN)
-    achieved = flops / res["mixed"]["kernel_s"] / 1e12
+    flops = W_total * E * FLOPS_PER_EDGE
+    t_main = res["mixed"]["stages_s"][1]
+    achieved = flops / t_main / 1e12
+    traffic = TRAFFIC["bytes_per_launch"] if TRAFFIC["src_sha256"] == kernel_sources_hash() else None
     out = {
         "metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
@@ -244,11 +303,15 @@ def main():
         "mixed_speedup_vs_fp64": value / fp64_value, "max_abs_dlnL_mixed_vs_fp64": dmix,
         "mixed_fp64_recomputed_fraction": res["mixed"]["routed"] / W_total,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_ALU_TFLOPS, "traffic": None,
-                     "kernel": "k_het_work<float>", "kernel_us": res["mixed"]["kernel_s"] * 1e6,
+                     "frac": achieved / PEAK_ALU_TFLOPS, "traffic": traffic,
+                     "kernel": "k_het_tiles<float> (main pass, mixed)", "kernel_us": t_main * 1e6,
                      "flops_per_launch": flops},
+        "stages_us": {k: {"setup": v["stages_s"][0] * 1e6, "main": v["stages_s"][1] * 1e6,
+                          "finish": v["stages_s"][2] * 1e6, "graph": v["kernel_s"] * 1e6} for k, v in res.items()},
+        "fp64_roofline_frac": flops / res["fp64"]["stages_s"][1] / 1e12 / PEAK_ALU_TFLOPS,
         "paper_context": {"het_evals_per_s": 2e5, "note": "~5 us per heterodyned lnL, unnamed GPU, PhenomD"},
     }
+    copy_calibration()
     if not args.quick:
         out.update(side_measurements(M, ctx, S, walkers, grid))
     if not args.no_cpu:
@@ -288,17 +351,26 @@ def side_measurements(M, ctx, S, walkers, grid):
     th4 = []
     for item, (_, _, W) in zip(S4.items, shapes):
         th4.append(torch.as_tensor(S4.walkers(item, (1, 4, 16, 64), (W + 3) // 4)[:W], device="cuda"))
-    for it4, t4 in zip(S4.items, th4):
-        M.autotune_heterodyned(ctx, it4["ref"], t4, M.MIXED)
-    ln4 = [torch.empty(len(t), dtype=torch.float64, device="cuda") for t in th4]
-    b4 = M.Batch(ctx, [x["ref"] for x in S4.items], th4, ln4, prec=M.MIXED)
-    st = torch.cuda.Stream()
-    wall, mean_s, _ = time_batch(M, ctx, b4, 50, 5, st)
     W4 = sum(len(t) for t in th4)
-    out["hm_batch"] = {"sources": 16, "walkers": W4, "evals_per_s": W4 * 50 / wall, "us_per_launch": mean_s * 1e6,
-                       "shapes": [[int(m), int(nb), int(w)] for (m, nb, w) in shapes]}
-    b4.close()
-    log(f"[bench] HM batch: {W4} walkers, {W4 * 50 / wall:.3g} evals/s")
+    hm = {"sources": 16, "walkers": W4, "shapes": [[int(m), int(nb), int(w)] for (m, nb, w) in shapes]}
+    st = torch.cuda.Stream()
+    lnl4 = {}
+    for name, prec in (("fp64", M.FP64), ("mixed", M.MIXED)):
+        for it4, t4 in zip(S4.items, th4):
+            M.autotune_heterodyned(ctx, it4["ref"], t4, prec)
+        ln4 = [torch.empty(len(t), dtype=torch.float64, device="cuda") for t in th4]
+        b4 = M.Batch(ctx, [x["ref"] for x in S4.items], th4, ln4, prec=prec)
+        wall, mean_s, _ = time_batch(M, ctx, b4, 50, 5, st)
+        hm[f"{name}_evals_per_s"] = W4 * 50 / wall
+        hm[f"{name}_us_per_launch"] = mean_s * 1e6
+        hm[f"{name}_routed_per_launch"] = b4.routed() / 55
+        lnl4[name] = np.concatenate([l.cpu().numpy() for l in ln4])
+        b4.close()
+        log(f"[bench] HM batch {name}: {W4} walkers, {W4 * 50 / wall:.3g} evals/s")
+    hm["mixed_speedup_vs_fp64"] = hm["mixed_evals_per_s"] / hm["fp64_evals_per_s"]
+    ok = np.isfinite(lnl4["fp64"])
+    hm["max_abs_dlnL_mixed_vs_fp64"] = float(np.max(np.abs(lnl4["mixed"][ok] - lnl4["fp64"][ok])))
+    out["hm_batch"] = hm
     # serving: Poisson stream over 4 resident sources at a fraction of capacity
     refs = [x["ref"] for x in S.items[:4]]
     pools = walkers[:4]

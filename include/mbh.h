@@ -186,6 +186,14 @@ mbh_status mbh_batch_create(mbh_ctx *ctx, int n, const mbh_ref *const *refs,
                             double *const *lnL_dev, double *const *dh_hh_dev,
                             mbh_precision prec, mbh_batch **out);
 mbh_status mbh_batch_launch(mbh_batch *batch, hipStream_t stream);
+/* One stage of the same work as a graph of its own, for measuring stages
+ * separately: MBH_STAGE_SETUP (walker constants, a1), MBH_STAGE_MAIN (the
+ * heterodyned main pass, a2-a7: the dominant kernel), MBH_STAGE_FINISH
+ * (per-walker totals and, on the mixed path, the FP64 recomputation).
+ * Launching the three in this order on one stream is mbh_batch_launch.
+ * Errors: MBH_EINVAL, MBH_EDEVICE. */
+enum { MBH_STAGE_SETUP = 1, MBH_STAGE_MAIN = 2, MBH_STAGE_FINISH = 3 };
+mbh_status mbh_batch_launch_stage(mbh_batch *batch, int stage, hipStream_t stream);
 /* Walkers of this batch that the mixed path recomputed in FP64 (see
  * mbh_loglike_heterodyned), summed over all launches so far.  Synchronous. */
 mbh_status mbh_batch_routed(const mbh_batch *batch, uint64_t *routed_out);

@@ -152,116 +152,11 @@ __device__ inline void ylm_pair(int mi, double c, double s, double ch, double sh
   }
 }
 
-__device__ inline bool imr_domain_ok(const double *th) {
+__device__ __forceinline__ bool imr_domain_ok(const double *th) {
   for (int i = 0; i < 11; ++i)
     if (!isfinite(th[i])) return false;
   return th[0] > 0.0 && th[1] >= 0.05 && th[1] <= 1.0 && fabs(th[2]) <= 0.99 &&
          fabs(th[3]) <= 0.99 && th[4] > 0.0;
-}
-
-// raw (unaligned) (2,2) phase and its slope at frequency f
-__device__ inline void raw_phase64(const WalkerC &w, double f, double &ph, double &dph) {
-  if (f <= w.f1) {
-    double v = cbrt(w.piM * f);
-    double iv = 1.0 / v, iv2 = iv * iv, iv3 = iv2 * iv, iv5 = iv3 * iv2;
-    ph = w.c5 * iv5 + w.c3 * iv3 + w.c2 * iv2;
-    dph = (w.d5 * iv5 + w.d3 * iv3 + w.d2 * iv2) / f;
-  } else {
-    double x = f - w.f1, y = f - w.fRD;
-    double L = w.fD / (y * y + w.fD * w.fD);
-    ph = w.P1 + w.dP1 * x + kKappa * (atan(y / w.fD) - w.at1 - w.L1 * x);
-    dph = w.dP1 + kKappa * (L - w.L1);
-  }
-}
-
-__device__ inline void walker_setup(const double *__restrict__ th, int model, uint32_t modes, WalkerC &w) {
-  w.model = model;
-  w.pad0 = w.pad1 = 0;
-  if (model == 1) {  // chirp
-    bool ok = isfinite(th[0]) && isfinite(th[1]) && isfinite(th[2]) && isfinite(th[3]) && th[0] > 0.0;
-    w.valid = ok ? 1 : 0;
-    w.piMc = kPi * th[0] * kMsunS;
-    w.amp = th[1] * kAmpScale;
-    w.tc = th[2];
-    w.phic = th[3];
-    return;
-  }
-  w.valid = imr_domain_ok(th) ? 1 : 0;
-  if (!w.valid) return;
-  double M = th[0] * kMsunS, q = th[1];
-  double m1 = 1.0 / (1.0 + q), m2 = q * m1;
-  double eta = m1 * m2, delta = m1 - m2;
-  double DL = th[4] * (kGpcM / kClight);
-  double psi2 = 3715.0 / 756.0 + 55.0 / 9.0 * eta;
-  double beta_so = ((113.0 * m1 * m1 + 75.0 * eta) * th[2] + (113.0 * m2 * m2 + 75.0 * eta) * th[3]) / 12.0;
-  double psi3 = -16.0 * kPi + 4.0 * beta_so;
-  double i128 = 1.0 / (128.0 * eta);
-  w.piM = kPi * M;
-  w.c5 = -3.0 * i128;
-  w.c3 = w.c5 * psi2;
-  w.c2 = w.c5 * psi3;
-  w.d5 = 5.0 * i128;
-  w.d3 = 3.0 * psi2 * i128;
-  w.d2 = 2.0 * psi3 * i128;
-  w.f1 = 0.018 / M;
-  double Mf = M * (1.0 - 0.19 * eta);
-  w.fRD = 0.0595 / Mf;
-  w.fD = 0.0142 / Mf;
-  w.fcut = 0.2 / M;
-  w.fmax = -2.0 * w.fRD + sqrt(9.0 * w.fRD * w.fRD + 5.0 * w.fD * w.fD);
-  {
-    double v = cbrt(w.piM * w.f1);
-    double iv = 1.0 / v, iv2 = iv * iv, iv3 = iv2 * iv, iv5 = iv3 * iv2;
-    w.P1 = w.c5 * iv5 + w.c3 * iv3 + w.c2 * iv2;
-    w.dP1 = (w.d5 * iv5 + w.d3 * iv3 + w.d2 * iv2) / w.f1;
-  }
-  w.lam_num = sq(w.f1 - w.fRD) + w.fD * w.fD;
-  w.inv_fD = 1.0 / w.fD;
-  w.L1 = w.fD / w.lam_num;
-  w.at1 = atan((w.f1 - w.fRD) / w.fD);
-  raw_phase64(w, w.fmax, w.ph_max, w.dph_max);
-  w.AN = kPi * sqrt(2.0 * eta / 3.0) * M * M / DL * kAmpScale;
-  w.tref = th[10];
-  double a = 1.0 - 3.0 * eta;
-  w.rel[0] = 1.0;
-  w.rel[1] = 0.75 * sqrt(15.0 / 14.0) * delta;
-  w.rel[2] = (4.0 / 9.0) * sqrt(10.0 / 7.0) * a;
-  w.rel[3] = delta / 3.0;
-  w.rel[4] = sqrt(5.0 / 7.0) / 3.0 * a;
-  w.rel[5] = 9.0 / (4.0 * sqrt(70.0)) * delta * (1.0 - 2.0 * eta);
-  double lam = th[7], bet = th[8], psi = th[9];
-  double cl = cos(lam), sl = sin(lam), cb = cos(bet), sb = sin(bet), cp = cos(psi), sp = sin(psi);
-  w.kx = -cb * cl;
-  w.ky = -cb * sl;
-  w.kz = -sb;
-  // u = (sin l, -cos l, 0), v = (-sin b cos l, -sin b sin l, cos b)
-  w.px = cp * sl - sp * sb * cl;
-  w.py = -cp * cl - sp * sb * sl;
-  w.pz = sp * cb;
-  w.qx = -sp * sl - cp * sb * cl;
-  w.qy = sp * cl - cp * sb * sl;
-  w.qz = cp * cb;
-  // polarisation weights of the active modes only; e^{i m phi_ref} as powers of e^{i phi_ref}
-  double ci, si, chi, shi, s1, c1;
-  sincos(th[6], &si, &ci);
-  sincos(0.5 * th[6], &shi, &chi);
-  sincos(th[5], &s1, &c1);
-  for (int mi = 0; mi < kNumModes; ++mi) {
-    if (!(modes & (1u << mi))) continue;
-    double yp, ym;
-    int ls;
-    ylm_pair(mi, ci, si, chi, shi, yp, ym, ls);
-    double cm = c1, sm = s1;
-    for (int k = 1; k < kModeM[mi]; ++k) {
-      double t = cm * c1 - sm * s1;
-      sm = sm * c1 + cm * s1;
-      cm = t;
-    }
-    w.kp[mi] = 0.5 * (yp + ls * ym);
-    w.kc[mi] = 0.5 * (yp - ls * ym);
-    w.eph[mi][0] = cm;
-    w.eph[mi][1] = sm;
-  }
 }
 
 // ---- precision-specific primitives ---------------------------------------
@@ -361,6 +256,123 @@ struct Prec<float> {
   static __device__ __forceinline__ void sincos_r(float x, float &s, float &c) { sincos_red<float>(x, s, c); }
   static __device__ __forceinline__ float sqrt_r(float x) { return sqrtf(x); }
 };
+
+// FP64 quotient x / y through the refined reciprocal (within 1 ulp; the
+// per-walker constants below need no correctly rounded division)
+__device__ __forceinline__ double div64(double x, double y) { return x * rcp64_nr(y); }
+
+// sin and cos of an unbounded parameter angle: reduced to [-pi, pi] first
+__device__ __forceinline__ void sincos_param(double x, double &s, double &c) {
+  sincos_red<double>(reduce_2pi(x), s, c);
+}
+
+// raw (unaligned) (2,2) phase and its slope at frequency f > f1 (merger-
+// ringdown continuation; the setup evaluates it at f_max)
+__device__ __forceinline__ void raw_phase_mr(const WalkerC &w, double f, double &ph, double &dph) {
+  const double x = f - w.f1, y = f - w.fRD;
+  const double L = div64(w.fD, y * y + w.fD * w.fD);
+  ph = w.P1 + w.dP1 * x + kKappa * (atan(y * w.inv_fD) - w.at1 - w.L1 * x);
+  dph = w.dP1 + kKappa * (L - w.L1);
+}
+
+// (pi M f1)^(1/3) with f1 = 0.018 / M: a constant of the model
+constexpr double kV1 = 0.38383165853550260132496406524933909994849537353683;
+
+__device__ __forceinline__ void walker_setup(const double *__restrict__ th, int model, uint32_t modes, WalkerC &w) {
+  w.model = model;
+  w.pad0 = w.pad1 = 0;
+  if (model == 1) {  // chirp
+    bool ok = isfinite(th[0]) && isfinite(th[1]) && isfinite(th[2]) && isfinite(th[3]) && th[0] > 0.0;
+    w.valid = ok ? 1 : 0;
+    w.piMc = kPi * th[0] * kMsunS;
+    w.amp = th[1] * kAmpScale;
+    w.tc = th[2];
+    w.phic = th[3];
+    return;
+  }
+  double t[11];
+#pragma unroll
+  for (int i = 0; i < 11; ++i) t[i] = th[i];
+  w.valid = imr_domain_ok(t) ? 1 : 0;
+  if (!w.valid) return;
+  const double M = t[0] * kMsunS, q = t[1];
+  const double m1 = rcp64_nr(1.0 + q), m2 = q * m1;
+  const double eta = m1 * m2, delta = m1 - m2;
+  const double DL = t[4] * (kGpcM / kClight);
+  const double psi2 = 3715.0 / 756.0 + 55.0 / 9.0 * eta;
+  const double beta_so = ((113.0 * m1 * m1 + 75.0 * eta) * t[2] + (113.0 * m2 * m2 + 75.0 * eta) * t[3]) * (1.0 / 12.0);
+  const double psi3 = -16.0 * kPi + 4.0 * beta_so;
+  const double i128 = rcp64_nr(128.0 * eta);
+  const double iM = 1.0 / M;  // IEEE division: M may lie far outside the FP32 range
+  w.piM = kPi * M;
+  w.c5 = -3.0 * i128;
+  w.c3 = w.c5 * psi2;
+  w.c2 = w.c5 * psi3;
+  w.d5 = 5.0 * i128;
+  w.d3 = 3.0 * psi2 * i128;
+  w.d2 = 2.0 * psi3 * i128;
+  w.f1 = 0.018 * iM;
+  const double iMf = iM * rcp64_nr(1.0 - 0.19 * eta);
+  w.fRD = 0.0595 * iMf;
+  w.fD = 0.0142 * iMf;
+  w.fcut = 0.2 * iM;
+  w.fmax = -2.0 * w.fRD + sqrt(9.0 * w.fRD * w.fRD + 5.0 * w.fD * w.fD);
+  {
+    const double iv = 1.0 / kV1, iv2 = iv * iv, iv3 = iv2 * iv, iv5 = iv3 * iv2;
+    w.P1 = w.c5 * iv5 + w.c3 * iv3 + w.c2 * iv2;
+    w.dP1 = (w.d5 * iv5 + w.d3 * iv3 + w.d2 * iv2) * rcp64_nr(w.f1);
+  }
+  w.lam_num = sq(w.f1 - w.fRD) + w.fD * w.fD;
+  w.inv_fD = rcp64_nr(w.fD);
+  w.L1 = div64(w.fD, w.lam_num);
+  w.at1 = atan((w.f1 - w.fRD) * w.inv_fD);
+  // f_max lies past f1 (the (2,2) amplitude peaks in the merger-ringdown part)
+  raw_phase_mr(w, w.fmax, w.ph_max, w.dph_max);
+  w.AN = kPi * sqrt(2.0 * eta / 3.0) * M * M / DL * kAmpScale;
+  w.tref = t[10];
+  const double a = 1.0 - 3.0 * eta;
+  w.rel[0] = 1.0;
+  w.rel[1] = 0.75 * sqrt(15.0 / 14.0) * delta;
+  w.rel[2] = (4.0 / 9.0) * sqrt(10.0 / 7.0) * a;
+  w.rel[3] = delta * (1.0 / 3.0);
+  w.rel[4] = sqrt(5.0 / 7.0) / 3.0 * a;
+  w.rel[5] = 9.0 / (4.0 * sqrt(70.0)) * delta * (1.0 - 2.0 * eta);
+  double cl, sl, cb, sb, cp, sp;
+  sincos_param(t[7], sl, cl);
+  sincos_param(t[8], sb, cb);
+  sincos_param(t[9], sp, cp);
+  w.kx = -cb * cl;
+  w.ky = -cb * sl;
+  w.kz = -sb;
+  // u = (sin l, -cos l, 0), v = (-sin b cos l, -sin b sin l, cos b)
+  w.px = cp * sl - sp * sb * cl;
+  w.py = -cp * cl - sp * sb * sl;
+  w.pz = sp * cb;
+  w.qx = -sp * sl - cp * sb * cl;
+  w.qy = sp * cl - cp * sb * sl;
+  w.qz = cp * cb;
+  // polarisation weights of the active modes only; e^{i m phi_ref} as powers of e^{i phi_ref}
+  double ci, si, chi, shi, s1, c1;
+  sincos_param(t[6], si, ci);
+  sincos_param(0.5 * t[6], shi, chi);
+  sincos_param(t[5], s1, c1);
+  for (int mi = 0; mi < kNumModes; ++mi) {
+    if (!(modes & (1u << mi))) continue;
+    double yp, ym;
+    int ls;
+    ylm_pair(mi, ci, si, chi, shi, yp, ym, ls);
+    double cm = c1, sm = s1;
+    for (int k = 1; k < kModeM[mi]; ++k) {
+      double tt = cm * c1 - sm * s1;
+      sm = sm * c1 + cm * s1;
+      cm = tt;
+    }
+    w.kp[mi] = 0.5 * (yp + ls * ym);
+    w.kc[mi] = 0.5 * (yp - ls * ym);
+    w.eph[mi][0] = cm;
+    w.eph[mi][1] = sm;
+  }
+}
 
 // (2,2) phase aligned at f_max, its slope, and the amplitude at (2,2)
 // frequency fp; amplitude scaled by v^vpow (v = (pi M fp)^(1/3)).  All FP64:

@@ -496,7 +496,8 @@ __device__ __forceinline__ void fix_plan(const WorkItem *__restrict__ items, con
   __syncthreads();
   if (threadIdx.x == 0) {
     int64_t acc = 0;
-    for (int k = 0; k < kBlock; ++k) {
+    const int n_used = min(kBlock, (n_items + per - 1) / per);
+    for (int k = 0; k < n_used; ++k) {
       const int64_t x = sh_c[k];
       sh_c[k] = acc;
       acc += x;
@@ -578,28 +579,79 @@ static __global__ __launch_bounds__(kBlock) void k_het_final(const WorkItem *__r
   }
 }
 
-// FP64 recomputation of the queued walkers, one wavefront per walker (the
-// 64-lane group mapping, so that the walker's sums never leave the
-// wavefront); the grid covers the largest possible queue and wavefronts past
-// the actual total fix_off[n_items] return at once
+// FP64 recomputation of the queued walkers, one workgroup per walker: its
+// kBlock lanes take kBlock edges at a time (one pass for up to 256 edges), so
+// a queued walker costs about one edge evaluation of latency; the bins' sums
+// are combined through LDS in a fixed order.  Workgroups loop over the queue
+// (its total is fix_off[n_items]) and all of them reach the end.
 template <bool DH>
 __global__ __launch_bounds__(kBlock) void k_het_fix(const WorkItem *__restrict__ items, WorkItem one, int n_items,
-                                                       const int64_t *__restrict__ fix_off) {
-  const int64_t g = (int64_t)blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (g >= fix_off[n_items]) return;
-  int lo = 0;
-  if (items) {
-    int hi = n_items - 1;  // last item whose first queue entry is <= g
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (fix_off[mid] <= g) lo = mid;
-      else hi = mid - 1;
+                                                    const int64_t *__restrict__ fix_off) {
+  __shared__ double sh_edge[kWaves][3][2];  // first edge value of each wavefront
+  __shared__ double sh_sum[4][kWaves];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t total = fix_off[n_items];
+  for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
+    int lo = 0;
+    if (items) {
+      int hi = n_items - 1;  // last item whose first queue entry is <= g
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (fix_off[mid] <= g) lo = mid;
+        else hi = mid - 1;
+      }
     }
-    lo = __builtin_amdgcn_readfirstlane(lo);
+    const WorkItem &it = items ? items[lo] : one;
+    const int64_t w = it.rlist[g - fix_off[lo]];
+    const WalkerC &c = it.wc[w];
+    const int E = it.E;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int j0 = 0; j0 < E - 1; j0 += kBlock - 1) {
+      // edges j0 .. j0 + 255; bins j0 .. j0 + 254 (the last lane only lends
+      // its edge to the bin before it)
+      const int j = j0 + threadIdx.x;
+      cx<double> dl[3];
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) dl[ch] = mk<double>(0.0, 0.0);
+      if (j < E) het_edge<double>(it.ref, c, j, dl);
+      if (lane == 0)
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+          sh_edge[wave][ch][0] = dl[ch].re;
+          sh_edge[wave][ch][1] = dl[ch].im;
+        }
+      __syncthreads();
+      cx<double> nb[3];
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        nb[ch].re = __shfl_down(dl[ch].re, 1, 64);
+        nb[ch].im = __shfl_down(dl[ch].im, 1, 64);
+        if (lane == 63 && wave + 1 < kWaves) {
+          nb[ch].re = sh_edge[wave + 1][ch][0];
+          nb[ch].im = sh_edge[wave + 1][ch][1];
+        }
+      }
+      if (threadIdx.x < kBlock - 1 && j < E - 1) bin_terms<false, DH>(it.ref, j, dl, nb, v);
+      __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double t = wave_sum(v[q]);
+      if (lane == 0) sh_sum[q][wave] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double s[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) s[q] = sh_sum[q][0] + sh_sum[q][1] + sh_sum[q][2] + sh_sum[q][3];
+      it.lnL[w] = it.ref.lnL0 + s[0];
+      if (it.dhhh) {
+        it.dhhh[2 * w] = it.ref.dh0 + s[1];
+        it.dhhh[2 * w + 1] = it.ref.hh0 + s[2];
+      }
+    }
+    __syncthreads();
   }
-  const WorkItem &it = items ? items[lo] : one;
-  const int64_t w = __builtin_amdgcn_readfirstlane(it.rlist[g - fix_off[lo]]);
-  het_walker<double, 64, DH, true>(it, w);
 }
 
 // single-item path: walker constants and cleared queue

@@ -629,7 +629,8 @@ void launch_finish(const mbh_ctx *ctx, int prec, bool dh, const WorkItem *items,
   }
   hipLaunchKernelGGL(k_het_final<true>, dim3(fb), dim3(kBlock), 0, st, items, one, n_items, total, done, fix_off,
                      routed);
-  const unsigned nb = (unsigned)std::max<int64_t>(1, (max_fix + kWaves - 1) / kWaves);
+  // one workgroup per queued walker, looping: at most two per compute unit
+  const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(max_fix, 2 * ctx->n_cu));
   if (dh) hipLaunchKernelGGL(k_het_fix<true>, dim3(nb), dim3(kBlock), 0, st, items, one, n_items, (const int64_t *)fix_off);
   else hipLaunchKernelGGL(k_het_fix<false>, dim3(nb), dim3(kBlock), 0, st, items, one, n_items, (const int64_t *)fix_off);
 }

@@ -117,13 +117,16 @@ static void launch_group(const TileGroup &g, const WorkItem *items, const WorkTi
 constexpr int kCounterWords = 4;
 
 // setup (a1), one grid per mapping group, the per-walker totals and, for the
-// mixed path, the FP64 recomputation of the walkers the totals queued
+// mixed path, the FP64 recomputation of the walkers the totals queued; the
+// stage mask selects 1 setup, 2 main pass, 4 totals and recomputation
 static void launch_work(const mbh_ctx *ctx, int prec, bool dh, int setup_blocks, int n_items, int64_t total,
                         const std::vector<TileGroup> &groups, const WorkHeader *hdr, const WorkItem *items,
-                        const WorkTile *tiles, unsigned *counters, int64_t *fix_off, hipStream_t st) {
+                        const WorkTile *tiles, unsigned *counters, int64_t *fix_off, hipStream_t st,
+                        int stages = 7) {
   unsigned *done = counters + 2;
-  hipLaunchKernelGGL(k_setup_work, dim3(setup_blocks), dim3(128), 0, st, hdr, items, done);
+  if (stages & 1) hipLaunchKernelGGL(k_setup_work, dim3(setup_blocks), dim3(128), 0, st, hdr, items, done);
   for (const TileGroup &g : groups) {
+    if (!(stages & 2)) break;
     if (prec == MBH_FP64) {
       if (dh) launch_group<double, true>(g, items, tiles, st);
       else launch_group<double, false>(g, items, tiles, st);
@@ -132,6 +135,7 @@ static void launch_work(const mbh_ctx *ctx, int prec, bool dh, int setup_blocks,
       else launch_group<float, false>(g, items, tiles, st);
     }
   }
+  if (!(stages & 4)) return;
   WorkItem none;
   std::memset(&none, 0, sizeof(none));
   launch_finish(ctx, prec, dh, items, none, n_items, total, total, done, fix_off, (unsigned long long *)counters, st);
@@ -150,11 +154,18 @@ struct mbh_batch {
   std::vector<TileGroup> groups;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  // the three stages as graphs of their own (setup, main pass, totals)
+  hipGraph_t sgraph[3] = {nullptr, nullptr, nullptr};
+  hipGraphExec_t sexec[3] = {nullptr, nullptr, nullptr};
 };
 
 static void batch_free(mbh_batch *b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (int i = 0; i < 3; ++i) {
+    if (b->sexec[i]) (void)hipGraphExecDestroy(b->sexec[i]);
+    if (b->sgraph[i]) (void)hipGraphDestroy(b->sgraph[i]);
+  }
   for (auto &a : b->allocs) ctx_free(b->ctx, a.first, a.second);
   delete b;
 }
@@ -246,6 +257,14 @@ extern "C" mbh_status mbh_batch_create(mbh_ctx *ctx, int n, const mbh_ref *const
     e = hipStreamEndCapture(cs, &b->graph);
   }
   if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+  for (int k = 0; k < 3 && e == hipSuccess; ++k) {
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) break;
+    launch_work(ctx, prec, dh, sblk, n, total, b->groups, b->hdr, b->items, b->tiles, b->counters, fix_off, cs,
+                1 << k);
+    e = hipStreamEndCapture(cs, &b->sgraph[k]);
+    if (e == hipSuccess) e = hipGraphInstantiate(&b->sexec[k], b->sgraph[k], nullptr, nullptr, 0);
+  }
   (void)hipStreamDestroy(cs);
   if (e != hipSuccess) return fail(mbh_fail(MBH_EDEVICE, "graph capture: %s", hipGetErrorString(e)));
   *out = b;
@@ -256,6 +275,13 @@ extern "C" mbh_status mbh_batch_launch(mbh_batch *b, hipStream_t st) {
   if (!b) return mbh_fail(MBH_EINVAL, "null batch");
   HIP_TRY(hipSetDevice(b->ctx->device));
   HIP_TRY(hipGraphLaunch(b->exec, st));
+  return MBH_OK;
+}
+
+extern "C" mbh_status mbh_batch_launch_stage(mbh_batch *b, int stage, hipStream_t st) {
+  if (!b || stage < MBH_STAGE_SETUP || stage > MBH_STAGE_FINISH) return mbh_fail(MBH_EINVAL, "bad batch or stage");
+  HIP_TRY(hipSetDevice(b->ctx->device));
+  HIP_TRY(hipGraphLaunch(b->sexec[stage - 1], st));
   return MBH_OK;
 }
 

@@ -25,6 +25,7 @@ MODEL_IMR, MODEL_TF2 = 0, 1
 MODE_22, MODE_33, MODE_44, MODE_21, MODE_32, MODE_43 = (1 << i for i in range(6))
 MODES_ALL = 0x3F
 FP64, MIXED = 0, 1
+STAGE_SETUP, STAGE_MAIN, STAGE_FINISH = 1, 2, 3
 NPARAM = 11
 
 if not os.path.exists(LIB_PATH):
@@ -75,6 +76,7 @@ _SIGS = {
     "mbh_loglike_full": [_vp, _vp, _i32, _u32, _vp, _i64, _i32, _vp, _vp, _vp],
     "mbh_batch_create": [_vp, _i32, _pp, _pp, ct.POINTER(ct.c_int64), _pp, _pp, _i32, _pp],
     "mbh_batch_launch": [_vp, _vp],
+    "mbh_batch_launch_stage": [_vp, _i32, _vp],
     "mbh_batch_routed": [_vp, ct.POINTER(ct.c_uint64)],
     "mbh_batch_release": [_vp],
     "mbh_autotune_heterodyned": [_vp, _vp, _vp, _i64, _i32, ct.POINTER(ct.c_int)],
@@ -316,6 +318,10 @@ class Batch:
 
     def launch(self, stream=None):
         _check(_L.mbh_batch_launch(self.h, _stream(stream)), "mbh_batch_launch")
+
+    def launch_stage(self, stage: int, stream=None):
+        """STAGE_SETUP, STAGE_MAIN or STAGE_FINISH alone (for measurement)."""
+        _check(_L.mbh_batch_launch_stage(self.h, stage, _stream(stream)), "mbh_batch_launch_stage")
 
     def routed(self) -> int:
         v = ct.c_uint64()

@@ -87,6 +87,14 @@ def test_batch_graph_replays_match_single_calls_and_oracle(M, ctx, sources, prec
         for s, l, ref_single in zip(sources, lnls, single):
             got = l.cpu().numpy()
             assert np.array_equal(got, ref_single), (s["modes"], s["nb"], s["W"])
+    # the three stages launched one by one are the same work
+    for l in lnls:
+        l.fill_(np.nan)
+    for stage in (M.STAGE_SETUP, M.STAGE_MAIN, M.STAGE_FINISH):
+        batch.launch_stage(stage)
+    torch.cuda.synchronize()
+    for l, ref_single in zip(lnls, single):
+        assert np.array_equal(l.cpu().numpy(), ref_single)
     # oracle parity on a subsample of every item (last positions)
     worst = 0.0
     for s, t, l in zip(sources, thetas, lnls):

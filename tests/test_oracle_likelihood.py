@@ -223,10 +223,15 @@ def test_noise_normalisation():
 
 def test_paper_printed_peak_likelihood_convention():
     """Maximum-likelihood table: with <d|d> removed, the noisy run peaked at
-    ~+76005 for a source of SNR ~390 (Sec. 3.3).  At h = s, lnL + <d|d>/2 =
+    ~+76005 for a source of SNR ~390 (Sec. 3.3; values in
+    tests/golden/paper_ldc1a_maxll.json).  At h = s, lnL + <d|d>/2 =
     <d|h> - <h|h>/2 = SNR^2/2 + <n|h>, with <n|h> ~ N(0, SNR^2)."""
-    snr = 390.0
-    assert abs(76005.0 - 0.5 * snr ** 2) < 1.0 * snr  # the printed pair is self-consistent
+    import json
+    import os
+
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_ldc1a_maxll.json")))
+    snr, peak = gold["injected_snr"], gold["max_lnL_without_dd"]
+    assert abs(peak - 0.5 * snr ** 2) < 1.0 * snr  # the printed pair is self-consistent
     vals = []
     for s in range(4):
         g, th, data, _ = _lisa_setup(seed=s, snr=snr)
@@ -237,7 +242,7 @@ def test_paper_printed_peak_likelihood_convention():
         assert abs(v - (dh[0] - 0.5 * hh[0])) < 1e-9 * dd
         assert abs(v - 0.5 * snr ** 2) < 5 * snr
         vals.append(v)
-    assert abs(np.mean(vals) - 76005.0) < 5 * snr
+    assert abs(np.mean(vals) - peak) < 5 * snr
 
 
 def test_chirp_het_vs_full_method_error_is_small_near_truth():
