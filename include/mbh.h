@@ -148,12 +148,12 @@ mbh_status mbh_ref_export(const mbh_ref *ref, double *edges, int64_t *kb, double
  * form lnL(h0) + sum_b {...} so that FP32 terms stay small.
  *   theta_dev [W][11] FP64; lnL_dev [W] FP64; dh_hh_dev [W][2] (Z[d,h],
  *   Z[h,h]) or NULL.  MBH_FP64 runs every step in FP64.  MBH_MIXED runs the
- *   LISA response geometry (orbit offsets, arm vectors, link phases, sinc
- *   factors, TDI combinations) in FP32 and keeps phases, times, time/phase
- *   shifts, per-walker amplitude and polarisation factors, the ratio and the
- *   bin contraction in FP64; each walker also gets an estimate of the FP32
- *   error of its lnL, and walkers whose estimate exceeds 5e-4 are recomputed
- *   in FP64 within the same call, so mixed results stay within 1e-3 of FP64.
+ *   sinc series of the six link transfers and the link phase factors in
+ *   FP32 and everything else (phases, times, Doppler, geometry, per-walker
+ *   amplitude and polarisation factors, the ratio and the contraction) in
+ *   FP64; each walker also gets an estimate of the FP32 error of its lnL,
+ *   and walkers whose estimate exceeds 9e-4 are recomputed in FP64 within
+ *   the same call, so mixed results stay within 1e-3 of FP64.
  * Errors: MBH_EINVAL, MBH_ENOMEM, MBH_EDEVICE. */
 mbh_status mbh_loglike_heterodyned(mbh_ctx *ctx, const mbh_ref *ref, const double *theta_dev,
                                    int64_t W, mbh_precision prec, double *lnL_dev,

@@ -467,16 +467,13 @@ __device__ __forceinline__ void het_chunk(const WorkItem &it, int64_t chunk) {
   }
 }
 
-// item of flattened walker t: the last item whose offset is <= t
-__device__ __forceinline__ int item_of(const WorkItem *__restrict__ items, int n_items, int64_t t) {
-  int lo = 0, hi = n_items - 1;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (items[mid].offset <= t) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
+// Walkers of one item handled by one workgroup of the setup and totals
+// kernels (kWalkerTile walkers from w_begin), so that the item is uniform.
+constexpr int kWalkerTile = 128;
+struct WalkerTile {
+  int32_t item, pad;
+  int64_t w_begin;
+};
 
 // Exclusive prefix sums of the per-item queue lengths (total in
 // fix_off[n_items]); adds the number of queued walkers to *routed_total.
@@ -484,8 +481,9 @@ __device__ __forceinline__ int item_of(const WorkItem *__restrict__ items, int n
 __device__ __forceinline__ void fix_plan(const WorkItem *__restrict__ items, const WorkItem &one, int n_items,
                                          int64_t *__restrict__ fix_off,
                                          unsigned long long *__restrict__ routed_total) {
-  __shared__ int64_t sh_c[kBlock];
-  const int per = (n_items + kBlock - 1) / kBlock;
+  constexpr int kT = kWalkerTile;  // threads of the calling workgroup
+  __shared__ int64_t sh_c[kT];
+  const int per = (n_items + kT - 1) / kT;
   const int i0 = threadIdx.x * per, i1 = min(n_items, i0 + per);
   int64_t c = 0;
   for (int i = i0; i < i1; ++i) {
@@ -496,7 +494,7 @@ __device__ __forceinline__ void fix_plan(const WorkItem *__restrict__ items, con
   __syncthreads();
   if (threadIdx.x == 0) {
     int64_t acc = 0;
-    const int n_used = min(kBlock, (n_items + per - 1) / per);
+    const int n_used = min(kT, (n_items + per - 1) / per);
     for (int k = 0; k < n_used; ++k) {
       const int64_t x = sh_c[k];
       sh_c[k] = acc;
@@ -517,57 +515,55 @@ __device__ __forceinline__ void fix_plan(const WorkItem *__restrict__ items, con
 // Per-walker totals of the main pass: the walker's slots are added in slot
 // order, then the outputs are written or (EST, mixed path) the walker is
 // queued for FP64 when its error estimate is above tolerance (one atomic per
-// wavefront and item).  On the mixed path the last workgroup to finish (done
-// counter, zeroed by the setup kernel; device-scope atomics only) builds the
-// plan of the FP64 recomputation.  A single item may be passed by value in
-// `one` with items == nullptr.
+// wavefront).  On the mixed path the last workgroup to finish (done counter,
+// zeroed by the setup kernel; device-scope atomics only) builds the plan of
+// the FP64 recomputation.  One workgroup of kWalkerTile threads per walker
+// tile (items, wtiles) or, for a single item passed by value in `one` with
+// items == nullptr, per kWalkerTile consecutive walkers.
 template <bool EST>
-static __global__ __launch_bounds__(kBlock) void k_het_final(const WorkItem *__restrict__ items, WorkItem one,
-                                                             int n_items, int64_t total, unsigned int *done,
-                                                             int64_t *fix_off, unsigned long long *routed_total) {
+static __global__ __launch_bounds__(kWalkerTile) void k_het_final(const WorkItem *__restrict__ items, WorkItem one,
+                                                                  const WalkerTile *__restrict__ wtiles, int n_items,
+                                                                  unsigned int *done, int64_t *fix_off,
+                                                                  unsigned long long *routed_total) {
   const int lane = threadIdx.x & 63;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  // grid-stride in whole wavefronts: every lane takes part in the queue appends
-  for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < total; base += stride) {
-    const int64_t t = base + lane;
-    const bool in = t < total;
-    const int ii = (in && items) ? item_of(items, n_items, t) : 0;
-    const WorkItem &it = items ? items[ii] : one;
-    const int64_t w = t - it.offset;
-    const bool act = in && w < it.W;
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
-    bool valid = false;
-    if (act) {
-      int n_slot = 1;
-      if (it.G == 0) n_slot = (int)((w * it.E + it.E - 2) / kChunk - (w * it.E) / kChunk) + 1;
-      const double *p = it.part + w * it.K * 4;
-      for (int k = 0; k < n_slot; ++k)
+  int64_t w0 = (int64_t)blockIdx.x * kWalkerTile;
+  int ii = 0;
+  if (items) {
+    const WalkerTile tl = wtiles[blockIdx.x];
+    ii = tl.item;
+    w0 = tl.w_begin;
+  }
+  const WorkItem &it = items ? items[ii] : one;
+  const int64_t w = w0 + threadIdx.x;
+  const bool act = w < it.W;
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  bool valid = false;
+  if (act) {
+    int n_slot = 1;
+    if (it.G == 0) n_slot = (int)((w * it.E + it.E - 2) / kChunk - (w * it.E) / kChunk) + 1;
+    const double *p = it.part + w * it.K * 4;
+    for (int k = 0; k < n_slot; ++k)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) s[q] += p[4 * k + q];
-      valid = it.wc[w].valid;
+      for (int q = 0; q < 4; ++q) s[q] += p[4 * k + q];
+    valid = it.wc[w].valid;
+  }
+  // s[3] lacks the gradient's factor 4: sqrt(S / 2) = sqrt(8 s[3])
+  const bool route = EST && act && valid && it.rcount && kMixedErrScale * sqrt(8.0 * s[3]) > kMixedRouteTol;
+  if (EST) {
+    const uint64_t m = __ballot(route);
+    if (m) {
+      const int leader = __ffsll((unsigned long long)m) - 1;
+      unsigned int slot0 = 0;
+      if (lane == leader) slot0 = atomicAdd(it.rcount, (unsigned int)__popcll(m));
+      slot0 = __shfl(slot0, leader, 64);
+      if (route) it.rlist[slot0 + __popcll(m & ((1ull << lane) - 1ull))] = (int)w;
     }
-    // s[3] lacks the gradient's factor 4: sqrt(S / 2) = sqrt(8 s[3])
-    const bool route = EST && act && valid && it.rcount && kMixedErrScale * sqrt(8.0 * s[3]) > kMixedRouteTol;
-    if (EST) {
-      uint64_t pending = __ballot(route);
-      while (pending) {
-        const int leader = __ffsll((unsigned long long)pending) - 1;
-        const int il = __shfl(ii, leader, 64);
-        const bool mine = route && ii == il;
-        const uint64_t m = __ballot(mine);
-        unsigned int slot0 = 0;
-        if (lane == leader) slot0 = atomicAdd(it.rcount, (unsigned int)__popcll(m));
-        slot0 = __shfl(slot0, leader, 64);
-        if (mine) it.rlist[slot0 + __popcll(m & ((1ull << lane) - 1ull))] = (int)w;
-        pending &= ~m;
-      }
-    }
-    if (act && !route) {
-      it.lnL[w] = valid ? it.ref.lnL0 + s[0] : -INFINITY;
-      if (it.dhhh) {
-        it.dhhh[2 * w] = valid ? it.ref.dh0 + s[1] : 0.0;
-        it.dhhh[2 * w + 1] = valid ? it.ref.hh0 + s[2] : 0.0;
-      }
+  }
+  if (act && !route) {
+    it.lnL[w] = valid ? it.ref.lnL0 + s[0] : -INFINITY;
+    if (it.dhhh) {
+      it.dhhh[2 * w] = valid ? it.ref.dh0 + s[1] : 0.0;
+      it.dhhh[2 * w + 1] = valid ? it.ref.hh0 + s[2] : 0.0;
     }
   }
   if (EST) {

@@ -615,19 +615,20 @@ static void launch_main(int prec, bool dh, const WorkItem &it, hipStream_t st) {
 
 // Totals of the main pass and, for the mixed path, the FP64 recomputation of
 // the queued walkers (k_het_final, which also plans the recomputation, then
-// k_het_fix over the largest possible queue, max_fix walkers).
-// done: the finishing grid's counter (zero before the launch); fix_off:
-// n_items + 1 entries; routed: running total (64-bit) or null.
-void launch_finish(const mbh_ctx *ctx, int prec, bool dh, const WorkItem *items, const WorkItem &one, int n_items,
-                   int64_t total, int64_t max_fix, unsigned *done, int64_t *fix_off, unsigned long long *routed,
-                   hipStream_t st) {
-  const unsigned fb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + kBlock - 1) / kBlock, 4 * ctx->n_cu));
+// k_het_fix over the largest possible queue, max_fix walkers).  Batches pass
+// their walker tiles (n_wtiles of them); a single item passes it by value
+// with items == nullptr.  done: the totals grid's counter (zero before the
+// launch); fix_off: n_items + 1 entries; routed: running total or null.
+void launch_finish(const mbh_ctx *ctx, int prec, bool dh, const WorkItem *items, const WorkItem &one,
+                   const WalkerTile *wtiles, int64_t n_wtiles, int n_items, int64_t max_fix, unsigned *done,
+                   int64_t *fix_off, unsigned long long *routed, hipStream_t st) {
+  const dim3 fb((unsigned)std::max<int64_t>(1, items ? n_wtiles : (one.W + kWalkerTile - 1) / kWalkerTile));
   if (prec == MBH_FP64) {
-    hipLaunchKernelGGL(k_het_final<false>, dim3(fb), dim3(kBlock), 0, st, items, one, n_items, total,
+    hipLaunchKernelGGL(k_het_final<false>, fb, dim3(kWalkerTile), 0, st, items, one, wtiles, n_items,
                        (unsigned *)nullptr, (int64_t *)nullptr, (unsigned long long *)nullptr);
     return;
   }
-  hipLaunchKernelGGL(k_het_final<true>, dim3(fb), dim3(kBlock), 0, st, items, one, n_items, total, done, fix_off,
+  hipLaunchKernelGGL(k_het_final<true>, fb, dim3(kWalkerTile), 0, st, items, one, wtiles, n_items, done, fix_off,
                      routed);
   // one workgroup per queued walker, looping: at most two per compute unit
   const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(max_fix, 2 * ctx->n_cu));
@@ -665,7 +666,7 @@ extern "C" mbh_status mbh_loglike_heterodyned(mbh_ctx *ctx, const mbh_ref *ref, 
   hipLaunchKernelGGL(k_setup_one, dim3((unsigned)((W + 127) / 128)), dim3(128), 0, st, it, done);
   const bool dh = dh_hh_dev != nullptr;
   launch_main(prec, dh, it, st);
-  launch_finish(ctx, prec, dh, nullptr, it, 1, W, W, done, fix_off, nullptr, st);
+  launch_finish(ctx, prec, dh, nullptr, it, nullptr, 0, 1, W, done, fix_off, nullptr, st);
   HIP_TRY(hipGetLastError());
   return MBH_OK;
 }

@@ -25,9 +25,14 @@ HetRef ref_view(const mbh_ref *r);
 int lanes_lookup(const mbh_ctx *ctx, int n_bins, int n_modes, int prec);
 int popcount_modes(uint32_t m);
 WorkItem make_item(const mbh_ref *r, int G);
-void launch_finish(const mbh_ctx *ctx, int prec, bool dh, const WorkItem *items, const WorkItem &one, int n_items,
-                   int64_t total, int64_t max_fix, unsigned *done, int64_t *fix_off, unsigned long long *routed,
-                   hipStream_t st);
+void launch_finish(const mbh_ctx *ctx, int prec, bool dh, const WorkItem *items, const WorkItem &one,
+                   const WalkerTile *wtiles, int64_t n_wtiles, int n_items, int64_t max_fix, unsigned *done,
+                   int64_t *fix_off, unsigned long long *routed, hipStream_t st);
+
+// walker tiles of one item (kWalkerTile walkers each)
+static void append_wtiles(std::vector<WalkerTile> &wt, int item, int64_t W) {
+  for (int64_t w = 0; w < W; w += kWalkerTile) wt.push_back(WalkerTile{item, 0, w});
+}
 
 #define HIP_TRY(x)                                                                          \
   do {                                                                                      \
@@ -119,12 +124,13 @@ constexpr int kCounterWords = 4;
 // setup (a1), one grid per mapping group, the per-walker totals and, for the
 // mixed path, the FP64 recomputation of the walkers the totals queued; the
 // stage mask selects 1 setup, 2 main pass, 4 totals and recomputation
-static void launch_work(const mbh_ctx *ctx, int prec, bool dh, int setup_blocks, int n_items, int64_t total,
-                        const std::vector<TileGroup> &groups, const WorkHeader *hdr, const WorkItem *items,
+static void launch_work(const mbh_ctx *ctx, int prec, bool dh, int64_t n_wtiles, int n_items, int64_t total,
+                        const std::vector<TileGroup> &groups, const WalkerTile *wtiles, const WorkItem *items,
                         const WorkTile *tiles, unsigned *counters, int64_t *fix_off, hipStream_t st,
                         int stages = 7) {
   unsigned *done = counters + 2;
-  if (stages & 1) hipLaunchKernelGGL(k_setup_work, dim3(setup_blocks), dim3(128), 0, st, hdr, items, done);
+  const dim3 nw((unsigned)std::max<int64_t>(1, n_wtiles));
+  if (stages & 1) hipLaunchKernelGGL(k_setup_work, nw, dim3(kWalkerTile), 0, st, items, wtiles, done);
   for (const TileGroup &g : groups) {
     if (!(stages & 2)) break;
     if (prec == MBH_FP64) {
@@ -138,7 +144,8 @@ static void launch_work(const mbh_ctx *ctx, int prec, bool dh, int setup_blocks,
   if (!(stages & 4)) return;
   WorkItem none;
   std::memset(&none, 0, sizeof(none));
-  launch_finish(ctx, prec, dh, items, none, n_items, total, total, done, fix_off, (unsigned long long *)counters, st);
+  launch_finish(ctx, prec, dh, items, none, wtiles, n_wtiles, n_items, total, done, fix_off,
+                (unsigned long long *)counters, st);
 }
 
 // ---------------------------------------------------------------- batch
@@ -146,9 +153,10 @@ struct mbh_batch {
   mbh_ctx *ctx = nullptr;
   int prec = 0;
   bool dh = false;
-  WorkHeader *hdr = nullptr;
   WorkItem *items = nullptr;
   WorkTile *tiles = nullptr;
+  WalkerTile *wtiles = nullptr;
+  int64_t n_wtiles = 0;
   unsigned *counters = nullptr;
   std::vector<std::pair<void *, size_t>> allocs;
   std::vector<TileGroup> groups;
@@ -218,6 +226,7 @@ extern "C" mbh_status mbh_batch_create(mbh_ctx *ctx, int n, const mbh_ref *const
     return fail(s);
   std::vector<WorkItem> items(n);
   std::vector<WorkTile> tiles;
+  std::vector<WalkerTile> wtiles;
   std::vector<double> cost;
   int64_t off = 0;
   for (int i = 0; i < n; ++i) {
@@ -233,35 +242,37 @@ extern "C" mbh_status mbh_batch_create(mbh_ctx *ctx, int n, const mbh_ref *const
     it.W = W[i];
     it.offset = off;
     append_tiles(tiles, cost, i, refs[i], it.G, W[i]);
+    append_wtiles(wtiles, i, W[i]);
     off += W[i];
   }
   b->groups = order_tiles(tiles, cost);
-  WorkHeader h{n, (int32_t)tiles.size(), total};
-  if ((s = batch_alloc(b, &b->hdr, 1)) != MBH_OK || (s = batch_alloc(b, &b->items, (size_t)n)) != MBH_OK ||
-      (s = batch_alloc(b, &b->tiles, tiles.size())) != MBH_OK)
+  if ((s = batch_alloc(b, &b->items, (size_t)n)) != MBH_OK ||
+      (s = batch_alloc(b, &b->tiles, tiles.size())) != MBH_OK ||
+      (s = batch_alloc(b, &b->wtiles, wtiles.size())) != MBH_OK)
     return fail(s);
+  b->n_wtiles = (int64_t)wtiles.size();
   std::vector<unsigned> zero(std::max(n, kCounterWords), 0u);
   if ((mixed && hipMemcpy(rcount, zero.data(), n * sizeof(unsigned), hipMemcpyHostToDevice) != hipSuccess) ||
       hipMemcpy(b->counters, zero.data(), kCounterWords * sizeof(unsigned), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(b->hdr, &h, sizeof(h), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(b->items, items.data(), n * sizeof(WorkItem), hipMemcpyHostToDevice) != hipSuccess ||
-      (!tiles.empty() && hipMemcpy(b->tiles, tiles.data(), tiles.size() * sizeof(WorkTile), hipMemcpyHostToDevice) != hipSuccess))
+      (!tiles.empty() && hipMemcpy(b->tiles, tiles.data(), tiles.size() * sizeof(WorkTile), hipMemcpyHostToDevice) != hipSuccess) ||
+      (!wtiles.empty() && hipMemcpy(b->wtiles, wtiles.data(), wtiles.size() * sizeof(WalkerTile), hipMemcpyHostToDevice) != hipSuccess))
     return fail(mbh_fail(MBH_EDEVICE, "upload work list"));
   // capture the whole pass once
-  const int sblk = (int)std::max<int64_t>(1, std::min<int64_t>((total + 127) / 128, 4 * ctx->n_cu));
   hipStream_t cs;
   if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return fail(mbh_fail(MBH_EDEVICE, "stream"));
   hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    launch_work(ctx, prec, dh, sblk, n, total, b->groups, b->hdr, b->items, b->tiles, b->counters, fix_off, cs);
+    launch_work(ctx, prec, dh, b->n_wtiles, n, total, b->groups, b->wtiles, b->items, b->tiles, b->counters, fix_off,
+                cs);
     e = hipStreamEndCapture(cs, &b->graph);
   }
   if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
   for (int k = 0; k < 3 && e == hipSuccess; ++k) {
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) break;
-    launch_work(ctx, prec, dh, sblk, n, total, b->groups, b->hdr, b->items, b->tiles, b->counters, fix_off, cs,
-                1 << k);
+    launch_work(ctx, prec, dh, b->n_wtiles, n, total, b->groups, b->wtiles, b->items, b->tiles, b->counters, fix_off,
+                cs, 1 << k);
     e = hipStreamEndCapture(cs, &b->sgraph[k]);
     if (e == hipSuccess) e = hipGraphInstantiate(&b->sexec[k], b->sgraph[k], nullptr, nullptr, 0);
   }
@@ -324,10 +335,12 @@ struct Slot {
   WorkHeader *hdr_h = nullptr;
   WorkItem *items_h = nullptr;
   WorkTile *tiles_h = nullptr;
+  WalkerTile *wtiles_h = nullptr;
   double *theta_d = nullptr, *res_d = nullptr;
-  WorkHeader *hdr_d = nullptr;
   WorkItem *items_d = nullptr;
   WorkTile *tiles_d = nullptr;
+  WalkerTile *wtiles_d = nullptr;
+  int64_t n_wtiles = 0;
   unsigned *counters_d = nullptr;  // kCounterWords
   unsigned *rcount_d = nullptr;    // [max_items]
   int64_t *fix_off_d = nullptr;    // [max_items + 1]
@@ -374,6 +387,7 @@ static void server_free(mbh_server *s) {
     if (sl.hdr_h) (void)hipHostFree(sl.hdr_h);
     if (sl.items_h) (void)hipHostFree(sl.items_h);
     if (sl.tiles_h) (void)hipHostFree(sl.tiles_h);
+    if (sl.wtiles_h) (void)hipHostFree(sl.wtiles_h);
   }
   for (auto &a : s->dev_allocs) ctx_free(s->ctx, a.first, a.second);
   delete s;
@@ -387,6 +401,7 @@ static bool server_pack(mbh_server *s, Slot &sl) {
   int64_t n_tiles = 0;
   const bool mixed = s->cfg.prec == MBH_MIXED;
   std::vector<WorkTile> tiles;
+  std::vector<WalkerTile> wtiles;
   std::vector<double> cost;
   while (!s->queue.empty()) {
     auto &r = s->queue.front();
@@ -420,6 +435,9 @@ static bool server_pack(mbh_server *s, Slot &sl) {
   }
   sl.groups = order_tiles(tiles, cost);
   std::memcpy(sl.tiles_h, tiles.data(), tiles.size() * sizeof(WorkTile));
+  for (int i = 0; i < n_items; ++i) append_wtiles(wtiles, i, sl.items_h[i].W);
+  std::memcpy(sl.wtiles_h, wtiles.data(), wtiles.size() * sizeof(WalkerTile));
+  sl.n_wtiles = (int64_t)wtiles.size();
   *sl.hdr_h = WorkHeader{n_items, (int32_t)tiles.size(), sl.walkers};
   return true;
 }
@@ -430,11 +448,10 @@ static bool server_launch(mbh_server *s, Slot &sl) {
   bool ok = hipMemcpyAsync(sl.theta_d, sl.theta_h, sl.walkers * 11 * sizeof(double), hipMemcpyHostToDevice, st) == hipSuccess &&
             hipMemcpyAsync(sl.items_d, sl.items_h, h.n_items * sizeof(WorkItem), hipMemcpyHostToDevice, st) == hipSuccess &&
             hipMemcpyAsync(sl.tiles_d, sl.tiles_h, h.n_tiles * sizeof(WorkTile), hipMemcpyHostToDevice, st) == hipSuccess &&
-            hipMemcpyAsync(sl.hdr_d, sl.hdr_h, sizeof(WorkHeader), hipMemcpyHostToDevice, st) == hipSuccess;
+            hipMemcpyAsync(sl.wtiles_d, sl.wtiles_h, sl.n_wtiles * sizeof(WalkerTile), hipMemcpyHostToDevice, st) == hipSuccess;
   if (!ok) return false;
-  const int sblk = (int)std::max<int64_t>(1, std::min<int64_t>((sl.walkers + 127) / 128, 4 * s->ctx->n_cu));
-  launch_work(s->ctx, s->cfg.prec, true, sblk, h.n_items, sl.walkers, sl.groups, sl.hdr_d, sl.items_d, sl.tiles_d,
-              sl.counters_d, sl.fix_off_d, st);
+  launch_work(s->ctx, s->cfg.prec, true, sl.n_wtiles, h.n_items, sl.walkers, sl.groups, sl.wtiles_d, sl.items_d,
+              sl.tiles_d, sl.counters_d, sl.fix_off_d, st);
   ok = hipGetLastError() == hipSuccess &&
        hipMemcpyAsync(sl.res_h, sl.res_d, sl.walkers * 3 * sizeof(double), hipMemcpyDeviceToHost, st) == hipSuccess &&
        hipEventRecord(sl.ev, st) == hipSuccess;
@@ -561,13 +578,15 @@ extern "C" mbh_status mbh_server_create(mbh_ctx *ctx, int n_refs, const mbh_ref 
         hipHostMalloc((void **)&sl.res_h, cap * 3 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&sl.hdr_h, sizeof(WorkHeader), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&sl.items_h, s->max_items * sizeof(WorkItem), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&sl.tiles_h, s->max_tiles * sizeof(WorkTile), hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc((void **)&sl.tiles_h, s->max_tiles * sizeof(WorkTile), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&sl.wtiles_h, (cap / kWalkerTile + s->max_items + 1) * sizeof(WalkerTile),
+                      hipHostMallocDefault) != hipSuccess) {
       server_free(s);
       return mbh_fail(MBH_EDEVICE, "server host resources");
     }
     if ((st = dalloc((void **)&sl.theta_d, cap * 11 * sizeof(double))) != MBH_OK ||
         (st = dalloc((void **)&sl.res_d, cap * 3 * sizeof(double))) != MBH_OK ||
-        (st = dalloc((void **)&sl.hdr_d, sizeof(WorkHeader))) != MBH_OK ||
+        (st = dalloc((void **)&sl.wtiles_d, (cap / kWalkerTile + s->max_items + 1) * sizeof(WalkerTile))) != MBH_OK ||
         (st = dalloc((void **)&sl.items_d, s->max_items * sizeof(WorkItem))) != MBH_OK ||
         (st = dalloc((void **)&sl.tiles_d, s->max_tiles * sizeof(WorkTile))) != MBH_OK ||
         (st = dalloc((void **)&sl.counters_d, kCounterWords * sizeof(unsigned))) != MBH_OK ||

@@ -25,20 +25,17 @@ struct WorkTile {
   int64_t begin;  // first chunk (G = 0) or first walker (G > 0) of the tile
 };
 
-// a1 for every walker of the batch (grid-stride over the flattened walkers);
-// also clears each item's FP64 queue and the finishing grid's counter
-static __global__ __launch_bounds__(128) void k_setup_work(const WorkHeader *__restrict__ hdr,
-                                                           const WorkItem *__restrict__ items,
-                                                           unsigned int *__restrict__ done) {
-  const int64_t total = hdr->total_walkers;
-  const int n = hdr->n_items;
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
-    const WorkItem &it = items[item_of(items, n, t)];
-    const int64_t w = t - it.offset;
-    if (t == 0) *done = 0u;
-    if (w == 0 && it.rcount) *it.rcount = 0u;
-    if (w < it.W) walker_setup(it.theta + w * 11, it.model, it.ref.modes, it.wc[w]);
-  }
+// a1 for every walker of the batch, one workgroup per walker tile; also
+// clears each item's FP64 queue and the totals grid's counter
+static __global__ __launch_bounds__(kWalkerTile) void k_setup_work(const WorkItem *__restrict__ items,
+                                                                   const WalkerTile *__restrict__ wtiles,
+                                                                   unsigned int *__restrict__ done) {
+  const WalkerTile tl = wtiles[blockIdx.x];
+  const WorkItem &it = items[tl.item];
+  const int64_t w = tl.w_begin + threadIdx.x;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *done = 0u;
+  if (w == 0 && it.rcount) *it.rcount = 0u;
+  if (w < it.W) walker_setup(it.theta + w * 11, it.model, it.ref.modes, it.wc[w]);
 }
 
 template <typename R, bool DH, int G>
