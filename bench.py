@@ -39,15 +39,17 @@ PEAK_HBM_GBS = 8000.0
 N_SOURCES, TEMPS, PER_TEMP, N_BINS = 8, tuple(2.0 ** k for k in range(8)), 64, 128
 # Floating-point work of one (walker, bin edge) of the heterodyned main pass
 # with the (2,2) mode and three channels, its bin included (FMA = 2 flops,
-# other arithmetic and transcendental instructions 1), as counted by the VALU
-# FLOP counters (SQ_INSTS_VALU_FLOPS_FP64, _FP32, _FP64_TRANS, _FP32_TRANS,
-# x 64 lanes) over a divergence-free launch of 4096 walkers x 129 edges: the
-# same 905 in both precisions (the mixed path moves ~16 % of it to FP32).
-FLOPS_PER_EDGE = 905.0
-# HBM traffic of the dominant kernel (bytes per launch) from the FETCH_SIZE and
-# WRITE_SIZE counters, scaled by the same counters' reading for a plain copy
-# of known size; valid only for the kernel sources it was measured on.
-TRAFFIC = {"src_sha256": None, "bytes_per_launch": None}
+# other arithmetic and transcendental instructions 1): the VALU FLOP counters
+# (SQ_INSTS_VALU_FLOPS_FP64, _FP32, _FP64_TRANS, _FP32_TRANS, x 64 lanes) of
+# the mixed main pass over this benchmark's 4096 walkers x 129 edges give
+# 4.914e8 per launch, 930 per edge (FP64 pass: 935); profiles/het_main_pass_bench.md.
+FLOPS_PER_EDGE = 930.0
+# HBM traffic of the mixed main pass (bytes per launch) from the FETCH_SIZE and
+# WRITE_SIZE counters divided by their reading for a 64 MiB device copy
+# (factors 0.5002 and 1.000); valid only for the kernel sources it was
+# measured on (sha256 over paper_2111_01064_amd/csrc).
+TRAFFIC = {"src_sha256": "d78a6d16e7f1dceea8f59debc48d5e6d2c11e210816a44887c4414c7bd245c36",
+           "bytes_per_launch": 6.165e6}
 
 
 def kernel_sources_hash() -> str:
@@ -328,7 +330,7 @@ def side_measurements(M, ctx, S, walkers, grid):
     out = {}
     # full-grid likelihood: brute-force prior draws on the 1.58e6-bin grid
     it = S.items[0]
-    draws = I.prior_draws(I.rng_for(3, 0), 2048, grid.t_obs)
+    draws = I.prior_draws(I.rng_for(3, 0), 16384, grid.t_obs)
     td = torch.as_tensor(draws, device="cuda")
     for name, prec in (("fp64", M.FP64), ("mixed", M.MIXED)):
         M.loglike_full(ctx, it["data"], M.MODEL_IMR, M.MODE_22, td[:64], prec)
