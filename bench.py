@@ -62,6 +62,14 @@ def kernel_sources_hash() -> str:
     return h.hexdigest()
 
 
+def walker_segments(W: int, E: int, lanes: int) -> int:
+    """Partial-sum segments of W walkers with E bin edges: the 63-bin chunks
+    each walker's bins touch (flattened mapping) or one per walker."""
+    if lanes:
+        return W
+    return sum((w * E + E - 2) // 63 - (w * E) // 63 + 1 for w in range(W))
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -246,6 +254,9 @@ def main():
     ap.add_argument("--mapping", type=int, default=None,
                     help="fix the heterodyned mapping (0 = flattened, or lanes per walker) instead of autotuning; "
                          "for profiler runs, whose timings would mislead the autotuner")
+    ap.add_argument("--mixed-tol", type=float, default=None,
+                    help="estimated-error tolerance of the mixed path (library default 9e-4; inf: no FP64 "
+                         "recomputation, 0: everything in FP64)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: every walker batch fits one MI355X and this build has no "
@@ -257,6 +268,8 @@ def main():
     from paper_2111_01064_amd import mbh as M
 
     ctx = M.Context(0)
+    if args.mixed_tol is not None:
+        M.set_mixed_tolerance(ctx, args.mixed_tol)
     grid = I.grid_lisa()
     t0 = time.perf_counter()
     S = Sources(M, ctx, grid, N_SOURCES)
@@ -282,8 +295,10 @@ def main():
                   for st in (M.STAGE_SETUP, M.STAGE_MAIN, M.STAGE_FINISH)]
         res[name]["stages_s"] = stages
         batch.close()
+        res[name]["segments"] = sum(walker_segments(len(w), N_BINS + 1, res[name]["lanes"]) for w in walkers)
         log(f"[bench] {name}: {W_total} walkers/step, {mean_s * 1e6:.1f} us/step (events), wall {wall:.3f} s, "
-            f"lanes {res[name]['lanes']}, FP64-recomputed walkers/step {routed:.1f}, stages (us) "
+            f"lanes {res[name]['lanes']}, FP64-recomputed segments/step {routed:.1f} of {res[name]['segments']}, "
+            f"stages (us) "
             + " / ".join(f"{x * 1e6:.1f}" for x in stages))
     dmix = float(np.max(np.abs(res["mixed"]["lnl"] - res["fp64"]["lnl"])))
     ms_per_step = res["mixed"]["wall"] / args.steps * 1e3
@@ -303,7 +318,8 @@ def main():
                    "walkers_per_step": W_total, "n_bins": N_BINS, "launch": "mbh_batch graph replay"},
         "fp64_evals_per_s": fp64_value, "fp64_ms_per_step": res["fp64"]["wall"] / args.steps * 1e3,
         "mixed_speedup_vs_fp64": value / fp64_value, "max_abs_dlnL_mixed_vs_fp64": dmix,
-        "mixed_fp64_recomputed_fraction": res["mixed"]["routed"] / W_total,
+        "mixed_fp64_recomputed_fraction": res["mixed"]["routed"] / res["mixed"]["segments"],
+        "mixed_tolerance": M.mixed_tolerance(ctx),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_ALU_TFLOPS, "traffic": traffic,
                      "kernel": "k_het_tiles<float> (main pass, mixed)", "kernel_us": t_main * 1e6,
@@ -365,7 +381,7 @@ def side_measurements(M, ctx, S, walkers, grid):
         wall, mean_s, _ = time_batch(M, ctx, b4, 50, 5, st)
         hm[f"{name}_evals_per_s"] = W4 * 50 / wall
         hm[f"{name}_us_per_launch"] = mean_s * 1e6
-        hm[f"{name}_routed_per_launch"] = b4.routed() / 55
+        hm[f"{name}_fp64_segments_per_launch"] = b4.routed() / 55
         lnl4[name] = np.concatenate([l.cpu().numpy() for l in ln4])
         b4.close()
         log(f"[bench] HM batch {name}: {W4} walkers, {W4 * 50 / wall:.3g} evals/s")

@@ -74,6 +74,9 @@ typedef struct mbh_server mbh_server;
  * memory the context's handles and scratch may hold (0 = no cap).
  * Errors: MBH_EINVAL (bad device / null out), MBH_EDEVICE. */
 mbh_status mbh_create(int device, size_t hbm_budget_bytes, mbh_ctx **out);
+/* Release the caller's context handle.  Data, references, batches and servers
+ * created from the context keep it alive: it is freed when the last of them
+ * is released, so handles may be released in any order. */
 mbh_status mbh_destroy(mbh_ctx *ctx);
 
 /* Message of the calling thread's last failed call ("" if none). */
@@ -151,9 +154,11 @@ mbh_status mbh_ref_export(const mbh_ref *ref, double *edges, int64_t *kb, double
  *   sinc series of the six link transfers and the link phase factors in
  *   FP32 and everything else (phases, times, Doppler, geometry, per-walker
  *   amplitude and polarisation factors, the ratio and the contraction) in
- *   FP64; each walker also gets an estimate of the FP32 error of its lnL,
- *   and walkers whose estimate exceeds 9e-4 are recomputed in FP64 within
- *   the same call, so mixed results stay within 1e-3 of FP64.
+ *   FP64.  The FP32 error of lnL is estimated per segment of a walker's
+ *   bins (the bins one wavefront handles); segments whose share could take
+ *   the walker's estimate above the tolerance (9e-4 by default, see
+ *   mbh_set_mixed_tolerance) are recomputed in FP64 by the same wavefront,
+ *   so mixed results stay within 1e-3 of FP64.
  * Errors: MBH_EINVAL, MBH_ENOMEM, MBH_EDEVICE. */
 mbh_status mbh_loglike_heterodyned(mbh_ctx *ctx, const mbh_ref *ref, const double *theta_dev,
                                    int64_t W, mbh_precision prec, double *lnL_dev,
@@ -169,11 +174,12 @@ mbh_status mbh_loglike_full(mbh_ctx *ctx, const mbh_data *data, int model, uint3
 
 /* ------------------------------------------------------ batching (a10) */
 
-/* One persistent launch over many (reference, walker batch) items with
- * ragged modes, bin counts and walker counts.  Items are packed into a
- * device work list of tiles (longest first) that the workgroups of a
- * persistent grid claim through one atomic counter; the launch is captured
- * once into a HIP graph and replayed by mbh_batch_launch.  The mapping of
+/* One launch over many (reference, walker batch) items with ragged modes,
+ * bin counts and walker counts.  Items are packed into a device work list of
+ * tiles, grouped by mapping and longest first within a group (one grid of
+ * one workgroup per tile per group, between the setup and totals grids);
+ * the whole pass is captured once into a HIP graph and replayed by
+ * mbh_batch_launch.  The mapping of
  * each item (see mbh_set_lanes) comes from the autotuner table (per bin count
  * and mode count), so a walker's result depends only on its inputs, its
  * reference and its index within its item, never on the rest of the batch.
@@ -188,14 +194,16 @@ mbh_status mbh_batch_create(mbh_ctx *ctx, int n, const mbh_ref *const *refs,
 mbh_status mbh_batch_launch(mbh_batch *batch, hipStream_t stream);
 /* One stage of the same work as a graph of its own, for measuring stages
  * separately: MBH_STAGE_SETUP (walker constants, a1), MBH_STAGE_MAIN (the
- * heterodyned main pass, a2-a7: the dominant kernel), MBH_STAGE_FINISH
- * (per-walker totals and, on the mixed path, the FP64 recomputation).
+ * heterodyned main pass, a2-a7, with the mixed path's FP64 recomputation:
+ * the dominant kernel), MBH_STAGE_FINISH (per-walker totals).
  * Launching the three in this order on one stream is mbh_batch_launch.
  * Errors: MBH_EINVAL, MBH_EDEVICE. */
 enum { MBH_STAGE_SETUP = 1, MBH_STAGE_MAIN = 2, MBH_STAGE_FINISH = 3 };
 mbh_status mbh_batch_launch_stage(mbh_batch *batch, int stage, hipStream_t stream);
-/* Walkers of this batch that the mixed path recomputed in FP64 (see
- * mbh_loglike_heterodyned), summed over all launches so far.  Synchronous. */
+/* Walker segments of this batch that the mixed path recomputed in FP64 (see
+ * mbh_loglike_heterodyned; a segment is a walker's bins within one
+ * 63-bin chunk of the flattened mapping, or the whole walker in a lane-group
+ * mapping), summed over all launches so far.  Synchronous. */
 mbh_status mbh_batch_routed(const mbh_batch *batch, uint64_t *routed_out);
 mbh_status mbh_batch_release(mbh_batch *batch);
 
@@ -217,6 +225,14 @@ mbh_status mbh_lanes_for(const mbh_ctx *ctx, int n_bins, int n_modes, mbh_precis
  * 1..64 (power of two) lanes per walker.  Results differ between mappings
  * only by rounding. */
 mbh_status mbh_set_lanes(mbh_ctx *ctx, int n_bins, int n_modes, mbh_precision prec, int lanes);
+/* Tolerance of the mixed path on the estimated FP32 error of each walker's
+ * lnL (default 9e-4): work whose share of the estimate could exceed it is
+ * recomputed in FP64.  0 recomputes everything (mixed results then equal the
+ * FP64 path's bit for bit); +inf recomputes nothing (the plain FP32 error,
+ * for measurement).  Applies to calls, batches and server batches created
+ * afterwards.  Errors: MBH_EINVAL for a negative or NaN tolerance. */
+mbh_status mbh_set_mixed_tolerance(mbh_ctx *ctx, double tol);
+mbh_status mbh_get_mixed_tolerance(const mbh_ctx *ctx, double *tol_out);
 mbh_status mbh_autotune_save(const mbh_ctx *ctx, const char *path);
 mbh_status mbh_autotune_load(mbh_ctx *ctx, const char *path);
 

@@ -21,10 +21,36 @@ struct mbh_ctx {
   mutable std::mutex mu;
   // lanes per walker of the heterodyned kernel, keyed by (n_bins, n_modes, precision)
   std::map<std::tuple<int, int, int>, int> lanes;
+  // mixed path: estimated lnL error above which work is recomputed in FP64
+  // (set from kMixedRouteTol at creation)
+  double mixed_tol = 0.0;
+  // the caller's reference plus one per live object created from the context
+  std::atomic<int> refs{1};
+};
+
+void ctx_retain(mbh_ctx *ctx);
+void ctx_release(mbh_ctx *ctx);
+
+// Member of every object created from a context: keeps the context alive
+// until the object is deleted, so objects and context may be released in any
+// order.
+struct CtxHold {
+  mbh_ctx *c = nullptr;
+  CtxHold() = default;
+  CtxHold(const CtxHold &) = delete;
+  CtxHold &operator=(const CtxHold &) = delete;
+  void set(mbh_ctx *x) {
+    ctx_retain(x);
+    c = x;
+  }
+  ~CtxHold() {
+    if (c) ctx_release(c);
+  }
 };
 
 struct mbh_data {
   mbh_ctx *ctx = nullptr;
+  CtxHold hold;
   int n_chan = 0;
   int64_t n_f = 0;
   double f0 = 0, df = 0, t_obs = 0;
@@ -42,6 +68,7 @@ struct mbh_data {
 
 struct mbh_ref {
   mbh_ctx *ctx = nullptr;
+  CtxHold hold;
   int model = 0;
   uint32_t modes = 0;
   int n_chan = 0, n_bins = 0;

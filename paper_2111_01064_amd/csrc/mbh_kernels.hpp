@@ -259,13 +259,17 @@ static __global__ __launch_bounds__(64) void k_ref_edges(const WalkerC *__restri
 //
 // Mixed precision: the FP32 parts of the response (sinc series, link phase
 // factors) leave a per-edge relative error of ~1e-7 on r - 1, random from
-// edge to edge; its effect on lnL is estimated per walker as
-// kMixedErrScale * sqrt(S / 2), S = sum over bins and channels of
-// |dT/d delta_0|^2 + 4 |dT/d delta_1|^2 (the gradient of the bin term T with
-// respect to the edge values).  kMixedErrScale bounds the measured ratio
-// |lnL_mixed - lnL_fp64| / sqrt(S / 2) over tempered walker clouds at SNR
-// 100-1000; walkers whose estimate exceeds kMixedRouteTol are queued and
-// recomputed in FP64, so the mixed result stays within 1e-3 of FP64.
+// edge to edge; its effect on lnL is estimated as kMixedErrScale sqrt(S / 2),
+// S = sum over bins and channels of |dT/d delta_0|^2 + 4 |dT/d delta_1|^2
+// (the gradient of the bin term T with respect to the edge values).
+// kMixedErrScale bounds the measured ratio |lnL_mixed - lnL_fp64| / sqrt(S / 2)
+// over tempered walker clouds at SNR 100-1000.  The estimate is formed per
+// segment (a walker's bins within one wavefront's chunk, or the whole walker
+// in a lane-group mapping) and a segment whose share could push the walker's
+// estimate above the tolerance tol (default kMixedRouteTol) is recomputed in
+// FP64 by the same wavefront right away: a segment of n of the N_b bins is
+// kept in FP32 only if kMixedErrScale^2 8 s < tol^2 n / N_b (s the segment's
+// sum S / 16), so the kept segments of a walker add up to at most tol.
 constexpr double kMixedErrScale = 2.5e-7;
 constexpr double kMixedRouteTol = 9e-4;
 
@@ -286,8 +290,10 @@ struct WorkItem {
   double *lnL;           // [W]
   double *dhhh;          // [W][2] or null
   double *part;          // [W][K][4] per-walker partial sums of the main pass
-  int *rlist;            // [W] walkers queued for FP64 (mixed path)
-  unsigned int *rcount;  // queue length, or null (no routing)
+  unsigned long long *redo;  // running count of segments recomputed in FP64, or null
+  // mixed path: a segment of n bins is recomputed in FP64 unless its error
+  // sum s[3] is below est_lim n / N_b
+  double est_lim;
   int64_t W;
   int64_t offset;        // first walker of this item in its batch
   int32_t E, K, G, model;
@@ -359,21 +365,17 @@ __device__ __forceinline__ void bin_terms(const HetRef &ref, int b, const cx<dou
 // Lane-group mapping: G lanes per walker, lane gl takes edges gl, gl + G, ...
 // The right edge of each bin comes from lane gl + 1 (rotation within the
 // group); the last lane's bin closes one iteration later with lane 0's next
-// edge.  The group's sums are the walker's single slot (main pass) or, for
-// the FP64 recomputation of a queued walker (FIX), its outputs.
-template <typename R, int G, bool DH, bool FIX = false>
-__device__ __forceinline__ void het_walker(const WorkItem &it, int64_t w) {
-  constexpr bool EST = !FIX && sizeof(R) == 4;
+// edge.  Every lane of the wavefront runs the loop (the rotations read other
+// lanes); lanes whose `on` is false evaluate nothing and sum zeros.  Returns
+// the group's sums in every lane of the group.
+template <typename R, int G, bool EST, bool DH>
+__device__ __forceinline__ void group_sums(const WorkItem &it, const WalkerC &c, bool on, double v[4]) {
   const int lane = threadIdx.x & 63;
   const int gl = lane & (G - 1);
-  // with one walker per wavefront its constants are wave-uniform
-  if constexpr (G == 64) w = (int64_t)__builtin_amdgcn_readfirstlane((int)w);
-  const bool active = w < it.W;
-  const WalkerC &c = it.wc[active ? w : 0];
-  const bool valid = active && c.valid;
   const int Nb = it.ref.n_bins, E = Nb + 1;
   const int n_iter = (E + G - 1) / G;
-  double v[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) v[q] = 0.0;
   cx<double> dprev[3];
 #pragma unroll
   for (int ch = 0; ch < 3; ++ch) dprev[ch] = mk<double>(0.0, 0.0);
@@ -383,7 +385,7 @@ __device__ __forceinline__ void het_walker(const WorkItem &it, int64_t w) {
     cx<double> dl[3];
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) dl[ch] = mk<double>(0.0, 0.0);
-    if (valid && j < E) het_edge<R>(it.ref, c, j, dl);
+    if (on && j < E) het_edge<R>(it.ref, c, j, dl);
     cx<double> nb[3], lft[3];
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
@@ -392,7 +394,7 @@ __device__ __forceinline__ void het_walker(const WorkItem &it, int64_t w) {
       lft[ch] = gl < G - 1 ? dl[ch] : dprev[ch];
     }
     const int b = gl < G - 1 ? j : itr * G - 1;
-    if (valid && b >= 0 && b < Nb) bin_terms<EST, DH>(it.ref, b, lft, nb, v);
+    if (on && b >= 0 && b < Nb) bin_terms<EST, DH>(it.ref, b, lft, nb, v);
     if (gl == G - 1) {
 #pragma unroll
       for (int ch = 0; ch < 3; ++ch) dprev[ch] = dl[ch];
@@ -402,24 +404,82 @@ __device__ __forceinline__ void het_walker(const WorkItem &it, int64_t w) {
   for (int off = G / 2; off >= 1; off >>= 1)
 #pragma unroll
     for (int q = 0; q < 4; ++q) v[q] += __shfl_xor(v[q], off, 64);
-  if (active && gl == 0) {
-    if constexpr (FIX) {
-      it.lnL[w] = it.ref.lnL0 + v[0];
-      if (it.dhhh) {
-        it.dhhh[2 * w] = it.ref.dh0 + v[1];
-        it.dhhh[2 * w + 1] = it.ref.hh0 + v[2];
-      }
-    } else {
-      double *o = it.part + w * it.K * 4;
+}
+
+// Main pass of walker w in the lane-group mapping: its single slot.  On the
+// mixed path a walker whose error sum reaches est_lim is recomputed in FP64
+// by its group (the other groups of the wavefront take part in the rotations
+// only).
+template <typename R, int G, bool DH>
+__device__ __forceinline__ void het_walker(const WorkItem &it, int64_t w) {
+  constexpr bool EST = sizeof(R) == 4;
+  const int lane = threadIdx.x & 63;
+  const int gl = lane & (G - 1);
+  // with one walker per wavefront its constants are wave-uniform
+  if constexpr (G == 64) w = (int64_t)__builtin_amdgcn_readfirstlane((int)w);
+  const bool active = w < it.W;
+  const WalkerC &c = it.wc[active ? w : 0];
+  const bool valid = active && c.valid;
+  double v[4];
+  group_sums<R, G, EST, DH>(it, c, valid, v);
+  if constexpr (EST) {
+    const bool redo = valid && !(v[3] < it.est_lim);
+    const uint64_t m = __ballot(redo && gl == 0);
+    if (m) {
+      double u[4];
+      group_sums<double, G, false, DH>(it, c, redo, u);
+      if (redo) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) o[q] = v[q];
+        for (int q = 0; q < 3; ++q) v[q] = u[q];
+        v[3] = 0.0;
+      }
+      if (lane == 0 && it.redo) atomicAdd(it.redo, (unsigned long long)__popcll(m));
     }
   }
+  if (active && gl == 0) {
+    double *o = it.part + w * it.K * 4;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) o[q] = v[q];
+  }
+}
+
+// Bin terms of one lane of a flattened chunk: the lane's edge value, the
+// right neighbour's from lane + 1, and the terms of the bin starting at the
+// lane's edge (zero where `bin` is false).  Run by every lane of the wavefront.
+template <typename R, bool EST, bool DH>
+__device__ __forceinline__ void chunk_terms(const WorkItem &it, const WalkerC &c, int j, bool edge, bool bin,
+                                            double val[4]) {
+  cx<double> dl[3];
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) dl[ch] = mk<double>(0.0, 0.0);
+  if (edge) het_edge<R>(it.ref, c, j, dl);
+  cx<double> nb[3];
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) {
+    nb[ch].re = __shfl_down(dl[ch].re, 1, 64);
+    nb[ch].im = __shfl_down(dl[ch].im, 1, 64);
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) val[q] = 0.0;
+  if (bin) bin_terms<EST, DH>(it.ref, j, dl, nb, val);
+}
+
+// chunk sums of walker vs (wave-uniform) over the lanes whose walker is vs,
+// fixed butterfly order
+template <bool EST, bool DH>
+__device__ __forceinline__ void segment_sums(const double val[4], bool mine, double s[4]) {
+  s[0] = wave_sum(mine ? val[0] : 0.0);
+  s[1] = DH ? wave_sum(mine ? val[1] : 0.0) : 0.0;
+  s[2] = DH ? wave_sum(mine ? val[2] : 0.0) : 0.0;
+  s[3] = EST ? wave_sum(mine ? val[3] : 0.0) : 0.0;
 }
 
 // Flattened mapping, one chunk per wavefront: the tasks of the item's W
 // walkers, E per walker.  For every walker with bins in the chunk, the
 // chunk's sums go to the walker's slot (chunk - first chunk of the walker).
+// On the mixed path, the segments whose error sum reaches their share of
+// est_lim are recomputed in FP64 by the same wavefront before their slots are
+// written.
 template <typename R, bool DH>
 __device__ __forceinline__ void het_chunk(const WorkItem &it, int64_t chunk) {
   constexpr bool EST = sizeof(R) == 4;
@@ -431,38 +491,52 @@ __device__ __forceinline__ void het_chunk(const WorkItem &it, int64_t chunk) {
   const int64_t v0 = t0 / E;
   const int j0 = (int)(t0 - v0 * E);
   const unsigned jl = (unsigned)(j0 + lane);
-  const unsigned qv = jl / (unsigned)E;
+  const unsigned qv = jl / (unsigned)E;  // v - v0, below 64
   const int64_t v = v0 + qv;
   const int j = (int)(jl - qv * (unsigned)E);
   const bool act = v < it.W;
   const WalkerC &c = it.wc[act ? v : 0];
   const bool valid = act && c.valid;
-  cx<double> dl[3];
-#pragma unroll
-  for (int ch = 0; ch < 3; ++ch) dl[ch] = mk<double>(0.0, 0.0);
-  if (valid) het_edge<R>(it.ref, c, j, dl);
-  cx<double> nb[3];
-#pragma unroll
-  for (int ch = 0; ch < 3; ++ch) {
-    nb[ch].re = __shfl_down(dl[ch].re, 1, 64);
-    nb[ch].im = __shfl_down(dl[ch].im, 1, 64);
-  }
-  double val[4] = {0.0, 0.0, 0.0, 0.0};
   const bool is_bin = valid && lane < kChunk && j < E - 1;
-  if (is_bin) bin_terms<EST, DH>(it.ref, j, dl, nb, val);
-  // per-walker sums over the lanes of this chunk, fixed butterfly order
+  double val[4];
+  chunk_terms<R, EST, DH>(it, c, j, valid, is_bin, val);
+  // walkers with a bin in the chunk: v0 unless the chunk starts at its last
+  // edge, up to the walker of lane kChunk - 1
+  const int64_t v_lo = v0 + (j0 == E - 1 ? 1 : 0);
   const int64_t v_hi = min(v0 + (j0 + kChunk - 1) / E, it.W - 1);
-  for (int64_t vs = v0; vs <= v_hi; ++vs) {
-    const bool mine = is_bin && v == vs;
+  uint64_t redo = 0;  // bit vs - v0: walker vs's segment goes to FP64
+  for (int64_t vs = v_lo; vs <= v_hi; ++vs) {
     double s[4];
-    s[0] = wave_sum(mine ? val[0] : 0.0);
-    s[1] = DH ? wave_sum(mine ? val[1] : 0.0) : 0.0;
-    s[2] = DH ? wave_sum(mine ? val[2] : 0.0) : 0.0;
-    s[3] = EST ? wave_sum(mine ? val[3] : 0.0) : 0.0;
+    segment_sums<EST, DH>(val, is_bin && v == vs, s);
+    if constexpr (EST) {
+      // n bins of walker vs here (none for an invalid walker: nothing to redo)
+      const int n = __popcll(__ballot(is_bin && v == vs));
+      if (n > 0 && __builtin_amdgcn_readfirstlane(s[3] * it.ref.n_bins < it.est_lim * n ? 0 : 1)) {
+        redo |= 1ull << (vs - v0);
+        continue;
+      }
+    }
     if (lane == 0) {
       double *o = it.part + (vs * it.K + (chunk - (vs * E) / kChunk)) * 4;
 #pragma unroll
       for (int q = 0; q < 4; ++q) o[q] = s[q];
+    }
+  }
+  if constexpr (EST) {
+    if (redo) {
+      const bool mine = (redo >> qv) & 1ull;
+      chunk_terms<double, false, DH>(it, c, j, valid && mine, is_bin && mine, val);
+      for (int64_t vs = v_lo; vs <= v_hi; ++vs) {
+        if (!((redo >> (vs - v0)) & 1ull)) continue;
+        double s[4];
+        segment_sums<false, DH>(val, is_bin && v == vs, s);
+        if (lane == 0) {
+          double *o = it.part + (vs * it.K + (chunk - (vs * E) / kChunk)) * 4;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) o[q] = s[q];
+        }
+      }
+      if (lane == 0 && it.redo) atomicAdd(it.redo, (unsigned long long)__popcll(redo));
     }
   }
 }
@@ -475,57 +549,12 @@ struct WalkerTile {
   int64_t w_begin;
 };
 
-// Exclusive prefix sums of the per-item queue lengths (total in
-// fix_off[n_items]); adds the number of queued walkers to *routed_total.
-// Run by one whole workgroup once every walker has been finished.
-__device__ __forceinline__ void fix_plan(const WorkItem *__restrict__ items, const WorkItem &one, int n_items,
-                                         int64_t *__restrict__ fix_off,
-                                         unsigned long long *__restrict__ routed_total) {
-  constexpr int kT = kWalkerTile;  // threads of the calling workgroup
-  __shared__ int64_t sh_c[kT];
-  const int per = (n_items + kT - 1) / kT;
-  const int i0 = threadIdx.x * per, i1 = min(n_items, i0 + per);
-  int64_t c = 0;
-  for (int i = i0; i < i1; ++i) {
-    const WorkItem &it = items ? items[i] : one;
-    c += it.rcount ? (int64_t)atomicAdd(it.rcount, 0u) : 0;
-  }
-  sh_c[threadIdx.x] = c;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int64_t acc = 0;
-    const int n_used = min(kT, (n_items + per - 1) / per);
-    for (int k = 0; k < n_used; ++k) {
-      const int64_t x = sh_c[k];
-      sh_c[k] = acc;
-      acc += x;
-    }
-    fix_off[n_items] = acc;
-    if (routed_total) *routed_total += (unsigned long long)acc;
-  }
-  __syncthreads();
-  int64_t acc = sh_c[threadIdx.x];
-  for (int i = i0; i < i1; ++i) {
-    const WorkItem &it = items ? items[i] : one;
-    fix_off[i] = acc;
-    acc += it.rcount ? (int64_t)atomicAdd(it.rcount, 0u) : 0;
-  }
-}
-
 // Per-walker totals of the main pass: the walker's slots are added in slot
-// order, then the outputs are written or (EST, mixed path) the walker is
-// queued for FP64 when its error estimate is above tolerance (one atomic per
-// wavefront).  On the mixed path the last workgroup to finish (done counter,
-// zeroed by the setup kernel; device-scope atomics only) builds the plan of
-// the FP64 recomputation.  One workgroup of kWalkerTile threads per walker
-// tile (items, wtiles) or, for a single item passed by value in `one` with
-// items == nullptr, per kWalkerTile consecutive walkers.
-template <bool EST>
+// order and the outputs written.  One workgroup of kWalkerTile threads per
+// walker tile (items, wtiles) or, for a single item passed by value in `one`
+// with items == nullptr, per kWalkerTile consecutive walkers.
 static __global__ __launch_bounds__(kWalkerTile) void k_het_final(const WorkItem *__restrict__ items, WorkItem one,
-                                                                  const WalkerTile *__restrict__ wtiles, int n_items,
-                                                                  unsigned int *done, int64_t *fix_off,
-                                                                  unsigned long long *routed_total) {
-  const int lane = threadIdx.x & 63;
+                                                                  const WalkerTile *__restrict__ wtiles) {
   int64_t w0 = (int64_t)blockIdx.x * kWalkerTile;
   int ii = 0;
   if (items) {
@@ -535,128 +564,25 @@ static __global__ __launch_bounds__(kWalkerTile) void k_het_final(const WorkItem
   }
   const WorkItem &it = items ? items[ii] : one;
   const int64_t w = w0 + threadIdx.x;
-  const bool act = w < it.W;
-  double s[4] = {0.0, 0.0, 0.0, 0.0};
-  bool valid = false;
-  if (act) {
-    int n_slot = 1;
-    if (it.G == 0) n_slot = (int)((w * it.E + it.E - 2) / kChunk - (w * it.E) / kChunk) + 1;
-    const double *p = it.part + w * it.K * 4;
-    for (int k = 0; k < n_slot; ++k)
+  if (w >= it.W) return;
+  double s[3] = {0.0, 0.0, 0.0};
+  int n_slot = 1;
+  if (it.G == 0) n_slot = (int)((w * it.E + it.E - 2) / kChunk - (w * it.E) / kChunk) + 1;
+  const double *p = it.part + w * it.K * 4;
+  for (int k = 0; k < n_slot; ++k)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) s[q] += p[4 * k + q];
-    valid = it.wc[w].valid;
-  }
-  // s[3] lacks the gradient's factor 4: sqrt(S / 2) = sqrt(8 s[3])
-  const bool route = EST && act && valid && it.rcount && kMixedErrScale * sqrt(8.0 * s[3]) > kMixedRouteTol;
-  if (EST) {
-    const uint64_t m = __ballot(route);
-    if (m) {
-      const int leader = __ffsll((unsigned long long)m) - 1;
-      unsigned int slot0 = 0;
-      if (lane == leader) slot0 = atomicAdd(it.rcount, (unsigned int)__popcll(m));
-      slot0 = __shfl(slot0, leader, 64);
-      if (route) it.rlist[slot0 + __popcll(m & ((1ull << lane) - 1ull))] = (int)w;
-    }
-  }
-  if (act && !route) {
-    it.lnL[w] = valid ? it.ref.lnL0 + s[0] : -INFINITY;
-    if (it.dhhh) {
-      it.dhhh[2 * w] = valid ? it.ref.dh0 + s[1] : 0.0;
-      it.dhhh[2 * w + 1] = valid ? it.ref.hh0 + s[2] : 0.0;
-    }
-  }
-  if (EST) {
-    __shared__ int s_last;
-    __syncthreads();
-    if (threadIdx.x == 0) s_last = atomicAdd(done, 1u) == gridDim.x - 1;
-    __syncthreads();
-    if (s_last) fix_plan(items, one, n_items, fix_off, routed_total);
+    for (int q = 0; q < 3; ++q) s[q] += p[4 * k + q];
+  const bool valid = it.wc[w].valid;
+  it.lnL[w] = valid ? it.ref.lnL0 + s[0] : -INFINITY;
+  if (it.dhhh) {
+    it.dhhh[2 * w] = valid ? it.ref.dh0 + s[1] : 0.0;
+    it.dhhh[2 * w + 1] = valid ? it.ref.hh0 + s[2] : 0.0;
   }
 }
 
-// FP64 recomputation of the queued walkers, one workgroup per walker: its
-// kBlock lanes take kBlock edges at a time (one pass for up to 256 edges), so
-// a queued walker costs about one edge evaluation of latency; the bins' sums
-// are combined through LDS in a fixed order.  Workgroups loop over the queue
-// (its total is fix_off[n_items]) and all of them reach the end.
-template <bool DH>
-__global__ __launch_bounds__(kBlock) void k_het_fix(const WorkItem *__restrict__ items, WorkItem one, int n_items,
-                                                    const int64_t *__restrict__ fix_off) {
-  __shared__ double sh_edge[kWaves][3][2];  // first edge value of each wavefront
-  __shared__ double sh_sum[4][kWaves];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t total = fix_off[n_items];
-  for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
-    int lo = 0;
-    if (items) {
-      int hi = n_items - 1;  // last item whose first queue entry is <= g
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (fix_off[mid] <= g) lo = mid;
-        else hi = mid - 1;
-      }
-    }
-    const WorkItem &it = items ? items[lo] : one;
-    const int64_t w = it.rlist[g - fix_off[lo]];
-    const WalkerC &c = it.wc[w];
-    const int E = it.E;
-    double v[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int j0 = 0; j0 < E - 1; j0 += kBlock - 1) {
-      // edges j0 .. j0 + 255; bins j0 .. j0 + 254 (the last lane only lends
-      // its edge to the bin before it)
-      const int j = j0 + threadIdx.x;
-      cx<double> dl[3];
-#pragma unroll
-      for (int ch = 0; ch < 3; ++ch) dl[ch] = mk<double>(0.0, 0.0);
-      if (j < E) het_edge<double>(it.ref, c, j, dl);
-      if (lane == 0)
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-          sh_edge[wave][ch][0] = dl[ch].re;
-          sh_edge[wave][ch][1] = dl[ch].im;
-        }
-      __syncthreads();
-      cx<double> nb[3];
-#pragma unroll
-      for (int ch = 0; ch < 3; ++ch) {
-        nb[ch].re = __shfl_down(dl[ch].re, 1, 64);
-        nb[ch].im = __shfl_down(dl[ch].im, 1, 64);
-        if (lane == 63 && wave + 1 < kWaves) {
-          nb[ch].re = sh_edge[wave + 1][ch][0];
-          nb[ch].im = sh_edge[wave + 1][ch][1];
-        }
-      }
-      if (threadIdx.x < kBlock - 1 && j < E - 1) bin_terms<false, DH>(it.ref, j, dl, nb, v);
-      __syncthreads();
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const double t = wave_sum(v[q]);
-      if (lane == 0) sh_sum[q][wave] = t;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double s[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) s[q] = sh_sum[q][0] + sh_sum[q][1] + sh_sum[q][2] + sh_sum[q][3];
-      it.lnL[w] = it.ref.lnL0 + s[0];
-      if (it.dhhh) {
-        it.dhhh[2 * w] = it.ref.dh0 + s[1];
-        it.dhhh[2 * w + 1] = it.ref.hh0 + s[2];
-      }
-    }
-    __syncthreads();
-  }
-}
-
-// single-item path: walker constants and cleared queue
-static __global__ __launch_bounds__(128) void k_setup_one(WorkItem one, unsigned int *done) {
+// single-item path: walker constants
+static __global__ __launch_bounds__(128) void k_setup_one(WorkItem one) {
   const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (w == 0) {
-    if (one.rcount) *one.rcount = 0u;
-    if (done) *done = 0u;
-  }
   if (w < one.W) walker_setup(one.theta + w * 11, one.model, one.ref.modes, one.wc[w]);
 }
 
@@ -670,10 +596,6 @@ template <typename R, bool DH>
 __global__ __launch_bounds__(kBlock, 2) void k_het_flat(WorkItem one, int64_t n_chunks) {
   const int64_t c = (int64_t)blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (c < n_chunks) het_chunk<R, DH>(one, c);
-}
-
-static __global__ void k_zero_u32(unsigned int *p, int n) {
-  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
 }
 
 // ---------------------------------------------------------------- a8: full grid

@@ -142,13 +142,20 @@ extern "C" mbh_status mbh_create(int device, size_t hbm_budget_bytes, mbh_ctx **
   c->budget = hbm_budget_bytes;
   c->n_cu = prop.multiProcessorCount;
   c->arch = prop.gcnArchName;
+  c->mixed_tol = kMixedRouteTol;
   *out = c;
   return MBH_OK;
 }
 
+void ctx_retain(mbh_ctx *ctx) { ctx->refs.fetch_add(1); }
+
+void ctx_release(mbh_ctx *ctx) {
+  if (ctx->refs.fetch_sub(1) == 1) delete ctx;
+}
+
 extern "C" mbh_status mbh_destroy(mbh_ctx *ctx) {
   if (!ctx) return MBH_OK;
-  delete ctx;
+  ctx_release(ctx);
   return MBH_OK;
 }
 
@@ -177,6 +184,7 @@ extern "C" mbh_status mbh_data_create(mbh_ctx *ctx, int n_chan, int64_t n_freq, 
   HIP_TRY(hipSetDevice(ctx->device));
   mbh_data *d = new mbh_data();
   d->ctx = ctx;
+  d->hold.set(ctx);
   d->n_chan = n_chan;
   d->n_f = n_freq;
   d->f0 = f0;
@@ -225,6 +233,7 @@ extern "C" mbh_status mbh_data_release(mbh_data *d) {
   ctx_free(d->ctx, d->dd_dev, sizeof(double));
   if (d->ready) (void)hipEventDestroy(d->ready);
   delete d;
+  (void)hipGetLastError();  // teardown errors are not left for the next call to find
   return MBH_OK;
 }
 
@@ -311,6 +320,7 @@ extern "C" mbh_status mbh_ref_release(mbh_ref *r) {
   (void)hipDeviceSynchronize();
   release_ref_dev(r);
   delete r;
+  (void)hipGetLastError();  // teardown errors are not left for the next call to find
   return MBH_OK;
 }
 
@@ -388,6 +398,7 @@ extern "C" mbh_status mbh_build_reference_coeffs(mbh_ctx *ctx, const mbh_data *d
 
   mbh_ref *r = new mbh_ref();
   r->ctx = ctx;
+  r->hold.set(ctx);
   r->model = model;
   r->modes = model == MBH_MODEL_IMR ? modes : 0u;
   r->n_chan = C;
@@ -569,8 +580,13 @@ int lanes_lookup(const mbh_ctx *ctx, int n_bins, int n_modes, int prec) {
   return default_lanes(n_bins, n_modes);
 }
 
+// FP64-recomputation threshold of the mixed path for a tolerance tol on the
+// estimated error of a walker's lnL: the walker's error sum may reach
+// tol^2 / (8 kMixedErrScale^2), shared among its segments by bin count
+void set_error_limits(WorkItem &it, double tol) { it.est_lim = tol * tol / (8.0 * kMixedErrScale * kMixedErrScale); }
+
 // a work item for reference r with mapping G; buffers are set by the caller
-WorkItem make_item(const mbh_ref *r, int G) {
+WorkItem make_item(const mbh_ctx *ctx, const mbh_ref *r, int G) {
   WorkItem it;
   std::memset(&it, 0, sizeof(it));
   it.ref = ref_view(r);
@@ -578,6 +594,12 @@ WorkItem make_item(const mbh_ref *r, int G) {
   it.K = flat_slots(it.E);
   it.G = G;
   it.model = r->model;
+  double tol;
+  {
+    std::lock_guard<std::mutex> g(ctx->mu);
+    tol = ctx->mixed_tol;
+  }
+  set_error_limits(it, tol);
   return it;
 }
 
@@ -613,27 +635,12 @@ static void launch_main(int prec, bool dh, const WorkItem &it, hipStream_t st) {
   }
 }
 
-// Totals of the main pass and, for the mixed path, the FP64 recomputation of
-// the queued walkers (k_het_final, which also plans the recomputation, then
-// k_het_fix over the largest possible queue, max_fix walkers).  Batches pass
-// their walker tiles (n_wtiles of them); a single item passes it by value
-// with items == nullptr.  done: the totals grid's counter (zero before the
-// launch); fix_off: n_items + 1 entries; routed: running total or null.
-void launch_finish(const mbh_ctx *ctx, int prec, bool dh, const WorkItem *items, const WorkItem &one,
-                   const WalkerTile *wtiles, int64_t n_wtiles, int n_items, int64_t max_fix, unsigned *done,
-                   int64_t *fix_off, unsigned long long *routed, hipStream_t st) {
+// Per-walker totals of the main pass.  Batches pass their walker tiles
+// (n_wtiles of them); a single item passes it by value with items == nullptr.
+void launch_finish(const WorkItem *items, const WorkItem &one, const WalkerTile *wtiles, int64_t n_wtiles,
+                   hipStream_t st) {
   const dim3 fb((unsigned)std::max<int64_t>(1, items ? n_wtiles : (one.W + kWalkerTile - 1) / kWalkerTile));
-  if (prec == MBH_FP64) {
-    hipLaunchKernelGGL(k_het_final<false>, fb, dim3(kWalkerTile), 0, st, items, one, wtiles, n_items,
-                       (unsigned *)nullptr, (int64_t *)nullptr, (unsigned long long *)nullptr);
-    return;
-  }
-  hipLaunchKernelGGL(k_het_final<true>, fb, dim3(kWalkerTile), 0, st, items, one, wtiles, n_items, done, fix_off,
-                     routed);
-  // one workgroup per queued walker, looping: at most two per compute unit
-  const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(max_fix, 2 * ctx->n_cu));
-  if (dh) hipLaunchKernelGGL(k_het_fix<true>, dim3(nb), dim3(kBlock), 0, st, items, one, n_items, (const int64_t *)fix_off);
-  else hipLaunchKernelGGL(k_het_fix<false>, dim3(nb), dim3(kBlock), 0, st, items, one, n_items, (const int64_t *)fix_off);
+  hipLaunchKernelGGL(k_het_final, fb, dim3(kWalkerTile), 0, st, items, one, wtiles);
 }
 
 extern "C" mbh_status mbh_loglike_heterodyned(mbh_ctx *ctx, const mbh_ref *ref, const double *theta_dev,
@@ -646,7 +653,7 @@ extern "C" mbh_status mbh_loglike_heterodyned(mbh_ctx *ctx, const mbh_ref *ref, 
   HIP_TRY(hipSetDevice(ctx->device));
   Scratch sc(ctx, st);
   const int G = lanes_lookup(ctx, ref->n_bins, popcount_modes(ref->modes ? ref->modes : 1u), prec);
-  WorkItem it = make_item(ref, G);
+  WorkItem it = make_item(ctx, ref, G);
   it.theta = theta_dev;
   it.lnL = lnL_dev;
   it.dhhh = dh_hh_dev;
@@ -654,19 +661,9 @@ extern "C" mbh_status mbh_loglike_heterodyned(mbh_ctx *ctx, const mbh_ref *ref, 
   it.offset = 0;
   MBH_TRY(sc.get(&it.wc, (size_t)W));
   MBH_TRY(sc.get(&it.part, (size_t)W * it.K * 4));
-  const bool mixed = prec == MBH_MIXED;
-  unsigned *done = nullptr;
-  int64_t *fix_off = nullptr;
-  if (mixed) {
-    MBH_TRY(sc.get(&it.rlist, (size_t)W));
-    MBH_TRY(sc.get(&it.rcount, 1));
-    MBH_TRY(sc.get(&done, 1));
-    MBH_TRY(sc.get(&fix_off, 2));
-  }
-  hipLaunchKernelGGL(k_setup_one, dim3((unsigned)((W + 127) / 128)), dim3(128), 0, st, it, done);
-  const bool dh = dh_hh_dev != nullptr;
-  launch_main(prec, dh, it, st);
-  launch_finish(ctx, prec, dh, nullptr, it, nullptr, 0, 1, W, done, fix_off, nullptr, st);
+  hipLaunchKernelGGL(k_setup_one, dim3((unsigned)((W + 127) / 128)), dim3(128), 0, st, it);
+  launch_main(prec, dh_hh_dev != nullptr, it, st);
+  launch_finish(nullptr, it, nullptr, 0, st);
   HIP_TRY(hipGetLastError());
   return MBH_OK;
 }
@@ -733,6 +730,20 @@ extern "C" mbh_status mbh_lanes_for(const mbh_ctx *ctx, int n_bins, int n_modes,
   return MBH_OK;
 }
 
+extern "C" mbh_status mbh_set_mixed_tolerance(mbh_ctx *ctx, double tol) {
+  if (!ctx || !(tol >= 0.0)) return mbh_fail(MBH_EINVAL, "tolerance must be >= 0 (inf allowed)");
+  std::lock_guard<std::mutex> g(ctx->mu);
+  ctx->mixed_tol = tol;
+  return MBH_OK;
+}
+
+extern "C" mbh_status mbh_get_mixed_tolerance(const mbh_ctx *ctx, double *tol_out) {
+  if (!ctx || !tol_out) return mbh_fail(MBH_EINVAL, "null argument");
+  std::lock_guard<std::mutex> g(ctx->mu);
+  *tol_out = ctx->mixed_tol;
+  return MBH_OK;
+}
+
 extern "C" mbh_status mbh_set_lanes(mbh_ctx *ctx, int n_bins, int n_modes, mbh_precision prec, int lanes) {
   if (!ctx || !valid_lanes(lanes)) return mbh_fail(MBH_EINVAL, "lanes must be 0 or a power of two in [1, 64]");
   std::lock_guard<std::mutex> g(ctx->mu);
@@ -754,7 +765,7 @@ extern "C" mbh_status mbh_autotune_heterodyned(mbh_ctx *ctx, const mbh_ref *ref,
   mbh_status rc = MBH_OK;
   {
     Scratch sc(ctx, st);
-    WorkItem it = make_item(ref, 0);
+    WorkItem it = make_item(ctx, ref, 0);
     double *th = nullptr, *lnL = nullptr;
     it.W = W;
     if ((rc = sc.get(&th, (size_t)W * 11)) != MBH_OK || (rc = sc.get(&lnL, (size_t)W)) != MBH_OK ||
@@ -784,7 +795,7 @@ extern "C" mbh_status mbh_autotune_heterodyned(mbh_ctx *ctx, const mbh_ref *ref,
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
     if (hipMemcpyAsync(th, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, st) == hipSuccess) {
-      hipLaunchKernelGGL(k_setup_one, dim3((unsigned)((W + 127) / 128)), dim3(128), 0, st, it, (unsigned *)nullptr);
+      hipLaunchKernelGGL(k_setup_one, dim3((unsigned)((W + 127) / 128)), dim3(128), 0, st, it);
       for (int G : {0, 16, 32, 64}) {
         it.G = G;
         launch_main(prec, false, it, st);  // warm-up

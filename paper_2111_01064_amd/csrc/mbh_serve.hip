@@ -24,10 +24,9 @@ using namespace mbh;
 HetRef ref_view(const mbh_ref *r);
 int lanes_lookup(const mbh_ctx *ctx, int n_bins, int n_modes, int prec);
 int popcount_modes(uint32_t m);
-WorkItem make_item(const mbh_ref *r, int G);
-void launch_finish(const mbh_ctx *ctx, int prec, bool dh, const WorkItem *items, const WorkItem &one,
-                   const WalkerTile *wtiles, int64_t n_wtiles, int n_items, int64_t max_fix, unsigned *done,
-                   int64_t *fix_off, unsigned long long *routed, hipStream_t st);
+WorkItem make_item(const mbh_ctx *ctx, const mbh_ref *r, int G);
+void launch_finish(const WorkItem *items, const WorkItem &one, const WalkerTile *wtiles, int64_t n_wtiles,
+                   hipStream_t st);
 
 // walker tiles of one item (kWalkerTile walkers each)
 static void append_wtiles(std::vector<WalkerTile> &wt, int item, int64_t W) {
@@ -116,21 +115,14 @@ static void launch_group(const TileGroup &g, const WorkItem *items, const WorkTi
   }
 }
 
-// Counters of one work list (zero at creation): [0..1] running total of the
-// walkers recomputed in FP64 (64-bit), [2] workgroups of the finishing grid
-// that have finished (cleared by the setup kernel of every launch).
-constexpr int kCounterWords = 4;
-
-// setup (a1), one grid per mapping group, the per-walker totals and, for the
-// mixed path, the FP64 recomputation of the walkers the totals queued; the
-// stage mask selects 1 setup, 2 main pass, 4 totals and recomputation
-static void launch_work(const mbh_ctx *ctx, int prec, bool dh, int64_t n_wtiles, int n_items, int64_t total,
-                        const std::vector<TileGroup> &groups, const WalkerTile *wtiles, const WorkItem *items,
-                        const WorkTile *tiles, unsigned *counters, int64_t *fix_off, hipStream_t st,
+// setup (a1), one grid per mapping group (main pass, with the mixed path's
+// FP64 recomputation inside), and the per-walker totals; the stage mask
+// selects 1 setup, 2 main pass, 4 totals
+static void launch_work(int prec, bool dh, int64_t n_wtiles, const std::vector<TileGroup> &groups,
+                        const WalkerTile *wtiles, const WorkItem *items, const WorkTile *tiles, hipStream_t st,
                         int stages = 7) {
-  unsigned *done = counters + 2;
   const dim3 nw((unsigned)std::max<int64_t>(1, n_wtiles));
-  if (stages & 1) hipLaunchKernelGGL(k_setup_work, nw, dim3(kWalkerTile), 0, st, items, wtiles, done);
+  if (stages & 1) hipLaunchKernelGGL(k_setup_work, nw, dim3(kWalkerTile), 0, st, items, wtiles);
   for (const TileGroup &g : groups) {
     if (!(stages & 2)) break;
     if (prec == MBH_FP64) {
@@ -144,20 +136,20 @@ static void launch_work(const mbh_ctx *ctx, int prec, bool dh, int64_t n_wtiles,
   if (!(stages & 4)) return;
   WorkItem none;
   std::memset(&none, 0, sizeof(none));
-  launch_finish(ctx, prec, dh, items, none, wtiles, n_wtiles, n_items, total, done, fix_off,
-                (unsigned long long *)counters, st);
+  launch_finish(items, none, wtiles, n_wtiles, st);
 }
 
 // ---------------------------------------------------------------- batch
 struct mbh_batch {
   mbh_ctx *ctx = nullptr;
+  CtxHold hold;
   int prec = 0;
   bool dh = false;
   WorkItem *items = nullptr;
   WorkTile *tiles = nullptr;
   WalkerTile *wtiles = nullptr;
   int64_t n_wtiles = 0;
-  unsigned *counters = nullptr;
+  unsigned long long *redo = nullptr;  // segments recomputed in FP64 (mixed), all launches
   std::vector<std::pair<void *, size_t>> allocs;
   std::vector<TileGroup> groups;
   hipGraph_t graph = nullptr;
@@ -206,23 +198,18 @@ extern "C" mbh_status mbh_batch_create(mbh_ctx *ctx, int n, const mbh_ref *const
   HIP_TRY(hipSetDevice(ctx->device));
   mbh_batch *b = new mbh_batch();
   b->ctx = ctx;
+  b->hold.set(ctx);
   b->prec = prec;
   b->dh = dh;
   auto fail = [&](mbh_status s) {
     batch_free(b);
     return s;
   };
-  const bool mixed = prec == MBH_MIXED;
   WalkerC *wc = nullptr;
   double *part = nullptr;
-  int *rlist = nullptr;
-  unsigned *rcount = nullptr;
-  int64_t *fix_off = nullptr;
   mbh_status s;
   if ((s = batch_alloc(b, &wc, (size_t)total)) != MBH_OK || (s = batch_alloc(b, &part, (size_t)total * Kmax * 4)) != MBH_OK ||
-      (mixed && (s = batch_alloc(b, &rlist, (size_t)total)) != MBH_OK) ||
-      (mixed && (s = batch_alloc(b, &rcount, (size_t)n)) != MBH_OK) ||
-      (s = batch_alloc(b, &fix_off, (size_t)n + 1)) != MBH_OK || (s = batch_alloc(b, &b->counters, kCounterWords)) != MBH_OK)
+      (s = batch_alloc(b, &b->redo, 1)) != MBH_OK)
     return fail(s);
   std::vector<WorkItem> items(n);
   std::vector<WorkTile> tiles;
@@ -231,14 +218,13 @@ extern "C" mbh_status mbh_batch_create(mbh_ctx *ctx, int n, const mbh_ref *const
   int64_t off = 0;
   for (int i = 0; i < n; ++i) {
     WorkItem &it = items[i];
-    it = make_item(refs[i], item_lanes(ctx, refs[i], prec));
+    it = make_item(ctx, refs[i], item_lanes(ctx, refs[i], prec));
     it.theta = theta_dev[i];
     it.wc = wc + off;
     it.lnL = lnL_dev[i];
     it.dhhh = dh_hh_dev ? dh_hh_dev[i] : nullptr;
     it.part = part + off * Kmax * 4;
-    it.rlist = mixed ? rlist + off : nullptr;
-    it.rcount = mixed ? rcount + i : nullptr;
+    it.redo = b->redo;
     it.W = W[i];
     it.offset = off;
     append_tiles(tiles, cost, i, refs[i], it.G, W[i]);
@@ -251,9 +237,8 @@ extern "C" mbh_status mbh_batch_create(mbh_ctx *ctx, int n, const mbh_ref *const
       (s = batch_alloc(b, &b->wtiles, wtiles.size())) != MBH_OK)
     return fail(s);
   b->n_wtiles = (int64_t)wtiles.size();
-  std::vector<unsigned> zero(std::max(n, kCounterWords), 0u);
-  if ((mixed && hipMemcpy(rcount, zero.data(), n * sizeof(unsigned), hipMemcpyHostToDevice) != hipSuccess) ||
-      hipMemcpy(b->counters, zero.data(), kCounterWords * sizeof(unsigned), hipMemcpyHostToDevice) != hipSuccess ||
+  const unsigned long long zero = 0ull;
+  if (hipMemcpy(b->redo, &zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(b->items, items.data(), n * sizeof(WorkItem), hipMemcpyHostToDevice) != hipSuccess ||
       (!tiles.empty() && hipMemcpy(b->tiles, tiles.data(), tiles.size() * sizeof(WorkTile), hipMemcpyHostToDevice) != hipSuccess) ||
       (!wtiles.empty() && hipMemcpy(b->wtiles, wtiles.data(), wtiles.size() * sizeof(WalkerTile), hipMemcpyHostToDevice) != hipSuccess))
@@ -263,16 +248,14 @@ extern "C" mbh_status mbh_batch_create(mbh_ctx *ctx, int n, const mbh_ref *const
   if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return fail(mbh_fail(MBH_EDEVICE, "stream"));
   hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    launch_work(ctx, prec, dh, b->n_wtiles, n, total, b->groups, b->wtiles, b->items, b->tiles, b->counters, fix_off,
-                cs);
+    launch_work(prec, dh, b->n_wtiles, b->groups, b->wtiles, b->items, b->tiles, cs);
     e = hipStreamEndCapture(cs, &b->graph);
   }
   if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
   for (int k = 0; k < 3 && e == hipSuccess; ++k) {
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) break;
-    launch_work(ctx, prec, dh, b->n_wtiles, n, total, b->groups, b->wtiles, b->items, b->tiles, b->counters, fix_off,
-                cs, 1 << k);
+    launch_work(prec, dh, b->n_wtiles, b->groups, b->wtiles, b->items, b->tiles, cs, 1 << k);
     e = hipStreamEndCapture(cs, &b->sgraph[k]);
     if (e == hipSuccess) e = hipGraphInstantiate(&b->sexec[k], b->sgraph[k], nullptr, nullptr, 0);
   }
@@ -300,7 +283,7 @@ extern "C" mbh_status mbh_batch_routed(const mbh_batch *b, uint64_t *routed_out)
   if (!b || !routed_out) return mbh_fail(MBH_EINVAL, "null argument");
   HIP_TRY(hipSetDevice(b->ctx->device));
   unsigned long long v = 0;
-  HIP_TRY(hipMemcpy(&v, b->counters, sizeof(v), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(&v, b->redo, sizeof(v), hipMemcpyDeviceToHost));
   *routed_out = v;
   return MBH_OK;
 }
@@ -310,6 +293,7 @@ extern "C" mbh_status mbh_batch_release(mbh_batch *b) {
   (void)hipSetDevice(b->ctx->device);
   (void)hipDeviceSynchronize();
   batch_free(b);
+  (void)hipGetLastError();  // teardown errors are not left for the next call to find
   return MBH_OK;
 }
 
@@ -341,11 +325,6 @@ struct Slot {
   WorkTile *tiles_d = nullptr;
   WalkerTile *wtiles_d = nullptr;
   int64_t n_wtiles = 0;
-  unsigned *counters_d = nullptr;  // kCounterWords
-  unsigned *rcount_d = nullptr;    // [max_items]
-  int64_t *fix_off_d = nullptr;    // [max_items + 1]
-  int *rlist_d = nullptr;          // [cap]
-
   double *part_d = nullptr;        // [cap][Kmax][4]
   WalkerC *wc_d = nullptr;
   std::vector<std::pair<std::shared_ptr<Request>, int64_t>> members;  // request, first walker in the slot
@@ -357,6 +336,7 @@ struct Slot {
 
 struct mbh_server {
   mbh_ctx *ctx = nullptr;
+  CtxHold hold;
   std::vector<const mbh_ref *> refs;
   mbh_server_config cfg{};
   int64_t cap_walkers = 0;  // per slot
@@ -399,7 +379,6 @@ static bool server_pack(mbh_server *s, Slot &sl) {
   sl.walkers = 0;
   int n_items = 0;
   int64_t n_tiles = 0;
-  const bool mixed = s->cfg.prec == MBH_MIXED;
   std::vector<WorkTile> tiles;
   std::vector<WalkerTile> wtiles;
   std::vector<double> cost;
@@ -410,12 +389,10 @@ static bool server_pack(mbh_server *s, Slot &sl) {
     const int64_t nt = tiles_of(G, r->W, ref->n_bins + 1);
     if (sl.walkers + r->W > s->cap_walkers || n_items + 1 > s->max_items || n_tiles + nt > s->max_tiles) break;
     WorkItem &it = sl.items_h[n_items];
-    it = make_item(ref, G);
+    it = make_item(s->ctx, ref, G);
     it.theta = sl.theta_d + sl.walkers * 11;
     it.wc = sl.wc_d + sl.walkers;
     it.part = sl.part_d + sl.walkers * s->Kmax * 4;
-    it.rlist = mixed ? sl.rlist_d + sl.walkers : nullptr;
-    it.rcount = mixed ? sl.rcount_d + n_items : nullptr;
     it.W = r->W;
     it.offset = sl.walkers;
     std::memcpy(sl.theta_h + sl.walkers * 11, r->theta.data(), r->W * 11 * sizeof(double));
@@ -450,8 +427,7 @@ static bool server_launch(mbh_server *s, Slot &sl) {
             hipMemcpyAsync(sl.tiles_d, sl.tiles_h, h.n_tiles * sizeof(WorkTile), hipMemcpyHostToDevice, st) == hipSuccess &&
             hipMemcpyAsync(sl.wtiles_d, sl.wtiles_h, sl.n_wtiles * sizeof(WalkerTile), hipMemcpyHostToDevice, st) == hipSuccess;
   if (!ok) return false;
-  launch_work(s->ctx, s->cfg.prec, true, sl.n_wtiles, h.n_items, sl.walkers, sl.groups, sl.wtiles_d, sl.items_d,
-              sl.tiles_d, sl.counters_d, sl.fix_off_d, st);
+  launch_work(s->cfg.prec, true, sl.n_wtiles, sl.groups, sl.wtiles_d, sl.items_d, sl.tiles_d, st);
   ok = hipGetLastError() == hipSuccess &&
        hipMemcpyAsync(sl.res_h, sl.res_d, sl.walkers * 3 * sizeof(double), hipMemcpyDeviceToHost, st) == hipSuccess &&
        hipEventRecord(sl.ev, st) == hipSuccess;
@@ -537,14 +513,14 @@ extern "C" mbh_status mbh_server_create(mbh_ctx *ctx, int n_refs, const mbh_ref 
   HIP_TRY(hipSetDevice(ctx->device));
   mbh_server *s = new mbh_server();
   s->ctx = ctx;
+  s->hold.set(ctx);
   s->refs.assign(refs, refs + n_refs);
   s->cfg = *cfg;
   for (int i = 0; i < n_refs; ++i) {
     s->Kmax = std::max(s->Kmax, flat_slots(refs[i]->n_bins + 1));
   }
   // inputs, outputs, walker constants and the per-walker partial sums
-  s->bytes_per_walker = 11 * sizeof(double) + 3 * sizeof(double) + sizeof(WalkerC) +
-                        4 * sizeof(double) * s->Kmax + sizeof(int);
+  s->bytes_per_walker = 11 * sizeof(double) + 3 * sizeof(double) + sizeof(WalkerC) + 4 * sizeof(double) * s->Kmax;
   int64_t cap = cfg->max_batch_walkers;
   if (cfg->hbm_budget_bytes) {
     int64_t by_budget = (int64_t)(cfg->hbm_budget_bytes / (cfg->max_inflight * s->bytes_per_walker));
@@ -589,21 +565,10 @@ extern "C" mbh_status mbh_server_create(mbh_ctx *ctx, int n_refs, const mbh_ref 
         (st = dalloc((void **)&sl.wtiles_d, (cap / kWalkerTile + s->max_items + 1) * sizeof(WalkerTile))) != MBH_OK ||
         (st = dalloc((void **)&sl.items_d, s->max_items * sizeof(WorkItem))) != MBH_OK ||
         (st = dalloc((void **)&sl.tiles_d, s->max_tiles * sizeof(WorkTile))) != MBH_OK ||
-        (st = dalloc((void **)&sl.counters_d, kCounterWords * sizeof(unsigned))) != MBH_OK ||
-        (st = dalloc((void **)&sl.rcount_d, s->max_items * sizeof(unsigned))) != MBH_OK ||
-        (st = dalloc((void **)&sl.fix_off_d, (s->max_items + 1) * sizeof(int64_t))) != MBH_OK ||
-        (st = dalloc((void **)&sl.rlist_d, cap * sizeof(int))) != MBH_OK ||
-
         (st = dalloc((void **)&sl.part_d, cap * s->Kmax * 4 * sizeof(double))) != MBH_OK ||
-
         (st = dalloc((void **)&sl.wc_d, cap * sizeof(WalkerC))) != MBH_OK) {
       server_free(s);
       return st;
-    }
-    std::vector<unsigned> zero(kCounterWords, 0u);
-    if (hipMemcpy(sl.counters_d, zero.data(), kCounterWords * sizeof(unsigned), hipMemcpyHostToDevice) != hipSuccess) {
-      server_free(s);
-      return mbh_fail(MBH_EDEVICE, "counter init");
     }
   }
   s->thr = std::thread(server_loop, s);
@@ -671,5 +636,6 @@ extern "C" mbh_status mbh_server_destroy(mbh_server *s) {
   if (s->thr.joinable()) s->thr.join();
   (void)hipSetDevice(s->ctx->device);
   server_free(s);
+  (void)hipGetLastError();  // teardown errors are not left for the next call to find
   return MBH_OK;
 }

@@ -25,16 +25,12 @@ struct WorkTile {
   int64_t begin;  // first chunk (G = 0) or first walker (G > 0) of the tile
 };
 
-// a1 for every walker of the batch, one workgroup per walker tile; also
-// clears each item's FP64 queue and the totals grid's counter
+// a1 for every walker of the batch, one workgroup per walker tile
 static __global__ __launch_bounds__(kWalkerTile) void k_setup_work(const WorkItem *__restrict__ items,
-                                                                   const WalkerTile *__restrict__ wtiles,
-                                                                   unsigned int *__restrict__ done) {
+                                                                   const WalkerTile *__restrict__ wtiles) {
   const WalkerTile tl = wtiles[blockIdx.x];
   const WorkItem &it = items[tl.item];
   const int64_t w = tl.w_begin + threadIdx.x;
-  if (blockIdx.x == 0 && threadIdx.x == 0) *done = 0u;
-  if (w == 0 && it.rcount) *it.rcount = 0u;
   if (w < it.W) walker_setup(it.theta + w * 11, it.model, it.ref.modes, it.wc[w]);
 }
 

@@ -82,6 +82,8 @@ _SIGS = {
     "mbh_autotune_heterodyned": [_vp, _vp, _vp, _i64, _i32, ct.POINTER(ct.c_int)],
     "mbh_lanes_for": [_vp, _i32, _i32, _i32, ct.POINTER(ct.c_int)],
     "mbh_set_lanes": [_vp, _i32, _i32, _i32, _i32],
+    "mbh_set_mixed_tolerance": [_vp, _d],
+    "mbh_get_mixed_tolerance": [_vp, _dp],
     "mbh_autotune_save": [_vp, ct.c_char_p],
     "mbh_autotune_load": [_vp, ct.c_char_p],
     "mbh_server_create": [_vp, _i32, _pp, ct.POINTER(ServerConfig), _pp],
@@ -274,6 +276,17 @@ def set_lanes(ctx: Context, n_bins: int, n_modes: int, prec: int, lanes: int):
     _check(_L.mbh_set_lanes(ctx.h, n_bins, n_modes, prec, lanes), "mbh_set_lanes")
 
 
+def set_mixed_tolerance(ctx: Context, tol: float):
+    """Estimated-error tolerance of the mixed path (0: all FP64, inf: none)."""
+    _check(_L.mbh_set_mixed_tolerance(ctx.h, float(tol)), "mbh_set_mixed_tolerance")
+
+
+def mixed_tolerance(ctx: Context) -> float:
+    v = ct.c_double()
+    _check(_L.mbh_get_mixed_tolerance(ctx.h, ct.byref(v)), "mbh_get_mixed_tolerance")
+    return v.value
+
+
 def autotune_heterodyned(ctx: Context, ref: Reference, walkers, prec: int) -> int:
     """Time every mapping on ``walkers`` (a [W, 11] float64 CUDA tensor of
     representative walkers) or, if ``walkers`` is an int W, on W copies of a
@@ -297,7 +310,7 @@ def autotune_load(ctx: Context, path: str):
 
 
 class Batch:
-    """mbh_batch_*: one persistent, graph-captured launch over many items."""
+    """mbh_batch_*: one graph-captured launch over many items."""
 
     def __init__(self, ctx: Context, refs, thetas, lnLs, dh_hhs=None, prec: int = FP64):
         n = len(refs)
@@ -324,6 +337,7 @@ class Batch:
         _check(_L.mbh_batch_launch_stage(self.h, stage, _stream(stream)), "mbh_batch_launch_stage")
 
     def routed(self) -> int:
+        """Walker segments recomputed in FP64 so far (mixed path)."""
         v = ct.c_uint64()
         _check(_L.mbh_batch_routed(self.h, ct.byref(v)), "mbh_batch_routed")
         return v.value
