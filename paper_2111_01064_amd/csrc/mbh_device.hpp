@@ -54,6 +54,15 @@ constexpr int kNumModes = 6;
 // mode order (2,2) (3,3) (4,4) (2,1) (3,2) (4,3)
 __device__ __constant__ const int kModeM[6] = {2, 3, 4, 1, 2, 3};
 __device__ __constant__ const int kModeVPow[6] = {0, 1, 2, 1, 2, 3};
+// powers of the ratio m / 2 between a mode's frequency argument 2 f / m and
+// f: (2/m)^(1/3), (m/2)^(1/3), m/2, (m/2)^(7/6) (decimal expansions rounded)
+__device__ __constant__ const double kModeP13[6] = {1.0, 0.87358046473629886905, 0.79370052598409973738,
+                                                    1.25992104989487316477, 1.0, 0.87358046473629886905};
+__device__ __constant__ const double kModeM13[6] = {1.0, 1.14471424255333186781, 1.25992104989487316477,
+                                                    0.79370052598409973738, 1.0, 1.14471424255333186781};
+__device__ __constant__ const double kModeHalf[6] = {1.0, 1.5, 2.0, 0.5, 1.0, 1.5};
+__device__ __constant__ const double kModeM76[6] = {1.0, 1.60486979090049442633, 2.24492409661874596287,
+                                                    0.44544935907016965237, 1.0, 1.60486979090049442633};
 
 template <typename R>
 struct cx {
@@ -95,6 +104,10 @@ struct WalkerC {
   double lam_num;             // (f1 - fRD)^2 + fD^2
   double inv_fD;              // 1 / fD
   double tref;
+  // (pi M)^(1/3), (pi M)^(-1/3), AN (pi M)^(-7/6) and sqrt(lam_num): with the
+  // frequency powers of FreqPow they give v, 1/v and the amplitude without a
+  // root or a division per frequency
+  double cpiM, icpiM, AN76, slam;
   double rel[6];              // relative amplitude coefficient of each mode
   // sky: propagation direction and polarisation basis
   double kx, ky, kz, px, py, pz, qx, qy, qz;
@@ -167,6 +180,14 @@ __device__ __forceinline__ double rcp64_nr(double x) {
   double y = (double)__builtin_amdgcn_rcpf((float)x);
   y = y * fma(-x, y, 2.0);
   return y * fma(-x, y, 2.0);
+}
+// FP64 reciprocal square root: FP32 estimate and two Newton steps
+// t <- t (1 + (1 - x t^2) / 2)
+__device__ __forceinline__ double rsq64_nr(double x) {
+  double t = (double)__builtin_amdgcn_rsqf((float)x);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) t = fma(0.5 * t, fma(-x * t, t, 1.0), t);
+  return t;
 }
 __device__ __forceinline__ double cbrt64_nr(double x) {
   double v = (double)__builtin_amdgcn_exp2f(__builtin_amdgcn_logf((float)x) * (1.0f / 3.0f));
@@ -329,6 +350,10 @@ __device__ __forceinline__ void walker_setup(const double *__restrict__ th, int 
   // f_max lies past f1 (the (2,2) amplitude peaks in the merger-ringdown part)
   raw_phase_mr(w, w.fmax, w.ph_max, w.dph_max);
   w.AN = kPi * sqrt(2.0 * eta / 3.0) * M * M / DL * kAmpScale;
+  w.cpiM = cbrt(w.piM);
+  w.icpiM = 1.0 / w.cpiM;
+  w.AN76 = w.AN * (w.icpiM * w.icpiM * w.icpiM) * sqrt(w.icpiM);
+  w.slam = sqrt(w.lam_num);
   w.tref = t[10];
   const double a = 1.0 - 3.0 * eta;
   w.rel[0] = 1.0;
@@ -374,29 +399,53 @@ __device__ __forceinline__ void walker_setup(const double *__restrict__ th, int 
   }
 }
 
+// Powers of a frequency f used by the waveform: f^(1/3), f^(-1/3), 1/f and
+// f^(-7/6), all FP64 (NR-refined estimates, within a few ulp).  The
+// heterodyned pass reads them per bin edge from the reference; the grid
+// kernels evaluate them per frequency.
+struct FreqPow {
+  double f13, fm13, fi, fm76;
+};
+__device__ __forceinline__ FreqPow freq_pows(double f) {
+  FreqPow p;
+  p.f13 = cbrt64_nr(f);
+  p.fm13 = rcp64_nr(p.f13);
+  p.fi = rcp64_nr(f);
+  p.fm76 = p.fi * sqrt(p.fm13);
+  return p;
+}
+// the powers at the frequency argument 2 f / m of mode mi
+__device__ __forceinline__ FreqPow mode_pows(const FreqPow &p, int mi) {
+  return FreqPow{p.f13 * kModeP13[mi], p.fm13 * kModeM13[mi], p.fi * kModeHalf[mi], p.fm76 * kModeM76[mi]};
+}
+
 // (2,2) phase aligned at f_max, its slope, and the amplitude at (2,2)
-// frequency fp; amplitude scaled by v^vpow (v = (pi M fp)^(1/3)).  All FP64:
-// the arctan of the merger-ringdown continuation and the amplitude factor
-// would otherwise carry FP32 roundings of per-walker constants (arctan at
-// f1) into every edge alike, i.e. coherent phase and amplitude shifts.
-__device__ __forceinline__ void wf22(const WalkerC &w, double fp, int vpow, double &ph, double &dph, double &amp) {
-  const double v = cbrt64_nr(w.piM * fp);
-  const double iv = rcp64_nr(v);
-  double lam2 = 1.0;
-  if (fp <= w.f1) {
-    const double iv2 = iv * iv, iv3 = iv2 * iv, iv5 = iv3 * iv2;
-    ph = w.c5 * iv5 + w.c3 * iv3 + w.c2 * iv2;
-    dph = (w.d5 * iv5 + w.d3 * iv3 + w.d2 * iv2) * rcp64_nr(fp);
-  } else {
-    const double x = fp - w.f1, y = fp - w.fRD;
-    const double rden = rcp64_nr(y * y + w.fD * w.fD);
-    ph = w.P1 + w.dP1 * x + kKappa * ((atan(y * w.inv_fD) - w.at1) - w.L1 * x);
-    dph = w.dP1 + kKappa * (w.fD * rden - w.L1);
-    lam2 = w.lam_num * rden;
-  }
+// frequency fp with powers pw; amplitude scaled by v^vpow (v = (pi M fp)^(1/3)).
+// All FP64: the arctan of the merger-ringdown continuation and the amplitude
+// factor would otherwise carry FP32 roundings of per-walker constants
+// (arctan at f1) into every edge alike, i.e. coherent phase and amplitude
+// shifts.  The inspiral and merger-ringdown forms are both evaluated and
+// selected per lane: a wavefront's lanes straddle f1 often, and the
+// straight-line code schedules better than the two branches.
+__device__ __forceinline__ void wf22(const WalkerC &w, double fp, const FreqPow &pw, int vpow, double &ph,
+                                     double &dph, double &amp) {
+  const double v = w.cpiM * pw.f13;
+  const double iv = w.icpiM * pw.fm13;
+  // both branches, selected per lane (no divergent control flow)
+  const double iv2 = iv * iv, iv3 = iv2 * iv, iv5 = iv3 * iv2;
+  const double ph_i = w.c5 * iv5 + w.c3 * iv3 + w.c2 * iv2;
+  const double dph_i = (w.d5 * iv5 + w.d3 * iv3 + w.d2 * iv2) * pw.fi;
+  const double x = fp - w.f1, y = fp - w.fRD;
+  const double t = rsq64_nr(y * y + w.fD * w.fD);
+  const double ph_m = w.P1 + w.dP1 * x + kKappa * ((atan(y * w.inv_fD) - w.at1) - w.L1 * x);
+  const double dph_m = w.dP1 + kKappa * (w.fD * (t * t) - w.L1);
+  const bool insp = fp <= w.f1;
+  ph = insp ? ph_i : ph_m;
+  dph = insp ? dph_i : dph_m;
+  const double lam = insp ? 1.0 : w.slam * t;
   ph = ph - w.ph_max - w.dph_max * (fp - w.fmax);
   dph = dph - w.dph_max;
-  double a = w.AN * (iv * iv * iv) * sqrt(iv * lam2);
+  double a = w.AN76 * pw.fm76 * lam;
   for (int k = 0; k < vpow; ++k) a *= v;
   amp = a;
 }
@@ -444,21 +493,28 @@ __device__ __constant__ const SincCoef32 kSincDev32 = SincCoef32{};
 // sinc series S(y) = sum_{n<=N} c_n y^n and its divided difference
 // S[y1, y2] = (S(y1) - S(y2)) / (y1 - y2) in one downward Horner pass:
 // with P_n(y) = sum_{k>=n} c_k y^(k-n), P_n = c_n + y P_{n+1} and
-// P_n[y1, y2] = P_{n+1}(y1) + y2 P_{n+1}[y1, y2].  N (<= 20) is uniform
-// across the wavefront, so the loop is scalar-controlled.
+// P_n[y1, y2] = P_{n+1}(y1) + y2 P_{n+1}[y1, y2].  The three links run in
+// the same pass (one coefficient load feeds six independent chains).  N
+// (<= 20) is uniform across the wavefront, so the loop is scalar-controlled.
 template <typename R>
-__device__ __forceinline__ void sinc_pair(R y1, R y2, int N, R &s1, R &dd) {
+__device__ __forceinline__ void sinc_pairs3(const R y1[3], const R y2[3], int N, R s1[3], R dd[3]) {
   const R *c;
   if constexpr (sizeof(R) == 8) c = (const R *)kSincDev64.c;
   else c = (const R *)kSincDev32.c;
-  R p = (R)0, d = (R)0;
-#pragma unroll 2
+  R p[3] = {(R)0, (R)0, (R)0}, d[3] = {(R)0, (R)0, (R)0};
   for (int n = N; n >= 0; --n) {
-    d = p + y2 * d;
-    p = c[n] + y1 * p;
+    const R cn = c[n];
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      d[l] = p[l] + y2[l] * d[l];
+      p[l] = cn + y1[l] * p[l];
+    }
   }
-  s1 = p;
-  dd = d;
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    s1[l] = p[l];
+    dd[l] = d[l];
+  }
 }
 
 // Frequency-only response factors for a = pi f L:
@@ -518,43 +574,58 @@ template <typename R>
 __device__ __forceinline__ void response_mode(const WalkerC &w, double kp, double kc, const FreqC &fc, double ca,
                                               double sa, cx<double> T[3]) {
   const double c2a = ca * ca - sa * sa, s2a = 2.0 * sa * ca;
-  // link phase factors z_l = e^{i a k.(p_i + p_j)}: link (0,1) has phase
-  // -a k.p_2, link (1,2) -a k.p_0 (the offsets sum to zero), and z_2 closes
-  cx<double> z[3];
+  // projections of the offsets on k, p and q: spacecraft 0 and 2 directly,
+  // spacecraft 1 from the zero sum; link l runs from l to (l + 1) mod 3, so
+  // its unit vector's projection is a difference of two of them
+  double kd[3], pd[3], qd[3];
   {
     double o[3];
     sc_offset(0, ca, sa, c2a, s2a, o);
-    const double kd0 = w.kx * o[0] + w.ky * o[1] + w.kz * o[2];
+    kd[0] = w.kx * o[0] + w.ky * o[1] + w.kz * o[2];
+    pd[0] = w.px * o[0] + w.py * o[1] + w.pz * o[2];
+    qd[0] = w.qx * o[0] + w.qy * o[1] + w.qz * o[2];
     sc_offset(2, ca, sa, c2a, s2a, o);
-    const double kd2 = w.kx * o[0] + w.ky * o[1] + w.kz * o[2];
+    kd[2] = w.kx * o[0] + w.ky * o[1] + w.kz * o[2];
+    pd[2] = w.px * o[0] + w.py * o[1] + w.pz * o[2];
+    qd[2] = w.qx * o[0] + w.qy * o[1] + w.qz * o[2];
+    kd[1] = -(kd[0] + kd[2]);
+    pd[1] = -(pd[0] + pd[2]);
+    qd[1] = -(qd[0] + qd[2]);
+  }
+  // link phase factors z_l = e^{i a k.(p_i + p_j)}: link (0,1) has phase
+  // -a k.p_2, link (1,2) -a k.p_0, and z_2 closes
+  cx<double> z[3];
+  {
     R s0, c0, s1, c1;
-    Prec<R>::sincos_r((R)(-fc.a * kd2), s0, c0);
-    Prec<R>::sincos_r((R)(-fc.a * kd0), s1, c1);
+    Prec<R>::sincos_r((R)(-fc.a * kd[2]), s0, c0);
+    Prec<R>::sincos_r((R)(-fc.a * kd[0]), s1, c1);
     z[0] = mk<double>((double)c0, (double)s0);
     z[1] = mk<double>((double)c1, (double)s1);
     z[2] = z[0] * z[1];
     z[2].im = -z[2].im;
   }
+  double kn[3];
+  R y1[3], y2[3], s1r[3], ddr[3];
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    const int m = l == 2 ? 0 : l + 1;
+    kn[l] = kd[m] - kd[l];
+    const double am = fc.a * (1.0 - kn[l]), ap = fc.a * (1.0 + kn[l]);
+    y1[l] = (R)(am * am);
+    y2[l] = (R)(ap * ap);
+  }
+  sinc_pairs3<R>(y1, y2, fc.ns, s1r, ddr);
   // sqrt2 A = Cp SAU - i Cm SAV, sqrt6 E = 3 Cp SEU - i Cm SEV, sqrt3 T = -2 i Cm STV
   cx<double> SAU = mk<double>(0, 0), SEU = mk<double>(0, 0), SAV = mk<double>(0, 0), SEV = mk<double>(0, 0),
              STV = mk<double>(0, 0);
 #pragma unroll
   for (int l = 0; l < 3; ++l) {
-    // unit vector of link l from spacecraft l to spacecraft (l + 1) mod 3
-    double oi[3], oj[3];
-    sc_offset(l, ca, sa, c2a, s2a, oi);
-    sc_offset(l == 2 ? 0 : l + 1, ca, sa, c2a, s2a, oj);
-    const double nx = oj[0] - oi[0], ny = oj[1] - oi[1], nz = oj[2] - oi[2];
-    const double kn = w.kx * nx + w.ky * ny + w.kz * nz;
-    const double am = fc.a * (1.0 - kn), ap = fc.a * (1.0 + kn);
-    R s1r, ddr;
-    sinc_pair<R>((R)(am * am), (R)(ap * ap), fc.ns, s1r, ddr);
-    const double np = w.px * nx + w.py * ny + w.pz * nz;
-    const double nq = w.qx * nx + w.qy * ny + w.qz * nz;
+    const int m = l == 2 ? 0 : l + 1;
+    const double np = pd[m] - pd[l], nq = qd[m] - qd[l];
     // n e+ n = np^2 - nq^2, n ex n = 2 np nq
     const cx<double> wl = mk<double>(kp * ((np - nq) * (np + nq)), kc * (2.0 * np * nq));
-    const double delta = -4.0 * fc.a * fc.a * kn * (double)ddr;  // sinc(x_ij) - sinc(x_ji)
-    const double sigma = (double)s1r - 0.5 * delta;             // (sinc(x_ij) + sinc(x_ji)) / 2
+    const double delta = -4.0 * fc.a * fc.a * kn[l] * (double)ddr[l];  // sinc(x_ij) - sinc(x_ji)
+    const double sigma = (double)s1r[l] - 0.5 * delta;                 // (sinc(x_ij) + sinc(x_ji)) / 2
     const cx<double> wz = wl * z[l];
     const cx<double> U = sigma * wz, V = delta * wz;
     if (l == 0) {
@@ -584,8 +655,8 @@ __device__ __forceinline__ void response_mode(const WalkerC &w, double kp, doubl
 // mode phase) is applied in FP64, so FP32 rounding cannot act as a coherent
 // shift of D_L or phi_ref.  Returns true if any mode is inside its support.
 template <typename R>
-__device__ __forceinline__ bool template_point(const WalkerC &w, uint32_t modes, double f, const FreqC &fc,
-                                               double t_obs, cx<double> s[3], double &psi) {
+__device__ __forceinline__ bool template_point(const WalkerC &w, uint32_t modes, double f, const FreqPow &pw,
+                                               const FreqC &fc, double t_obs, cx<double> s[3], double &psi) {
   if (w.model == 1) {  // 0PN chirp, one channel
     double x = w.piMc * f;
     double cx1 = cbrt64_nr(x);
@@ -599,7 +670,7 @@ __device__ __forceinline__ bool template_point(const WalkerC &w, uint32_t modes,
   }
   // carrier: (2,2) phase, t_ref shift, guiding-centre Doppler at t_22, arm phase
   double ph22, dph22, amp22;
-  wf22(w, f, 0, ph22, dph22, amp22);
+  wf22(w, f, pw, 0, ph22, dph22, amp22);
   double t22 = w.tref - dph22 * kInvTwoPi;
   double al22 = reduce_2pi(t22 * (kTwoPi / kYearS));
   double sa22, ca22;
@@ -624,7 +695,7 @@ __device__ __forceinline__ bool template_point(const WalkerC &w, uint32_t modes,
       fm = mk<double>(amp * w.eph[0][0], amp * w.eph[0][1]);
     } else {
       double ph, dph;
-      wf22(w, fp, kModeVPow[mi], ph, dph, amp);
+      wf22(w, fp, mode_pows(pw, mi), kModeVPow[mi], ph, dph, amp);
       amp *= w.rel[mi];
       tlm = w.tref - dph * kInvTwoPi;
       double al = reduce_2pi(tlm * (kTwoPi / kYearS));

@@ -11,9 +11,12 @@ constexpr int kBlock = 256;
 // Everything the heterodyned kernel needs about one reference, as device
 // pointers.  coef is [C][Nb][6] FP64: Re/Im (A0-B0), Re/Im (A1-B1)/dF_b, B0,
 // B1/dF_b, where dF_b = F_{b+1} - F_b.
+// per-edge frequency constants: FreqC's a, Cp, Cm, then FreqPow
+constexpr int kFq = 7;
+
 struct HetRef {
   const double *F;      // [E] bin edges
-  const double *fq;     // [E][3] response factors a, Cp, Cm of each edge
+  const double *fq;     // [E][kFq] response factors a, Cp, Cm and FreqPow of each edge
   const double *psi0;   // [E] carrier phase of h0
   const double *is064;  // [C][E][2] 1/s0
   const double *coef;   // [C][Nb][6]
@@ -112,7 +115,7 @@ static __global__ __launch_bounds__(kBlock) void k_template_grid(const WalkerC *
   cx<double> s[3];
   double psi;
   const int ns = sinc_terms_for<double>(grid_freq(f0, df, n_f - 1));
-  bool any = template_point<double>(w, modes, f, freq_consts<double>(f, ns), t_obs, s, psi);
+  bool any = template_point<double>(w, modes, f, freq_pows(f), freq_consts<double>(f, ns), t_obs, s, psi);
   double sp = 0.0, cp = 1.0;
   if (any) sincos_red<double>(reduce_2pi(psi), sp, cp);
   for (int c = 0; c < n_chan; ++c) {
@@ -139,7 +142,7 @@ static __global__ __launch_bounds__(kBlock) void k_ref_grid(const WalkerC *__res
     double f = grid_freq(f0, df, k);
     cx<double> s[3];
     double psi;
-    bool any = template_point<double>(w, modes, f, freq_consts<double>(f, ns), t_obs, s, psi);
+    bool any = template_point<double>(w, modes, f, freq_pows(f), freq_consts<double>(f, ns), t_obs, s, psi);
     double sp = 0.0, cp = 1.0;
     if (any) sincos_red<double>(reduce_2pi(psi), sp, cp);
     bool nz = false;
@@ -239,12 +242,18 @@ static __global__ __launch_bounds__(64) void k_ref_edges(const WalkerC *__restri
   FreqC fc;
   freq_consts64(F[j], fc.a, fc.Cp, fc.Cm);
   fc.ns = sinc_terms_for<double>(F[E - 1]);
-  fq[3 * j] = fc.a;
-  fq[3 * j + 1] = fc.Cp;
-  fq[3 * j + 2] = fc.Cm;
+  const FreqPow pw = freq_pows(F[j]);
+  double *q = fq + (int64_t)kFq * j;
+  q[0] = fc.a;
+  q[1] = fc.Cp;
+  q[2] = fc.Cm;
+  q[3] = pw.f13;
+  q[4] = pw.fm13;
+  q[5] = pw.fi;
+  q[6] = pw.fm76;
   cx<double> s[3];
   double psi;
-  bool any = template_point<double>(wc[0], modes, F[j], fc, t_obs, s, psi);
+  bool any = template_point<double>(wc[0], modes, F[j], pw, fc, t_obs, s, psi);
   psi0[j] = psi;
   for (int c = 0; c < n_chan; ++c) s0[c * E + j] = any ? make_double2(s[c].re, s[c].im) : make_double2(0.0, 0.0);
 }
@@ -309,8 +318,10 @@ template <typename R>
 __device__ __forceinline__ void het_edge(const HetRef &ref, const WalkerC &c, int j, cx<double> dl[3]) {
   cx<double> s[3];
   double psi;
-  const FreqC fc{ref.fq[3 * j], ref.fq[3 * j + 1], ref.fq[3 * j + 2], sizeof(R) == 8 ? ref.ns64 : ref.ns32};
-  template_point<R>(c, ref.modes, ref.F[j], fc, ref.t_obs, s, psi);
+  const double *q = ref.fq + (int64_t)kFq * j;
+  const FreqC fc{q[0], q[1], q[2], sizeof(R) == 8 ? ref.ns64 : ref.ns32};
+  const FreqPow pw{q[3], q[4], q[5], q[6]};
+  template_point<R>(c, ref.modes, ref.F[j], pw, fc, ref.t_obs, s, psi);
   // the carrier difference enters every channel of the edge at once: FP64
   // in both paths
   const double dpsi = reduce_2pi(psi - ref.psi0[j]);
@@ -663,7 +674,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_full(const typename DataPtrs<R>::
         if (!inr[i]) continue;
         cx<double> s[3];
         double psi;
-        bool any = template_point<R>(c, modes, fq[i], fcs[i], t_obs, s, psi);
+        bool any = template_point<R>(c, modes, fq[i], freq_pows(fq[i]), fcs[i], t_obs, s, psi);
         R sp = (R)0, cp = (R)1;
         if (any) Prec<R>::sincos_r((R)reduce_2pi(psi), sp, cp);
 #pragma unroll

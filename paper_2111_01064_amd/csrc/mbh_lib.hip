@@ -308,7 +308,7 @@ static void release_ref_dev(mbh_ref *r) {
   const int E = r->n_bins + 1;
   ctx_free(c, r->F, E * sizeof(double));
   ctx_free(c, r->psi0, E * sizeof(double));
-  ctx_free(c, r->fq, (size_t)E * 3 * sizeof(double));
+  ctx_free(c, r->fq, (size_t)E * kFq * sizeof(double));
   ctx_free(c, r->is064, (size_t)r->n_chan * E * 2 * sizeof(double));
   ctx_free(c, r->coef, (size_t)r->n_chan * r->n_bins * 6 * sizeof(double));
   r->F = r->psi0 = r->fq = r->is064 = r->coef = nullptr;
@@ -416,7 +416,7 @@ extern "C" mbh_status mbh_build_reference_coeffs(mbh_ctx *ctx, const mbh_data *d
   mbh_status s;
   if ((s = ctx_alloc(ctx, (void **)&r->F, E * sizeof(double))) != MBH_OK) return fail_free(s);
   if ((s = ctx_alloc(ctx, (void **)&r->psi0, E * sizeof(double))) != MBH_OK) return fail_free(s);
-  if ((s = ctx_alloc(ctx, (void **)&r->fq, (size_t)E * 3 * sizeof(double))) != MBH_OK) return fail_free(s);
+  if ((s = ctx_alloc(ctx, (void **)&r->fq, (size_t)E * kFq * sizeof(double))) != MBH_OK) return fail_free(s);
   if ((s = ctx_alloc(ctx, (void **)&r->is064, (size_t)C * E * 2 * sizeof(double))) != MBH_OK) return fail_free(s);
   if ((s = ctx_alloc(ctx, (void **)&r->coef, (size_t)C * n_bins * 6 * sizeof(double))) != MBH_OK)
     return fail_free(s);
