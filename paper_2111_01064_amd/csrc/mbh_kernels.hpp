@@ -27,10 +27,29 @@ struct HetRef {
 };
 
 // ---------------------------------------------------------------- utilities
+// value of lane perm(i) within lane i's row of 16 (DPP control CTRL), for
+// both halves of a double
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double lane_f64(double x, int lane) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), lane),
+                          __builtin_amdgcn_readlane(__double2loint(x), lane));
+}
+
+// Sum over the 64 lanes of a wavefront, returned (uniform) in every lane, in
+// a fixed order: within each row of 16 lanes by data-parallel-primitive
+// moves (lane xor 1, xor 2, the mirrored half row, the mirrored row), then
+// the four row sums as (r0 + r1) + (r2 + r3).
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+  v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_f64<0x141>(v);  // row_half_mirror
+  v += dpp_f64<0x140>(v);  // row_mirror
+  return (lane_f64(v, 0) + lane_f64(v, 16)) + (lane_f64(v, 32) + lane_f64(v, 48));
 }
 
 // fixed-order block sum of up to 3 values; result valid in thread 0
