@@ -123,23 +123,27 @@ class Sources:
         return w
 
 
-def time_batch(M, ctx, batch, steps, warmup, stream):
+def time_batch(M, ctx, batch, steps, warmup, stream, mode="direct"):
+    """Wall time of `steps` batch launches queued back to back on `stream`
+    (bracketed by device synchronisation), and the device time between two
+    events around them, per step.  mode: "direct" (mbh_batch_launch_direct:
+    stream launches) or "graph" (mbh_batch_launch: one graph replay)."""
     import torch
 
+    fn = batch.launch_direct if mode == "direct" else batch.launch
     for _ in range(warmup):
-        batch.launch(stream)
+        fn(stream)
     torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     with torch.cuda.stream(stream):
-        for a, b in ev:
-            a.record(stream)
-            batch.launch(stream)
-            b.record(stream)
+        a.record(stream)
+        for _ in range(steps):
+            fn(stream)
+        b.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    per = [a.elapsed_time(b) * 1e-3 for a, b in ev]
-    return wall, float(np.mean(per)), per
+    return wall, a.elapsed_time(b) * 1e-3 / steps
 
 
 def time_stage(batch, stage, steps, stream):
@@ -287,16 +291,19 @@ def main():
             M.set_lanes(ctx, N_BINS, 1, prec, args.mapping)
         lnls = [torch.empty(len(w), dtype=torch.float64, device="cuda") for w in walkers]
         batch = M.Batch(ctx, [it["ref"] for it in S.items], thetas, lnls, prec=prec)
-        wall, mean_s, per = time_batch(M, ctx, batch, args.steps, args.warmup, stream)
+        wall, mean_s = time_batch(M, ctx, batch, args.steps, args.warmup, stream, "direct")
         routed = batch.routed() / (args.steps + args.warmup)
         res[name] = dict(wall=wall, kernel_s=mean_s, lnl=np.concatenate([l.cpu().numpy() for l in lnls]),
                          lanes=M.lanes_for(ctx, N_BINS, 1, prec), routed=routed)
+        gwall, gmean = time_batch(M, ctx, batch, args.steps, args.warmup, stream, "graph")
+        res[name]["graph_us"] = gwall / args.steps * 1e6
         stages = [time_stage(batch, st, max(20, args.steps // 4), stream)
                   for st in (M.STAGE_SETUP, M.STAGE_MAIN, M.STAGE_FINISH)]
         res[name]["stages_s"] = stages
         batch.close()
         res[name]["segments"] = sum(walker_segments(len(w), N_BINS + 1, res[name]["lanes"]) for w in walkers)
-        log(f"[bench] {name}: {W_total} walkers/step, {mean_s * 1e6:.1f} us/step (events), wall {wall:.3f} s, "
+        log(f"[bench] {name}: {W_total} walkers/step, {wall / args.steps * 1e6:.1f} us/step "
+            f"(graph replay {res[name]['graph_us']:.1f}), {mean_s * 1e6:.1f} us/step (events), wall {wall:.3f} s, "
             f"lanes {res[name]['lanes']}, FP64-recomputed segments/step {routed:.1f} of {res[name]['segments']}, "
             f"stages (us) "
             + " / ".join(f"{x * 1e6:.1f}" for x in stages))
@@ -315,7 +322,8 @@ def main():
         "vs_baseline": None, "dtype": "f32+f64 (mixed)", "data": "synthetic",
         "config": {"workload": "8 sources x (8 temps x 64 walkers), (2,2) IMR-lite + TDI A/E/T, "
                                "1 yr dt=10 s (1577880 bins x 3 ch), 128 bins, SNR 100-1000, noisy",
-                   "walkers_per_step": W_total, "n_bins": N_BINS, "launch": "mbh_batch graph replay"},
+                   "walkers_per_step": W_total, "n_bins": N_BINS,
+                   "launch": "mbh_batch_launch_direct (work list resident, stream launches)"},
         "fp64_evals_per_s": fp64_value, "fp64_ms_per_step": res["fp64"]["wall"] / args.steps * 1e3,
         "mixed_speedup_vs_fp64": value / fp64_value, "max_abs_dlnL_mixed_vs_fp64": dmix,
         "mixed_fp64_recomputed_fraction": res["mixed"]["routed"] / res["mixed"]["segments"],
@@ -325,7 +333,8 @@ def main():
                      "kernel": "k_het_tiles<float> (main pass, mixed)", "kernel_us": t_main * 1e6,
                      "flops_per_launch": flops},
         "stages_us": {k: {"setup": v["stages_s"][0] * 1e6, "main": v["stages_s"][1] * 1e6,
-                          "finish": v["stages_s"][2] * 1e6, "graph": v["kernel_s"] * 1e6} for k, v in res.items()},
+                          "finish": v["stages_s"][2] * 1e6, "step_events": v["kernel_s"] * 1e6,
+                          "step_graph_replay": v["graph_us"]} for k, v in res.items()},
         "fp64_roofline_frac": flops / res["fp64"]["stages_s"][1] / 1e12 / PEAK_ALU_TFLOPS,
         "paper_context": {"het_evals_per_s": 2e5, "note": "~5 us per heterodyned lnL, unnamed GPU, PhenomD"},
     }
@@ -378,7 +387,7 @@ def side_measurements(M, ctx, S, walkers, grid):
             M.autotune_heterodyned(ctx, it4["ref"], t4, prec)
         ln4 = [torch.empty(len(t), dtype=torch.float64, device="cuda") for t in th4]
         b4 = M.Batch(ctx, [x["ref"] for x in S4.items], th4, ln4, prec=prec)
-        wall, mean_s, _ = time_batch(M, ctx, b4, 50, 5, st)
+        wall, mean_s = time_batch(M, ctx, b4, 50, 5, st)
         hm[f"{name}_evals_per_s"] = W4 * 50 / wall
         hm[f"{name}_us_per_launch"] = mean_s * 1e6
         hm[f"{name}_fp64_segments_per_launch"] = b4.routed() / 55

@@ -192,6 +192,14 @@ mbh_status mbh_batch_create(mbh_ctx *ctx, int n, const mbh_ref *const *refs,
                             double *const *lnL_dev, double *const *dh_hh_dev,
                             mbh_precision prec, mbh_batch **out);
 mbh_status mbh_batch_launch(mbh_batch *batch, hipStream_t stream);
+/* The same work as mbh_batch_launch, issued as the batch's kernel launches on
+ * the stream (setup, one main-pass grid per mapping group, totals) instead of
+ * one graph replay; results are bit-identical.  On ROCm a graph replay costs
+ * several microseconds more per launch than the equivalent stream launches,
+ * which matters for steps of a few tens of microseconds.  The launches can
+ * themselves be captured into a caller's graph.
+ * Errors: MBH_EINVAL, MBH_EDEVICE. */
+mbh_status mbh_batch_launch_direct(mbh_batch *batch, hipStream_t stream);
 /* One stage of the same work as a graph of its own, for measuring stages
  * separately: MBH_STAGE_SETUP (walker constants, a1), MBH_STAGE_MAIN (the
  * heterodyned main pass, a2-a7, with the mixed path's FP64 recomputation:

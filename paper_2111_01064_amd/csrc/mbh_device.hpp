@@ -299,7 +299,60 @@ __device__ __forceinline__ void raw_phase_mr(const WalkerC &w, double f, double 
 // (pi M f1)^(1/3) with f1 = 0.018 / M: a constant of the model
 constexpr double kV1 = 0.38383165853550260132496406524933909994849537353683;
 
-__device__ __forceinline__ void walker_setup(const double *__restrict__ th, int model, uint32_t modes, WalkerC &w) {
+// extrinsic part of walker_setup: sky and polarisation vectors and the mode
+// polarisation weights
+__device__ __forceinline__ void walker_setup_sky(const double *__restrict__ th, uint32_t modes, WalkerC &w) {
+  double t[11];
+#pragma unroll
+  for (int i = 5; i < 10; ++i) t[i] = th[i];
+  double cl, sl, cb, sb, cp, sp;
+  sincos_param(t[7], sl, cl);
+  sincos_param(t[8], sb, cb);
+  sincos_param(t[9], sp, cp);
+  w.kx = -cb * cl;
+  w.ky = -cb * sl;
+  w.kz = -sb;
+  // u = (sin l, -cos l, 0), v = (-sin b cos l, -sin b sin l, cos b)
+  w.px = cp * sl - sp * sb * cl;
+  w.py = -cp * cl - sp * sb * sl;
+  w.pz = sp * cb;
+  w.qx = -sp * sl - cp * sb * cl;
+  w.qy = sp * cl - cp * sb * sl;
+  w.qz = cp * cb;
+  // polarisation weights of the active modes only; e^{i m phi_ref} as powers of e^{i phi_ref}
+  double ci, si, chi, shi, s1, c1;
+  sincos_param(t[6], si, ci);
+  sincos_param(0.5 * t[6], shi, chi);
+  sincos_param(t[5], s1, c1);
+  for (int mi = 0; mi < kNumModes; ++mi) {
+    if (!(modes & (1u << mi))) continue;
+    double yp, ym;
+    int ls;
+    ylm_pair(mi, ci, si, chi, shi, yp, ym, ls);
+    double cm = c1, sm = s1;
+    for (int k = 1; k < kModeM[mi]; ++k) {
+      double tt = cm * c1 - sm * s1;
+      sm = sm * c1 + cm * s1;
+      cm = tt;
+    }
+    w.kp[mi] = 0.5 * (yp + ls * ym);
+    w.kc[mi] = 0.5 * (yp - ls * ym);
+    w.eph[mi][0] = cm;
+    w.eph[mi][1] = sm;
+  }
+}
+
+// Per-walker constants from theta.  part 1 sets the validity and the
+// intrinsic constants (masses, spins, distance, t_ref: phase, amplitude and
+// frequencies), part 2 the extrinsic ones (sky and polarisation vectors,
+// mode polarisation weights); the two write disjoint fields, so two threads
+// may build one walker together (part 0 does both).
+__device__ __forceinline__ void walker_setup(const double *__restrict__ th, int model, uint32_t modes, WalkerC &w,
+                                             int part = 0) {
+  if (part == 2) {
+    if (model != 1) walker_setup_sky(th, modes, w);
+    return;
+  }
   w.model = model;
   w.pad0 = w.pad1 = 0;
   if (model == 1) {  // chirp
@@ -362,41 +415,7 @@ __device__ __forceinline__ void walker_setup(const double *__restrict__ th, int 
   w.rel[3] = delta * (1.0 / 3.0);
   w.rel[4] = sqrt(5.0 / 7.0) / 3.0 * a;
   w.rel[5] = 9.0 / (4.0 * sqrt(70.0)) * delta * (1.0 - 2.0 * eta);
-  double cl, sl, cb, sb, cp, sp;
-  sincos_param(t[7], sl, cl);
-  sincos_param(t[8], sb, cb);
-  sincos_param(t[9], sp, cp);
-  w.kx = -cb * cl;
-  w.ky = -cb * sl;
-  w.kz = -sb;
-  // u = (sin l, -cos l, 0), v = (-sin b cos l, -sin b sin l, cos b)
-  w.px = cp * sl - sp * sb * cl;
-  w.py = -cp * cl - sp * sb * sl;
-  w.pz = sp * cb;
-  w.qx = -sp * sl - cp * sb * cl;
-  w.qy = sp * cl - cp * sb * sl;
-  w.qz = cp * cb;
-  // polarisation weights of the active modes only; e^{i m phi_ref} as powers of e^{i phi_ref}
-  double ci, si, chi, shi, s1, c1;
-  sincos_param(t[6], si, ci);
-  sincos_param(0.5 * t[6], shi, chi);
-  sincos_param(t[5], s1, c1);
-  for (int mi = 0; mi < kNumModes; ++mi) {
-    if (!(modes & (1u << mi))) continue;
-    double yp, ym;
-    int ls;
-    ylm_pair(mi, ci, si, chi, shi, yp, ym, ls);
-    double cm = c1, sm = s1;
-    for (int k = 1; k < kModeM[mi]; ++k) {
-      double tt = cm * c1 - sm * s1;
-      sm = sm * c1 + cm * s1;
-      cm = tt;
-    }
-    w.kp[mi] = 0.5 * (yp + ls * ym);
-    w.kc[mi] = 0.5 * (yp - ls * ym);
-    w.eph[mi][0] = cm;
-    w.eph[mi][1] = sm;
-  }
+  if (part == 0) walker_setup_sky(th, modes, w);
 }
 
 // Powers of a frequency f used by the waveform: f^(1/3), f^(-1/3), 1/f and

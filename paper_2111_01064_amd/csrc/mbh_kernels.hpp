@@ -74,11 +74,13 @@ __device__ __forceinline__ void block_sum(double v[NV], double *sh /* [NV][kBloc
 }
 
 // ---------------------------------------------------------------- a1: ingest
+// two threads per walker (intrinsic and extrinsic parts), 64 walkers per
+// workgroup of 128 threads
 static __global__ __launch_bounds__(128) void k_walker_setup(const double *__restrict__ theta, int64_t W, int model,
                                                              uint32_t modes, WalkerC *__restrict__ out) {
-  int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t w = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
   if (w >= W) return;
-  walker_setup(theta + w * 11, model, modes, out[w]);
+  walker_setup(theta + w * 11, model, modes, out[w], threadIdx.x < 64 ? 1 : 2);
 }
 
 // ---------------------------------------------------------------- data
@@ -610,10 +612,11 @@ static __global__ __launch_bounds__(kWalkerTile) void k_het_final(const WorkItem
   }
 }
 
-// single-item path: walker constants
+// single-item path: walker constants, two threads per walker (intrinsic and
+// extrinsic parts), 64 walkers per workgroup of 128 threads
 static __global__ __launch_bounds__(128) void k_setup_one(WorkItem one) {
-  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (w < one.W) walker_setup(one.theta + w * 11, one.model, one.ref.modes, one.wc[w]);
+  const int64_t w = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+  if (w < one.W) walker_setup(one.theta + w * 11, one.model, one.ref.modes, one.wc[w], threadIdx.x < 64 ? 1 : 2);
 }
 
 // single-item launches of the main pass

@@ -277,7 +277,7 @@ static mbh_status setup_one(Scratch &sc, const double *theta_host, int model, ui
   WalkerC *wc = nullptr;
   MBH_TRY(sc.get(&wc, 1));
   HIP_TRY(hipMemcpyAsync(th, theta_host, 11 * sizeof(double), hipMemcpyHostToDevice, sc.st));
-  hipLaunchKernelGGL(k_walker_setup, dim3(1), dim3(64), 0, sc.st, th, (int64_t)1, model, modes, wc);
+  hipLaunchKernelGGL(k_walker_setup, dim3(1), dim3(128), 0, sc.st, th, (int64_t)1, model, modes, wc);
   int32_t v = 0;
   HIP_TRY(hipMemcpyAsync(&v, &wc->valid, sizeof(int32_t), hipMemcpyDeviceToHost, sc.st));
   HIP_TRY(hipStreamSynchronize(sc.st));
@@ -661,7 +661,7 @@ extern "C" mbh_status mbh_loglike_heterodyned(mbh_ctx *ctx, const mbh_ref *ref, 
   it.offset = 0;
   MBH_TRY(sc.get(&it.wc, (size_t)W));
   MBH_TRY(sc.get(&it.part, (size_t)W * it.K * 4));
-  hipLaunchKernelGGL(k_setup_one, dim3((unsigned)((W + 127) / 128)), dim3(128), 0, st, it);
+  hipLaunchKernelGGL(k_setup_one, dim3((unsigned)((W + 63) / 64)), dim3(128), 0, st, it);
   launch_main(prec, dh_hh_dev != nullptr, it, st);
   launch_finish(nullptr, it, nullptr, 0, st);
   HIP_TRY(hipGetLastError());
@@ -709,7 +709,7 @@ extern "C" mbh_status mbh_loglike_full(mbh_ctx *ctx, const mbh_data *data, int m
   Scratch sc(ctx, st);
   WalkerC *wc = nullptr;
   MBH_TRY(sc.get(&wc, (size_t)W));
-  hipLaunchKernelGGL(k_walker_setup, dim3((unsigned)((W + 127) / 128)), dim3(128), 0, st, theta_dev, W, model,
+  hipLaunchKernelGGL(k_walker_setup, dim3((unsigned)((W + 63) / 64)), dim3(128), 0, st, theta_dev, W, model,
                      model == MBH_MODEL_IMR ? modes : 0u, wc);
   uint32_t m = model == MBH_MODEL_IMR ? modes : 0u;
   if (prec == MBH_FP64)
@@ -795,7 +795,7 @@ extern "C" mbh_status mbh_autotune_heterodyned(mbh_ctx *ctx, const mbh_ref *ref,
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
     if (hipMemcpyAsync(th, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, st) == hipSuccess) {
-      hipLaunchKernelGGL(k_setup_one, dim3((unsigned)((W + 127) / 128)), dim3(128), 0, st, it);
+      hipLaunchKernelGGL(k_setup_one, dim3((unsigned)((W + 63) / 64)), dim3(128), 0, st, it);
       for (int G : {0, 16, 32, 64}) {
         it.G = G;
         launch_main(prec, false, it, st);  // warm-up

@@ -122,7 +122,7 @@ static void launch_work(int prec, bool dh, int64_t n_wtiles, const std::vector<T
                         const WalkerTile *wtiles, const WorkItem *items, const WorkTile *tiles, hipStream_t st,
                         int stages = 7) {
   const dim3 nw((unsigned)std::max<int64_t>(1, n_wtiles));
-  if (stages & 1) hipLaunchKernelGGL(k_setup_work, nw, dim3(kWalkerTile), 0, st, items, wtiles);
+  if (stages & 1) hipLaunchKernelGGL(k_setup_work, nw, dim3(2 * kWalkerTile), 0, st, items, wtiles);
   for (const TileGroup &g : groups) {
     if (!(stages & 2)) break;
     if (prec == MBH_FP64) {
@@ -269,6 +269,14 @@ extern "C" mbh_status mbh_batch_launch(mbh_batch *b, hipStream_t st) {
   if (!b) return mbh_fail(MBH_EINVAL, "null batch");
   HIP_TRY(hipSetDevice(b->ctx->device));
   HIP_TRY(hipGraphLaunch(b->exec, st));
+  return MBH_OK;
+}
+
+extern "C" mbh_status mbh_batch_launch_direct(mbh_batch *b, hipStream_t st) {
+  if (!b) return mbh_fail(MBH_EINVAL, "null batch");
+  HIP_TRY(hipSetDevice(b->ctx->device));
+  launch_work(b->prec, b->dh, b->n_wtiles, b->groups, b->wtiles, b->items, b->tiles, st);
+  HIP_TRY(hipGetLastError());
   return MBH_OK;
 }
 

@@ -25,13 +25,16 @@ struct WorkTile {
   int64_t begin;  // first chunk (G = 0) or first walker (G > 0) of the tile
 };
 
-// a1 for every walker of the batch, one workgroup per walker tile
-static __global__ __launch_bounds__(kWalkerTile) void k_setup_work(const WorkItem *__restrict__ items,
-                                                                   const WalkerTile *__restrict__ wtiles) {
+// a1 for every walker of the batch, one workgroup per walker tile: the first
+// kWalkerTile threads set the intrinsic constants, the other kWalkerTile the
+// extrinsic ones, of the same walkers
+static __global__ __launch_bounds__(2 * kWalkerTile) void k_setup_work(const WorkItem *__restrict__ items,
+                                                                       const WalkerTile *__restrict__ wtiles) {
   const WalkerTile tl = wtiles[blockIdx.x];
   const WorkItem &it = items[tl.item];
-  const int64_t w = tl.w_begin + threadIdx.x;
-  if (w < it.W) walker_setup(it.theta + w * 11, it.model, it.ref.modes, it.wc[w]);
+  const int64_t w = tl.w_begin + (threadIdx.x & (kWalkerTile - 1));
+  const int part = threadIdx.x < kWalkerTile ? 1 : 2;
+  if (w < it.W) walker_setup(it.theta + w * 11, it.model, it.ref.modes, it.wc[w], part);
 }
 
 template <typename R, bool DH, int G>

@@ -77,6 +77,7 @@ _SIGS = {
     "mbh_batch_create": [_vp, _i32, _pp, _pp, ct.POINTER(ct.c_int64), _pp, _pp, _i32, _pp],
     "mbh_batch_launch": [_vp, _vp],
     "mbh_batch_launch_stage": [_vp, _i32, _vp],
+    "mbh_batch_launch_direct": [_vp, _vp],
     "mbh_batch_routed": [_vp, ct.POINTER(ct.c_uint64)],
     "mbh_batch_release": [_vp],
     "mbh_autotune_heterodyned": [_vp, _vp, _vp, _i64, _i32, ct.POINTER(ct.c_int)],
@@ -331,6 +332,10 @@ class Batch:
 
     def launch(self, stream=None):
         _check(_L.mbh_batch_launch(self.h, _stream(stream)), "mbh_batch_launch")
+
+    def launch_direct(self, stream=None):
+        """The same work as launch(), as stream launches instead of a graph replay."""
+        _check(_L.mbh_batch_launch_direct(self.h, _stream(stream)), "mbh_batch_launch_direct")
 
     def launch_stage(self, stage: int, stream=None):
         """STAGE_SETUP, STAGE_MAIN or STAGE_FINISH alone (for measurement)."""

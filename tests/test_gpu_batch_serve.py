@@ -95,6 +95,13 @@ def test_batch_graph_replays_match_single_calls_and_oracle(M, ctx, sources, prec
     torch.cuda.synchronize()
     for l, ref_single in zip(lnls, single):
         assert np.array_equal(l.cpu().numpy(), ref_single)
+    # stream launches of the same work (no graph) agree bit for bit
+    for l in lnls:
+        l.fill_(np.nan)
+    batch.launch_direct()
+    torch.cuda.synchronize()
+    for l, ref_single in zip(lnls, single):
+        assert np.array_equal(l.cpu().numpy(), ref_single)
     # oracle parity on a subsample of every item (last positions)
     worst = 0.0
     for s, t, l in zip(sources, thetas, lnls):
