@@ -42,21 +42,25 @@ N_SOURCES, TEMPS, PER_TEMP, N_BINS = 8, tuple(2.0 ** k for k in range(8)), 64, 1
 # other arithmetic and transcendental instructions 1): the VALU FLOP counters
 # (SQ_INSTS_VALU_FLOPS_FP64, _FP32, _FP64_TRANS, _FP32_TRANS, x 64 lanes) of
 # the mixed main pass over this benchmark's 4096 walkers x 129 edges give
-# 4.914e8 per launch, 930 per edge (FP64 pass: 935); profiles/het_main_pass_bench.md.
-FLOPS_PER_EDGE = 930.0
+# 4.554e8 per launch, 862 per edge (FP64 pass: 856); profiles/het_main_pass_bench.md.
+FLOPS_PER_EDGE = 862.0
 # HBM traffic of the mixed main pass (bytes per launch) from the FETCH_SIZE and
 # WRITE_SIZE counters divided by their reading for a 64 MiB device copy
 # (factors 0.5002 and 1.000); valid only for the kernel sources it was
-# measured on (sha256 over paper_2111_01064_amd/csrc).
-TRAFFIC = {"src_sha256": "d78a6d16e7f1dceea8f59debc48d5e6d2c11e210816a44887c4414c7bd245c36",
-           "bytes_per_launch": 6.165e6}
+# measured on (sha256 over KERNEL_SOURCES).
+TRAFFIC = {"src_sha256": "fed42850807ce4bb884d92931c4d7d8173190e090b7eb4f5a4e3ddcc14eca0d2",
+           "bytes_per_launch": 6.749e6}
+
+
+# the sources that define the device code of the main pass
+KERNEL_SOURCES = ("mbh_device.hpp", "mbh_kernels.hpp", "mbh_work.hpp")
 
 
 def kernel_sources_hash() -> str:
     import hashlib
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2111_01064_amd", "csrc")
-    for fn in sorted(os.listdir(d)):
+    for fn in KERNEL_SOURCES:
         with open(os.path.join(d, fn), "rb") as f:
             h.update(fn.encode() + b"\0" + f.read())
     return h.hexdigest()
@@ -147,10 +151,10 @@ def time_batch(M, ctx, batch, steps, warmup, stream, mode="direct"):
 
 
 def time_stage(batch, stage, steps, stream):
-    """Mean duration of one stage of the batch (a graph of its own): `steps`
-    launches queued back to back between two events on the launch stream, so
-    that the host-side launch latency overlaps the device work; the stage's
-    inputs come from a preceding full launch."""
+    """Mean duration of one stage of the batch (mbh_batch_launch_stage):
+    `steps` launches queued back to back between two events on the launch
+    stream, so that the host-side launch latency overlaps the device work;
+    the stage's inputs come from a preceding full launch."""
     import torch
 
     batch.launch(stream)

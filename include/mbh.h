@@ -200,11 +200,12 @@ mbh_status mbh_batch_launch(mbh_batch *batch, hipStream_t stream);
  * themselves be captured into a caller's graph.
  * Errors: MBH_EINVAL, MBH_EDEVICE. */
 mbh_status mbh_batch_launch_direct(mbh_batch *batch, hipStream_t stream);
-/* One stage of the same work as a graph of its own, for measuring stages
- * separately: MBH_STAGE_SETUP (walker constants, a1), MBH_STAGE_MAIN (the
- * heterodyned main pass, a2-a7, with the mixed path's FP64 recomputation:
- * the dominant kernel), MBH_STAGE_FINISH (per-walker totals).
- * Launching the three in this order on one stream is mbh_batch_launch.
+/* One stage of the same work launched on its own (stream launches), for
+ * measuring stages separately: MBH_STAGE_SETUP (walker constants, a1),
+ * MBH_STAGE_MAIN (the heterodyned main pass, a2-a7, with the mixed path's
+ * FP64 recomputation: the dominant kernel), MBH_STAGE_FINISH (per-walker
+ * totals).  Launching the three in this order on one stream is the work of
+ * mbh_batch_launch.
  * Errors: MBH_EINVAL, MBH_EDEVICE. */
 enum { MBH_STAGE_SETUP = 1, MBH_STAGE_MAIN = 2, MBH_STAGE_FINISH = 3 };
 mbh_status mbh_batch_launch_stage(mbh_batch *batch, int stage, hipStream_t stream);

@@ -154,18 +154,11 @@ struct mbh_batch {
   std::vector<TileGroup> groups;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  // the three stages as graphs of their own (setup, main pass, totals)
-  hipGraph_t sgraph[3] = {nullptr, nullptr, nullptr};
-  hipGraphExec_t sexec[3] = {nullptr, nullptr, nullptr};
 };
 
 static void batch_free(mbh_batch *b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
-  for (int i = 0; i < 3; ++i) {
-    if (b->sexec[i]) (void)hipGraphExecDestroy(b->sexec[i]);
-    if (b->sgraph[i]) (void)hipGraphDestroy(b->sgraph[i]);
-  }
   for (auto &a : b->allocs) ctx_free(b->ctx, a.first, a.second);
   delete b;
 }
@@ -252,13 +245,6 @@ extern "C" mbh_status mbh_batch_create(mbh_ctx *ctx, int n, const mbh_ref *const
     e = hipStreamEndCapture(cs, &b->graph);
   }
   if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
-  for (int k = 0; k < 3 && e == hipSuccess; ++k) {
-    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) break;
-    launch_work(prec, dh, b->n_wtiles, b->groups, b->wtiles, b->items, b->tiles, cs, 1 << k);
-    e = hipStreamEndCapture(cs, &b->sgraph[k]);
-    if (e == hipSuccess) e = hipGraphInstantiate(&b->sexec[k], b->sgraph[k], nullptr, nullptr, 0);
-  }
   (void)hipStreamDestroy(cs);
   if (e != hipSuccess) return fail(mbh_fail(MBH_EDEVICE, "graph capture: %s", hipGetErrorString(e)));
   *out = b;
@@ -283,7 +269,8 @@ extern "C" mbh_status mbh_batch_launch_direct(mbh_batch *b, hipStream_t st) {
 extern "C" mbh_status mbh_batch_launch_stage(mbh_batch *b, int stage, hipStream_t st) {
   if (!b || stage < MBH_STAGE_SETUP || stage > MBH_STAGE_FINISH) return mbh_fail(MBH_EINVAL, "bad batch or stage");
   HIP_TRY(hipSetDevice(b->ctx->device));
-  HIP_TRY(hipGraphLaunch(b->sexec[stage - 1], st));
+  launch_work(b->prec, b->dh, b->n_wtiles, b->groups, b->wtiles, b->items, b->tiles, st, 1 << (stage - 1));
+  HIP_TRY(hipGetLastError());
   return MBH_OK;
 }
 
