@@ -213,7 +213,7 @@ mbh_status mbh_batch_launch_stage(mbh_batch *batch, int stage, hipStream_t strea
  * mbh_loglike_heterodyned; a segment is a walker's bins within one
  * 63-bin chunk of the flattened mapping, or the whole walker in a lane-group
  * mapping), summed over all launches so far.  Synchronous. */
-mbh_status mbh_batch_routed(const mbh_batch *batch, uint64_t *routed_out);
+mbh_status mbh_batch_fp64_segments(const mbh_batch *batch, uint64_t *count_out);
 mbh_status mbh_batch_release(mbh_batch *batch);
 
 /* --------------------------------------------------------- autotuner */

@@ -274,12 +274,12 @@ extern "C" mbh_status mbh_batch_launch_stage(mbh_batch *b, int stage, hipStream_
   return MBH_OK;
 }
 
-extern "C" mbh_status mbh_batch_routed(const mbh_batch *b, uint64_t *routed_out) {
-  if (!b || !routed_out) return mbh_fail(MBH_EINVAL, "null argument");
+extern "C" mbh_status mbh_batch_fp64_segments(const mbh_batch *b, uint64_t *count_out) {
+  if (!b || !count_out) return mbh_fail(MBH_EINVAL, "null argument");
   HIP_TRY(hipSetDevice(b->ctx->device));
   unsigned long long v = 0;
   HIP_TRY(hipMemcpy(&v, b->redo, sizeof(v), hipMemcpyDeviceToHost));
-  *routed_out = v;
+  *count_out = v;
   return MBH_OK;
 }
 

@@ -78,7 +78,7 @@ _SIGS = {
     "mbh_batch_launch": [_vp, _vp],
     "mbh_batch_launch_stage": [_vp, _i32, _vp],
     "mbh_batch_launch_direct": [_vp, _vp],
-    "mbh_batch_routed": [_vp, ct.POINTER(ct.c_uint64)],
+    "mbh_batch_fp64_segments": [_vp, ct.POINTER(ct.c_uint64)],
     "mbh_batch_release": [_vp],
     "mbh_autotune_heterodyned": [_vp, _vp, _vp, _i64, _i32, ct.POINTER(ct.c_int)],
     "mbh_lanes_for": [_vp, _i32, _i32, _i32, ct.POINTER(ct.c_int)],
@@ -341,10 +341,10 @@ class Batch:
         """STAGE_SETUP, STAGE_MAIN or STAGE_FINISH alone (for measurement)."""
         _check(_L.mbh_batch_launch_stage(self.h, stage, _stream(stream)), "mbh_batch_launch_stage")
 
-    def routed(self) -> int:
-        """Walker segments recomputed in FP64 so far (mixed path)."""
+    def fp64_segments(self) -> int:
+        """Walker segments the mixed path computed in FP64 so far."""
         v = ct.c_uint64()
-        _check(_L.mbh_batch_routed(self.h, ct.byref(v)), "mbh_batch_routed")
+        _check(_L.mbh_batch_fp64_segments(self.h, ct.byref(v)), "mbh_batch_fp64_segments")
         return v.value
 
     def close(self):

@@ -1,4 +1,5 @@
-"""Batching (one persistent, graph-captured launch over ragged items) and
+"""Batching (one device-resident work list over ragged items, replayed as a graph
+or as stream launches) and
 serving (continuous batching), checked against single calls and the oracle.
 
 Every walker's result depends only on its inputs, its reference and the lanes
