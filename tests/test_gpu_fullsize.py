@@ -1,0 +1,128 @@
+"""Parity at the benchmark's full size: the 1-yr grid at dt = 10 s
+(1 577 880 Fourier bins x 3 channels), 128 bins, each source with
+8 temperatures x 64 walkers, launched the way bench.py launches the step (a
+batch issued with mbh_batch_launch_direct, flattened mapping).  The data,
+references and walkers come from the oracle and the input generators only.
+
+Every heterodyned result of the batch is checked against the oracle's
+heterodyned likelihood (cheap per walker at any grid size); the reference
+build (coefficients, band, lnL(h0)) and a few full-grid evaluations, which
+cost the oracle about half a second each at this size, are checked too.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2111_01064_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-3
+N_SOURCES = 2
+TEMPS = (1, 2, 4, 8, 16, 32, 64, 128)
+PER_TEMP = 64
+N_BINS = 128
+
+
+@pytest.fixture(scope="module")
+def M():
+    from paper_2111_01064_amd import mbh
+
+    return mbh
+
+
+@pytest.fixture(scope="module")
+def ctx(M):
+    return M.Context(0)
+
+
+@pytest.fixture(scope="module")
+def full(M, ctx):
+    import torch
+
+    g = I.grid_lisa()
+    psd = I.psd_lisa_aet(g.freqs)
+    out = []
+    for s in range(N_SOURCES):
+        rng = I.rng_for(6, s)
+        th, snr = I.draw_mbhb_source(rng, g.t_obs)
+        # the template scales as 1/D_L (placeholder 1 Gpc)
+        h = O.template(O.MODEL_IMR, O.MODE_22, th, g.freqs, g.t_obs)
+        th[4] = I.distance_for_snr(O.inner(h, h, psd, g.df), snr)
+        d = h * (1.0 / th[4]) + I.noise(psd, g.df, rng)
+        del h
+        data = O.Data(d, psd, g.f0, g.df, g.t_obs)
+        ref = O.Reference(O.MODEL_IMR, O.MODE_22, th, data, N_BINS)
+        assert ref.status == O.OK
+        sig = I.curvature_sigma(lambda x: ref.loglike(x)[0], th)
+        w = I.walker_cloud(th, sig, TEMPS, PER_TEMP, rng)
+        gd = M.data_create(ctx, torch.as_tensor(d, device="cuda"), torch.as_tensor(psd, device="cuda"), g.f0, g.df,
+                           g.t_obs)
+        gr = M.build_reference_coeffs(ctx, gd, M.MODEL_IMR, M.MODE_22, th, N_BINS)
+        print(f"[fullsize] source {s}: SNR {snr:.0f}, M_T {th[0]:.3g} Msun, band bins {ref.k_lo}..{ref.k_hi}",
+              flush=True)
+        out.append(dict(th=th, snr=snr, data=data, ref=ref, walkers=w, gdata=gd, gref=gr))
+    return g, out
+
+
+def test_fullsize_reference(full):
+    _, srcs = full
+    for c in srcs:
+        r, gr = c["ref"], c["gref"]
+        ex, info = gr.export(), gr.info
+        assert info["k_lo"] == r.k_lo and info["k_hi"] == r.k_hi
+        assert np.array_equal(ex["kb"], r.kb)
+        for name, a, b in (("A0", ex["A0"], r.A0c), ("A1", ex["A1"], r.A1c), ("B0", ex["B0"], r.B0),
+                           ("B1", ex["B1"], r.B1)):
+            err = np.abs(a - b).max() / np.abs(b).max()
+            print(f"[fullsize] reference {name}: max rel err {err:.2e}", flush=True)
+            assert err < 1e-9
+        lf, _, _ = O.loglike_full(O.MODEL_IMR, O.MODE_22, c["th"], c["data"])
+        print(f"[fullsize] lnL(h0): library {info['lnL0']:.6f} oracle full grid {lf[0]:.6f}", flush=True)
+        assert abs(info["lnL0"] - lf[0]) < TOL
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_fullsize_batch_heterodyned(M, ctx, full, prec):
+    import torch
+
+    _, srcs = full
+    p = M.FP64 if prec == "fp64" else M.MIXED
+    M.set_lanes(ctx, N_BINS, 1, p, 0)
+    thetas = [torch.as_tensor(c["walkers"], device="cuda") for c in srcs]
+    lnls = [torch.empty(len(c["walkers"]), dtype=torch.float64, device="cuda") for c in srcs]
+    b = M.Batch(ctx, [c["gref"] for c in srcs], thetas, lnls, prec=p)
+    b.launch_direct()
+    torch.cuda.synchronize()
+    b.close()
+    for c, l in zip(srcs, lnls):
+        got = l.cpu().numpy()
+        ref_l, _, _ = c["ref"].loglike(c["walkers"])
+        err = np.abs(got - ref_l)
+        print(f"[fullsize] het {prec}: n={got.size} max|dlnL|={err.max():.3e} median={np.median(err):.3e} "
+              f"lnL range=[{ref_l.min():.4g}, {ref_l.max():.4g}]", flush=True)
+        assert np.all(err <= TOL)
+        if prec == "fp64":
+            assert np.all(err <= 1e-6 + 1e-12 * np.abs(ref_l))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_fullsize_full_grid(M, ctx, full, prec):
+    import torch
+
+    _, srcs = full
+    p = M.FP64 if prec == "fp64" else M.MIXED
+    for c in srcs:
+        w = c["walkers"][[0, 200, 511]]  # cold, warm and hot rungs
+        got = M.loglike_full(ctx, c["gdata"], M.MODEL_IMR, M.MODE_22, torch.as_tensor(w, device="cuda"),
+                             p).cpu().numpy()
+        ref_l, _, _ = O.loglike_full(O.MODEL_IMR, O.MODE_22, w, c["data"])
+        err = np.abs(got - ref_l)
+        print(f"[fullsize] full {prec}: max|dlnL|={err.max():.3e} lnL range=[{ref_l.min():.4g}, {ref_l.max():.4g}]",
+              flush=True)
+        if prec == "fp64":
+            assert np.all(err <= 1e-6 + 1e-11 * np.abs(ref_l))
+        else:
+            # FP32 residuals: |err| <~ 2 eps32 sqrt(sum |r|^2 |d|^2) with |r|, |d| whitened
+            bound = 1e-3 + 4 * 6e-8 * np.sqrt(np.abs(ref_l) * (2 * c["ref"].dd))
+            assert np.all(err <= bound)
