@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -53,6 +54,15 @@ static int64_t tiles_of(int G, int64_t W, int E) {
   return (W + wpb - 1) / wpb;
 }
 
+// Tile cost for the longest-first order: the work per lane, plus a small term
+// that puts the tiles of louder references (larger <h0|h0>) first among
+// equals: on the mixed path their walkers are the likeliest to need the FP64
+// recomputation, which then overlaps the rest of the pass instead of
+// trailing it.
+static double tile_cost(double work, const mbh_ref *r) {
+  return work + 0.05 * std::log10(1.0 + std::max(0.0, r->hh0));
+}
+
 static void append_tiles(std::vector<WorkTile> &tiles, std::vector<double> &cost, int item, const mbh_ref *r,
                          int G, int64_t W) {
   const int E = r->n_bins + 1;
@@ -62,12 +72,12 @@ static void append_tiles(std::vector<WorkTile> &tiles, std::vector<double> &cost
     const int64_t nc = flat_chunks(W, E);
     for (int64_t c = 0; c < nc; c += kWaves) {
       tiles.push_back(WorkTile{item, 0, c});
-      cost.push_back((double)nm);
+      cost.push_back(tile_cost((double)nm, r));
     }
     return;
   }
   const int64_t wpb = kBlock / G;
-  const double c = (double)((E + G - 1) / G) * nm;
+  const double c = tile_cost((double)((E + G - 1) / G) * nm, r);
   for (int64_t w = 0; w < W; w += wpb) {
     tiles.push_back(WorkTile{item, G, w});
     cost.push_back(c);
