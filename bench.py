@@ -45,6 +45,11 @@ N_SOURCES, TEMPS, PER_TEMP, N_BINS = 8, tuple(2.0 ** k for k in range(8)), 64, 1
 # the mixed main pass over this benchmark's 4096 walkers x 129 edges give
 # 4.554e8 per launch, 862 per edge (FP64 pass: 856); profiles/het_main_pass_bench.md.
 FLOPS_PER_EDGE = 862.0
+# Floating-point work of the full-grid likelihood per (walker, grid point),
+# three channels, (2,2) mode (FLOP counters of k_full, FP64 pass;
+# profiles/full_grid_reference_build.md); the call also streams 24-48 B of
+# data per point per walker tile, far below the VALU time.
+FULL_FLOPS_PER_POINT = 761.0
 # HBM traffic of the mixed main pass (bytes per launch) from the FETCH_SIZE and
 # WRITE_SIZE counters divided by their reading for a 64 MiB device copy
 # (factors 0.5002 and 1.000); valid only for the kernel sources it was
@@ -378,6 +383,9 @@ def side_measurements(M, ctx, S, walkers, grid):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         out[f"full_grid_{name}_evals_per_s"] = len(draws) / dt
+        # VALU work from the FLOP counters: FULL_FLOPS_PER_POINT per (walker, grid point)
+        out[f"full_grid_{name}_roofline_frac"] = (len(draws) * grid.n_f * FULL_FLOPS_PER_POINT / dt / 1e12
+                                                  / PEAK_ALU_TFLOPS)
         log(f"[bench] full grid {name}: {len(draws) / dt:.1f} evals/s")
     # reference build (a9)
     torch.cuda.synchronize()
