@@ -222,6 +222,43 @@ def cpu_baseline(budget_s: float = 15.0):
                 full_grid_s_per_eval_per_core=full_s * O.max_threads(), setup_s=setup_s)
 
 
+def chirp_case(M, ctx):
+    """The single-channel 0PN chirp case (2^14 linear bins on [1e-4, 0.1] Hz,
+    64 bins, 32 walkers at 1e-4 relative scatter): the oracle's heterodyned and
+    full-grid lnL, their difference and CPU seconds, and the library's FP64
+    heterodyned lnL against the oracle's."""
+    import torch
+
+    import oracle as O
+
+    g = I.grid_chirp()
+    rng = I.rng_for(1, 0)
+    th = I.draw_chirp_source(rng)
+    psd = I.psd_chirp(g.freqs)
+    h = O.template(O.MODEL_TF2, 0, th, g.freqs, g.t_obs)
+    th[1] = 100.0 / math.sqrt(O.inner(h, h, psd, g.df))
+    d = O.template(O.MODEL_TF2, 0, th, g.freqs, g.t_obs) + I.noise(psd, g.df, rng)
+    data = O.Data(d, psd, g.f0, g.df, g.t_obs)
+    t0 = time.perf_counter()
+    ref = O.Reference(O.MODEL_TF2, 0, th, data, 64)
+    w = I.relative_cloud(th, 1e-4, 32, rng)
+    w[:, 4:] = 0.0
+    lh, _, _ = ref.loglike(w)
+    t_het = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    lf, _, _ = O.loglike_full(O.MODEL_TF2, 0, w, data)
+    t_full = time.perf_counter() - t0
+    gd = M.data_create(ctx, torch.as_tensor(np.atleast_2d(d), device="cuda"),
+                       torch.as_tensor(np.atleast_2d(psd), device="cuda"), g.f0, g.df, g.t_obs)
+    gr = M.build_reference_coeffs(ctx, gd, M.MODEL_TF2, 0, th, 64)
+    lg = M.loglike_heterodyned(ctx, gr, torch.as_tensor(w, device="cuda"), M.FP64).cpu().numpy()
+    gr.close()
+    gd.close()
+    return dict(walkers=len(w), bins=64, grid=g.n_f, max_abs_het_minus_full=float(np.max(np.abs(lh - lf))),
+                oracle_het_s=t_het, oracle_full_s=t_full, cores=O.max_threads(),
+                max_abs_gpu_fp64_minus_oracle_het=float(np.max(np.abs(lg - lh))))
+
+
 def serve_run(M, ctx, refs, pools, prec, rate_hz, n_req, warm):
     rng = I.rng_for(5, 1)
     reqs = I.poisson_requests(rng, n_req + warm, rate_hz, 64, len(refs), 4096)
@@ -318,6 +355,15 @@ def main():
             f"stages (us) "
             + " / ".join(f"{x * 1e6:.1f}" for x in stages))
     dmix = float(np.max(np.abs(res["mixed"]["lnl"] - res["fp64"]["lnl"])))
+    # |dlnL| against the distance below each source's best walker
+    dist = np.concatenate([l.max() - l for l in np.split(res["fp64"]["lnl"], np.cumsum([len(w) for w in walkers])[:-1])])
+    dabs = np.abs(res["mixed"]["lnl"] - res["fp64"]["lnl"])
+    by_dist = []
+    for lo, hi in ((0, 10), (10, 100), (100, 1e3), (1e3, 1e4), (1e4, np.inf)):
+        m = (dist >= lo) & (dist < hi)
+        if m.any():
+            by_dist.append({"below_max": [lo, None if np.isinf(hi) else hi], "walkers": int(m.sum()),
+                            "max_abs_dlnL": float(dabs[m].max())})
     ms_per_step = res["mixed"]["wall"] / args.steps * 1e3
     value = W_total * args.steps / res["mixed"]["wall"]
     fp64_value = W_total * args.steps / res["fp64"]["wall"]
@@ -343,6 +389,7 @@ def main():
                    "launch": "mbh_batch_launch_direct (work list resident, stream launches)"},
         "fp64_evals_per_s": fp64_value, "fp64_ms_per_step": res["fp64"]["wall"] / args.steps * 1e3,
         "mixed_speedup_vs_fp64": value / fp64_value, "max_abs_dlnL_mixed_vs_fp64": dmix,
+        "dlnL_mixed_vs_fp64_by_distance": by_dist,
         "mixed_fp64_recomputed_fraction": res["mixed"]["fp64_segs"] / res["mixed"]["segments"],
         "mixed_tolerance": M.mixed_tolerance(ctx),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s",
@@ -364,6 +411,8 @@ def main():
         cb = cpu_baseline()
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
         out["cpu_baseline_full_grid_s_per_eval_per_core"] = cb["full_grid_s_per_eval_per_core"]
+        out["chirp_case"] = chirp_case(M, ctx)
+        log(f"[bench] chirp case: {out['chirp_case']}")
     print(json.dumps(out), flush=True)
 
 
@@ -426,6 +475,15 @@ def side_measurements(M, ctx, S, walkers, grid):
     for name, prec in (("mixed", M.MIXED), ("fp64", M.FP64)):
         serve[name] = serve_run(M, ctx, refs, pools, prec, rate_hz=2000.0, n_req=4000, warm=400)
         log(f"[bench] serve {name}: {serve[name]}")
+    # offered load up to what one Python submitting thread sustains (each
+    # request's walkers are copied into the server); the GPU side runs at a
+    # few % of its capacity even at the highest rate
+    sweep = []
+    for rate in (10000.0, 30000.0):
+        r = serve_run(M, ctx, refs, pools, M.MIXED, rate_hz=rate, n_req=6000, warm=600)
+        sweep.append(r)
+        log(f"[bench] serve mixed at {rate:.0f} req/s: {r}")
+    serve["mixed_rate_sweep"] = sweep
     out["serving"] = serve
     return out
 
