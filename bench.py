@@ -43,8 +43,8 @@ N_SOURCES, TEMPS, PER_TEMP, N_BINS = 8, tuple(2.0 ** k for k in range(8)), 64, 1
 # other arithmetic and transcendental instructions 1): the VALU FLOP counters
 # (SQ_INSTS_VALU_FLOPS_FP64, _FP32, _FP64_TRANS, _FP32_TRANS, x 64 lanes) of
 # the mixed main pass over this benchmark's 4096 walkers x 129 edges give
-# 4.554e8 per launch, 862 per edge (FP64 pass: 856); profiles/het_main_pass_bench.md.
-FLOPS_PER_EDGE = 862.0
+# 4.49e8 per launch, 850 per edge (FP64 pass: 856); profiles/het_main_pass_bench.md.
+FLOPS_PER_EDGE = 850.0
 # Floating-point work of the full-grid likelihood per (walker, grid point),
 # three channels, (2,2) mode (FLOP counters of k_full, FP64 pass;
 # profiles/full_grid_reference_build.md); the call also streams 24-48 B of
@@ -54,8 +54,8 @@ FULL_FLOPS_PER_POINT = 761.0
 # WRITE_SIZE counters divided by their reading for a 64 MiB device copy
 # (factors 0.5002 and 1.000); valid only for the kernel sources it was
 # measured on (sha256 over KERNEL_SOURCES).
-TRAFFIC = {"src_sha256": "fed42850807ce4bb884d92931c4d7d8173190e090b7eb4f5a4e3ddcc14eca0d2",
-           "bytes_per_launch": 6.749e6}
+TRAFFIC = {"src_sha256": "7c214e7afad1de09ced6686d4685be02cf09eabf9948c7271c31f02d29b4c65e",
+           "bytes_per_launch": 6.759e6}
 
 
 # the sources that define the device code of the main pass

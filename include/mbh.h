@@ -151,8 +151,9 @@ mbh_status mbh_ref_export(const mbh_ref *ref, double *edges, int64_t *kb, double
  * form lnL(h0) + sum_b {...} so that FP32 terms stay small.
  *   theta_dev [W][11] FP64; lnL_dev [W] FP64; dh_hh_dev [W][2] (Z[d,h],
  *   Z[h,h]) or NULL.  MBH_FP64 runs every step in FP64.  MBH_MIXED runs the
- *   sinc series of the six link transfers and the link phase factors in
- *   FP32 and everything else (phases, times, Doppler, geometry, per-walker
+ *   sinc series of the six link transfers, the link phase factors and the
+ *   sine and cosine of the (FP64-reduced) carrier difference to h0 in FP32,
+ *   and everything else (phases, times, Doppler, geometry, per-walker
  *   amplitude and polarisation factors, the ratio and the contraction) in
  *   FP64.  The FP32 error of lnL is estimated per segment of a walker's
  *   bins (the bins one wavefront handles); segments whose share could take

@@ -343,11 +343,21 @@ __device__ __forceinline__ void het_edge(const HetRef &ref, const WalkerC &c, in
   const FreqC fc{q[0], q[1], q[2], sizeof(R) == 8 ? ref.ns64 : ref.ns32};
   const FreqPow pw{q[3], q[4], q[5], q[6]};
   template_point<R>(c, ref.modes, ref.F[j], pw, fc, ref.t_obs, s, psi);
-  // the carrier difference enters every channel of the edge at once: FP64
-  // in both paths
+  // the carrier difference enters every channel of the edge at once: formed
+  // and reduced to [-pi, pi] in FP64 in both paths; its sine and cosine in
+  // the template precision (in FP32 they add an edge-to-edge random error of
+  // the same size as the response's, which the error estimate's calibration
+  // covers)
   const double dpsi = reduce_2pi(psi - ref.psi0[j]);
   double hs, hc;
-  sincos_red<double>(0.5 * dpsi, hs, hc);
+  if constexpr (sizeof(R) == 4) {
+    float hs32, hc32;
+    sincos_red<float>((float)(0.5 * dpsi), hs32, hc32);
+    hs = hs32;
+    hc = hc32;
+  } else {
+    sincos_red<double>(0.5 * dpsi, hs, hc);
+  }
   // e^{-i dpsi} - 1 = -2 sin^2(dpsi/2) - i sin(dpsi)
   const cx<double> em1 = mk<double>(-2.0 * hs * hs, -2.0 * hs * hc);
   const cx<double> e = mk<double>(1.0 + em1.re, em1.im);
@@ -575,7 +585,7 @@ __device__ __forceinline__ void het_chunk(const WorkItem &it, int64_t chunk) {
 
 // Walkers of one item handled by one workgroup of the setup and totals
 // kernels (kWalkerTile walkers from w_begin), so that the item is uniform.
-constexpr int kWalkerTile = 128;
+constexpr int kWalkerTile = 64;
 struct WalkerTile {
   int32_t item, pad;
   int64_t w_begin;
