@@ -442,6 +442,28 @@ def side_measurements(M, ctx, S, walkers, grid):
     r = M.build_reference_coeffs(ctx, it["data"], M.MODEL_IMR, M.MODE_22, it["th"], N_BINS)
     out["reference_build_ms"] = (time.perf_counter() - t0) * 1e3
     r.close()
+    # reference update on the device (Sec. 3.2): the best walker of the
+    # population becomes the reference, rebuilt in place with no host sync
+    r = M.build_reference_coeffs(ctx, it["data"], M.MODEL_IMR, M.MODE_22, it["th"], N_BINS)
+    tw = torch.as_tensor(walkers[0], device="cuda")
+    lw = M.loglike_heterodyned(ctx, r, tw, M.FP64)
+    r.refresh(it["data"], tw, lw)  # the first update allocates the staging buffers
+    torch.cuda.synchronize()
+    st_r = torch.cuda.Stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    n_rep = 20
+    t0 = time.perf_counter()
+    e0.record(st_r)
+    for _ in range(n_rep):
+        r.refresh(it["data"], tw, lw, stream=st_r)
+    e1.record(st_r)
+    t_issue = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    res = r.refresh_result()
+    out["reference_refresh"] = {"device_us": e0.elapsed_time(e1) * 1e3 / n_rep, "host_issue_us": t_issue * 1e6 / n_rep,
+                                "status": res["status"], "generation": res["generation"]}
+    log(f"[bench] reference refresh on the device: {out['reference_refresh']}")
+    r.close()
     # ragged higher-mode batch: 16 sources, modes 1-6, N_b 64-512, W 128-4096
     shapes = I.batch_shapes(I.rng_for(4, 0), 16)
     S4 = Sources(M, ctx, grid, 16, modes_list=[s[0] for s in shapes], n_bins_list=[s[1] for s in shapes], cfg=4)

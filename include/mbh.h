@@ -142,6 +142,45 @@ mbh_status mbh_ref_get_info(const mbh_ref *ref, mbh_ref_info *out);
 mbh_status mbh_ref_export(const mbh_ref *ref, double *edges, int64_t *kb, double *A0, double *A1,
                           double *B0, double *B1, double *h0_edges);
 
+/* Reference update of Sec. 3.2 (the reference is replaced, every few
+ * thousand sampler iterations, by the highest-likelihood point of the
+ * population), done on the device with no host round trip.  Picks the
+ * walker with the largest finite lnL_dev[w] (the lowest index among equal
+ * values; NaN and +-inf are skipped) and rebuilds `ref` in place from
+ * theta_dev[w] exactly as mbh_build_reference_coeffs would: same model,
+ * modes and n_bins, new band, edges, bin assignment, coefficients, lnL(h0).
+ *   theta_dev [W][11] FP64 and lnL_dev [W] FP64 on the device, caller-owned
+ *   (typically the walkers and the heterodyned lnL the sampler holds);
+ *   `data` must be the data the reference was built on.
+ * Asynchronous on `stream`; nothing is synchronised.  Work issued later on
+ * `stream` (likelihood calls, batch launches, also batches created before
+ * the refresh: they read the reference's device arrays) sees the new
+ * reference; work on other streams must be ordered by the caller, and must
+ * not run on `ref` while the refresh does.  The outcome is known on the
+ * device only: if no walker has a finite lnL, the picked walker lies outside
+ * the model domain (MBH_EINVAL) or its template is empty on the grid or zero
+ * at an edge (MBH_EBAND), the reference is left unchanged; read the outcome
+ * with mbh_ref_refresh_result.  mbh_ref_get_info and mbh_ref_export wait for
+ * the last refresh and report the live reference.
+ * The first refresh of a reference allocates its staging and work buffers
+ * (about 16 B per grid point and channel, plus a few times the reference's
+ * size; freed with the reference) and synchronises `stream` once; later
+ * refreshes allocate nothing and only enqueue kernels.  The work buffers are
+ * the reference's own: refreshes of one reference must be ordered (issue
+ * them on one stream).
+ * Errors returned at once: MBH_EINVAL (null pointers, W < 1, another
+ * context, a data grid other than the reference's), MBH_ENOMEM,
+ * MBH_EDEVICE. */
+mbh_status mbh_ref_refresh(mbh_ctx *ctx, const mbh_data *data, mbh_ref *ref,
+                           const double *theta_dev, const double *lnL_dev, int64_t W,
+                           hipStream_t stream);
+/* Outcome of the last mbh_ref_refresh of `ref` (waits for it): its status
+ * (MBH_OK, or the reason the reference was left unchanged), the walker it
+ * picked (-1 if none) and the number of refreshes committed so far.  Before
+ * any refresh: MBH_OK, -1, 0.  Any out pointer may be NULL. */
+mbh_status mbh_ref_refresh_result(mbh_ref *ref, int32_t *status, int64_t *pick,
+                                  int32_t *generation);
+
 /* ---------------------------------------------------- likelihoods (a1-a8) */
 
 /* Heterodyned log-likelihood of W walkers against a reference (Sec. 2.2):

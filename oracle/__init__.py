@@ -292,3 +292,32 @@ class Reference:
         if rc != OK:
             raise ValueError("oracle_loglike_het failed")
         return lnL, dh, hh
+
+
+def best_walker(lnL) -> int:
+    """Walker that the reference update of Sec. 3.2 (the reference becomes the
+    highest-likelihood point of the population) moves to: the largest finite
+    lnL, the lowest index among equal values; -1 if no value is finite."""
+    v = np.asarray(lnL, dtype=np.float64).ravel()
+    ok = np.isfinite(v)
+    if not ok.any():
+        return -1
+    return int(np.flatnonzero(ok & (v == v[ok].max()))[0])
+
+
+def refresh_reference(ref: Reference, walkers, lnL):
+    """Sec. 3.2 reference update: (status, picked walker, new Reference with
+    the same model, modes and bin count built at that walker, or None).
+    status is EINVAL when no lnL is finite or the walker lies outside the
+    model domain, EBAND when its template is empty on the grid or zero at an
+    edge; the caller then keeps the old reference."""
+    pick = best_walker(lnL)
+    if pick < 0:
+        return EINVAL, -1, None
+    try:
+        new = Reference(ref.model, ref.modes, np.asarray(walkers)[pick], ref.data, ref.n_bins)
+    except ValueError:
+        return EINVAL, pick, None
+    if new.status != OK:
+        return new.status, pick, None
+    return OK, pick, new

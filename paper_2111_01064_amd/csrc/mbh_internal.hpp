@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "mbh.h"
+#include "mbh_kernels.hpp"
 
 struct mbh_ctx {
   int device = 0;
@@ -74,11 +75,37 @@ struct mbh_ref {
   int n_chan = 0, n_bins = 0;
   int64_t k_lo = 0, k_hi = 0;
   double t_obs = 0, lnL0 = 0, dd = 0, dh0 = 0, hh0 = 0;
-  // device: edges [E], response factors [E][3], carrier phase of h0 [E],
-  // 1/s0 [C][E][2], residual-form coefficients [C][Nb][6]
+  // device: edges [E], response factors [E][kFq], carrier phase of h0 [E],
+  // 1/s0 [C][E][2], residual-form coefficients [C][Nb][6], scalars
   double *F = nullptr, *fq = nullptr, *psi0 = nullptr, *is064 = nullptr, *coef = nullptr;
+  mbh::RefMeta *meta = nullptr;
+  // host copies for mbh_ref_get_info / mbh_ref_export (refreshed from the
+  // device after a refresh on the device)
   std::vector<double> edges, A0, A1, B0, B1, h0_edges;
   std::vector<int64_t> kb;
+  // the data grid the reference was built on
+  int64_t n_f = 0;
+  double f0 = 0, df = 0;
+  // refresh on the device (allocated at the first refresh): staging copies
+  // of the arrays above, and the export arrays (kb [E], paper-form
+  // coefficients [C][Nb][6], h0 at the edges [C][E][2]) live and staged
+  struct Refresh {
+    double *F = nullptr, *fq = nullptr, *psi0 = nullptr, *is064 = nullptr, *coef = nullptr;
+    mbh::RefMeta *meta = nullptr;
+    int64_t *kb = nullptr, *kb_live = nullptr;
+    double *paper = nullptr, *paper_live = nullptr, *h0e = nullptr, *h0e_live = nullptr;
+    // work buffers of the rebuild (kept, so that a refresh allocates nothing)
+    mbh::WalkerC *wc = nullptr;
+    unsigned long long *band = nullptr;
+    double2 *h0w = nullptr, *s0 = nullptr;
+    double *part1 = nullptr, *sums1 = nullptr, *part2 = nullptr, *sums2 = nullptr;
+    int nb1 = 0, n_sub = 0;
+    int64_t max_len = 0;
+    hipEvent_t done = nullptr;  // recorded after the last refresh's commit
+    int64_t issued = 0, mirrored = 0;
+  } rf;
+  bool rf_ready = false;
+  std::mutex mu;
 };
 
 mbh_status mbh_fail(mbh_status s, const char *fmt, ...);

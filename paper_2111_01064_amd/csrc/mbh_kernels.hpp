@@ -1,6 +1,7 @@
 // mbh_kernels.hpp -- HIP kernels of libmbh (gfx950).
 #pragma once
 
+#include "mbh.h"
 #include "mbh_device.hpp"
 
 namespace mbh {
@@ -14,17 +15,42 @@ constexpr int kBlock = 256;
 // per-edge frequency constants: FreqC's a, Cp, Cm, then FreqPow
 constexpr int kFq = 7;
 
+// Scalars of a reference that a refresh on the device may change, kept in
+// device memory next to its arrays.
+struct RefMeta {
+  double lnL0, dh0, hh0;  // lnL(h0), <d|h0>, <h0|h0>
+  int32_t ns64, ns32;     // sinc terms over the edges for FP64 / FP32
+  int64_t k_lo, k_hi;     // band in grid indices
+  // outcome of the last refresh: walker chosen (-1: none), mbh_status,
+  // refreshes committed so far
+  int64_t pick;
+  int32_t status, generation;
+};
+
 struct HetRef {
   const double *F;      // [E] bin edges
   const double *fq;     // [E][kFq] response factors a, Cp, Cm and FreqPow of each edge
   const double *psi0;   // [E] carrier phase of h0
   const double *is064;  // [C][E][2] 1/s0
   const double *coef;   // [C][Nb][6]
-  double lnL0, dh0, hh0, t_obs;
+  const RefMeta *meta;
+  double t_obs;
   int32_t n_bins, n_chan;
   uint32_t modes;
-  int32_t ns64, ns32;   // sinc terms over the edges for FP64 / FP32
+  int32_t ns64, ns32;   // meta's sinc term counts, loaded once per workgroup (with_meta)
 };
+
+// A reference view whose by-value copies of the scalars that a refresh may
+// change are read from its device block: done once at kernel entry, so that
+// the per-edge code reads them from registers.
+__device__ __forceinline__ HetRef with_meta(HetRef r) {
+  const RefMeta *m = r.meta;
+  // uniform by construction; readfirstlane keeps the loop counts in scalar
+  // registers (the load itself may be a vector load)
+  r.ns64 = __builtin_amdgcn_readfirstlane(m->ns64);
+  r.ns32 = __builtin_amdgcn_readfirstlane(m->ns32);
+  return r;
+}
 
 // ---------------------------------------------------------------- utilities
 // value of lane perm(i) within lane i's row of 16 (DPP control CTRL), for
@@ -152,7 +178,8 @@ static __global__ __launch_bounds__(kBlock) void k_ref_grid(const WalkerC *__res
                                                      int64_t n_f, double f0, double df, double t_obs,
                                                      const double2 *__restrict__ dw, const double *__restrict__ sw,
                                                      double2 *__restrict__ h0w, unsigned long long *band,
-                                                     double *__restrict__ part) {
+                                                     double *__restrict__ part, const RefMeta *gate) {
+  if (gate && gate->status != 0) return;
   __shared__ double sh[3 * (kBlock / 64)];
   const WalkerC &w = wc[0];
   double a_res = 0.0, a_dh = 0.0, a_hh = 0.0;
@@ -205,7 +232,9 @@ constexpr int kRefChunk = 4096;
 static __global__ __launch_bounds__(kBlock) void k_ref_bins(const int64_t *__restrict__ kb, const double *__restrict__ F,
                                                      int n_bins, int n_sub, int n_chan, int64_t n_f, double f0,
                                                      double df, const double2 *__restrict__ dw,
-                                                     const double2 *__restrict__ h0w, double *__restrict__ part) {
+                                                     const double2 *__restrict__ h0w, double *__restrict__ part,
+                                                     const RefMeta *gate) {
+  if (gate && gate->status != 0) return;
   __shared__ double sh[18 * (kBlock / 64)];
   const int b = blockIdx.x, sub = blockIdx.y;
   const int64_t k_begin = kb[b] + (int64_t)sub * kRefChunk;
@@ -257,7 +286,8 @@ static __global__ void k_sum_bins(const double *__restrict__ part, int n_sub, do
 static __global__ __launch_bounds__(64) void k_ref_edges(const WalkerC *__restrict__ wc, uint32_t modes, int n_chan,
                                                          int E, const double *__restrict__ F, double t_obs,
                                                          double *__restrict__ fq, double *__restrict__ psi0,
-                                                         double2 *__restrict__ s0) {
+                                                         double2 *__restrict__ s0, const RefMeta *gate) {
+  if (gate && gate->status != 0) return;
   int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= E) return;
   FreqC fc;
@@ -277,6 +307,219 @@ static __global__ __launch_bounds__(64) void k_ref_edges(const WalkerC *__restri
   bool any = template_point<double>(wc[0], modes, F[j], pw, fc, t_obs, s, psi);
   psi0[j] = psi;
   for (int c = 0; c < n_chan; ++c) s0[c * E + j] = any ? make_double2(s[c].re, s[c].im) : make_double2(0.0, 0.0);
+}
+
+// ---------------------------------------------------------------- reference refresh
+// Sec. 3.2 replaces the reference by the highest-likelihood point of the
+// population every few thousand sampler iterations.  On the device this is
+// the reference build above with its host steps moved into kernels: pick the
+// walker, then band, edges and bin assignment, then the coefficients, all
+// written to a staging copy that replaces the live reference only if every
+// step succeeded.  A failed step sets the staging status and the later
+// kernels return at once.
+
+// Best walker (largest finite lnL; the lowest index among equals), its
+// walker constants, and the band's initial value.  One block of 256.
+static __global__ __launch_bounds__(256) void k_refresh_pick(const double *__restrict__ theta,
+                                                             const double *__restrict__ lnL, int64_t W, int model,
+                                                             uint32_t modes, WalkerC *__restrict__ wc,
+                                                             unsigned long long *band, RefMeta *stg) {
+  __shared__ double sv[256];
+  __shared__ int64_t si[256];
+  __shared__ double th[11];
+  const int t = threadIdx.x;
+  double bv = 0.0;
+  int64_t bi = -1;
+  for (int64_t i = t; i < W; i += 256) {
+    const double v = lnL[i];
+    if (isfinite(v) && (bi < 0 || v > bv)) {
+      bv = v;
+      bi = i;
+    }
+  }
+  sv[t] = bv;
+  si[t] = bi;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h) {
+      const double v = sv[t + h];
+      const int64_t i = si[t + h];
+      if (i >= 0 && (si[t] < 0 || v > sv[t] || (v == sv[t] && i < si[t]))) {
+        sv[t] = v;
+        si[t] = i;
+      }
+    }
+    __syncthreads();
+  }
+  const int64_t pick = si[0];
+  if (pick >= 0 && t < 11) th[t] = theta[pick * 11 + t];
+  __syncthreads();
+  if (pick >= 0 && (t == 0 || t == 64)) walker_setup(th, model, modes, wc[0], t == 0 ? 1 : 2);
+  __syncthreads();
+  if (t == 0) {
+    stg->pick = pick;
+    stg->status = pick < 0 ? MBH_EINVAL : (wc[0].valid ? MBH_OK : MBH_EINVAL);
+    band[0] = ~0ull;
+    band[1] = 0ull;
+  }
+}
+
+// Band, log-spaced edges and the first grid index of each bin, with the same
+// roundings as the host build (the interior edges go through the device's
+// exp and log).  Fails if the band is empty or a bin holds more than
+// max_len grid points (the bound the bin-sum launch was sized for).  One
+// block of 256.
+#pragma clang fp contract(off)
+static __global__ __launch_bounds__(256) void k_refresh_edges(const unsigned long long *band, double f0, double df,
+                                                              int n_bins, int64_t max_len, double *__restrict__ F,
+                                                              int64_t *__restrict__ kb, RefMeta *stg) {
+  if (stg->status != 0) return;
+  __shared__ unsigned long long worst;
+  const unsigned long long lo = band[0], hi = band[1];
+  if (lo == ~0ull || hi <= lo) {
+    if (threadIdx.x == 0) stg->status = MBH_EBAND;
+    return;
+  }
+  if (threadIdx.x == 0) worst = 0ull;
+  const int64_t k_lo = (int64_t)lo, k_hi = (int64_t)hi;
+  const double F0 = grid_freq(f0, df, k_lo), FN = grid_freq(f0, df, k_hi);
+  const double l0 = log(F0), span = log(FN) - l0;
+  for (int j = threadIdx.x; j <= n_bins; j += blockDim.x) {
+    double e;
+    int64_t k;
+    if (j == 0) {
+      e = F0;
+      k = k_lo;
+    } else if (j == n_bins) {
+      e = FN;
+      k = k_hi + 1;
+    } else {
+      e = exp(l0 + (double)j * span / (double)n_bins);
+      int64_t a = k_lo, b = k_hi;  // smallest k with f_k >= e
+      while (a < b) {
+        const int64_t mid = a + (b - a) / 2;
+        if (grid_freq(f0, df, mid) >= e) b = mid;
+        else a = mid + 1;
+      }
+      k = a;
+    }
+    F[j] = e;
+    kb[j] = k;
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < n_bins; b += blockDim.x) {
+    const int64_t len = kb[b + 1] - kb[b];
+    if (len > max_len || len < 0) atomicMax(&worst, 1ull);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (worst) stg->status = MBH_EINVAL;
+    stg->k_lo = k_lo;
+    stg->k_hi = k_hi;
+  }
+}
+
+// Coefficients from the bin sums (as in the host build), 1/s0, h0 at the
+// edges in the paper's units and the reference scalars.  Fails if h0 is zero
+// or not finite at an edge.  One block of 256.
+static __global__ __launch_bounds__(256) void k_refresh_finish(const double *__restrict__ sums1,
+                                                               const double *__restrict__ sums2,
+                                                               const double2 *__restrict__ s0,
+                                                               const double *__restrict__ F,
+                                                               const double *__restrict__ psi0, int n_chan, int n_bins,
+                                                               double *__restrict__ coef, double *__restrict__ is064,
+                                                               double *__restrict__ paper, double *__restrict__ h0e,
+                                                               RefMeta *stg) {
+  if (stg->status != 0) return;
+  __shared__ int bad;
+  const int E = n_bins + 1, t = threadIdx.x;
+  if (t == 0) bad = 0;
+  __syncthreads();
+  for (int i = t; i < n_chan * E; i += blockDim.x) {
+    const double2 v = s0[i];
+    if (!(v.x != 0.0 || v.y != 0.0) || !isfinite(v.x) || !isfinite(v.y)) atomicOr(&bad, 1);
+  }
+  __syncthreads();
+  if (bad) {
+    if (t == 0) stg->status = MBH_EBAND;
+    return;
+  }
+  for (int o = t; o < n_chan * n_bins; o += blockDim.x) {
+    const int c = o / n_bins, b = o - c * n_bins;
+    const double *q = sums2 + (int64_t)b * 18 + c * 6;
+    // the grid sums carry w = 4 df / S; the coefficients carry df / S
+    const double amb0r = 0.25 * q[0], amb0i = 0.25 * q[1], amb1r = 0.25 * q[2], amb1i = 0.25 * q[3];
+    const double b0 = 0.25 * q[4], b1 = 0.25 * q[5];
+    const double idf = 1.0 / (F[b + 1] - F[b]);
+    double *k = coef + 6 * (int64_t)o;
+    k[0] = amb0r;
+    k[1] = amb0i;
+    k[2] = amb1r * idf;
+    k[3] = amb1i * idf;
+    k[4] = b0;
+    k[5] = b1 * idf;
+    double *p = paper + 6 * (int64_t)o;
+    p[0] = amb0r + b0;
+    p[1] = amb0i;
+    p[2] = amb1r + b1;
+    p[3] = amb1i;
+    p[4] = b0;
+    p[5] = b1;
+  }
+  for (int i = t; i < n_chan * E; i += blockDim.x) {
+    const double re = s0[i].x, im = s0[i].y;
+    const double den = re * re + im * im;
+    is064[2 * i] = re / den;
+    is064[2 * i + 1] = -im / den;
+    const int j = i % E;
+    const double ph = remainder(psi0[j], 2.0 * kPi);
+    const double cp = cos(ph), sp = sin(ph);
+    h0e[2 * i] = (re * cp + im * sp) / kAmpScale;
+    h0e[2 * i + 1] = (im * cp - re * sp) / kAmpScale;
+  }
+  if (t == 0) {
+    stg->lnL0 = -0.5 * sums1[0];
+    stg->dh0 = sums1[1];
+    stg->hh0 = sums1[2];
+    stg->ns64 = sinc_terms_for<double>(F[E - 1]);
+    stg->ns32 = sinc_terms_for<float>(F[E - 1]);
+  }
+}
+#pragma clang fp contract(on)
+
+// Arrays a refresh replaces, staging -> live, in one launch.
+struct RefreshCopy {
+  static constexpr int kMax = 8;
+  const double *src[kMax];
+  double *dst[kMax];
+  int64_t n[kMax];
+  int count;
+};
+
+// Copy staging to live if the refresh succeeded; record its outcome in the
+// live scalars either way.
+static __global__ __launch_bounds__(256) void k_refresh_commit(RefreshCopy cp, const RefMeta *stg, RefMeta *live) {
+  const bool ok = stg->status == 0;
+  if (ok) {
+    for (int a = 0; a < cp.count; ++a)
+      for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cp.n[a];
+           i += (int64_t)gridDim.x * blockDim.x)
+        cp.dst[a][i] = cp.src[a][i];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (ok) {
+      live->lnL0 = stg->lnL0;
+      live->dh0 = stg->dh0;
+      live->hh0 = stg->hh0;
+      live->ns64 = stg->ns64;
+      live->ns32 = stg->ns32;
+      live->k_lo = stg->k_lo;
+      live->k_hi = stg->k_hi;
+      live->generation += 1;
+    }
+    live->pick = stg->pick;
+    live->status = stg->status;
+  }
 }
 
 // ---------------------------------------------------------------- a2-a7: heterodyned
@@ -615,10 +858,11 @@ static __global__ __launch_bounds__(kWalkerTile) void k_het_final(const WorkItem
 #pragma unroll
     for (int q = 0; q < 3; ++q) s[q] += p[4 * k + q];
   const bool valid = it.wc[w].valid;
-  it.lnL[w] = valid ? it.ref.lnL0 + s[0] : -INFINITY;
+  const RefMeta &m = *it.ref.meta;
+  it.lnL[w] = valid ? m.lnL0 + s[0] : -INFINITY;
   if (it.dhhh) {
-    it.dhhh[2 * w] = valid ? it.ref.dh0 + s[1] : 0.0;
-    it.dhhh[2 * w + 1] = valid ? it.ref.hh0 + s[2] : 0.0;
+    it.dhhh[2 * w] = valid ? m.dh0 + s[1] : 0.0;
+    it.dhhh[2 * w + 1] = valid ? m.hh0 + s[2] : 0.0;
   }
 }
 
@@ -632,12 +876,14 @@ static __global__ __launch_bounds__(128) void k_setup_one(WorkItem one) {
 // single-item launches of the main pass
 template <typename R, int G, bool DH>
 __global__ __launch_bounds__(kBlock, 2) void k_het_lane(WorkItem one) {
+  one.ref = with_meta(one.ref);
   het_walker<R, G, DH>(one, (int64_t)blockIdx.x * (kBlock / G) + threadIdx.x / G);
 }
 
 template <typename R, bool DH>
 __global__ __launch_bounds__(kBlock, 2) void k_het_flat(WorkItem one, int64_t n_chunks) {
   const int64_t c = (int64_t)blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  one.ref = with_meta(one.ref);
   if (c < n_chunks) het_chunk<R, DH>(one, c);
 }
 

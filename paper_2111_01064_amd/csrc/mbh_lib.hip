@@ -310,8 +310,37 @@ static void release_ref_dev(mbh_ref *r) {
   ctx_free(c, r->psi0, E * sizeof(double));
   ctx_free(c, r->fq, (size_t)E * kFq * sizeof(double));
   ctx_free(c, r->is064, (size_t)r->n_chan * E * 2 * sizeof(double));
-  ctx_free(c, r->coef, (size_t)r->n_chan * r->n_bins * 6 * sizeof(double));
+  const size_t nce = (size_t)r->n_chan * E, ncb = (size_t)r->n_chan * r->n_bins;
+  ctx_free(c, r->coef, ncb * 6 * sizeof(double));
+  ctx_free(c, r->meta, sizeof(RefMeta));
   r->F = r->psi0 = r->fq = r->is064 = r->coef = nullptr;
+  r->meta = nullptr;
+  if (r->rf_ready) {
+    auto &f = r->rf;
+    ctx_free(c, f.F, E * sizeof(double));
+    ctx_free(c, f.psi0, E * sizeof(double));
+    ctx_free(c, f.fq, (size_t)E * kFq * sizeof(double));
+    ctx_free(c, f.is064, nce * 2 * sizeof(double));
+    ctx_free(c, f.coef, ncb * 6 * sizeof(double));
+    ctx_free(c, f.meta, sizeof(RefMeta));
+    ctx_free(c, f.kb, E * sizeof(int64_t));
+    ctx_free(c, f.kb_live, E * sizeof(int64_t));
+    ctx_free(c, f.paper, ncb * 6 * sizeof(double));
+    ctx_free(c, f.paper_live, ncb * 6 * sizeof(double));
+    ctx_free(c, f.h0e, nce * 2 * sizeof(double));
+    ctx_free(c, f.h0e_live, nce * 2 * sizeof(double));
+    ctx_free(c, f.wc, sizeof(WalkerC));
+    ctx_free(c, f.band, 2 * sizeof(unsigned long long));
+    ctx_free(c, f.h0w, (size_t)r->n_f * r->n_chan * sizeof(double2));
+    ctx_free(c, f.s0, nce * sizeof(double2));
+    ctx_free(c, f.part1, (size_t)f.nb1 * 3 * sizeof(double));
+    ctx_free(c, f.sums1, 3 * sizeof(double));
+    ctx_free(c, f.part2, (size_t)r->n_bins * f.n_sub * 18 * sizeof(double));
+    ctx_free(c, f.sums2, (size_t)r->n_bins * 18 * sizeof(double));
+    if (f.done) (void)hipEventDestroy(f.done);
+    f = mbh_ref::Refresh{};
+    r->rf_ready = false;
+  }
 }
 
 extern "C" mbh_status mbh_ref_release(mbh_ref *r) {
@@ -366,7 +395,7 @@ extern "C" mbh_status mbh_build_reference_coeffs(mbh_ctx *ctx, const mbh_data *d
   MBH_TRY(sc.get(&sums1, 3));
   hipLaunchKernelGGL(k_init_band, dim3(1), dim3(1), 0, st, band);
   hipLaunchKernelGGL(k_ref_grid, dim3(nb1), dim3(kBlock), 0, st, wc, modes, C, N, data->f0, data->df,
-                     data->t_obs, data->dw64, data->sw64, h0w, band, part1);
+                     data->t_obs, data->dw64, data->sw64, h0w, band, part1, nullptr);
   hipLaunchKernelGGL(k_sum_partials, dim3(3), dim3(64), 0, st, part1, nb1, 3, 3, sums1);
   HIP_TRY(hipGetLastError());
   unsigned long long hb[2];
@@ -406,6 +435,9 @@ extern "C" mbh_status mbh_build_reference_coeffs(mbh_ctx *ctx, const mbh_data *d
   r->k_lo = k_lo;
   r->k_hi = k_hi;
   r->t_obs = data->t_obs;
+  r->n_f = N;
+  r->f0 = data->f0;
+  r->df = data->df;
   r->edges = edges;
   r->kb = kb;
   auto fail_free = [&](mbh_status s) {
@@ -420,6 +452,7 @@ extern "C" mbh_status mbh_build_reference_coeffs(mbh_ctx *ctx, const mbh_data *d
   if ((s = ctx_alloc(ctx, (void **)&r->is064, (size_t)C * E * 2 * sizeof(double))) != MBH_OK) return fail_free(s);
   if ((s = ctx_alloc(ctx, (void **)&r->coef, (size_t)C * n_bins * 6 * sizeof(double))) != MBH_OK)
     return fail_free(s);
+  if ((s = ctx_alloc(ctx, (void **)&r->meta, sizeof(RefMeta))) != MBH_OK) return fail_free(s);
   int64_t *kb_dev = nullptr;
   double *part2 = nullptr, *sums2 = nullptr;
   double2 *s0 = nullptr;
@@ -431,11 +464,11 @@ extern "C" mbh_status mbh_build_reference_coeffs(mbh_ctx *ctx, const mbh_data *d
       hipMemcpyAsync(kb_dev, kb.data(), E * sizeof(int64_t), hipMemcpyHostToDevice, st) != hipSuccess)
     return fail_free(mbh_fail(MBH_EDEVICE, "upload edges"));
   hipLaunchKernelGGL(k_ref_bins, dim3(n_bins, n_sub), dim3(kBlock), 0, st, kb_dev, r->F, n_bins, n_sub, C, N,
-                     data->f0, data->df, data->dw64, h0w, part2);
+                     data->f0, data->df, data->dw64, h0w, part2, nullptr);
   // sum the n_sub chunks of each bin in order: part2 is [Nb][n_sub][18]
   hipLaunchKernelGGL(k_sum_bins, dim3(n_bins), dim3(64), 0, st, part2, n_sub, sums2);
   hipLaunchKernelGGL(k_ref_edges, dim3((E + 63) / 64), dim3(64), 0, st, wc, r->modes, C, E, r->F, data->t_obs,
-                     r->fq, r->psi0, s0);
+                     r->fq, r->psi0, s0, nullptr);
   if (hipGetLastError() != hipSuccess) return fail_free(mbh_fail(MBH_EDEVICE, "reference kernels"));
   std::vector<double> hs2((size_t)n_bins * 18), hs0((size_t)C * E * 2);
   if (hipMemcpyAsync(hs2.data(), sums2, hs2.size() * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -507,16 +540,64 @@ extern "C" mbh_status mbh_build_reference_coeffs(mbh_ctx *ctx, const mbh_data *d
         r->h0_edges[2 * (c * E + j) + 1] = (im * cp - re * sp) / kAmpScale;
       }
   }
+  RefMeta m{};
+  m.lnL0 = r->lnL0;
+  m.dh0 = r->dh0;
+  m.hh0 = r->hh0;
+  m.ns64 = sinc_terms_for<double>(edges.back());
+  m.ns32 = sinc_terms_for<float>(edges.back());
+  m.k_lo = k_lo;
+  m.k_hi = k_hi;
+  m.pick = -1;
   if (hipMemcpyAsync(r->coef, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemcpyAsync(r->is064, is64.data(), is64.size() * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(r->meta, &m, sizeof(m), hipMemcpyHostToDevice, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     return fail_free(mbh_fail(MBH_EDEVICE, "upload coefficients"));
   *out = r;
   return MBH_OK;
 }
 
+// After a refresh on the device, bring the host copies of the reference up
+// to date (waits for the last refresh).
+static mbh_status sync_mirror(const mbh_ref *rc) {
+  mbh_ref *r = const_cast<mbh_ref *>(rc);
+  std::lock_guard<std::mutex> g(r->mu);
+  if (!r->rf_ready || r->rf.mirrored == r->rf.issued) return MBH_OK;
+  HIP_TRY(hipSetDevice(r->ctx->device));
+  HIP_TRY(hipEventSynchronize(r->rf.done));
+  const int C = r->n_chan, Nb = r->n_bins, E = Nb + 1;
+  RefMeta m;
+  std::vector<double> paper((size_t)C * Nb * 6), h0e((size_t)C * E * 2), F(E);
+  std::vector<int64_t> kb(E);
+  HIP_TRY(hipMemcpy(&m, r->meta, sizeof(m), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(F.data(), r->F, E * sizeof(double), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(kb.data(), r->rf.kb_live, E * sizeof(int64_t), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(paper.data(), r->rf.paper_live, paper.size() * sizeof(double), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(h0e.data(), r->rf.h0e_live, h0e.size() * sizeof(double), hipMemcpyDeviceToHost));
+  r->lnL0 = m.lnL0;
+  r->dh0 = m.dh0;
+  r->hh0 = m.hh0;
+  r->k_lo = m.k_lo;
+  r->k_hi = m.k_hi;
+  r->edges = F;
+  r->kb = kb;
+  r->h0_edges = h0e;
+  for (size_t o = 0; o < (size_t)C * Nb; ++o) {
+    r->A0[2 * o] = paper[6 * o + 0];
+    r->A0[2 * o + 1] = paper[6 * o + 1];
+    r->A1[2 * o] = paper[6 * o + 2];
+    r->A1[2 * o + 1] = paper[6 * o + 3];
+    r->B0[o] = paper[6 * o + 4];
+    r->B1[o] = paper[6 * o + 5];
+  }
+  r->rf.mirrored = r->rf.issued;
+  return MBH_OK;
+}
+
 extern "C" mbh_status mbh_ref_get_info(const mbh_ref *r, mbh_ref_info *o) {
   if (!r || !o) return mbh_fail(MBH_EINVAL, "null argument");
+  MBH_TRY(sync_mirror(r));
   o->model = r->model;
   o->n_chan = r->n_chan;
   o->n_bins = r->n_bins;
@@ -533,6 +614,7 @@ extern "C" mbh_status mbh_ref_get_info(const mbh_ref *r, mbh_ref_info *o) {
 extern "C" mbh_status mbh_ref_export(const mbh_ref *r, double *edges, int64_t *kb, double *A0, double *A1,
                                      double *B0, double *B1, double *h0_edges) {
   if (!r) return mbh_fail(MBH_EINVAL, "null reference");
+  MBH_TRY(sync_mirror(r));
   if (edges) std::memcpy(edges, r->edges.data(), r->edges.size() * sizeof(double));
   if (kb) std::memcpy(kb, r->kb.data(), r->kb.size() * sizeof(int64_t));
   if (A0) std::memcpy(A0, r->A0.data(), r->A0.size() * sizeof(double));
@@ -543,6 +625,148 @@ extern "C" mbh_status mbh_ref_export(const mbh_ref *r, double *edges, int64_t *k
   return MBH_OK;
 }
 
+// staging and export buffers of the refresh, allocated once per reference;
+// the live export arrays start as the host build's values
+static mbh_status refresh_alloc(mbh_ref *r, hipStream_t st) {
+  if (r->rf_ready) return MBH_OK;
+  mbh_ctx *ctx = r->ctx;
+  const int C = r->n_chan, Nb = r->n_bins, E = Nb + 1;
+  const size_t nce = (size_t)C * E, ncb = (size_t)C * Nb;
+  mbh_ref::Refresh f;
+  // grid points of the widest bin: the last (log spacing), at most
+  // f_max (1 - (f_min / f_max)^(1 / Nb)) / df + 1, plus slack for rounding
+  const int64_t N = r->n_f;
+  const double fmax = r->f0 + (double)(N - 1) * r->df;
+  f.max_len = N;
+  if (r->f0 > 0.0 && fmax > r->f0) {
+    const double len = -fmax * std::expm1(-std::log(fmax / r->f0) / Nb) / r->df;
+    f.max_len = std::min<int64_t>(N, (int64_t)std::ceil(len) + 3);
+  }
+  f.n_sub = (int)std::max<int64_t>(1, (f.max_len + kRefChunk - 1) / kRefChunk);
+  f.nb1 = grid_blocks(N, 4 * ctx->n_cu);
+  std::vector<std::pair<void **, size_t>> want = {
+      {(void **)&f.wc, sizeof(WalkerC)},
+      {(void **)&f.band, 2 * sizeof(unsigned long long)},
+      {(void **)&f.h0w, (size_t)N * C * sizeof(double2)},
+      {(void **)&f.s0, nce * sizeof(double2)},
+      {(void **)&f.part1, (size_t)f.nb1 * 3 * sizeof(double)},
+      {(void **)&f.sums1, 3 * sizeof(double)},
+      {(void **)&f.part2, (size_t)Nb * f.n_sub * 18 * sizeof(double)},
+      {(void **)&f.sums2, (size_t)Nb * 18 * sizeof(double)},
+      {(void **)&f.F, E * sizeof(double)},          {(void **)&f.psi0, E * sizeof(double)},
+      {(void **)&f.fq, (size_t)E * kFq * sizeof(double)}, {(void **)&f.is064, nce * 2 * sizeof(double)},
+      {(void **)&f.coef, ncb * 6 * sizeof(double)},  {(void **)&f.meta, sizeof(RefMeta)},
+      {(void **)&f.kb, E * sizeof(int64_t)},         {(void **)&f.kb_live, E * sizeof(int64_t)},
+      {(void **)&f.paper, ncb * 6 * sizeof(double)}, {(void **)&f.paper_live, ncb * 6 * sizeof(double)},
+      {(void **)&f.h0e, nce * 2 * sizeof(double)},   {(void **)&f.h0e_live, nce * 2 * sizeof(double)}};
+  size_t done = 0;
+  mbh_status s = MBH_OK;
+  for (; done < want.size(); ++done)
+    if ((s = ctx_alloc(ctx, want[done].first, want[done].second)) != MBH_OK) break;
+  if (s == MBH_OK && hipEventCreateWithFlags(&f.done, hipEventDisableTiming) != hipSuccess)
+    s = mbh_fail(MBH_EDEVICE, "refresh event");
+  std::vector<double> paper(ncb * 6);
+  for (size_t o = 0; o < ncb && s == MBH_OK; ++o) {
+    paper[6 * o + 0] = r->A0[2 * o];
+    paper[6 * o + 1] = r->A0[2 * o + 1];
+    paper[6 * o + 2] = r->A1[2 * o];
+    paper[6 * o + 3] = r->A1[2 * o + 1];
+    paper[6 * o + 4] = r->B0[o];
+    paper[6 * o + 5] = r->B1[o];
+  }
+  if (s == MBH_OK &&
+      (hipMemcpyAsync(f.kb_live, r->kb.data(), E * sizeof(int64_t), hipMemcpyHostToDevice, st) != hipSuccess ||
+       hipMemcpyAsync(f.paper_live, paper.data(), paper.size() * sizeof(double), hipMemcpyHostToDevice, st) !=
+           hipSuccess ||
+       hipMemcpyAsync(f.h0e_live, r->h0_edges.data(), nce * 2 * sizeof(double), hipMemcpyHostToDevice, st) !=
+           hipSuccess ||
+       hipStreamSynchronize(st) != hipSuccess))
+    s = mbh_fail(MBH_EDEVICE, "refresh set-up");
+  if (s != MBH_OK) {
+    for (size_t i = 0; i < done; ++i) ctx_free(ctx, *want[i].first, want[i].second);
+    if (f.done) (void)hipEventDestroy(f.done);
+    return s;
+  }
+  r->rf = f;
+  r->rf_ready = true;
+  return MBH_OK;
+}
+
+extern "C" mbh_status mbh_ref_refresh(mbh_ctx *ctx, const mbh_data *data, mbh_ref *r, const double *theta_dev,
+                                      const double *lnL_dev, int64_t W, hipStream_t st) {
+  if (!ctx || !data || !r || !theta_dev || !lnL_dev) return mbh_fail(MBH_EINVAL, "null argument");
+  if (W < 1) return mbh_fail(MBH_EINVAL, "W = %lld", (long long)W);
+  if (r->ctx != ctx || data->ctx != ctx) return mbh_fail(MBH_EINVAL, "reference or data from another context");
+  if (data->n_chan != r->n_chan || data->n_f != r->n_f || data->f0 != r->f0 || data->df != r->df ||
+      data->t_obs != r->t_obs)
+    return mbh_fail(MBH_EINVAL, "data grid differs from the one the reference was built on");
+  HIP_TRY(hipSetDevice(ctx->device));
+  std::lock_guard<std::mutex> g(r->mu);
+  MBH_TRY(refresh_alloc(r, st));
+  const int C = r->n_chan, Nb = r->n_bins, E = Nb + 1;
+  const int64_t N = data->n_f;
+  const double f0 = data->f0, df = data->df;
+  auto &f = r->rf;
+  WalkerC *wc = f.wc;
+  unsigned long long *band = f.band;
+  double2 *h0w = f.h0w, *s0 = f.s0;
+  double *part1 = f.part1, *sums1 = f.sums1, *part2 = f.part2, *sums2 = f.sums2;
+  const int nb1 = f.nb1, n_sub = f.n_sub;
+  const int64_t max_len = f.max_len;
+  hipLaunchKernelGGL(k_refresh_pick, dim3(1), dim3(256), 0, st, theta_dev, lnL_dev, W, r->model, r->modes, wc, band,
+                     f.meta);
+  hipLaunchKernelGGL(k_ref_grid, dim3(nb1), dim3(kBlock), 0, st, wc, r->modes, C, N, f0, df, data->t_obs, data->dw64,
+                     data->sw64, h0w, band, part1, f.meta);
+  hipLaunchKernelGGL(k_sum_partials, dim3(3), dim3(64), 0, st, part1, nb1, 3, 3, sums1);
+  hipLaunchKernelGGL(k_refresh_edges, dim3(1), dim3(256), 0, st, band, f0, df, Nb, max_len, f.F, f.kb, f.meta);
+  hipLaunchKernelGGL(k_ref_bins, dim3(Nb, n_sub), dim3(kBlock), 0, st, f.kb, f.F, Nb, n_sub, C, N, f0, df,
+                     data->dw64, h0w, part2, f.meta);
+  hipLaunchKernelGGL(k_sum_bins, dim3(Nb), dim3(64), 0, st, part2, n_sub, sums2);
+  hipLaunchKernelGGL(k_ref_edges, dim3((E + 63) / 64), dim3(64), 0, st, wc, r->modes, C, E, f.F, data->t_obs, f.fq,
+                     f.psi0, s0, f.meta);
+  hipLaunchKernelGGL(k_refresh_finish, dim3(1), dim3(256), 0, st, sums1, sums2, s0, f.F, f.psi0, C, Nb, f.coef,
+                     f.is064, f.paper, f.h0e, f.meta);
+  // 8-byte words: kb is copied as raw words like the doubles
+  RefreshCopy cp{};
+  auto add = [&](const void *src, void *dst, int64_t n) {
+    cp.src[cp.count] = (const double *)src;
+    cp.dst[cp.count] = (double *)dst;
+    cp.n[cp.count] = n;
+    ++cp.count;
+  };
+  add(f.F, r->F, E);
+  add(f.fq, r->fq, (int64_t)E * kFq);
+  add(f.psi0, r->psi0, E);
+  add(f.is064, r->is064, (int64_t)C * E * 2);
+  add(f.coef, r->coef, (int64_t)C * Nb * 6);
+  add(f.kb, f.kb_live, E);
+  add(f.paper, f.paper_live, (int64_t)C * Nb * 6);
+  add(f.h0e, f.h0e_live, (int64_t)C * E * 2);
+  hipLaunchKernelGGL(k_refresh_commit, dim3(8), dim3(256), 0, st, cp, (const RefMeta *)f.meta, r->meta);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipEventRecord(f.done, st));
+  ++f.issued;
+  return MBH_OK;
+}
+
+extern "C" mbh_status mbh_ref_refresh_result(mbh_ref *r, int32_t *status, int64_t *pick, int32_t *generation) {
+  if (!r) return mbh_fail(MBH_EINVAL, "null reference");
+  RefMeta m{};
+  m.pick = -1;
+  {
+    std::lock_guard<std::mutex> g(r->mu);
+    if (r->rf_ready && r->rf.issued > 0) {
+      HIP_TRY(hipSetDevice(r->ctx->device));
+      HIP_TRY(hipEventSynchronize(r->rf.done));
+      HIP_TRY(hipMemcpy(&m, r->meta, sizeof(m), hipMemcpyDeviceToHost));
+    }
+  }
+  if (status) *status = m.status;
+  if (pick) *pick = m.pick;
+  if (generation) *generation = m.generation;
+  return MBH_OK;
+}
+
 HetRef ref_view(const mbh_ref *r) {
   HetRef h;
   h.F = r->F;
@@ -550,15 +774,12 @@ HetRef ref_view(const mbh_ref *r) {
   h.fq = r->fq;
   h.is064 = r->is064;
   h.coef = r->coef;
-  h.lnL0 = r->lnL0;
-  h.dh0 = r->dh0;
-  h.hh0 = r->hh0;
+  h.meta = r->meta;
   h.t_obs = r->t_obs;
   h.n_bins = r->n_bins;
   h.n_chan = r->n_chan;
   h.modes = r->modes;
-  h.ns64 = sinc_terms_for<double>(r->edges.back());
-  h.ns32 = sinc_terms_for<float>(r->edges.back());
+  h.ns64 = h.ns32 = 0;  // set from meta on the device
   return h;
 }
 

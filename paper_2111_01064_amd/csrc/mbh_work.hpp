@@ -42,7 +42,8 @@ __global__ __launch_bounds__(kBlock, 2) void k_het_tiles(const WorkItem *__restr
                                                          const WorkTile *__restrict__ tiles) {
   const WorkTile tl = tiles[blockIdx.x];
   // the item's fields are uniform: load them once, up front, into scalars
-  const WorkItem it = items[tl.item];
+  WorkItem it = items[tl.item];
+  it.ref = with_meta(it.ref);
   if constexpr (G == 0) {
     const int64_t c = tl.begin + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (c < flat_chunks(it.W, it.E)) het_chunk<R, DH>(it, c);

@@ -72,6 +72,8 @@ _SIGS = {
     "mbh_ref_release": [_vp],
     "mbh_ref_get_info": [_vp, ct.POINTER(_RefInfo)],
     "mbh_ref_export": [_vp, _dp, ct.POINTER(ct.c_int64), _dp, _dp, _dp, _dp, _dp],
+    "mbh_ref_refresh": [_vp, _vp, _vp, _vp, _vp, _i64, _vp],
+    "mbh_ref_refresh_result": [_vp, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int32)],
     "mbh_loglike_heterodyned": [_vp, _vp, _vp, _i64, _i32, _vp, _vp, _vp],
     "mbh_loglike_full": [_vp, _vp, _i32, _u32, _vp, _i64, _i32, _vp, _vp, _vp],
     "mbh_batch_create": [_vp, _i32, _pp, _pp, ct.POINTER(ct.c_int64), _pp, _pp, _i32, _pp],
@@ -179,10 +181,28 @@ class Data:
 class Reference:
     def __init__(self, ctx: Context, h):
         self.ctx, self.h = ctx, h
+        info = self.info
+        self.n_bins, self.n_chan = info["n_bins"], info["n_chan"]
+
+    @property
+    def info(self) -> dict:
+        """mbh_ref_get_info (waits for a pending refresh)."""
         info = _RefInfo()
-        _check(_L.mbh_ref_get_info(h, ct.byref(info)), "mbh_ref_get_info")
-        self.info = {k: getattr(info, k) for k, _ in _RefInfo._fields_}
-        self.n_bins, self.n_chan = info.n_bins, info.n_chan
+        _check(_L.mbh_ref_get_info(self.h, ct.byref(info)), "mbh_ref_get_info")
+        return {k: getattr(info, k) for k, _ in _RefInfo._fields_}
+
+    def refresh(self, data: "Data", theta: torch.Tensor, lnL: torch.Tensor, stream=None):
+        """mbh_ref_refresh: rebuild in place from the walker with the largest finite lnL (device tensors)."""
+        W = theta.shape[0]
+        _check(_L.mbh_ref_refresh(self.ctx.h, data.h, self.h, _dev_ptr(theta, torch.float64, (W, NPARAM)),
+                                  _dev_ptr(lnL, torch.float64, (W,)), W, _stream(stream)), "mbh_ref_refresh")
+
+    def refresh_result(self) -> dict:
+        """mbh_ref_refresh_result: status, picked walker and refreshes committed."""
+        st, pick, gen = ct.c_int32(), ct.c_int64(), ct.c_int32()
+        _check(_L.mbh_ref_refresh_result(self.h, ct.byref(st), ct.byref(pick), ct.byref(gen)),
+               "mbh_ref_refresh_result")
+        return dict(status=st.value, pick=pick.value, generation=gen.value)
 
     def export(self) -> dict:
         nb, nc = self.n_bins, self.n_chan

@@ -256,3 +256,56 @@ def test_chirp_het_vs_full_method_error_is_small_near_truth():
     near = (lf - lf.max()) > -50
     # method (not implementation) error of 64 bins near the peak: a few 1e-2
     assert np.all(np.abs(lh - lf)[near] < 0.1)
+
+
+# ----------------------------------------------------------------- reference update (Sec. 3.2)
+def _best_by_definition(v):
+    """Brute force: the first index i with v[i] finite and no finite value above it."""
+    fin = [i for i in range(len(v)) if math.isfinite(v[i])]
+    for i in fin:
+        if all(v[j] <= v[i] for j in fin):
+            return i
+    return -1
+
+
+def test_best_walker_brute_force():
+    rng = np.random.default_rng(5)
+    specials = [np.nan, np.inf, -np.inf]
+    for trial in range(300):
+        n = int(rng.integers(0, 12))
+        v = rng.integers(-3, 3, size=n).astype(np.float64)  # many ties
+        for i in range(n):
+            if rng.random() < 0.25:
+                v[i] = specials[int(rng.integers(0, 3))]
+        assert O.best_walker(v) == _best_by_definition(list(v)), v
+    assert O.best_walker([]) == -1
+    assert O.best_walker([np.nan, -np.inf, np.inf]) == -1
+    assert O.best_walker([np.inf, 1.0, 1.0]) == 1
+    assert O.best_walker([-5.0, 2.0, np.nan, 2.0]) == 1
+
+
+def test_refresh_reference_rebuilds_at_the_best_walker():
+    g = I.grid_lisa_small(2048, 0.05)
+    rng = I.rng_for(2, 11)
+    th, _ = I.draw_mbhb_source(rng, g.t_obs)
+    psd = I.psd_lisa_aet(g.freqs)
+    d = O.template(O.MODEL_IMR, O.MODE_22, th, g.freqs, g.t_obs)
+    data = O.Data(d, psd, g.f0, g.df, g.t_obs)
+    ref = O.Reference(O.MODEL_IMR, O.MODE_22, th, data, 32)
+    w = I.walker_cloud(th, np.abs(th) * 1e-4 + 1e-6, (1, 4), 4, rng)
+    lnl, _, _ = ref.loglike(w)
+    st, pick, new = O.refresh_reference(ref, w, lnl)
+    assert st == O.OK and pick == int(np.argmax(lnl))
+    direct = O.Reference(O.MODEL_IMR, O.MODE_22, w[pick], data, 32)
+    assert new.n_bins == 32 and new.k_lo == direct.k_lo and new.k_hi == direct.k_hi
+    for name in ("edges", "kb", "A0", "A1", "B0", "B1", "h0_edges"):
+        assert np.array_equal(getattr(new, name), getattr(direct, name)), name
+    # failures leave the caller with the old reference
+    assert O.refresh_reference(ref, w, np.full(len(w), -np.inf))[:2] == (O.EINVAL, -1)
+    bad = w.copy()
+    bad[0, 1] = 2.0  # q outside (0.05, 1]
+    assert O.refresh_reference(ref, bad, np.arange(len(w))[::-1].astype(float))[:2] == (O.EINVAL, 0)
+    late = w.copy()
+    late[0, 10] = -1e3 * g.t_obs  # the whole signal lies before the observation
+    st, pick, new = O.refresh_reference(ref, late, np.arange(len(w))[::-1].astype(float))
+    assert (st, pick, new) == (O.EBAND, 0, None)
