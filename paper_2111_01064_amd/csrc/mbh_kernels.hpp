@@ -44,11 +44,13 @@ struct HetRef {
 // change are read from its device block: done once at kernel entry, so that
 // the per-edge code reads them from registers.
 __device__ __forceinline__ HetRef with_meta(HetRef r) {
-  const RefMeta *m = r.meta;
-  // uniform by construction; readfirstlane keeps the loop counts in scalar
-  // registers (the load itself may be a vector load)
-  r.ns64 = __builtin_amdgcn_readfirstlane(m->ns64);
-  r.ns32 = __builtin_amdgcn_readfirstlane(m->ns32);
+  // read through the constant address space: the block does not change
+  // while a likelihood kernel runs, so the load is a scalar one and the term
+  // counts stay in scalar registers
+  typedef const RefMeta __attribute__((address_space(4))) ConstMeta;
+  ConstMeta *m = (ConstMeta *)(uintptr_t)r.meta;
+  r.ns64 = m->ns64;
+  r.ns32 = m->ns32;
   return r;
 }
 
@@ -140,6 +142,7 @@ static __global__ __launch_bounds__(64) void k_sum_partials(const double *__rest
   const int i = blockIdx.x;
   if (i >= n_out) return;
   double s = 0.0;
+#pragma unroll 4
   for (int b = threadIdx.x; b < n_part; b += 64) s += part[(int64_t)b * stride + i];
   s = wave_sum(s);
   if (threadIdx.x == 0) out[i] = s;
@@ -271,14 +274,18 @@ static __global__ __launch_bounds__(kBlock) void k_ref_bins(const int64_t *__res
   }
 }
 
-// sum the chunks of each bin in a fixed order: part [Nb][n_sub][18] -> out [Nb][18]
-static __global__ void k_sum_bins(const double *__restrict__ part, int n_sub, double *__restrict__ out) {
-  const int b = blockIdx.x;
-  for (int i = threadIdx.x; i < 18; i += blockDim.x) {
-    double s = 0.0;
-    for (int sub = 0; sub < n_sub; ++sub) s += part[((int64_t)b * n_sub + sub) * 18 + i];
-    out[(int64_t)b * 18 + i] = s;
-  }
+// sum the chunks of each bin in a fixed order: part [Nb][n_sub][18] -> out
+// [Nb][18], one thread per (bin, value); the loads run ahead of the adds
+static __global__ __launch_bounds__(256) void k_sum_bins(const double *__restrict__ part, int n_bins, int n_sub,
+                                                         double *__restrict__ out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_bins * 18) return;
+  const int b = t / 18, i = t - b * 18;
+  const double *p = part + (int64_t)b * n_sub * 18 + i;
+  double s = 0.0;
+#pragma unroll 8
+  for (int sub = 0; sub < n_sub; ++sub) s += p[(int64_t)sub * 18];
+  out[t] = s;
 }
 
 // pass 3: response factors of the edges, carrier phase and small factors of

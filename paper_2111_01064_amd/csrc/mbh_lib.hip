@@ -466,7 +466,7 @@ extern "C" mbh_status mbh_build_reference_coeffs(mbh_ctx *ctx, const mbh_data *d
   hipLaunchKernelGGL(k_ref_bins, dim3(n_bins, n_sub), dim3(kBlock), 0, st, kb_dev, r->F, n_bins, n_sub, C, N,
                      data->f0, data->df, data->dw64, h0w, part2, nullptr);
   // sum the n_sub chunks of each bin in order: part2 is [Nb][n_sub][18]
-  hipLaunchKernelGGL(k_sum_bins, dim3(n_bins), dim3(64), 0, st, part2, n_sub, sums2);
+  hipLaunchKernelGGL(k_sum_bins, dim3((n_bins * 18 + 255) / 256), dim3(256), 0, st, part2, n_bins, n_sub, sums2);
   hipLaunchKernelGGL(k_ref_edges, dim3((E + 63) / 64), dim3(64), 0, st, wc, r->modes, C, E, r->F, data->t_obs,
                      r->fq, r->psi0, s0, nullptr);
   if (hipGetLastError() != hipSuccess) return fail_free(mbh_fail(MBH_EDEVICE, "reference kernels"));
@@ -721,7 +721,7 @@ extern "C" mbh_status mbh_ref_refresh(mbh_ctx *ctx, const mbh_data *data, mbh_re
   hipLaunchKernelGGL(k_refresh_edges, dim3(1), dim3(256), 0, st, band, f0, df, Nb, max_len, f.F, f.kb, f.meta);
   hipLaunchKernelGGL(k_ref_bins, dim3(Nb, n_sub), dim3(kBlock), 0, st, f.kb, f.F, Nb, n_sub, C, N, f0, df,
                      data->dw64, h0w, part2, f.meta);
-  hipLaunchKernelGGL(k_sum_bins, dim3(Nb), dim3(64), 0, st, part2, n_sub, sums2);
+  hipLaunchKernelGGL(k_sum_bins, dim3((Nb * 18 + 255) / 256), dim3(256), 0, st, part2, Nb, n_sub, sums2);
   hipLaunchKernelGGL(k_ref_edges, dim3((E + 63) / 64), dim3(64), 0, st, wc, r->modes, C, E, f.F, data->t_obs, f.fq,
                      f.psi0, s0, f.meta);
   hipLaunchKernelGGL(k_refresh_finish, dim3(1), dim3(256), 0, st, sums1, sums2, s0, f.F, f.psi0, C, Nb, f.coef,

@@ -204,3 +204,63 @@ def test_selection_rule_on_ties_and_non_finite_values(M, ctx, case):
         gen += 1
         assert res == dict(status=0, pick=O.best_walker(lv), generation=gen)
     gr.close()
+
+
+def _refresh_case(M, ctx, model, modes, n_bins, data, gdata, th0, walkers, tag):
+    """Reference at th0, update from the walkers' FP64 lnL, compare with the oracle's update."""
+    gr = M.build_reference_coeffs(ctx, gdata, model, modes, th0, n_bins)
+    ref0 = O.Reference(model, modes, th0, data, n_bins)
+    lnl0, _, _ = ref0.loglike(walkers)
+    top = np.sort(lnl0[np.isfinite(lnl0)])[-2:]
+    assert top[1] - top[0] > 1e-5
+    st, pick, r1 = O.refresh_reference(ref0, walkers, lnl0)
+    assert st == O.OK
+    tw = _t(walkers)
+    gr.refresh(gdata, tw, M.loglike_heterodyned(ctx, gr, tw, M.FP64))
+    assert gr.refresh_result() == dict(status=0, pick=pick, generation=1)
+    ex, info = gr.export(), gr.info
+    assert info["k_lo"] == r1.k_lo and info["k_hi"] == r1.k_hi
+    assert np.array_equal(ex["kb"], r1.kb)
+    assert np.abs(ex["edges"] - r1.edges).max() <= 4e-16 * r1.edges.max()
+    for name, a, b in (("A0", ex["A0"], r1.A0c), ("B0", ex["B0"], r1.B0), ("h0", ex["h0_edges"], r1.h0c)):
+        assert np.abs(a - b).max() < 1e-9 * np.abs(b).max(), name
+    ref_l, _, _ = r1.loglike(walkers)
+    for p in (M.FP64, M.MIXED):
+        got = M.loglike_heterodyned(ctx, gr, tw, p).cpu().numpy()
+        err = np.abs(got - ref_l)
+        print(f"[refresh] {tag} prec {p}: picked {pick}, max|dlnL|={err.max():.3e}", flush=True)
+        assert np.all(err <= (1e-6 + 1e-12 * np.abs(ref_l) if p == M.FP64 else TOL))
+    gr.close()
+
+
+def test_refresh_higher_modes(M, ctx):
+    g = I.grid_lisa_small(16384, 0.05)
+    rng = I.rng_for(2, 21)
+    th, snr = I.draw_mbhb_source(rng, g.t_obs)
+    psd = I.psd_lisa_aet(g.freqs)
+    h = O.template(O.MODEL_IMR, O.ALL_MODES, th, g.freqs, g.t_obs)
+    th[4] = I.distance_for_snr(O.inner(h, h, psd, g.df), snr)
+    d = O.template(O.MODEL_IMR, O.ALL_MODES, th, g.freqs, g.t_obs) + I.noise(psd, g.df, rng)
+    data = O.Data(d, psd, g.f0, g.df, g.t_obs)
+    ref_true = O.Reference(O.MODEL_IMR, O.ALL_MODES, th, data, 256)
+    sig = I.curvature_sigma(lambda x: ref_true.loglike(x)[0], th)
+    walkers = I.walker_cloud(th, sig, (1, 4, 16, 64), 32, rng)
+    gd = M.data_create(ctx, _tc(d), _t(psd), g.f0, g.df, g.t_obs)
+    _refresh_case(M, ctx, M.MODEL_IMR, O.ALL_MODES, 256, data, gd, walkers[40], walkers, "higher modes")
+
+
+def test_refresh_chirp_model(M, ctx):
+    import math
+
+    g = I.grid_chirp()
+    rng = I.rng_for(1, 0)
+    th = I.draw_chirp_source(rng)
+    psd = I.psd_chirp(g.freqs)
+    h = O.template(O.MODEL_TF2, 0, th, g.freqs, g.t_obs)
+    th[1] = 100.0 / math.sqrt(O.inner(h, h, psd, g.df))
+    d = O.template(O.MODEL_TF2, 0, th, g.freqs, g.t_obs) + I.noise(psd, g.df, rng)
+    data = O.Data(d, psd, g.f0, g.df, g.t_obs)
+    w = I.relative_cloud(th, 1e-4, 32, rng)
+    w[:, 4:] = 0.0
+    gd = M.data_create(ctx, _tc(d[None, :] if d.ndim == 1 else d), _t(np.atleast_2d(psd)), g.f0, g.df, g.t_obs)
+    _refresh_case(M, ctx, M.MODEL_TF2, 0, 64, data, gd, w[7], w, "chirp")
