@@ -54,8 +54,8 @@ FULL_FLOPS_PER_POINT = 761.0
 # WRITE_SIZE counters divided by their reading for a 64 MiB device copy
 # (factors 0.5002 and 1.000); valid only for the kernel sources it was
 # measured on (sha256 over KERNEL_SOURCES).
-TRAFFIC = {"src_sha256": "3c7ac782314fa4470d807145d7a5a471d3c265a793060a12be32cbee946ae2fa",
-           "bytes_per_launch": 6.768e6}
+TRAFFIC = {"src_sha256": "e4b13b5f84e7b0c6bd325b482c42bca968b0e7dddc565dd21305d693671efd5b",
+           "bytes_per_launch": 6.755e6}
 
 
 # the sources that define the device code of the main pass
