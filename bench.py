@@ -463,6 +463,42 @@ def side_measurements(M, ctx, S, walkers, grid):
     out["reference_refresh"] = {"device_us": e0.elapsed_time(e1) * 1e3 / n_rep, "host_issue_us": t_issue * 1e6 / n_rep,
                                 "status": res["status"], "generation": res["generation"]}
     log(f"[bench] reference refresh on the device: {out['reference_refresh']}")
+    # a sampler-like loop (one batch per step, results read on the host) with
+    # the reference moved to the best walker every 10th step: per-step
+    # latency with the update on the device vs a host rebuild (new reference
+    # handle, hence a new batch)
+    lat = {}
+    for mode in ("device", "host"):
+        ref = M.build_reference_coeffs(ctx, it["data"], M.MODEL_IMR, M.MODE_22, it["th"], N_BINS)
+        lb = torch.empty(len(walkers[0]), dtype=torch.float64, device="cuda")
+        b = M.Batch(ctx, [ref], [tw], [lb], prec=M.MIXED)
+        b.launch_direct(st_r)
+        torch.cuda.synchronize()
+        ts = []
+        for step in range(200):
+            t0 = time.perf_counter()
+            if step % 10 == 9:
+                if mode == "device":
+                    ref.refresh(it["data"], tw, lb, stream=st_r)
+                else:
+                    best = int(torch.argmax(lb).item())
+                    new = M.build_reference_coeffs(ctx, it["data"], M.MODEL_IMR, M.MODE_22,
+                                                   walkers[0][best], N_BINS, stream=st_r)
+                    b.close()
+                    ref.close()
+                    ref = new
+                    b = M.Batch(ctx, [ref], [tw], [lb], prec=M.MIXED)
+            b.launch_direct(st_r)
+            st_r.synchronize()
+            ts.append(time.perf_counter() - t0)
+        ts = np.array(ts) * 1e3
+        upd = ts[9::10]
+        lat[mode] = {"p50_ms": float(np.percentile(ts, 50)), "p99_ms": float(np.percentile(ts, 99)),
+                     "update_step_mean_ms": float(upd.mean()), "plain_step_mean_ms": float(np.delete(ts, np.s_[9::10]).mean())}
+        b.close()
+        ref.close()
+    out["reference_update_step_latency"] = lat
+    log(f"[bench] steps with a reference update every 10th step: {lat}")
     r.close()
     # ragged higher-mode batch: 16 sources, modes 1-6, N_b 64-512, W 128-4096
     shapes = I.batch_shapes(I.rng_for(4, 0), 16)
