@@ -305,6 +305,22 @@ mbh_status mbh_server_create(mbh_ctx *ctx, int n_refs, const mbh_ref *const *ref
  * Returns MBH_EAGAIN if the request alone exceeds the batch or budget caps. */
 mbh_status mbh_server_submit(mbh_server *srv, int ref_index, const double *theta_host,
                              int64_t W, uint64_t *request_id);
+/* Queue the reference update of Sec. 3.2 (see mbh_ref_refresh) for resident
+ * reference ref_index, in submission order: requests submitted before it are
+ * evaluated against the old reference, requests submitted after it against
+ * the new one.  The population (theta_host [W][11], lnL_host [W], host
+ * memory, copied) is the one the update picks its best walker from; `data`
+ * must be the data the reference was built on and stay alive until the
+ * update has completed.  The update runs on the device, ordered after the
+ * batches in flight by their events and before later batches by an event of
+ * its own (no host synchronisation).  mbh_server_wait on *request_id
+ * returns when it has completed (no results are copied);
+ * mbh_ref_refresh_result on the reference gives its outcome.
+ * Errors: MBH_EINVAL (bad arguments, another data grid), MBH_EAGAIN (W above
+ * the per-batch capacity). */
+mbh_status mbh_server_refresh(mbh_server *srv, int ref_index, const mbh_data *data,
+                              const double *theta_host, const double *lnL_host, int64_t W,
+                              uint64_t *request_id);
 /* Copy results of a finished request to host buffers (lnL [W], dh_hh [W][2]
  * or NULL) and forget it.  timeout_ms < 0 waits forever, 0 polls.
  * MBH_EAGAIN if not finished in time; MBH_ENOTFOUND for an unknown id.

@@ -75,6 +75,9 @@ struct mbh_ref {
   int n_chan = 0, n_bins = 0;
   int64_t k_lo = 0, k_hi = 0;
   double t_obs = 0, lnL0 = 0, dd = 0, dh0 = 0, hh0 = 0;
+  // <h0|h0> at build time (never changed afterwards: read without a lock by
+  // the server's tile ordering)
+  double hh0_build = 0;
   // device: edges [E], response factors [E][kFq], carrier phase of h0 [E],
   // 1/s0 [C][E][2], residual-form coefficients [C][Nb][6], scalars
   double *F = nullptr, *fq = nullptr, *psi0 = nullptr, *is064 = nullptr, *coef = nullptr;

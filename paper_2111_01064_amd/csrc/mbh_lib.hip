@@ -489,6 +489,7 @@ extern "C" mbh_status mbh_build_reference_coeffs(mbh_ctx *ctx, const mbh_data *d
   r->lnL0 = -0.5 * s1[0];
   r->dh0 = s1[1];
   r->hh0 = s1[2];
+  r->hh0_build = s1[2];
 
   // paper-form coefficients (A0 = sum d h0* / S df, ...) and the kernel's
   // residual-form coefficients, scaled by 1/dF_b for the slope terms

@@ -60,7 +60,7 @@ static int64_t tiles_of(int G, int64_t W, int E) {
 // recomputation, which then overlaps the rest of the pass instead of
 // trailing it.
 static double tile_cost(double work, const mbh_ref *r) {
-  return work + 0.05 * std::log10(1.0 + std::max(0.0, r->hh0));
+  return work + 0.05 * std::log10(1.0 + std::max(0.0, r->hh0_build));
 }
 
 static void append_tiles(std::vector<WorkTile> &tiles, std::vector<double> &cost, int item, const mbh_ref *r,
@@ -309,11 +309,15 @@ using Clock = std::chrono::steady_clock;
 struct Request {
   uint64_t id = 0;
   int ref = 0;
-  int64_t W = 0;
+  int64_t W = 0;  // walkers evaluated (0 for a reference update)
   std::vector<double> theta;
   std::vector<double> lnL, dhhh;
   Clock::time_point t_submit, t_done;
   bool done = false;
+  // reference update: the population (theta, lnL_in) it picks from
+  const mbh_data *data = nullptr;
+  std::vector<double> lnL_in;
+  int64_t W_update = 0;
 };
 
 // one in-flight batch: device buffers, pinned host staging, stream, event
@@ -360,9 +364,13 @@ struct mbh_server {
   size_t bytes_in_flight = 0;
   int64_t walkers_in_flight = 0;
   std::string thread_error;
+  // later batches wait for the last reference update until it has finished
+  hipEvent_t barrier = nullptr;
+  int updates_in_flight = 0;
 };
 
 static void server_free(mbh_server *s) {
+  if (s->barrier) (void)hipEventDestroy(s->barrier);
   for (auto &sl : s->slots) {
     if (sl.st) (void)hipStreamSynchronize(sl.st);
     if (sl.ev) (void)hipEventDestroy(sl.ev);
@@ -389,6 +397,7 @@ static bool server_pack(mbh_server *s, Slot &sl) {
   std::vector<double> cost;
   while (!s->queue.empty()) {
     auto &r = s->queue.front();
+    if (r->data) break;  // a reference update: later requests go after it
     const mbh_ref *ref = s->refs[r->ref];
     const int G = item_lanes(s->ctx, ref, s->cfg.prec);
     const int64_t nt = tiles_of(G, r->W, ref->n_bins + 1);
@@ -427,6 +436,7 @@ static bool server_pack(mbh_server *s, Slot &sl) {
 static bool server_launch(mbh_server *s, Slot &sl) {
   const WorkHeader &h = *sl.hdr_h;
   hipStream_t st = sl.st;
+  if (s->updates_in_flight > 0 && hipStreamWaitEvent(st, s->barrier, 0) != hipSuccess) return false;
   bool ok = hipMemcpyAsync(sl.theta_d, sl.theta_h, sl.walkers * 11 * sizeof(double), hipMemcpyHostToDevice, st) == hipSuccess &&
             hipMemcpyAsync(sl.items_d, sl.items_h, h.n_items * sizeof(WorkItem), hipMemcpyHostToDevice, st) == hipSuccess &&
             hipMemcpyAsync(sl.tiles_d, sl.tiles_h, h.n_tiles * sizeof(WorkTile), hipMemcpyHostToDevice, st) == hipSuccess &&
@@ -445,6 +455,7 @@ static void server_complete(mbh_server *s, Slot &sl) {
   auto now = Clock::now();
   for (auto &m : sl.members) {
     Request &r = *m.first;
+    if (r.data) s->updates_in_flight -= 1;  // the update has finished
     r.lnL.assign(lnL + m.second, lnL + m.second + r.W);
     r.dhhh.assign(dh + 2 * m.second, dh + 2 * (m.second + r.W));
     r.t_done = now;
@@ -455,6 +466,24 @@ static void server_complete(mbh_server *s, Slot &sl) {
   s->bytes_in_flight -= (size_t)sl.walkers * s->bytes_per_walker;
   sl.members.clear();
   sl.busy = false;
+}
+
+// Issue the reference update at the head of the queue on free slot sl:
+// ordered after every batch in flight (their events) and before every later
+// batch (the barrier event).
+static bool server_issue_update(mbh_server *s, Slot &sl, const std::shared_ptr<Request> &r) {
+  hipStream_t st = sl.st;
+  for (auto &o : s->slots)
+    if (o.busy && hipStreamWaitEvent(st, o.ev, 0) != hipSuccess) return false;
+  const int64_t W = r->W_update;
+  std::memcpy(sl.theta_h, r->theta.data(), W * 11 * sizeof(double));
+  std::memcpy(sl.res_h, r->lnL_in.data(), W * sizeof(double));
+  if (hipMemcpyAsync(sl.theta_d, sl.theta_h, W * 11 * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(sl.res_d, sl.res_h, W * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess)
+    return false;
+  mbh_ref *ref = const_cast<mbh_ref *>(s->refs[r->ref]);
+  if (mbh_ref_refresh(s->ctx, r->data, ref, sl.theta_d, sl.res_d, W, st) != MBH_OK) return false;
+  return hipEventRecord(s->barrier, st) == hipSuccess && hipEventRecord(sl.ev, st) == hipSuccess;
 }
 
 static void server_loop(mbh_server *s) {
@@ -473,6 +502,28 @@ static void server_loop(mbh_server *s) {
     // 2. admit queued work into free slots (continuous batching)
     for (auto &sl : s->slots) {
       if (sl.busy || s->queue.empty()) continue;
+      if (s->queue.front()->data) {
+        std::shared_ptr<Request> r = s->queue.front();
+        s->queue.pop_front();
+        sl.members.clear();
+        sl.members.emplace_back(r, 0);
+        sl.walkers = 0;
+        sl.busy = true;
+        s->updates_in_flight += 1;
+        s->stats.batches += 1;
+        lk.unlock();
+        bool ok = server_issue_update(s, sl, r);
+        lk.lock();
+        if (!ok) {
+          s->thread_error = "reference update failed";
+          r->done = true;
+          sl.members.clear();
+          sl.busy = false;
+          s->updates_in_flight -= 1;
+        }
+        progressed = true;
+        continue;
+      }
       if (!server_pack(s, sl)) continue;
       sl.busy = true;
       s->walkers_in_flight += sl.walkers;
@@ -576,6 +627,10 @@ extern "C" mbh_status mbh_server_create(mbh_ctx *ctx, int n_refs, const mbh_ref 
       return st;
     }
   }
+  if (hipEventCreateWithFlags(&s->barrier, hipEventDisableTiming) != hipSuccess) {
+    server_free(s);
+    return mbh_fail(MBH_EDEVICE, "server event");
+  }
   s->thr = std::thread(server_loop, s);
   *out = s;
   return MBH_OK;
@@ -592,6 +647,38 @@ extern "C" mbh_status mbh_server_submit(mbh_server *s, int ref_index, const doub
   r->ref = ref_index;
   r->W = W;
   r->theta.assign(theta_host, theta_host + W * 11);
+  r->t_submit = Clock::now();
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    r->id = s->next_id++;
+    s->live[r->id] = r;
+    s->queue.push_back(r);
+    s->stats.submitted += 1;
+  }
+  s->cv_work.notify_one();
+  *request_id = r->id;
+  return MBH_OK;
+}
+
+extern "C" mbh_status mbh_server_refresh(mbh_server *s, int ref_index, const mbh_data *data,
+                                         const double *theta_host, const double *lnL_host, int64_t W,
+                                         uint64_t *request_id) {
+  if (!s || !data || !theta_host || !lnL_host || !request_id || W < 1) return mbh_fail(MBH_EINVAL, "bad argument");
+  if (ref_index < 0 || ref_index >= (int)s->refs.size()) return mbh_fail(MBH_EINVAL, "reference index %d", ref_index);
+  const mbh_ref *ref = s->refs[ref_index];
+  if (data->ctx != s->ctx || data->n_chan != ref->n_chan || data->n_f != ref->n_f || data->f0 != ref->f0 ||
+      data->df != ref->df || data->t_obs != ref->t_obs)
+    return mbh_fail(MBH_EINVAL, "data grid differs from the one the reference was built on");
+  if (W > s->cap_walkers)
+    return mbh_fail(MBH_EAGAIN, "update population of %lld walkers exceeds the per-batch capacity %lld",
+                    (long long)W, (long long)s->cap_walkers);
+  auto r = std::make_shared<Request>();
+  r->ref = ref_index;
+  r->W = 0;
+  r->data = data;
+  r->W_update = W;
+  r->theta.assign(theta_host, theta_host + W * 11);
+  r->lnL_in.assign(lnL_host, lnL_host + W);
   r->t_submit = Clock::now();
   {
     std::lock_guard<std::mutex> g(s->mu);

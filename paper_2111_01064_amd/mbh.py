@@ -92,6 +92,7 @@ _SIGS = {
     "mbh_server_create": [_vp, _i32, _pp, ct.POINTER(ServerConfig), _pp],
     "mbh_server_submit": [_vp, _i32, _dp, _i64, ct.POINTER(ct.c_uint64)],
     "mbh_server_wait": [_vp, ct.c_uint64, _i32, _dp, _dp, _dp],
+    "mbh_server_refresh": [_vp, _i32, _vp, _dp, _dp, _i64, ct.POINTER(ct.c_uint64)],
     "mbh_server_get_stats": [_vp, ct.POINTER(ServerStats)],
     "mbh_server_destroy": [_vp],
 }
@@ -396,6 +397,17 @@ class Server:
         rid = ct.c_uint64()
         _check(_L.mbh_server_submit(self.h, ref_index, th.ctypes.data_as(_dp), th.shape[0], ct.byref(rid)),
                "mbh_server_submit")
+        return rid.value
+
+    def refresh(self, ref_index: int, data: "Data", theta: np.ndarray, lnL: np.ndarray) -> int:
+        """mbh_server_refresh: queue a reference update (host population); wait() on the id with W = 0."""
+        th = np.ascontiguousarray(theta, dtype=np.float64).reshape(-1, NPARAM)
+        lv = np.ascontiguousarray(lnL, dtype=np.float64).reshape(-1)
+        if lv.shape[0] != th.shape[0]:
+            raise ValueError("theta and lnL sizes differ")
+        rid = ct.c_uint64()
+        _check(_L.mbh_server_refresh(self.h, ref_index, data.h, th.ctypes.data_as(_dp), lv.ctypes.data_as(_dp),
+                                     th.shape[0], ct.byref(rid)), "mbh_server_refresh")
         return rid.value
 
     def wait(self, rid: int, W: int, timeout_ms: int = -1, want_dh_hh: bool = False):

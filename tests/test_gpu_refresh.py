@@ -264,3 +264,41 @@ def test_refresh_chirp_model(M, ctx):
     w[:, 4:] = 0.0
     gd = M.data_create(ctx, _tc(d[None, :] if d.ndim == 1 else d), _t(np.atleast_2d(psd)), g.f0, g.df, g.t_obs)
     _refresh_case(M, ctx, M.MODEL_TF2, 0, 64, data, gd, w[7], w, "chirp")
+
+
+def test_server_update_orders_requests(M, ctx, case):
+    """Requests submitted before a queued update see the old reference, those
+    after it the new one; two updates back to back."""
+    w = case["walkers"][:256]
+    gr = M.build_reference_coeffs(ctx, case["gdata"], M.MODEL_IMR, O.MODE_22, case["ref0"].theta0, 128)
+    srv = M.Server(ctx, [gr], max_inflight=3, max_batch_walkers=4096, prec=M.FP64)
+    picks = (100, 200)
+    ids = {"before": [], "mid": [], "after": []}
+    upd = []
+    for phase, k in (("before", picks[0]), ("mid", picks[1]), ("after", None)):
+        for i in range(0, len(w), 32):
+            ids[phase].append((srv.submit(0, w[i:i + 32]), i))
+        if k is not None:
+            lv = -np.abs(np.arange(len(w)) - k).astype(np.float64)  # unique maximum at walker k
+            upd.append(srv.refresh(0, case["gdata"], w, lv))
+    got = {}
+    for phase, lst in ids.items():
+        out = np.empty(len(w))
+        for rid, i in lst:
+            out[i:i + 32] = srv.wait(rid, 32)[0]
+        got[phase] = out
+    for rid in upd:
+        srv.wait(rid, 0)
+    assert gr.refresh_result() == dict(status=0, pick=picks[1], generation=2)
+    expect = {"before": case["ref0"],
+              "mid": O.Reference(O.MODEL_IMR, O.MODE_22, w[picks[0]], case["data"], 128),
+              "after": O.Reference(O.MODEL_IMR, O.MODE_22, w[picks[1]], case["data"], 128)}
+    for phase, r in expect.items():
+        ref_l, _, _ = r.loglike(w)
+        err = np.abs(got[phase] - ref_l)
+        print(f"[refresh] server {phase}: max|dlnL|={err.max():.3e}", flush=True)
+        assert np.all(err <= 1e-6 + 1e-12 * np.abs(ref_l)), phase
+    st = srv.stats()
+    assert st["completed"] == st["submitted"] == 3 * len(ids["before"]) + 2
+    srv.close()
+    gr.close()
