@@ -259,12 +259,15 @@ def chirp_case(M, ctx):
                 max_abs_gpu_fp64_minus_oracle_het=float(np.max(np.abs(lg - lh))))
 
 
-def serve_run(M, ctx, refs, pools, prec, rate_hz, n_req, warm):
+def serve_run(M, ctx, refs, pools, prec, rate_hz, n_req, warm, update=None):
+    """Poisson request stream; with update = (datas, lnls, every) a reference
+    update of the request's source is queued after every `every`-th request."""
     rng = I.rng_for(5, 1)
     reqs = I.poisson_requests(rng, n_req + warm, rate_hz, 64, len(refs), 4096)
     srv = M.Server(ctx, refs, max_inflight=3, max_batch_walkers=65536, hbm_budget_bytes=2 << 30, prec=prec)
     lat = [None] * len(reqs)
     ids = [None] * len(reqs)
+    upd_ids = []
     done = threading.Event()
 
     def collector():
@@ -284,15 +287,23 @@ def serve_run(M, ctx, refs, pools, prec, rate_hz, n_req, warm):
         pool = pools[src]
         sel = rng.integers(0, len(pool), W)
         ids[i] = srv.submit(src, pool[sel])
+        if update is not None and i % update[2] == update[2] - 1:
+            upd_ids.append(srv.refresh(src, update[0][src], pool, update[1][src]))
     done.wait()
+    for u in upd_ids:
+        srv.wait(u, 0)
     wall = time.perf_counter() - t0
     st = srv.stats()
     srv.close()
     l = np.array(lat[warm:]) * 1e3
     walkers = sum(r[3] for r in reqs)
-    return dict(p50_ms=float(np.percentile(l, 50)), p99_ms=float(np.percentile(l, 99)),
-                throughput_evals_s=walkers / wall, requests=n_req, rate_hz=rate_hz, batches=st["batches"],
-                mean_walkers_per_batch=st["walkers"] / max(1, st["batches"]))
+    out = dict(p50_ms=float(np.percentile(l, 50)), p99_ms=float(np.percentile(l, 99)),
+               throughput_evals_s=walkers / wall, requests=n_req, rate_hz=rate_hz, batches=st["batches"],
+               mean_walkers_per_batch=st["walkers"] / max(1, st["batches"]))
+    if update is not None:
+        out["reference_updates"] = len(upd_ids)
+        out["max_ms"] = float(l.max())
+    return out
 
 
 def main():
@@ -542,6 +553,14 @@ def side_measurements(M, ctx, S, walkers, grid):
         sweep.append(r)
         log(f"[bench] serve mixed at {rate:.0f} req/s: {r}")
     serve["mixed_rate_sweep"] = sweep
+    # the same stream with a reference update (best walker of the source's
+    # pool, rebuilt on the device) queued after every 100th request
+    datas = [x["data"] for x in S.items[:4]]
+    lnls = [M.loglike_heterodyned(ctx, rf, torch.as_tensor(pl, device="cuda"), M.FP64).cpu().numpy()
+            for rf, pl in zip(refs, pools)]
+    r = serve_run(M, ctx, refs, pools, M.MIXED, rate_hz=2000.0, n_req=4000, warm=400, update=(datas, lnls, 100))
+    serve["mixed_with_reference_updates"] = r
+    log(f"[bench] serve mixed with a reference update every 100 requests: {r}")
     out["serving"] = serve
     return out
 
