@@ -481,6 +481,8 @@ def side_measurements(M, ctx, S, walkers, grid):
     lat = {}
     for mode in ("device", "host"):
         ref = M.build_reference_coeffs(ctx, it["data"], M.MODEL_IMR, M.MODE_22, it["th"], N_BINS)
+        if mode == "device":
+            ref.prepare_refresh()  # once, when the sampler starts
         lb = torch.empty(len(walkers[0]), dtype=torch.float64, device="cuda")
         b = M.Batch(ctx, [ref], [tw], [lb], prec=M.MIXED)
         b.launch_direct(st_r)
@@ -556,6 +558,8 @@ def side_measurements(M, ctx, S, walkers, grid):
     # the same stream with a reference update (best walker of the source's
     # pool, rebuilt on the device) queued after every 100th request
     datas = [x["data"] for x in S.items[:4]]
+    for rf in refs:
+        rf.prepare_refresh()
     lnls = [M.loglike_heterodyned(ctx, rf, torch.as_tensor(pl, device="cuda"), M.FP64).cpu().numpy()
             for rf, pl in zip(refs, pools)]
     r = serve_run(M, ctx, refs, pools, M.MIXED, rate_hz=2000.0, n_req=4000, warm=400, update=(datas, lnls, 100))

@@ -174,6 +174,11 @@ mbh_status mbh_ref_export(const mbh_ref *ref, double *edges, int64_t *kb, double
 mbh_status mbh_ref_refresh(mbh_ctx *ctx, const mbh_data *data, mbh_ref *ref,
                            const double *theta_dev, const double *lnL_dev, int64_t W,
                            hipStream_t stream);
+/* Allocate the update buffers of `ref` now (what its first mbh_ref_refresh
+ * would do: device memory and one synchronisation of `stream`), so that no
+ * update allocates.  Idempotent.  Errors: MBH_EINVAL, MBH_ENOMEM,
+ * MBH_EDEVICE. */
+mbh_status mbh_ref_refresh_prepare(mbh_ref *ref, hipStream_t stream);
 /* Outcome of the last mbh_ref_refresh of `ref` (waits for it): its status
  * (MBH_OK, or the reason the reference was left unchanged), the walker it
  * picked (-1 if none) and the number of refreshes committed so far.  Before

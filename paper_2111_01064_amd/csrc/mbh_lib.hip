@@ -693,6 +693,13 @@ static mbh_status refresh_alloc(mbh_ref *r, hipStream_t st) {
   return MBH_OK;
 }
 
+extern "C" mbh_status mbh_ref_refresh_prepare(mbh_ref *r, hipStream_t st) {
+  if (!r) return mbh_fail(MBH_EINVAL, "null reference");
+  HIP_TRY(hipSetDevice(r->ctx->device));
+  std::lock_guard<std::mutex> g(r->mu);
+  return refresh_alloc(r, st);
+}
+
 extern "C" mbh_status mbh_ref_refresh(mbh_ctx *ctx, const mbh_data *data, mbh_ref *r, const double *theta_dev,
                                       const double *lnL_dev, int64_t W, hipStream_t st) {
   if (!ctx || !data || !r || !theta_dev || !lnL_dev) return mbh_fail(MBH_EINVAL, "null argument");

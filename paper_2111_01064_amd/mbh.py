@@ -74,6 +74,7 @@ _SIGS = {
     "mbh_ref_export": [_vp, _dp, ct.POINTER(ct.c_int64), _dp, _dp, _dp, _dp, _dp],
     "mbh_ref_refresh": [_vp, _vp, _vp, _vp, _vp, _i64, _vp],
     "mbh_ref_refresh_result": [_vp, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int32)],
+    "mbh_ref_refresh_prepare": [_vp, _vp],
     "mbh_loglike_heterodyned": [_vp, _vp, _vp, _i64, _i32, _vp, _vp, _vp],
     "mbh_loglike_full": [_vp, _vp, _i32, _u32, _vp, _i64, _i32, _vp, _vp, _vp],
     "mbh_batch_create": [_vp, _i32, _pp, _pp, ct.POINTER(ct.c_int64), _pp, _pp, _i32, _pp],
@@ -197,6 +198,10 @@ class Reference:
         W = theta.shape[0]
         _check(_L.mbh_ref_refresh(self.ctx.h, data.h, self.h, _dev_ptr(theta, torch.float64, (W, NPARAM)),
                                   _dev_ptr(lnL, torch.float64, (W,)), W, _stream(stream)), "mbh_ref_refresh")
+
+    def prepare_refresh(self, stream=None):
+        """mbh_ref_refresh_prepare: allocate the update buffers now."""
+        _check(_L.mbh_ref_refresh_prepare(self.h, _stream(stream)), "mbh_ref_refresh_prepare")
 
     def refresh_result(self) -> dict:
         """mbh_ref_refresh_result: status, picked walker and refreshes committed."""

@@ -194,6 +194,9 @@ def test_selection_rule_on_ties_and_non_finite_values(M, ctx, case):
     w = case["walkers"][:40]
     rng = np.random.default_rng(9)
     gr = M.build_reference_coeffs(ctx, case["gdata"], M.MODEL_IMR, O.MODE_22, case["ref0"].theta0, 128)
+    gr.prepare_refresh()
+    gr.prepare_refresh()  # idempotent
+    assert gr.refresh_result() == dict(status=0, pick=-1, generation=0)
     gen = 0
     for trial in range(4):
         lv = rng.integers(-2, 2, size=len(w)).astype(np.float64)
