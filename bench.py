@@ -298,7 +298,8 @@ def serve_run(M, ctx, refs, pools, prec, rate_hz, n_req, warm, update=None):
     l = np.array(lat[warm:]) * 1e3
     walkers = sum(r[3] for r in reqs)
     out = dict(p50_ms=float(np.percentile(l, 50)), p99_ms=float(np.percentile(l, 99)),
-               throughput_evals_s=walkers / wall, requests=n_req, rate_hz=rate_hz, batches=st["batches"],
+               throughput_evals_s=walkers / wall, requests_per_s=len(reqs) / wall, requests=n_req,
+               rate_hz=rate_hz, batches=st["batches"],
                mean_walkers_per_batch=st["walkers"] / max(1, st["batches"]))
     if update is not None:
         out["reference_updates"] = len(upd_ids)
@@ -539,32 +540,39 @@ def side_measurements(M, ctx, S, walkers, grid):
     ok = np.isfinite(lnl4["fp64"])
     hm["max_abs_dlnL_mixed_vs_fp64"] = float(np.max(np.abs(lnl4["mixed"][ok] - lnl4["fp64"][ok])))
     out["hm_batch"] = hm
-    # serving: Poisson stream over 4 resident sources at a fraction of capacity
-    refs = [x["ref"] for x in S.items[:4]]
-    pools = walkers[:4]
-    serve = {}
-    for name, prec in (("mixed", M.MIXED), ("fp64", M.FP64)):
-        serve[name] = serve_run(M, ctx, refs, pools, prec, rate_hz=2000.0, n_req=4000, warm=400)
-        log(f"[bench] serve {name}: {serve[name]}")
-    # offered load up to what one Python submitting thread sustains (each
-    # request's walkers are copied into the server); the GPU side runs at a
-    # few % of its capacity even at the highest rate
-    sweep = []
-    for rate in (10000.0, 30000.0):
-        r = serve_run(M, ctx, refs, pools, M.MIXED, rate_hz=rate, n_req=6000, warm=600)
-        sweep.append(r)
-        log(f"[bench] serve mixed at {rate:.0f} req/s: {r}")
-    serve["mixed_rate_sweep"] = sweep
-    # the same stream with a reference update (best walker of the source's
-    # pool, rebuilt on the device) queued after every 100th request
-    datas = [x["data"] for x in S.items[:4]]
+    # serving: 4 resident sources (the step's physics with 1-6 modes each and
+    # 64 / 128 / 256 / 512 bins), a Poisson stream from 64 samplers with
+    # request sizes log-uniform in 1-4096 walkers, at fractions of the
+    # measured capacity, in both precisions
+    masks = [sh[0] for sh in I.batch_shapes(I.rng_for(5, 0), 4)]
+    nbs = [64, 128, 256, 512]
+    S5 = Sources(M, ctx, grid, 4, modes_list=masks, n_bins_list=nbs, cfg=5)
+    refs = [x["ref"] for x in S5.items]
+    pools = [S5.walkers(x, (1, 4, 16, 64), 64) for x in S5.items]
+    serve = {"sources": [{"modes": int(m), "bins": nb} for m, nb in zip(masks, nbs)]}
+    # capacity: the request rate the server sustains when the submitting
+    # thread never waits (one Python thread submits, another collects)
+    cap = serve_run(M, ctx, refs, pools, M.MIXED, rate_hz=1e7, n_req=20000, warm=1000)
+    serve["capacity_req_per_s"] = cap["requests_per_s"]
+    serve["capacity_evals_per_s"] = cap["throughput_evals_s"]
+    log(f"[bench] serving capacity: {cap['requests_per_s']:.0f} req/s, {cap['throughput_evals_s']:.3g} evals/s")
+    for rho in (0.5, 0.8, 0.95):
+        for name, prec in (("mixed", M.MIXED), ("fp64", M.FP64)):
+            r = serve_run(M, ctx, refs, pools, prec, rate_hz=rho * cap["requests_per_s"], n_req=20000, warm=1000)
+            serve[f"{name}_rho{rho}"] = r
+            log(f"[bench] serve {name} at {rho} x capacity: {r}")
+    # the same stream (0.5 x capacity, mixed) with a reference update (best
+    # walker of the source's pool, rebuilt on the device) queued after every
+    # 100th request
+    datas = [x["data"] for x in S5.items]
     for rf in refs:
         rf.prepare_refresh()
     lnls = [M.loglike_heterodyned(ctx, rf, torch.as_tensor(pl, device="cuda"), M.FP64).cpu().numpy()
             for rf, pl in zip(refs, pools)]
-    r = serve_run(M, ctx, refs, pools, M.MIXED, rate_hz=2000.0, n_req=4000, warm=400, update=(datas, lnls, 100))
-    serve["mixed_with_reference_updates"] = r
-    log(f"[bench] serve mixed with a reference update every 100 requests: {r}")
+    r = serve_run(M, ctx, refs, pools, M.MIXED, rate_hz=0.5 * cap["requests_per_s"], n_req=20000, warm=1000,
+                  update=(datas, lnls, 100))
+    serve["mixed_rho0.5_with_reference_updates"] = r
+    log(f"[bench] serve mixed at 0.5 x capacity with a reference update every 100 requests: {r}")
     out["serving"] = serve
     return out
 
