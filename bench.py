@@ -224,39 +224,46 @@ def cpu_baseline(budget_s: float = 15.0):
 
 def chirp_case(M, ctx):
     """The single-channel 0PN chirp case (2^14 linear bins on [1e-4, 0.1] Hz,
-    64 bins, 32 walkers at 1e-4 relative scatter): the oracle's heterodyned and
-    full-grid lnL, their difference and CPU seconds, and the library's FP64
-    heterodyned lnL against the oracle's."""
+    64 bins, 32 walkers at 1e-4 relative scatter), noiseless data and a
+    seeded noisy variant: the oracle's heterodyned and full-grid lnL, their
+    difference and CPU seconds, and the library's FP64 heterodyned lnL
+    against the oracle's."""
     import torch
 
     import oracle as O
 
-    g = I.grid_chirp()
-    rng = I.rng_for(1, 0)
-    th = I.draw_chirp_source(rng)
-    psd = I.psd_chirp(g.freqs)
-    h = O.template(O.MODEL_TF2, 0, th, g.freqs, g.t_obs)
-    th[1] = 100.0 / math.sqrt(O.inner(h, h, psd, g.df))
-    d = O.template(O.MODEL_TF2, 0, th, g.freqs, g.t_obs) + I.noise(psd, g.df, rng)
-    data = O.Data(d, psd, g.f0, g.df, g.t_obs)
-    t0 = time.perf_counter()
-    ref = O.Reference(O.MODEL_TF2, 0, th, data, 64)
-    w = I.relative_cloud(th, 1e-4, 32, rng)
-    w[:, 4:] = 0.0
-    lh, _, _ = ref.loglike(w)
-    t_het = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    lf, _, _ = O.loglike_full(O.MODEL_TF2, 0, w, data)
-    t_full = time.perf_counter() - t0
-    gd = M.data_create(ctx, torch.as_tensor(np.atleast_2d(d), device="cuda"),
-                       torch.as_tensor(np.atleast_2d(psd), device="cuda"), g.f0, g.df, g.t_obs)
-    gr = M.build_reference_coeffs(ctx, gd, M.MODEL_TF2, 0, th, 64)
-    lg = M.loglike_heterodyned(ctx, gr, torch.as_tensor(w, device="cuda"), M.FP64).cpu().numpy()
-    gr.close()
-    gd.close()
-    return dict(walkers=len(w), bins=64, grid=g.n_f, max_abs_het_minus_full=float(np.max(np.abs(lh - lf))),
-                oracle_het_s=t_het, oracle_full_s=t_full, cores=O.max_threads(),
-                max_abs_gpu_fp64_minus_oracle_het=float(np.max(np.abs(lg - lh))))
+    out = {}
+    for variant in ("noiseless", "noisy"):
+        g = I.grid_chirp()
+        rng = I.rng_for(1, 0)
+        th = I.draw_chirp_source(rng)
+        psd = I.psd_chirp(g.freqs)
+        h = O.template(O.MODEL_TF2, 0, th, g.freqs, g.t_obs)
+        th[1] = 100.0 / math.sqrt(O.inner(h, h, psd, g.df))
+        d = O.template(O.MODEL_TF2, 0, th, g.freqs, g.t_obs)
+        if variant == "noisy":
+            d = d + I.noise(psd, g.df, rng)
+        data = O.Data(d, psd, g.f0, g.df, g.t_obs)
+        t0 = time.perf_counter()
+        ref = O.Reference(O.MODEL_TF2, 0, th, data, 64)
+        w = I.relative_cloud(th, 1e-4, 32, rng)
+        w[:, 4:] = 0.0
+        lh, _, _ = ref.loglike(w)
+        t_het = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        lf, _, _ = O.loglike_full(O.MODEL_TF2, 0, w, data)
+        t_full = time.perf_counter() - t0
+        gd = M.data_create(ctx, torch.as_tensor(np.atleast_2d(d), device="cuda"),
+                           torch.as_tensor(np.atleast_2d(psd), device="cuda"), g.f0, g.df, g.t_obs)
+        gr = M.build_reference_coeffs(ctx, gd, M.MODEL_TF2, 0, th, 64)
+        lg = M.loglike_heterodyned(ctx, gr, torch.as_tensor(w, device="cuda"), M.FP64).cpu().numpy()
+        gr.close()
+        gd.close()
+        out[variant] = dict(walkers=len(w), bins=64, grid=g.n_f,
+                            max_abs_het_minus_full=float(np.max(np.abs(lh - lf))), oracle_het_s=t_het,
+                            oracle_full_s=t_full, cores=O.max_threads(),
+                            max_abs_gpu_fp64_minus_oracle_het=float(np.max(np.abs(lg - lh))))
+    return out
 
 
 def serve_run(M, ctx, refs, pools, prec, rate_hz, n_req, warm, update=None):
@@ -436,18 +443,33 @@ def side_measurements(M, ctx, S, walkers, grid):
     it = S.items[0]
     draws = I.prior_draws(I.rng_for(3, 0), 16384, grid.t_obs)
     td = torch.as_tensor(draws, device="cuda")
+    full = {}
     for name, prec in (("fp64", M.FP64), ("mixed", M.MIXED)):
         M.loglike_full(ctx, it["data"], M.MODEL_IMR, M.MODE_22, td[:64], prec)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        M.loglike_full(ctx, it["data"], M.MODEL_IMR, M.MODE_22, td, prec)
+        lf = M.loglike_full(ctx, it["data"], M.MODEL_IMR, M.MODE_22, td, prec)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        full[name] = lf.cpu().numpy()
         out[f"full_grid_{name}_evals_per_s"] = len(draws) / dt
         # VALU work from the FLOP counters: FULL_FLOPS_PER_POINT per (walker, grid point)
         out[f"full_grid_{name}_roofline_frac"] = (len(draws) * grid.n_f * FULL_FLOPS_PER_POINT / dt / 1e12
                                                   / PEAK_ALU_TFLOPS)
         log(f"[bench] full grid {name}: {len(draws) / dt:.1f} evals/s")
+    # |lnL_mixed - lnL_fp64| per draw, by distance below the best draw
+    ok = np.isfinite(full["fp64"])
+    dl = np.abs(full["mixed"][ok] - full["fp64"][ok])
+    below = full["fp64"][ok].max() - full["fp64"][ok]
+    rows = []
+    for lo, hi in ((0.0, 1e2), (1e2, 1e4), (1e4, 1e6), (1e6, np.inf)):
+        sel = (below >= lo) & (below < hi)
+        if sel.any():
+            rows.append({"below_max": [lo, hi if np.isfinite(hi) else None], "draws": int(sel.sum()),
+                         "max_abs_dlnL": float(dl[sel].max()), "max_rel_dlnL": float((dl[sel] / np.abs(full["fp64"][ok][sel])).max())})
+    out["full_grid_dlnL_mixed_vs_fp64"] = {"draws": int(ok.sum()), "max_abs": float(dl.max()),
+                                           "within_1e-3": float(np.mean(dl <= 1e-3)), "by_distance": rows}
+    log(f"[bench] full grid mixed vs fp64: {out['full_grid_dlnL_mixed_vs_fp64']}")
     # reference build (a9)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -525,8 +547,11 @@ def side_measurements(M, ctx, S, walkers, grid):
     st = torch.cuda.Stream()
     lnl4 = {}
     for name, prec in (("fp64", M.FP64), ("mixed", M.MIXED)):
+        chosen = []
         for it4, t4 in zip(S4.items, th4):
-            M.autotune_heterodyned(ctx, it4["ref"], t4, prec)
+            chosen.append(int(M.autotune_heterodyned(ctx, it4["ref"], t4, prec)))
+        # lanes per walker the autotuner picked per item (0 = flattened, one lane per walker and edge)
+        hm[f"{name}_autotuned_lanes"] = chosen
         ln4 = [torch.empty(len(t), dtype=torch.float64, device="cuda") for t in th4]
         b4 = M.Batch(ctx, [x["ref"] for x in S4.items], th4, ln4, prec=prec)
         wall, mean_s = time_batch(M, ctx, b4, 50, 5, st)
