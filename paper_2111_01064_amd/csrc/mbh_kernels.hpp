@@ -494,11 +494,12 @@ static __global__ __launch_bounds__(256) void k_refresh_finish(const double *__r
 }
 #pragma clang fp contract(on)
 
-// Arrays a refresh replaces, staging -> live, in one launch.
+// Arrays a refresh replaces, staging -> live, in one launch, copied as
+// 8-byte words (the doubles bit for bit, and the int64 bin indices).
 struct RefreshCopy {
   static constexpr int kMax = 8;
-  const double *src[kMax];
-  double *dst[kMax];
+  const uint64_t *src[kMax];
+  uint64_t *dst[kMax];
   int64_t n[kMax];
   int count;
 };

@@ -389,7 +389,10 @@ extern "C" mbh_status mbh_build_reference_coeffs(mbh_ctx *ctx, const mbh_data *d
   MBH_TRY(sc.get(&h0w, (size_t)C * N));
   unsigned long long *band = nullptr;
   MBH_TRY(sc.get(&band, 2));
-  const int nb1 = grid_blocks(N, 4 * ctx->n_cu);
+  // one workgroup of four wavefronts per two SIMDs: the whole grid pass in a
+  // single round of resident wavefronts (2 per SIMD at its register use);
+  // more workgroups run in several rounds and were measured slower
+  const int nb1 = grid_blocks(N, 2 * ctx->n_cu);
   double *part1 = nullptr, *sums1 = nullptr;
   MBH_TRY(sc.get(&part1, (size_t)nb1 * 3));
   MBH_TRY(sc.get(&sums1, 3));
@@ -644,7 +647,7 @@ static mbh_status refresh_alloc(mbh_ref *r, hipStream_t st) {
     f.max_len = std::min<int64_t>(N, (int64_t)std::ceil(len) + 3);
   }
   f.n_sub = (int)std::max<int64_t>(1, (f.max_len + kRefChunk - 1) / kRefChunk);
-  f.nb1 = grid_blocks(N, 4 * ctx->n_cu);
+  f.nb1 = grid_blocks(N, 2 * ctx->n_cu);  // as in the build's grid pass
   std::vector<std::pair<void **, size_t>> want = {
       {(void **)&f.wc, sizeof(WalkerC)},
       {(void **)&f.band, 2 * sizeof(unsigned long long)},
@@ -734,11 +737,10 @@ extern "C" mbh_status mbh_ref_refresh(mbh_ctx *ctx, const mbh_data *data, mbh_re
                      f.psi0, s0, f.meta);
   hipLaunchKernelGGL(k_refresh_finish, dim3(1), dim3(256), 0, st, sums1, sums2, s0, f.F, f.psi0, C, Nb, f.coef,
                      f.is064, f.paper, f.h0e, f.meta);
-  // 8-byte words: kb is copied as raw words like the doubles
   RefreshCopy cp{};
   auto add = [&](const void *src, void *dst, int64_t n) {
-    cp.src[cp.count] = (const double *)src;
-    cp.dst[cp.count] = (double *)dst;
+    cp.src[cp.count] = (const uint64_t *)src;
+    cp.dst[cp.count] = (uint64_t *)dst;
     cp.n[cp.count] = n;
     ++cp.count;
   };
