@@ -54,7 +54,7 @@ FULL_FLOPS_PER_POINT = 761.0
 # WRITE_SIZE counters divided by their reading for a 64 MiB device copy
 # (factors 0.5002 and 1.000); valid only for the kernel sources it was
 # measured on (sha256 over KERNEL_SOURCES).
-TRAFFIC = {"src_sha256": "e4b13b5f84e7b0c6bd325b482c42bca968b0e7dddc565dd21305d693671efd5b",
+TRAFFIC = {"src_sha256": "2f1b6a3a74ce4ed66622c775bfd765afcd34430a8dd1d80f9670d4e4e3af71f0",
            "bytes_per_launch": 6.755e6}
 
 
