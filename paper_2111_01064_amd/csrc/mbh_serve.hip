@@ -109,6 +109,53 @@ static std::vector<TileGroup> order_tiles(std::vector<WorkTile> &tiles, const st
   return groups;
 }
 
+// Workgroups are dealt to the eight XCDs in turn (workgroup b on XCD b mod 8)
+// and each XCD has its own L2.  Place the setup and main-pass work of a
+// walker on one XCD, so that the main pass finds the walker constants the
+// setup kernel has just written in its own L2: walker tile j of item i gets
+// colour (i + j) mod 8 (so that the tiles of one temperature rung, which
+// carry similar work, spread over all XCDs), the walker-tile array deals
+// colours in turn, and the flattened main-pass tiles, kept in their order
+// within each XCD, are dealt to the XCD of their first walker's setup tile.
+// Results do not depend on the order (each walker's partial slots are fixed).
+constexpr int kXcds = 8;
+static void xcd_align(std::vector<WorkTile> &tiles, const std::vector<TileGroup> &groups,
+                      std::vector<WalkerTile> &wtiles, const WorkItem *items, int n_items) {
+  std::vector<int64_t> wt_first(n_items + 1, 0);
+  for (int i = 0; i < n_items; ++i) wt_first[i + 1] = wt_first[i] + (items[i].W + kWalkerTile - 1) / kWalkerTile;
+  std::vector<std::deque<size_t>> cq(kXcds);
+  for (size_t k = 0; k < wtiles.size(); ++k) {
+    const int i = wtiles[k].item;
+    cq[(size_t)((i + ((int64_t)k - wt_first[i])) % kXcds)].push_back(k);
+  }
+  std::vector<WalkerTile> wt2(wtiles.size());
+  std::vector<int> xcd_of(wtiles.size());
+  for (size_t pos = 0; pos < wtiles.size(); ++pos) {
+    size_t c = pos % kXcds;
+    while (cq[c].empty()) c = (c + 1) % kXcds;
+    const size_t k = cq[c].front();
+    cq[c].pop_front();
+    wt2[pos] = wtiles[k];
+    xcd_of[k] = (int)(pos % kXcds);
+  }
+  wtiles.swap(wt2);
+  for (const auto &g : groups) {
+    if (g.G != 0) continue;
+    std::vector<std::deque<WorkTile>> q(kXcds);
+    for (int64_t i = g.begin; i < g.begin + g.count; ++i) {
+      const WorkTile &t = tiles[i];
+      const int64_t w = (t.begin * kChunk) / items[t.item].E;
+      q[xcd_of[wt_first[t.item] + w / kWalkerTile]].push_back(t);
+    }
+    for (int64_t pos = 0; pos < g.count; ++pos) {
+      int k = (int)(pos % kXcds);
+      while (q[k].empty()) k = (k + 1) % kXcds;
+      tiles[g.begin + pos] = q[k].front();
+      q[k].pop_front();
+    }
+  }
+}
+
 template <typename R, bool DH>
 static void launch_group(const TileGroup &g, const WorkItem *items, const WorkTile *tiles, hipStream_t st) {
   const dim3 grid((unsigned)g.count), blk(kBlock);
@@ -235,6 +282,7 @@ extern "C" mbh_status mbh_batch_create(mbh_ctx *ctx, int n, const mbh_ref *const
     off += W[i];
   }
   b->groups = order_tiles(tiles, cost);
+  xcd_align(tiles, b->groups, wtiles, items.data(), n);
   if ((s = batch_alloc(b, &b->items, (size_t)n)) != MBH_OK ||
       (s = batch_alloc(b, &b->tiles, tiles.size())) != MBH_OK ||
       (s = batch_alloc(b, &b->wtiles, wtiles.size())) != MBH_OK)
@@ -425,8 +473,9 @@ static bool server_pack(mbh_server *s, Slot &sl) {
     it.dhhh = sl.res_d + sl.walkers + 2 * it.offset;
   }
   sl.groups = order_tiles(tiles, cost);
-  std::memcpy(sl.tiles_h, tiles.data(), tiles.size() * sizeof(WorkTile));
   for (int i = 0; i < n_items; ++i) append_wtiles(wtiles, i, sl.items_h[i].W);
+  xcd_align(tiles, sl.groups, wtiles, sl.items_h, n_items);
+  std::memcpy(sl.tiles_h, tiles.data(), tiles.size() * sizeof(WorkTile));
   std::memcpy(sl.wtiles_h, wtiles.data(), wtiles.size() * sizeof(WalkerTile));
   sl.n_wtiles = (int64_t)wtiles.size();
   *sl.hdr_h = WorkHeader{n_items, (int32_t)tiles.size(), sl.walkers};
