@@ -213,6 +213,15 @@ def cpu_baseline(budget_s: float = 15.0):
         ref.loglike(w)
         n_done += len(w)
     el = time.perf_counter() - t_start
+    # the same on one core (a shorter sample)
+    n_threads = O.max_threads()
+    O.set_threads(1)
+    n1, t1s = 0, time.perf_counter()
+    while time.perf_counter() - t1s < budget_s / 5:
+        ref.loglike(w)
+        n1 += len(w)
+    single = n1 / (time.perf_counter() - t1s)
+    O.set_threads(n_threads)
     # one full-grid evaluation for the per-evaluation cost of the direct likelihood
     t1 = time.perf_counter()
     O.loglike_full(O.MODEL_IMR, O.MODE_22, w[: O.max_threads()], data)
@@ -220,7 +229,8 @@ def cpu_baseline(budget_s: float = 15.0):
     return dict(value=n_done / el, unit="evals/s", cores=O.max_threads(), kind="oracle",
                 sample=f"1 source, {len(w)} walkers (8 temps x 64) x {n_done // len(w)} passes, "
                        f"1.58e6-bin grid, 128 bins, {el:.1f} s",
-                full_grid_s_per_eval_per_core=full_s * O.max_threads(), setup_s=setup_s)
+                full_grid_s_per_eval_per_core=full_s * O.max_threads(), setup_s=setup_s,
+                single_core_value=single)
 
 
 def chirp_case(M, ctx):
@@ -431,6 +441,7 @@ def main():
         cb = cpu_baseline()
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
         out["cpu_baseline_full_grid_s_per_eval_per_core"] = cb["full_grid_s_per_eval_per_core"]
+        out["cpu_baseline_single_core_evals_per_s"] = cb["single_core_value"]
         out["chirp_case"] = chirp_case(M, ctx)
         log(f"[bench] chirp case: {out['chirp_case']}")
     print(json.dumps(out), flush=True)

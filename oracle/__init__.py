@@ -73,6 +73,8 @@ def lib():
         L.oracle_loglike_het.argtypes = [i32, u32, i64, dp, i32, i32, dp, dp, dp, dp, dp, d, dp,
                                          d, dp, dp, dp]
         L.oracle_max_threads.restype = i32
+        L.oracle_set_threads.argtypes = [i32]
+        L.oracle_set_threads.restype = None
         _lib = L
     return _lib
 
@@ -91,6 +93,11 @@ def n_chan(model: int) -> int:
 
 def max_threads() -> int:
     return lib().oracle_max_threads()
+
+
+def set_threads(n: int) -> None:
+    """Threads of the walker loops (for timing; results do not depend on it)."""
+    lib().oracle_set_threads(int(n))
 
 
 def sylm(l: int, m: int, theta: float, phi: float) -> complex:

@@ -60,6 +60,15 @@ int oracle_max_threads(void) {
 #endif
 }
 
+/* threads of the walker loops (timing only; results do not depend on it) */
+void oracle_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 int oracle_n_chan(int model) { return model == OR_MODEL_TF2 ? 1 : 3; }
 
 /* ---- spin-weighted spherical harmonics ----------------------------------
