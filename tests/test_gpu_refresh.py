@@ -305,3 +305,30 @@ def test_server_update_orders_requests(M, ctx, case):
     assert st["completed"] == st["submitted"] == 3 * len(ids["before"]) + 2
     srv.close()
     gr.close()
+
+
+@pytest.mark.parametrize("n_bins", [1, 2, 1000])
+def test_refresh_edge_sizes(M, ctx, case, n_bins):
+    """One walker in the population, and the smallest and a large bin count."""
+    w = case["walkers"][10:11]
+    gr = M.build_reference_coeffs(ctx, case["gdata"], M.MODEL_IMR, O.MODE_22, case["ref0"].theta0, n_bins)
+    gr.refresh(case["gdata"], _t(w), _t(np.array([-3.0])))
+    assert gr.refresh_result() == dict(status=0, pick=0, generation=1)
+    r1 = O.Reference(O.MODEL_IMR, O.MODE_22, w[0], case["data"], n_bins)
+    ex, info = gr.export(), gr.info
+    assert info["k_lo"] == r1.k_lo and info["k_hi"] == r1.k_hi
+    assert np.array_equal(ex["kb"], r1.kb)
+    assert np.abs(ex["edges"] - r1.edges).max() <= 4e-16 * r1.edges.max()
+    for name, a, b in (("A0", ex["A0"], r1.A0c), ("B0", ex["B0"], r1.B0), ("B1", ex["B1"], r1.B1)):
+        assert np.abs(a - b).max() <= 1e-9 * np.abs(b).max(), name
+    probe = case["walkers"][:64]
+    ref_l, _, _ = r1.loglike(probe)
+    got = M.loglike_heterodyned(ctx, gr, _t(probe), M.FP64).cpu().numpy()
+    err = np.abs(got - ref_l)
+    print(f"[refresh] n_bins {n_bins}: max|dlnL|={err.max():.3e}", flush=True)
+    # the parity target, as for the host-built references at these bin
+    # counts: with very few bins the ratio's deviation delta is O(1) across
+    # a bin, so the FP64 rounding of the bin terms exceeds the 1e-6 bar that
+    # holds at the workload's 128 bins
+    assert np.all(err <= TOL)
+    gr.close()
