@@ -156,7 +156,9 @@ mbh_status mbh_ref_export(const mbh_ref *ref, double *edges, int64_t *kb, double
  * `stream` (likelihood calls, batch launches, also batches created before
  * the refresh: they read the reference's device arrays) sees the new
  * reference; work on other streams must be ordered by the caller, and must
- * not run on `ref` while the refresh does.  The outcome is known on the
+ * not run on `ref` while the refresh does.  For a reference resident in a
+ * server, use mbh_server_refresh, which orders the update with the
+ * server's own streams.  The outcome is known on the
  * device only: if no walker has a finite lnL, the picked walker lies outside
  * the model domain (MBH_EINVAL) or its template is empty on the grid or zero
  * at an edge (MBH_EBAND), the reference is left unchanged; read the outcome
