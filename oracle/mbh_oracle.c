@@ -187,18 +187,30 @@ static void wf22(const wf_t *w, double f, double *amp, double *ph, double *dph) 
   *dph = dp - w->dph_max;
 }
 
-/* relative amplitude law of mode index mi at (2,2)-equivalent frequency fp */
+/* Relative amplitude of mode index mi at (2,2)-equivalent frequency fp, i.e.
+ * A_lm(f) / A_22(fp) with fp = 2 f / m (both at the same orbital frequency,
+ * v = (pi M fp)^(1/3)).  It is the product of
+ *  - the leading-order magnitude |H_lm| of the post-Newtonian mode amplitude
+ *    relative to H_22 = 1 (Blanchet, Living Rev. Relativ. 17 (2014) 2,
+ *    Sec. 9.5), with delta = (m1 - m2) / M:
+ *      |H33| = (3/4) sqrt(15/14) delta v,  |H44| = (8/9) sqrt(5/7) (1 - 3 eta) v^2,
+ *      |H21| = (1/3) delta v,               |H32| = (1/3) sqrt(5/7) (1 - 3 eta) v^2,
+ *      |H43| = 9 / (4 sqrt 70) delta (1 - 2 eta) v^3;
+ *  - the ratio sqrt(2/m) of the stationary-phase factors sqrt(2 pi / (m Phi''))
+ *    of mode m and of mode 2 at the same orbital frequency (the Fourier
+ *    amplitude of a mode is its time-domain amplitude times that factor). */
 static double mode_rel_amp(const wf_t *w, int mi, double fp) {
   double v = cbrt(PI * w->M * fp);
+  double H = 0.0;
   switch (mi) {
-    case 0: return 1.0;
-    case 1: return 0.75 * sqrt(15.0 / 14.0) * w->delta * v;
-    case 2: return (4.0 / 9.0) * sqrt(10.0 / 7.0) * (1.0 - 3.0 * w->eta) * v * v;
-    case 3: return (1.0 / 3.0) * w->delta * v;
-    case 4: return (1.0 / 3.0) * sqrt(5.0 / 7.0) * (1.0 - 3.0 * w->eta) * v * v;
-    case 5: return 9.0 / (4.0 * sqrt(70.0)) * w->delta * (1.0 - 2.0 * w->eta) * v * v * v;
+    case 0: H = 1.0; break;
+    case 1: H = 0.75 * sqrt(15.0 / 14.0) * w->delta * v; break;
+    case 2: H = (8.0 / 9.0) * sqrt(5.0 / 7.0) * (1.0 - 3.0 * w->eta) * v * v; break;
+    case 3: H = (1.0 / 3.0) * w->delta * v; break;
+    case 4: H = (1.0 / 3.0) * sqrt(5.0 / 7.0) * (1.0 - 3.0 * w->eta) * v * v; break;
+    case 5: H = 9.0 / (4.0 * sqrt(70.0)) * w->delta * (1.0 - 2.0 * w->eta) * v * v * v; break;
   }
-  return 0.0;
+  return H * sqrt(2.0 / MODE_M[mi]);
 }
 
 /* mode mi at frequency f: amplitude, phase phi_lm (no t_ref term), t_lm */

@@ -408,13 +408,19 @@ __device__ __forceinline__ void walker_setup(const double *__restrict__ th, int 
   w.AN76 = w.AN * (w.icpiM * w.icpiM * w.icpiM) * sqrt(w.icpiM);
   w.slam = sqrt(w.lam_num);
   w.tref = t[10];
+  // mode amplitude relative to (2,2) at the same orbital frequency, without
+  // its power of v: leading-order PN mode magnitude |H_lm| times the
+  // stationary-phase ratio sqrt(2/m), folded into one constant per mode
+  // ((3,3): (3/4) sqrt(15/14) sqrt(2/3) = (3/4) sqrt(5/7); (4,4): (8/9)
+  // sqrt(5/7) sqrt(1/2) = (4/9) sqrt(10/7); (2,1): sqrt2 / 3; (3,2): m = 2;
+  // (4,3): 9 / (4 sqrt70) sqrt(2/3) = (3/4) sqrt(3/35))
   const double a = 1.0 - 3.0 * eta;
   w.rel[0] = 1.0;
-  w.rel[1] = 0.75 * sqrt(15.0 / 14.0) * delta;
+  w.rel[1] = 0.75 * sqrt(5.0 / 7.0) * delta;
   w.rel[2] = (4.0 / 9.0) * sqrt(10.0 / 7.0) * a;
-  w.rel[3] = delta * (1.0 / 3.0);
+  w.rel[3] = (kSqrt2 / 3.0) * delta;
   w.rel[4] = sqrt(5.0 / 7.0) / 3.0 * a;
-  w.rel[5] = 9.0 / (4.0 * sqrt(70.0)) * delta * (1.0 - 2.0 * eta);
+  w.rel[5] = 0.75 * sqrt(3.0 / 35.0) * delta * (1.0 - 2.0 * eta);
   if (part == 0) walker_setup_sky(th, modes, w);
 }
 

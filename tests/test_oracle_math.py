@@ -10,6 +10,8 @@ inner                    0PN chirp <h|h> closed forms (power-law PSD and the
 template (chirp)         stationary-phase time t(f) = t_c - (5/256) Mc (pi Mc f)^(-8/3)
 mode (IMR-lite)          eq. (tf) by numerical differentiation; 1.5PN spin-orbit
                          time-to-coalescence; Newtonian quadrupole amplitude;
+                         higher-mode amplitudes from Fourier transforms of
+                         time-domain PN modes (Blanchet's leading-order H_lm);
                          C1 phase / C0 amplitude at the transition; f_ref = argmax f^2 A22
 orbit                    centroid = guiding centre, arm length, 60 deg inclination
 link                     time-domain single-link Doppler of a monochromatic plane wave
@@ -196,6 +198,59 @@ def test_newtonian_quadrupole_amplitude():
         a, _, _, _ = O.mode(th, 2, 2, np.array([f]))
         ref = math.sqrt(5 / 24) * math.pi ** (-2 / 3) * Mc ** (5 / 6) * f ** (-7 / 6) / D
         assert abs(abs(Kp) * a[0] / ref - 1) < 1e-12
+
+
+# Leading-order magnitudes of the post-Newtonian mode amplitudes H_lm,
+# relative to H_22 = 1 (Blanchet, Living Rev. Relativ. 17 (2014) 2, Sec. 9.5):
+# h_lm(t) is proportional to x H_lm(x) e^{-i m Phi(t)}, x = (M omega)^(2/3),
+# delta = (m1 - m2) / M.
+def _pn_mode_magnitude(l, m, eta, delta, x):
+    v = np.sqrt(x)
+    return {(2, 2): np.ones_like(x),
+            (3, 3): 0.75 * math.sqrt(15 / 14) * delta * v,
+            (4, 4): 8 / 9 * math.sqrt(5 / 7) * (1 - 3 * eta) * x,
+            (2, 1): delta * v / 3,
+            (3, 2): math.sqrt(5 / 7) / 3 * (1 - 3 * eta) * x,
+            (4, 3): 9 / (4 * math.sqrt(70)) * delta * (1 - 2 * eta) * x ** 1.5}[(l, m)]
+
+
+def _fourier_amplitude_of_td_mode(l, m, M, eta, delta, x_s):
+    """|int h_lm(t) e^{2 pi i f t} dt| by direct quadrature, for the Newtonian
+    inspiral (dx/dt = 64 eta x^5 / (5 M), Phi = -x^(-5/2) / (32 eta)) at the
+    frequency f = m omega / 2 pi whose stationary point has x = x_s.  A
+    Gaussian window of width 4 / sqrt(m Phi'') about the stationary time keeps
+    the integral finite; its effect on the magnitude is the same factor for
+    every mode, so it cancels in ratios between modes."""
+    phi2 = m * 96 / 5 * eta * x_s ** 5.5 / M ** 2
+    sig = 4 / math.sqrt(phi2)
+    tau_s = 5 * M / (256 * eta * x_s ** 4)
+    t = np.linspace(-6 * sig, 6 * sig, 60001)
+    x = (5 * M / (256 * eta * (tau_s - t))) ** 0.25
+    f = m * x_s ** 1.5 / (2 * math.pi * M)
+    ph = 2 * math.pi * f * t + (x ** -2.5 - x_s ** -2.5) * m / (32 * eta)
+    h = x * _pn_mode_magnitude(l, m, eta, delta, x) * np.exp(1j * ph - t ** 2 / (2 * sig ** 2))
+    return abs(np.trapezoid(h, t)), f
+
+
+@pytest.mark.parametrize("q", [0.3, 0.8])
+@pytest.mark.parametrize("lm", [(3, 3), (4, 4), (2, 1), (3, 2), (4, 3)])
+def test_higher_mode_amplitude_ratio_from_time_domain_modes(q, lm):
+    """A_lm(f) / A_22(2f/m) against the Fourier transform of time-domain
+    post-Newtonian modes (leading-order H_lm, Newtonian phasing): fixes each
+    mode's numerical prefactor, its power of v and the stationary-phase
+    factor sqrt(2/m) that relates time-domain and Fourier amplitudes."""
+    l, m = lm
+    th = THETA.copy()
+    th[0], th[1] = 3e5, q
+    M = th[0] * MSUN_S
+    eta, delta = q / (1 + q) ** 2, (1 - q) / (1 + q)
+    for x_s in (1e-3, 3e-3):
+        a22, f22 = _fourier_amplitude_of_td_mode(2, 2, M, eta, delta, x_s)
+        alm, f = _fourier_amplitude_of_td_mode(l, m, M, eta, delta, x_s)
+        assert abs(f22 - 2 * f / m) <= 1e-12 * f22
+        want = alm / a22
+        got = O.mode(th, l, m, np.array([f]))[0][0] / O.mode(th, 2, 2, np.array([f22]))[0][0]
+        assert abs(got / want - 1) < 1e-5, (lm, q, x_s, got, want)
 
 
 def test_transition_continuity_and_fmax():
