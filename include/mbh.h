@@ -232,8 +232,10 @@ mbh_status mbh_loglike_full(mbh_ctx *ctx, const mbh_data *data, int model, uint3
  * reference and its index within its item, never on the rest of the batch.
  *   refs[n], theta_dev[n] ([W_i][11]), W[n], lnL_dev[n] ([W_i]),
  *   dh_hh_dev[n] (each [W_i][2] or NULL; the array itself may be NULL).
- * Caller buffers must stay valid while the batch exists.
- * Errors: MBH_EINVAL, MBH_ENOMEM, MBH_EDEVICE. */
+ * Caller buffers must stay valid while the batch exists.  Items may hold
+ * no walkers (W[i] = 0), but not all of them.
+ * Errors: MBH_EINVAL (also for a batch with no walkers at all), MBH_ENOMEM,
+ * MBH_EDEVICE. */
 mbh_status mbh_batch_create(mbh_ctx *ctx, int n, const mbh_ref *const *refs,
                             const double *const *theta_dev, const int64_t *W,
                             double *const *lnL_dev, double *const *dh_hh_dev,

@@ -178,7 +178,8 @@ static void launch_group(const TileGroup &g, const WorkItem *items, const WorkTi
 static void launch_work(int prec, bool dh, int64_t n_wtiles, const std::vector<TileGroup> &groups,
                         const WalkerTile *wtiles, const WorkItem *items, const WorkTile *tiles, hipStream_t st,
                         int stages = 7) {
-  const dim3 nw((unsigned)std::max<int64_t>(1, n_wtiles));
+  if (n_wtiles <= 0) return;  // no walkers: no walker tile to read
+  const dim3 nw((unsigned)n_wtiles);
   if (stages & 1) hipLaunchKernelGGL(k_setup_work, nw, dim3(2 * kWalkerTile), 0, st, items, wtiles);
   for (const TileGroup &g : groups) {
     if (!(stages & 2)) break;
@@ -245,6 +246,7 @@ extern "C" mbh_status mbh_batch_create(mbh_ctx *ctx, int n, const mbh_ref *const
     if (dh_hh_dev && dh_hh_dev[i]) dh = true;
     Kmax = std::max(Kmax, flat_slots(refs[i]->n_bins + 1));
   }
+  if (total == 0) return mbh_fail(MBH_EINVAL, "batch of %d items holds no walkers", n);
   HIP_TRY(hipSetDevice(ctx->device));
   mbh_batch *b = new mbh_batch();
   b->ctx = ctx;

@@ -174,3 +174,25 @@ def test_autotuner_records_a_valid_choice(M, ctx, sources, tmp_path):
     ctx2 = M.Context(0)
     M.autotune_load(ctx2, path)
     assert M.lanes_for(ctx2, s["nb"], nm, M.MIXED) == lanes
+
+
+def test_batch_without_walkers_is_refused(M, ctx, sources):
+    """A batch whose items all hold zero walkers is refused at creation (it
+    would have no walker tile for the setup and totals kernels to read);
+    one empty item among others is fine."""
+    import torch
+
+    s = sources[0]
+    empty = torch.empty((0, 11), dtype=torch.float64, device="cuda")
+    out = torch.empty(0, dtype=torch.float64, device="cuda")
+    with pytest.raises(M.MbhError) as e:
+        M.Batch(ctx, [s["gref"], sources[1]["gref"]], [empty, empty], [out, out], prec=M.FP64)
+    assert e.value.status == M.MBH_EINVAL
+    tw = _t(s["walkers"][:5])
+    lnl = torch.empty(5, dtype=torch.float64, device="cuda")
+    b = M.Batch(ctx, [sources[1]["gref"], s["gref"]], [empty, tw], [out, lnl], prec=M.FP64)
+    b.launch()
+    torch.cuda.synchronize()
+    single = M.loglike_heterodyned(ctx, s["gref"], tw, M.FP64).cpu().numpy()
+    assert np.array_equal(lnl.cpu().numpy(), single)
+    b.close()
