@@ -211,6 +211,26 @@ mbh_status mbh_loglike_heterodyned(mbh_ctx *ctx, const mbh_ref *ref, const doubl
                                    int64_t W, mbh_precision prec, double *lnL_dev,
                                    double *dh_hh_dev, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the work
+ * and results of mbh_loglike_heterodyned, with its scratch (walker constants
+ * and partial sums) taken from a fixed device array of
+ * MBH_NOALLOC_SCRATCH_BYTES that the library holds on each GPU until the
+ * process ends (its address is resolved once per device by mbh_create).
+ * The call allocates nothing, neither device nor host memory.  A call of W
+ * walkers at N_b bins needs W * 568 bytes (rounded up to 256) plus
+ * W * 32 * ((N_b - 1) / 63 + 2) bytes; larger calls are refused with
+ * MBH_EINVAL and a message (at 128 bins about 36 000 walkers fit).  Every
+ * call on one GPU shares that GPU's array: calls that overlap on the device
+ * (on different streams, or from several contexts on one GPU) race and give
+ * wrong results, so the caller must order them, e.g. issue them on one
+ * stream.  The array keeps the last call's contents; nothing in it needs to
+ * start at zero.  Arguments, outputs and errors as mbh_loglike_heterodyned. */
+#define MBH_NOALLOC_SCRATCH_BYTES ((size_t)24 << 20)
+mbh_status mbh_loglike_heterodyned_noalloc(mbh_ctx *ctx, const mbh_ref *ref, const double *theta_dev,
+                                           int64_t W, mbh_precision prec, double *lnL_dev,
+                                           double *dh_hh_dev, hipStream_t stream);
+
 /* Full-grid log-likelihood -1/2 <d-h|d-h> (eqs. like and inner, Sec. 2) of W
  * walkers: the template is generated on every grid frequency on the fly and
  * never stored.  Same argument conventions as above.

@@ -127,6 +127,37 @@ struct Scratch {
     if (s_ != MBH_OK) return s_;    \
   } while (0)
 
+// ---------------------------------------------------------------- no-allocation scratch
+// Scratch of mbh_loglike_heterodyned_noalloc (walker constants and partial
+// sums) in a file-scope device array: every GPU the library runs on holds its
+// own copy until the process ends.  In host code `scratch` names a host-side
+// stand-in, never the device memory: the device address is resolved once per
+// device (hipGetSymbolAddress, with that device current) by mbh_create and
+// kept in g_scratch_dev, which is what host code passes to kernels.
+static __device__ __align__(256) unsigned char scratch[MBH_NOALLOC_SCRATCH_BYTES];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_dev[kMaxDevices];
+
+// with `device` current
+static mbh_status noalloc_scratch_init(int device) {
+  if (device >= kMaxDevices) return MBH_OK;  // the no-allocation entry point refuses such devices
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (g_scratch_dev[device]) return MBH_OK;
+  void *p = nullptr;
+  hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p)
+    return mbh_fail(MBH_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", device, hipGetErrorString(e));
+  g_scratch_dev[device] = p;
+  return MBH_OK;
+}
+
+static void *noalloc_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  return g_scratch_dev[device];
+}
+
 // ---------------------------------------------------------------- context
 extern "C" mbh_status mbh_create(int device, size_t hbm_budget_bytes, mbh_ctx **out) {
   if (!out) return mbh_fail(MBH_EINVAL, "null out");
@@ -137,6 +168,7 @@ extern "C" mbh_status mbh_create(int device, size_t hbm_budget_bytes, mbh_ctx **
   HIP_TRY(hipSetDevice(device));
   hipDeviceProp_t prop;
   HIP_TRY(hipGetDeviceProperties(&prop, device));
+  MBH_TRY(noalloc_scratch_init(device));
   mbh_ctx *c = new mbh_ctx();
   c->device = device;
   c->budget = hbm_budget_bytes;
@@ -874,15 +906,17 @@ void launch_finish(const WorkItem *items, const WorkItem &one, const WalkerTile 
   hipLaunchKernelGGL(k_het_final, fb, dim3(kWalkerTile), 0, st, items, one, wtiles);
 }
 
-extern "C" mbh_status mbh_loglike_heterodyned(mbh_ctx *ctx, const mbh_ref *ref, const double *theta_dev,
-                                              int64_t W, mbh_precision prec, double *lnL_dev,
-                                              double *dh_hh_dev, hipStream_t st) {
+static mbh_status het_check(const mbh_ctx *ctx, const mbh_ref *ref, const double *theta_dev, int64_t W,
+                            mbh_precision prec, const double *lnL_dev) {
   if (!ctx || !ref || (W > 0 && (!theta_dev || !lnL_dev))) return mbh_fail(MBH_EINVAL, "null argument");
   if (W < 0 || W > (int64_t)1 << 30) return mbh_fail(MBH_EINVAL, "W = %lld out of range", (long long)W);
   if (prec != MBH_FP64 && prec != MBH_MIXED) return mbh_fail(MBH_EINVAL, "bad precision");
-  if (W == 0) return MBH_OK;
-  HIP_TRY(hipSetDevice(ctx->device));
-  Scratch sc(ctx, st);
+  return MBH_OK;
+}
+
+// the single-call work item of W walkers (its scratch pointers set by the caller)
+static WorkItem het_item(const mbh_ctx *ctx, const mbh_ref *ref, const double *theta_dev, int64_t W,
+                         mbh_precision prec, double *lnL_dev, double *dh_hh_dev) {
   const int G = lanes_lookup(ctx, ref->n_bins, popcount_modes(ref->modes ? ref->modes : 1u), prec);
   WorkItem it = make_item(ctx, ref, G);
   it.theta = theta_dev;
@@ -890,13 +924,58 @@ extern "C" mbh_status mbh_loglike_heterodyned(mbh_ctx *ctx, const mbh_ref *ref, 
   it.dhhh = dh_hh_dev;
   it.W = W;
   it.offset = 0;
-  MBH_TRY(sc.get(&it.wc, (size_t)W));
-  MBH_TRY(sc.get(&it.part, (size_t)W * it.K * 4));
-  hipLaunchKernelGGL(k_setup_one, dim3((unsigned)((W + 63) / 64)), dim3(128), 0, st, it);
-  launch_main(prec, dh_hh_dev != nullptr, it, st);
+  return it;
+}
+
+// setup, main pass and totals of one item on `st`
+static mbh_status het_launch(const WorkItem &it, mbh_precision prec, hipStream_t st) {
+  hipLaunchKernelGGL(k_setup_one, dim3((unsigned)((it.W + 63) / 64)), dim3(128), 0, st, it);
+  launch_main(prec, it.dhhh != nullptr, it, st);
   launch_finish(nullptr, it, nullptr, 0, st);
   HIP_TRY(hipGetLastError());
   return MBH_OK;
+}
+
+extern "C" mbh_status mbh_loglike_heterodyned(mbh_ctx *ctx, const mbh_ref *ref, const double *theta_dev,
+                                              int64_t W, mbh_precision prec, double *lnL_dev,
+                                              double *dh_hh_dev, hipStream_t st) {
+  MBH_TRY(het_check(ctx, ref, theta_dev, W, prec, lnL_dev));
+  if (W == 0) return MBH_OK;
+  HIP_TRY(hipSetDevice(ctx->device));
+  Scratch sc(ctx, st);
+  WorkItem it = het_item(ctx, ref, theta_dev, W, prec, lnL_dev, dh_hh_dev);
+  MBH_TRY(sc.get(&it.wc, (size_t)W));
+  MBH_TRY(sc.get(&it.part, (size_t)W * it.K * 4));
+  return het_launch(it, prec, st);
+}
+
+// Bytes of scratch a single call of W walkers needs: walker constants, then
+// (from the next 256-byte boundary) the partial sums [W][K][4].
+static size_t het_scratch_bytes(int64_t W, int K, size_t *part_off) {
+  const size_t wc = ((size_t)W * sizeof(WalkerC) + 255) & ~(size_t)255;
+  *part_off = wc;
+  return wc + (size_t)W * K * 4 * sizeof(double);
+}
+
+extern "C" mbh_status mbh_loglike_heterodyned_noalloc(mbh_ctx *ctx, const mbh_ref *ref, const double *theta_dev,
+                                                      int64_t W, mbh_precision prec, double *lnL_dev,
+                                                      double *dh_hh_dev, hipStream_t st) {
+  MBH_TRY(het_check(ctx, ref, theta_dev, W, prec, lnL_dev));
+  if (W == 0) return MBH_OK;
+  size_t part_off = 0;
+  const size_t need = het_scratch_bytes(W, flat_slots(ref->n_bins + 1), &part_off);
+  if (need > (size_t)MBH_NOALLOC_SCRATCH_BYTES)
+    return mbh_fail(MBH_EINVAL, "W = %lld walkers at %d bins need %zu bytes of scratch, above the %zu-byte maximum",
+                    (long long)W, ref->n_bins, need, (size_t)MBH_NOALLOC_SCRATCH_BYTES);
+  unsigned char *base = (unsigned char *)noalloc_scratch(ctx->device);
+  if (!base) return mbh_fail(MBH_EINVAL, "no scratch on device %d", ctx->device);
+  HIP_TRY(hipSetDevice(ctx->device));
+  WorkItem it = het_item(ctx, ref, theta_dev, W, prec, lnL_dev, dh_hh_dev);
+  // every slot the totals read is written by the main pass of the same call,
+  // so nothing needs clearing between calls
+  it.wc = (WalkerC *)base;
+  it.part = (double *)(base + part_off);
+  return het_launch(it, prec, st);
 }
 
 // ---------------------------------------------------------------- full grid

@@ -76,6 +76,7 @@ _SIGS = {
     "mbh_ref_refresh_result": [_vp, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int32)],
     "mbh_ref_refresh_prepare": [_vp, _vp],
     "mbh_loglike_heterodyned": [_vp, _vp, _vp, _i64, _i32, _vp, _vp, _vp],
+    "mbh_loglike_heterodyned_noalloc": [_vp, _vp, _vp, _i64, _i32, _vp, _vp, _vp],
     "mbh_loglike_full": [_vp, _vp, _i32, _u32, _vp, _i64, _i32, _vp, _vp, _vp],
     "mbh_batch_create": [_vp, _i32, _pp, _pp, ct.POINTER(ct.c_int64), _pp, _pp, _i32, _pp],
     "mbh_batch_launch": [_vp, _vp],
@@ -278,6 +279,18 @@ def loglike_heterodyned(ctx: Context, ref: Reference, theta: torch.Tensor, prec:
     dp = _dev_ptr(dh_hh, torch.float64, (W, 2)) if dh_hh is not None else None
     _check(_L.mbh_loglike_heterodyned(ctx.h, ref.h, tp, W, prec, _dev_ptr(lnL, torch.float64, (W,)), dp,
                                       _stream(stream)), "mbh_loglike_heterodyned")
+    return lnL
+
+
+def loglike_heterodyned_noalloc(ctx: Context, ref: Reference, theta: torch.Tensor, lnL: torch.Tensor,
+                                prec: int = FP64, dh_hh: torch.Tensor | None = None, stream=None):
+    """mbh_loglike_heterodyned_noalloc: outputs are the caller's (no allocation
+    here or in the library); calls on one GPU must not overlap."""
+    W = theta.shape[0]
+    tp = _dev_ptr(theta, torch.float64, (W, NPARAM))
+    dp = _dev_ptr(dh_hh, torch.float64, (W, 2)) if dh_hh is not None else None
+    _check(_L.mbh_loglike_heterodyned_noalloc(ctx.h, ref.h, tp, W, prec, _dev_ptr(lnL, torch.float64, (W,)), dp,
+                                              _stream(stream)), "mbh_loglike_heterodyned_noalloc")
     return lnL
 
 
