@@ -38,24 +38,28 @@ METRIC = "heterodyned lnL evals/s (mixed vs FP64, |ΔlnL|≤1e-3); p50/p99 reque
 PEAK_ALU_TFLOPS = 78.6   # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, unpacked FP32 and FP64 alike
 PEAK_HBM_GBS = 8000.0
 N_SOURCES, TEMPS, PER_TEMP, N_BINS = 8, tuple(2.0 ** k for k in range(8)), 64, 128
-# Floating-point work of one (walker, bin edge) of the heterodyned main pass
-# with the (2,2) mode and three channels, its bin included (FMA = 2 flops,
-# other arithmetic and transcendental instructions 1): the VALU FLOP counters
-# (SQ_INSTS_VALU_FLOPS_FP64, _FP32, _FP64_TRANS, _FP32_TRANS, x 64 lanes) of
-# the mixed main pass over this benchmark's 4096 walkers x 129 edges give
-# 4.49e8 per launch, 850 per edge (FP64 pass: 856); profiles/het_main_pass_bench.md.
-FLOPS_PER_EDGE = 850.0
-# Floating-point work of the full-grid likelihood per (walker, grid point),
-# three channels, (2,2) mode (FLOP counters of k_full, FP64 pass;
-# profiles/full_grid_reference_build.md); the call also streams 24-48 B of
-# data per point per walker tile, far below the VALU time.
-FULL_FLOPS_PER_POINT = 761.0
-# HBM traffic of the mixed main pass (bytes per launch) from the FETCH_SIZE and
-# WRITE_SIZE counters divided by their reading for a 64 MiB device copy
-# (factors 0.5002 and 1.000); valid only for the kernel sources it was
-# measured on (sha256 over KERNEL_SOURCES).
-TRAFFIC = {"src_sha256": "dd172a8d9a953817cc418b6cfece7f8d1893a3d4005f2e14699258408d0fd8f0",
-           "bytes_per_launch": 5.528e6}
+# Algorithmic work of one heterodyned evaluation (roofline "achieved"): the
+# per-unit figure of the measurement plan, 5e4 flops per evaluation for the
+# (2,2) mode, three channels and 129 bin edges (waveform ~60 flops, response
+# ~200 flops and ~13 transcendentals per edge, contraction ~30 per bin;
+# transcendental = 1 flop, FMA = 2); the design notes derive it.  The bytes
+# an evaluation must move are its 11 parameters in and one lnL out (96 B).
+ALGO_FLOPS_PER_EVAL = 5.0e4
+ALGO_BYTES_PER_EVAL = 96.0
+# Algorithmic work of the full-grid likelihood per (walker, grid point): the
+# template (~250 flops and ~15 transcendentals for (2,2) and three channels)
+# and the residual contraction; the data and weights (32 B per point) are
+# read once per walker tile.
+ALGO_FULL_FLOPS_PER_POINT = 250.0
+# Hardware counter figures of the current kernels (rocprofv3): VALU flops per
+# (walker, edge) of the mixed main pass (SQ_INSTS_VALU_FLOPS_* x 64 lanes,
+# FMA = 2), VALU flops per (walker, point) of the FP64 full grid, and HBM bytes
+# per launch of the mixed main pass (FETCH_SIZE and WRITE_SIZE divided by
+# their reading for a 64 MiB device copy: factors 0.5002 and 1.000).  Valid
+# only for the kernel sources they were measured on (sha256 over
+# KERNEL_SOURCES); reported as null otherwise.
+COUNTERS = {"src_sha256": "dd172a8d9a953817cc418b6cfece7f8d1893a3d4005f2e14699258408d0fd8f0",
+            "valu_flops_per_edge": 850.0, "full_valu_flops_per_point": 761.0, "bytes_per_launch": 5.528e6}
 
 
 # the sources that define the device code of the main pass and the order
@@ -189,13 +193,22 @@ def copy_calibration():
     torch.cuda.synchronize()
 
 
-def cpu_baseline(budget_s: float = 15.0):
-    """The FP64 oracle (OpenMP over walkers) on one source of the same
-    workload: its own data, reference and walker cloud, timed on the host."""
+LOUDEST_SOURCE = 1  # the step's loudest source (SNR ~950)
+
+
+def cpu_baseline(M, ctx, budget_s: float = 15.0):
+    """The FP64 oracle (OpenMP over walkers) on one source of the step's
+    workload, its loudest: its own data, reference and walker cloud (the
+    step's seed and recipe, built by the oracle), timed on the host.  The
+    library then evaluates the same oracle-made walkers on the same data
+    (one batch, launched as the step is, in both precisions) and the largest
+    |dlnL| against the oracle is reported."""
+    import torch
+
     import oracle as O
 
     g = I.grid_lisa()
-    rng = I.rng_for(2, 0)
+    rng = I.rng_for(2, LOUDEST_SOURCE)
     th, snr = I.draw_mbhb_source(rng, g.t_obs)
     f = g.freqs
     psd = I.psd_lisa_aet(f)
@@ -203,6 +216,7 @@ def cpu_baseline(budget_s: float = 15.0):
     h = O.template(O.MODEL_IMR, O.MODE_22, th, f, g.t_obs)
     th[4] = I.distance_for_snr(O.inner(h, h, psd, g.df), snr)
     d = h / th[4] + I.noise(psd, g.df, rng)
+    del h
     data = O.Data(d, psd, g.f0, g.df, g.t_obs)
     ref = O.Reference(O.MODEL_IMR, O.MODE_22, th, data, N_BINS)
     sig = I.curvature_sigma(lambda x: ref.loglike(x)[0], th)
@@ -210,7 +224,7 @@ def cpu_baseline(budget_s: float = 15.0):
     setup_s = time.perf_counter() - t0
     n_done, t_start = 0, time.perf_counter()
     while time.perf_counter() - t_start < budget_s:
-        ref.loglike(w)
+        lo, _, _ = ref.loglike(w)
         n_done += len(w)
     el = time.perf_counter() - t_start
     # the same on one core (a shorter sample)
@@ -226,11 +240,26 @@ def cpu_baseline(budget_s: float = 15.0):
     t1 = time.perf_counter()
     O.loglike_full(O.MODEL_IMR, O.MODE_22, w[: O.max_threads()], data)
     full_s = (time.perf_counter() - t1) / O.max_threads()
+    # the library on the oracle's inputs
+    gd = M.data_create(ctx, torch.as_tensor(d, device="cuda"), torch.as_tensor(psd, device="cuda"), g.f0, g.df,
+                       g.t_obs)
+    gr = M.build_reference_coeffs(ctx, gd, M.MODEL_IMR, M.MODE_22, th, N_BINS)
+    tw = torch.as_tensor(w, device="cuda")
+    vs_oracle = {}
+    for name, prec in (("fp64", M.FP64), ("mixed", M.MIXED)):
+        lb = torch.empty(len(w), dtype=torch.float64, device="cuda")
+        b = M.Batch(ctx, [gr], [tw], [lb], prec=prec)
+        b.launch_direct()
+        torch.cuda.synchronize()
+        b.close()
+        vs_oracle[name] = float(np.max(np.abs(lb.cpu().numpy() - lo)))
+    gr.close()
+    gd.close()
     return dict(value=n_done / el, unit="evals/s", cores=O.max_threads(), kind="oracle",
-                sample=f"1 source, {len(w)} walkers (8 temps x 64) x {n_done // len(w)} passes, "
-                       f"1.58e6-bin grid, 128 bins, {el:.1f} s",
+                sample=f"source {LOUDEST_SOURCE} of the step (SNR {snr:.0f}), {len(w)} walkers (8 temps x 64) "
+                       f"x {n_done // len(w)} passes, 1.58e6-bin grid, 128 bins, {el:.1f} s",
                 full_grid_s_per_eval_per_core=full_s * O.max_threads(), setup_s=setup_s,
-                single_core_value=single)
+                single_core_value=single, vs_oracle=vs_oracle, lnL_range=[float(lo.min()), float(lo.max())])
 
 
 def chirp_case(M, ctx):
@@ -278,47 +307,53 @@ def chirp_case(M, ctx):
 
 
 def serve_run(M, ctx, refs, pools, prec, rate_hz, n_req, warm, update=None):
-    """Poisson request stream; with update = (datas, lnls, every) a reference
-    update of the request's source is queued after every `every`-th request."""
+    """Poisson request stream replayed through the server by its native trace
+    replay (mbh_server_replay: submission at the arrival times and collection
+    in the library's own threads).  With update = (datas, lnls, every) a
+    reference update of the request's source is queued (from Python, while
+    the replay runs) at the arrival of every `every`-th request."""
     rng = I.rng_for(5, 1)
     reqs = I.poisson_requests(rng, n_req + warm, rate_hz, 64, len(refs), 4096)
     srv = M.Server(ctx, refs, max_inflight=3, max_batch_walkers=65536, hbm_budget_bytes=2 << 30, prec=prec)
-    lat = [None] * len(reqs)
-    ids = [None] * len(reqs)
-    upd_ids = []
-    done = threading.Event()
-
-    def collector():
-        for i in range(len(reqs)):
-            while ids[i] is None:
-                time.sleep(0.0001)
-            _, l = srv.wait(ids[i], reqs[i][3])
-            lat[i] = l
-        done.set()
-
-    th = threading.Thread(target=collector, daemon=True)
-    th.start()
-    t0 = time.perf_counter()
-    for i, (t_arr, sampler, src, W) in enumerate(reqs):
-        while time.perf_counter() - t0 < t_arr:
-            time.sleep(0.0002)
+    rows, theta, off = [], [], 0
+    for (_, _, src, W) in reqs:
         pool = pools[src]
-        sel = rng.integers(0, len(pool), W)
-        ids[i] = srv.submit(src, pool[sel])
-        if update is not None and i % update[2] == update[2] - 1:
-            upd_ids.append(srv.refresh(src, update[0][src], pool, update[1][src]))
-    done.wait()
+        theta.append(pool[rng.integers(0, len(pool), W)])
+        rows.append(off)
+        off += W
+    theta = np.concatenate(theta)
+    t_arr = [r[0] for r in reqs]
+    result = {}
+
+    def run():
+        result["out"] = srv.replay(t_arr, [r[2] for r in reqs], [r[3] for r in reqs], rows, theta)
+
+    th = threading.Thread(target=run)
+    t0 = time.perf_counter()
+    th.start()
+    upd_ids = []
+    if update is not None:
+        for i in range(update[2] - 1, len(reqs), update[2]):
+            while th.is_alive() and time.perf_counter() - t0 < t_arr[i]:
+                time.sleep(0.0002)
+            src = reqs[i][2]
+            upd_ids.append(srv.refresh(src, update[0][src], pools[src], update[1][src]))
+    th.join()
+    if "out" not in result:
+        raise RuntimeError("server replay failed")
     for u in upd_ids:
         srv.wait(u, 0)
-    wall = time.perf_counter() - t0
+    out_r = result["out"]
     st = srv.stats()
     srv.close()
-    l = np.array(lat[warm:]) * 1e3
+    l = out_r["latency_s"][warm:] * 1e3
     walkers = sum(r[3] for r in reqs)
+    wall = out_r["wall_s"]
     out = dict(p50_ms=float(np.percentile(l, 50)), p99_ms=float(np.percentile(l, 99)),
                throughput_evals_s=walkers / wall, requests_per_s=len(reqs) / wall, requests=n_req,
-               rate_hz=rate_hz, batches=st["batches"],
-               mean_walkers_per_batch=st["walkers"] / max(1, st["batches"]))
+               rate_hz=rate_hz, achieved_over_offered=(len(reqs) / wall) / rate_hz, batches=st["batches"],
+               mean_walkers_per_batch=st["walkers"] / max(1, st["batches"]),
+               max_submit_lag_ms=float(out_r["submit_lag_s"].max() * 1e3))
     if update is not None:
         out["reference_updates"] = len(upd_ids)
         out["max_ms"] = float(l.max())
@@ -398,7 +433,7 @@ def main():
     value = W_total * args.steps / res["mixed"]["wall"]
     fp64_value = W_total * args.steps / res["fp64"]["wall"]
     E = N_BINS + 1
-    flops = W_total * E * FLOPS_PER_EDGE
+    flops = W_total * ALGO_FLOPS_PER_EVAL
     # the main pass's duration inside the step: the step's time less the setup
     # and totals stages (each measured back to back on its own).  Back-to-back
     # launches of the main pass alone overlap one launch's tail with the next
@@ -408,7 +443,9 @@ def main():
 
     t_main = main_in_step(res["mixed"])
     achieved = flops / t_main / 1e12
-    traffic = TRAFFIC["bytes_per_launch"] if TRAFFIC["src_sha256"] == kernel_sources_hash() else None
+    counters_ok = COUNTERS["src_sha256"] == kernel_sources_hash()
+    traffic = COUNTERS["bytes_per_launch"] if counters_ok else None
+    hw_flops = W_total * E * COUNTERS["valu_flops_per_edge"] if counters_ok else None
     out = {
         "metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
@@ -426,11 +463,15 @@ def main():
                      "frac": achieved / PEAK_ALU_TFLOPS, "traffic": traffic,
                      "kernel": "k_het_tiles<float> (main pass, mixed)", "kernel_us": t_main * 1e6,
                      "kernel_us_back_to_back": res["mixed"]["stages_s"][1] * 1e6,
-                     "flops_per_launch": flops},
+                     "flops_per_launch": flops, "algorithmic_flops_per_eval": ALGO_FLOPS_PER_EVAL,
+                     "frac_hw": (hw_flops / t_main / 1e12 / PEAK_ALU_TFLOPS) if hw_flops else None,
+                     "algorithmic_bytes_per_launch": W_total * ALGO_BYTES_PER_EVAL,
+                     "traffic_over_algorithmic": (traffic / (W_total * ALGO_BYTES_PER_EVAL)) if traffic else None},
         "stages_us": {k: {"setup": v["stages_s"][0] * 1e6, "main": v["stages_s"][1] * 1e6,
                           "finish": v["stages_s"][2] * 1e6, "step_events": v["kernel_s"] * 1e6,
                           "step_graph_replay": v["graph_us"]} for k, v in res.items()},
         "fp64_roofline_frac": flops / main_in_step(res["fp64"]) / 1e12 / PEAK_ALU_TFLOPS,
+        "roofline_counters_current": counters_ok,
         "paper_context": {"het_evals_per_s": 2e5, "note": "~5 us per heterodyned lnL, unnamed GPU, PhenomD"},
     }
     copy_calibration()
@@ -438,8 +479,11 @@ def main():
         out.update(side_measurements(M, ctx, S, walkers, grid))
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle) ...")
-        cb = cpu_baseline()
+        cb = cpu_baseline(M, ctx)
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+        out["max_abs_dlnL_vs_oracle"] = {**cb["vs_oracle"], "source": LOUDEST_SOURCE, "walkers": len(TEMPS) * PER_TEMP,
+                                         "oracle_lnL_range": cb["lnL_range"]}
+        log(f"[bench] vs oracle (loudest source, 512 walkers): {out['max_abs_dlnL_vs_oracle']}")
         out["cpu_baseline_full_grid_s_per_eval_per_core"] = cb["full_grid_s_per_eval_per_core"]
         out["cpu_baseline_single_core_evals_per_s"] = cb["single_core_value"]
         out["chirp_case"] = chirp_case(M, ctx)
@@ -465,9 +509,12 @@ def side_measurements(M, ctx, S, walkers, grid):
         dt = time.perf_counter() - t0
         full[name] = lf.cpu().numpy()
         out[f"full_grid_{name}_evals_per_s"] = len(draws) / dt
-        # VALU work from the FLOP counters: FULL_FLOPS_PER_POINT per (walker, grid point)
-        out[f"full_grid_{name}_roofline_frac"] = (len(draws) * grid.n_f * FULL_FLOPS_PER_POINT / dt / 1e12
+        # algorithmic work per (walker, grid point); the counter figure beside it
+        out[f"full_grid_{name}_roofline_frac"] = (len(draws) * grid.n_f * ALGO_FULL_FLOPS_PER_POINT / dt / 1e12
                                                   / PEAK_ALU_TFLOPS)
+        if COUNTERS["src_sha256"] == kernel_sources_hash():
+            out[f"full_grid_{name}_roofline_frac_hw"] = (len(draws) * grid.n_f * COUNTERS["full_valu_flops_per_point"]
+                                                         / dt / 1e12 / PEAK_ALU_TFLOPS)
         log(f"[bench] full grid {name}: {len(draws) / dt:.1f} evals/s")
     # |lnL_mixed - lnL_fp64| per draw, by distance below the best draw
     ok = np.isfinite(full["fp64"])
@@ -587,15 +634,20 @@ def side_measurements(M, ctx, S, walkers, grid):
     refs = [x["ref"] for x in S5.items]
     pools = [S5.walkers(x, (1, 4, 16, 64), 64) for x in S5.items]
     serve = {"sources": [{"modes": int(m), "bins": nb} for m, nb in zip(masks, nbs)]}
-    # capacity: the request rate the server sustains when the submitting
-    # thread never waits (one Python thread submits, another collects)
-    cap = serve_run(M, ctx, refs, pools, M.MIXED, rate_hz=1e7, n_req=20000, warm=1000)
-    serve["capacity_req_per_s"] = cap["requests_per_s"]
-    serve["capacity_evals_per_s"] = cap["throughput_evals_s"]
-    log(f"[bench] serving capacity: {cap['requests_per_s']:.0f} req/s, {cap['throughput_evals_s']:.3g} evals/s")
+    # capacity of each precision: the request rate the server sustains when
+    # every request arrives at once (native replay: no interpreter in the loop)
+    caps = {}
+    for name, prec in (("mixed", M.MIXED), ("fp64", M.FP64)):
+        cap = serve_run(M, ctx, refs, pools, prec, rate_hz=1e9, n_req=20000, warm=1000)
+        caps[name] = cap["requests_per_s"]
+        serve[f"{name}_capacity_req_per_s"] = cap["requests_per_s"]
+        serve[f"{name}_capacity_evals_per_s"] = cap["throughput_evals_s"]
+        log(f"[bench] serving capacity {name}: {cap['requests_per_s']:.0f} req/s, {cap['throughput_evals_s']:.3g} evals/s")
+    serve["capacity_req_per_s"] = serve["mixed_capacity_req_per_s"]
+    serve["capacity_evals_per_s"] = serve["mixed_capacity_evals_per_s"]
     for rho in (0.5, 0.8, 0.95):
         for name, prec in (("mixed", M.MIXED), ("fp64", M.FP64)):
-            r = serve_run(M, ctx, refs, pools, prec, rate_hz=rho * cap["requests_per_s"], n_req=20000, warm=1000)
+            r = serve_run(M, ctx, refs, pools, prec, rate_hz=rho * caps[name], n_req=20000, warm=1000)
             serve[f"{name}_rho{rho}"] = r
             log(f"[bench] serve {name} at {rho} x capacity: {r}")
     # the same stream (0.5 x capacity, mixed) with a reference update (best
@@ -606,7 +658,7 @@ def side_measurements(M, ctx, S, walkers, grid):
         rf.prepare_refresh()
     lnls = [M.loglike_heterodyned(ctx, rf, torch.as_tensor(pl, device="cuda"), M.FP64).cpu().numpy()
             for rf, pl in zip(refs, pools)]
-    r = serve_run(M, ctx, refs, pools, M.MIXED, rate_hz=0.5 * cap["requests_per_s"], n_req=20000, warm=1000,
+    r = serve_run(M, ctx, refs, pools, M.MIXED, rate_hz=0.5 * caps["mixed"], n_req=20000, warm=1000,
                   update=(datas, lnls, 100))
     serve["mixed_rho0.5_with_reference_updates"] = r
     log(f"[bench] serve mixed at 0.5 x capacity with a reference update every 100 requests: {r}")

@@ -350,12 +350,42 @@ mbh_status mbh_server_submit(mbh_server *srv, int ref_index, const double *theta
 mbh_status mbh_server_refresh(mbh_server *srv, int ref_index, const mbh_data *data,
                               const double *theta_host, const double *lnL_host, int64_t W,
                               uint64_t *request_id);
-/* Copy results of a finished request to host buffers (lnL [W], dh_hh [W][2]
- * or NULL) and forget it.  timeout_ms < 0 waits forever, 0 polls.
- * MBH_EAGAIN if not finished in time; MBH_ENOTFOUND for an unknown id.
+/* Copy results of a finished request to host buffers (lnL [W], dh_hh [W][2];
+ * either may be NULL) and forget it.  capacity is the number of walkers the
+ * caller's buffers hold: MBH_EINVAL (nothing copied, the request kept) if a
+ * buffer is given and capacity is below the request's W (0 for a reference
+ * update).  timeout_ms < 0 waits forever, 0 polls.  MBH_EAGAIN if not
+ * finished in time; MBH_ENOTFOUND for an unknown id; MBH_EDEVICE (and the
+ * request forgotten) if its batch or update could not be issued.
  * latency_s_out (may be NULL) = completion time - submit time. */
 mbh_status mbh_server_wait(mbh_server *srv, uint64_t request_id, int timeout_ms,
-                           double *lnL_host, double *dh_hh_host, double *latency_s_out);
+                           double *lnL_host, double *dh_hh_host, int64_t capacity,
+                           double *latency_s_out);
+/* One request of a trace for mbh_server_replay. */
+typedef struct {
+  double t_arrival_s; /* seconds after the replay starts; finite, >= 0, non-decreasing */
+  int32_t ref_index;  /* resident reference                                          */
+  int32_t reserved;   /* 0                                                           */
+  int64_t W;          /* walkers, 1 .. the server's per-batch capacity               */
+  int64_t theta_row;  /* the request's walkers are theta_host[theta_row .. + W)      */
+} mbh_request_spec;
+/* Replay a request trace through the server from native code, so that the
+ * measured latencies and rates are the server's own (no interpreter in the
+ * loop).  The calling thread submits request i (as mbh_server_submit) when
+ * the steady clock reaches t_arrival_s after the start, at once if it is
+ * behind; a second thread collects the results in request order.  Returns
+ * when every request has finished.
+ *   theta_host [theta_rows][11] (host, caller-owned; rows may be shared by
+ *   requests); latency_s [n]: result available on the host minus the
+ *   scheduled arrival (NaN for a request whose batch could not be issued);
+ *   submit_lag_s [n] or NULL: submission minus scheduled arrival (how far
+ *   the submitting thread fell behind); lnL_host [sum W] or NULL: results
+ *   in request order; wall_s or NULL: start to the last result.
+ * Requests submitted by other threads meanwhile are served alongside.
+ * Errors: MBH_EINVAL (bad trace; nothing submitted), MBH_EAGAIN, MBH_EDEVICE. */
+mbh_status mbh_server_replay(mbh_server *srv, const mbh_request_spec *reqs, int64_t n,
+                             const double *theta_host, int64_t theta_rows, double *latency_s,
+                             double *submit_lag_s, double *lnL_host, double *wall_s);
 typedef struct {
   uint64_t submitted, completed, batches, walkers;
   uint64_t max_walkers_in_flight;

@@ -364,6 +364,7 @@ struct Request {
   std::vector<double> lnL, dhhh;
   Clock::time_point t_submit, t_done;
   bool done = false;
+  bool failed = false;  // its launch or update could not be issued
   // reference update: the population (theta, lnL_in) it picks from
   const mbh_data *data = nullptr;
   std::vector<double> lnL_in;
@@ -564,13 +565,17 @@ static void server_loop(mbh_server *s) {
         s->stats.batches += 1;
         lk.unlock();
         bool ok = server_issue_update(s, sl, r);
+        if (!ok) (void)hipStreamSynchronize(sl.st);  // work already enqueued finishes before the slot is reused
         lk.lock();
         if (!ok) {
           s->thread_error = "reference update failed";
+          r->t_done = Clock::now();
+          r->failed = true;
           r->done = true;
           sl.members.clear();
           sl.busy = false;
           s->updates_in_flight -= 1;
+          s->cv_done.notify_all();
         }
         progressed = true;
         continue;
@@ -585,11 +590,21 @@ static void server_loop(mbh_server *s) {
       s->stats.walkers += sl.walkers;
       lk.unlock();
       bool ok = server_launch(s, sl);
+      if (!ok) (void)hipStreamSynchronize(sl.st);  // copies already enqueued finish before the slot is reused
       lk.lock();
       if (!ok) {
         s->thread_error = "launch failed";
-        for (auto &m : sl.members) m.first->done = true;
+        const auto now = Clock::now();
+        for (auto &m : sl.members) {
+          m.first->t_done = now;
+          m.first->failed = true;
+          m.first->done = true;
+        }
+        s->walkers_in_flight -= sl.walkers;
+        s->bytes_in_flight -= (size_t)sl.walkers * s->bytes_per_walker;
+        sl.members.clear();
         sl.busy = false;
+        s->cv_done.notify_all();
       }
       progressed = true;
     }
@@ -744,21 +759,105 @@ extern "C" mbh_status mbh_server_refresh(mbh_server *s, int ref_index, const mbh
 }
 
 extern "C" mbh_status mbh_server_wait(mbh_server *s, uint64_t id, int timeout_ms, double *lnL_host,
-                                      double *dh_hh_host, double *latency_s_out) {
+                                      double *dh_hh_host, int64_t capacity, double *latency_s_out) {
   if (!s) return mbh_fail(MBH_EINVAL, "null server");
   std::unique_lock<std::mutex> lk(s->mu);
   auto it = s->live.find(id);
   if (it == s->live.end()) return mbh_fail(MBH_ENOTFOUND, "request %llu", (unsigned long long)id);
   std::shared_ptr<Request> r = it->second;
+  if ((lnL_host || dh_hh_host) && capacity < r->W)
+    return mbh_fail(MBH_EINVAL, "request %llu holds %lld walkers, the output buffers %lld", (unsigned long long)id,
+                    (long long)r->W, (long long)capacity);
   auto ready = [&] { return r->done; };
   if (timeout_ms < 0) s->cv_done.wait(lk, ready);
   else if (!s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), ready))
     return MBH_EAGAIN;
-  if (!s->thread_error.empty() && r->lnL.empty()) return mbh_fail(MBH_EDEVICE, "server: %s", s->thread_error.c_str());
+  if (r->failed) {
+    s->live.erase(it);
+    return mbh_fail(MBH_EDEVICE, "server: %s", s->thread_error.c_str());
+  }
   if (lnL_host) std::memcpy(lnL_host, r->lnL.data(), r->W * sizeof(double));
   if (dh_hh_host) std::memcpy(dh_hh_host, r->dhhh.data(), r->W * 2 * sizeof(double));
   if (latency_s_out) *latency_s_out = std::chrono::duration<double>(r->t_done - r->t_submit).count();
   s->live.erase(it);
+  return MBH_OK;
+}
+
+// Submit and collect a request trace from native threads: the calling thread
+// submits request i when the steady clock reaches its arrival time, a second
+// thread takes the results in request order as they finish.
+extern "C" mbh_status mbh_server_replay(mbh_server *s, const mbh_request_spec *reqs, int64_t n,
+                                        const double *theta_host, int64_t theta_rows, double *latency_s,
+                                        double *submit_lag_s, double *lnL_host, double *wall_s) {
+  if (!s || !reqs || n < 1 || !theta_host || !latency_s) return mbh_fail(MBH_EINVAL, "bad argument");
+  std::vector<int64_t> out_off((size_t)n + 1, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    const mbh_request_spec &q = reqs[i];
+    if (!(q.t_arrival_s >= 0.0) || (i > 0 && q.t_arrival_s < reqs[i - 1].t_arrival_s))
+      return mbh_fail(MBH_EINVAL, "request %lld: arrival times must be finite, >= 0 and non-decreasing", (long long)i);
+    if (q.ref_index < 0 || q.ref_index >= (int)s->refs.size() || q.W < 1 || q.W > s->cap_walkers ||
+        q.theta_row < 0 || q.theta_row + q.W > theta_rows)
+      return mbh_fail(MBH_EINVAL, "request %lld: bad reference, walker count or theta rows", (long long)i);
+    out_off[i + 1] = out_off[i] + q.W;
+  }
+  using Sec = std::chrono::duration<double>;
+  std::vector<uint64_t> ids((size_t)n, 0);
+  std::vector<std::atomic<int>> posted((size_t)n);
+  for (auto &p : posted) p.store(0);
+  std::atomic<int64_t> submitted{0};
+  mbh_status failure = MBH_OK;
+  std::string failure_msg;
+  const auto t0 = Clock::now();
+  std::thread collector([&] {
+    for (int64_t i = 0; i < n; ++i) {
+      while (!posted[i].load(std::memory_order_acquire)) {
+        if (posted[i].load() < 0) return;
+        std::this_thread::yield();
+      }
+      if (posted[i].load() < 0) return;
+      std::shared_ptr<Request> r;
+      {
+        std::unique_lock<std::mutex> lk(s->mu);
+        auto it = s->live.find(ids[i]);
+        if (it == s->live.end()) continue;
+        r = it->second;
+        s->cv_done.wait(lk, [&] { return r->done; });
+        s->live.erase(it);
+      }
+      const auto arrival = t0 + std::chrono::duration_cast<Clock::duration>(Sec(reqs[i].t_arrival_s));
+      latency_s[i] = r->failed ? NAN : Sec(r->t_done - arrival).count();
+      if (submit_lag_s) submit_lag_s[i] = Sec(r->t_submit - arrival).count();
+      if (lnL_host) {
+        if (r->failed) std::fill(lnL_host + out_off[i], lnL_host + out_off[i + 1], NAN);
+        else std::copy(r->lnL.begin(), r->lnL.end(), lnL_host + out_off[i]);
+      }
+    }
+  });
+  int64_t i = 0;
+  for (; i < n; ++i) {
+    const auto arrival = t0 + std::chrono::duration_cast<Clock::duration>(Sec(reqs[i].t_arrival_s));
+    for (;;) {
+      const auto now = Clock::now();
+      if (now >= arrival) break;
+      if (arrival - now > std::chrono::microseconds(300)) std::this_thread::sleep_for(std::chrono::microseconds(100));
+      else std::this_thread::yield();
+    }
+    mbh_status st = mbh_server_submit(s, reqs[i].ref_index, theta_host + reqs[i].theta_row * 11, reqs[i].W, &ids[i]);
+    if (st != MBH_OK) {
+      failure = st;
+      failure_msg = mbh_last_error();
+      break;
+    }
+    posted[i].store(1, std::memory_order_release);
+  }
+  for (int64_t k = i; k < n; ++k) posted[k].store(-1);
+  collector.join();
+  if (wall_s) *wall_s = Sec(Clock::now() - t0).count();
+  if (failure != MBH_OK) return mbh_fail(failure, "request %lld: %s", (long long)i, failure_msg.c_str());
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    if (!s->thread_error.empty()) return mbh_fail(MBH_EDEVICE, "server: %s", s->thread_error.c_str());
+  }
   return MBH_OK;
 }
 

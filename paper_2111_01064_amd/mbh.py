@@ -52,6 +52,11 @@ class ServerConfig(ct.Structure):
                 ("hbm_budget_bytes", ct.c_size_t), ("prec", ct.c_int)]
 
 
+class RequestSpec(ct.Structure):
+    _fields_ = [("t_arrival_s", ct.c_double), ("ref_index", ct.c_int32), ("reserved", ct.c_int32),
+                ("W", ct.c_int64), ("theta_row", ct.c_int64)]
+
+
 class ServerStats(ct.Structure):
     _fields_ = [("submitted", ct.c_uint64), ("completed", ct.c_uint64), ("batches", ct.c_uint64),
                 ("walkers", ct.c_uint64), ("max_walkers_in_flight", ct.c_uint64),
@@ -93,8 +98,9 @@ _SIGS = {
     "mbh_autotune_load": [_vp, ct.c_char_p],
     "mbh_server_create": [_vp, _i32, _pp, ct.POINTER(ServerConfig), _pp],
     "mbh_server_submit": [_vp, _i32, _dp, _i64, ct.POINTER(ct.c_uint64)],
-    "mbh_server_wait": [_vp, ct.c_uint64, _i32, _dp, _dp, _dp],
+    "mbh_server_wait": [_vp, ct.c_uint64, _i32, _dp, _dp, _i64, _dp],
     "mbh_server_refresh": [_vp, _i32, _vp, _dp, _dp, _i64, ct.POINTER(ct.c_uint64)],
+    "mbh_server_replay": [_vp, ct.POINTER(RequestSpec), _i64, _dp, _i64, _dp, _dp, _dp, _dp],
     "mbh_server_get_stats": [_vp, ct.POINTER(ServerStats)],
     "mbh_server_destroy": [_vp],
 }
@@ -409,16 +415,18 @@ class Server:
         _check(_L.mbh_server_create(ctx.h, n, (ct.c_void_p * n)(*[r.h for r in refs]), ct.byref(cfg),
                                     ct.byref(h)), "mbh_server_create")
         self.h, self.ctx, self._refs = h, ctx, refs
+        self._W = {}  # walkers of each request not yet waited for
 
     def submit(self, ref_index: int, theta: np.ndarray) -> int:
         th = np.ascontiguousarray(theta, dtype=np.float64).reshape(-1, NPARAM)
         rid = ct.c_uint64()
         _check(_L.mbh_server_submit(self.h, ref_index, th.ctypes.data_as(_dp), th.shape[0], ct.byref(rid)),
                "mbh_server_submit")
+        self._W[rid.value] = th.shape[0]
         return rid.value
 
     def refresh(self, ref_index: int, data: "Data", theta: np.ndarray, lnL: np.ndarray) -> int:
-        """mbh_server_refresh: queue a reference update (host population); wait() on the id with W = 0."""
+        """mbh_server_refresh: queue a reference update (host population); wait() on its id returns no results."""
         th = np.ascontiguousarray(theta, dtype=np.float64).reshape(-1, NPARAM)
         lv = np.ascontiguousarray(lnL, dtype=np.float64).reshape(-1)
         if lv.shape[0] != th.shape[0]:
@@ -426,18 +434,49 @@ class Server:
         rid = ct.c_uint64()
         _check(_L.mbh_server_refresh(self.h, ref_index, data.h, th.ctypes.data_as(_dp), lv.ctypes.data_as(_dp),
                                      th.shape[0], ct.byref(rid)), "mbh_server_refresh")
+        self._W[rid.value] = 0
         return rid.value
 
-    def wait(self, rid: int, W: int, timeout_ms: int = -1, want_dh_hh: bool = False):
-        lnL = np.zeros(W)
-        dh = np.zeros((W, 2)) if want_dh_hh else None
+    def wait(self, rid: int, W: int | None = None, timeout_ms: int = -1, want_dh_hh: bool = False):
+        """mbh_server_wait; the buffers are sized from the request's own walker
+        count (W, if given, must equal it)."""
+        n = self._W.get(rid)
+        if n is None:
+            raise KeyError(f"unknown request {rid}")
+        if W is not None and W != n:
+            raise ValueError(f"request {rid} holds {n} walkers, not {W}")
+        lnL = np.zeros(n)
+        dh = np.zeros((n, 2)) if want_dh_hh else None
         lat = ct.c_double()
         st = _L.mbh_server_wait(self.h, rid, timeout_ms, lnL.ctypes.data_as(_dp),
-                                dh.ctypes.data_as(_dp) if dh is not None else None, ct.byref(lat))
+                                dh.ctypes.data_as(_dp) if dh is not None else None, n, ct.byref(lat))
         if st == MBH_EAGAIN:
             return None
+        if st in (MBH_OK, MBH_EDEVICE, MBH_ENOTFOUND):  # the library has forgotten the request
+            del self._W[rid]
         _check(st, "mbh_server_wait")
         return (lnL, dh, lat.value) if want_dh_hh else (lnL, lat.value)
+
+    def replay(self, t_arrival, ref_index, W, theta_row, theta: np.ndarray, want_lnL: bool = False):
+        """mbh_server_replay: submit a request trace at its arrival times and
+        collect it, all in native threads.  Returns a dict with per-request
+        latency_s and submit_lag_s, wall_s and (want_lnL) the results in
+        request order."""
+        n = len(t_arrival)
+        specs = (RequestSpec * n)()
+        for i in range(n):
+            specs[i] = RequestSpec(float(t_arrival[i]), int(ref_index[i]), 0, int(W[i]), int(theta_row[i]))
+        th = np.ascontiguousarray(theta, dtype=np.float64).reshape(-1, NPARAM)
+        lat, lag = np.zeros(n), np.zeros(n)
+        lnL = np.zeros(int(np.sum(W))) if want_lnL else None
+        wall = ct.c_double()
+        _check(_L.mbh_server_replay(self.h, specs, n, th.ctypes.data_as(_dp), th.shape[0], lat.ctypes.data_as(_dp),
+                                    lag.ctypes.data_as(_dp), lnL.ctypes.data_as(_dp) if lnL is not None else None,
+                                    ct.byref(wall)), "mbh_server_replay")
+        out = dict(latency_s=lat, submit_lag_s=lag, wall_s=wall.value)
+        if want_lnL:
+            out["lnL"] = lnL
+        return out
 
     def stats(self) -> dict:
         s = ServerStats()

@@ -162,6 +162,50 @@ def test_server_alone_equals_mix_and_backpressure(M, ctx, sources):
     small.close()
 
 
+def test_server_replay_and_wait_capacity(M, ctx, sources):
+    """A Poisson trace replayed from native threads (mbh_server_replay): every
+    result equals the single call on the same walkers bit for bit, latencies
+    are positive; mbh_server_wait refuses output buffers smaller than the
+    request."""
+    import ctypes as ct
+
+    refs = [s["gref"] for s in sources[:4]]
+    srv = M.Server(ctx, refs, max_inflight=3, max_batch_walkers=16384, hbm_budget_bytes=256 << 20, prec=M.MIXED)
+    rng = I.rng_for(5, 2)
+    trace = I.poisson_requests(rng, 200, 20000.0, 64, 4, 512)
+    pools = [sources[k]["walkers"] for k in range(4)]
+    rows, theta = [], []
+    off = 0
+    for (_, _, src, W) in trace:
+        sel = pools[src][rng.integers(0, len(pools[src]), W)]
+        theta.append(sel)
+        rows.append(off)
+        off += W
+    theta = np.concatenate(theta)
+    out = srv.replay([t for (t, _, _, _) in trace], [src for (_, _, src, _) in trace],
+                     [W for (_, _, _, W) in trace], rows, theta, want_lnL=True)
+    assert np.all(out["latency_s"] > 0) and np.all(np.isfinite(out["latency_s"]))
+    assert out["wall_s"] > 0
+    k = 0
+    for (t, _, src, W), r0 in zip(trace, rows):
+        ref = M.loglike_heterodyned(ctx, refs[src], _t(theta[r0:r0 + W]), M.MIXED).cpu().numpy()
+        assert np.array_equal(out["lnL"][k:k + W], ref)
+        k += W
+    print(f"[serve] replay of {len(trace)} requests: p50 {np.percentile(out['latency_s'], 50) * 1e3:.3f} ms, "
+          f"p99 {np.percentile(out['latency_s'], 99) * 1e3:.3f} ms, wall {out['wall_s']:.3f} s", flush=True)
+    # output capacity below the request's walker count: refused, the request kept
+    rid = srv.submit(0, pools[0][:10])
+    buf = np.zeros(9)
+    lat = ct.c_double()
+    st = M._L.mbh_server_wait(srv.h, rid, -1, buf.ctypes.data_as(M._dp), None, 9, ct.byref(lat))
+    assert st == M.MBH_EINVAL
+    res, _ = srv.wait(rid)
+    assert res.shape == (10,) and np.all(np.isfinite(res))
+    st = srv.stats()
+    assert st["completed"] == st["submitted"] == len(trace) + 1
+    srv.close()
+
+
 def test_autotuner_records_a_valid_choice(M, ctx, sources, tmp_path):
     s = sources[0]
     lanes = M.autotune_heterodyned(ctx, s["gref"], _t(s["walkers"]), M.MIXED)

@@ -1,13 +1,19 @@
-"""Parity at the benchmark's full size: the 1-yr grid at dt = 10 s
-(1 577 880 Fourier bins x 3 channels), 128 bins, each source with
-8 temperatures x 64 walkers, launched the way bench.py launches the step (a
-batch issued with mbh_batch_launch_direct, flattened mapping).  The data,
-references and walkers come from the oracle and the input generators only.
+"""Parity at the benchmark's full size, on the benchmark's own workload: the
+1-yr grid at dt = 10 s (1 577 880 Fourier bins x 3 channels), 128 bins, the
+eight sources of the benchmark step (the same seeds and recipe, SNR 107-948)
+with 8 temperatures x 64 walkers each (4096 walkers), launched the way
+bench.py launches the step (one batch issued with mbh_batch_launch_direct,
+flattened mapping).  The data, references and walkers come from the oracle
+and the input generators only (the benchmark sets D_L from the library's
+<h|h>; here it is the oracle's, so the data agree with the benchmark's to
+rounding, not bit for bit).
 
 Every heterodyned result of the batch is checked against the oracle's
-heterodyned likelihood (cheap per walker at any grid size); the reference
-build (coefficients, band, lnL(h0)) and a few full-grid evaluations, which
-cost the oracle about half a second each at this size, are checked too.
+heterodyned likelihood (cheap per walker at any grid size) in both
+precisions; the reference build (coefficients, band, lnL(h0) against the
+oracle's full grid) and three full-grid walkers per source (cold, warm and
+hot rungs), which cost the oracle about half a second each at this size,
+are checked too.
 """
 import numpy as np
 import pytest
@@ -18,7 +24,7 @@ from paper_2111_01064_amd import inputs as I
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-3
-N_SOURCES = 2
+N_SOURCES = 8  # the benchmark step's sources
 TEMPS = (1, 2, 4, 8, 16, 32, 64, 128)
 PER_TEMP = 64
 N_BINS = 128
@@ -44,7 +50,7 @@ def full(M, ctx):
     psd = I.psd_lisa_aet(g.freqs)
     out = []
     for s in range(N_SOURCES):
-        rng = I.rng_for(6, s)
+        rng = I.rng_for(2, s)  # the benchmark step's seeds
         th, snr = I.draw_mbhb_source(rng, g.t_obs)
         # the template scales as 1/D_L (placeholder 1 Gpc)
         h = O.template(O.MODEL_IMR, O.MODE_22, th, g.freqs, g.t_obs)
