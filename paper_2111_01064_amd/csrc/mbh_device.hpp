@@ -278,6 +278,18 @@ struct Prec<float> {
   static __device__ __forceinline__ float sqrt_r(float x) { return sqrtf(x); }
 };
 
+// FP64 arctangent: the FP32 value refined by one Newton step in FP64 on
+// g(a) = sin a - z cos a, whose second derivative vanishes at the root
+// a = atan z, so the step converges cubically (relative error ~1e-7 -> below
+// the FP64 rounding level).  Shorter and far lighter on registers than a
+// full FP64 polynomial, and the same in both precision paths.
+__device__ __forceinline__ double atan64_nr(double z) {
+  const double a = (double)atanf((float)z);
+  double s, c;
+  sincos_red<double>(a, s, c);
+  return a - (s - z * c) * rcp64_nr(fma(z, s, c));
+}
+
 // FP64 quotient x / y through the refined reciprocal (within 1 ulp; the
 // per-walker constants below need no correctly rounded division)
 __device__ __forceinline__ double div64(double x, double y) { return x * rcp64_nr(y); }
@@ -292,7 +304,7 @@ __device__ __forceinline__ void sincos_param(double x, double &s, double &c) {
 __device__ __forceinline__ void raw_phase_mr(const WalkerC &w, double f, double &ph, double &dph) {
   const double x = f - w.f1, y = f - w.fRD;
   const double L = div64(w.fD, y * y + w.fD * w.fD);
-  ph = w.P1 + w.dP1 * x + kKappa * (atan(y * w.inv_fD) - w.at1 - w.L1 * x);
+  ph = w.P1 + w.dP1 * x + kKappa * (atan64_nr(y * w.inv_fD) - w.at1 - w.L1 * x);
   dph = w.dP1 + kKappa * (L - w.L1);
 }
 
@@ -399,7 +411,7 @@ __device__ __forceinline__ void walker_setup(const double *__restrict__ th, int 
   w.lam_num = sq(w.f1 - w.fRD) + w.fD * w.fD;
   w.inv_fD = rcp64_nr(w.fD);
   w.L1 = div64(w.fD, w.lam_num);
-  w.at1 = atan((w.f1 - w.fRD) * w.inv_fD);
+  w.at1 = atan64_nr((w.f1 - w.fRD) * w.inv_fD);
   // f_max lies past f1 (the (2,2) amplitude peaks in the merger-ringdown part)
   raw_phase_mr(w, w.fmax, w.ph_max, w.dph_max);
   w.AN = kPi * sqrt(2.0 * eta / 3.0) * M * M / DL * kAmpScale;
@@ -462,7 +474,7 @@ __device__ __forceinline__ void wf22(const WalkerC &w, double fp, const FreqPow 
   const double dph_i = (w.d5 * iv5 + w.d3 * iv3 + w.d2 * iv2) * pw.fi;
   const double x = fp - w.f1, y = fp - w.fRD;
   const double t = rsq64_nr(y * y + w.fD * w.fD);
-  const double ph_m = w.P1 + w.dP1 * x + kKappa * ((atan(y * w.inv_fD) - w.at1) - w.L1 * x);
+  const double ph_m = w.P1 + w.dP1 * x + kKappa * ((atan64_nr(y * w.inv_fD) - w.at1) - w.L1 * x);
   const double dph_m = w.dP1 + kKappa * (w.fD * (t * t) - w.L1);
   const bool insp = fp <= w.f1;
   ph = insp ? ph_i : ph_m;
@@ -679,7 +691,10 @@ __device__ __forceinline__ void response_mode(const WalkerC &w, double kp, doubl
 // per-walker constant factor (amplitude, polarisation weights, e^{i m phi_ref},
 // mode phase) is applied in FP64, so FP32 rounding cannot act as a coherent
 // shift of D_L or phi_ref.  Returns true if any mode is inside its support.
-template <typename R>
+// HM = false compiles the (2,2) mode alone (callers pass it only for mode
+// mask (2,2) or the chirp model): without the higher-mode loop the kernels
+// need under half the registers and run at several times the occupancy.
+template <typename R, bool HM = true>
 __device__ __forceinline__ bool template_point(const WalkerC &w, uint32_t modes, double f, const FreqPow &pw,
                                                const FreqC &fc, double t_obs, cx<double> s[3], double &psi) {
   if (w.model == 1) {  // 0PN chirp, one channel
@@ -706,7 +721,7 @@ __device__ __forceinline__ bool template_point(const WalkerC &w, uint32_t modes,
   s[0] = s[1] = s[2] = mk<double>(0.0, 0.0);
   bool any = false;
 #pragma unroll 1
-  for (int mi = 0; mi < kNumModes; ++mi) {
+  for (int mi = 0; mi < (HM ? kNumModes : 1); ++mi) {
     if (!(modes & (1u << mi))) continue;
     int m = kModeM[mi];
     double fp = 2.0 * f / m;

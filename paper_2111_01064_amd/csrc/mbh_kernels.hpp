@@ -177,7 +177,8 @@ static __global__ __launch_bounds__(kBlock) void k_template_grid(const WalkerC *
 // ---------------------------------------------------------------- a9: reference build
 // pass 1: whitened h0 on the grid, band ends, and block partials of
 // -2 lnL(h0) = sum |dw - h0w|^2, <d|h0>, <h0|h0>
-static __global__ __launch_bounds__(kBlock) void k_ref_grid(const WalkerC *__restrict__ wc, uint32_t modes, int n_chan,
+template <bool HM>
+__global__ __launch_bounds__(kBlock) void k_ref_grid(const WalkerC *__restrict__ wc, uint32_t modes, int n_chan,
                                                      int64_t n_f, double f0, double df, double t_obs,
                                                      const double2 *__restrict__ dw, const double *__restrict__ sw,
                                                      double2 *__restrict__ h0w, unsigned long long *band,
@@ -193,7 +194,7 @@ static __global__ __launch_bounds__(kBlock) void k_ref_grid(const WalkerC *__res
     double f = grid_freq(f0, df, k);
     cx<double> s[3];
     double psi;
-    bool any = template_point<double>(w, modes, f, freq_pows(f), freq_consts<double>(f, ns), t_obs, s, psi);
+    bool any = template_point<double, HM>(w, modes, f, freq_pows(f), freq_consts<double>(f, ns), t_obs, s, psi);
     double sp = 0.0, cp = 1.0;
     if (any) sincos_red<double>(reduce_2pi(psi), sp, cp);
     bool nz = false;
@@ -578,6 +579,7 @@ struct WorkItem {
   int64_t W;
   int64_t offset;        // first walker of this item in its batch
   int32_t E, K, G, model;
+  int32_t hm, pad;       // hm: the reference has modes beyond (2,2) (kernels compiled with HM)
 };
 
 // chunks of the flattened main pass (the last bin sits at task W E - 2)
@@ -586,14 +588,14 @@ __host__ __device__ inline int64_t flat_chunks(int64_t W, int E) { return (W * E
 __host__ __device__ inline int flat_slots(int E) { return (E - 2) / kChunk + 2; }
 
 // delta = r - 1 at edge j of walker c
-template <typename R>
+template <typename R, bool HM>
 __device__ __forceinline__ void het_edge(const HetRef &ref, const WalkerC &c, int j, cx<double> dl[3]) {
   cx<double> s[3];
   double psi;
   const double *q = ref.fq + (int64_t)kFq * j;
   const FreqC fc{q[0], q[1], q[2], sizeof(R) == 8 ? ref.ns64 : ref.ns32};
   const FreqPow pw{q[3], q[4], q[5], q[6]};
-  template_point<R>(c, ref.modes, ref.F[j], pw, fc, ref.t_obs, s, psi);
+  template_point<R, HM>(c, ref.modes, ref.F[j], pw, fc, ref.t_obs, s, psi);
   // the carrier difference enters every channel of the edge at once: formed
   // and reduced to [-pi, pi] in FP64 in both paths; its sine and cosine in
   // the template precision (in FP32 they add an edge-to-edge random error of
@@ -661,7 +663,7 @@ __device__ __forceinline__ void bin_terms(const HetRef &ref, int b, const cx<dou
 // edge.  Every lane of the wavefront runs the loop (the rotations read other
 // lanes); lanes whose `on` is false evaluate nothing and sum zeros.  Returns
 // the group's sums in every lane of the group.
-template <typename R, int G, bool EST, bool DH>
+template <typename R, int G, bool EST, bool DH, bool HM>
 __device__ __forceinline__ void group_sums(const WorkItem &it, const WalkerC &c, bool on, double v[4]) {
   const int lane = threadIdx.x & 63;
   const int gl = lane & (G - 1);
@@ -678,7 +680,7 @@ __device__ __forceinline__ void group_sums(const WorkItem &it, const WalkerC &c,
     cx<double> dl[3];
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) dl[ch] = mk<double>(0.0, 0.0);
-    if (on && j < E) het_edge<R>(it.ref, c, j, dl);
+    if (on && j < E) het_edge<R, HM>(it.ref, c, j, dl);
     cx<double> nb[3], lft[3];
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
@@ -703,7 +705,7 @@ __device__ __forceinline__ void group_sums(const WorkItem &it, const WalkerC &c,
 // mixed path a walker whose error sum reaches est_lim is recomputed in FP64
 // by its group (the other groups of the wavefront take part in the rotations
 // only).
-template <typename R, int G, bool DH>
+template <typename R, int G, bool DH, bool HM>
 __device__ __forceinline__ void het_walker(const WorkItem &it, int64_t w) {
   constexpr bool EST = sizeof(R) == 4;
   const int lane = threadIdx.x & 63;
@@ -714,13 +716,13 @@ __device__ __forceinline__ void het_walker(const WorkItem &it, int64_t w) {
   const WalkerC &c = it.wc[active ? w : 0];
   const bool valid = active && c.valid;
   double v[4];
-  group_sums<R, G, EST, DH>(it, c, valid, v);
+  group_sums<R, G, EST, DH, HM>(it, c, valid, v);
   if constexpr (EST) {
     const bool redo = valid && !(v[3] < it.est_lim);
     const uint64_t m = __ballot(redo && gl == 0);
     if (m) {
       double u[4];
-      group_sums<double, G, false, DH>(it, c, redo, u);
+      group_sums<double, G, false, DH, HM>(it, c, redo, u);
       if (redo) {
 #pragma unroll
         for (int q = 0; q < 3; ++q) v[q] = u[q];
@@ -739,13 +741,13 @@ __device__ __forceinline__ void het_walker(const WorkItem &it, int64_t w) {
 // Bin terms of one lane of a flattened chunk: the lane's edge value, the
 // right neighbour's from lane + 1, and the terms of the bin starting at the
 // lane's edge (zero where `bin` is false).  Run by every lane of the wavefront.
-template <typename R, bool EST, bool DH>
+template <typename R, bool EST, bool DH, bool HM>
 __device__ __forceinline__ void chunk_terms(const WorkItem &it, const WalkerC &c, int j, bool edge, bool bin,
                                             double val[4]) {
   cx<double> dl[3];
 #pragma unroll
   for (int ch = 0; ch < 3; ++ch) dl[ch] = mk<double>(0.0, 0.0);
-  if (edge) het_edge<R>(it.ref, c, j, dl);
+  if (edge) het_edge<R, HM>(it.ref, c, j, dl);
   cx<double> nb[3];
 #pragma unroll
   for (int ch = 0; ch < 3; ++ch) {
@@ -773,7 +775,7 @@ __device__ __forceinline__ void segment_sums(const double val[4], bool mine, dou
 // On the mixed path, the segments whose error sum reaches their share of
 // est_lim are recomputed in FP64 by the same wavefront before their slots are
 // written.
-template <typename R, bool DH>
+template <typename R, bool DH, bool HM>
 __device__ __forceinline__ void het_chunk(const WorkItem &it, int64_t chunk) {
   constexpr bool EST = sizeof(R) == 4;
   const int lane = threadIdx.x & 63;
@@ -792,7 +794,7 @@ __device__ __forceinline__ void het_chunk(const WorkItem &it, int64_t chunk) {
   const bool valid = act && c.valid;
   const bool is_bin = valid && lane < kChunk && j < E - 1;
   double val[4];
-  chunk_terms<R, EST, DH>(it, c, j, valid, is_bin, val);
+  chunk_terms<R, EST, DH, HM>(it, c, j, valid, is_bin, val);
   // walkers with a bin in the chunk: v0 unless the chunk starts at its last
   // edge, up to the walker of lane kChunk - 1
   const int64_t v_lo = v0 + (j0 == E - 1 ? 1 : 0);
@@ -818,7 +820,7 @@ __device__ __forceinline__ void het_chunk(const WorkItem &it, int64_t chunk) {
   if constexpr (EST) {
     if (redo) {
       const bool mine = (redo >> qv) & 1ull;
-      chunk_terms<double, false, DH>(it, c, j, valid && mine, is_bin && mine, val);
+      chunk_terms<double, false, DH, HM>(it, c, j, valid && mine, is_bin && mine, val);
       for (int64_t vs = v_lo; vs <= v_hi; ++vs) {
         if (!((redo >> (vs - v0)) & 1ull)) continue;
         double s[4];
@@ -882,17 +884,17 @@ static __global__ __launch_bounds__(128) void k_setup_one(WorkItem one) {
 }
 
 // single-item launches of the main pass
-template <typename R, int G, bool DH>
+template <typename R, int G, bool DH, bool HM>
 __global__ __launch_bounds__(kBlock, 2) void k_het_lane(WorkItem one) {
   one.ref = with_meta(one.ref);
-  het_walker<R, G, DH>(one, (int64_t)blockIdx.x * (kBlock / G) + threadIdx.x / G);
+  het_walker<R, G, DH, HM>(one, (int64_t)blockIdx.x * (kBlock / G) + threadIdx.x / G);
 }
 
-template <typename R, bool DH>
+template <typename R, bool DH, bool HM>
 __global__ __launch_bounds__(kBlock, 2) void k_het_flat(WorkItem one, int64_t n_chunks) {
   const int64_t c = (int64_t)blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   one.ref = with_meta(one.ref);
-  if (c < n_chunks) het_chunk<R, DH>(one, c);
+  if (c < n_chunks) het_chunk<R, DH, HM>(one, c);
 }
 
 // ---------------------------------------------------------------- a8: full grid
@@ -911,7 +913,7 @@ struct DataPtrs<float> {
   using R2 = float2;
 };
 
-template <typename R, int KF, bool DH>
+template <typename R, int KF, bool DH, bool HM>
 __global__ __launch_bounds__(kBlock, 2) void k_full(const typename DataPtrs<R>::R2 *__restrict__ dw,
                                                  const R *__restrict__ sw, int n_chan, int64_t n_f, double f0,
                                                  double df, double t_obs, uint32_t modes,
@@ -960,7 +962,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_full(const typename DataPtrs<R>::
         if (!inr[i]) continue;
         cx<double> s[3];
         double psi;
-        bool any = template_point<R>(c, modes, fq[i], freq_pows(fq[i]), fcs[i], t_obs, s, psi);
+        bool any = template_point<R, HM>(c, modes, fq[i], freq_pows(fq[i]), fcs[i], t_obs, s, psi);
         R sp = (R)0, cp = (R)1;
         if (any) Prec<R>::sincos_r((R)reduce_2pi(psi), sp, cp);
 #pragma unroll

@@ -197,6 +197,24 @@ extern "C" mbh_status mbh_memory_in_use(const mbh_ctx *ctx, size_t *bytes_out) {
   return MBH_OK;
 }
 
+// The kernels that generate templates are compiled twice: for the (2,2)
+// mode alone (the chirp model included) and for any mode mask.
+static bool modes_hm(int model, uint32_t modes) { return model != MBH_MODEL_TF2 && modes != MBH_MODE_22; }
+
+// workgroups of `block` threads of kernel k resident on the whole device at once
+static int resident_blocks(const mbh_ctx *ctx, const void *k, int block) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, block, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+  return per_cu * ctx->n_cu;
+}
+
+// the reference grid pass for this mode set and its grid: one round of
+// resident workgroups (more workgroups run in several rounds and were
+// measured slower)
+static const void *ref_grid_kernel(bool hm) {
+  return hm ? reinterpret_cast<const void *>(&k_ref_grid<true>) : reinterpret_cast<const void *>(&k_ref_grid<false>);
+}
+
 // ---------------------------------------------------------------- data
 static int grid_blocks(int64_t n, int cap) {
   int64_t b = (n + kBlock - 1) / kBlock;
@@ -422,15 +440,18 @@ extern "C" mbh_status mbh_build_reference_coeffs(mbh_ctx *ctx, const mbh_data *d
   unsigned long long *band = nullptr;
   MBH_TRY(sc.get(&band, 2));
   // one workgroup of four wavefronts per two SIMDs: the whole grid pass in a
-  // single round of resident wavefronts (2 per SIMD at its register use);
-  // more workgroups run in several rounds and were measured slower
-  const int nb1 = grid_blocks(N, 2 * ctx->n_cu);
+  const bool hm = modes_hm(model, modes);
+  const int nb1 = grid_blocks(N, resident_blocks(ctx, ref_grid_kernel(hm), kBlock));
   double *part1 = nullptr, *sums1 = nullptr;
   MBH_TRY(sc.get(&part1, (size_t)nb1 * 3));
   MBH_TRY(sc.get(&sums1, 3));
   hipLaunchKernelGGL(k_init_band, dim3(1), dim3(1), 0, st, band);
-  hipLaunchKernelGGL(k_ref_grid, dim3(nb1), dim3(kBlock), 0, st, wc, modes, C, N, data->f0, data->df,
-                     data->t_obs, data->dw64, data->sw64, h0w, band, part1, nullptr);
+  if (hm)
+    hipLaunchKernelGGL(k_ref_grid<true>, dim3(nb1), dim3(kBlock), 0, st, wc, modes, C, N, data->f0, data->df,
+                       data->t_obs, data->dw64, data->sw64, h0w, band, part1, nullptr);
+  else
+    hipLaunchKernelGGL(k_ref_grid<false>, dim3(nb1), dim3(kBlock), 0, st, wc, modes, C, N, data->f0, data->df,
+                       data->t_obs, data->dw64, data->sw64, h0w, band, part1, nullptr);
   hipLaunchKernelGGL(k_sum_partials, dim3(3), dim3(64), 0, st, part1, nb1, 3, 3, sums1);
   HIP_TRY(hipGetLastError());
   unsigned long long hb[2];
@@ -679,7 +700,7 @@ static mbh_status refresh_alloc(mbh_ref *r, hipStream_t st) {
     f.max_len = std::min<int64_t>(N, (int64_t)std::ceil(len) + 3);
   }
   f.n_sub = (int)std::max<int64_t>(1, (f.max_len + kRefChunk - 1) / kRefChunk);
-  f.nb1 = grid_blocks(N, 2 * ctx->n_cu);  // as in the build's grid pass
+  f.nb1 = grid_blocks(N, resident_blocks(ctx, ref_grid_kernel(modes_hm(r->model, r->modes)), kBlock));  // as in the build
   std::vector<std::pair<void **, size_t>> want = {
       {(void **)&f.wc, sizeof(WalkerC)},
       {(void **)&f.band, 2 * sizeof(unsigned long long)},
@@ -758,8 +779,12 @@ extern "C" mbh_status mbh_ref_refresh(mbh_ctx *ctx, const mbh_data *data, mbh_re
   const int64_t max_len = f.max_len;
   hipLaunchKernelGGL(k_refresh_pick, dim3(1), dim3(256), 0, st, theta_dev, lnL_dev, W, r->model, r->modes, wc, band,
                      f.meta);
-  hipLaunchKernelGGL(k_ref_grid, dim3(nb1), dim3(kBlock), 0, st, wc, r->modes, C, N, f0, df, data->t_obs, data->dw64,
-                     data->sw64, h0w, band, part1, f.meta);
+  if (modes_hm(r->model, r->modes))
+    hipLaunchKernelGGL(k_ref_grid<true>, dim3(nb1), dim3(kBlock), 0, st, wc, r->modes, C, N, f0, df, data->t_obs,
+                       data->dw64, data->sw64, h0w, band, part1, f.meta);
+  else
+    hipLaunchKernelGGL(k_ref_grid<false>, dim3(nb1), dim3(kBlock), 0, st, wc, r->modes, C, N, f0, df, data->t_obs,
+                       data->dw64, data->sw64, h0w, band, part1, f.meta);
   hipLaunchKernelGGL(k_sum_partials, dim3(3), dim3(64), 0, st, part1, nb1, 3, 3, sums1);
   hipLaunchKernelGGL(k_refresh_edges, dim3(1), dim3(256), 0, st, band, f0, df, Nb, max_len, f.F, f.kb, f.meta);
   hipLaunchKernelGGL(k_ref_bins, dim3(Nb, n_sub), dim3(kBlock), 0, st, f.kb, f.F, Nb, n_sub, C, N, f0, df,
@@ -857,6 +882,7 @@ WorkItem make_item(const mbh_ctx *ctx, const mbh_ref *r, int G) {
   it.K = flat_slots(it.E);
   it.G = G;
   it.model = r->model;
+  it.hm = modes_hm(r->model, r->modes) ? 1 : 0;
   double tol;
   {
     std::lock_guard<std::mutex> g(ctx->mu);
@@ -866,35 +892,41 @@ WorkItem make_item(const mbh_ctx *ctx, const mbh_ref *r, int G) {
   return it;
 }
 
-template <typename R, bool DH>
+template <typename R, bool DH, bool HM>
 static void launch_main_t(const WorkItem &it, hipStream_t st) {
   if (it.G == 0) {
     const int64_t nc = flat_chunks(it.W, it.E);
-    hipLaunchKernelGGL((k_het_flat<R, DH>), dim3((unsigned)((nc + kWaves - 1) / kWaves)), dim3(kBlock), 0, st, it,
-                       nc);
+    hipLaunchKernelGGL((k_het_flat<R, DH, HM>), dim3((unsigned)((nc + kWaves - 1) / kWaves)), dim3(kBlock), 0, st,
+                       it, nc);
     return;
   }
   const int wpb = kBlock / it.G;
   const dim3 grid((unsigned)((it.W + wpb - 1) / wpb)), blk(kBlock);
   switch (it.G) {
-    case 1: hipLaunchKernelGGL((k_het_lane<R, 1, DH>), grid, blk, 0, st, it); break;
-    case 2: hipLaunchKernelGGL((k_het_lane<R, 2, DH>), grid, blk, 0, st, it); break;
-    case 4: hipLaunchKernelGGL((k_het_lane<R, 4, DH>), grid, blk, 0, st, it); break;
-    case 8: hipLaunchKernelGGL((k_het_lane<R, 8, DH>), grid, blk, 0, st, it); break;
-    case 16: hipLaunchKernelGGL((k_het_lane<R, 16, DH>), grid, blk, 0, st, it); break;
-    case 32: hipLaunchKernelGGL((k_het_lane<R, 32, DH>), grid, blk, 0, st, it); break;
-    default: hipLaunchKernelGGL((k_het_lane<R, 64, DH>), grid, blk, 0, st, it); break;
+    case 1: hipLaunchKernelGGL((k_het_lane<R, 1, DH, HM>), grid, blk, 0, st, it); break;
+    case 2: hipLaunchKernelGGL((k_het_lane<R, 2, DH, HM>), grid, blk, 0, st, it); break;
+    case 4: hipLaunchKernelGGL((k_het_lane<R, 4, DH, HM>), grid, blk, 0, st, it); break;
+    case 8: hipLaunchKernelGGL((k_het_lane<R, 8, DH, HM>), grid, blk, 0, st, it); break;
+    case 16: hipLaunchKernelGGL((k_het_lane<R, 16, DH, HM>), grid, blk, 0, st, it); break;
+    case 32: hipLaunchKernelGGL((k_het_lane<R, 32, DH, HM>), grid, blk, 0, st, it); break;
+    default: hipLaunchKernelGGL((k_het_lane<R, 64, DH, HM>), grid, blk, 0, st, it); break;
   }
+}
+
+template <typename R, bool DH>
+static void launch_main_m(const WorkItem &it, hipStream_t st) {
+  if (it.hm) launch_main_t<R, DH, true>(it, st);
+  else launch_main_t<R, DH, false>(it, st);
 }
 
 // main heterodyned pass of one item (partial sums only)
 static void launch_main(int prec, bool dh, const WorkItem &it, hipStream_t st) {
   if (prec == MBH_FP64) {
-    if (dh) launch_main_t<double, true>(it, st);
-    else launch_main_t<double, false>(it, st);
+    if (dh) launch_main_m<double, true>(it, st);
+    else launch_main_m<double, false>(it, st);
   } else {
-    if (dh) launch_main_t<float, true>(it, st);
-    else launch_main_t<float, false>(it, st);
+    if (dh) launch_main_m<float, true>(it, st);
+    else launch_main_m<float, false>(it, st);
   }
 }
 
@@ -979,7 +1011,7 @@ extern "C" mbh_status mbh_loglike_heterodyned_noalloc(mbh_ctx *ctx, const mbh_re
 }
 
 // ---------------------------------------------------------------- full grid
-template <typename R, bool DH>
+template <typename R, bool DH, bool HM>
 static mbh_status full_impl(mbh_ctx *ctx, const mbh_data *d, uint32_t modes, const WalkerC *wc, int64_t W,
                             double *lnL, double *dhhh, hipStream_t st, Scratch &sc) {
   constexpr int KF = 2;
@@ -1001,10 +1033,10 @@ static mbh_status full_impl(mbh_ctx *ctx, const mbh_data *d, uint32_t modes, con
   MBH_TRY(sc.get(&part, (size_t)nv * n_fc * W));
   dim3 grid((unsigned)n_fc, (unsigned)n_wc);
   if constexpr (sizeof(R) == 8)
-    hipLaunchKernelGGL((k_full<double, KF, DH>), grid, dim3(kBlock), 0, st, d->dw64, d->sw64, d->n_chan, d->n_f,
+    hipLaunchKernelGGL((k_full<double, KF, DH, HM>), grid, dim3(kBlock), 0, st, d->dw64, d->sw64, d->n_chan, d->n_f,
                        d->f0, d->df, d->t_obs, modes, wc, W, (int)wpb, part);
   else
-    hipLaunchKernelGGL((k_full<float, KF, DH>), grid, dim3(kBlock), 0, st, d->dw32, d->sw32, d->n_chan, d->n_f,
+    hipLaunchKernelGGL((k_full<float, KF, DH, HM>), grid, dim3(kBlock), 0, st, d->dw32, d->sw32, d->n_chan, d->n_f,
                        d->f0, d->df, d->t_obs, modes, wc, W, (int)wpb, part);
   hipLaunchKernelGGL(k_full_reduce, dim3((unsigned)((W + kBlock / 64 - 1) / (kBlock / 64))), dim3(kBlock), 0, st,
                      part, (int)n_fc, W, nv, wc, lnL, dhhh);
@@ -1027,11 +1059,19 @@ extern "C" mbh_status mbh_loglike_full(mbh_ctx *ctx, const mbh_data *data, int m
   hipLaunchKernelGGL(k_walker_setup, dim3((unsigned)((W + 63) / 64)), dim3(128), 0, st, theta_dev, W, model,
                      model == MBH_MODEL_IMR ? modes : 0u, wc);
   uint32_t m = model == MBH_MODEL_IMR ? modes : 0u;
-  if (prec == MBH_FP64)
-    return dh_hh_dev ? full_impl<double, true>(ctx, data, m, wc, W, lnL_dev, dh_hh_dev, st, sc)
-                     : full_impl<double, false>(ctx, data, m, wc, W, lnL_dev, nullptr, st, sc);
-  return dh_hh_dev ? full_impl<float, true>(ctx, data, m, wc, W, lnL_dev, dh_hh_dev, st, sc)
-                   : full_impl<float, false>(ctx, data, m, wc, W, lnL_dev, nullptr, st, sc);
+  const bool hm = modes_hm(model, m);
+  if (prec == MBH_FP64) {
+    if (hm)
+      return dh_hh_dev ? full_impl<double, true, true>(ctx, data, m, wc, W, lnL_dev, dh_hh_dev, st, sc)
+                       : full_impl<double, false, true>(ctx, data, m, wc, W, lnL_dev, nullptr, st, sc);
+    return dh_hh_dev ? full_impl<double, true, false>(ctx, data, m, wc, W, lnL_dev, dh_hh_dev, st, sc)
+                     : full_impl<double, false, false>(ctx, data, m, wc, W, lnL_dev, nullptr, st, sc);
+  }
+  if (hm)
+    return dh_hh_dev ? full_impl<float, true, true>(ctx, data, m, wc, W, lnL_dev, dh_hh_dev, st, sc)
+                     : full_impl<float, false, true>(ctx, data, m, wc, W, lnL_dev, nullptr, st, sc);
+  return dh_hh_dev ? full_impl<float, true, false>(ctx, data, m, wc, W, lnL_dev, dh_hh_dev, st, sc)
+                   : full_impl<float, false, false>(ctx, data, m, wc, W, lnL_dev, nullptr, st, sc);
 }
 
 // ---------------------------------------------------------------- autotuner

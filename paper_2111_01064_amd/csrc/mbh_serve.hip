@@ -84,18 +84,22 @@ static void append_tiles(std::vector<WorkTile> &tiles, std::vector<double> &cost
   }
 }
 
-// tiles grouped by mapping, longest first within a group (stable), and the
-// group ranges (G, first tile, count)
+// tiles grouped by kernel (mapping, and the (2,2)-only or any-mode
+// template), longest first within a group (stable), and the group ranges
+// (G, hm, first tile, count)
 struct TileGroup {
-  int G;
+  int G, hm;
   int64_t begin, count;
 };
 
-static std::vector<TileGroup> order_tiles(std::vector<WorkTile> &tiles, const std::vector<double> &cost) {
+static std::vector<TileGroup> order_tiles(std::vector<WorkTile> &tiles, const std::vector<double> &cost,
+                                          const WorkItem *items) {
   std::vector<size_t> idx(tiles.size());
   for (size_t i = 0; i < idx.size(); ++i) idx[i] = i;
+  auto hm = [&](size_t i) { return items[tiles[i].item].hm; };
   std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) {
     if (tiles[a].G != tiles[b].G) return tiles[a].G < tiles[b].G;
+    if (hm(a) != hm(b)) return hm(a) < hm(b);
     return cost[a] > cost[b];
   });
   std::vector<WorkTile> out(tiles.size());
@@ -103,7 +107,9 @@ static std::vector<TileGroup> order_tiles(std::vector<WorkTile> &tiles, const st
   tiles.swap(out);
   std::vector<TileGroup> groups;
   for (size_t i = 0; i < tiles.size(); ++i) {
-    if (groups.empty() || groups.back().G != tiles[i].G) groups.push_back(TileGroup{tiles[i].G, (int64_t)i, 0});
+    const int h = items[tiles[i].item].hm;
+    if (groups.empty() || groups.back().G != tiles[i].G || groups.back().hm != h)
+      groups.push_back(TileGroup{tiles[i].G, h, (int64_t)i, 0});
     groups.back().count += 1;
   }
   return groups;
@@ -156,20 +162,26 @@ static void xcd_align(std::vector<WorkTile> &tiles, const std::vector<TileGroup>
   }
 }
 
-template <typename R, bool DH>
-static void launch_group(const TileGroup &g, const WorkItem *items, const WorkTile *tiles, hipStream_t st) {
+template <typename R, bool DH, bool HM>
+static void launch_group_t(const TileGroup &g, const WorkItem *items, const WorkTile *tiles, hipStream_t st) {
   const dim3 grid((unsigned)g.count), blk(kBlock);
   const WorkTile *t = tiles + g.begin;
   switch (g.G) {
-    case 0: hipLaunchKernelGGL((k_het_tiles<R, DH, 0>), grid, blk, 0, st, items, t); break;
-    case 1: hipLaunchKernelGGL((k_het_tiles<R, DH, 1>), grid, blk, 0, st, items, t); break;
-    case 2: hipLaunchKernelGGL((k_het_tiles<R, DH, 2>), grid, blk, 0, st, items, t); break;
-    case 4: hipLaunchKernelGGL((k_het_tiles<R, DH, 4>), grid, blk, 0, st, items, t); break;
-    case 8: hipLaunchKernelGGL((k_het_tiles<R, DH, 8>), grid, blk, 0, st, items, t); break;
-    case 16: hipLaunchKernelGGL((k_het_tiles<R, DH, 16>), grid, blk, 0, st, items, t); break;
-    case 32: hipLaunchKernelGGL((k_het_tiles<R, DH, 32>), grid, blk, 0, st, items, t); break;
-    default: hipLaunchKernelGGL((k_het_tiles<R, DH, 64>), grid, blk, 0, st, items, t); break;
+    case 0: hipLaunchKernelGGL((k_het_tiles<R, DH, 0, HM>), grid, blk, 0, st, items, t); break;
+    case 1: hipLaunchKernelGGL((k_het_tiles<R, DH, 1, HM>), grid, blk, 0, st, items, t); break;
+    case 2: hipLaunchKernelGGL((k_het_tiles<R, DH, 2, HM>), grid, blk, 0, st, items, t); break;
+    case 4: hipLaunchKernelGGL((k_het_tiles<R, DH, 4, HM>), grid, blk, 0, st, items, t); break;
+    case 8: hipLaunchKernelGGL((k_het_tiles<R, DH, 8, HM>), grid, blk, 0, st, items, t); break;
+    case 16: hipLaunchKernelGGL((k_het_tiles<R, DH, 16, HM>), grid, blk, 0, st, items, t); break;
+    case 32: hipLaunchKernelGGL((k_het_tiles<R, DH, 32, HM>), grid, blk, 0, st, items, t); break;
+    default: hipLaunchKernelGGL((k_het_tiles<R, DH, 64, HM>), grid, blk, 0, st, items, t); break;
   }
+}
+
+template <typename R, bool DH>
+static void launch_group(const TileGroup &g, const WorkItem *items, const WorkTile *tiles, hipStream_t st) {
+  if (g.hm) launch_group_t<R, DH, true>(g, items, tiles, st);
+  else launch_group_t<R, DH, false>(g, items, tiles, st);
 }
 
 // setup (a1), one grid per mapping group (main pass, with the mixed path's
@@ -283,7 +295,7 @@ extern "C" mbh_status mbh_batch_create(mbh_ctx *ctx, int n, const mbh_ref *const
     append_wtiles(wtiles, i, W[i]);
     off += W[i];
   }
-  b->groups = order_tiles(tiles, cost);
+  b->groups = order_tiles(tiles, cost, items.data());
   xcd_align(tiles, b->groups, wtiles, items.data(), n);
   if ((s = batch_alloc(b, &b->items, (size_t)n)) != MBH_OK ||
       (s = batch_alloc(b, &b->tiles, tiles.size())) != MBH_OK ||
@@ -475,7 +487,7 @@ static bool server_pack(mbh_server *s, Slot &sl) {
     it.lnL = sl.res_d + it.offset;
     it.dhhh = sl.res_d + sl.walkers + 2 * it.offset;
   }
-  sl.groups = order_tiles(tiles, cost);
+  sl.groups = order_tiles(tiles, cost, sl.items_h);
   for (int i = 0; i < n_items; ++i) append_wtiles(wtiles, i, sl.items_h[i].W);
   xcd_align(tiles, sl.groups, wtiles, sl.items_h, n_items);
   std::memcpy(sl.tiles_h, tiles.data(), tiles.size() * sizeof(WorkTile));

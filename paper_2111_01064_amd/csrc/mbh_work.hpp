@@ -37,7 +37,7 @@ static __global__ __launch_bounds__(2 * kWalkerTile) void k_setup_work(const Wor
   if (w < it.W) walker_setup(it.theta + w * 11, it.model, it.ref.modes, it.wc[w], part);
 }
 
-template <typename R, bool DH, int G>
+template <typename R, bool DH, int G, bool HM>
 __global__ __launch_bounds__(kBlock, 2) void k_het_tiles(const WorkItem *__restrict__ items,
                                                          const WorkTile *__restrict__ tiles) {
   const WorkTile tl = tiles[blockIdx.x];
@@ -46,9 +46,9 @@ __global__ __launch_bounds__(kBlock, 2) void k_het_tiles(const WorkItem *__restr
   it.ref = with_meta(it.ref);
   if constexpr (G == 0) {
     const int64_t c = tl.begin + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (c < flat_chunks(it.W, it.E)) het_chunk<R, DH>(it, c);
+    if (c < flat_chunks(it.W, it.E)) het_chunk<R, DH, HM>(it, c);
   } else {
-    het_walker<R, G, DH>(it, tl.begin + threadIdx.x / G);
+    het_walker<R, G, DH, HM>(it, tl.begin + threadIdx.x / G);
   }
 }
 
