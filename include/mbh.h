@@ -142,6 +142,55 @@ mbh_status mbh_ref_get_info(const mbh_ref *ref, mbh_ref_info *out);
 mbh_status mbh_ref_export(const mbh_ref *ref, double *edges, int64_t *kb, double *A0, double *A1,
                           double *B0, double *B1, double *h0_edges);
 
+/* Per-mode relative binning for higher modes: Sec. 2.2's relative binning
+ * applied to every harmonic mode of the reference on its own.  Mode L of
+ * h0 = h(theta0) gets its own band (first and last grid frequency where
+ * h0_L != 0 in any channel; a mode with no band takes no part), n_bins_mode[L]
+ * log-spaced bins over it (half-open, the last closed) and its own ratio
+ * r_L = h_L / h0_L, fitted by a complex line across each of its bins.
+ * <d|h> and the diagonal <h_L|h_L> terms are eqs. (d_h_rel_bin) and
+ * (h_h_rel_bin) per mode; the cross terms <h_L|h_L'> are summed on the merged
+ * edge grid of the two modes (the union of their edges over the overlap of
+ * their bands), with both lines evaluated at each merged bin's centre and
+ * their product linearised about it.  IMR model only; the likelihood calls
+ * (mbh_loglike_heterodyned, batches) evaluate such a reference in MBH_FP64
+ * only and return MBH_EINVAL for MBH_MIXED.  Not for the server, the
+ * device reference update, mbh_loglike_heterodyned_noalloc, the autotuner or
+ * mbh_ref_export (MBH_EINVAL); mbh_ref_get_info reports the total bin count
+ * and the union of the bands.
+ *   n_bins_mode [6] (host): bins of each mode in the mask, in the order of
+ *   the MBH_MODE_* bits, each in [1, 4096].
+ * Synchronises `stream`.  Device memory during the build: 16 B per grid
+ * point, channel and mode, plus one more such array.
+ * Errors: MBH_EINVAL, MBH_EBAND (no mode has a band, or a mode's reference
+ * is exactly zero at one of its edges), MBH_ENOMEM, MBH_EDEVICE. */
+mbh_status mbh_build_reference_coeffs_pm(mbh_ctx *ctx, const mbh_data *data, int model,
+                                         uint32_t modes, const double *theta0_host,
+                                         const int32_t *n_bins_mode, hipStream_t stream,
+                                         mbh_ref **out);
+/* Modes of a per-mode reference that have bins (bit mask) and the number of
+ * mode pairs with overlapping bands.  MBH_EINVAL for other references. */
+mbh_status mbh_ref_pm_info(const mbh_ref *ref, uint32_t *modes_with_bins, int32_t *n_pairs);
+/* One mode of a per-mode reference, to host buffers (any may be NULL; call
+ * with NULL buffers to learn n_bins first): band k_lo..k_hi, edges
+ * [n_bins+1], kb [n_bins+1] (first grid index of each bin, kb[n_bins] =
+ * k_hi + 1), the residual-form sums Ares0, Ares1 [3][n_bins][2]
+ * (sum (d - h0) conj(h0_L) / S df and the same times (f - f_b)), B0, B1
+ * [3][n_bins] (|h0_L|^2 / S df and times (f - f_b)), h0_edges
+ * [3][n_bins+1][2] (h0_L at its edges).  mode_index is the bit position of
+ * the mode (0 = (2,2)); MBH_EINVAL if the mode has no bins. */
+mbh_status mbh_ref_pm_mode(const mbh_ref *ref, int mode_index, int64_t *k_lo, int64_t *k_hi,
+                           int32_t *n_bins, double *edges, int64_t *kb, double *Ares0,
+                           double *Ares1, double *B0, double *B1, double *h0_edges);
+/* One mode pair of a per-mode reference (pairs ordered by mode index):
+ * the two modes, the merged edges [n_merged+1], kb [n_merged+1], each mode's
+ * own bin holding each merged bin (bin_a, bin_b [n_merged]), and the sums
+ * C0 = sum h0_a conj(h0_b) / S df and C1 = the same times (f - f_m)
+ * [3][n_merged][2].  Any pointer may be NULL. */
+mbh_status mbh_ref_pm_pair(const mbh_ref *ref, int pair, int32_t *mode_a, int32_t *mode_b,
+                           int32_t *n_merged, double *edges, int64_t *kb, int32_t *bin_a,
+                           int32_t *bin_b, double *C0, double *C1);
+
 /* Reference update of Sec. 3.2 (the reference is replaced, every few
  * thousand sampler iterations, by the highest-likelihood point of the
  * population), done on the device with no host round trip.  Picks the

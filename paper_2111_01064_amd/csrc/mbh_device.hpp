@@ -759,6 +759,37 @@ __device__ __forceinline__ bool template_point(const WalkerC &w, uint32_t modes,
   return any;
 }
 
+// One mode (index mi) alone at frequency f, for per-mode relative binning:
+// the small factors s[c] and the mode's own carrier psi = its phase
+// (m/2) phi_22(2f/m), the t_ref shift, the guiding-centre Doppler at
+// t_lm(f) and the arm phase.  Returns false (s = 0) outside the mode's
+// support.  The same arithmetic as the mode's term in template_point, with
+// the mode's phase kept in the carrier instead of relative to (2,2).
+template <typename R>
+__device__ __forceinline__ bool mode_point(const WalkerC &w, int mi, double f, const FreqPow &pw, const FreqC &fc,
+                                           double t_obs, cx<double> s[3], double &psi) {
+  const int m = kModeM[mi];
+  const double fp = 2.0 * f / m;
+  double ph, dph, amp;
+  wf22(w, fp, mode_pows(pw, mi), kModeVPow[mi], ph, dph, amp);
+  amp *= w.rel[mi];
+  const double tlm = w.tref - dph * kInvTwoPi;
+  const double al = reduce_2pi(tlm * (kTwoPi / kYearS));
+  double sa, ca;
+  sincos_red<double>(al, sa, ca);
+  const double dop = kTwoPi * f * kOrbR * (w.kx * ca + w.ky * sa);
+  psi = 0.5 * m * ph - kTwoPi * f * w.tref - dop - 4.0 * kPi * f * kArmS;
+  s[0] = s[1] = s[2] = mk<double>(0.0, 0.0);
+  if (!(fp <= w.fcut && tlm >= 0.0 && tlm <= t_obs)) return false;
+  cx<double> T[3];
+  response_mode<R>(w, w.kp[mi], w.kc[mi], fc, ca, sa, T);
+  const cx<double> fm = mk<double>(amp * w.eph[mi][0], amp * w.eph[mi][1]);
+  const double nrm[3] = {1.0 / kSqrt2, 1.0 / kSqrt6, 1.0 / kSqrt3};
+#pragma unroll
+  for (int c = 0; c < 3; ++c) s[c] = fm * (nrm[c] * T[c]);
+  return true;
+}
+
 // grid frequency with the two roundings of f0 + k df (no FMA contraction)
 __device__ __forceinline__ double grid_freq(double f0, double df, int64_t k) {
   return __dadd_rn(f0, __dmul_rn((double)k, df));

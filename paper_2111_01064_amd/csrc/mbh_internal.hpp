@@ -109,6 +109,32 @@ struct mbh_ref {
   } rf;
   bool rf_ready = false;
   std::mutex mu;
+  // edges held by F, fq, psi0 and is064: n_bins + 1, or T1 for a per-mode
+  // reference
+  int32_t n_edges = 0;
+  // per-mode relative binning (mbh_build_reference_coeffs_pm): every mode
+  // with its own band, bins and ratio; F, fq, psi0, is064 hold the edges of
+  // all modes one mode after the other (T1), coef their bins (n_bins in all)
+  bool pm = false;
+  struct PmMode {
+    int mode;
+    int64_t k_lo, k_hi;
+    int32_t e_off, b_off;  // first edge and first bin of the mode in the concatenated arrays
+    std::vector<double> edges, Ares0, Ares1, B0, B1, h0_edges;
+    std::vector<int64_t> kb;
+  };
+  struct PmPair {
+    int mode_a, mode_b;
+    std::vector<double> edges, C0, C1;
+    std::vector<int64_t> kb;
+    std::vector<int32_t> bin_a, bin_b;
+  };
+  std::vector<PmMode> pm_modes;
+  std::vector<PmPair> pm_pairs;
+  int32_t pm_T1 = 0, pm_T2 = 0;
+  int32_t *pm_mode_of = nullptr, *pm_bin_of = nullptr;
+  mbh::PmCross *pm_cross = nullptr;
+  double *pm_ccoef = nullptr;
 };
 
 mbh_status mbh_fail(mbh_status s, const char *fmt, ...);

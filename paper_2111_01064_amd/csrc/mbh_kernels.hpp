@@ -562,6 +562,27 @@ constexpr double kMixedRouteTol = 9e-4;
 constexpr int kChunk = 63;
 constexpr int kWaves = kBlock / 64;
 
+// Per-mode relative binning (higher modes, each mode with its own bins and
+// ratio r_L = h_L / h0_L; Sec. 2.2 applied per mode).  The reference's edge
+// arrays (F, fq, psi0, is064) hold the edges of all its modes one mode after
+// the other (T1 of them), its coefficient array the bins likewise (NB).
+// Cross terms between two modes run over their merged edge grids (T2 merged
+// bins in all): merged bin m lies in bin ea of one mode and eb of the other
+// (given as the bins' left edges in the edge arrays), at offsets xa, xb from
+// the two bins' centres; ia, ib are the reciprocal bin widths.
+struct PmCross {
+  int32_t ea, eb;
+  double xa, xb, ia, ib;
+};
+struct PmView {
+  const int32_t *mode_of;  // [T1] mode index of each edge
+  const int32_t *bin_of;   // [T1] bin starting at the edge (-1 at a mode's last edge)
+  const PmCross *cross;    // [T2]
+  const double *ccoef;     // [C][T2][4]: Re/Im C0, Re/Im C1 of the merged bins
+  double2 *dsc;            // [W][T1][C] delta = r - 1 at every edge (per-call scratch)
+  int32_t T1, T2;
+};
+
 // One heterodyned work item: a reference, a walker batch, its outputs and
 // per-walker scratch.  G is the number of lanes per walker of the lane-group
 // mapping, or 0 for the flattened mapping.
@@ -580,6 +601,10 @@ struct WorkItem {
   int64_t offset;        // first walker of this item in its batch
   int32_t E, K, G, model;
   int32_t hm, pad;       // hm: the reference has modes beyond (2,2) (kernels compiled with HM)
+  // per-mode references (pm.T1 > 0): E = T1 tasks per walker in the edge pass
+  // (slots 0..), E2 = T2 + 1 in the cross pass (slots K1..); E2 = 0 otherwise
+  PmView pm;
+  int32_t E2, K1;
 };
 
 // chunks of the flattened main pass (the last bin sits at task W E - 2)
@@ -867,6 +892,12 @@ static __global__ __launch_bounds__(kWalkerTile) void k_het_final(const WorkItem
   for (int k = 0; k < n_slot; ++k)
 #pragma unroll
     for (int q = 0; q < 3; ++q) s[q] += p[4 * k + q];
+  if (it.E2 > 1) {  // the cross pass of a per-mode reference
+    const int n2 = (int)((w * it.E2 + it.E2 - 2) / kChunk - (w * it.E2) / kChunk) + 1;
+    for (int k = 0; k < n2; ++k)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) s[q] += p[4 * (it.K1 + k) + q];
+  }
   const bool valid = it.wc[w].valid;
   const RefMeta &m = *it.ref.meta;
   it.lnL[w] = valid ? m.lnL0 + s[0] : -INFINITY;
@@ -1006,6 +1037,359 @@ static __global__ __launch_bounds__(kBlock) void k_full_reduce(const double *__r
     dhhh[2 * w] = ok ? s[1] : 0.0;
     dhhh[2 * w + 1] = ok ? s[2] : 0.0;
   }
+}
+
+// ---------------------------------------------------------------- per-mode relative binning
+// Reference build, grid pass: each mode's whitened h0_L (at rank r of the
+// reference's modes: h0w + r C N), their sum htot, each mode's band (first
+// and last grid index where h0_L != 0) and the block partials of
+// -2 lnL(h0), <d|h0>, <h0|h0>.  IMR model, three channels.
+static __global__ __launch_bounds__(kBlock) void k_pm_ref_grid(const WalkerC *__restrict__ wc, uint32_t modes,
+                                                              int64_t n_f, double f0, double df, double t_obs,
+                                                              const double2 *__restrict__ dw,
+                                                              const double *__restrict__ sw, double2 *__restrict__ h0w,
+                                                              double2 *__restrict__ htot, unsigned long long *band,
+                                                              double *__restrict__ part) {
+  __shared__ double sh[3 * (kBlock / 64)];
+  const WalkerC &w = wc[0];
+  double a_res = 0.0, a_dh = 0.0, a_hh = 0.0;
+  unsigned long long lo[kNumModes], hi[kNumModes];
+#pragma unroll
+  for (int r = 0; r < kNumModes; ++r) {
+    lo[r] = ~0ull;
+    hi[r] = 0ull;
+  }
+  const int ns = sinc_terms_for<double>(grid_freq(f0, df, n_f - 1));
+  for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < n_f; k += (int64_t)gridDim.x * kBlock) {
+    const double f = grid_freq(f0, df, k);
+    const FreqPow pw = freq_pows(f);
+    const FreqC fc = freq_consts<double>(f, ns);
+    cx<double> tot[3] = {mk<double>(0.0, 0.0), mk<double>(0.0, 0.0), mk<double>(0.0, 0.0)};
+    int rank = 0;
+#pragma unroll 1
+    for (int mi = 0; mi < kNumModes; ++mi) {
+      if (!(modes & (1u << mi))) continue;
+      cx<double> s[3];
+      double psi;
+      const bool any = mode_point<double>(w, mi, f, pw, fc, t_obs, s, psi);
+      double sp = 0.0, cp = 1.0;
+      if (any) sincos_red<double>(reduce_2pi(psi), sp, cp);
+      bool nz = false;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int64_t i = c * n_f + k;
+        cx<double> h = any ? s[c] * mk<double>(cp, -sp) : mk<double>(0.0, 0.0);
+        h = sw[i] * h;
+        if (h.re != 0.0 || h.im != 0.0) nz = true;
+        h0w[((int64_t)rank * 3 + c) * n_f + k] = make_double2(h.re, h.im);
+        tot[c] = tot[c] + h;
+      }
+      if (nz) {
+        lo[rank] = min(lo[rank], (unsigned long long)k);
+        hi[rank] = (unsigned long long)k;
+      }
+      ++rank;
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int64_t i = c * n_f + k;
+      htot[i] = make_double2(tot[c].re, tot[c].im);
+      const double2 d = dw[i];
+      const double rr = d.x - tot[c].re, ri = d.y - tot[c].im;
+      a_res += rr * rr + ri * ri;
+      a_dh += d.x * tot[c].re + d.y * tot[c].im;
+      a_hh += tot[c].re * tot[c].re + tot[c].im * tot[c].im;
+    }
+  }
+  for (int r = 0; r < kNumModes; ++r) {
+    if (lo[r] != ~0ull) {
+      atomicMin(&band[2 * r], lo[r]);
+      atomicMax(&band[2 * r + 1], hi[r]);
+    }
+  }
+  double v[3] = {a_res, a_dh, a_hh};
+  block_sum<3>(v, sh);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x * 3 + 0] = v[0];
+    part[blockIdx.x * 3 + 1] = v[1];
+    part[blockIdx.x * 3 + 2] = v[2];
+  }
+}
+
+// Mode bins: per (bin, chunk) sums over the bin's grid points of
+// (dw - htot) conj(h0w_L) {1, (f - f_b)} and |h0w_L|^2 {1, (f - f_b)} per
+// channel (the residual-form A - B and B of the mode), part [Nb][n_sub][18].
+static __global__ __launch_bounds__(kBlock) void k_pm_mode_bins(const int64_t *__restrict__ kb,
+                                                               const double *__restrict__ F, int n_sub, int64_t n_f,
+                                                               double f0, double df, const double2 *__restrict__ dw,
+                                                               const double2 *__restrict__ htot,
+                                                               const double2 *__restrict__ hL,
+                                                               double *__restrict__ part) {
+  __shared__ double sh[18 * (kBlock / 64)];
+  const int b = blockIdx.x, sub = blockIdx.y;
+  const int64_t k_begin = kb[b] + (int64_t)sub * kRefChunk;
+  const int64_t k_end = min(kb[b + 1], k_begin + kRefChunk);
+  double acc[18];
+#pragma unroll
+  for (int i = 0; i < 18; ++i) acc[i] = 0.0;
+  if (k_begin < k_end) {
+    const double fb = 0.5 * (F[b] + F[b + 1]);
+    for (int64_t k = k_begin + threadIdx.x; k < k_end; k += kBlock) {
+      const double x = grid_freq(f0, df, k) - fb;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int64_t i = c * n_f + k;
+        const double2 d = dw[i], t = htot[i], h = hL[i];
+        const double rr = d.x - t.x, ri = d.y - t.y;
+        const double tr = rr * h.x + ri * h.y, ti = ri * h.x - rr * h.y;
+        const double h2 = h.x * h.x + h.y * h.y;
+        acc[c * 6 + 0] += tr;
+        acc[c * 6 + 1] += ti;
+        acc[c * 6 + 2] += tr * x;
+        acc[c * 6 + 3] += ti * x;
+        acc[c * 6 + 4] += h2;
+        acc[c * 6 + 5] += h2 * x;
+      }
+    }
+  }
+  block_sum<18>(acc, sh);
+  if (threadIdx.x == 0) {
+    double *o = part + ((int64_t)b * n_sub + sub) * 18;
+    for (int i = 0; i < 18; ++i) o[i] = acc[i];
+  }
+}
+
+// Merged bins of mode pairs: per (merged bin, chunk) sums over grid points
+// kbeg[m] .. kend[m] - 1 of hA conj(hB) {1, (f - fm[m])} per channel, with
+// hA, hB the whitened h0 of the modes at ranks ra[m], rb[m];
+// part [M][n_sub][12].
+static __global__ __launch_bounds__(kBlock) void k_pm_pair_bins(const int64_t *__restrict__ kbeg,
+                                                               const int64_t *__restrict__ kend,
+                                                               const double *__restrict__ fm,
+                                                               const int32_t *__restrict__ ra,
+                                                               const int32_t *__restrict__ rb, int n_sub, int64_t n_f,
+                                                               double f0, double df, const double2 *__restrict__ h0w,
+                                                               double *__restrict__ part) {
+  __shared__ double sh[12 * (kBlock / 64)];
+  const int m = blockIdx.x, sub = blockIdx.y;
+  const int64_t k_begin = kbeg[m] + (int64_t)sub * kRefChunk;
+  const int64_t k_end = min(kend[m], k_begin + kRefChunk);
+  const double2 *hA = h0w + (int64_t)ra[m] * 3 * n_f, *hB = h0w + (int64_t)rb[m] * 3 * n_f;
+  double acc[12];
+#pragma unroll
+  for (int i = 0; i < 12; ++i) acc[i] = 0.0;
+  if (k_begin < k_end) {
+    const double fc = fm[m];
+    for (int64_t k = k_begin + threadIdx.x; k < k_end; k += kBlock) {
+      const double x = grid_freq(f0, df, k) - fc;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int64_t i = c * n_f + k;
+        const double2 a = hA[i], b = hB[i];
+        const double tr = a.x * b.x + a.y * b.y, ti = a.y * b.x - a.x * b.y;  // a conj(b)
+        acc[c * 4 + 0] += tr;
+        acc[c * 4 + 1] += ti;
+        acc[c * 4 + 2] += tr * x;
+        acc[c * 4 + 3] += ti * x;
+      }
+    }
+  }
+  block_sum<12>(acc, sh);
+  if (threadIdx.x == 0) {
+    double *o = part + ((int64_t)m * n_sub + sub) * 12;
+    for (int i = 0; i < 12; ++i) o[i] = acc[i];
+  }
+}
+
+// sum the chunks of each bin in a fixed order: part [n][n_sub][nv] -> out [n][nv]
+static __global__ __launch_bounds__(256) void k_pm_sum(const double *__restrict__ part, int n, int n_sub, int nv,
+                                                       double *__restrict__ out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * nv) return;
+  const int b = t / nv, i = t - b * nv;
+  const double *p = part + (int64_t)b * n_sub * nv + i;
+  double s = 0.0;
+  for (int sub = 0; sub < n_sub; ++sub) s += p[(int64_t)sub * nv];
+  out[t] = s;
+}
+
+// the edges of every mode: response factors and frequency powers, and h0_L
+// at its own edges (carrier psi0 and small factors s0 [C][T1])
+static __global__ __launch_bounds__(64) void k_pm_ref_edges(const WalkerC *__restrict__ wc,
+                                                           const int32_t *__restrict__ mode_of, int T1,
+                                                           const double *__restrict__ F, int ns, double t_obs,
+                                                           double *__restrict__ fq, double *__restrict__ psi0,
+                                                           double2 *__restrict__ s0) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= T1) return;
+  FreqC fc;
+  freq_consts64(F[j], fc.a, fc.Cp, fc.Cm);
+  fc.ns = ns;
+  const FreqPow pw = freq_pows(F[j]);
+  double *q = fq + (int64_t)kFq * j;
+  q[0] = fc.a;
+  q[1] = fc.Cp;
+  q[2] = fc.Cm;
+  q[3] = pw.f13;
+  q[4] = pw.fm13;
+  q[5] = pw.fi;
+  q[6] = pw.fm76;
+  cx<double> s[3];
+  double psi;
+  const bool any = mode_point<double>(wc[0], mode_of[j], F[j], pw, fc, t_obs, s, psi);
+  psi0[j] = psi;
+  for (int c = 0; c < 3; ++c) s0[c * T1 + j] = any ? make_double2(s[c].re, s[c].im) : make_double2(0.0, 0.0);
+}
+
+// delta_L = h_L / h0_L - 1 at edge tau (of mode mode_of[tau]) of walker c,
+// without cancellation, as het_edge (FP64)
+__device__ __forceinline__ void pm_edge(const WorkItem &it, const WalkerC &c, int tau, cx<double> dl[3]) {
+  const HetRef &ref = it.ref;
+  const double *q = ref.fq + (int64_t)kFq * tau;
+  const FreqC fc{q[0], q[1], q[2], ref.ns64};
+  const FreqPow pw{q[3], q[4], q[5], q[6]};
+  cx<double> s[3];
+  double psi;
+  mode_point<double>(c, it.pm.mode_of[tau], ref.F[tau], pw, fc, ref.t_obs, s, psi);
+  const double dpsi = reduce_2pi(psi - ref.psi0[tau]);
+  double hs, hc;
+  sincos_red<double>(0.5 * dpsi, hs, hc);
+  const cx<double> em1 = mk<double>(-2.0 * hs * hs, -2.0 * hs * hc);
+  const cx<double> e = mk<double>(1.0 + em1.re, em1.im);
+  const int T1 = it.pm.T1;
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) {
+    const cx<double> is0 = mk<double>(ref.is064[2 * (ch * T1 + tau)], ref.is064[2 * (ch * T1 + tau) + 1]);
+    cx<double> r = s[ch] * is0;
+    r.re -= 1.0;
+    dl[ch] = r * e + em1;
+  }
+}
+
+// the chunk's sums of each walker with bins in it go to the walker's slot
+// `slot0 + chunk - first chunk of the walker` (as het_chunk, FP64)
+template <bool DH>
+__device__ __forceinline__ void pm_store_segments(const WorkItem &it, int64_t chunk, int E, int64_t v0, int j0,
+                                                  int64_t v, bool is_bin, const double val[4], int slot0) {
+  const int lane = threadIdx.x & 63;
+  const int64_t v_lo = v0 + (j0 == E - 1 ? 1 : 0);
+  const int64_t v_hi = min(v0 + (j0 + kChunk - 1) / E, it.W - 1);
+  for (int64_t vs = v_lo; vs <= v_hi; ++vs) {
+    double s[4];
+    segment_sums<false, DH>(val, is_bin && v == vs, s);
+    if (lane == 0) {
+      double *o = it.part + (vs * it.K + slot0 + (chunk - (vs * E) / kChunk)) * 4;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) o[q] = s[q];
+    }
+  }
+}
+
+// Edge pass of a per-mode reference, one chunk per wavefront: task
+// t = w T1 + tau is (walker w, edge tau); every lane evaluates its mode at
+// its edge and stores delta (for the cross pass), and lanes 0..62 close the
+// bin that starts at their edge (unless it is the mode's last edge) with
+// the value of lane + 1: data term and the mode's own <h|h> term.
+template <bool DH>
+__device__ __forceinline__ void pm_chunk_edges(const WorkItem &it, int64_t chunk) {
+  const int lane = threadIdx.x & 63;
+  const int E = it.E;
+  const int64_t t0 = chunk * kChunk;
+  const int64_t v0 = t0 / E;
+  const int j0 = (int)(t0 - v0 * E);
+  const unsigned jl = (unsigned)(j0 + lane);
+  const unsigned qv = jl / (unsigned)E;
+  const int64_t v = v0 + qv;
+  const int tau = (int)(jl - qv * (unsigned)E);
+  const bool act = v < it.W;
+  const WalkerC &c = it.wc[act ? v : 0];
+  const bool valid = act && c.valid;
+  const int b = it.pm.bin_of[tau];
+  const bool is_bin = valid && lane < kChunk && b >= 0;
+  cx<double> dl[3];
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) dl[ch] = mk<double>(0.0, 0.0);
+  if (valid) pm_edge(it, c, tau, dl);
+  if (act) {
+    double2 *o = it.pm.dsc + ((int64_t)v * E + tau) * 3;
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) o[ch] = make_double2(dl[ch].re, dl[ch].im);
+  }
+  cx<double> nb[3];
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) {
+    nb[ch].re = __shfl_down(dl[ch].re, 1, 64);
+    nb[ch].im = __shfl_down(dl[ch].im, 1, 64);
+  }
+  double val[4] = {0.0, 0.0, 0.0, 0.0};
+  if (is_bin) bin_terms<false, DH>(it.ref, b, dl, nb, val);
+  pm_store_segments<DH>(it, chunk, E, v0, j0, v, is_bin, val, 0);
+}
+
+// Cross pass: task t = w (T2 + 1) + mu is (walker w, merged bin mu) (the
+// last task of a walker is empty).  Both modes' lines at the merged centre
+// from the deltas of their own bins' edges, and the merged bin's terms:
+//   lnL:          -4 Re[C0 P0 + C1 P1],
+//   Z[d,h]:       +4 Re[C0 dA + C1 dA1] + 4 Re[C0 dB* + C1 dB1*],
+//   Z[h,h]:       +8 Re[C0 (P0 + dA + dB*) + C1 (P1 + dA1 + dB1*)],
+// with P0 = dA dB*, P1 = dA1 dB* + dA dB1* (dA, dB the lines at the centre,
+// dA1, dB1 their slopes): the cross terms of <h|h> linearised about the
+// merged centre, and the parts of the data and <h|h> terms that involve the
+// other mode's reference.
+template <bool DH>
+__device__ __forceinline__ void pm_chunk_cross(const WorkItem &it, int64_t chunk) {
+  const int lane = threadIdx.x & 63;
+  const int E = it.E2;
+  const int T1 = it.pm.T1, T2 = it.pm.T2;
+  const int64_t t0 = chunk * kChunk;
+  const int64_t v0 = t0 / E;
+  const int j0 = (int)(t0 - v0 * E);
+  const unsigned jl = (unsigned)(j0 + lane);
+  const unsigned qv = jl / (unsigned)E;
+  const int64_t v = v0 + qv;
+  const int mu = (int)(jl - qv * (unsigned)E);
+  const bool act = v < it.W;
+  const bool valid = act && it.wc[act ? v : 0].valid;
+  const bool is_bin = valid && lane < kChunk && mu < T2;
+  double val[4] = {0.0, 0.0, 0.0, 0.0};
+  if (is_bin) {
+    const PmCross x = it.pm.cross[mu];
+    const double2 *D = it.pm.dsc + (int64_t)v * T1 * 3;
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      const double2 a0 = D[x.ea * 3 + ch], a1 = D[(x.ea + 1) * 3 + ch];
+      const double2 b0 = D[x.eb * 3 + ch], b1 = D[(x.eb + 1) * 3 + ch];
+      const cx<double> sA = mk<double>((a1.x - a0.x) * x.ia, (a1.y - a0.y) * x.ia);
+      const cx<double> sB = mk<double>((b1.x - b0.x) * x.ib, (b1.y - b0.y) * x.ib);
+      const cx<double> dA = mk<double>(0.5 * (a0.x + a1.x) + sA.re * x.xa, 0.5 * (a0.y + a1.y) + sA.im * x.xa);
+      const cx<double> dB = mk<double>(0.5 * (b0.x + b1.x) + sB.re * x.xb, 0.5 * (b0.y + b1.y) + sB.im * x.xb);
+      const cx<double> cB = mk<double>(dB.re, -dB.im), cSB = mk<double>(sB.re, -sB.im);
+      const cx<double> P0 = dA * cB;
+      const cx<double> P1 = sA * cB + dA * cSB;
+      const double *k = it.pm.ccoef + ((int64_t)ch * T2 + mu) * 4;
+      const cx<double> C0 = mk<double>(k[0], k[1]), C1 = mk<double>(k[2], k[3]);
+      const double q = (C0 * P0).re + (C1 * P1).re;
+      val[0] -= 4.0 * q;
+      if constexpr (DH) {
+        val[1] += 4.0 * ((C0 * dA).re + (C1 * sA).re + (C0 * cB).re + (C1 * cSB).re);
+        val[2] += 8.0 * (q + (C0 * dA).re + (C0 * cB).re + (C1 * sA).re + (C1 * cSB).re);
+      }
+    }
+  }
+  pm_store_segments<DH>(it, chunk, E, v0, j0, v, is_bin, val, it.K1);
+}
+
+// single-item launches of the two passes
+template <bool DH>
+__global__ __launch_bounds__(kBlock, 2) void k_pm_edges(WorkItem one, int64_t n_chunks) {
+  const int64_t c = (int64_t)blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  one.ref = with_meta(one.ref);
+  if (c < n_chunks) pm_chunk_edges<DH>(one, c);
+}
+template <bool DH>
+__global__ __launch_bounds__(kBlock, 2) void k_pm_cross(WorkItem one, int64_t n_chunks) {
+  const int64_t c = (int64_t)blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (c < n_chunks) pm_chunk_cross<DH>(one, c);
 }
 
 }  // namespace mbh

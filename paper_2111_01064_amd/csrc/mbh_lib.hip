@@ -355,7 +355,14 @@ extern "C" mbh_status mbh_template_full(mbh_ctx *ctx, const mbh_data *data, int 
 // ---------------------------------------------------------------- reference
 static void release_ref_dev(mbh_ref *r) {
   mbh_ctx *c = r->ctx;
-  const int E = r->n_bins + 1;
+  const int E = r->n_edges;
+  ctx_free(c, r->pm_mode_of, (size_t)r->pm_T1 * sizeof(int32_t));
+  ctx_free(c, r->pm_bin_of, (size_t)r->pm_T1 * sizeof(int32_t));
+  ctx_free(c, r->pm_cross, (size_t)r->pm_T2 * sizeof(PmCross));
+  ctx_free(c, r->pm_ccoef, (size_t)r->n_chan * r->pm_T2 * 4 * sizeof(double));
+  r->pm_mode_of = r->pm_bin_of = nullptr;
+  r->pm_cross = nullptr;
+  r->pm_ccoef = nullptr;
   ctx_free(c, r->F, E * sizeof(double));
   ctx_free(c, r->psi0, E * sizeof(double));
   ctx_free(c, r->fq, (size_t)E * kFq * sizeof(double));
@@ -488,6 +495,7 @@ extern "C" mbh_status mbh_build_reference_coeffs(mbh_ctx *ctx, const mbh_data *d
   r->modes = model == MBH_MODEL_IMR ? modes : 0u;
   r->n_chan = C;
   r->n_bins = n_bins;
+  r->n_edges = E;
   r->k_lo = k_lo;
   r->k_hi = k_hi;
   r->t_obs = data->t_obs;
@@ -615,6 +623,435 @@ extern "C" mbh_status mbh_build_reference_coeffs(mbh_ctx *ctx, const mbh_data *d
   return MBH_OK;
 }
 
+// ---------------------------------------------------------------- per-mode reference
+// first grid index of each bin: kb[b] = smallest k in [k_lo, k_hi] with
+// f_k >= edges[b] (b >= 1), kb[0] = k_lo, kb[n] = k_hi + 1 (FP64 on the host)
+static std::vector<int64_t> host_kb(double f0, double df, int64_t k_lo, int64_t k_hi, const std::vector<double> &edges) {
+  const int n = (int)edges.size() - 1;
+  std::vector<int64_t> kb(n + 1);
+  kb[0] = k_lo;
+  kb[n] = k_hi + 1;
+  for (int b = 1; b < n; ++b) {
+    int64_t lo = k_lo, hi = k_hi + 1;
+    while (lo < hi) {
+      int64_t mid = lo + (hi - lo) / 2;
+      if (host_grid_freq(f0, df, mid) >= edges[b]) hi = mid;
+      else lo = mid + 1;
+    }
+    kb[b] = lo;
+  }
+  for (int b = n - 1; b >= 1; --b) kb[b] = std::min(kb[b], kb[b + 1]);
+  return kb;
+}
+
+// the bin [F_b, F_b+1) (the last closed) of a mode's edges that holds f
+static int host_bin_of(const std::vector<double> &edges, double f) {
+  const int n = (int)edges.size() - 1;
+  int b = (int)(std::upper_bound(edges.begin(), edges.end(), f) - edges.begin()) - 1;
+  return std::min(std::max(b, 0), n - 1);
+}
+
+extern "C" mbh_status mbh_build_reference_coeffs_pm(mbh_ctx *ctx, const mbh_data *data_c, int model, uint32_t modes,
+                                                    const double *theta0_host, const int32_t *n_bins_mode,
+                                                    hipStream_t st, mbh_ref **out) {
+  mbh_data *data = const_cast<mbh_data *>(data_c);
+  if (!ctx || !data || !theta0_host || !n_bins_mode || !out) return mbh_fail(MBH_EINVAL, "null argument");
+  *out = nullptr;
+  if (model != MBH_MODEL_IMR) return mbh_fail(MBH_EINVAL, "per-mode binning needs the IMR model");
+  MBH_TRY(check_model(data, model, modes));
+  std::vector<int> mode_list;
+  for (int mi = 0; mi < kNumModes; ++mi)
+    if (modes & (1u << mi)) {
+      if (n_bins_mode[mi] < 1 || n_bins_mode[mi] > 4096)
+        return mbh_fail(MBH_EINVAL, "mode %d: n_bins %d outside [1, 4096]", mi, n_bins_mode[mi]);
+      mode_list.push_back(mi);
+    }
+  HIP_TRY(hipSetDevice(ctx->device));
+  const int C = 3, nm = (int)mode_list.size();
+  const int64_t N = data->n_f;
+  const double f0 = data->f0, df = data->df;
+  Scratch sc(ctx, st);
+  WalkerC *wc = nullptr;
+  bool valid = false;
+  MBH_TRY(setup_one(sc, theta0_host, model, modes, &wc, &valid));
+  if (!valid) return mbh_fail(MBH_EINVAL, "theta0 outside the model domain");
+
+  // grid pass: each mode's whitened h0, their sum, bands, lnL(h0) pieces
+  double2 *h0w = nullptr, *htot = nullptr;
+  MBH_TRY(sc.get(&h0w, (size_t)nm * C * N));
+  MBH_TRY(sc.get(&htot, (size_t)C * N));
+  unsigned long long *band = nullptr;
+  MBH_TRY(sc.get(&band, 2 * kNumModes));
+  const int nb1 = grid_blocks(N, resident_blocks(ctx, reinterpret_cast<const void *>(&k_pm_ref_grid), kBlock));
+  double *part1 = nullptr, *sums1 = nullptr;
+  MBH_TRY(sc.get(&part1, (size_t)nb1 * 3));
+  MBH_TRY(sc.get(&sums1, 3));
+  unsigned long long band0[2 * kNumModes];
+  for (int i = 0; i < kNumModes; ++i) {
+    band0[2 * i] = ~0ull;
+    band0[2 * i + 1] = 0ull;
+  }
+  HIP_TRY(hipMemcpyAsync(band, band0, sizeof(band0), hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(k_pm_ref_grid, dim3(nb1), dim3(kBlock), 0, st, wc, modes, N, f0, df, data->t_obs, data->dw64,
+                     data->sw64, h0w, htot, band, part1);
+  hipLaunchKernelGGL(k_sum_partials, dim3(3), dim3(64), 0, st, part1, nb1, 3, 3, sums1);
+  HIP_TRY(hipGetLastError());
+  unsigned long long hb[2 * kNumModes];
+  double s1[3];
+  HIP_TRY(hipMemcpyAsync(hb, band, sizeof(hb), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(s1, sums1, sizeof(s1), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+
+  mbh_ref *r = new mbh_ref();
+  r->ctx = ctx;
+  r->hold.set(ctx);
+  r->model = model;
+  r->modes = modes;
+  r->n_chan = C;
+  r->t_obs = data->t_obs;
+  r->n_f = N;
+  r->f0 = f0;
+  r->df = df;
+  r->pm = true;
+  auto fail_free = [&](mbh_status e) {
+    release_ref_dev(r);
+    delete r;
+    return e;
+  };
+  // modes with a band on the grid (a mode without one takes no part), their
+  // edges and bins, one mode after the other
+  std::vector<int> rank_of(kNumModes, -1);
+  int32_t T1 = 0, NB = 0;
+  for (int rk = 0; rk < nm; ++rk) {
+    const int mi = mode_list[rk];
+    rank_of[mi] = rk;
+    if (hb[2 * rk] == ~0ull || hb[2 * rk + 1] <= hb[2 * rk]) continue;
+    mbh_ref::PmMode pmm;
+    pmm.mode = mi;
+    pmm.k_lo = (int64_t)hb[2 * rk];
+    pmm.k_hi = (int64_t)hb[2 * rk + 1];
+    host_edges(host_grid_freq(f0, df, pmm.k_lo), host_grid_freq(f0, df, pmm.k_hi), n_bins_mode[mi], pmm.edges);
+    pmm.kb = host_kb(f0, df, pmm.k_lo, pmm.k_hi, pmm.edges);
+    pmm.e_off = T1;
+    pmm.b_off = NB;
+    T1 += n_bins_mode[mi] + 1;
+    NB += n_bins_mode[mi];
+    r->pm_modes.push_back(std::move(pmm));
+  }
+  if (r->pm_modes.empty()) return fail_free(mbh_fail(MBH_EBAND, "reference template empty on the grid in every mode"));
+  r->n_bins = NB;
+  r->n_edges = T1;
+  r->pm_T1 = T1;
+  r->k_lo = INT64_MAX;
+  r->k_hi = 0;
+  for (auto &m : r->pm_modes) {
+    r->k_lo = std::min(r->k_lo, m.k_lo);
+    r->k_hi = std::max(r->k_hi, m.k_hi);
+  }
+  // mode pairs with overlapping bands: merged edges, bins, each mode's bin
+  std::vector<PmCross> cross;
+  std::vector<int64_t> mkbeg, mkend;
+  std::vector<double> mfc;
+  std::vector<int32_t> mra, mrb;
+  for (size_t a = 0; a < r->pm_modes.size(); ++a)
+    for (size_t b = a + 1; b < r->pm_modes.size(); ++b) {
+      const auto &A = r->pm_modes[a], &B = r->pm_modes[b];
+      const int64_t lo = std::max(A.k_lo, B.k_lo), hi = std::min(A.k_hi, B.k_hi);
+      if (hi < lo) continue;
+      const double Flo = host_grid_freq(f0, df, lo), Fhi = host_grid_freq(f0, df, hi);
+      mbh_ref::PmPair pp;
+      pp.mode_a = A.mode;
+      pp.mode_b = B.mode;
+      for (double e : A.edges)
+        if (e >= Flo && e <= Fhi) pp.edges.push_back(e);
+      for (double e : B.edges)
+        if (e >= Flo && e <= Fhi) pp.edges.push_back(e);
+      std::sort(pp.edges.begin(), pp.edges.end());
+      pp.edges.erase(std::unique(pp.edges.begin(), pp.edges.end()), pp.edges.end());
+      if (pp.edges.size() < 2) pp.edges = {Flo, Fhi};  // an overlap of one grid point
+      pp.kb = host_kb(f0, df, lo, hi, pp.edges);
+      const int nmb = (int)pp.edges.size() - 1;
+      for (int m = 0; m < nmb; ++m) {
+        const double fm = 0.5 * (pp.edges[m] + pp.edges[m + 1]);
+        const int ba = host_bin_of(A.edges, pp.edges[m]), bb = host_bin_of(B.edges, pp.edges[m]);
+        pp.bin_a.push_back(ba);
+        pp.bin_b.push_back(bb);
+        PmCross x;
+        x.ea = A.e_off + ba;
+        x.eb = B.e_off + bb;
+        x.xa = fm - 0.5 * (A.edges[ba] + A.edges[ba + 1]);
+        x.xb = fm - 0.5 * (B.edges[bb] + B.edges[bb + 1]);
+        x.ia = 1.0 / (A.edges[ba + 1] - A.edges[ba]);
+        x.ib = 1.0 / (B.edges[bb + 1] - B.edges[bb]);
+        cross.push_back(x);
+        mkbeg.push_back(pp.kb[m]);
+        mkend.push_back(pp.kb[m + 1]);
+        mfc.push_back(fm);
+        mra.push_back(rank_of[A.mode]);
+        mrb.push_back(rank_of[B.mode]);
+      }
+      r->pm_pairs.push_back(std::move(pp));
+    }
+  const int32_t T2 = (int32_t)cross.size();
+  r->pm_T2 = T2;
+
+  // concatenated edge arrays and the edge -> mode / bin maps
+  std::vector<double> Fcat(T1);
+  std::vector<int32_t> mode_of(T1), bin_of(T1);
+  for (auto &m : r->pm_modes) {
+    const int n = (int)m.edges.size() - 1;
+    for (int j = 0; j <= n; ++j) {
+      Fcat[m.e_off + j] = m.edges[j];
+      mode_of[m.e_off + j] = m.mode;
+      bin_of[m.e_off + j] = j < n ? m.b_off + j : -1;
+    }
+  }
+  mbh_status e;
+  if ((e = ctx_alloc(ctx, (void **)&r->F, T1 * sizeof(double))) != MBH_OK) return fail_free(e);
+  if ((e = ctx_alloc(ctx, (void **)&r->psi0, T1 * sizeof(double))) != MBH_OK) return fail_free(e);
+  if ((e = ctx_alloc(ctx, (void **)&r->fq, (size_t)T1 * kFq * sizeof(double))) != MBH_OK) return fail_free(e);
+  if ((e = ctx_alloc(ctx, (void **)&r->is064, (size_t)C * T1 * 2 * sizeof(double))) != MBH_OK) return fail_free(e);
+  if ((e = ctx_alloc(ctx, (void **)&r->coef, (size_t)C * NB * 6 * sizeof(double))) != MBH_OK) return fail_free(e);
+  if ((e = ctx_alloc(ctx, (void **)&r->meta, sizeof(RefMeta))) != MBH_OK) return fail_free(e);
+  if ((e = ctx_alloc(ctx, (void **)&r->pm_mode_of, T1 * sizeof(int32_t))) != MBH_OK) return fail_free(e);
+  if ((e = ctx_alloc(ctx, (void **)&r->pm_bin_of, T1 * sizeof(int32_t))) != MBH_OK) return fail_free(e);
+  if (T2 > 0) {
+    if ((e = ctx_alloc(ctx, (void **)&r->pm_cross, (size_t)T2 * sizeof(PmCross))) != MBH_OK) return fail_free(e);
+    if ((e = ctx_alloc(ctx, (void **)&r->pm_ccoef, (size_t)C * T2 * 4 * sizeof(double))) != MBH_OK)
+      return fail_free(e);
+  }
+  // per-mode bin sums (one mode after the other through one part buffer)
+  int64_t max_part = 0;
+  std::vector<int> n_sub_of;
+  for (auto &m : r->pm_modes) {
+    int64_t ml = 0;
+    for (size_t b = 0; b + 1 < m.kb.size(); ++b) ml = std::max(ml, m.kb[b + 1] - m.kb[b]);
+    const int ns = (int)std::max<int64_t>(1, (ml + kRefChunk - 1) / kRefChunk);
+    n_sub_of.push_back(ns);
+    max_part = std::max<int64_t>(max_part, (int64_t)(m.edges.size() - 1) * ns * 18);
+  }
+  int64_t *kb_dev = nullptr;
+  double *part2 = nullptr, *sums2 = nullptr;
+  double2 *s0 = nullptr;
+  int32_t *mode_of_dev = r->pm_mode_of;
+  if ((e = sc.get(&kb_dev, (size_t)T1)) != MBH_OK) return fail_free(e);
+  if ((e = sc.get(&part2, (size_t)max_part)) != MBH_OK) return fail_free(e);
+  if ((e = sc.get(&sums2, (size_t)NB * 18)) != MBH_OK) return fail_free(e);
+  if ((e = sc.get(&s0, (size_t)C * T1)) != MBH_OK) return fail_free(e);
+  std::vector<int64_t> kbcat(T1);
+  for (auto &m : r->pm_modes)
+    for (size_t j = 0; j < m.kb.size(); ++j) kbcat[m.e_off + j] = m.kb[j];
+  if (hipMemcpyAsync(r->F, Fcat.data(), T1 * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(kb_dev, kbcat.data(), T1 * sizeof(int64_t), hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(mode_of_dev, mode_of.data(), T1 * sizeof(int32_t), hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(r->pm_bin_of, bin_of.data(), T1 * sizeof(int32_t), hipMemcpyHostToDevice, st) != hipSuccess)
+    return fail_free(mbh_fail(MBH_EDEVICE, "upload edges"));
+  for (size_t i = 0; i < r->pm_modes.size(); ++i) {
+    const auto &m = r->pm_modes[i];
+    const int n = (int)m.edges.size() - 1, ns = n_sub_of[i];
+    hipLaunchKernelGGL(k_pm_mode_bins, dim3(n, ns), dim3(kBlock), 0, st, kb_dev + m.e_off, r->F + m.e_off, ns, N, f0,
+                       df, data->dw64, htot, h0w + (int64_t)rank_of[m.mode] * C * N, part2);
+    hipLaunchKernelGGL(k_pm_sum, dim3((n * 18 + 255) / 256), dim3(256), 0, st, part2, n, ns, 18,
+                       sums2 + (int64_t)m.b_off * 18);
+  }
+  // merged bins of the mode pairs
+  double *csum = nullptr;
+  if (T2 > 0) {
+    int64_t ml = 0;
+    for (int32_t m = 0; m < T2; ++m) ml = std::max(ml, mkend[m] - mkbeg[m]);
+    const int ns = (int)std::max<int64_t>(1, (ml + kRefChunk - 1) / kRefChunk);
+    int64_t *kbeg_d = nullptr, *kend_d = nullptr;
+    double *fm_d = nullptr, *part3 = nullptr;
+    int32_t *ra_d = nullptr, *rb_d = nullptr;
+    if ((e = sc.get(&kbeg_d, T2)) != MBH_OK || (e = sc.get(&kend_d, T2)) != MBH_OK ||
+        (e = sc.get(&fm_d, T2)) != MBH_OK || (e = sc.get(&ra_d, T2)) != MBH_OK || (e = sc.get(&rb_d, T2)) != MBH_OK ||
+        (e = sc.get(&part3, (size_t)T2 * ns * 12)) != MBH_OK || (e = sc.get(&csum, (size_t)T2 * 12)) != MBH_OK)
+      return fail_free(e);
+    if (hipMemcpyAsync(kbeg_d, mkbeg.data(), T2 * sizeof(int64_t), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(kend_d, mkend.data(), T2 * sizeof(int64_t), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(fm_d, mfc.data(), T2 * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(ra_d, mra.data(), T2 * sizeof(int32_t), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(rb_d, mrb.data(), T2 * sizeof(int32_t), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(r->pm_cross, cross.data(), T2 * sizeof(PmCross), hipMemcpyHostToDevice, st) != hipSuccess)
+      return fail_free(mbh_fail(MBH_EDEVICE, "upload merged bins"));
+    hipLaunchKernelGGL(k_pm_pair_bins, dim3(T2, ns), dim3(kBlock), 0, st, kbeg_d, kend_d, fm_d, ra_d, rb_d, ns, N, f0,
+                       df, h0w, part3);
+    hipLaunchKernelGGL(k_pm_sum, dim3((T2 * 12 + 255) / 256), dim3(256), 0, st, part3, T2, ns, 12, csum);
+  }
+  double fmax_e = 0.0;
+  for (double f : Fcat) fmax_e = std::max(fmax_e, f);
+  const int ns64 = sinc_terms_for<double>(fmax_e);
+  hipLaunchKernelGGL(k_pm_ref_edges, dim3((T1 + 63) / 64), dim3(64), 0, st, wc, mode_of_dev, T1, r->F, ns64,
+                     data->t_obs, r->fq, r->psi0, s0);
+  if (hipGetLastError() != hipSuccess) return fail_free(mbh_fail(MBH_EDEVICE, "per-mode reference kernels"));
+  std::vector<double> hs2((size_t)NB * 18), hs0((size_t)C * T1 * 2), hcs((size_t)T2 * 12), psi(T1);
+  if (hipMemcpyAsync(hs2.data(), sums2, hs2.size() * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipMemcpyAsync(hs0.data(), s0, hs0.size() * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      (T2 > 0 &&
+       hipMemcpyAsync(hcs.data(), csum, hcs.size() * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess) ||
+      hipMemcpyAsync(psi.data(), r->psi0, T1 * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return fail_free(mbh_fail(MBH_EDEVICE, "download per-mode sums"));
+  // each mode's ratio must exist at each of its edges
+  for (auto &m : r->pm_modes)
+    for (int c = 0; c < C; ++c)
+      for (size_t j = 0; j < m.edges.size(); ++j) {
+        const size_t i = (size_t)c * T1 + m.e_off + j;
+        const double re = hs0[2 * i], im = hs0[2 * i + 1];
+        if (!(re != 0.0 || im != 0.0) || !std::isfinite(re) || !std::isfinite(im))
+          return fail_free(mbh_fail(MBH_EBAND, "mode %d of the reference is zero at its edge %zu (f = %.6g Hz), channel %d",
+                                    m.mode, j, m.edges[j], c));
+      }
+  double dd = 0.0;
+  if ((e = data_dd(data, &dd)) != MBH_OK) return fail_free(e);
+  r->dd = dd;
+  r->lnL0 = -0.5 * s1[0];
+  r->dh0 = s1[1];
+  r->hh0 = s1[2];
+  r->hh0_build = s1[2];
+  // coefficients: residual form for the kernels ([C][NB][6], slopes scaled
+  // by 1 / dF_b), sums in df / S units for export (the grid sums carry
+  // w = 4 df / S)
+  std::vector<double> coef((size_t)C * NB * 6);
+  for (auto &m : r->pm_modes) {
+    const int n = (int)m.edges.size() - 1;
+    m.Ares0.assign((size_t)C * n * 2, 0.0);
+    m.Ares1.assign((size_t)C * n * 2, 0.0);
+    m.B0.assign((size_t)C * n, 0.0);
+    m.B1.assign((size_t)C * n, 0.0);
+    m.h0_edges.assign((size_t)C * (n + 1) * 2, 0.0);
+    for (int c = 0; c < C; ++c)
+      for (int b = 0; b < n; ++b) {
+        const double *q = &hs2[(size_t)(m.b_off + b) * 18 + c * 6];
+        const size_t o = (size_t)c * n + b;
+        m.Ares0[2 * o] = 0.25 * q[0];
+        m.Ares0[2 * o + 1] = 0.25 * q[1];
+        m.Ares1[2 * o] = 0.25 * q[2];
+        m.Ares1[2 * o + 1] = 0.25 * q[3];
+        m.B0[o] = 0.25 * q[4];
+        m.B1[o] = 0.25 * q[5];
+        const double idf = 1.0 / (m.edges[b + 1] - m.edges[b]);
+        double *k = &coef[6 * ((size_t)c * NB + m.b_off + b)];
+        k[0] = 0.25 * q[0];
+        k[1] = 0.25 * q[1];
+        k[2] = 0.25 * q[2] * idf;
+        k[3] = 0.25 * q[3] * idf;
+        k[4] = 0.25 * q[4];
+        k[5] = 0.25 * q[5] * idf;
+      }
+    for (int c = 0; c < C; ++c)
+      for (int j = 0; j <= n; ++j) {
+        const size_t i = (size_t)c * T1 + m.e_off + j;
+        const double re = hs0[2 * i], im = hs0[2 * i + 1];
+        const double p = std::remainder(psi[m.e_off + j], 2.0 * M_PI);
+        const double cp = std::cos(p), sp = std::sin(p);
+        m.h0_edges[2 * ((size_t)c * (n + 1) + j)] = (re * cp + im * sp) / kAmpScale;
+        m.h0_edges[2 * ((size_t)c * (n + 1) + j) + 1] = (im * cp - re * sp) / kAmpScale;
+      }
+  }
+  std::vector<double> is64((size_t)C * T1 * 2);
+  for (size_t i = 0; i < (size_t)C * T1; ++i) {
+    const double re = hs0[2 * i], im = hs0[2 * i + 1], den = re * re + im * im;
+    is64[2 * i] = re / den;
+    is64[2 * i + 1] = -im / den;
+  }
+  std::vector<double> ccoef((size_t)C * T2 * 4);
+  {
+    int32_t mu = 0;
+    for (auto &pp : r->pm_pairs) {
+      const int n = (int)pp.edges.size() - 1;
+      pp.C0.assign((size_t)C * n * 2, 0.0);
+      pp.C1.assign((size_t)C * n * 2, 0.0);
+      for (int m = 0; m < n; ++m, ++mu)
+        for (int c = 0; c < C; ++c) {
+          const double *q = &hcs[(size_t)mu * 12 + c * 4];
+          const size_t o = (size_t)c * n + m;
+          pp.C0[2 * o] = 0.25 * q[0];
+          pp.C0[2 * o + 1] = 0.25 * q[1];
+          pp.C1[2 * o] = 0.25 * q[2];
+          pp.C1[2 * o + 1] = 0.25 * q[3];
+          double *k = &ccoef[4 * ((size_t)c * T2 + mu)];
+          for (int i = 0; i < 4; ++i) k[i] = 0.25 * q[i];
+        }
+    }
+  }
+  RefMeta mt{};
+  mt.lnL0 = r->lnL0;
+  mt.dh0 = r->dh0;
+  mt.hh0 = r->hh0;
+  mt.ns64 = ns64;
+  mt.ns32 = sinc_terms_for<float>(fmax_e);
+  mt.k_lo = r->k_lo;
+  mt.k_hi = r->k_hi;
+  mt.pick = -1;
+  if (hipMemcpyAsync(r->coef, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(r->is064, is64.data(), is64.size() * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(r->meta, &mt, sizeof(mt), hipMemcpyHostToDevice, st) != hipSuccess ||
+      (T2 > 0 && hipMemcpyAsync(r->pm_ccoef, ccoef.data(), ccoef.size() * sizeof(double), hipMemcpyHostToDevice, st) !=
+                     hipSuccess) ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return fail_free(mbh_fail(MBH_EDEVICE, "upload per-mode coefficients"));
+  *out = r;
+  return MBH_OK;
+}
+
+extern "C" mbh_status mbh_ref_pm_info(const mbh_ref *r, uint32_t *modes_with_bins, int32_t *n_pairs) {
+  if (!r) return mbh_fail(MBH_EINVAL, "null reference");
+  if (!r->pm) return mbh_fail(MBH_EINVAL, "not a per-mode reference");
+  uint32_t m = 0;
+  for (auto &x : r->pm_modes) m |= 1u << x.mode;
+  if (modes_with_bins) *modes_with_bins = m;
+  if (n_pairs) *n_pairs = (int32_t)r->pm_pairs.size();
+  return MBH_OK;
+}
+
+extern "C" mbh_status mbh_ref_pm_mode(const mbh_ref *r, int mode_index, int64_t *k_lo, int64_t *k_hi,
+                                      int32_t *n_bins, double *edges, int64_t *kb, double *Ares0, double *Ares1,
+                                      double *B0, double *B1, double *h0_edges) {
+  if (!r) return mbh_fail(MBH_EINVAL, "null reference");
+  if (!r->pm) return mbh_fail(MBH_EINVAL, "not a per-mode reference");
+  for (auto &m : r->pm_modes) {
+    if (m.mode != mode_index) continue;
+    if (k_lo) *k_lo = m.k_lo;
+    if (k_hi) *k_hi = m.k_hi;
+    if (n_bins) *n_bins = (int32_t)m.edges.size() - 1;
+    auto cp = [](void *dst, const auto &v) {
+      if (dst) std::memcpy(dst, v.data(), v.size() * sizeof(v[0]));
+    };
+    cp(edges, m.edges);
+    cp(kb, m.kb);
+    cp(Ares0, m.Ares0);
+    cp(Ares1, m.Ares1);
+    cp(B0, m.B0);
+    cp(B1, m.B1);
+    cp(h0_edges, m.h0_edges);
+    return MBH_OK;
+  }
+  return mbh_fail(MBH_EINVAL, "mode %d has no bins in this reference", mode_index);
+}
+
+extern "C" mbh_status mbh_ref_pm_pair(const mbh_ref *r, int pair, int32_t *mode_a, int32_t *mode_b,
+                                      int32_t *n_merged, double *edges, int64_t *kb, int32_t *bin_a, int32_t *bin_b,
+                                      double *C0, double *C1) {
+  if (!r) return mbh_fail(MBH_EINVAL, "null reference");
+  if (!r->pm) return mbh_fail(MBH_EINVAL, "not a per-mode reference");
+  if (pair < 0 || pair >= (int)r->pm_pairs.size()) return mbh_fail(MBH_EINVAL, "pair %d", pair);
+  const auto &p = r->pm_pairs[pair];
+  if (mode_a) *mode_a = p.mode_a;
+  if (mode_b) *mode_b = p.mode_b;
+  if (n_merged) *n_merged = (int32_t)p.edges.size() - 1;
+  auto cp = [](void *dst, const auto &v) {
+    if (dst) std::memcpy(dst, v.data(), v.size() * sizeof(v[0]));
+  };
+  cp(edges, p.edges);
+  cp(kb, p.kb);
+  cp(bin_a, p.bin_a);
+  cp(bin_b, p.bin_b);
+  cp(C0, p.C0);
+  cp(C1, p.C1);
+  return MBH_OK;
+}
+
 // After a refresh on the device, bring the host copies of the reference up
 // to date (waits for the last refresh).
 static mbh_status sync_mirror(const mbh_ref *rc) {
@@ -671,6 +1108,7 @@ extern "C" mbh_status mbh_ref_get_info(const mbh_ref *r, mbh_ref_info *o) {
 extern "C" mbh_status mbh_ref_export(const mbh_ref *r, double *edges, int64_t *kb, double *A0, double *A1,
                                      double *B0, double *B1, double *h0_edges) {
   if (!r) return mbh_fail(MBH_EINVAL, "null reference");
+  if (r->pm) return mbh_fail(MBH_EINVAL, "per-mode reference: export with mbh_ref_pm_mode and mbh_ref_pm_pair");
   MBH_TRY(sync_mirror(r));
   if (edges) std::memcpy(edges, r->edges.data(), r->edges.size() * sizeof(double));
   if (kb) std::memcpy(kb, r->kb.data(), r->kb.size() * sizeof(int64_t));
@@ -751,6 +1189,7 @@ static mbh_status refresh_alloc(mbh_ref *r, hipStream_t st) {
 
 extern "C" mbh_status mbh_ref_refresh_prepare(mbh_ref *r, hipStream_t st) {
   if (!r) return mbh_fail(MBH_EINVAL, "null reference");
+  if (r->pm) return mbh_fail(MBH_EINVAL, "per-mode references are not updated on the device");
   HIP_TRY(hipSetDevice(r->ctx->device));
   std::lock_guard<std::mutex> g(r->mu);
   return refresh_alloc(r, st);
@@ -760,6 +1199,7 @@ extern "C" mbh_status mbh_ref_refresh(mbh_ctx *ctx, const mbh_data *data, mbh_re
                                       const double *lnL_dev, int64_t W, hipStream_t st) {
   if (!ctx || !data || !r || !theta_dev || !lnL_dev) return mbh_fail(MBH_EINVAL, "null argument");
   if (W < 1) return mbh_fail(MBH_EINVAL, "W = %lld", (long long)W);
+  if (r->pm) return mbh_fail(MBH_EINVAL, "per-mode references are not updated on the device");
   if (r->ctx != ctx || data->ctx != ctx) return mbh_fail(MBH_EINVAL, "reference or data from another context");
   if (data->n_chan != r->n_chan || data->n_f != r->n_f || data->f0 != r->f0 || data->df != r->df ||
       data->t_obs != r->t_obs)
@@ -883,6 +1323,19 @@ WorkItem make_item(const mbh_ctx *ctx, const mbh_ref *r, int G) {
   it.G = G;
   it.model = r->model;
   it.hm = modes_hm(r->model, r->modes) ? 1 : 0;
+  if (r->pm) {  // per-mode reference: edge pass over T1 tasks, cross pass over T2 + 1, flattened
+    it.G = 0;
+    it.E = r->pm_T1;
+    it.K1 = flat_slots(r->pm_T1);
+    it.E2 = r->pm_T2 + 1;
+    it.K = it.K1 + flat_slots(it.E2);
+    it.pm.mode_of = r->pm_mode_of;
+    it.pm.bin_of = r->pm_bin_of;
+    it.pm.cross = r->pm_cross;
+    it.pm.ccoef = r->pm_ccoef;
+    it.pm.T1 = r->pm_T1;
+    it.pm.T2 = r->pm_T2;
+  }
   double tol;
   {
     std::lock_guard<std::mutex> g(ctx->mu);
@@ -968,16 +1421,38 @@ static mbh_status het_launch(const WorkItem &it, mbh_precision prec, hipStream_t
   return MBH_OK;
 }
 
+// setup, edge pass, cross pass and totals of one per-mode item on `st` (FP64)
+static mbh_status pm_launch(const WorkItem &it, hipStream_t st) {
+  hipLaunchKernelGGL(k_setup_one, dim3((unsigned)((it.W + 63) / 64)), dim3(128), 0, st, it);
+  const int64_t n1 = flat_chunks(it.W, it.E), n2 = flat_chunks(it.W, it.E2);
+  const dim3 g1((unsigned)((n1 + kWaves - 1) / kWaves)), g2((unsigned)((n2 + kWaves - 1) / kWaves));
+  if (it.dhhh) {
+    hipLaunchKernelGGL(k_pm_edges<true>, g1, dim3(kBlock), 0, st, it, n1);
+    if (it.pm.T2 > 0) hipLaunchKernelGGL(k_pm_cross<true>, g2, dim3(kBlock), 0, st, it, n2);
+  } else {
+    hipLaunchKernelGGL(k_pm_edges<false>, g1, dim3(kBlock), 0, st, it, n1);
+    if (it.pm.T2 > 0) hipLaunchKernelGGL(k_pm_cross<false>, g2, dim3(kBlock), 0, st, it, n2);
+  }
+  launch_finish(nullptr, it, nullptr, 0, st);
+  HIP_TRY(hipGetLastError());
+  return MBH_OK;
+}
+
 extern "C" mbh_status mbh_loglike_heterodyned(mbh_ctx *ctx, const mbh_ref *ref, const double *theta_dev,
                                               int64_t W, mbh_precision prec, double *lnL_dev,
                                               double *dh_hh_dev, hipStream_t st) {
   MBH_TRY(het_check(ctx, ref, theta_dev, W, prec, lnL_dev));
+  if (ref->pm && prec != MBH_FP64) return mbh_fail(MBH_EINVAL, "per-mode references are evaluated in MBH_FP64");
   if (W == 0) return MBH_OK;
   HIP_TRY(hipSetDevice(ctx->device));
   Scratch sc(ctx, st);
   WorkItem it = het_item(ctx, ref, theta_dev, W, prec, lnL_dev, dh_hh_dev);
   MBH_TRY(sc.get(&it.wc, (size_t)W));
   MBH_TRY(sc.get(&it.part, (size_t)W * it.K * 4));
+  if (ref->pm) {
+    MBH_TRY(sc.get(&it.pm.dsc, (size_t)W * it.pm.T1 * 3));
+    return pm_launch(it, st);
+  }
   return het_launch(it, prec, st);
 }
 
@@ -993,6 +1468,7 @@ extern "C" mbh_status mbh_loglike_heterodyned_noalloc(mbh_ctx *ctx, const mbh_re
                                                       int64_t W, mbh_precision prec, double *lnL_dev,
                                                       double *dh_hh_dev, hipStream_t st) {
   MBH_TRY(het_check(ctx, ref, theta_dev, W, prec, lnL_dev));
+  if (ref->pm) return mbh_fail(MBH_EINVAL, "per-mode references are evaluated with mbh_loglike_heterodyned");
   if (W == 0) return MBH_OK;
   size_t part_off = 0;
   const size_t need = het_scratch_bytes(W, flat_slots(ref->n_bins + 1), &part_off);
@@ -1114,6 +1590,7 @@ extern "C" mbh_status mbh_autotune_heterodyned(mbh_ctx *ctx, const mbh_ref *ref,
                                                int64_t W, mbh_precision prec, int *lanes_out) {
   if (!ctx || !ref || W < 1) return mbh_fail(MBH_EINVAL, "bad argument");
   if (prec != MBH_FP64 && prec != MBH_MIXED) return mbh_fail(MBH_EINVAL, "bad precision");
+  if (ref->pm) return mbh_fail(MBH_EINVAL, "per-mode references use the flattened mapping only");
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t st;
   HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));

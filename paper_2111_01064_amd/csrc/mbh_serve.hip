@@ -68,6 +68,21 @@ static void append_tiles(std::vector<WorkTile> &tiles, std::vector<double> &cost
   const int E = r->n_bins + 1;
   const int nm = popcount_modes(r->modes ? r->modes : 1u);
   if (W <= 0) return;
+  if (r->pm) {  // per-mode reference: edge-pass tiles, then cross-pass tiles
+    const int64_t n1 = flat_chunks(W, r->pm_T1);
+    for (int64_t c = 0; c < n1; c += kWaves) {
+      tiles.push_back(WorkTile{item, kPmEdgeTiles, c});
+      cost.push_back(tile_cost(1.0, r));
+    }
+    if (r->pm_T2 > 0) {
+      const int64_t n2 = flat_chunks(W, r->pm_T2 + 1);
+      for (int64_t c = 0; c < n2; c += kWaves) {
+        tiles.push_back(WorkTile{item, kPmCrossTiles, c});
+        cost.push_back(tile_cost(1.0, r));
+      }
+    }
+    return;
+  }
   if (G == 0) {
     const int64_t nc = flat_chunks(W, E);
     for (int64_t c = 0; c < nc; c += kWaves) {
@@ -180,6 +195,13 @@ static void launch_group_t(const TileGroup &g, const WorkItem *items, const Work
 
 template <typename R, bool DH>
 static void launch_group(const TileGroup &g, const WorkItem *items, const WorkTile *tiles, hipStream_t st) {
+  if (g.G == kPmEdgeTiles || g.G == kPmCrossTiles) {  // per-mode items (FP64 batches only)
+    const dim3 grid((unsigned)g.count), blk(kBlock);
+    const WorkTile *t = tiles + g.begin;
+    if (g.G == kPmEdgeTiles) hipLaunchKernelGGL((k_pm_tiles<DH, 1>), grid, blk, 0, st, items, t);
+    else hipLaunchKernelGGL((k_pm_tiles<DH, 2>), grid, blk, 0, st, items, t);
+    return;
+  }
   if (g.hm) launch_group_t<R, DH, true>(g, items, tiles, st);
   else launch_group_t<R, DH, false>(g, items, tiles, st);
 }
@@ -250,13 +272,18 @@ extern "C" mbh_status mbh_batch_create(mbh_ctx *ctx, int n, const mbh_ref *const
   int64_t total = 0;
   bool dh = false;
   int Kmax = 1;
+  size_t pm_cells = 0;  // per-mode items: deltas at the edges, W T1 C of them
   for (int i = 0; i < n; ++i) {
     if (!refs[i] || W[i] < 0 || (W[i] > 0 && (!theta_dev[i] || !lnL_dev[i])))
       return mbh_fail(MBH_EINVAL, "item %d: null reference or buffers", i);
     if (refs[i]->ctx != ctx) return mbh_fail(MBH_EINVAL, "item %d: reference of another context", i);
+    if (refs[i]->pm && prec != MBH_FP64)
+      return mbh_fail(MBH_EINVAL, "item %d: per-mode references are evaluated in MBH_FP64", i);
     total += W[i];
     if (dh_hh_dev && dh_hh_dev[i]) dh = true;
-    Kmax = std::max(Kmax, flat_slots(refs[i]->n_bins + 1));
+    Kmax = std::max(Kmax, refs[i]->pm ? flat_slots(refs[i]->pm_T1) + flat_slots(refs[i]->pm_T2 + 1)
+                                      : flat_slots(refs[i]->n_bins + 1));
+    if (refs[i]->pm) pm_cells += (size_t)W[i] * refs[i]->pm_T1 * 3;
   }
   if (total == 0) return mbh_fail(MBH_EINVAL, "batch of %d items holds no walkers", n);
   HIP_TRY(hipSetDevice(ctx->device));
@@ -271,10 +298,12 @@ extern "C" mbh_status mbh_batch_create(mbh_ctx *ctx, int n, const mbh_ref *const
   };
   WalkerC *wc = nullptr;
   double *part = nullptr;
+  double2 *dsc = nullptr;
   mbh_status s;
   if ((s = batch_alloc(b, &wc, (size_t)total)) != MBH_OK || (s = batch_alloc(b, &part, (size_t)total * Kmax * 4)) != MBH_OK ||
-      (s = batch_alloc(b, &b->redo, 1)) != MBH_OK)
+      (s = batch_alloc(b, &b->redo, 1)) != MBH_OK || (pm_cells && (s = batch_alloc(b, &dsc, pm_cells)) != MBH_OK))
     return fail(s);
+  size_t dsc_off = 0;
   std::vector<WorkItem> items(n);
   std::vector<WorkTile> tiles;
   std::vector<WalkerTile> wtiles;
@@ -291,6 +320,10 @@ extern "C" mbh_status mbh_batch_create(mbh_ctx *ctx, int n, const mbh_ref *const
     it.redo = b->redo;
     it.W = W[i];
     it.offset = off;
+    if (refs[i]->pm) {
+      it.pm.dsc = dsc + dsc_off;
+      dsc_off += (size_t)W[i] * refs[i]->pm_T1 * 3;
+    }
     append_tiles(tiles, cost, i, refs[i], it.G, W[i]);
     append_wtiles(wtiles, i, W[i]);
     off += W[i];
@@ -642,8 +675,10 @@ extern "C" mbh_status mbh_server_create(mbh_ctx *ctx, int n_refs, const mbh_ref 
   if (cfg->max_inflight < 1 || cfg->max_inflight > 8 || cfg->max_batch_walkers < 1)
     return mbh_fail(MBH_EINVAL, "max_inflight in [1, 8] and max_batch_walkers >= 1 required");
   if (cfg->prec != MBH_FP64 && cfg->prec != MBH_MIXED) return mbh_fail(MBH_EINVAL, "bad precision");
-  for (int i = 0; i < n_refs; ++i)
+  for (int i = 0; i < n_refs; ++i) {
     if (!refs[i] || refs[i]->ctx != ctx) return mbh_fail(MBH_EINVAL, "reference %d invalid", i);
+    if (refs[i]->pm) return mbh_fail(MBH_EINVAL, "reference %d: per-mode references are not served", i);
+  }
   HIP_TRY(hipSetDevice(ctx->device));
   mbh_server *s = new mbh_server();
   s->ctx = ctx;

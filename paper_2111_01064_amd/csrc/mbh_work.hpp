@@ -52,4 +52,24 @@ __global__ __launch_bounds__(kBlock, 2) void k_het_tiles(const WorkItem *__restr
   }
 }
 
+// Tiles of per-mode items carry these in place of G: kWaves chunks of the
+// edge pass or of the cross pass (which reads the edge pass's deltas: its
+// group is launched after every edge-pass group).
+constexpr int kPmEdgeTiles = 128;
+constexpr int kPmCrossTiles = 129;
+
+template <bool DH, int PASS>
+__global__ __launch_bounds__(kBlock, 2) void k_pm_tiles(const WorkItem *__restrict__ items,
+                                                        const WorkTile *__restrict__ tiles) {
+  const WorkTile tl = tiles[blockIdx.x];
+  WorkItem it = items[tl.item];
+  it.ref = with_meta(it.ref);
+  const int64_t c = tl.begin + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if constexpr (PASS == 1) {
+    if (c < flat_chunks(it.W, it.E)) pm_chunk_edges<DH>(it, c);
+  } else {
+    if (c < flat_chunks(it.W, it.E2)) pm_chunk_cross<DH>(it, c);
+  }
+}
+
 }  // namespace mbh

@@ -77,6 +77,12 @@ _SIGS = {
     "mbh_ref_release": [_vp],
     "mbh_ref_get_info": [_vp, ct.POINTER(_RefInfo)],
     "mbh_ref_export": [_vp, _dp, ct.POINTER(ct.c_int64), _dp, _dp, _dp, _dp, _dp],
+    "mbh_build_reference_coeffs_pm": [_vp, _vp, _i32, _u32, _dp, ct.POINTER(ct.c_int32), _vp, _pp],
+    "mbh_ref_pm_info": [_vp, ct.POINTER(ct.c_uint32), ct.POINTER(ct.c_int32)],
+    "mbh_ref_pm_mode": [_vp, _i32, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int32), _dp,
+                        ct.POINTER(ct.c_int64), _dp, _dp, _dp, _dp, _dp],
+    "mbh_ref_pm_pair": [_vp, _i32, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32), _dp,
+                        ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32), _dp, _dp],
     "mbh_ref_refresh": [_vp, _vp, _vp, _vp, _vp, _i64, _vp],
     "mbh_ref_refresh_result": [_vp, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int32)],
     "mbh_ref_refresh_prepare": [_vp, _vp],
@@ -230,6 +236,46 @@ class Reference:
         return dict(edges=edges, kb=kb, A0=A0[..., 0] + 1j * A0[..., 1], A1=A1[..., 0] + 1j * A1[..., 1],
                     B0=B0, B1=B1, h0_edges=h0[..., 0] + 1j * h0[..., 1])
 
+    def pm_info(self) -> dict:
+        """mbh_ref_pm_info: modes with bins (mask) and mode pairs with overlapping bands."""
+        m, n = ct.c_uint32(), ct.c_int32()
+        _check(_L.mbh_ref_pm_info(self.h, ct.byref(m), ct.byref(n)), "mbh_ref_pm_info")
+        return dict(modes=m.value, n_pairs=n.value)
+
+    def pm_mode(self, mode_index: int) -> dict:
+        """mbh_ref_pm_mode: one mode's band, edges, bins and sums (complex arrays)."""
+        lo, hi, nb = ct.c_int64(), ct.c_int64(), ct.c_int32()
+        z = ct.POINTER(ct.c_double)()
+        zi = ct.POINTER(ct.c_int64)()
+        _check(_L.mbh_ref_pm_mode(self.h, mode_index, ct.byref(lo), ct.byref(hi), ct.byref(nb), z, zi, z, z, z, z, z),
+               "mbh_ref_pm_mode")
+        n = nb.value
+        edges, kb = np.zeros(n + 1), np.zeros(n + 1, dtype=np.int64)
+        a0, a1, b0, b1, h0 = np.zeros((3, n, 2)), np.zeros((3, n, 2)), np.zeros((3, n)), np.zeros((3, n)), np.zeros((3, n + 1, 2))
+        P = lambda a: a.ctypes.data_as(_dp)
+        _check(_L.mbh_ref_pm_mode(self.h, mode_index, None, None, None, P(edges),
+                                  kb.ctypes.data_as(ct.POINTER(ct.c_int64)), P(a0), P(a1), P(b0), P(b1), P(h0)),
+               "mbh_ref_pm_mode")
+        c = lambda x: x[..., 0] + 1j * x[..., 1]
+        return dict(k_lo=lo.value, k_hi=hi.value, edges=edges, kb=kb, Ares0=c(a0), Ares1=c(a1), B0=b0, B1=b1,
+                    h0_edges=c(h0))
+
+    def pm_pair(self, pair: int) -> dict:
+        """mbh_ref_pm_pair: one mode pair's merged grid and cross sums."""
+        ma, mb, nm = ct.c_int32(), ct.c_int32(), ct.c_int32()
+        _check(_L.mbh_ref_pm_pair(self.h, pair, ct.byref(ma), ct.byref(mb), ct.byref(nm), None, None, None, None,
+                                  None, None), "mbh_ref_pm_pair")
+        n = nm.value
+        edges, kb = np.zeros(n + 1), np.zeros(n + 1, dtype=np.int64)
+        ba, bb = np.zeros(n, dtype=np.int32), np.zeros(n, dtype=np.int32)
+        c0, c1 = np.zeros((3, n, 2)), np.zeros((3, n, 2))
+        P = lambda a: a.ctypes.data_as(_dp)
+        I32 = lambda a: a.ctypes.data_as(ct.POINTER(ct.c_int32))
+        _check(_L.mbh_ref_pm_pair(self.h, pair, None, None, None, P(edges), kb.ctypes.data_as(ct.POINTER(ct.c_int64)),
+                                  I32(ba), I32(bb), P(c0), P(c1)), "mbh_ref_pm_pair")
+        c = lambda x: x[..., 0] + 1j * x[..., 1]
+        return dict(mode_a=ma.value, mode_b=mb.value, edges=edges, kb=kb, bin_a=ba, bin_b=bb, C0=c(c0), C1=c(c1))
+
     def close(self):
         if getattr(self, "h", None):
             _L.mbh_ref_release(self.h)
@@ -273,6 +319,17 @@ def build_reference_coeffs(ctx: Context, data: Data, model: int, modes: int, the
     h = ct.c_void_p()
     _check(_L.mbh_build_reference_coeffs(ctx.h, data.h, model, modes, th.ctypes.data_as(_dp), n_bins,
                                          _stream(stream), ct.byref(h)), "mbh_build_reference_coeffs")
+    return Reference(ctx, h)
+
+
+def build_reference_coeffs_pm(ctx: Context, data: Data, model: int, modes: int, theta0, n_bins_mode,
+                              stream=None) -> Reference:
+    """mbh_build_reference_coeffs_pm: per-mode relative binning (n_bins_mode: 6 bin counts)."""
+    th = _host_theta(theta0)
+    nb = (ct.c_int32 * 6)(*[int(x) for x in n_bins_mode])
+    h = ct.c_void_p()
+    _check(_L.mbh_build_reference_coeffs_pm(ctx.h, data.h, model, modes, th.ctypes.data_as(_dp), nb,
+                                            _stream(stream), ct.byref(h)), "mbh_build_reference_coeffs_pm")
     return Reference(ctx, h)
 
 
