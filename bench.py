@@ -491,6 +491,57 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def sampler_search(M, ctx, item):
+    import torch
+
+    K, W = 10, 400
+    lo = np.array([math.log(1e5), 0.05, -0.99, -0.99, 1e-2, 0.0, -1.0, 0.0, -1.0, 0.0, 0.0])
+    hi = np.array([math.log(1e8), 1.0, 0.99, 0.99, 1e3, 2 * math.pi, 1.0, 2 * math.pi, 1.0, math.pi, item["data"].t_obs])
+    th = item["th"]
+
+    def het(x):
+        return M.loglike_heterodyned(ctx, item["ref"], torch.as_tensor(x, device="cuda"), M.FP64).cpu().numpy()
+
+    sig = I.curvature_sigma(het, th)
+    cloud = I.walker_cloud(th, sig, tuple(4.0 ** k for k in range(K)), W, I.rng_for(2, 900))
+    x0 = cloud.copy()
+    x0[:, 0] = np.log(cloud[:, 0])
+    x0[:, 6] = np.cos(cloud[:, 6])
+    x0[:, 8] = np.sin(cloud[:, 8])
+    x0 = np.clip(x0, lo, hi)
+    ref = M.build_reference_coeffs(ctx, item["data"], M.MODEL_IMR, M.MODE_22, cloud[-1], N_BINS)
+    like = M.Sampler.likelihood(ref=ref)
+    betas = 1.0 / 1.6 ** np.arange(K)
+    smp = M.Sampler(ctx, betas, W, lo, hi, seed=20211101, prec=M.MIXED)
+    smp.set_walkers(x0, like)
+    r = smp.run(like, check_every=150, lnl_tol=1.0, lnl_checks=30, refresh_every=1000, refresh_data=item["data"],
+                max_iter=30000)
+    st = smp.stats()
+    # the best walker of the cold rung and the source, on the full grid
+    fin = smp.get()
+    xb = fin["x"][int(np.argmax(fin["lnL"][:W]))]
+    tb = xb.copy()
+    tb[0], tb[6], tb[8] = math.exp(xb[0]), math.acos(xb[6]), math.asin(xb[8])
+    lf = M.loglike_full(ctx, item["data"], M.MODEL_IMR, M.MODE_22,
+                        torch.as_tensor(np.stack([tb, th]), device="cuda"), M.FP64).cpu().numpy()
+    acc = st["accepted"].astype(float)
+    prop = np.maximum(st["proposed"].astype(float), 1.0)
+    l_true = float(het(th[None, :])[0])
+    out = dict(rungs=K, walkers_per_rung=W, iterations=r["iterations"],
+               stop={0: "max_iter", 1: "snr", 2: "converged"}[r["reason"]], reference_updates=r["refreshes"],
+               seconds=r["seconds"], us_per_iteration=r["seconds"] / max(1, r["iterations"]) * 1e6,
+               lnL_evals_per_s=2 * (K * W // 2) * r["iterations"] / r["seconds"],
+               max_lnL=r["max_lnL"], lnL_at_source=l_true, best_extracted_snr=r["best_snr"],
+               full_grid_lnL_best=float(lf[0]), full_grid_lnL_source=float(lf[1]),
+               source_snr=item["snr"], cold_acceptance={"stretch": acc[0, 0] / prop[0, 0],
+                                                        "sky_hops": acc[0, 1:].sum() / prop[0, 1:].sum()},
+               swap_acceptance_cold_pair=float(st["swaps"][0]) / (W * max(1, r["iterations"])))
+    smp.close()
+    ref.close()
+    log(f"[bench] sampler search: {out}")
+    return out
+
+
 def side_measurements(M, ctx, S, walkers, grid):
     import torch
 
@@ -623,7 +674,45 @@ def side_measurements(M, ctx, S, walkers, grid):
     hm["mixed_speedup_vs_fp64"] = hm["mixed_evals_per_s"] / hm["fp64_evals_per_s"]
     ok = np.isfinite(lnl4["fp64"])
     hm["max_abs_dlnL_mixed_vs_fp64"] = float(np.max(np.abs(lnl4["mixed"][ok] - lnl4["fp64"][ok])))
+    # the same sources and walkers with per-mode relative binning (each mode
+    # its own bins, log-uniform 64-512 per mode; FP64), and the method error
+    # of both schemes against the full-grid likelihood on a walker subset
+    nbm = [I.per_mode_bins(I.rng_for(4, 200 + k), sh[0]) for k, sh in enumerate(shapes)]
+    pm_refs = [M.build_reference_coeffs_pm(ctx, it4["data"], M.MODEL_IMR, it4["modes"], it4["th"], nb)
+               for it4, nb in zip(S4.items, nbm)]
+    lnp = [torch.empty(len(t), dtype=torch.float64, device="cuda") for t in th4]
+    bp = M.Batch(ctx, pm_refs, th4, lnp, prec=M.FP64)
+    wall, mean_s = time_batch(M, ctx, bp, 50, 5, st)
+    hm["per_mode_fp64_evals_per_s"] = W4 * 50 / wall
+    hm["per_mode_fp64_us_per_launch"] = mean_s * 1e6
+    hm["per_mode_bins"] = nbm
+    bp.close()
+    lnp = [l.cpu().numpy() for l in lnp]
+    err_sum, err_pm = [], []
+    for k, (it4, t4) in enumerate(zip(S4.items, th4)):
+        idx = np.arange(0, len(t4), max(1, len(t4) // 32))[:32]
+        sub = t4[torch.as_tensor(idx, device="cuda")].contiguous()
+        lf = M.loglike_full(ctx, it4["data"], M.MODEL_IMR, it4["modes"], sub, M.FP64).cpu().numpy()
+        off = sum(len(x) for x in th4[:k])
+        err_sum.append(np.abs(lnl4["fp64"][off + idx] - lf))
+        err_pm.append(np.abs(lnp[k][idx] - lf))
+    es, ep = np.concatenate(err_sum), np.concatenate(err_pm)
+    hm["method_error_vs_full_grid"] = {
+        "walkers": int(es.size),
+        "mode_summed": {"max": float(es.max()), "median": float(np.median(es))},
+        "per_mode": {"max": float(ep.max()), "median": float(np.median(ep))}}
+    for r in pm_refs:
+        r.close()
+    log(f"[bench] HM batch per-mode FP64: {hm['per_mode_fp64_evals_per_s']:.3g} evals/s; method error "
+        f"{hm['method_error_vs_full_grid']}")
     out["hm_batch"] = hm
+    # a heterodyned search (Sec. 3's second module) on the loudest source of
+    # the step: 10 rungs x 400 walkers from a wide cloud around the source,
+    # the reference starting at a hot walker and moved to the best walker on
+    # the device every 1000 iterations (the paper: 5000, in runs of 1e4+
+    # iterations), stopped when the maximum lnL has moved by less than 1 over
+    # 30 checks 150 iterations apart
+    out["sampler_search"] = sampler_search(M, ctx, S.items[1])
     # serving: 4 resident sources (the step's physics with 1-6 modes each and
     # 64 / 128 / 256 / 512 bins), a Poisson stream from 64 samplers with
     # request sizes log-uniform in 1-4096 walkers, at fractions of the

@@ -444,6 +444,116 @@ typedef struct {
 mbh_status mbh_server_get_stats(const mbh_server *srv, mbh_server_stats *out);
 mbh_status mbh_server_destroy(mbh_server *srv);
 
+/* ---------------------------------------------------------- sampler (Sec. 3) */
+
+/* Tempered ensemble sampler on the device, as described in Sec. 3 of the
+ * paper: an affine-invariant ensemble with parallel tempering, the stretch
+ * proposal for most moves and sky-mode hops for the rest, the extracted-SNR
+ * stopping rule of the first (full-grid) search, the maximum-likelihood
+ * convergence rule of the heterodyned search, and the reference moved to the
+ * best walker every few thousand iterations.
+ * Sampling coordinates x (11, per walker): (ln M_T, q, a1, a2, D_L, phi_ref,
+ * cos iota, lambda, sin beta, psi, t_ref), with a uniform prior on a box
+ * (the paper's prior table); the likelihood takes theta (M_T, q, a1, a2, D_L,
+ * phi_ref, iota, lambda, beta, psi, t_ref).  Rung k samples
+ * L(x)^betas[k] p(x).  Each rung's walkers move in two halves (the first with
+ * the second as complement, then the reverse); each walker draws its move:
+ * a stretch (partner from the other half, z from g(z) ~ 1/sqrt(z) on
+ * [1/a, a], acceptance factor z^10) or, with the shares p_sky_*, a hop to one
+ * of the eight sky modes at random (lambda and psi turned by k pi/2, times the
+ * reflection beta -> -beta, cos iota -> -cos iota, psi -> pi - psi), a
+ * longitudinal turn alone or the reflection alone.  After both halves,
+ * adjacent rungs exchange walkers (walker i of rung k with walker (i + s) mod W
+ * of rung k + 1, s uniform per iteration and pair).  Every random number is a
+ * Philox4x32-10 draw keyed by `seed` with counter (iteration, index, stream,
+ * half), so a run is reproducible and independent of launch shapes. */
+typedef struct mbh_sampler mbh_sampler;
+typedef struct {
+  int32_t n_temps;          /* rungs, 1..64                                   */
+  int32_t walkers_per_temp; /* even, 4..65536                                 */
+  double stretch_a;         /* stretch scale a > 1 (2 is usual)               */
+  double p_sky_all, p_sky_lon, p_sky_lat; /* hop shares (the paper: 0.04, 0.03, 0.08) */
+  uint64_t seed;
+  mbh_precision prec;       /* of the heterodyned / full-grid likelihood      */
+} mbh_sampler_config;
+/* The likelihood a sampler evaluates: heterodyned against `ref` (IMR; a
+ * per-mode reference runs in FP64), or, with ref NULL, the full grid of
+ * `data` with `modes` (IMR). */
+typedef struct {
+  const mbh_ref *ref;
+  const mbh_data *data;
+  uint32_t modes;
+} mbh_likelihood;
+/* betas_host [n_temps]: inverse temperatures, betas[0] = 1, strictly
+ * decreasing, >= 0.  prior_lo_host, prior_hi_host [11]: the box in x.
+ * Errors: MBH_EINVAL, MBH_ENOMEM, MBH_EDEVICE. */
+mbh_status mbh_sampler_create(mbh_ctx *ctx, const mbh_sampler_config *cfg, const double *betas_host,
+                              const double *prior_lo_host, const double *prior_hi_host,
+                              mbh_sampler **out);
+mbh_status mbh_sampler_destroy(mbh_sampler *s);
+/* Walkers x_host [n_temps * walkers_per_temp][11] (rung-major, host,
+ * copied) and their lnL: lnL_host [n_temps * walkers_per_temp] if given
+ * (their <d|h>, <h|h> set to 0; `like` may then be NULL), else evaluated
+ * under `like` on `stream`. */
+mbh_status mbh_sampler_set_walkers(mbh_sampler *s, const double *x_host, const double *lnL_host,
+                                   const mbh_likelihood *like, hipStream_t stream);
+/* n_iter iterations on `stream` (asynchronous). */
+mbh_status mbh_sampler_step(mbh_sampler *s, const mbh_likelihood *like, int64_t n_iter, hipStream_t stream);
+/* The parts of one iteration, for callers that evaluate the likelihood
+ * themselves: mbh_sampler_propose writes the proposals of half 0 or 1 of
+ * every rung (mbh_sampler_proposals copies them out: x and theta
+ * [n_temps * walkers_per_temp / 2][11], theta[0] NaN outside the prior box,
+ * and the move kind 0 stretch, 1 all sky modes, 2 longitudinal,
+ * 3 latitudinal); mbh_sampler_accept takes their lnL (device,
+ * [n_temps * walkers_per_temp / 2], rung-major; -inf outside the prior) and
+ * optionally their <d|h>, <h|h> ([..][2] or NULL); mbh_sampler_swap makes the
+ * exchanges and ends the iteration.  propose(0), accept(0), propose(1),
+ * accept(1), swap is one iteration. */
+mbh_status mbh_sampler_propose(mbh_sampler *s, int half, hipStream_t stream);
+mbh_status mbh_sampler_proposals(mbh_sampler *s, double *x_host, double *theta_host, int32_t *kind_host);
+mbh_status mbh_sampler_accept(mbh_sampler *s, int half, const double *lnL_prop_dev,
+                              const double *dh_hh_prop_dev, hipStream_t stream);
+mbh_status mbh_sampler_swap(mbh_sampler *s, hipStream_t stream);
+/* Current walkers (x [n][11], lnL [n], <d|h> <h|h> [n][2]; any may be NULL)
+ * and the iterations done.  Synchronous. */
+mbh_status mbh_sampler_get(mbh_sampler *s, double *x_host, double *lnL_host, double *dh_hh_host,
+                           int64_t *iteration);
+/* Accepted and proposed moves per rung and move kind ([n_temps][4]) and
+ * accepted exchanges per pair of rungs ([n_temps - 1]); any may be NULL. */
+mbh_status mbh_sampler_stats(mbh_sampler *s, uint64_t *accepted, uint64_t *proposed, uint64_t *swaps);
+/* Stopping rules of Sec. 3 (checked every check_every iterations on the
+ * best walker of the first rung): snr_stop > 0 stops when its extracted SNR
+ * <d|h> / sqrt(<h|h>) reaches snr_stop (the first search); lnl_checks > 0
+ * stops when the maximum lnL has moved by less than lnl_tol over lnl_checks
+ * consecutive checks (the heterodyned search: 1 and 30).  refresh_every > 0
+ * moves the reference to the best walker of the population every
+ * refresh_every iterations (mbh_ref_refresh, on the device) and re-evaluates
+ * every walker against it (heterodyned likelihood only; refresh_data is the
+ * data the reference was built on). */
+enum { MBH_STOP_MAX_ITER = 0, MBH_STOP_SNR = 1, MBH_STOP_CONVERGED = 2 };
+typedef struct {
+  int32_t check_every;
+  double snr_stop;
+  double lnl_tol;
+  int32_t lnl_checks;
+  int32_t refresh_every;
+  const mbh_data *refresh_data;
+  int64_t max_iter;
+} mbh_sampler_stop;
+typedef struct {
+  int64_t iterations;  /* done in this call                       */
+  int32_t reason;      /* MBH_STOP_*                              */
+  int32_t checks, refreshes;
+  double max_lnL;      /* best lnL of the first rung at the last check */
+  double best_snr;     /* its extracted SNR                       */
+  double seconds;      /* wall time of the call                   */
+} mbh_sampler_report;
+/* Iterate until a stopping rule holds or max_iter iterations are done.
+ * Synchronises `stream` at every check.  Errors: MBH_EINVAL, MBH_EDEVICE and
+ * those of the likelihood calls. */
+mbh_status mbh_sampler_run(mbh_sampler *s, const mbh_likelihood *like, const mbh_sampler_stop *stop,
+                           hipStream_t stream, mbh_sampler_report *report);
+
 #ifdef __cplusplus
 }
 #endif

@@ -249,6 +249,16 @@ def batch_shapes(rng: np.random.Generator, n_sources: int = 16):
     return shapes
 
 
+def per_mode_bins(rng: np.random.Generator, mask: int):
+    """Bin counts of the six modes for per-mode relative binning: log-uniform
+    over [64, 512] for the modes in the mask (0 for the others)."""
+    out = [0] * 6
+    for i in range(6):
+        if mask & (1 << i):
+            out[i] = int(round(math.exp(rng.uniform(math.log(64), math.log(512)))))
+    return out
+
+
 def poisson_requests(rng: np.random.Generator, n: int, rate_hz: float, n_samplers: int = 64,
                      n_sources: int = 4, w_max: int = 4096):
     """Open-loop Poisson arrivals: (arrival_s, sampler, source, W) with

@@ -57,6 +57,28 @@ class RequestSpec(ct.Structure):
                 ("W", ct.c_int64), ("theta_row", ct.c_int64)]
 
 
+class SamplerConfig(ct.Structure):
+    _fields_ = [("n_temps", ct.c_int32), ("walkers_per_temp", ct.c_int32), ("stretch_a", ct.c_double),
+                ("p_sky_all", ct.c_double), ("p_sky_lon", ct.c_double), ("p_sky_lat", ct.c_double),
+                ("seed", ct.c_uint64), ("prec", ct.c_int)]
+
+
+class Likelihood(ct.Structure):
+    _fields_ = [("ref", ct.c_void_p), ("data", ct.c_void_p), ("modes", ct.c_uint32)]
+
+
+class SamplerStop(ct.Structure):
+    _fields_ = [("check_every", ct.c_int32), ("snr_stop", ct.c_double), ("lnl_tol", ct.c_double),
+                ("lnl_checks", ct.c_int32), ("refresh_every", ct.c_int32), ("refresh_data", ct.c_void_p),
+                ("max_iter", ct.c_int64)]
+
+
+class SamplerReport(ct.Structure):
+    _fields_ = [("iterations", ct.c_int64), ("reason", ct.c_int32), ("checks", ct.c_int32),
+                ("refreshes", ct.c_int32), ("max_lnL", ct.c_double), ("best_snr", ct.c_double),
+                ("seconds", ct.c_double)]
+
+
 class ServerStats(ct.Structure):
     _fields_ = [("submitted", ct.c_uint64), ("completed", ct.c_uint64), ("batches", ct.c_uint64),
                 ("walkers", ct.c_uint64), ("max_walkers_in_flight", ct.c_uint64),
@@ -108,6 +130,17 @@ _SIGS = {
     "mbh_server_refresh": [_vp, _i32, _vp, _dp, _dp, _i64, ct.POINTER(ct.c_uint64)],
     "mbh_server_replay": [_vp, ct.POINTER(RequestSpec), _i64, _dp, _i64, _dp, _dp, _dp, _dp],
     "mbh_server_get_stats": [_vp, ct.POINTER(ServerStats)],
+    "mbh_sampler_create": [_vp, ct.POINTER(SamplerConfig), _dp, _dp, _dp, _pp],
+    "mbh_sampler_destroy": [_vp],
+    "mbh_sampler_set_walkers": [_vp, _dp, _dp, ct.POINTER(Likelihood), _vp],
+    "mbh_sampler_step": [_vp, ct.POINTER(Likelihood), _i64, _vp],
+    "mbh_sampler_propose": [_vp, _i32, _vp],
+    "mbh_sampler_proposals": [_vp, _dp, _dp, ct.POINTER(ct.c_int32)],
+    "mbh_sampler_accept": [_vp, _i32, _vp, _vp, _vp],
+    "mbh_sampler_swap": [_vp, _vp],
+    "mbh_sampler_get": [_vp, _dp, _dp, _dp, ct.POINTER(ct.c_int64)],
+    "mbh_sampler_stats": [_vp, ct.POINTER(ct.c_uint64), ct.POINTER(ct.c_uint64), ct.POINTER(ct.c_uint64)],
+    "mbh_sampler_run": [_vp, ct.POINTER(Likelihood), ct.POINTER(SamplerStop), _vp, ct.POINTER(SamplerReport)],
     "mbh_server_destroy": [_vp],
 }
 for _name, _args in _SIGS.items():
@@ -543,6 +576,94 @@ class Server:
     def close(self):
         if getattr(self, "h", None):
             _L.mbh_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+STOP_MAX_ITER, STOP_SNR, STOP_CONVERGED = 0, 1, 2
+
+
+class Sampler:
+    """mbh_sampler_*: tempered ensemble sampler on the device (Sec. 3)."""
+
+    def __init__(self, ctx: Context, betas, walkers_per_temp: int, prior_lo, prior_hi, seed: int = 1,
+                 stretch_a: float = 2.0, p_sky=(0.04, 0.03, 0.08), prec: int = MIXED):
+        betas = np.ascontiguousarray(betas, dtype=np.float64)
+        lo = np.ascontiguousarray(prior_lo, dtype=np.float64)
+        hi = np.ascontiguousarray(prior_hi, dtype=np.float64)
+        cfg = SamplerConfig(betas.size, walkers_per_temp, stretch_a, p_sky[0], p_sky[1], p_sky[2], seed, prec)
+        h = ct.c_void_p()
+        _check(_L.mbh_sampler_create(ctx.h, ct.byref(cfg), betas.ctypes.data_as(_dp), lo.ctypes.data_as(_dp),
+                                     hi.ctypes.data_as(_dp), ct.byref(h)), "mbh_sampler_create")
+        self.h, self.ctx = h, ctx
+        self.K, self.W = betas.size, walkers_per_temp
+
+    @staticmethod
+    def likelihood(ref: "Reference | None" = None, data: "Data | None" = None, modes: int = MODE_22) -> Likelihood:
+        return Likelihood(ref.h if ref is not None else None, data.h if data is not None else None, modes)
+
+    def set_walkers(self, x, like: Likelihood | None = None, lnL=None, stream=None):
+        """Walkers in sampling coordinates and their lnL (given, or evaluated under `like`)."""
+        x = np.ascontiguousarray(x, dtype=np.float64).reshape(self.K * self.W, NPARAM)
+        lv = None if lnL is None else np.ascontiguousarray(lnL, dtype=np.float64).reshape(self.K * self.W)
+        _check(_L.mbh_sampler_set_walkers(self.h, x.ctypes.data_as(_dp), lv.ctypes.data_as(_dp) if lv is not None
+                                          else None, ct.byref(like) if like is not None else None, _stream(stream)),
+               "mbh_sampler_set_walkers")
+
+    def step(self, like: Likelihood, n_iter: int = 1, stream=None):
+        _check(_L.mbh_sampler_step(self.h, ct.byref(like), n_iter, _stream(stream)), "mbh_sampler_step")
+
+    def propose(self, half: int, stream=None):
+        _check(_L.mbh_sampler_propose(self.h, half, _stream(stream)), "mbh_sampler_propose")
+
+    def proposals(self):
+        n = self.K * self.W // 2
+        x, th, kind = np.zeros((n, NPARAM)), np.zeros((n, NPARAM)), np.zeros(n, dtype=np.int32)
+        _check(_L.mbh_sampler_proposals(self.h, x.ctypes.data_as(_dp), th.ctypes.data_as(_dp),
+                                        kind.ctypes.data_as(ct.POINTER(ct.c_int32))), "mbh_sampler_proposals")
+        return x, th, kind
+
+    def accept(self, half: int, lnL: torch.Tensor, dh_hh: torch.Tensor | None = None, stream=None):
+        n = self.K * self.W // 2
+        _check(_L.mbh_sampler_accept(self.h, half, _dev_ptr(lnL, torch.float64, (n,)),
+                                     _dev_ptr(dh_hh, torch.float64, (n, 2)) if dh_hh is not None else None,
+                                     _stream(stream)), "mbh_sampler_accept")
+
+    def swap(self, stream=None):
+        _check(_L.mbh_sampler_swap(self.h, _stream(stream)), "mbh_sampler_swap")
+
+    def get(self):
+        n = self.K * self.W
+        x, l, dh = np.zeros((n, NPARAM)), np.zeros(n), np.zeros((n, 2))
+        it = ct.c_int64()
+        _check(_L.mbh_sampler_get(self.h, x.ctypes.data_as(_dp), l.ctypes.data_as(_dp), dh.ctypes.data_as(_dp),
+                                  ct.byref(it)), "mbh_sampler_get")
+        return dict(x=x, lnL=l, dh_hh=dh, iteration=it.value)
+
+    def stats(self):
+        acc, prop = np.zeros(self.K * 4, dtype=np.uint64), np.zeros(self.K * 4, dtype=np.uint64)
+        sw = np.zeros(max(self.K - 1, 1), dtype=np.uint64)
+        P = lambda a: a.ctypes.data_as(ct.POINTER(ct.c_uint64))
+        _check(_L.mbh_sampler_stats(self.h, P(acc), P(prop), P(sw)), "mbh_sampler_stats")
+        return dict(accepted=acc.reshape(self.K, 4), proposed=prop.reshape(self.K, 4), swaps=sw[: self.K - 1])
+
+    def run(self, like: Likelihood, check_every=150, snr_stop=0.0, lnl_tol=1.0, lnl_checks=0, refresh_every=0,
+            refresh_data: "Data | None" = None, max_iter=10000, stream=None) -> dict:
+        stop = SamplerStop(check_every, snr_stop, lnl_tol, lnl_checks, refresh_every,
+                           refresh_data.h if refresh_data is not None else None, max_iter)
+        rep = SamplerReport()
+        _check(_L.mbh_sampler_run(self.h, ct.byref(like), ct.byref(stop), _stream(stream), ct.byref(rep)),
+               "mbh_sampler_run")
+        return {k: getattr(rep, k) for k, _ in SamplerReport._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            _L.mbh_sampler_destroy(self.h)
             self.h = None
 
     def __del__(self):
