@@ -53,13 +53,13 @@ ALGO_BYTES_PER_EVAL = 96.0
 ALGO_FULL_FLOPS_PER_POINT = 250.0
 # Hardware counter figures of the current kernels (rocprofv3): VALU flops per
 # (walker, edge) of the mixed main pass (SQ_INSTS_VALU_FLOPS_* x 64 lanes,
-# FMA = 2), VALU flops per (walker, point) of the FP64 full grid, and HBM bytes
-# per launch of the mixed main pass (FETCH_SIZE and WRITE_SIZE divided by
+# FMA = 2), VALU flops per (walker, point) of the FP64 full grid (None: not
+# taken for these sources), and HBM bytes per launch of the mixed main pass (FETCH_SIZE and WRITE_SIZE divided by
 # their reading for a 64 MiB device copy: factors 0.5002 and 1.000).  Valid
 # only for the kernel sources they were measured on (sha256 over
 # KERNEL_SOURCES); reported as null otherwise.
-COUNTERS = {"src_sha256": "dd172a8d9a953817cc418b6cfece7f8d1893a3d4005f2e14699258408d0fd8f0",
-            "valu_flops_per_edge": 850.0, "full_valu_flops_per_point": 761.0, "bytes_per_launch": 5.528e6}
+COUNTERS = {"src_sha256": "08cf87041c4d3fe71893c6cf5fea7dc0a85bb16f1f8b3447e3b0466e1017e646",
+            "valu_flops_per_edge": 850.7, "full_valu_flops_per_point": None, "bytes_per_launch": 5.496e6}
 
 
 # the sources that define the device code of the main pass and the order
@@ -563,7 +563,7 @@ def side_measurements(M, ctx, S, walkers, grid):
         # algorithmic work per (walker, grid point); the counter figure beside it
         out[f"full_grid_{name}_roofline_frac"] = (len(draws) * grid.n_f * ALGO_FULL_FLOPS_PER_POINT / dt / 1e12
                                                   / PEAK_ALU_TFLOPS)
-        if COUNTERS["src_sha256"] == kernel_sources_hash():
+        if COUNTERS["src_sha256"] == kernel_sources_hash() and COUNTERS["full_valu_flops_per_point"]:
             out[f"full_grid_{name}_roofline_frac_hw"] = (len(draws) * grid.n_f * COUNTERS["full_valu_flops_per_point"]
                                                          / dt / 1e12 / PEAK_ALU_TFLOPS)
         log(f"[bench] full grid {name}: {len(draws) / dt:.1f} evals/s")
