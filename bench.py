@@ -546,40 +546,35 @@ def side_measurements(M, ctx, S, walkers, grid):
     import torch
 
     out = {}
-    # full-grid likelihood: brute-force prior draws on the 1.58e6-bin grid
+    # full-grid likelihood: brute-force prior draws on the 1.58e6-bin grid,
+    # FP64 (MBH_MIXED runs the same path), with the tile the autotuner picks
+    # on the first 2048 draws
     it = S.items[0]
     draws = I.prior_draws(I.rng_for(3, 0), 16384, grid.t_obs)
     td = torch.as_tensor(draws, device="cuda")
-    full = {}
-    for name, prec in (("fp64", M.FP64), ("mixed", M.MIXED)):
-        M.loglike_full(ctx, it["data"], M.MODEL_IMR, M.MODE_22, td[:64], prec)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        lf = M.loglike_full(ctx, it["data"], M.MODEL_IMR, M.MODE_22, td, prec)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        full[name] = lf.cpu().numpy()
-        out[f"full_grid_{name}_evals_per_s"] = len(draws) / dt
-        # algorithmic work per (walker, grid point); the counter figure beside it
-        out[f"full_grid_{name}_roofline_frac"] = (len(draws) * grid.n_f * ALGO_FULL_FLOPS_PER_POINT / dt / 1e12
-                                                  / PEAK_ALU_TFLOPS)
-        if COUNTERS["src_sha256"] == kernel_sources_hash() and COUNTERS["full_valu_flops_per_point"]:
-            out[f"full_grid_{name}_roofline_frac_hw"] = (len(draws) * grid.n_f * COUNTERS["full_valu_flops_per_point"]
-                                                         / dt / 1e12 / PEAK_ALU_TFLOPS)
-        log(f"[bench] full grid {name}: {len(draws) / dt:.1f} evals/s")
-    # |lnL_mixed - lnL_fp64| per draw, by distance below the best draw
-    ok = np.isfinite(full["fp64"])
-    dl = np.abs(full["mixed"][ok] - full["fp64"][ok])
-    below = full["fp64"][ok].max() - full["fp64"][ok]
-    rows = []
-    for lo, hi in ((0.0, 1e2), (1e2, 1e4), (1e4, 1e6), (1e6, np.inf)):
-        sel = (below >= lo) & (below < hi)
-        if sel.any():
-            rows.append({"below_max": [lo, hi if np.isfinite(hi) else None], "draws": int(sel.sum()),
-                         "max_abs_dlnL": float(dl[sel].max()), "max_rel_dlnL": float((dl[sel] / np.abs(full["fp64"][ok][sel])).max())})
-    out["full_grid_dlnL_mixed_vs_fp64"] = {"draws": int(ok.sum()), "max_abs": float(dl.max()),
-                                           "within_1e-3": float(np.mean(dl <= 1e-3)), "by_distance": rows}
-    log(f"[bench] full grid mixed vs fp64: {out['full_grid_dlnL_mixed_vs_fp64']}")
+    out["full_grid_shape_default"] = list(M.full_shape(ctx, False))
+    M.loglike_full(ctx, it["data"], M.MODEL_IMR, M.MODE_22, td[:64], M.FP64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    M.loglike_full(ctx, it["data"], M.MODEL_IMR, M.MODE_22, td, M.FP64)
+    torch.cuda.synchronize()
+    out["full_grid_default_shape_evals_per_s"] = len(draws) / (time.perf_counter() - t0)
+    out["full_grid_shape"] = list(M.autotune_full(ctx, it["data"], M.MODEL_IMR, M.MODE_22, td[:2048]))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lf = M.loglike_full(ctx, it["data"], M.MODEL_IMR, M.MODE_22, td, M.FP64)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out["full_grid_evals_per_s"] = len(draws) / dt
+    # algorithmic work per (walker, grid point); the counter figure beside it
+    out["full_grid_roofline_frac"] = len(draws) * grid.n_f * ALGO_FULL_FLOPS_PER_POINT / dt / 1e12 / PEAK_ALU_TFLOPS
+    if COUNTERS["src_sha256"] == kernel_sources_hash() and COUNTERS["full_valu_flops_per_point"]:
+        out["full_grid_roofline_frac_hw"] = (len(draws) * grid.n_f * COUNTERS["full_valu_flops_per_point"] / dt
+                                             / 1e12 / PEAK_ALU_TFLOPS)
+    lm = M.loglike_full(ctx, it["data"], M.MODEL_IMR, M.MODE_22, td, M.MIXED)
+    out["full_grid_mixed_equals_fp64"] = bool(torch.equal(lm, lf))
+    log(f"[bench] full grid: {out['full_grid_evals_per_s']:.1f} evals/s with tile {out['full_grid_shape']} "
+        f"(default {out['full_grid_shape_default']}: {out['full_grid_default_shape_evals_per_s']:.1f})")
     # reference build (a9)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

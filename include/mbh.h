@@ -282,7 +282,16 @@ mbh_status mbh_loglike_heterodyned_noalloc(mbh_ctx *ctx, const mbh_ref *ref, con
 
 /* Full-grid log-likelihood -1/2 <d-h|d-h> (eqs. like and inner, Sec. 2) of W
  * walkers: the template is generated on every grid frequency on the fly and
- * never stored.  Same argument conventions as above.
+ * never stored; lnL is formed as -1/2 (<d|d> + sum (|h|^2 - 2 Re d* h)), so
+ * grid points outside the template's support add nothing.  Same argument
+ * conventions as above.  Every step runs in FP64 for either precision:
+ * MBH_MIXED is accepted and gives the FP64 results (on this hardware FP32
+ * arithmetic issues at the FP64 rate; an FP32 response loses accuracy where
+ * the TDI combinations cancel, and an FP32 carrier with the error control it
+ * then needs is slower than FP64).  The grid tile is the context's
+ * (mbh_set_full_shape, mbh_autotune_full); results do not depend on its
+ * walkers per workgroup and differ between frequencies-per-thread settings
+ * only by rounding.
  * Errors: MBH_EINVAL, MBH_ENOMEM, MBH_EDEVICE. */
 mbh_status mbh_loglike_full(mbh_ctx *ctx, const mbh_data *data, int model, uint32_t modes,
                             const double *theta_dev, int64_t W, mbh_precision prec,
@@ -360,6 +369,21 @@ mbh_status mbh_set_lanes(mbh_ctx *ctx, int n_bins, int n_modes, mbh_precision pr
  * afterwards.  Errors: MBH_EINVAL for a negative or NaN tolerance. */
 mbh_status mbh_set_mixed_tolerance(mbh_ctx *ctx, double tol);
 mbh_status mbh_get_mixed_tolerance(const mbh_ctx *ctx, double *tol_out);
+/* Tile of the full-grid pass for a mode class (higher_modes 0: the (2,2)
+ * mode alone or the chirp model; 1: any other mode mask): kf grid
+ * frequencies per thread (1 or 2) and at most wpb_cap walkers per workgroup
+ * (8, 16, 32, 64 or 128).  Default (1, 32).  Applies to later calls.
+ * Errors: MBH_EINVAL for another value. */
+mbh_status mbh_set_full_shape(mbh_ctx *ctx, int higher_modes, int kf, int wpb_cap);
+mbh_status mbh_full_shape(const mbh_ctx *ctx, int higher_modes, int *kf_out, int *wpb_cap_out);
+/* Time mbh_loglike_full over every supported tile with these walkers
+ * (theta_dev [W][11] on the device, e.g. the sampler's ensemble) and record
+ * the fastest for this mode class; synchronous.  Outputs may be NULL.
+ * Errors: as mbh_loglike_full. */
+mbh_status mbh_autotune_full(mbh_ctx *ctx, const mbh_data *data, int model, uint32_t modes,
+                             const double *theta_dev, int64_t W, int *kf_out, int *wpb_cap_out);
+/* Save or load the tuned mappings and full-grid tiles (a text file, one
+ * entry per line; entries of another architecture are ignored). */
 mbh_status mbh_autotune_save(const mbh_ctx *ctx, const char *path);
 mbh_status mbh_autotune_load(mbh_ctx *ctx, const char *path);
 

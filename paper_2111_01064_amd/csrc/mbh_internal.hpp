@@ -25,6 +25,9 @@ struct mbh_ctx {
   // mixed path: estimated lnL error above which work is recomputed in FP64
   // (set from kMixedRouteTol at creation)
   double mixed_tol = 0.0;
+  // full-grid tile: (frequencies per thread, most walkers per workgroup),
+  // keyed by mode class (1: higher modes); absent = (1, 32)
+  std::map<int, std::pair<int, int>> full_shape;
   // the caller's reference plus one per live object created from the context
   std::atomic<int> refs{1};
 };
@@ -57,8 +60,6 @@ struct mbh_data {
   double f0 = 0, df = 0, t_obs = 0;
   double2 *dw64 = nullptr;  // whitened data d sqrt(4 df / S)         [C][N]
   double *sw64 = nullptr;   // sqrt(4 df / S) / amplitude scale        [C][N]
-  float2 *dw32 = nullptr;
-  float *sw32 = nullptr;
   double *dd_dev = nullptr;
   double dd_host = 0;
   bool dd_ready = false;

@@ -116,8 +116,7 @@ static __global__ __launch_bounds__(128) void k_walker_setup(const double *__res
 // Per-block partial of <d|d> = sum |dw|^2.
 static __global__ __launch_bounds__(kBlock) void k_whiten(const double *__restrict__ d, const double *__restrict__ psd,
                                                    int64_t n_total, double df, double2 *__restrict__ dw64,
-                                                   double *__restrict__ sw64, float2 *__restrict__ dw32,
-                                                   float *__restrict__ sw32, double *__restrict__ part) {
+                                                   double *__restrict__ sw64, double *__restrict__ part) {
   __shared__ double sh[kBlock / 64];
   double acc = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n_total; i += (int64_t)gridDim.x * kBlock) {
@@ -126,8 +125,6 @@ static __global__ __launch_bounds__(kBlock) void k_whiten(const double *__restri
     double re = d[2 * i] * s, im = d[2 * i + 1] * s;
     dw64[i] = make_double2(re, im);
     sw64[i] = s / kAmpScale;
-    dw32[i] = make_float2((float)re, (float)im);
-    sw32[i] = (float)(s / kAmpScale);
     acc += re * re + im * im;
   }
   double v[1] = {acc};
@@ -929,53 +926,45 @@ __global__ __launch_bounds__(kBlock, 2) void k_het_flat(WorkItem one, int64_t n_
 }
 
 // ---------------------------------------------------------------- a8: full grid
+// lnL = -1/2 <d-h|d-h> = -1/2 (<d|d> + sum (|h|^2 - 2 Re d* h)) over the
+// grid and channels: <d|d> is the data's (FP64, computed once), so the
+// points outside the template's support add exactly nothing and the data
+// enter only through Re d* h.  FP64 throughout.
+//
 // Block (fc, wc): KF grid frequencies per thread kept in registers, then a
 // loop over the block's walkers (wave-uniform constants); per walker and
-// block one FP64 partial of sum |dw - hw|^2 (and <d|h>, <h|h>).
+// block one FP64 partial of sum (|h|^2 - 2 Re d* h) (and <d|h>, <h|h>).
 // part layout [NV][n_fchunks][W].
-template <typename R>
-struct DataPtrs;
-template <>
-struct DataPtrs<double> {
-  using R2 = double2;
-};
-template <>
-struct DataPtrs<float> {
-  using R2 = float2;
-};
-
-template <typename R, int KF, bool DH, bool HM>
-__global__ __launch_bounds__(kBlock, 2) void k_full(const typename DataPtrs<R>::R2 *__restrict__ dw,
-                                                 const R *__restrict__ sw, int n_chan, int64_t n_f, double f0,
-                                                 double df, double t_obs, uint32_t modes,
-                                                 const WalkerC *__restrict__ wc, int64_t W, int w_per_block,
-                                                 double *__restrict__ part) {
-  using R2 = typename DataPtrs<R>::R2;
+template <int KF, bool DH, bool HM>
+__global__ __launch_bounds__(kBlock, 2) void k_full(const double2 *__restrict__ dw, const double *__restrict__ sw,
+                                                 int n_chan, int64_t n_f, double f0, double df, double t_obs,
+                                                 uint32_t modes, const WalkerC *__restrict__ wc, int64_t W,
+                                                 int w_per_block, double *__restrict__ part) {
   constexpr int NV = DH ? 3 : 1;
   __shared__ double sh[NV * (kBlock / 64)];
   const int64_t n_fc = gridDim.x;
-  R2 d[KF][3];
-  R s_w[KF][3];
+  double2 d[KF][3];
+  double s_w[KF][3];
   double fq[KF];
   FreqC fcs[KF];
   bool inr[KF];
   // sinc terms for the highest frequency of this workgroup (uniform)
-  const int ns = sinc_terms_for<R>(
+  const int ns = sinc_terms_for<double>(
       grid_freq(f0, df, min(n_f - 1, (int64_t)blockIdx.x * (kBlock * KF) + kBlock * KF - 1)));
 #pragma unroll
   for (int i = 0; i < KF; ++i) {
     int64_t k = (int64_t)blockIdx.x * (kBlock * KF) + i * kBlock + threadIdx.x;
     inr[i] = k < n_f;
     fq[i] = grid_freq(f0, df, inr[i] ? k : 0);
-    fcs[i] = freq_consts<R>(fq[i], ns);
+    fcs[i] = freq_consts<double>(fq[i], ns);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       if (c < n_chan && inr[i]) {
         d[i][c] = dw[c * n_f + k];
         s_w[i][c] = sw[c * n_f + k];
       } else {
-        d[i][c].x = d[i][c].y = (R)0;
-        s_w[i][c] = (R)0;
+        d[i][c].x = d[i][c].y = 0.0;
+        s_w[i][c] = 0.0;
       }
     }
   }
@@ -993,20 +982,20 @@ __global__ __launch_bounds__(kBlock, 2) void k_full(const typename DataPtrs<R>::
         if (!inr[i]) continue;
         cx<double> s[3];
         double psi;
-        bool any = template_point<R, HM>(c, modes, fq[i], freq_pows(fq[i]), fcs[i], t_obs, s, psi);
-        R sp = (R)0, cp = (R)1;
-        if (any) Prec<R>::sincos_r((R)reduce_2pi(psi), sp, cp);
+        if (!template_point<double, HM>(c, modes, fq[i], freq_pows(fq[i]), fcs[i], t_obs, s, psi)) continue;
+        double sp, cp;
+        sincos_red<double>(reduce_2pi(psi), sp, cp);
+        const cx<double> e = mk<double>(cp, -sp);
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
           if (ch >= n_chan) break;
-          cx<R> sr = mk<R>((R)s[ch].re, (R)s[ch].im);
-          cx<R> h = any ? sr * mk<R>(cp, -sp) : mk<R>((R)0, (R)0);
-          h = s_w[i][ch] * h;
-          R rr = d[i][ch].x - h.re, ri = d[i][ch].y - h.im;
-          v[0] += (double)(rr * rr + ri * ri);
+          const cx<double> h = s_w[i][ch] * (s[ch] * e);
+          const double hh = h.re * h.re + h.im * h.im;
+          const double dh = d[i][ch].x * h.re + d[i][ch].y * h.im;
+          v[0] += hh - 2.0 * dh;
           if constexpr (DH) {
-            v[1] += (double)(d[i][ch].x * h.re + d[i][ch].y * h.im);
-            v[2] += (double)(h.re * h.re + h.im * h.im);
+            v[1] += dh;
+            v[2] += hh;
           }
         }
       }
@@ -1020,7 +1009,8 @@ __global__ __launch_bounds__(kBlock, 2) void k_full(const typename DataPtrs<R>::
 
 // one wavefront per walker: lanes stride over the frequency chunks, fixed butterfly
 static __global__ __launch_bounds__(kBlock) void k_full_reduce(const double *__restrict__ part, int n_fc, int64_t W,
-                                                               int nv, const WalkerC *__restrict__ wc,
+                                                               int nv, const double *__restrict__ dd,
+                                                               const WalkerC *__restrict__ wc,
                                                                double *__restrict__ lnL, double *__restrict__ dhhh) {
   const int64_t w = (int64_t)blockIdx.x * (kBlock / 64) + threadIdx.x / 64;
   if (w >= W) return;
@@ -1031,8 +1021,8 @@ static __global__ __launch_bounds__(kBlock) void k_full_reduce(const double *__r
     s[i] = wave_sum(s[i]);
   }
   if (lane != 0) return;
-  bool ok = wc[w].valid;
-  lnL[w] = ok ? -0.5 * s[0] : -INFINITY;
+  const bool ok = wc[w].valid;
+  lnL[w] = ok ? -0.5 * (*dd + s[0]) : -INFINITY;
   if (dhhh) {
     dhhh[2 * w] = ok ? s[1] : 0.0;
     dhhh[2 * w + 1] = ok ? s[2] : 0.0;

@@ -250,17 +250,12 @@ extern "C" mbh_status mbh_data_create(mbh_ctx *ctx, int n_chan, int64_t n_freq, 
   d->bytes += n * sizeof(double2);
   if ((s = ctx_alloc(ctx, (void **)&d->sw64, n * sizeof(double))) != MBH_OK) return fail_free(s);
   d->bytes += n * sizeof(double);
-  if ((s = ctx_alloc(ctx, (void **)&d->dw32, n * sizeof(float2))) != MBH_OK) return fail_free(s);
-  d->bytes += n * sizeof(float2);
-  if ((s = ctx_alloc(ctx, (void **)&d->sw32, n * sizeof(float))) != MBH_OK) return fail_free(s);
-  d->bytes += n * sizeof(float);
   if ((s = ctx_alloc(ctx, (void **)&d->dd_dev, sizeof(double))) != MBH_OK) return fail_free(s);
   d->bytes += sizeof(double);
   const int nb = grid_blocks(n, 2048);
   double *part = nullptr;
   if ((s = ctx_alloc_async(ctx, (void **)&part, nb * sizeof(double), st)) != MBH_OK) return fail_free(s);
-  hipLaunchKernelGGL(k_whiten, dim3(nb), dim3(kBlock), 0, st, d_reim_dev, psd_dev, n, df, d->dw64, d->sw64,
-                     d->dw32, d->sw32, part);
+  hipLaunchKernelGGL(k_whiten, dim3(nb), dim3(kBlock), 0, st, d_reim_dev, psd_dev, n, df, d->dw64, d->sw64, part);
   hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, st, part, nb, 1, 1, d->dd_dev);
   ctx_free_async(ctx, part, nb * sizeof(double), st);
   hipError_t e = hipGetLastError();
@@ -278,8 +273,6 @@ extern "C" mbh_status mbh_data_release(mbh_data *d) {
   (void)hipDeviceSynchronize();
   ctx_free(d->ctx, d->dw64, d->n_chan * d->n_f * sizeof(double2));
   ctx_free(d->ctx, d->sw64, d->n_chan * d->n_f * sizeof(double));
-  ctx_free(d->ctx, d->dw32, d->n_chan * d->n_f * sizeof(float2));
-  ctx_free(d->ctx, d->sw32, d->n_chan * d->n_f * sizeof(float));
   ctx_free(d->ctx, d->dd_dev, sizeof(double));
   if (d->ready) (void)hipEventDestroy(d->ready);
   delete d;
@@ -1487,37 +1480,73 @@ extern "C" mbh_status mbh_loglike_heterodyned_noalloc(mbh_ctx *ctx, const mbh_re
 }
 
 // ---------------------------------------------------------------- full grid
-template <typename R, bool DH, bool HM>
+// Tile of the full-grid pass: KF frequencies per thread (1 or 2) and at most
+// wpb_cap walkers per workgroup.  Walker rows are sized so that the grid
+// keeps >= ~8 workgroups per CU in total and runs as many short rounds of
+// resident workgroups (a long-running last round leaves most of the chip
+// idle); the per-(chunk, walker) partials, and so the results, do not depend
+// on the number of walkers per workgroup, only on KF (the chunking).  The
+// default (1, 32) measured fastest for the (2,2) mode on the 1-yr grid.
+struct FullShape {
+  int kf = 1, wpb_cap = 32;
+};
+
+static FullShape full_shape_of(const mbh_ctx *ctx, bool hm) {
+  std::lock_guard<std::mutex> g(ctx->mu);
+  auto it = ctx->full_shape.find(hm ? 1 : 0);
+  FullShape f;
+  if (it != ctx->full_shape.end()) {
+    f.kf = it->second.first;
+    f.wpb_cap = it->second.second;
+  }
+  return f;
+}
+
+static bool valid_full_shape(int kf, int wpb_cap) {
+  return (kf == 1 || kf == 2) && (wpb_cap == 8 || wpb_cap == 16 || wpb_cap == 32 || wpb_cap == 64 || wpb_cap == 128);
+}
+
+template <int KF, bool DH, bool HM>
 static mbh_status full_impl(mbh_ctx *ctx, const mbh_data *d, uint32_t modes, const WalkerC *wc, int64_t W,
-                            double *lnL, double *dhhh, hipStream_t st, Scratch &sc) {
-  constexpr int KF = 2;
+                            int wpb_cap, double *lnL, double *dhhh, hipStream_t st, Scratch &sc) {
   const int64_t fpb = (int64_t)kBlock * KF;
   const int64_t n_fc = (d->n_f + fpb - 1) / fpb;
-  if (n_fc > 65535 * 32) return mbh_fail(MBH_EINVAL, "grid too large");
-  // walkers per block: keep >= ~4 blocks per CU in total, and at most 32 per
-  // block, so that the grid runs as many short rounds of resident workgroups
-  // (a long-running last round left most of the chip idle: 14 % slower with
-  // one block per frequency chunk on the 1-yr grid); the per-(chunk, walker)
-  // partials, and so the results, do not depend on the split
-  int64_t target = (int64_t)ctx->n_cu * 8;
+  if (n_fc > 65535 * 64) return mbh_fail(MBH_EINVAL, "grid too large");
+  const int64_t target = (int64_t)ctx->n_cu * 8;
   int64_t n_wc = std::max<int64_t>(1, std::min<int64_t>(W, target / std::max<int64_t>(1, n_fc)));
-  int64_t wpb = std::min<int64_t>((W + n_wc - 1) / n_wc, 32);
+  int64_t wpb = std::min<int64_t>((W + n_wc - 1) / n_wc, wpb_cap);
   wpb = std::max<int64_t>(wpb, (W + 65534) / 65535);  // grid y at most 65535
   n_wc = (W + wpb - 1) / wpb;
   const int nv = DH ? 3 : 1;
   double *part = nullptr;
   MBH_TRY(sc.get(&part, (size_t)nv * n_fc * W));
-  dim3 grid((unsigned)n_fc, (unsigned)n_wc);
-  if constexpr (sizeof(R) == 8)
-    hipLaunchKernelGGL((k_full<double, KF, DH, HM>), grid, dim3(kBlock), 0, st, d->dw64, d->sw64, d->n_chan, d->n_f,
-                       d->f0, d->df, d->t_obs, modes, wc, W, (int)wpb, part);
-  else
-    hipLaunchKernelGGL((k_full<float, KF, DH, HM>), grid, dim3(kBlock), 0, st, d->dw32, d->sw32, d->n_chan, d->n_f,
-                       d->f0, d->df, d->t_obs, modes, wc, W, (int)wpb, part);
+  hipLaunchKernelGGL((k_full<KF, DH, HM>), dim3((unsigned)n_fc, (unsigned)n_wc), dim3(kBlock), 0, st, d->dw64,
+                     d->sw64, d->n_chan, d->n_f, d->f0, d->df, d->t_obs, modes, wc, W, (int)wpb, part);
   hipLaunchKernelGGL(k_full_reduce, dim3((unsigned)((W + kBlock / 64 - 1) / (kBlock / 64))), dim3(kBlock), 0, st,
-                     part, (int)n_fc, W, nv, wc, lnL, dhhh);
+                     part, (int)n_fc, W, nv, d->dd_dev, wc, lnL, dhhh);
   HIP_TRY(hipGetLastError());
   return MBH_OK;
+}
+
+template <bool DH, bool HM>
+static mbh_status full_kf(mbh_ctx *ctx, const mbh_data *d, uint32_t modes, const WalkerC *wc, int64_t W,
+                          FullShape f, double *lnL, double *dhhh, hipStream_t st, Scratch &sc) {
+  if (f.kf == 1) return full_impl<1, DH, HM>(ctx, d, modes, wc, W, f.wpb_cap, lnL, dhhh, st, sc);
+  return full_impl<2, DH, HM>(ctx, d, modes, wc, W, f.wpb_cap, lnL, dhhh, st, sc);
+}
+
+static mbh_status full_run(mbh_ctx *ctx, const mbh_data *d, int model, uint32_t modes, const double *theta_dev,
+                           int64_t W, const FullShape &f, double *lnL_dev, double *dh_hh_dev, hipStream_t st,
+                           Scratch &sc) {
+  WalkerC *wc = nullptr;
+  MBH_TRY(sc.get(&wc, (size_t)W));
+  const uint32_t m = model == MBH_MODEL_IMR ? modes : 0u;
+  hipLaunchKernelGGL(k_walker_setup, dim3((unsigned)((W + 63) / 64)), dim3(128), 0, st, theta_dev, W, model, m, wc);
+  if (modes_hm(model, m))
+    return dh_hh_dev ? full_kf<true, true>(ctx, d, m, wc, W, f, lnL_dev, dh_hh_dev, st, sc)
+                     : full_kf<false, true>(ctx, d, m, wc, W, f, lnL_dev, nullptr, st, sc);
+  return dh_hh_dev ? full_kf<true, false>(ctx, d, m, wc, W, f, lnL_dev, dh_hh_dev, st, sc)
+                   : full_kf<false, false>(ctx, d, m, wc, W, f, lnL_dev, nullptr, st, sc);
 }
 
 extern "C" mbh_status mbh_loglike_full(mbh_ctx *ctx, const mbh_data *data, int model, uint32_t modes,
@@ -1530,24 +1559,85 @@ extern "C" mbh_status mbh_loglike_full(mbh_ctx *ctx, const mbh_data *data, int m
   if (W == 0) return MBH_OK;
   HIP_TRY(hipSetDevice(ctx->device));
   Scratch sc(ctx, st);
-  WalkerC *wc = nullptr;
-  MBH_TRY(sc.get(&wc, (size_t)W));
-  hipLaunchKernelGGL(k_walker_setup, dim3((unsigned)((W + 63) / 64)), dim3(128), 0, st, theta_dev, W, model,
-                     model == MBH_MODEL_IMR ? modes : 0u, wc);
-  uint32_t m = model == MBH_MODEL_IMR ? modes : 0u;
+  const uint32_t m = model == MBH_MODEL_IMR ? modes : 0u;
+  return full_run(ctx, data, model, modes, theta_dev, W, full_shape_of(ctx, modes_hm(model, m)), lnL_dev, dh_hh_dev,
+                  st, sc);
+}
+
+extern "C" mbh_status mbh_set_full_shape(mbh_ctx *ctx, int higher_modes, int kf, int wpb_cap) {
+  if (!ctx) return mbh_fail(MBH_EINVAL, "null argument");
+  if (!valid_full_shape(kf, wpb_cap))
+    return mbh_fail(MBH_EINVAL, "tile (%d frequencies per thread, %d walkers) not supported", kf, wpb_cap);
+  std::lock_guard<std::mutex> g(ctx->mu);
+  ctx->full_shape[higher_modes ? 1 : 0] = std::make_pair(kf, wpb_cap);
+  return MBH_OK;
+}
+
+extern "C" mbh_status mbh_full_shape(const mbh_ctx *ctx, int higher_modes, int *kf_out, int *wpb_cap_out) {
+  if (!ctx) return mbh_fail(MBH_EINVAL, "null argument");
+  const FullShape f = full_shape_of(ctx, higher_modes != 0);
+  if (kf_out) *kf_out = f.kf;
+  if (wpb_cap_out) *wpb_cap_out = f.wpb_cap;
+  return MBH_OK;
+}
+
+extern "C" mbh_status mbh_autotune_full(mbh_ctx *ctx, const mbh_data *data, int model, uint32_t modes,
+                                        const double *theta_dev, int64_t W, int *kf_out, int *wpb_cap_out) {
+  if (!ctx || !data || !theta_dev || W < 1) return mbh_fail(MBH_EINVAL, "bad argument");
+  if (W > (int64_t)1 << 24) return mbh_fail(MBH_EINVAL, "W = %lld out of range", (long long)W);
+  MBH_TRY(check_model(data, model, modes));
+  HIP_TRY(hipSetDevice(ctx->device));
+  const uint32_t m = model == MBH_MODEL_IMR ? modes : 0u;
   const bool hm = modes_hm(model, m);
-  if (prec == MBH_FP64) {
-    if (hm)
-      return dh_hh_dev ? full_impl<double, true, true>(ctx, data, m, wc, W, lnL_dev, dh_hh_dev, st, sc)
-                       : full_impl<double, false, true>(ctx, data, m, wc, W, lnL_dev, nullptr, st, sc);
-    return dh_hh_dev ? full_impl<double, true, false>(ctx, data, m, wc, W, lnL_dev, dh_hh_dev, st, sc)
-                     : full_impl<double, false, false>(ctx, data, m, wc, W, lnL_dev, nullptr, st, sc);
+  hipStream_t st;
+  HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+  mbh_status rc = MBH_OK;
+  std::vector<std::pair<float, std::pair<int, int>>> res;
+  {
+    Scratch sc(ctx, st);
+    double *lnL = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if ((rc = sc.get(&lnL, (size_t)W)) == MBH_OK && hipEventCreate(&e0) == hipSuccess &&
+        hipEventCreate(&e1) == hipSuccess) {
+      for (int kf : {1, 2})
+        for (int cap : {8, 16, 32, 64, 128}) {
+          FullShape f;
+          f.kf = kf;
+          f.wpb_cap = cap;
+          // one untimed call, then the median of three
+          std::vector<float> t;
+          for (int r = 0; r < 4 && rc == MBH_OK; ++r) {
+            (void)hipEventRecord(e0, st);
+            Scratch s2(ctx, st);
+            rc = full_run(ctx, data, model, modes, theta_dev, W, f, lnL, nullptr, st, s2);
+            (void)hipEventRecord(e1, st);
+            (void)hipEventSynchronize(e1);
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (r > 0) t.push_back(ms);
+          }
+          if (rc != MBH_OK) break;
+          std::sort(t.begin(), t.end());
+          res.emplace_back(t[1], std::make_pair(kf, cap));
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (rc == MBH_OK && (hipGetLastError() != hipSuccess || res.empty()))
+      rc = mbh_fail(MBH_EDEVICE, "autotune launches failed");
   }
-  if (hm)
-    return dh_hh_dev ? full_impl<float, true, true>(ctx, data, m, wc, W, lnL_dev, dh_hh_dev, st, sc)
-                     : full_impl<float, false, true>(ctx, data, m, wc, W, lnL_dev, nullptr, st, sc);
-  return dh_hh_dev ? full_impl<float, true, false>(ctx, data, m, wc, W, lnL_dev, dh_hh_dev, st, sc)
-                   : full_impl<float, false, false>(ctx, data, m, wc, W, lnL_dev, nullptr, st, sc);
+  (void)hipStreamSynchronize(st);
+  (void)hipStreamDestroy(st);
+  if (rc != MBH_OK) return rc;
+  std::sort(res.begin(), res.end());
+  const auto best = res.front().second;
+  {
+    std::lock_guard<std::mutex> g(ctx->mu);
+    ctx->full_shape[hm ? 1 : 0] = best;
+  }
+  if (kf_out) *kf_out = best.first;
+  if (wpb_cap_out) *wpb_cap_out = best.second;
+  return MBH_OK;
 }
 
 // ---------------------------------------------------------------- autotuner
@@ -1657,7 +1747,9 @@ extern "C" mbh_status mbh_autotune_heterodyned(mbh_ctx *ctx, const mbh_ref *ref,
   return rc;
 }
 
-// cache file: one line per entry "arch n_bins n_modes prec lanes"
+// cache file: one line per entry, "arch n_bins n_modes prec lanes" for the
+// heterodyned mapping and "arch full higher_modes kf wpb_cap" for the
+// full-grid tile
 extern "C" mbh_status mbh_autotune_save(const mbh_ctx *ctx, const char *path) {
   if (!ctx || !path) return mbh_fail(MBH_EINVAL, "null argument");
   FILE *f = fopen(path, "w");
@@ -1666,6 +1758,8 @@ extern "C" mbh_status mbh_autotune_save(const mbh_ctx *ctx, const char *path) {
   for (auto &kv : ctx->lanes)
     fprintf(f, "%s %d %d %d %d\n", ctx->arch.c_str(), std::get<0>(kv.first), std::get<1>(kv.first),
             std::get<2>(kv.first), kv.second);
+  for (auto &kv : ctx->full_shape)
+    fprintf(f, "%s full %d %d %d\n", ctx->arch.c_str(), kv.first, kv.second.first, kv.second.second);
   fclose(f);
   return MBH_OK;
 }
@@ -1674,13 +1768,22 @@ extern "C" mbh_status mbh_autotune_load(mbh_ctx *ctx, const char *path) {
   if (!ctx || !path) return mbh_fail(MBH_EINVAL, "null argument");
   FILE *f = fopen(path, "r");
   if (!f) return mbh_fail(MBH_EINVAL, "cannot read %s", path);
-  char arch[128];
-  int nb, nm, pr, g;
+  char line[256], arch[128];
+  int a, b, c, d;
   std::lock_guard<std::mutex> lk(ctx->mu);
-  while (fscanf(f, "%127s %d %d %d %d", arch, &nb, &nm, &pr, &g) == 5) {
+  while (fgets(line, sizeof line, f)) {
+    bool full = false;
+    if (sscanf(line, "%127s full %d %d %d", arch, &a, &b, &c) == 4)
+      full = true;
+    else if (sscanf(line, "%127s %d %d %d %d", arch, &a, &b, &c, &d) != 5)
+      continue;
     // entries measured on another architecture are ignored
-    if (ctx->arch.rfind(arch, 0) == 0 || std::string(arch).rfind(ctx->arch, 0) == 0)
-      if (valid_lanes(g)) ctx->lanes[std::make_tuple(nb, nm, pr)] = g;
+    if (!(ctx->arch.rfind(arch, 0) == 0 || std::string(arch).rfind(ctx->arch, 0) == 0)) continue;
+    if (full) {
+      if ((a == 0 || a == 1) && valid_full_shape(b, c)) ctx->full_shape[a] = std::make_pair(b, c);
+    } else if (valid_lanes(d)) {
+      ctx->lanes[std::make_tuple(a, b, c)] = d;
+    }
   }
   fclose(f);
   return MBH_OK;

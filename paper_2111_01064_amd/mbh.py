@@ -122,6 +122,9 @@ _SIGS = {
     "mbh_set_lanes": [_vp, _i32, _i32, _i32, _i32],
     "mbh_set_mixed_tolerance": [_vp, _d],
     "mbh_get_mixed_tolerance": [_vp, _dp],
+    "mbh_set_full_shape": [_vp, _i32, _i32, _i32],
+    "mbh_full_shape": [_vp, _i32, ct.POINTER(ct.c_int), ct.POINTER(ct.c_int)],
+    "mbh_autotune_full": [_vp, _vp, _i32, _u32, _vp, _i64, ct.POINTER(ct.c_int), ct.POINTER(ct.c_int)],
     "mbh_autotune_save": [_vp, ct.c_char_p],
     "mbh_autotune_load": [_vp, ct.c_char_p],
     "mbh_server_create": [_vp, _i32, _pp, ct.POINTER(ServerConfig), _pp],
@@ -435,6 +438,28 @@ def autotune_heterodyned(ctx: Context, ref: Reference, walkers, prec: int) -> in
         ptr = _dev_ptr(walkers, torch.float64, (W, NPARAM))
     _check(_L.mbh_autotune_heterodyned(ctx.h, ref.h, ptr, W, prec, ct.byref(v)), "mbh_autotune_heterodyned")
     return v.value
+
+
+def set_full_shape(ctx: Context, higher_modes: bool, kf: int, wpb_cap: int):
+    """Full-grid tile: kf frequencies per thread, at most wpb_cap walkers per workgroup."""
+    _check(_L.mbh_set_full_shape(ctx.h, int(bool(higher_modes)), kf, wpb_cap), "mbh_set_full_shape")
+
+
+def full_shape(ctx: Context, higher_modes: bool) -> tuple[int, int]:
+    kf, cap = ct.c_int(), ct.c_int()
+    _check(_L.mbh_full_shape(ctx.h, int(bool(higher_modes)), ct.byref(kf), ct.byref(cap)), "mbh_full_shape")
+    return kf.value, cap.value
+
+
+def autotune_full(ctx: Context, data: Data, model: int, modes: int, theta: torch.Tensor) -> tuple[int, int]:
+    """Time every full-grid tile on the walkers ``theta`` ([W, 11] float64,
+    CUDA); records and returns the fastest (frequencies per thread, walkers
+    per workgroup at most)."""
+    W = theta.shape[0]
+    kf, cap = ct.c_int(), ct.c_int()
+    _check(_L.mbh_autotune_full(ctx.h, data.h, model, modes, _dev_ptr(theta, torch.float64, (W, NPARAM)), W,
+                                ct.byref(kf), ct.byref(cap)), "mbh_autotune_full")
+    return kf.value, cap.value
 
 
 def autotune_save(ctx: Context, path: str):
