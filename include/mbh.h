@@ -464,6 +464,8 @@ typedef struct {
   uint64_t max_walkers_in_flight;
   uint64_t max_bytes_in_flight;
   uint64_t admission_waits; /* times the scheduler held work back for budget/slots */
+  double host_build_s;      /* scheduler thread: building work lists and issuing launches */
+  double host_complete_s;   /* scheduler thread: copying results out */
 } mbh_server_stats;
 mbh_status mbh_server_get_stats(const mbh_server *srv, mbh_server_stats *out);
 mbh_status mbh_server_destroy(mbh_server *srv);

@@ -107,18 +107,31 @@ struct TileGroup {
   int64_t begin, count;
 };
 
+// The tiles arrive as runs (consecutive tiles of one item and one kernel,
+// equal cost): the runs are stably sorted, which orders the tiles exactly as
+// a stable sort of the tiles themselves would, at the cost of sorting the
+// runs only.
 static std::vector<TileGroup> order_tiles(std::vector<WorkTile> &tiles, const std::vector<double> &cost,
                                           const WorkItem *items) {
-  std::vector<size_t> idx(tiles.size());
-  for (size_t i = 0; i < idx.size(); ++i) idx[i] = i;
-  auto hm = [&](size_t i) { return items[tiles[i].item].hm; };
-  std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) {
-    if (tiles[a].G != tiles[b].G) return tiles[a].G < tiles[b].G;
+  struct Run {
+    int64_t begin, count;
+  };
+  std::vector<Run> runs;
+  for (size_t i = 0; i < tiles.size(); ++i) {
+    if (i == 0 || tiles[i].item != tiles[i - 1].item || tiles[i].G != tiles[i - 1].G || cost[i] != cost[i - 1])
+      runs.push_back(Run{(int64_t)i, 0});
+    runs.back().count += 1;
+  }
+  auto hm = [&](const Run &r) { return items[tiles[r.begin].item].hm; };
+  std::stable_sort(runs.begin(), runs.end(), [&](const Run &a, const Run &b) {
+    const WorkTile &ta = tiles[a.begin], &tb = tiles[b.begin];
+    if (ta.G != tb.G) return ta.G < tb.G;
     if (hm(a) != hm(b)) return hm(a) < hm(b);
-    return cost[a] > cost[b];
+    return cost[a.begin] > cost[b.begin];
   });
-  std::vector<WorkTile> out(tiles.size());
-  for (size_t i = 0; i < idx.size(); ++i) out[i] = tiles[idx[i]];
+  std::vector<WorkTile> out;
+  out.reserve(tiles.size());
+  for (const Run &r : runs) out.insert(out.end(), tiles.begin() + r.begin, tiles.begin() + r.begin + r.count);
   tiles.swap(out);
   std::vector<TileGroup> groups;
   for (size_t i = 0; i < tiles.size(); ++i) {
@@ -139,41 +152,60 @@ static std::vector<TileGroup> order_tiles(std::vector<WorkTile> &tiles, const st
 // colours in turn, and the flattened main-pass tiles, kept in their order
 // within each XCD, are dealt to the XCD of their first walker's setup tile.
 // Results do not depend on the order (each walker's partial slots are fixed).
+// Dealing: position p takes the next element of colour p mod 8, or of the
+// next colour (cyclically) that still has elements; the colour classes are
+// formed by a counting sort.
 constexpr int kXcds = 8;
+template <typename T>
+static void deal_by_colour(const std::vector<T> &in, const std::vector<uint8_t> &colour, T *out,
+                           std::vector<int64_t> *out_colour_of_in = nullptr) {
+  const int64_t n = (int64_t)in.size();
+  int64_t cnt[kXcds] = {0}, head[kXcds], end[kXcds];
+  for (int64_t k = 0; k < n; ++k) cnt[colour[k]] += 1;
+  std::vector<int64_t> order((size_t)n);
+  int64_t off = 0;
+  for (int c = 0; c < kXcds; ++c) {
+    head[c] = off;
+    off += cnt[c];
+    end[c] = off;
+  }
+  {
+    int64_t fill[kXcds];
+    for (int c = 0; c < kXcds; ++c) fill[c] = head[c];
+    for (int64_t k = 0; k < n; ++k) order[(size_t)fill[colour[k]]++] = k;
+  }
+  for (int64_t pos = 0; pos < n; ++pos) {
+    int c = (int)(pos % kXcds);
+    while (head[c] == end[c]) c = (c + 1) % kXcds;
+    const int64_t k = order[(size_t)head[c]++];
+    out[pos] = in[(size_t)k];
+    if (out_colour_of_in) (*out_colour_of_in)[(size_t)k] = pos % kXcds;
+  }
+}
+
 static void xcd_align(std::vector<WorkTile> &tiles, const std::vector<TileGroup> &groups,
                       std::vector<WalkerTile> &wtiles, const WorkItem *items, int n_items) {
   std::vector<int64_t> wt_first(n_items + 1, 0);
   for (int i = 0; i < n_items; ++i) wt_first[i + 1] = wt_first[i] + (items[i].W + kWalkerTile - 1) / kWalkerTile;
-  std::vector<std::deque<size_t>> cq(kXcds);
+  std::vector<uint8_t> colour(wtiles.size());
   for (size_t k = 0; k < wtiles.size(); ++k) {
     const int i = wtiles[k].item;
-    cq[(size_t)((i + ((int64_t)k - wt_first[i])) % kXcds)].push_back(k);
+    colour[k] = (uint8_t)((i + ((int64_t)k - wt_first[i])) % kXcds);
   }
   std::vector<WalkerTile> wt2(wtiles.size());
-  std::vector<int> xcd_of(wtiles.size());
-  for (size_t pos = 0; pos < wtiles.size(); ++pos) {
-    size_t c = pos % kXcds;
-    while (cq[c].empty()) c = (c + 1) % kXcds;
-    const size_t k = cq[c].front();
-    cq[c].pop_front();
-    wt2[pos] = wtiles[k];
-    xcd_of[k] = (int)(pos % kXcds);
-  }
+  std::vector<int64_t> xcd_of(wtiles.size());
+  deal_by_colour(wtiles, colour, wt2.data(), &xcd_of);
   wtiles.swap(wt2);
   for (const auto &g : groups) {
     if (g.G != 0) continue;
-    std::vector<std::deque<WorkTile>> q(kXcds);
-    for (int64_t i = g.begin; i < g.begin + g.count; ++i) {
-      const WorkTile &t = tiles[i];
+    std::vector<WorkTile> in(tiles.begin() + g.begin, tiles.begin() + g.begin + g.count);
+    std::vector<uint8_t> col((size_t)g.count);
+    for (int64_t i = 0; i < g.count; ++i) {
+      const WorkTile &t = in[(size_t)i];
       const int64_t w = (t.begin * kChunk) / items[t.item].E;
-      q[xcd_of[wt_first[t.item] + w / kWalkerTile]].push_back(t);
+      col[(size_t)i] = (uint8_t)xcd_of[(size_t)(wt_first[t.item] + w / kWalkerTile)];
     }
-    for (int64_t pos = 0; pos < g.count; ++pos) {
-      int k = (int)(pos % kXcds);
-      while (q[k].empty()) k = (k + 1) % kXcds;
-      tiles[g.begin + pos] = q[k].front();
-      q[k].pop_front();
-    }
+    deal_by_colour(in, col, tiles.data() + g.begin);
   }
 }
 
@@ -435,6 +467,10 @@ struct Slot {
   std::vector<std::pair<std::shared_ptr<Request>, int64_t>> members;  // request, first walker in the slot
   int64_t walkers = 0;
   std::vector<TileGroup> groups;
+  // work-list scratch, kept between batches
+  std::vector<WorkTile> tiles;
+  std::vector<WalkerTile> wtiles;
+  std::vector<double> cost;
   bool busy = false;
 };
 }  // namespace
@@ -482,52 +518,62 @@ static void server_free(mbh_server *s) {
   delete s;
 }
 
-// pack queued requests into a free slot (FIFO, as walker capacity allows)
-static bool server_pack(mbh_server *s, Slot &sl) {
+// Take queued requests for a free slot (FIFO, as walker, item and tile
+// capacity allow); called with the server lock held.  Only the membership is
+// decided here: the work list is built by server_build without the lock.
+static bool server_take(mbh_server *s, Slot &sl) {
   sl.members.clear();
   sl.walkers = 0;
   int n_items = 0;
   int64_t n_tiles = 0;
-  std::vector<WorkTile> tiles;
-  std::vector<WalkerTile> wtiles;
-  std::vector<double> cost;
   while (!s->queue.empty()) {
     auto &r = s->queue.front();
     if (r->data) break;  // a reference update: later requests go after it
     const mbh_ref *ref = s->refs[r->ref];
-    const int G = item_lanes(s->ctx, ref, s->cfg.prec);
-    const int64_t nt = tiles_of(G, r->W, ref->n_bins + 1);
+    const int64_t nt = tiles_of(item_lanes(s->ctx, ref, s->cfg.prec), r->W, ref->n_bins + 1);
     if (sl.walkers + r->W > s->cap_walkers || n_items + 1 > s->max_items || n_tiles + nt > s->max_tiles) break;
-    WorkItem &it = sl.items_h[n_items];
-    it = make_item(s->ctx, ref, G);
-    it.theta = sl.theta_d + sl.walkers * 11;
-    it.wc = sl.wc_d + sl.walkers;
-    it.part = sl.part_d + sl.walkers * s->Kmax * 4;
-    it.W = r->W;
-    it.offset = sl.walkers;
-    std::memcpy(sl.theta_h + sl.walkers * 11, r->theta.data(), r->W * 11 * sizeof(double));
-    append_tiles(tiles, cost, n_items, ref, G, r->W);
     n_tiles += nt;
     sl.members.emplace_back(r, sl.walkers);
     sl.walkers += r->W;
     ++n_items;
     s->queue.pop_front();
   }
-  if (n_items == 0) return false;
-  // results of item i: lnL at res_d + 3 off (W entries), then dh/hh pairs after the lnL block
+  return n_items > 0;
+}
+
+// Work list of a slot's requests (items, main-pass tiles, walker tiles,
+// parameters in the pinned staging buffer); no lock needed: the slot and its
+// requests' inputs belong to the server thread until the results are out.
+static void server_build(mbh_server *s, Slot &sl) {
+  sl.tiles.clear();
+  sl.cost.clear();
+  sl.wtiles.clear();
+  const int n_items = (int)sl.members.size();
   for (int i = 0; i < n_items; ++i) {
+    const Request &r = *sl.members[i].first;
+    const int64_t off = sl.members[i].second;
+    const mbh_ref *ref = s->refs[r.ref];
+    const int G = item_lanes(s->ctx, ref, s->cfg.prec);
     WorkItem &it = sl.items_h[i];
-    it.lnL = sl.res_d + it.offset;
-    it.dhhh = sl.res_d + sl.walkers + 2 * it.offset;
+    it = make_item(s->ctx, ref, G);
+    it.theta = sl.theta_d + off * 11;
+    it.wc = sl.wc_d + off;
+    it.part = sl.part_d + off * s->Kmax * 4;
+    it.W = r.W;
+    it.offset = off;
+    // results of item i: lnL at res_d + off (W entries), then dh/hh pairs after the lnL block
+    it.lnL = sl.res_d + off;
+    it.dhhh = sl.res_d + sl.walkers + 2 * off;
+    std::memcpy(sl.theta_h + off * 11, r.theta.data(), r.W * 11 * sizeof(double));
+    append_tiles(sl.tiles, sl.cost, i, ref, G, r.W);
   }
-  sl.groups = order_tiles(tiles, cost, sl.items_h);
-  for (int i = 0; i < n_items; ++i) append_wtiles(wtiles, i, sl.items_h[i].W);
-  xcd_align(tiles, sl.groups, wtiles, sl.items_h, n_items);
-  std::memcpy(sl.tiles_h, tiles.data(), tiles.size() * sizeof(WorkTile));
-  std::memcpy(sl.wtiles_h, wtiles.data(), wtiles.size() * sizeof(WalkerTile));
-  sl.n_wtiles = (int64_t)wtiles.size();
-  *sl.hdr_h = WorkHeader{n_items, (int32_t)tiles.size(), sl.walkers};
-  return true;
+  sl.groups = order_tiles(sl.tiles, sl.cost, sl.items_h);
+  for (int i = 0; i < n_items; ++i) append_wtiles(sl.wtiles, i, sl.items_h[i].W);
+  xcd_align(sl.tiles, sl.groups, sl.wtiles, sl.items_h, n_items);
+  std::memcpy(sl.tiles_h, sl.tiles.data(), sl.tiles.size() * sizeof(WorkTile));
+  std::memcpy(sl.wtiles_h, sl.wtiles.data(), sl.wtiles.size() * sizeof(WalkerTile));
+  sl.n_wtiles = (int64_t)sl.wtiles.size();
+  *sl.hdr_h = WorkHeader{n_items, (int32_t)sl.tiles.size(), sl.walkers};
 }
 
 static bool server_launch(mbh_server *s, Slot &sl) {
@@ -546,15 +592,25 @@ static bool server_launch(mbh_server *s, Slot &sl) {
   return ok;
 }
 
-static void server_complete(mbh_server *s, Slot &sl) {
+// results of a finished batch into its requests' buffers (sized at submit);
+// no lock: nobody reads them before server_publish marks the requests done
+static void server_copy_results(Slot &sl) {
   const double *lnL = sl.res_h;
   const double *dh = sl.res_h + sl.walkers;
-  auto now = Clock::now();
+  for (auto &m : sl.members) {
+    Request &r = *m.first;
+    if (r.data) continue;
+    std::memcpy(r.lnL.data(), lnL + m.second, r.W * sizeof(double));
+    std::memcpy(r.dhhh.data(), dh + 2 * m.second, r.W * 2 * sizeof(double));
+  }
+}
+
+// mark a finished slot's requests done (lock held)
+static void server_publish(mbh_server *s, Slot &sl) {
+  const auto now = Clock::now();
   for (auto &m : sl.members) {
     Request &r = *m.first;
     if (r.data) s->updates_in_flight -= 1;  // the update has finished
-    r.lnL.assign(lnL + m.second, lnL + m.second + r.W);
-    r.dhhh.assign(dh + 2 * m.second, dh + 2 * (m.second + r.W));
     r.t_done = now;
     r.done = true;
   }
@@ -565,13 +621,31 @@ static void server_complete(mbh_server *s, Slot &sl) {
   sl.busy = false;
 }
 
-// Issue the reference update at the head of the queue on free slot sl:
-// ordered after every batch in flight (their events) and before every later
-// batch (the barrier event).
-static bool server_issue_update(mbh_server *s, Slot &sl, const std::shared_ptr<Request> &r) {
+// a slot whose launch or update could not be issued (lock held): its work
+// already enqueued has finished (the caller synchronised the slot's stream)
+static void server_fail_slot(mbh_server *s, Slot &sl, const char *what) {
+  s->thread_error = what;
+  const auto now = Clock::now();
+  for (auto &m : sl.members) {
+    if (m.first->data) s->updates_in_flight -= 1;
+    m.first->t_done = now;
+    m.first->failed = true;
+    m.first->done = true;
+  }
+  s->walkers_in_flight -= sl.walkers;
+  s->bytes_in_flight -= (size_t)sl.walkers * s->bytes_per_walker;
+  sl.members.clear();
+  sl.busy = false;
+  s->cv_done.notify_all();
+}
+
+// Issue the reference update held by slot sl: ordered after every batch in
+// flight (their events) and before every later batch (the barrier event).
+static bool server_issue_update(mbh_server *s, Slot &sl) {
+  const std::shared_ptr<Request> &r = sl.members.front().first;
   hipStream_t st = sl.st;
   for (auto &o : s->slots)
-    if (o.busy && hipStreamWaitEvent(st, o.ev, 0) != hipSuccess) return false;
+    if (&o != &sl && o.busy && hipStreamWaitEvent(st, o.ev, 0) != hipSuccess) return false;
   const int64_t W = r->W_update;
   std::memcpy(sl.theta_h, r->theta.data(), W * 11 * sizeof(double));
   std::memcpy(sl.res_h, r->lnL_in.data(), W * sizeof(double));
@@ -583,88 +657,79 @@ static bool server_issue_update(mbh_server *s, Slot &sl, const std::shared_ptr<R
   return hipEventRecord(s->barrier, st) == hipSuccess && hipEventRecord(sl.ev, st) == hipSuccess;
 }
 
+// The scheduler thread.  Slot state, staging buffers and the in-flight
+// update count belong to this thread; the queue, request flags and
+// statistics are shared under s->mu, which is held only to retire finished
+// batches, to take queued work and to record failures.  Building the work
+// lists, copying parameters and results and issuing launches run without
+// it, so submitting and waiting threads are not held up by them.
 static void server_loop(mbh_server *s) {
   (void)hipSetDevice(s->ctx->device);
-  std::unique_lock<std::mutex> lk(s->mu);
+  using Sec = std::chrono::duration<double>;
+  std::vector<Slot *> finished, filled;
   while (!s->stop.load()) {
-    bool progressed = false;
-    // 1. retire finished batches
-    for (auto &sl : s->slots) {
-      if (sl.busy && hipEventQuery(sl.ev) == hipSuccess) {
-        server_complete(s, sl);
-        progressed = true;
-      }
-    }
-    if (progressed) s->cv_done.notify_all();
-    // 2. admit queued work into free slots (continuous batching)
-    for (auto &sl : s->slots) {
-      if (sl.busy || s->queue.empty()) continue;
-      if (s->queue.front()->data) {
-        std::shared_ptr<Request> r = s->queue.front();
-        s->queue.pop_front();
-        sl.members.clear();
-        sl.members.emplace_back(r, 0);
-        sl.walkers = 0;
-        sl.busy = true;
-        s->updates_in_flight += 1;
-        s->stats.batches += 1;
-        lk.unlock();
-        bool ok = server_issue_update(s, sl, r);
-        if (!ok) (void)hipStreamSynchronize(sl.st);  // work already enqueued finishes before the slot is reused
-        lk.lock();
-        if (!ok) {
-          s->thread_error = "reference update failed";
-          r->t_done = Clock::now();
-          r->failed = true;
-          r->done = true;
+    // 1. finished batches: results out without the lock
+    finished.clear();
+    for (auto &sl : s->slots)
+      if (sl.busy && hipEventQuery(sl.ev) == hipSuccess) finished.push_back(&sl);
+    const auto t0 = Clock::now();
+    for (Slot *sl : finished) server_copy_results(*sl);
+    const auto t1 = Clock::now();
+    // 2. retire them and take queued work for the free slots
+    filled.clear();
+    bool any_busy = false;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->stats.host_complete_s += Sec(t1 - t0).count();
+      for (Slot *sl : finished) server_publish(s, *sl);
+      if (!finished.empty()) s->cv_done.notify_all();
+      for (auto &sl : s->slots) {
+        if (sl.busy || s->queue.empty()) continue;
+        if (s->queue.front()->data) {
           sl.members.clear();
-          sl.busy = false;
-          s->updates_in_flight -= 1;
-          s->cv_done.notify_all();
+          sl.members.emplace_back(s->queue.front(), 0);
+          s->queue.pop_front();
+          sl.walkers = 0;
+        } else if (!server_take(s, sl)) {
+          continue;
+        } else {
+          s->walkers_in_flight += sl.walkers;
+          s->bytes_in_flight += (size_t)sl.walkers * s->bytes_per_walker;
+          s->stats.max_walkers_in_flight = std::max<uint64_t>(s->stats.max_walkers_in_flight, s->walkers_in_flight);
+          s->stats.max_bytes_in_flight = std::max<uint64_t>(s->stats.max_bytes_in_flight, s->bytes_in_flight);
+          s->stats.walkers += sl.walkers;
         }
-        progressed = true;
+        s->stats.batches += 1;
+        sl.busy = true;
+        filled.push_back(&sl);
+      }
+      for (auto &sl : s->slots) any_busy |= sl.busy;
+      if (!s->queue.empty() && filled.empty()) s->stats.admission_waits += 1;
+      if (finished.empty() && filled.empty() && !any_busy) {
+        s->cv_work.wait_for(lk, std::chrono::milliseconds(50));
         continue;
       }
-      if (!server_pack(s, sl)) continue;
-      sl.busy = true;
-      s->walkers_in_flight += sl.walkers;
-      s->bytes_in_flight += (size_t)sl.walkers * s->bytes_per_walker;
-      s->stats.max_walkers_in_flight = std::max<uint64_t>(s->stats.max_walkers_in_flight, s->walkers_in_flight);
-      s->stats.max_bytes_in_flight = std::max<uint64_t>(s->stats.max_bytes_in_flight, s->bytes_in_flight);
-      s->stats.batches += 1;
-      s->stats.walkers += sl.walkers;
-      lk.unlock();
-      bool ok = server_launch(s, sl);
-      if (!ok) (void)hipStreamSynchronize(sl.st);  // copies already enqueued finish before the slot is reused
-      lk.lock();
-      if (!ok) {
-        s->thread_error = "launch failed";
-        const auto now = Clock::now();
-        for (auto &m : sl.members) {
-          m.first->t_done = now;
-          m.first->failed = true;
-          m.first->done = true;
-        }
-        s->walkers_in_flight -= sl.walkers;
-        s->bytes_in_flight -= (size_t)sl.walkers * s->bytes_per_walker;
-        sl.members.clear();
-        sl.busy = false;
-        s->cv_done.notify_all();
+    }
+    // 3. build and issue the filled slots without the lock
+    for (Slot *sl : filled) {
+      const bool update = sl->members.front().first->data != nullptr;
+      const auto b0 = Clock::now();
+      bool ok;
+      if (update) {
+        s->updates_in_flight += 1;
+        ok = server_issue_update(s, *sl);
+      } else {
+        server_build(s, *sl);
+        ok = server_launch(s, *sl);
       }
-      progressed = true;
+      const auto b1 = Clock::now();
+      if (!ok) (void)hipStreamSynchronize(sl->st);  // work already enqueued finishes before the slot is reused
+      std::lock_guard<std::mutex> g(s->mu);
+      s->stats.host_build_s += Sec(b1 - b0).count();
+      if (!ok) server_fail_slot(s, *sl, update ? "reference update failed" : "launch failed");
     }
-    bool any_busy = false;
-    for (auto &sl : s->slots) any_busy |= sl.busy;
-    if (!s->queue.empty() && !progressed) s->stats.admission_waits += 1;
-    if (progressed) continue;
-    if (any_busy) {
-      // poll the oldest batch without holding the lock
-      lk.unlock();
-      std::this_thread::yield();
-      lk.lock();
-    } else {
-      s->cv_work.wait_for(lk, std::chrono::milliseconds(50));
-    }
+    // 4. nothing changed: let the submitting and waiting threads run
+    if (finished.empty() && filled.empty()) std::this_thread::yield();
   }
 }
 
@@ -760,6 +825,8 @@ extern "C" mbh_status mbh_server_submit(mbh_server *s, int ref_index, const doub
   r->ref = ref_index;
   r->W = W;
   r->theta.assign(theta_host, theta_host + W * 11);
+  r->lnL.resize(W);
+  r->dhhh.resize(2 * W);
   r->t_submit = Clock::now();
   {
     std::lock_guard<std::mutex> g(s->mu);

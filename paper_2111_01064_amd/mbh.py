@@ -82,7 +82,8 @@ class SamplerReport(ct.Structure):
 class ServerStats(ct.Structure):
     _fields_ = [("submitted", ct.c_uint64), ("completed", ct.c_uint64), ("batches", ct.c_uint64),
                 ("walkers", ct.c_uint64), ("max_walkers_in_flight", ct.c_uint64),
-                ("max_bytes_in_flight", ct.c_uint64), ("admission_waits", ct.c_uint64)]
+                ("max_bytes_in_flight", ct.c_uint64), ("admission_waits", ct.c_uint64),
+                ("host_build_s", ct.c_double), ("host_complete_s", ct.c_double)]
 
 
 _vp, _dp, _i64, _u32, _i32, _d, _sz = ct.c_void_p, ct.POINTER(ct.c_double), ct.c_int64, ct.c_uint32, ct.c_int, ct.c_double, ct.c_size_t
