@@ -104,6 +104,33 @@ mbh_status mbh_data_release(mbh_data *data);
 /* <d|d> (synchronises the creation stream on first use). */
 mbh_status mbh_data_inner_dd(mbh_data *data, double *dd_out);
 
+/* TDI ingest (Sec. 2.1): the A, E, T frequency series of X, Y, Z time
+ * series.  A = (Z - X)/sqrt2, E = (X - 2Y + Z)/sqrt6, T = (X + Y + Z)/sqrt3
+ * (the combination the paper gives), each multiplied by a Tukey window
+ * (cosine tapers of alpha (N - 1) / 2 samples at either end; alpha = 0: no
+ * window) and Fourier transformed in the templates' convention:
+ *   out_c(f_k) = dt sum_n w_n c(t0 + n dt) e^{-2 pi i f_k (t0 + n dt)},
+ *   f_k = k / (N dt),  k = k_first .. k_first + n_freq - 1.
+ *   xyz_dev [3][N] FP64 on the device (X, then Y, then Z; sample n at time
+ *   t0 + n dt), caller-owned; aet_dev [3][n_freq][2] FP64 (re, im), the
+ *   layout mbh_data_create takes.
+ * Requires 4 <= N < 2^31, dt > 0, finite t0, 0 <= alpha <= 1, k_first >= 1,
+ * n_freq >= 2 and k_first + n_freq - 1 <= N / 2.  Allocates device scratch
+ * (~72 N bytes) and an FFT plan, and synchronises `stream` before it returns.
+ * Errors: MBH_EINVAL, MBH_ENOMEM, MBH_EDEVICE. */
+mbh_status mbh_tdi_to_aet_fd(mbh_ctx *ctx, int64_t n_samples, double dt, double t0,
+                             const double *xyz_dev, double tukey_alpha, int64_t k_first,
+                             int64_t n_freq, double *aet_dev, hipStream_t stream);
+/* Data handle straight from X, Y, Z time series: mbh_tdi_to_aet_fd on the
+ * band, then mbh_data_create on the grid f0 = k_first / (N dt),
+ * df = 1 / (N dt) with psd_dev [3][n_freq] (A, E, T PSDs on that grid).
+ * Synchronises `stream`; the caller may free its inputs on return.
+ * Errors: as mbh_tdi_to_aet_fd and mbh_data_create. */
+mbh_status mbh_data_create_tdi(mbh_ctx *ctx, int64_t n_samples, double dt, double t0,
+                               const double *xyz_dev, double tukey_alpha, int64_t k_first,
+                               int64_t n_freq, const double *psd_dev, double t_obs,
+                               hipStream_t stream, mbh_data **out);
+
 /* Template h^c(f_k) of one parameter vector on the data grid (eq. response
  * of Sec. 2.1), FP64, written to h_dev [n_chan][n_freq][2].  For synthetic
  * signal injection and tests.  Errors: MBH_EINVAL (incl. invalid theta). */

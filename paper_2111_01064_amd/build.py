@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmbh.so")
-SOURCES = ["mbh_lib.hip", "mbh_serve.hip", "mbh_sampler.hip"]
+SOURCES = ["mbh_lib.hip", "mbh_serve.hip", "mbh_sampler.hip", "mbh_ingest.hip"]
+LIBS = ["-lpthread", "-lhipfft"]
 ARCH = os.environ.get("MBH_OFFLOAD_ARCH", "gfx950")
 
 
@@ -22,7 +23,7 @@ def _flags():
 def hipcc_cmd(out: str = LIB, extra=()):
     """One hipcc line that compiles and links every source (for reference)."""
     return (["hipcc"] + _flags() + ["-shared", "-o", out]
-            + [os.path.join(CSRC, s) for s in SOURCES] + ["-lpthread"] + list(extra))
+            + [os.path.join(CSRC, s) for s in SOURCES] + LIBS + list(extra))
 
 
 def build(verbose: bool = False) -> str:
@@ -39,7 +40,7 @@ def build(verbose: bool = False) -> str:
         if p.wait() != 0:
             raise subprocess.CalledProcessError(p.returncode, cmd)
     tmp = LIB + ".tmp"
-    link = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-o", tmp] + objs + ["-lpthread"]
+    link = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-o", tmp] + objs + LIBS
     if verbose:
         print(" ".join(link), flush=True)
     subprocess.run(link, check=True)

@@ -95,6 +95,8 @@ _SIGS = {
     "mbh_data_create": [_vp, _i32, _i64, _d, _d, _d, _vp, _vp, _vp, _pp],
     "mbh_data_release": [_vp],
     "mbh_data_inner_dd": [_vp, _dp],
+    "mbh_tdi_to_aet_fd": [_vp, _i64, _d, _d, _vp, _d, _i64, _i64, _vp, _vp],
+    "mbh_data_create_tdi": [_vp, _i64, _d, _d, _vp, _d, _i64, _i64, _vp, _d, _vp, _pp],
     "mbh_template_full": [_vp, _vp, _i32, _u32, _dp, _vp, _vp],
     "mbh_build_reference_coeffs": [_vp, _vp, _i32, _u32, _dp, _i32, _vp, _pp],
     "mbh_ref_release": [_vp],
@@ -339,6 +341,28 @@ def data_create(ctx: Context, d: torch.Tensor, psd: torch.Tensor, f0: float, df:
                               _dev_ptr(psd, torch.float64, (C, N)), _stream(stream), ct.byref(h)),
            "mbh_data_create")
     return Data(ctx, h, C, N, f0, df, t_obs, keep=(d, psd))
+
+
+def tdi_to_aet_fd(ctx: Context, xyz: torch.Tensor, dt: float, t0: float, k_first: int, n_freq: int,
+                  alpha: float = 0.0, stream=None) -> torch.Tensor:
+    """mbh_tdi_to_aet_fd: xyz float64 [3][N] on the device -> complex128 [3][n_freq]."""
+    N = xyz.shape[1]
+    out = torch.empty((3, n_freq), dtype=torch.complex128, device=xyz.device)
+    _check(_L.mbh_tdi_to_aet_fd(ctx.h, N, dt, t0, _dev_ptr(xyz, torch.float64, (3, N)), alpha, k_first, n_freq,
+                                torch.view_as_real(out).data_ptr(), _stream(stream)), "mbh_tdi_to_aet_fd")
+    return out
+
+
+def data_create_tdi(ctx: Context, xyz: torch.Tensor, dt: float, t0: float, k_first: int, n_freq: int,
+                    psd: torch.Tensor, t_obs: float, alpha: float = 0.0, stream=None) -> Data:
+    """mbh_data_create_tdi: data on f_k = k / (N dt), k = k_first.., from X, Y, Z series."""
+    N = xyz.shape[1]
+    h = ct.c_void_p()
+    _check(_L.mbh_data_create_tdi(ctx.h, N, dt, t0, _dev_ptr(xyz, torch.float64, (3, N)), alpha, k_first, n_freq,
+                                  _dev_ptr(psd, torch.float64, (3, n_freq)), t_obs, _stream(stream), ct.byref(h)),
+           "mbh_data_create_tdi")
+    T = N * dt
+    return Data(ctx, h, 3, n_freq, k_first / T, 1.0 / T, t_obs, keep=(psd,))
 
 
 def template_full(ctx: Context, data: Data, model: int, modes: int, theta, stream=None) -> torch.Tensor:
