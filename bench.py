@@ -370,6 +370,9 @@ def main():
     ap.add_argument("--mapping", type=int, default=None,
                     help="fix the heterodyned mapping (0 = flattened, or lanes per walker) instead of autotuning; "
                          "for profiler runs, whose timings would mislead the autotuner")
+    ap.add_argument("--full-grid-only", type=int, default=0, metavar="DRAWS",
+                    help="time only the full-grid likelihood on this many prior draws of the first source "
+                         "(default tile, FP64; for profiler runs) and exit")
     ap.add_argument("--mixed-tol", type=float, default=None,
                     help="estimated-error tolerance of the mixed path (library default 9e-4; inf: no FP64 "
                          "recomputation, 0: everything in FP64)")
@@ -387,6 +390,19 @@ def main():
     if args.mixed_tol is not None:
         M.set_mixed_tolerance(ctx, args.mixed_tol)
     grid = I.grid_lisa()
+    if args.full_grid_only:
+        S = Sources(M, ctx, grid, 1)
+        draws = torch.as_tensor(I.prior_draws(I.rng_for(3, 0), args.full_grid_only, grid.t_obs), device="cuda")
+        M.loglike_full(ctx, S.items[0]["data"], M.MODEL_IMR, M.MODE_22, draws[:64], M.FP64)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            M.loglike_full(ctx, S.items[0]["data"], M.MODEL_IMR, M.MODE_22, draws, M.FP64)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        print(json.dumps({"metric": "full-grid lnL evals/s", "value": len(draws) / dt, "unit": "evals/s",
+                          "draws": len(draws), "shape": list(M.full_shape(ctx, False)), "steps": args.steps}))
+        return
     t0 = time.perf_counter()
     S = Sources(M, ctx, grid, N_SOURCES)
     log(f"[bench] built {N_SOURCES} sources on {grid.n_f} bins in {time.perf_counter() - t0:.1f} s")

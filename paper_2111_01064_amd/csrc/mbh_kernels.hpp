@@ -934,7 +934,8 @@ __global__ __launch_bounds__(kBlock, 2) void k_het_flat(WorkItem one, int64_t n_
 // Block (fc, wc): KF grid frequencies per thread kept in registers, then a
 // loop over the block's walkers (wave-uniform constants); per walker and
 // block one FP64 partial of sum (|h|^2 - 2 Re d* h) (and <d|h>, <h|h>).
-// part layout [NV][n_fchunks][W].
+// part layout [NV][W][n_fchunks] (a walker's partials contiguous for the
+// totals kernel).
 template <int KF, bool DH, bool HM>
 __global__ __launch_bounds__(kBlock, 2) void k_full(const double2 *__restrict__ dw, const double *__restrict__ sw,
                                                  int n_chan, int64_t n_f, double f0, double df, double t_obs,
@@ -1003,29 +1004,38 @@ __global__ __launch_bounds__(kBlock, 2) void k_full(const double2 *__restrict__ 
     block_sum<NV>(v, sh);
     if (threadIdx.x == 0)
 #pragma unroll
-      for (int i = 0; i < NV; ++i) part[((int64_t)i * n_fc + blockIdx.x) * W + w] = v[i];
+      for (int i = 0; i < NV; ++i) part[((int64_t)i * W + w) * n_fc + blockIdx.x] = v[i];
   }
 }
 
-// one wavefront per walker: lanes stride over the frequency chunks, fixed butterfly
+// Totals, one workgroup per walker: its threads stride over the walker's
+// contiguous chunk partials, then a fixed-order block sum (the result does
+// not depend on W or on the launch).
+template <int NV>
 static __global__ __launch_bounds__(kBlock) void k_full_reduce(const double *__restrict__ part, int n_fc, int64_t W,
-                                                               int nv, const double *__restrict__ dd,
+                                                               const double *__restrict__ dd,
                                                                const WalkerC *__restrict__ wc,
                                                                double *__restrict__ lnL, double *__restrict__ dhhh) {
-  const int64_t w = (int64_t)blockIdx.x * (kBlock / 64) + threadIdx.x / 64;
-  if (w >= W) return;
-  const int lane = threadIdx.x & 63;
-  double s[3] = {0.0, 0.0, 0.0};
-  for (int i = 0; i < nv; ++i) {
-    for (int fc = lane; fc < n_fc; fc += 64) s[i] += part[((int64_t)i * n_fc + fc) * W + w];
-    s[i] = wave_sum(s[i]);
+  __shared__ double sh[NV * (kBlock / 64)];
+  const int64_t w = blockIdx.x;
+  double s[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const double *p = part + ((int64_t)i * W + w) * n_fc;
+    double a = 0.0;
+#pragma unroll 8
+    for (int fc = threadIdx.x; fc < n_fc; fc += kBlock) a += p[fc];
+    s[i] = a;
   }
-  if (lane != 0) return;
+  block_sum<NV>(s, sh);
+  if (threadIdx.x != 0) return;
   const bool ok = wc[w].valid;
   lnL[w] = ok ? -0.5 * (*dd + s[0]) : -INFINITY;
-  if (dhhh) {
-    dhhh[2 * w] = ok ? s[1] : 0.0;
-    dhhh[2 * w + 1] = ok ? s[2] : 0.0;
+  if constexpr (NV == 3) {
+    if (dhhh) {
+      dhhh[2 * w] = ok ? s[1] : 0.0;
+      dhhh[2 * w + 1] = ok ? s[2] : 0.0;
+    }
   }
 }
 

@@ -1522,8 +1522,8 @@ static mbh_status full_impl(mbh_ctx *ctx, const mbh_data *d, uint32_t modes, con
   MBH_TRY(sc.get(&part, (size_t)nv * n_fc * W));
   hipLaunchKernelGGL((k_full<KF, DH, HM>), dim3((unsigned)n_fc, (unsigned)n_wc), dim3(kBlock), 0, st, d->dw64,
                      d->sw64, d->n_chan, d->n_f, d->f0, d->df, d->t_obs, modes, wc, W, (int)wpb, part);
-  hipLaunchKernelGGL(k_full_reduce, dim3((unsigned)((W + kBlock / 64 - 1) / (kBlock / 64))), dim3(kBlock), 0, st,
-                     part, (int)n_fc, W, nv, d->dd_dev, wc, lnL, dhhh);
+  hipLaunchKernelGGL((k_full_reduce<DH ? 3 : 1>), dim3((unsigned)W), dim3(kBlock), 0, st, part, (int)n_fc, W,
+                     d->dd_dev, wc, lnL, dhhh);
   HIP_TRY(hipGetLastError());
   return MBH_OK;
 }
