@@ -417,6 +417,33 @@ static void host_edges(double F0, double FN, int n_bins, std::vector<double> &ed
 }
 #pragma clang fp contract(on)
 
+// Byte offsets of several device arrays inside one scratch allocation
+// (each aligned to 256 bytes), so that a call makes one allocation.
+struct Carve {
+  size_t bytes = 0;
+  template <typename T>
+  size_t add(size_t n) {
+    bytes = (bytes + 255) & ~(size_t)255;
+    const size_t o = bytes;
+    bytes += std::max<size_t>(1, n) * sizeof(T);
+    return o;
+  }
+};
+
+// the walker's domain check as the gate of the grid pass: an invalid theta0
+// leaves the pass idle and is reported with the band
+static __global__ void k_valid_gate(const WalkerC *wc, RefMeta *gate) {
+  RefMeta m{};
+  m.status = wc[0].valid ? 0 : MBH_EINVAL;
+  m.pick = -1;
+  *gate = m;
+}
+
+// Host build: two synchronisations of `st`, one after the grid pass (the
+// band sets the edges, computed on the host in FP64 as the oracle does) and
+// one after the bin sums and coefficients (computed on the device by the
+// same kernel as a reference update), which also brings back the host
+// mirrors used by mbh_ref_export.
 extern "C" mbh_status mbh_build_reference_coeffs(mbh_ctx *ctx, const mbh_data *data_c, int model,
                                                  uint32_t modes, const double *theta0_host, int n_bins,
                                                  hipStream_t st, mbh_ref **out) {
@@ -428,37 +455,41 @@ extern "C" mbh_status mbh_build_reference_coeffs(mbh_ctx *ctx, const mbh_data *d
   HIP_TRY(hipSetDevice(ctx->device));
   const int C = data->n_chan, E = n_bins + 1;
   const int64_t N = data->n_f;
-  Scratch sc(ctx, st);
-  WalkerC *wc = nullptr;
-  bool valid = false;
-  MBH_TRY(setup_one(sc, theta0_host, model, modes, &wc, &valid));
-  if (!valid) return mbh_fail(MBH_EINVAL, "theta0 outside the model domain");
-
-  // pass 1: h0 on the grid, band, lnL(h0) pieces
-  double2 *h0w = nullptr;
-  MBH_TRY(sc.get(&h0w, (size_t)C * N));
-  unsigned long long *band = nullptr;
-  MBH_TRY(sc.get(&band, 2));
-  // one workgroup of four wavefronts per two SIMDs: the whole grid pass in a
-  const bool hm = modes_hm(model, modes);
+  const uint32_t m_modes = model == MBH_MODEL_IMR ? modes : 0u;
+  const bool hm = modes_hm(model, m_modes);
   const int nb1 = grid_blocks(N, resident_blocks(ctx, ref_grid_kernel(hm), kBlock));
-  double *part1 = nullptr, *sums1 = nullptr;
-  MBH_TRY(sc.get(&part1, (size_t)nb1 * 3));
-  MBH_TRY(sc.get(&sums1, 3));
+  Scratch sc(ctx, st);
+
+  // pass 1: walker constants, h0 on the grid, band, lnL(h0) pieces
+  Carve c1;
+  const size_t o_th = c1.add<double>(11), o_wc = c1.add<WalkerC>(1), o_gate = c1.add<RefMeta>(1),
+               o_band = c1.add<unsigned long long>(2), o_sums1 = c1.add<double>(3),
+               o_part1 = c1.add<double>((size_t)nb1 * 3), o_h0w = c1.add<double2>((size_t)C * N);
+  char *b1 = nullptr;
+  MBH_TRY(sc.get(&b1, c1.bytes));
+  double *th = (double *)(b1 + o_th), *sums1 = (double *)(b1 + o_sums1), *part1 = (double *)(b1 + o_part1);
+  WalkerC *wc = (WalkerC *)(b1 + o_wc);
+  RefMeta *gate = (RefMeta *)(b1 + o_gate);
+  unsigned long long *band = (unsigned long long *)(b1 + o_band);
+  double2 *h0w = (double2 *)(b1 + o_h0w);
+  HIP_TRY(hipMemcpyAsync(th, theta0_host, 11 * sizeof(double), hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(k_walker_setup, dim3(1), dim3(128), 0, st, th, (int64_t)1, model, m_modes, wc);
+  hipLaunchKernelGGL(k_valid_gate, dim3(1), dim3(1), 0, st, wc, gate);
   hipLaunchKernelGGL(k_init_band, dim3(1), dim3(1), 0, st, band);
   if (hm)
-    hipLaunchKernelGGL(k_ref_grid<true>, dim3(nb1), dim3(kBlock), 0, st, wc, modes, C, N, data->f0, data->df,
-                       data->t_obs, data->dw64, data->sw64, h0w, band, part1, nullptr);
+    hipLaunchKernelGGL(k_ref_grid<true>, dim3(nb1), dim3(kBlock), 0, st, wc, m_modes, C, N, data->f0, data->df,
+                       data->t_obs, data->dw64, data->sw64, h0w, band, part1, gate);
   else
-    hipLaunchKernelGGL(k_ref_grid<false>, dim3(nb1), dim3(kBlock), 0, st, wc, modes, C, N, data->f0, data->df,
-                       data->t_obs, data->dw64, data->sw64, h0w, band, part1, nullptr);
+    hipLaunchKernelGGL(k_ref_grid<false>, dim3(nb1), dim3(kBlock), 0, st, wc, m_modes, C, N, data->f0, data->df,
+                       data->t_obs, data->dw64, data->sw64, h0w, band, part1, gate);
   hipLaunchKernelGGL(k_sum_partials, dim3(3), dim3(64), 0, st, part1, nb1, 3, 3, sums1);
   HIP_TRY(hipGetLastError());
   unsigned long long hb[2];
-  double s1[3];
+  RefMeta g{};
+  HIP_TRY(hipMemcpyAsync(&g, gate, sizeof(g), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipMemcpyAsync(hb, band, sizeof(hb), hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipMemcpyAsync(s1, sums1, sizeof(s1), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
+  if (g.status != 0) return mbh_fail(MBH_EINVAL, "theta0 outside the model domain");
   if (hb[0] == ~0ull || hb[1] <= hb[0]) return mbh_fail(MBH_EBAND, "reference template is empty on the grid");
   const int64_t k_lo = (int64_t)hb[0], k_hi = (int64_t)hb[1];
 
@@ -485,7 +516,7 @@ extern "C" mbh_status mbh_build_reference_coeffs(mbh_ctx *ctx, const mbh_data *d
   r->ctx = ctx;
   r->hold.set(ctx);
   r->model = model;
-  r->modes = model == MBH_MODEL_IMR ? modes : 0u;
+  r->modes = m_modes;
   r->n_chan = C;
   r->n_bins = n_bins;
   r->n_edges = E;
@@ -510,15 +541,25 @@ extern "C" mbh_status mbh_build_reference_coeffs(mbh_ctx *ctx, const mbh_data *d
   if ((s = ctx_alloc(ctx, (void **)&r->coef, (size_t)C * n_bins * 6 * sizeof(double))) != MBH_OK)
     return fail_free(s);
   if ((s = ctx_alloc(ctx, (void **)&r->meta, sizeof(RefMeta))) != MBH_OK) return fail_free(s);
-  int64_t *kb_dev = nullptr;
-  double *part2 = nullptr, *sums2 = nullptr;
-  double2 *s0 = nullptr;
-  if ((s = sc.get(&kb_dev, E)) != MBH_OK) return fail_free(s);
-  if ((s = sc.get(&part2, (size_t)n_bins * n_sub * 18)) != MBH_OK) return fail_free(s);
-  if ((s = sc.get(&sums2, (size_t)n_bins * 18)) != MBH_OK) return fail_free(s);
-  if ((s = sc.get(&s0, (size_t)C * E)) != MBH_OK) return fail_free(s);
+
+  // pass 2: bin sums, h0 at the edges, coefficients and scalars
+  Carve c2;
+  const size_t o_kb = c2.add<int64_t>(E), o_part2 = c2.add<double>((size_t)n_bins * n_sub * 18),
+               o_sums2 = c2.add<double>((size_t)n_bins * 18), o_s0 = c2.add<double2>((size_t)C * E),
+               o_paper = c2.add<double>((size_t)C * n_bins * 6), o_h0e = c2.add<double>((size_t)C * E * 2);
+  char *b2 = nullptr;
+  if ((s = sc.get(&b2, c2.bytes)) != MBH_OK) return fail_free(s);
+  int64_t *kb_dev = (int64_t *)(b2 + o_kb);
+  double *part2 = (double *)(b2 + o_part2), *sums2 = (double *)(b2 + o_sums2);
+  double *paper = (double *)(b2 + o_paper), *h0e = (double *)(b2 + o_h0e);
+  double2 *s0 = (double2 *)(b2 + o_s0);
+  RefMeta m{};
+  m.k_lo = k_lo;
+  m.k_hi = k_hi;
+  m.pick = -1;
   if (hipMemcpyAsync(r->F, edges.data(), E * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess ||
-      hipMemcpyAsync(kb_dev, kb.data(), E * sizeof(int64_t), hipMemcpyHostToDevice, st) != hipSuccess)
+      hipMemcpyAsync(kb_dev, kb.data(), E * sizeof(int64_t), hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(r->meta, &m, sizeof(m), hipMemcpyHostToDevice, st) != hipSuccess)
     return fail_free(mbh_fail(MBH_EDEVICE, "upload edges"));
   hipLaunchKernelGGL(k_ref_bins, dim3(n_bins, n_sub), dim3(kBlock), 0, st, kb_dev, r->F, n_bins, n_sub, C, N,
                      data->f0, data->df, data->dw64, h0w, part2, nullptr);
@@ -526,92 +567,39 @@ extern "C" mbh_status mbh_build_reference_coeffs(mbh_ctx *ctx, const mbh_data *d
   hipLaunchKernelGGL(k_sum_bins, dim3((n_bins * 18 + 255) / 256), dim3(256), 0, st, part2, n_bins, n_sub, sums2);
   hipLaunchKernelGGL(k_ref_edges, dim3((E + 63) / 64), dim3(64), 0, st, wc, r->modes, C, E, r->F, data->t_obs,
                      r->fq, r->psi0, s0, nullptr);
+  // paper-form and residual-form coefficients, 1/s0, h0 at the edges, lnL(h0)
+  // and the sinc term counts; status MBH_EBAND if h0 vanishes at an edge
+  hipLaunchKernelGGL(k_refresh_finish, dim3(1), dim3(256), 0, st, sums1, sums2, s0, r->F, r->psi0, C, n_bins, r->coef,
+                     r->is064, paper, h0e, r->meta);
   if (hipGetLastError() != hipSuccess) return fail_free(mbh_fail(MBH_EDEVICE, "reference kernels"));
-  std::vector<double> hs2((size_t)n_bins * 18), hs0((size_t)C * E * 2);
-  if (hipMemcpyAsync(hs2.data(), sums2, hs2.size() * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
-      hipMemcpyAsync(hs0.data(), s0, hs0.size() * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+  std::vector<double> hp((size_t)C * n_bins * 6);
+  r->h0_edges.assign((size_t)C * E * 2, 0.0);
+  if (hipMemcpyAsync(&m, r->meta, sizeof(m), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipMemcpyAsync(hp.data(), paper, hp.size() * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipMemcpyAsync(r->h0_edges.data(), h0e, r->h0_edges.size() * sizeof(double), hipMemcpyDeviceToHost, st) !=
+          hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
-    return fail_free(mbh_fail(MBH_EDEVICE, "download reference sums"));
-
-  // the ratio h/h0 must exist at every edge
-  for (int c = 0; c < C; ++c)
-    for (int j = 0; j < E; ++j) {
-      double re = hs0[2 * (c * E + j)], im = hs0[2 * (c * E + j) + 1];
-      if (!(re != 0.0 || im != 0.0) || !std::isfinite(re) || !std::isfinite(im))
-        return fail_free(mbh_fail(MBH_EBAND, "reference is zero at edge %d (f = %.6g Hz), channel %d", j, edges[j], c));
-    }
+    return fail_free(mbh_fail(MBH_EDEVICE, "download reference"));
+  if (m.status != 0) return fail_free(mbh_fail(MBH_EBAND, "reference is zero or not finite at a bin edge"));
   double dd = 0.0;
   if ((s = data_dd(data, &dd)) != MBH_OK) return fail_free(s);
   r->dd = dd;
-  r->lnL0 = -0.5 * s1[0];
-  r->dh0 = s1[1];
-  r->hh0 = s1[2];
-  r->hh0_build = s1[2];
-
-  // paper-form coefficients (A0 = sum d h0* / S df, ...) and the kernel's
-  // residual-form coefficients, scaled by 1/dF_b for the slope terms
+  r->lnL0 = m.lnL0;
+  r->dh0 = m.dh0;
+  r->hh0 = m.hh0;
+  r->hh0_build = m.hh0;
   r->A0.assign((size_t)C * n_bins * 2, 0.0);
   r->A1.assign((size_t)C * n_bins * 2, 0.0);
   r->B0.assign((size_t)C * n_bins, 0.0);
   r->B1.assign((size_t)C * n_bins, 0.0);
-  std::vector<double> coef((size_t)C * n_bins * 6);
-  for (int c = 0; c < C; ++c)
-    for (int b = 0; b < n_bins; ++b) {
-      const double *q = &hs2[(size_t)b * 18 + c * 6];
-      // the grid sums carry w = 4 df / S; the coefficients carry df / S
-      double amb0r = 0.25 * q[0], amb0i = 0.25 * q[1], amb1r = 0.25 * q[2], amb1i = 0.25 * q[3];
-      double b0 = 0.25 * q[4], b1 = 0.25 * q[5];
-      size_t o = (size_t)c * n_bins + b;
-      r->A0[2 * o] = amb0r + b0;
-      r->A0[2 * o + 1] = amb0i;
-      r->A1[2 * o] = amb1r + b1;
-      r->A1[2 * o + 1] = amb1i;
-      r->B0[o] = b0;
-      r->B1[o] = b1;
-      double idf = 1.0 / (edges[b + 1] - edges[b]);
-      coef[6 * o + 0] = amb0r;
-      coef[6 * o + 1] = amb0i;
-      coef[6 * o + 2] = amb1r * idf;
-      coef[6 * o + 3] = amb1i * idf;
-      coef[6 * o + 4] = b0;
-      coef[6 * o + 5] = b1 * idf;
-    }
-  std::vector<double> is64((size_t)C * E * 2);
-  r->h0_edges.assign((size_t)C * E * 2, 0.0);
-  for (size_t i = 0; i < (size_t)C * E; ++i) {
-    double re = hs0[2 * i], im = hs0[2 * i + 1];
-    double den = re * re + im * im;
-    is64[2 * i] = re / den;
-    is64[2 * i + 1] = -im / den;
+  for (size_t o = 0; o < (size_t)C * n_bins; ++o) {
+    r->A0[2 * o] = hp[6 * o + 0];
+    r->A0[2 * o + 1] = hp[6 * o + 1];
+    r->A1[2 * o] = hp[6 * o + 2];
+    r->A1[2 * o + 1] = hp[6 * o + 3];
+    r->B0[o] = hp[6 * o + 4];
+    r->B1[o] = hp[6 * o + 5];
   }
-  // h0 at the edges in the paper's units (for export): s0 e^{-i psi0} / scale
-  {
-    std::vector<double> psi(E);
-    if (hipMemcpy(psi.data(), r->psi0, E * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
-      return fail_free(mbh_fail(MBH_EDEVICE, "download psi0"));
-    for (int c = 0; c < C; ++c)
-      for (int j = 0; j < E; ++j) {
-        double re = hs0[2 * (c * E + j)], im = hs0[2 * (c * E + j) + 1];
-        double p = std::remainder(psi[j], 2.0 * M_PI);
-        double cp = std::cos(p), sp = std::sin(p);
-        r->h0_edges[2 * (c * E + j)] = (re * cp + im * sp) / kAmpScale;
-        r->h0_edges[2 * (c * E + j) + 1] = (im * cp - re * sp) / kAmpScale;
-      }
-  }
-  RefMeta m{};
-  m.lnL0 = r->lnL0;
-  m.dh0 = r->dh0;
-  m.hh0 = r->hh0;
-  m.ns64 = sinc_terms_for<double>(edges.back());
-  m.ns32 = sinc_terms_for<float>(edges.back());
-  m.k_lo = k_lo;
-  m.k_hi = k_hi;
-  m.pick = -1;
-  if (hipMemcpyAsync(r->coef, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess ||
-      hipMemcpyAsync(r->is064, is64.data(), is64.size() * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess ||
-      hipMemcpyAsync(r->meta, &m, sizeof(m), hipMemcpyHostToDevice, st) != hipSuccess ||
-      hipStreamSynchronize(st) != hipSuccess)
-    return fail_free(mbh_fail(MBH_EDEVICE, "upload coefficients"));
   *out = r;
   return MBH_OK;
 }
