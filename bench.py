@@ -53,13 +53,13 @@ ALGO_BYTES_PER_EVAL = 96.0
 ALGO_FULL_FLOPS_PER_POINT = 250.0
 # Hardware counter figures of the current kernels (rocprofv3): VALU flops per
 # (walker, edge) of the mixed main pass (SQ_INSTS_VALU_FLOPS_* x 64 lanes,
-# FMA = 2), VALU flops per (walker, point) of the FP64 full grid (None: not
-# taken for these sources), and HBM bytes per launch of the mixed main pass (FETCH_SIZE and WRITE_SIZE divided by
+# FMA = 2), VALU flops per (walker, point) of the FP64 full grid, and HBM
+# bytes per launch of the mixed main pass (FETCH_SIZE and WRITE_SIZE divided by
 # their reading for a 64 MiB device copy: factors 0.5002 and 1.000).  Valid
 # only for the kernel sources they were measured on (sha256 over
 # KERNEL_SOURCES); reported as null otherwise.
-COUNTERS = {"src_sha256": "08cf87041c4d3fe71893c6cf5fea7dc0a85bb16f1f8b3447e3b0466e1017e646",
-            "valu_flops_per_edge": 850.7, "full_valu_flops_per_point": None, "bytes_per_launch": 5.496e6}
+COUNTERS = {"src_sha256": "02846ed2bc564448bd9a66ccf633fb7ede5f7fc4a942e11140660b5b7def1212",
+            "valu_flops_per_edge": 850.7, "full_valu_flops_per_point": 504.7, "bytes_per_launch": 5.482e6}
 
 
 # the sources that define the device code of the main pass and the order
