@@ -1494,24 +1494,34 @@ static bool valid_full_shape(int kf, int wpb_cap) {
   return (kf == 1 || kf == 2) && (wpb_cap == 8 || wpb_cap == 16 || wpb_cap == 32 || wpb_cap == 64 || wpb_cap == 128);
 }
 
+// Partial sums of one pass are NV x W x n_chunks doubles; walkers are taken
+// in groups whose partials fit kFullPartBytes, so that scratch stays bounded
+// for any W (each walker's result is independent of the grouping).
+constexpr size_t kFullPartBytes = (size_t)1 << 30;
+
 template <int KF, bool DH, bool HM>
 static mbh_status full_impl(mbh_ctx *ctx, const mbh_data *d, uint32_t modes, const WalkerC *wc, int64_t W,
                             int wpb_cap, double *lnL, double *dhhh, hipStream_t st, Scratch &sc) {
   const int64_t fpb = (int64_t)kBlock * KF;
   const int64_t n_fc = (d->n_f + fpb - 1) / fpb;
   if (n_fc > 65535 * 64) return mbh_fail(MBH_EINVAL, "grid too large");
-  const int64_t target = (int64_t)ctx->n_cu * 8;
-  int64_t n_wc = std::max<int64_t>(1, std::min<int64_t>(W, target / std::max<int64_t>(1, n_fc)));
-  int64_t wpb = std::min<int64_t>((W + n_wc - 1) / n_wc, wpb_cap);
-  wpb = std::max<int64_t>(wpb, (W + 65534) / 65535);  // grid y at most 65535
-  n_wc = (W + wpb - 1) / wpb;
   const int nv = DH ? 3 : 1;
+  const int64_t group = std::max<int64_t>(1, std::min<int64_t>(W, (int64_t)(kFullPartBytes / ((size_t)nv * n_fc *
+                                                                                                sizeof(double)))));
   double *part = nullptr;
-  MBH_TRY(sc.get(&part, (size_t)nv * n_fc * W));
-  hipLaunchKernelGGL((k_full<KF, DH, HM>), dim3((unsigned)n_fc, (unsigned)n_wc), dim3(kBlock), 0, st, d->dw64,
-                     d->sw64, d->n_chan, d->n_f, d->f0, d->df, d->t_obs, modes, wc, W, (int)wpb, part);
-  hipLaunchKernelGGL((k_full_reduce<DH ? 3 : 1>), dim3((unsigned)W), dim3(kBlock), 0, st, part, (int)n_fc, W,
-                     d->dd_dev, wc, lnL, dhhh);
+  MBH_TRY(sc.get(&part, (size_t)nv * n_fc * group));
+  const int64_t target = (int64_t)ctx->n_cu * 8;
+  for (int64_t w0 = 0; w0 < W; w0 += group) {
+    const int64_t Wg = std::min<int64_t>(group, W - w0);
+    int64_t n_wc = std::max<int64_t>(1, std::min<int64_t>(Wg, target / std::max<int64_t>(1, n_fc)));
+    int64_t wpb = std::min<int64_t>((Wg + n_wc - 1) / n_wc, wpb_cap);
+    wpb = std::max<int64_t>(wpb, (Wg + 65534) / 65535);  // grid y at most 65535
+    n_wc = (Wg + wpb - 1) / wpb;
+    hipLaunchKernelGGL((k_full<KF, DH, HM>), dim3((unsigned)n_fc, (unsigned)n_wc), dim3(kBlock), 0, st, d->dw64,
+                       d->sw64, d->n_chan, d->n_f, d->f0, d->df, d->t_obs, modes, wc + w0, Wg, (int)wpb, part);
+    hipLaunchKernelGGL((k_full_reduce<DH ? 3 : 1>), dim3((unsigned)Wg), dim3(kBlock), 0, st, part, (int)n_fc, Wg,
+                       d->dd_dev, wc + w0, lnL + w0, dhhh ? dhhh + 2 * w0 : nullptr);
+  }
   HIP_TRY(hipGetLastError());
   return MBH_OK;
 }

@@ -127,3 +127,32 @@ def test_fullsize_full_grid(M, ctx, full, prec):
         print(f"[fullsize] full {prec}: max|dlnL|={err.max():.3e} lnL range=[{ref_l.min():.4g}, {ref_l.max():.4g}]",
               flush=True)
         assert np.all(err <= 1e-6 + 1e-11 * np.abs(ref_l))
+
+
+def test_fullsize_full_grid_walker_groups(M, ctx, full):
+    """A full-grid call larger than one group of walkers (the partial sums of
+    a group are capped at 1 GiB: 7258 walkers with <d|h>, <h|h> on this grid)
+    gives, walker for walker, the results of smaller calls bit for bit, and
+    the oracle's on a sample."""
+    import torch
+
+    g, srcs = full
+    c = srcs[0]
+    draws = I.prior_draws(I.rng_for(3, 0), 7500, g.t_obs)
+    td = torch.as_tensor(draws, device="cuda")
+    dh_all = torch.empty((len(draws), 2), dtype=torch.float64, device="cuda")
+    big = M.loglike_full(ctx, c["gdata"], M.MODEL_IMR, M.MODE_22, td, M.FP64, dh_hh=dh_all).cpu().numpy()
+    parts, dhs = [], []
+    for a, b in ((0, 4000), (4000, 7500)):
+        dh = torch.empty((b - a, 2), dtype=torch.float64, device="cuda")
+        parts.append(M.loglike_full(ctx, c["gdata"], M.MODEL_IMR, M.MODE_22, td[a:b].contiguous(), M.FP64,
+                                    dh_hh=dh).cpu().numpy())
+        dhs.append(dh.cpu().numpy())
+    assert np.array_equal(big, np.concatenate(parts), equal_nan=True)
+    assert np.array_equal(dh_all.cpu().numpy(), np.concatenate(dhs))
+    sample = [0, 7257, 7258, 7499]
+    ref_l, _, _ = O.loglike_full(O.MODEL_IMR, O.MODE_22, draws[sample], c["data"])
+    ok = np.isfinite(ref_l)
+    err = np.abs(big[sample] - ref_l)[ok]
+    print(f"[fullsize] full grid, 7500 draws in two groups: sample max|dlnL|={err.max():.3e}", flush=True)
+    assert np.all(err <= 1e-6 + 1e-11 * np.abs(ref_l[ok]))
