@@ -212,6 +212,131 @@ __global__ __launch_bounds__(1024) void k_smp_swap(SmpParams p, uint32_t it, dou
   }
 }
 
+// The same exchanges for ensembles of at most kSwapLdsMax walkers in all,
+// decided in LDS: the lnL values and a slot permutation live in LDS while the
+// pairs of rungs are taken in turn (same uniforms, drawn beforehand by
+// k_smp_swap_prep, same arithmetic, same order, so the same decisions; the
+// exchange counts are summed per wavefront before one atomic add).  At the
+// end lnL is written from LDS and <d|h>, <h|h> are moved in place (each
+// thread reads the moved slots it owns into registers, then a barrier, then
+// writes them); the permutation goes out for k_smp_permute, which moves x.  Dynamic LDS: K W + K doubles (lnL, beta differences),
+// K W + 2 K ints (permutation, shifts, counters).
+constexpr int kSwapLdsMax = 4096;
+constexpr int kSwapThreads = 1024;
+constexpr int kSwapSlotsPerThread = kSwapLdsMax / kSwapThreads;
+constexpr int kSwapPrefetch = 16;  // pairs of rungs whose ln v a thread holds in registers
+
+// The uniforms of the exchanges do not depend on the walkers: ln v of every
+// (pair of rungs k, walker i) and the shift s of every pair, over the whole
+// chip, before the exchange kernel (logv [(K-1) W], shift [K-1]).
+__global__ __launch_bounds__(256) void k_smp_swap_prep(SmpParams p, uint32_t it, double *__restrict__ logv,
+                                                       int32_t *__restrict__ shift) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int W = p.W, np = (p.K - 1) * W;
+  if (t < np) {
+    const int k = t / W, i = t - k * W;
+    const U4 v = philox_uniforms(p.seed, it, (uint32_t)(k * W + i), kStreamSwap, 1u);
+    logv[t] = log(v.u[0]);
+  }
+  if (t < p.K - 1) {
+    const U4 us = philox_uniforms(p.seed, it, (uint32_t)t, kStreamSwap, 0u);
+    shift[t] = min((int)floor(__dmul_rn(us.u[0], (double)W)), W - 1);
+  }
+}
+
+__global__ __launch_bounds__(kSwapThreads) void k_smp_swap_lds(SmpParams p, const double *__restrict__ logv,
+                                                               const int32_t *__restrict__ shift,
+                                                               int32_t *__restrict__ perm_out,
+                                                               double *__restrict__ lnL, double *__restrict__ dhhh,
+                                                               unsigned long long *__restrict__ swaps) {
+  extern __shared__ double smem[];
+  const int W = p.W, n = p.K * W, np = p.K - 1, tid = threadIdx.x, nt = blockDim.x;
+  double *sl = smem;
+  double *sdb = sl + n;                // [K-1] beta_k - beta_k+1
+  int *perm = (int *)(sdb + p.K);      // [n]
+  int *ssh = perm + n;                 // [K-1] shifts
+  unsigned int *cnt = (unsigned int *)(ssh + p.K);
+  for (int t = tid; t < n; t += nt) {
+    sl[t] = lnL[t];
+    perm[t] = t;
+  }
+  for (int k = tid; k < np; k += nt) {
+    sdb[k] = __dadd_rn(p.betas[k], -p.betas[k + 1]);
+    ssh[k] = shift[k];
+    cnt[k] = 0u;
+  }
+  // with one walker per thread and rung, its ln v of the first pairs in registers
+  const bool one = W <= nt;
+  double lv[kSwapPrefetch];
+#pragma unroll
+  for (int k = 0; k < kSwapPrefetch; ++k) lv[k] = (one && tid < W && k < np) ? logv[k * W + tid] : 0.0;
+  __syncthreads();
+  for (int k = 0; k < np; ++k) {
+    const int s = ssh[k];
+    const double db = sdb[k];
+    unsigned int mine = 0u;
+    for (int i = tid; i < W; i += nt) {
+      const int j = i + s < W ? i + s : i + s - W;
+      const int oa = k * W + i, ob = (k + 1) * W + j;
+      double lu = 0.0;
+      if (one && k < kSwapPrefetch) {
+#pragma unroll
+        for (int q = 0; q < kSwapPrefetch; ++q)
+          if (q == k) lu = lv[q];
+      } else {
+        lu = logv[oa];
+      }
+      const double a = sl[oa], b = sl[ob];
+      const double la = __dmul_rn(db, __dadd_rn(b, -a));
+      if (!(lu < (isnan(la) ? -INFINITY : la))) continue;
+      sl[oa] = b;
+      sl[ob] = a;
+      const int pa = perm[oa];
+      perm[oa] = perm[ob];
+      perm[ob] = pa;
+      ++mine;
+    }
+    // one atomic add per wavefront
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) mine += __shfl_xor(mine, off, 64);
+    if ((tid & 63) == 0 && mine) atomicAdd(&cnt[k], mine);
+    __syncthreads();
+  }
+  double dr[kSwapSlotsPerThread][2];
+#pragma unroll
+  for (int q = 0; q < kSwapSlotsPerThread; ++q) {
+    const int t = tid + q * nt;
+    if (t >= n) continue;
+    perm_out[t] = perm[t];
+    if (perm[t] == t) continue;
+    const int64_t src = perm[t];
+    dr[q][0] = dhhh[2 * src];
+    dr[q][1] = dhhh[2 * src + 1];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kSwapSlotsPerThread; ++q) {
+    const int t = tid + q * nt;
+    if (t >= n || perm[t] == t) continue;
+    dhhh[2 * (int64_t)t] = dr[q][0];
+    dhhh[2 * (int64_t)t + 1] = dr[q][1];
+    lnL[t] = sl[t];
+  }
+  for (int k = tid; k < np; k += nt)
+    if (cnt[k]) atomicAdd(&swaps[k], (unsigned long long)cnt[k]);
+}
+
+// x after the exchanges: x_out[t] = x_in[perm[t]], element by element over
+// the whole chip (consecutive threads take consecutive coordinates, so reads
+// and writes are coalesced); the sampler then uses x_out as its walkers.
+__global__ __launch_bounds__(256) void k_smp_permute(int n, const int32_t *__restrict__ perm,
+                                                     const double *__restrict__ x_in, double *__restrict__ x_out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * kDim) return;
+  const int t = e / kDim, d = e - t * kDim;
+  x_out[e] = x_in[(int64_t)perm[t] * kDim + d];
+}
+
 // theta of every walker, and whether its x lies in the prior box
 __global__ __launch_bounds__(256) void k_smp_theta(int n, const double *__restrict__ x, const double *__restrict__ lo,
                                                    const double *__restrict__ hi, double *__restrict__ th) {
@@ -234,6 +359,10 @@ struct mbh_sampler {
   int K = 0, W = 0, H = 0;
   SmpParams p{};
   double *lo = nullptr, *hi = nullptr, *betas = nullptr;
+  double *swap_logv = nullptr;  // [(K-1) W] ln v of the exchanges of one iteration
+  int32_t *swap_shift = nullptr;  // [K-1]
+  int32_t *swap_perm = nullptr;   // [K W] slot permutation of one iteration's exchanges
+  double *x_alt = nullptr;        // [K W][11] the other buffer of the walkers (swapped with x)
   double *x = nullptr, *lnL = nullptr, *dhhh = nullptr, *th = nullptr;
   double *y = nullptr, *thy = nullptr, *lny = nullptr, *dhy = nullptr, *lz = nullptr;
   int32_t *kind = nullptr;
@@ -292,7 +421,9 @@ extern "C" mbh_status mbh_sampler_create(mbh_ctx *ctx, const mbh_sampler_config 
       (e = smp_alloc(s, &s->th, n * kDim)) || (e = smp_alloc(s, &s->y, nh * kDim)) ||
       (e = smp_alloc(s, &s->thy, nh * kDim)) || (e = smp_alloc(s, &s->lny, nh)) || (e = smp_alloc(s, &s->dhy, 2 * nh)) ||
       (e = smp_alloc(s, &s->lz, nh)) || (e = smp_alloc(s, &s->kind, nh)) || (e = smp_alloc(s, &s->counts, K * 8)) ||
-      (e = smp_alloc(s, &s->swaps, K))) {
+      (e = smp_alloc(s, &s->swaps, K)) || (e = smp_alloc(s, &s->swap_logv, (size_t)std::max(K - 1, 1) * W)) ||
+      (e = smp_alloc(s, &s->swap_shift, std::max(K - 1, 1))) || (e = smp_alloc(s, &s->swap_perm, n)) ||
+      (e = smp_alloc(s, &s->x_alt, n * kDim))) {
     sampler_free(s);
     return e;
   }
@@ -416,9 +547,20 @@ extern "C" mbh_status mbh_sampler_accept(mbh_sampler *s, int half, const double 
 extern "C" mbh_status mbh_sampler_swap(mbh_sampler *s, hipStream_t st) {
   if (!s) return mbh_fail(MBH_EINVAL, "null sampler");
   HIP_TRY(hipSetDevice(s->ctx->device));
-  if (s->K > 1)
+  const int n = s->K * s->W;
+  if (s->K > 1 && n <= kSwapLdsMax) {
+    const size_t lds = (size_t)n * (sizeof(double) + sizeof(int)) + (size_t)s->K * (sizeof(double) + 2 * sizeof(int));
+    const int np = (s->K - 1) * s->W;
+    hipLaunchKernelGGL(k_smp_swap_prep, dim3((np + 255) / 256), dim3(256), 0, st, s->p, (uint32_t)s->it, s->swap_logv,
+                       s->swap_shift);
+    hipLaunchKernelGGL(k_smp_swap_lds, dim3(1), dim3(kSwapThreads), lds, st, s->p, s->swap_logv, s->swap_shift,
+                       s->swap_perm, s->lnL, s->dhhh, s->swaps);
+    hipLaunchKernelGGL(k_smp_permute, dim3((n * kDim + 255) / 256), dim3(256), 0, st, n, s->swap_perm, s->x, s->x_alt);
+    std::swap(s->x, s->x_alt);
+  } else if (s->K > 1) {
     hipLaunchKernelGGL(k_smp_swap, dim3(1), dim3(std::min(1024, s->W)), 0, st, s->p, (uint32_t)s->it, s->x, s->lnL,
                        s->dhhh, s->swaps);
+  }
   HIP_TRY(hipGetLastError());
   s->it += 1;
   return MBH_OK;
