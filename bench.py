@@ -507,8 +507,13 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def sampler_search(M, ctx, item):
+def sampler_search(M, ctx, item, prec=None, mixed_rungs=0):
     import torch
+
+    # FP64: at 2000 walkers per half-ensemble launch the heterodyned pass is
+    # latency-bound, so FP32 gains nothing while hot rungs recompute many
+    # segments in FP64 (measured: 87.7 us per iteration FP64, 110-123 mixed)
+    prec = M.FP64 if prec is None else prec
 
     K, W = 10, 400
     lo = np.array([math.log(1e5), 0.05, -0.99, -0.99, 1e-2, 0.0, -1.0, 0.0, -1.0, 0.0, 0.0])
@@ -528,7 +533,7 @@ def sampler_search(M, ctx, item):
     ref = M.build_reference_coeffs(ctx, item["data"], M.MODEL_IMR, M.MODE_22, cloud[-1], N_BINS)
     like = M.Sampler.likelihood(ref=ref)
     betas = 1.0 / 1.6 ** np.arange(K)
-    smp = M.Sampler(ctx, betas, W, lo, hi, seed=20211101, prec=M.MIXED)
+    smp = M.Sampler(ctx, betas, W, lo, hi, seed=20211101, prec=prec, mixed_rungs=mixed_rungs)
     smp.set_walkers(x0, like)
     r = smp.run(like, check_every=150, lnl_tol=1.0, lnl_checks=30, refresh_every=1000, refresh_data=item["data"],
                 max_iter=30000)
@@ -543,7 +548,8 @@ def sampler_search(M, ctx, item):
     acc = st["accepted"].astype(float)
     prop = np.maximum(st["proposed"].astype(float), 1.0)
     l_true = float(het(th[None, :])[0])
-    out = dict(rungs=K, walkers_per_rung=W, iterations=r["iterations"],
+    out = dict(rungs=K, walkers_per_rung=W, precision="fp64" if prec == M.FP64 else "mixed",
+               mixed_rungs=mixed_rungs, iterations=r["iterations"],
                stop={0: "max_iter", 1: "snr", 2: "converged"}[r["reason"]], reference_updates=r["refreshes"],
                seconds=r["seconds"], us_per_iteration=r["seconds"] / max(1, r["iterations"]) * 1e6,
                lnL_evals_per_s=2 * (K * W // 2) * r["iterations"] / r["seconds"],

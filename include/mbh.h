@@ -345,6 +345,17 @@ mbh_status mbh_batch_create(mbh_ctx *ctx, int n, const mbh_ref *const *refs,
                             const double *const *theta_dev, const int64_t *W,
                             double *const *lnL_dev, double *const *dh_hh_dev,
                             mbh_precision prec, mbh_batch **out);
+/* The same with a precision per item (precs[n], MBH_FP64 or MBH_MIXED):
+ * the tiles are grouped by precision as well, each item's results are those
+ * of the uniform batch (or the single call) in its own precision.  For
+ * populations whose hot part gains nothing from the mixed path (walkers far
+ * from the reference mostly exceed the FP32 error budget and are computed
+ * twice), e.g. a tempered ensemble with its cold rungs mixed and the rest in
+ * FP64.  Per-mode references must be MBH_FP64.  Errors: as mbh_batch_create. */
+mbh_status mbh_batch_create_prec(mbh_ctx *ctx, int n, const mbh_ref *const *refs,
+                                 const double *const *theta_dev, const int64_t *W,
+                                 double *const *lnL_dev, double *const *dh_hh_dev,
+                                 const mbh_precision *precs, mbh_batch **out);
 mbh_status mbh_batch_launch(mbh_batch *batch, hipStream_t stream);
 /* The same work as mbh_batch_launch, issued as the batch's kernel launches on
  * the stream (setup, one main-pass grid per mapping group, totals) instead of
@@ -528,6 +539,9 @@ typedef struct {
   double p_sky_all, p_sky_lon, p_sky_lat; /* hop shares (the paper: 0.04, 0.03, 0.08) */
   uint64_t seed;
   mbh_precision prec;       /* of the heterodyned / full-grid likelihood      */
+  int32_t mixed_rungs;      /* with prec MBH_MIXED and a heterodyned
+                               likelihood: only the mixed_rungs coldest rungs
+                               run mixed, the rest FP64 (0: every rung mixed) */
 } mbh_sampler_config;
 /* The likelihood a sampler evaluates: heterodyned against `ref` (IMR; a
  * per-mode reference runs in FP64), or, with ref NULL, the full grid of

@@ -597,7 +597,8 @@ struct WorkItem {
   int64_t W;
   int64_t offset;        // first walker of this item in its batch
   int32_t E, K, G, model;
-  int32_t hm, pad;       // hm: the reference has modes beyond (2,2) (kernels compiled with HM)
+  int32_t hm, prec;      // hm: the reference has modes beyond (2,2) (kernels compiled with HM);
+                         // prec: MBH_FP64 or MBH_MIXED (batches group their tiles by it)
   // per-mode references (pm.T1 > 0): E = T1 tasks per walker in the edge pass
   // (slots 0..), E2 = T2 + 1 in the cross pass (slots K1..); E2 = 0 otherwise
   PmView pm;

@@ -1385,6 +1385,7 @@ static WorkItem het_item(const mbh_ctx *ctx, const mbh_ref *ref, const double *t
                          mbh_precision prec, double *lnL_dev, double *dh_hh_dev) {
   const int G = lanes_lookup(ctx, ref->n_bins, popcount_modes(ref->modes ? ref->modes : 1u), prec);
   WorkItem it = make_item(ctx, ref, G);
+  it.prec = prec;
   it.theta = theta_dev;
   it.lnL = lnL_dev;
   it.dhhh = dh_hh_dev;

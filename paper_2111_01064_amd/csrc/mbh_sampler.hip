@@ -396,6 +396,7 @@ extern "C" mbh_status mbh_sampler_create(mbh_ctx *ctx, const mbh_sampler_config 
   *out = nullptr;
   const int K = cfg->n_temps, W = cfg->walkers_per_temp;
   if (K < 1 || K > 64 || W < 4 || W % 2 || W > 65536) return mbh_fail(MBH_EINVAL, "n_temps in [1, 64], walkers even in [4, 65536]");
+  if (cfg->mixed_rungs < 0) return mbh_fail(MBH_EINVAL, "mixed_rungs must be >= 0");
   if (!(cfg->stretch_a > 1.0) || cfg->p_sky_all < 0 || cfg->p_sky_lon < 0 || cfg->p_sky_lat < 0 ||
       cfg->p_sky_all + cfg->p_sky_lon + cfg->p_sky_lat > 1.0)
     return mbh_fail(MBH_EINVAL, "stretch a > 1 and sky-hop shares in [0, 1] summing to at most 1");
@@ -458,16 +459,21 @@ static mbh_status smp_batches(mbh_sampler *s, const mbh_ref *ref) {
   if (s->all_batch) mbh_batch_release(s->all_batch);
   s->half_batch = s->all_batch = nullptr;
   const mbh_precision prec = ref->pm ? MBH_FP64 : s->cfg.prec;
-  const int64_t nh = (int64_t)s->K * s->H, n = (int64_t)s->K * s->W;
-  const double *th1[1] = {s->thy};
-  double *l1[1] = {s->lny};
-  double *d1[1] = {s->dhy};
-  const mbh_ref *r1[1] = {ref};
-  MBH_TRY(mbh_batch_create(s->ctx, 1, r1, th1, &nh, l1, d1, prec, &s->half_batch));
-  const double *th2[1] = {s->th};
-  double *l2[1] = {s->lnL};
-  double *d2[1] = {s->dhhh};
-  MBH_TRY(mbh_batch_create(s->ctx, 1, r1, th2, &n, l2, d2, prec, &s->all_batch));
+  // rungs [0, m) in prec and [m, K) in FP64: two items over the rung-major arrays
+  const int m = (prec == MBH_MIXED && s->cfg.mixed_rungs > 0 && s->cfg.mixed_rungs < s->K) ? s->cfg.mixed_rungs
+                                                                                          : s->K;
+  const int n_items = m < s->K ? 2 : 1;
+  const mbh_ref *r2[2] = {ref, ref};
+  const mbh_precision p2[2] = {prec, MBH_FP64};
+  for (int b = 0; b < 2; ++b) {
+    const int64_t per = b == 0 ? s->H : s->W;  // walkers per rung in the half / whole batch
+    double *thb = b == 0 ? s->thy : s->th, *lb = b == 0 ? s->lny : s->lnL, *db = b == 0 ? s->dhy : s->dhhh;
+    const double *th[2] = {thb, thb + (int64_t)m * per * kDim};
+    double *l[2] = {lb, lb + (int64_t)m * per};
+    double *d[2] = {db, db + 2 * (int64_t)m * per};
+    const int64_t W2[2] = {(int64_t)m * per, (int64_t)(s->K - m) * per};
+    MBH_TRY(mbh_batch_create_prec(s->ctx, n_items, r2, th, W2, l, d, p2, b == 0 ? &s->half_batch : &s->all_batch));
+  }
   s->bref = ref;
   return MBH_OK;
 }

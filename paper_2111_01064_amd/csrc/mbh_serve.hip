@@ -103,7 +103,7 @@ static void append_tiles(std::vector<WorkTile> &tiles, std::vector<double> &cost
 // template), longest first within a group (stable), and the group ranges
 // (G, hm, first tile, count)
 struct TileGroup {
-  int G, hm;
+  int G, hm, prec;
   int64_t begin, count;
 };
 
@@ -123,8 +123,10 @@ static std::vector<TileGroup> order_tiles(std::vector<WorkTile> &tiles, const st
     runs.back().count += 1;
   }
   auto hm = [&](const Run &r) { return items[tiles[r.begin].item].hm; };
+  auto pr = [&](const Run &r) { return items[tiles[r.begin].item].prec; };
   std::stable_sort(runs.begin(), runs.end(), [&](const Run &a, const Run &b) {
     const WorkTile &ta = tiles[a.begin], &tb = tiles[b.begin];
+    if (pr(a) != pr(b)) return pr(a) > pr(b);  // mixed-precision groups first
     if (ta.G != tb.G) return ta.G < tb.G;
     if (hm(a) != hm(b)) return hm(a) < hm(b);
     return cost[a.begin] > cost[b.begin];
@@ -135,9 +137,9 @@ static std::vector<TileGroup> order_tiles(std::vector<WorkTile> &tiles, const st
   tiles.swap(out);
   std::vector<TileGroup> groups;
   for (size_t i = 0; i < tiles.size(); ++i) {
-    const int h = items[tiles[i].item].hm;
-    if (groups.empty() || groups.back().G != tiles[i].G || groups.back().hm != h)
-      groups.push_back(TileGroup{tiles[i].G, h, (int64_t)i, 0});
+    const int h = items[tiles[i].item].hm, p = items[tiles[i].item].prec;
+    if (groups.empty() || groups.back().G != tiles[i].G || groups.back().hm != h || groups.back().prec != p)
+      groups.push_back(TileGroup{tiles[i].G, h, p, (int64_t)i, 0});
     groups.back().count += 1;
   }
   return groups;
@@ -238,18 +240,17 @@ static void launch_group(const TileGroup &g, const WorkItem *items, const WorkTi
   else launch_group_t<R, DH, false>(g, items, tiles, st);
 }
 
-// setup (a1), one grid per mapping group (main pass, with the mixed path's
-// FP64 recomputation inside), and the per-walker totals; the stage mask
-// selects 1 setup, 2 main pass, 4 totals
-static void launch_work(int prec, bool dh, int64_t n_wtiles, const std::vector<TileGroup> &groups,
-                        const WalkerTile *wtiles, const WorkItem *items, const WorkTile *tiles, hipStream_t st,
-                        int stages = 7) {
+// setup (a1), one grid per group of tiles (main pass in the group's
+// precision, with the mixed path's FP64 recomputation inside), and the
+// per-walker totals; the stage mask selects 1 setup, 2 main pass, 4 totals
+static void launch_work(bool dh, int64_t n_wtiles, const std::vector<TileGroup> &groups, const WalkerTile *wtiles,
+                        const WorkItem *items, const WorkTile *tiles, hipStream_t st, int stages = 7) {
   if (n_wtiles <= 0) return;  // no walkers: no walker tile to read
   const dim3 nw((unsigned)n_wtiles);
   if (stages & 1) hipLaunchKernelGGL(k_setup_work, nw, dim3(2 * kWalkerTile), 0, st, items, wtiles);
   for (const TileGroup &g : groups) {
     if (!(stages & 2)) break;
-    if (prec == MBH_FP64) {
+    if (g.prec == MBH_FP64) {
       if (dh) launch_group<double, true>(g, items, tiles, st);
       else launch_group<double, false>(g, items, tiles, st);
     } else {
@@ -267,7 +268,6 @@ static void launch_work(int prec, bool dh, int64_t n_wtiles, const std::vector<T
 struct mbh_batch {
   mbh_ctx *ctx = nullptr;
   CtxHold hold;
-  int prec = 0;
   bool dh = false;
   WorkItem *items = nullptr;
   WorkTile *tiles = nullptr;
@@ -295,12 +295,15 @@ static mbh_status batch_alloc(mbh_batch *b, T **p, size_t n) {
   return s;
 }
 
-extern "C" mbh_status mbh_batch_create(mbh_ctx *ctx, int n, const mbh_ref *const *refs, const double *const *theta_dev,
-                                       const int64_t *W, double *const *lnL_dev, double *const *dh_hh_dev,
-                                       mbh_precision prec, mbh_batch **out) {
-  if (!ctx || !refs || !theta_dev || !W || !lnL_dev || !out || n < 1) return mbh_fail(MBH_EINVAL, "bad argument");
+extern "C" mbh_status mbh_batch_create_prec(mbh_ctx *ctx, int n, const mbh_ref *const *refs,
+                                            const double *const *theta_dev, const int64_t *W,
+                                            double *const *lnL_dev, double *const *dh_hh_dev,
+                                            const mbh_precision *precs, mbh_batch **out) {
+  if (!ctx || !refs || !theta_dev || !W || !lnL_dev || !out || !precs || n < 1)
+    return mbh_fail(MBH_EINVAL, "bad argument");
   *out = nullptr;
-  if (prec != MBH_FP64 && prec != MBH_MIXED) return mbh_fail(MBH_EINVAL, "bad precision");
+  for (int i = 0; i < n; ++i)
+    if (precs[i] != MBH_FP64 && precs[i] != MBH_MIXED) return mbh_fail(MBH_EINVAL, "item %d: bad precision", i);
   int64_t total = 0;
   bool dh = false;
   int Kmax = 1;
@@ -309,7 +312,7 @@ extern "C" mbh_status mbh_batch_create(mbh_ctx *ctx, int n, const mbh_ref *const
     if (!refs[i] || W[i] < 0 || (W[i] > 0 && (!theta_dev[i] || !lnL_dev[i])))
       return mbh_fail(MBH_EINVAL, "item %d: null reference or buffers", i);
     if (refs[i]->ctx != ctx) return mbh_fail(MBH_EINVAL, "item %d: reference of another context", i);
-    if (refs[i]->pm && prec != MBH_FP64)
+    if (refs[i]->pm && precs[i] != MBH_FP64)
       return mbh_fail(MBH_EINVAL, "item %d: per-mode references are evaluated in MBH_FP64", i);
     total += W[i];
     if (dh_hh_dev && dh_hh_dev[i]) dh = true;
@@ -322,7 +325,6 @@ extern "C" mbh_status mbh_batch_create(mbh_ctx *ctx, int n, const mbh_ref *const
   mbh_batch *b = new mbh_batch();
   b->ctx = ctx;
   b->hold.set(ctx);
-  b->prec = prec;
   b->dh = dh;
   auto fail = [&](mbh_status s) {
     batch_free(b);
@@ -343,7 +345,8 @@ extern "C" mbh_status mbh_batch_create(mbh_ctx *ctx, int n, const mbh_ref *const
   int64_t off = 0;
   for (int i = 0; i < n; ++i) {
     WorkItem &it = items[i];
-    it = make_item(ctx, refs[i], item_lanes(ctx, refs[i], prec));
+    it = make_item(ctx, refs[i], item_lanes(ctx, refs[i], precs[i]));
+    it.prec = precs[i];
     it.theta = theta_dev[i];
     it.wc = wc + off;
     it.lnL = lnL_dev[i];
@@ -378,7 +381,7 @@ extern "C" mbh_status mbh_batch_create(mbh_ctx *ctx, int n, const mbh_ref *const
   if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return fail(mbh_fail(MBH_EDEVICE, "stream"));
   hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    launch_work(prec, dh, b->n_wtiles, b->groups, b->wtiles, b->items, b->tiles, cs);
+    launch_work(dh, b->n_wtiles, b->groups, b->wtiles, b->items, b->tiles, cs);
     e = hipStreamEndCapture(cs, &b->graph);
   }
   if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
@@ -386,6 +389,14 @@ extern "C" mbh_status mbh_batch_create(mbh_ctx *ctx, int n, const mbh_ref *const
   if (e != hipSuccess) return fail(mbh_fail(MBH_EDEVICE, "graph capture: %s", hipGetErrorString(e)));
   *out = b;
   return MBH_OK;
+}
+
+extern "C" mbh_status mbh_batch_create(mbh_ctx *ctx, int n, const mbh_ref *const *refs, const double *const *theta_dev,
+                                       const int64_t *W, double *const *lnL_dev, double *const *dh_hh_dev,
+                                       mbh_precision prec, mbh_batch **out) {
+  if (n < 1) return mbh_fail(MBH_EINVAL, "bad argument");
+  std::vector<mbh_precision> precs((size_t)n, prec);
+  return mbh_batch_create_prec(ctx, n, refs, theta_dev, W, lnL_dev, dh_hh_dev, precs.data(), out);
 }
 
 extern "C" mbh_status mbh_batch_launch(mbh_batch *b, hipStream_t st) {
@@ -398,7 +409,7 @@ extern "C" mbh_status mbh_batch_launch(mbh_batch *b, hipStream_t st) {
 extern "C" mbh_status mbh_batch_launch_direct(mbh_batch *b, hipStream_t st) {
   if (!b) return mbh_fail(MBH_EINVAL, "null batch");
   HIP_TRY(hipSetDevice(b->ctx->device));
-  launch_work(b->prec, b->dh, b->n_wtiles, b->groups, b->wtiles, b->items, b->tiles, st);
+  launch_work(b->dh, b->n_wtiles, b->groups, b->wtiles, b->items, b->tiles, st);
   HIP_TRY(hipGetLastError());
   return MBH_OK;
 }
@@ -406,7 +417,7 @@ extern "C" mbh_status mbh_batch_launch_direct(mbh_batch *b, hipStream_t st) {
 extern "C" mbh_status mbh_batch_launch_stage(mbh_batch *b, int stage, hipStream_t st) {
   if (!b || stage < MBH_STAGE_SETUP || stage > MBH_STAGE_FINISH) return mbh_fail(MBH_EINVAL, "bad batch or stage");
   HIP_TRY(hipSetDevice(b->ctx->device));
-  launch_work(b->prec, b->dh, b->n_wtiles, b->groups, b->wtiles, b->items, b->tiles, st, 1 << (stage - 1));
+  launch_work(b->dh, b->n_wtiles, b->groups, b->wtiles, b->items, b->tiles, st, 1 << (stage - 1));
   HIP_TRY(hipGetLastError());
   return MBH_OK;
 }
@@ -556,6 +567,7 @@ static void server_build(mbh_server *s, Slot &sl) {
     const int G = item_lanes(s->ctx, ref, s->cfg.prec);
     WorkItem &it = sl.items_h[i];
     it = make_item(s->ctx, ref, G);
+    it.prec = s->cfg.prec;
     it.theta = sl.theta_d + off * 11;
     it.wc = sl.wc_d + off;
     it.part = sl.part_d + off * s->Kmax * 4;
@@ -585,7 +597,7 @@ static bool server_launch(mbh_server *s, Slot &sl) {
             hipMemcpyAsync(sl.tiles_d, sl.tiles_h, h.n_tiles * sizeof(WorkTile), hipMemcpyHostToDevice, st) == hipSuccess &&
             hipMemcpyAsync(sl.wtiles_d, sl.wtiles_h, sl.n_wtiles * sizeof(WalkerTile), hipMemcpyHostToDevice, st) == hipSuccess;
   if (!ok) return false;
-  launch_work(s->cfg.prec, true, sl.n_wtiles, sl.groups, sl.wtiles_d, sl.items_d, sl.tiles_d, st);
+  launch_work(true, sl.n_wtiles, sl.groups, sl.wtiles_d, sl.items_d, sl.tiles_d, st);
   ok = hipGetLastError() == hipSuccess &&
        hipMemcpyAsync(sl.res_h, sl.res_d, sl.walkers * 3 * sizeof(double), hipMemcpyDeviceToHost, st) == hipSuccess &&
        hipEventRecord(sl.ev, st) == hipSuccess;

@@ -60,7 +60,7 @@ class RequestSpec(ct.Structure):
 class SamplerConfig(ct.Structure):
     _fields_ = [("n_temps", ct.c_int32), ("walkers_per_temp", ct.c_int32), ("stretch_a", ct.c_double),
                 ("p_sky_all", ct.c_double), ("p_sky_lon", ct.c_double), ("p_sky_lat", ct.c_double),
-                ("seed", ct.c_uint64), ("prec", ct.c_int)]
+                ("seed", ct.c_uint64), ("prec", ct.c_int), ("mixed_rungs", ct.c_int32)]
 
 
 class Likelihood(ct.Structure):
@@ -115,6 +115,7 @@ _SIGS = {
     "mbh_loglike_heterodyned_noalloc": [_vp, _vp, _vp, _i64, _i32, _vp, _vp, _vp],
     "mbh_loglike_full": [_vp, _vp, _i32, _u32, _vp, _i64, _i32, _vp, _vp, _vp],
     "mbh_batch_create": [_vp, _i32, _pp, _pp, ct.POINTER(ct.c_int64), _pp, _pp, _i32, _pp],
+    "mbh_batch_create_prec": [_vp, _i32, _pp, _pp, ct.POINTER(ct.c_int64), _pp, _pp, ct.POINTER(ct.c_int32), _pp],
     "mbh_batch_launch": [_vp, _vp],
     "mbh_batch_launch_stage": [_vp, _i32, _vp],
     "mbh_batch_launch_direct": [_vp, _vp],
@@ -498,7 +499,8 @@ def autotune_load(ctx: Context, path: str):
 class Batch:
     """mbh_batch_*: one graph-captured launch over many items."""
 
-    def __init__(self, ctx: Context, refs, thetas, lnLs, dh_hhs=None, prec: int = FP64):
+    def __init__(self, ctx: Context, refs, thetas, lnLs, dh_hhs=None, prec: int = FP64, precs=None):
+        """precs: one precision per item (mbh_batch_create_prec); else `prec` for every item."""
         n = len(refs)
         self.ctx = ctx
         arr = lambda xs: (ct.c_void_p * n)(*xs)
@@ -510,8 +512,15 @@ class Batch:
             dp = arr([_dev_ptr(x, torch.float64, (t.shape[0], 2)) if x is not None else None
                       for x, t in zip(dh_hhs, thetas)])
         h = ct.c_void_p()
-        _check(_L.mbh_batch_create(ctx.h, n, arr([r.h for r in refs]), tp, Ws, lp, dp, prec, ct.byref(h)),
-               "mbh_batch_create")
+        if precs is None:
+            _check(_L.mbh_batch_create(ctx.h, n, arr([r.h for r in refs]), tp, Ws, lp, dp, prec, ct.byref(h)),
+                   "mbh_batch_create")
+        else:
+            if len(precs) != n:
+                raise ValueError("one precision per item")
+            pv = (ct.c_int32 * n)(*precs)
+            _check(_L.mbh_batch_create_prec(ctx.h, n, arr([r.h for r in refs]), tp, Ws, lp, dp, pv, ct.byref(h)),
+                   "mbh_batch_create_prec")
         self.h = h
         self._keep = (refs, thetas, lnLs, dh_hhs)
 
@@ -642,11 +651,12 @@ class Sampler:
     """mbh_sampler_*: tempered ensemble sampler on the device (Sec. 3)."""
 
     def __init__(self, ctx: Context, betas, walkers_per_temp: int, prior_lo, prior_hi, seed: int = 1,
-                 stretch_a: float = 2.0, p_sky=(0.04, 0.03, 0.08), prec: int = MIXED):
+                 stretch_a: float = 2.0, p_sky=(0.04, 0.03, 0.08), prec: int = FP64, mixed_rungs: int = 0):
         betas = np.ascontiguousarray(betas, dtype=np.float64)
         lo = np.ascontiguousarray(prior_lo, dtype=np.float64)
         hi = np.ascontiguousarray(prior_hi, dtype=np.float64)
-        cfg = SamplerConfig(betas.size, walkers_per_temp, stretch_a, p_sky[0], p_sky[1], p_sky[2], seed, prec)
+        cfg = SamplerConfig(betas.size, walkers_per_temp, stretch_a, p_sky[0], p_sky[1], p_sky[2], seed, prec,
+                            mixed_rungs)
         h = ct.c_void_p()
         _check(_L.mbh_sampler_create(ctx.h, ct.byref(cfg), betas.ctypes.data_as(_dp), lo.ctypes.data_as(_dp),
                                      hi.ctypes.data_as(_dp), ct.byref(h)), "mbh_sampler_create")

@@ -114,6 +114,31 @@ def test_batch_graph_replays_match_single_calls_and_oracle(M, ctx, sources, prec
     print(f"[batch] {prec}: {len(sources)} items, {sum(s['W'] for s in sources)} walkers, oracle max|dlnL| {worst:.2e}")
 
 
+def test_batch_per_item_precision_matches_single_calls(M, ctx, sources):
+    """mbh_batch_create_prec: items of one batch in different precisions, each
+    bit-identical to a single call in its own precision (replay and stream
+    launches); a per-mode-free batch only, and a bad precision is refused."""
+    import torch
+
+    precs = [M.MIXED if i % 3 else M.FP64 for i in range(len(sources))]
+    thetas = [_t(s["walkers"]) for s in sources]
+    lnls = [torch.empty(s["W"], dtype=torch.float64, device="cuda") for s in sources]
+    dhs = [torch.empty((s["W"], 2), dtype=torch.float64, device="cuda") for s in sources]
+    batch = M.Batch(ctx, [s["gref"] for s in sources], thetas, lnls, dhs, precs=precs)
+    single = [M.loglike_heterodyned(ctx, s["gref"], t, p).cpu().numpy() for s, t, p in zip(sources, thetas, precs)]
+    for launch in (batch.launch, batch.launch_direct, batch.launch):
+        for l in lnls:
+            l.fill_(np.nan)
+        launch()
+        torch.cuda.synchronize()
+        for s, l, want, p in zip(sources, lnls, single, precs):
+            assert np.array_equal(l.cpu().numpy(), want), (p, s["modes"], s["nb"], s["W"])
+    with pytest.raises(M.MbhError):
+        M.Batch(ctx, [sources[0]["gref"]], thetas[:1], lnls[:1], precs=[7])
+    print(f"[batch] per-item precision: {sum(p == M.MIXED for p in precs)} mixed, "
+          f"{sum(p == M.FP64 for p in precs)} FP64 items, bit-identical to single calls", flush=True)
+
+
 def test_server_alone_equals_mix_and_backpressure(M, ctx, sources):
     import time
 

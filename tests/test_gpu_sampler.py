@@ -156,6 +156,46 @@ def test_sampler_heterodyned_search_with_reference_updates(M, ctx, src):
     assert r1["reason"] in (M.STOP_CONVERGED, M.STOP_MAX_ITER)
 
 
+def test_sampler_mixed_rungs_split_precision(M, ctx, src):
+    """mixed_rungs = m: the m coldest rungs are evaluated mixed, the others in
+    FP64.  The cold rungs' lnL of the start is bit-identical to that of an
+    all-mixed sampler (the same walker indices within the launch), the hot
+    rungs' equals an all-FP64 sampler's to FP64 rounding; after a short search
+    every held lnL is within the mixed bar of a fresh FP64 evaluation (an
+    exchange carries a walker's lnL with it, so hot rungs may hold values
+    that were evaluated mixed on a cold rung)."""
+    K, W, m = 4, 32, 2
+    lo, hi = OS.prior_box(src["g"].t_obs)
+    betas = 1.0 / 2.0 ** np.arange(K)
+    x0 = _start(src, K, W, 5)
+    gref = M.build_reference_coeffs(ctx, src["gd"], M.MODEL_IMR, M.MODE_22, src["th"], 64)
+    like = M.Sampler.likelihood(ref=gref)
+    start = {}
+    for name, prec, mr in (("fp64", M.FP64, 0), ("mixed", M.MIXED, 0), ("split", M.MIXED, m)):
+        gs = M.Sampler(ctx, betas, W, lo, hi, seed=11, prec=prec, mixed_rungs=mr)
+        gs.set_walkers(x0.reshape(-1, 11), like)
+        start[name] = gs.get()["lnL"].reshape(K, W)
+        if name == "split":
+            split = gs
+        else:
+            gs.close()
+    assert np.array_equal(start["split"][:m], start["mixed"][:m])
+    hot = np.abs(start["split"][m:] - start["fp64"][m:])
+    assert np.all(hot <= 1e-6 + 1e-12 * np.abs(start["fp64"][m:]))
+    split.step(like, 60)
+    st = split.get()
+    fresh = M.loglike_heterodyned(ctx, gref, _t(OS.x_to_theta(st["x"])), M.FP64).cpu().numpy().reshape(K, W)
+    held = st["lnL"].reshape(K, W)
+    d_cold, d_hot = np.abs(held[:m] - fresh[:m]), np.abs(held[m:] - fresh[m:])
+    print(f"[sampler] mixed_rungs={m}: max |held - fresh FP64| cold {d_cold.max():.2e}, hot {d_hot.max():.2e}",
+          flush=True)
+    assert np.all(d_cold <= 1e-3) and np.all(d_hot <= 1e-3)
+    with pytest.raises(M.MbhError):
+        M.Sampler(ctx, betas, W, lo, hi, mixed_rungs=-1)
+    split.close()
+    gref.close()
+
+
 def test_sampler_full_grid_extracted_snr_stop(M, ctx, src):
     """Sec. 3's first module: the full-grid likelihood, stopped when the best
     walker's extracted SNR <d|h> / sqrt(<h|h>) reaches the threshold."""
