@@ -58,7 +58,7 @@ ALGO_FULL_FLOPS_PER_POINT = 250.0
 # their reading for a 64 MiB device copy: factors 0.5002 and 1.000).  Valid
 # only for the kernel sources they were measured on (sha256 over
 # KERNEL_SOURCES); reported as null otherwise.
-COUNTERS = {"src_sha256": "02846ed2bc564448bd9a66ccf633fb7ede5f7fc4a942e11140660b5b7def1212",
+COUNTERS = {"src_sha256": "c583c86c91ffaa3af456d9eec50c36fa42cc9fba6fdaee302bb9be888b0df591",
             "valu_flops_per_edge": 850.7, "full_valu_flops_per_point": 504.7, "bytes_per_launch": 5.482e6}
 
 
@@ -373,6 +373,8 @@ def main():
     ap.add_argument("--full-grid-only", type=int, default=0, metavar="DRAWS",
                     help="time only the full-grid likelihood on this many prior draws of the first source "
                          "(default tile, FP64; for profiler runs) and exit")
+    ap.add_argument("--ingest-only", action="store_true",
+                    help="time only the TDI ingest (X, Y, Z -> A, E, T band) and exit (for profiler runs)")
     ap.add_argument("--mixed-tol", type=float, default=None,
                     help="estimated-error tolerance of the mixed path (library default 9e-4; inf: no FP64 "
                          "recomputation, 0: everything in FP64)")
@@ -390,6 +392,9 @@ def main():
     if args.mixed_tol is not None:
         M.set_mixed_tolerance(ctx, args.mixed_tol)
     grid = I.grid_lisa()
+    if args.ingest_only:
+        print(json.dumps(ingest_leg(M, ctx)))
+        return
     if args.full_grid_only:
         S = Sources(M, ctx, grid, 1)
         draws = torch.as_tensor(I.prior_draws(I.rng_for(3, 0), args.full_grid_only, grid.t_obs), device="cuda")
@@ -505,6 +510,41 @@ def main():
         out["chirp_case"] = chirp_case(M, ctx)
         log(f"[bench] chirp case: {out['chirp_case']}")
     print(json.dumps(out), flush=True)
+
+
+def ingest_leg(M, ctx, reps=20):
+    """TDI X, Y, Z -> A, E, T band (Sec. 2.1) on the step's data grid: one
+    year of samples at dt = 10 s (N = 3 155 760), the band k = 1 .. N/2 that
+    the 1.58e6-bin grid holds; the plan is made by a first, untimed call.
+    Algorithmic bytes: the three series read once (24 N) and the band written
+    once (48 n_freq)."""
+    import torch
+
+    def run(n, dt, alpha):
+        nf = n // 2
+        g = torch.Generator(device="cuda").manual_seed(7)
+        xyz = torch.randn((3, n), dtype=torch.float64, device="cuda", generator=g)
+        st = torch.cuda.Stream()
+        out = torch.empty((3, nf), dtype=torch.complex128, device="cuda")
+        M.tdi_to_aet_fd(ctx, xyz, dt, 0.0, 1, nf, alpha, out=out, stream=st)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        for _ in range(reps):
+            M.tdi_to_aet_fd(ctx, xyz, dt, 0.0, 1, nf, alpha, out=out, stream=st)
+        b.record(st)
+        torch.cuda.synchronize()
+        sec = a.elapsed_time(b) * 1e-3 / reps
+        gbs = (24.0 * n + 48.0 * nf) / sec * 1e-9
+        return {"samples": n, "dt": dt, "band_bins": nf, "tukey_alpha": alpha, "ms_per_call": sec * 1e3,
+                "algorithmic_GB_per_s": gbs, "frac_hbm": gbs / PEAK_HBM_GBS}
+
+    n = int(round(I.YEAR_S / 10.0))  # 2^4 3^4 5 487: the transform takes rocFFT's Bluestein path
+    res = {"year_dt10": run(n, 10.0, 0.0), "year_dt10_tukey0.1": run(n, 10.0, 0.1),
+           # the same year in 2^22 samples, for the cost of the odd length
+           "year_pow2": run(1 << 22, I.YEAR_S / (1 << 22), 0.0)}
+    log(f"[bench] ingest: {res}")
+    return res
 
 
 def sampler_search(M, ctx, item, prec=None, mixed_rungs=0):
@@ -730,6 +770,7 @@ def side_measurements(M, ctx, S, walkers, grid):
     # iterations), stopped when the maximum lnL has moved by less than 1 over
     # 30 checks 150 iterations apart
     out["sampler_search"] = sampler_search(M, ctx, S.items[1])
+    out["ingest"] = ingest_leg(M, ctx)
     # serving: 4 resident sources (the step's physics with 1-6 modes each and
     # 64 / 128 / 256 / 512 bins), a Poisson stream from 64 samplers with
     # request sizes log-uniform in 1-4096 walkers, at fractions of the

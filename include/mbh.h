@@ -116,7 +116,10 @@ mbh_status mbh_data_inner_dd(mbh_data *data, double *dd_out);
  *   layout mbh_data_create takes.
  * Requires 4 <= N < 2^31, dt > 0, finite t0, 0 <= alpha <= 1, k_first >= 1,
  * n_freq >= 2 and k_first + n_freq - 1 <= N / 2.  Allocates device scratch
- * (~72 N bytes) and an FFT plan, and synchronises `stream` before it returns.
+ * (~72 N bytes plus the transform's work area, released in stream order) and,
+ * on the first call with a given N, an FFT plan that the context keeps until
+ * it is destroyed.  Does not synchronise: xyz_dev must stay valid, and
+ * aet_dev is written, in stream order.
  * Errors: MBH_EINVAL, MBH_ENOMEM, MBH_EDEVICE. */
 mbh_status mbh_tdi_to_aet_fd(mbh_ctx *ctx, int64_t n_samples, double dt, double t0,
                              const double *xyz_dev, double tukey_alpha, int64_t k_first,

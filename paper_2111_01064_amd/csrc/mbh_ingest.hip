@@ -57,7 +57,36 @@ __global__ __launch_bounds__(kBlock) void k_band(const double2 *__restrict__ spe
   }
 }
 
-int blocks_for(int64_t n) { return (int)std::min<int64_t>((n + kBlock - 1) / kBlock, 8192); }
+// one element per thread up to 2^28 elements (a partial second pass of a
+// capped grid left a third of the combine kernel's threads idle)
+int blocks_for(int64_t n) { return (int)std::min<int64_t>((n + kBlock - 1) / kBlock, 1 << 20); }
+
+void destroy_plan(void *p) { (void)hipfftDestroy((hipfftHandle)p); }
+
+// The context's plan of three batched D2Z transforms of length N (made on
+// first use, without a work area of its own) and the work-area size it needs.
+// Caller holds ctx->mu.
+hipfftResult plan_for(mbh_ctx *ctx, int64_t N, hipfftHandle *plan, size_t *work) {
+  auto it = ctx->fft_plans.find(N);
+  if (it != ctx->fft_plans.end()) {
+    *plan = (hipfftHandle)it->second;
+    return hipfftGetSize(*plan, work);
+  }
+  hipfftHandle p = nullptr;
+  hipfftResult r = hipfftCreate(&p);
+  if (r != HIPFFT_SUCCESS) return r;
+  int n = (int)N;
+  r = hipfftSetAutoAllocation(p, 0);
+  if (r == HIPFFT_SUCCESS) r = hipfftMakePlanMany(p, 1, &n, nullptr, 1, n, nullptr, 1, n / 2 + 1, HIPFFT_D2Z, 3, work);
+  if (r != HIPFFT_SUCCESS) {
+    (void)hipfftDestroy(p);
+    return r;
+  }
+  ctx->fft_plans[N] = (void *)p;
+  ctx->fft_plan_destroy = destroy_plan;
+  *plan = p;
+  return HIPFFT_SUCCESS;
+}
 
 }  // namespace
 
@@ -80,30 +109,43 @@ extern "C" mbh_status mbh_tdi_to_aet_fd(mbh_ctx *ctx, int64_t n_samples, double 
   if (s != MBH_OK) return s;
   if (hipSetDevice(ctx->device) != hipSuccess) return mbh_fail(MBH_EDEVICE, "hipSetDevice");
   const int64_t n_half = N / 2 + 1;
+  hipfftHandle plan = nullptr;
+  size_t work_bytes = 0;
+  hipfftResult fr;
+  {
+    std::lock_guard<std::mutex> g(ctx->mu);
+    fr = plan_for(ctx, N, &plan, &work_bytes);
+  }
+  if (fr != HIPFFT_SUCCESS) return mbh_fail(MBH_EDEVICE, "hipFFT plan error %d", (int)fr);
   double *aet = nullptr;
   double2 *spec = nullptr;
+  void *work = nullptr;
   if ((s = ctx_alloc_async(ctx, (void **)&aet, (size_t)3 * N * sizeof(double), st)) != MBH_OK) return s;
-  if ((s = ctx_alloc_async(ctx, (void **)&spec, (size_t)3 * n_half * sizeof(double2), st)) != MBH_OK) {
+  if ((s = ctx_alloc_async(ctx, (void **)&spec, (size_t)3 * n_half * sizeof(double2), st)) != MBH_OK ||
+      (s = ctx_alloc_async(ctx, &work, work_bytes, st)) != MBH_OK) {
+    ctx_free_async(ctx, spec, (size_t)3 * n_half * sizeof(double2), st);
     ctx_free_async(ctx, aet, (size_t)3 * N * sizeof(double), st);
     return s;
   }
   hipLaunchKernelGGL(k_tdi_combine, dim3(blocks_for(N)), dim3(kBlock), 0, st, xyz_dev, N,
                      tukey_alpha * (double)(N - 1) / 2.0, aet);
-  hipfftHandle plan = 0;
-  int n = (int)N;
-  hipfftResult fr = hipfftPlanMany(&plan, 1, &n, nullptr, 1, (int)N, nullptr, 1, (int)n_half, HIPFFT_D2Z, 3);
-  if (fr == HIPFFT_SUCCESS) fr = hipfftSetStream(plan, st);
-  if (fr == HIPFFT_SUCCESS) fr = hipfftExecD2Z(plan, aet, (hipfftDoubleComplex *)spec);
+  {
+    // the plan is shared by the context's calls: stream and work area are set
+    // and the transform enqueued under the lock (the launch takes both along)
+    std::lock_guard<std::mutex> g(ctx->mu);
+    fr = hipfftSetStream(plan, st);
+    if (fr == HIPFFT_SUCCESS && work) fr = hipfftSetWorkArea(plan, work);
+    if (fr == HIPFFT_SUCCESS) fr = hipfftExecD2Z(plan, aet, (hipfftDoubleComplex *)spec);
+  }
   if (fr == HIPFFT_SUCCESS)
     hipLaunchKernelGGL(k_band, dim3(blocks_for(3 * n_freq)), dim3(kBlock), 0, st, spec, n_half, N, dt, t0, k_first,
                        n_freq, aet_dev);
-  // the plan's work area is released with the plan: wait for the transform first
-  const hipError_t e = hipStreamSynchronize(st);
-  if (plan) (void)hipfftDestroy(plan);
+  // stream-ordered frees: the buffers are released after the kernels have run
+  ctx_free_async(ctx, work, work_bytes, st);
   ctx_free_async(ctx, spec, (size_t)3 * n_half * sizeof(double2), st);
   ctx_free_async(ctx, aet, (size_t)3 * N * sizeof(double), st);
   if (fr != HIPFFT_SUCCESS) return mbh_fail(MBH_EDEVICE, "hipFFT error %d", (int)fr);
-  if (e != hipSuccess || hipGetLastError() != hipSuccess) return mbh_fail(MBH_EDEVICE, "ingest kernels failed");
+  if (hipGetLastError() != hipSuccess) return mbh_fail(MBH_EDEVICE, "ingest kernels failed to launch");
   return MBH_OK;
 }
 

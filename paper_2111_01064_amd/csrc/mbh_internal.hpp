@@ -28,6 +28,11 @@ struct mbh_ctx {
   // full-grid tile: (frequencies per thread, most walkers per workgroup),
   // keyed by mode class (1: higher modes); absent = (1, 32)
   std::map<int, std::pair<int, int>> full_shape;
+  // ingest: batched real-to-complex transform plans keyed by series length,
+  // made on first use (their work areas come with each call) and destroyed
+  // with the context through fft_plan_destroy
+  std::map<int64_t, void *> fft_plans;
+  void (*fft_plan_destroy)(void *) = nullptr;
   // the caller's reference plus one per live object created from the context
   std::atomic<int> refs{1};
 };

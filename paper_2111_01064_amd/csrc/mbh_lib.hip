@@ -182,7 +182,12 @@ extern "C" mbh_status mbh_create(int device, size_t hbm_budget_bytes, mbh_ctx **
 void ctx_retain(mbh_ctx *ctx) { ctx->refs.fetch_add(1); }
 
 void ctx_release(mbh_ctx *ctx) {
-  if (ctx->refs.fetch_sub(1) == 1) delete ctx;
+  if (ctx->refs.fetch_sub(1) != 1) return;
+  if (ctx->fft_plan_destroy && !ctx->fft_plans.empty()) {
+    (void)hipSetDevice(ctx->device);
+    for (auto &p : ctx->fft_plans) ctx->fft_plan_destroy(p.second);
+  }
+  delete ctx;
 }
 
 extern "C" mbh_status mbh_destroy(mbh_ctx *ctx) {

@@ -345,12 +345,17 @@ def data_create(ctx: Context, d: torch.Tensor, psd: torch.Tensor, f0: float, df:
 
 
 def tdi_to_aet_fd(ctx: Context, xyz: torch.Tensor, dt: float, t0: float, k_first: int, n_freq: int,
-                  alpha: float = 0.0, stream=None) -> torch.Tensor:
-    """mbh_tdi_to_aet_fd: xyz float64 [3][N] on the device -> complex128 [3][n_freq]."""
+                  alpha: float = 0.0, stream=None, out: torch.Tensor | None = None) -> torch.Tensor:
+    """mbh_tdi_to_aet_fd: xyz float64 [3][N] on the device -> complex128 [3][n_freq]
+    (into `out` when given)."""
     N = xyz.shape[1]
-    out = torch.empty((3, n_freq), dtype=torch.complex128, device=xyz.device)
+    if out is None:
+        out = torch.empty((3, n_freq), dtype=torch.complex128, device=xyz.device)
+    if out.dtype != torch.complex128:
+        raise TypeError("out must be complex128")
     _check(_L.mbh_tdi_to_aet_fd(ctx.h, N, dt, t0, _dev_ptr(xyz, torch.float64, (3, N)), alpha, k_first, n_freq,
-                                torch.view_as_real(out).data_ptr(), _stream(stream)), "mbh_tdi_to_aet_fd")
+                                _dev_ptr(torch.view_as_real(out), torch.float64, (3, n_freq, 2)), _stream(stream)),
+           "mbh_tdi_to_aet_fd")
     return out
 
 
