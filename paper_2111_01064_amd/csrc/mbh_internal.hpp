@@ -148,3 +148,6 @@ mbh_status ctx_alloc(mbh_ctx *ctx, void **p, size_t bytes);
 void ctx_free(mbh_ctx *ctx, void *p, size_t bytes);
 mbh_status ctx_alloc_async(mbh_ctx *ctx, void **p, size_t bytes, hipStream_t st);
 void ctx_free_async(mbh_ctx *ctx, void *p, size_t bytes, hipStream_t st);
+// The device copy of a batch's items (for kernels that run a batch's setup
+// or totals fused with their own work).
+const mbh::WorkItem *batch_device_items(const mbh_batch *b);

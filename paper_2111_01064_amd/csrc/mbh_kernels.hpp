@@ -867,22 +867,14 @@ struct WalkerTile {
   int64_t w_begin;
 };
 
-// Per-walker totals of the main pass: the walker's slots are added in slot
-// order and the outputs written.  One workgroup of kWalkerTile threads per
-// walker tile (items, wtiles) or, for a single item passed by value in `one`
-// with items == nullptr, per kWalkerTile consecutive walkers.
-static __global__ __launch_bounds__(kWalkerTile) void k_het_final(const WorkItem *__restrict__ items, WorkItem one,
-                                                                  const WalkerTile *__restrict__ wtiles) {
-  int64_t w0 = (int64_t)blockIdx.x * kWalkerTile;
-  int ii = 0;
-  if (items) {
-    const WalkerTile tl = wtiles[blockIdx.x];
-    ii = tl.item;
-    w0 = tl.w_begin;
-  }
-  const WorkItem &it = items ? items[ii] : one;
-  const int64_t w = w0 + threadIdx.x;
-  if (w >= it.W) return;
+struct WalkerTotals {
+  double lnL, dh, hh;
+};
+
+// lnL, <d|h> and <h|h> of walker w of an item: its partial slots added in
+// slot order and the reference's h0 terms added; written to the item's
+// outputs and returned
+__device__ inline WalkerTotals het_walker_totals(const WorkItem &it, int64_t w) {
   double s[3] = {0.0, 0.0, 0.0};
   int n_slot = 1;
   if (it.G == 0) n_slot = (int)((w * it.E + it.E - 2) / kChunk - (w * it.E) / kChunk) + 1;
@@ -898,11 +890,30 @@ static __global__ __launch_bounds__(kWalkerTile) void k_het_final(const WorkItem
   }
   const bool valid = it.wc[w].valid;
   const RefMeta &m = *it.ref.meta;
-  it.lnL[w] = valid ? m.lnL0 + s[0] : -INFINITY;
+  const WalkerTotals r{valid ? m.lnL0 + s[0] : -INFINITY, valid ? m.dh0 + s[1] : 0.0, valid ? m.hh0 + s[2] : 0.0};
+  it.lnL[w] = r.lnL;
   if (it.dhhh) {
-    it.dhhh[2 * w] = valid ? m.dh0 + s[1] : 0.0;
-    it.dhhh[2 * w + 1] = valid ? m.hh0 + s[2] : 0.0;
+    it.dhhh[2 * w] = r.dh;
+    it.dhhh[2 * w + 1] = r.hh;
   }
+  return r;
+}
+
+// Per-walker totals of the main pass.  One workgroup of kWalkerTile threads
+// per walker tile (items, wtiles) or, for a single item passed by value in
+// `one` with items == nullptr, per kWalkerTile consecutive walkers.
+static __global__ __launch_bounds__(kWalkerTile) void k_het_final(const WorkItem *__restrict__ items, WorkItem one,
+                                                                  const WalkerTile *__restrict__ wtiles) {
+  int64_t w0 = (int64_t)blockIdx.x * kWalkerTile;
+  int ii = 0;
+  if (items) {
+    const WalkerTile tl = wtiles[blockIdx.x];
+    ii = tl.item;
+    w0 = tl.w_begin;
+  }
+  const WorkItem &it = items ? items[ii] : one;
+  const int64_t w = w0 + threadIdx.x;
+  if (w < it.W) (void)het_walker_totals(it, w);
 }
 
 // single-item path: walker constants, two threads per walker (intrinsic and

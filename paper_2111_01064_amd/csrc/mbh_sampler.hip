@@ -85,16 +85,16 @@ struct SmpParams {
   const double *lo, *hi, *betas;
 };
 
-// Proposals of one half (walkers half * W/2 .. of every rung), one thread
-// per (rung, walker): the move kind, then a stretch from a partner of the
-// other half or a sky-mode hop.  Roundings as written (no contraction), so
-// that the proposals follow the operations of their definition exactly.
-__global__ __launch_bounds__(256) void k_smp_propose(SmpParams p, int half, uint32_t it, const double *__restrict__ x,
-                                                     double *__restrict__ y, double *__restrict__ thy,
-                                                     int32_t *__restrict__ kind, double *__restrict__ lz) {
+// Proposal t of one half (walker half * W/2 + t mod W/2 of rung t div W/2):
+// the move kind, then a stretch from a partner of the other half or a
+// sky-mode hop.  Roundings as written (no contraction), so that the proposals
+// follow the operations of their definition exactly.  The proposal's theta
+// also goes to th_out when it is given.
+__device__ __forceinline__ void smp_propose_one(const SmpParams &p, int half, uint32_t it, int t,
+                                                const double *__restrict__ x, double *__restrict__ y,
+                                                double *__restrict__ thy, int32_t *__restrict__ kind,
+                                                double *__restrict__ lz, double *th_out) {
   const int H = p.W / 2;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= p.K * H) return;
   const int k = t / H, i = t - k * H, w = half * H + i;
   const U4 u = philox_uniforms(p.seed, it, (uint32_t)(k * p.W + w), kStreamMove, (uint32_t)half);
   int kd = kStretch;
@@ -135,28 +135,36 @@ __global__ __launch_bounds__(256) void k_smp_propose(SmpParams p, int half, uint
   x_to_theta(yv, th);
   if (!in) th[0] = NAN;  // outside the prior: the likelihood returns -inf, the walker stays
   for (int d = 0; d < kDim; ++d) to[d] = th[d];
+  if (th_out)
+    for (int d = 0; d < kDim; ++d) th_out[d] = th[d];
   kind[t] = kd;
   lz[t] = l;
 }
 
-// Metropolis decision of each walker of one half, and the acceptance counts
-// per rung and move kind: accept when ln v < ln z^(d-1) + beta (lnL_y - lnL)
-// inside the prior with a finite lnL_y (a walker whose lnL is not finite takes
-// any such proposal).
-__global__ __launch_bounds__(256) void k_smp_accept(SmpParams p, int half, uint32_t it, const double *__restrict__ y,
-                                                    const int32_t *__restrict__ kind, const double *__restrict__ lz,
-                                                    const double *__restrict__ lny, const double *__restrict__ dhy,
-                                                    double *__restrict__ x, double *__restrict__ lnL,
-                                                    double *__restrict__ dhhh, unsigned long long *__restrict__ counts) {
-  const int H = p.W / 2;
+// the proposals of one half, one thread per (rung, walker)
+__global__ __launch_bounds__(256) void k_smp_propose(SmpParams p, int half, uint32_t it, const double *__restrict__ x,
+                                                     double *__restrict__ y, double *__restrict__ thy,
+                                                     int32_t *__restrict__ kind, double *__restrict__ lz) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= p.K * H) return;
+  if (t < p.K * (p.W / 2)) smp_propose_one(p, half, it, t, x, y, thy, kind, lz, nullptr);
+}
+
+// Metropolis decision of proposal t of one half: accept when
+// ln v < ln z^(d-1) + beta (lnL_y - lnL) inside the prior with a finite lnL_y
+// (a walker whose lnL is not finite takes any such proposal); an accepted
+// proposal replaces the walker, its lnL and overlaps.  Returns
+// 2 (4 k + kind) + 1 when the proposal was accepted, 2 (4 k + kind) if not.
+__device__ __forceinline__ int smp_accept_one(const SmpParams &p, int half, uint32_t it, int t,
+                                              const double *__restrict__ y, const int32_t *__restrict__ kind,
+                                              const double *__restrict__ lz, double ly, double dh, double hh,
+                                              bool has_dh, double *__restrict__ x, double *__restrict__ lnL,
+                                              double *__restrict__ dhhh) {
+  const int H = p.W / 2;
   const int k = t / H, i = t - k * H, w = half * H + i;
   const U4 v = philox_uniforms(p.seed, it, (uint32_t)(k * p.W + w), kStreamMove, (uint32_t)(half + 2));
   const double *yv = y + (int64_t)t * kDim;
   bool in = true;
   for (int d = 0; d < kDim; ++d) in = in && yv[d] >= p.lo[d] && yv[d] <= p.hi[d];
-  const double ly = lny[t];
   const int64_t o = (int64_t)k * p.W + w;
   const double cur = lnL[o];
   bool acc = false;
@@ -164,16 +172,49 @@ __global__ __launch_bounds__(256) void k_smp_accept(SmpParams p, int half, uint3
     const double la = isfinite(cur) ? __dadd_rn(lz[t], __dmul_rn(p.betas[k], __dadd_rn(ly, -cur))) : INFINITY;
     acc = log(v.u[0]) < la;
   }
-  const int kd = kind[t];
-  atomicAdd(&counts[(k * 4 + kd) * 2 + 1], 1ull);
-  if (!acc) return;
-  atomicAdd(&counts[(k * 4 + kd) * 2], 1ull);
+  const int c = 2 * (k * 4 + kind[t]);
+  if (!acc) return c;
   for (int d = 0; d < kDim; ++d) x[o * kDim + d] = yv[d];
   lnL[o] = ly;
-  if (dhy) {
-    dhhh[2 * o] = dhy[2 * t];
-    dhhh[2 * o + 1] = dhy[2 * t + 1];
+  if (has_dh) {
+    dhhh[2 * o] = dh;
+    dhhh[2 * o + 1] = hh;
   }
+  return c + 1;
+}
+
+// The acceptance counters (accepted, proposed) per rung and move kind, K x 4
+// pairs: each workgroup counts in LDS, then adds its nonzero counts.
+constexpr int kMaxCounters = 64 * 4;
+__device__ __forceinline__ void smp_count(unsigned *cnt, int code) {
+  if (code < 0) return;
+  atomicAdd(&cnt[code >> 1], 1u << 16);  // proposed: high half
+  if (code & 1) atomicAdd(&cnt[code >> 1], 1u);  // accepted: low half
+}
+__device__ __forceinline__ void smp_count_flush(const unsigned *cnt, int n_cnt, unsigned long long *counts) {
+  for (int c = threadIdx.x; c < n_cnt; c += blockDim.x) {
+    const unsigned v = cnt[c];
+    if (v & 0xFFFFu) atomicAdd(&counts[2 * c], (unsigned long long)(v & 0xFFFFu));
+    if (v >> 16) atomicAdd(&counts[2 * c + 1], (unsigned long long)(v >> 16));
+  }
+}
+
+// the decisions of one half from the proposals' lnL (and overlaps) in lny, dhy
+__global__ __launch_bounds__(256) void k_smp_accept(SmpParams p, int half, uint32_t it, const double *__restrict__ y,
+                                                    const int32_t *__restrict__ kind, const double *__restrict__ lz,
+                                                    const double *__restrict__ lny, const double *__restrict__ dhy,
+                                                    double *__restrict__ x, double *__restrict__ lnL,
+                                                    double *__restrict__ dhhh, unsigned long long *__restrict__ counts) {
+  __shared__ unsigned cnt[kMaxCounters];
+  const int n_cnt = p.K * 4;
+  for (int c = threadIdx.x; c < n_cnt; c += blockDim.x) cnt[c] = 0u;
+  __syncthreads();
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < p.K * (p.W / 2))
+    smp_count(cnt, smp_accept_one(p, half, it, t, y, kind, lz, lny[t], dhy ? dhy[2 * t] : 0.0,
+                                  dhy ? dhy[2 * t + 1] : 0.0, dhy != nullptr, x, lnL, dhhh));
+  __syncthreads();
+  smp_count_flush(cnt, n_cnt, counts);
 }
 
 // Exchanges between adjacent rungs, k = 0, 1, ... in turn, in one workgroup:
@@ -229,9 +270,8 @@ constexpr int kSwapPrefetch = 16;  // pairs of rungs whose ln v a thread holds i
 // The uniforms of the exchanges do not depend on the walkers: ln v of every
 // (pair of rungs k, walker i) and the shift s of every pair, over the whole
 // chip, before the exchange kernel (logv [(K-1) W], shift [K-1]).
-__global__ __launch_bounds__(256) void k_smp_swap_prep(SmpParams p, uint32_t it, double *__restrict__ logv,
-                                                       int32_t *__restrict__ shift) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void smp_swap_uniforms(const SmpParams &p, uint32_t it, int t, double *__restrict__ logv,
+                                                  int32_t *__restrict__ shift) {
   const int W = p.W, np = (p.K - 1) * W;
   if (t < np) {
     const int k = t / W, i = t - k * W;
@@ -242,6 +282,69 @@ __global__ __launch_bounds__(256) void k_smp_swap_prep(SmpParams p, uint32_t it,
     const U4 us = philox_uniforms(p.seed, it, (uint32_t)t, kStreamSwap, 0u);
     shift[t] = min((int)floor(__dmul_rn(us.u[0], (double)W)), W - 1);
   }
+}
+__global__ __launch_bounds__(256) void k_smp_swap_prep(SmpParams p, uint32_t it, double *__restrict__ logv,
+                                                       int32_t *__restrict__ shift) {
+  smp_swap_uniforms(p, it, blockIdx.x * blockDim.x + threadIdx.x, logv, shift);
+}
+
+// A sampler step with the heterodyned likelihood runs the half batch's main
+// pass between two kernels of its own, each fused with the batch stage next
+// to it (so a half step is three launches, not five):
+//  * proposals and the batch's walker constants: 64 proposals per workgroup
+//    of 128 threads; the first 64 threads propose (their theta kept in LDS),
+//    then the two threads of each proposal set its intrinsic and extrinsic
+//    constants in the batch item that holds it (items[0] holds proposals
+//    0 .. n0-1, items[1] the rest).  With logv set, the iteration's exchange
+//    uniforms are drawn too, over the grid.
+//  * totals and decisions: one thread per proposal adds its partial sums
+//    (as the batch's totals stage, writing the item's outputs) and takes the
+//    Metropolis decision from them.
+// Proposals, constants, totals and decisions are those of the separate
+// kernels bit for bit.
+__global__ __launch_bounds__(128) void k_smp_propose_setup(SmpParams p, int half, uint32_t it,
+                                                           const double *__restrict__ x, double *__restrict__ y,
+                                                           double *__restrict__ thy, int32_t *__restrict__ kind,
+                                                           double *__restrict__ lz, const WorkItem *__restrict__ items,
+                                                           int n0, double *__restrict__ logv,
+                                                           int32_t *__restrict__ shift) {
+  __shared__ double th_s[64][kDim];
+  const int nh = p.K * (p.W / 2);
+  const int j = threadIdx.x & 63;
+  const int t = blockIdx.x * 64 + j;
+  if (threadIdx.x < 64 && t < nh) smp_propose_one(p, half, it, t, x, y, thy, kind, lz, th_s[j]);
+  __syncthreads();
+  if (t < nh) {
+    const int ii = t < n0 ? 0 : 1;
+    const WorkItem &itm = items[ii];
+    const int64_t w = ii ? t - n0 : t;
+    walker_setup(th_s[j], itm.model, itm.ref.modes, itm.wc[w], threadIdx.x < 64 ? 1 : 2);
+  }
+  if (logv)
+    for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < (p.K - 1) * p.W; u += gridDim.x * blockDim.x)
+      smp_swap_uniforms(p, it, u, logv, shift);
+}
+
+__global__ __launch_bounds__(256) void k_smp_final_accept(SmpParams p, int half, uint32_t it,
+                                                          const WorkItem *__restrict__ items, int n0,
+                                                          const double *__restrict__ y,
+                                                          const int32_t *__restrict__ kind,
+                                                          const double *__restrict__ lz, double *__restrict__ x,
+                                                          double *__restrict__ lnL, double *__restrict__ dhhh,
+                                                          unsigned long long *__restrict__ counts) {
+  __shared__ unsigned cnt[kMaxCounters];
+  const int n_cnt = p.K * 4;
+  for (int c = threadIdx.x; c < n_cnt; c += blockDim.x) cnt[c] = 0u;
+  __syncthreads();
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < p.K * (p.W / 2)) {
+    const int ii = t < n0 ? 0 : 1;
+    const WorkItem &itm = items[ii];
+    const WalkerTotals r = het_walker_totals(itm, ii ? t - n0 : t);
+    smp_count(cnt, smp_accept_one(p, half, it, t, y, kind, lz, r.lnL, r.dh, r.hh, itm.dhhh != nullptr, x, lnL, dhhh));
+  }
+  __syncthreads();
+  smp_count_flush(cnt, n_cnt, counts);
 }
 
 __global__ __launch_bounds__(kSwapThreads) void k_smp_swap_lds(SmpParams p, const double *__restrict__ logv,
@@ -373,6 +476,7 @@ struct mbh_sampler {
   // over the whole population, for the reference they were made for
   const mbh_ref *bref = nullptr;
   mbh_batch *half_batch = nullptr, *all_batch = nullptr;
+  int half_n0 = 0;  // proposals in the half batch's first item
 };
 
 static void sampler_free(mbh_sampler *s) {
@@ -474,6 +578,7 @@ static mbh_status smp_batches(mbh_sampler *s, const mbh_ref *ref) {
     const int64_t W2[2] = {(int64_t)m * per, (int64_t)(s->K - m) * per};
     MBH_TRY(mbh_batch_create_prec(s->ctx, n_items, r2, th, W2, l, d, p2, b == 0 ? &s->half_batch : &s->all_batch));
   }
+  s->half_n0 = m * s->H;
   s->bref = ref;
   return MBH_OK;
 }
@@ -550,15 +655,18 @@ extern "C" mbh_status mbh_sampler_accept(mbh_sampler *s, int half, const double 
   return MBH_OK;
 }
 
-extern "C" mbh_status mbh_sampler_swap(mbh_sampler *s, hipStream_t st) {
-  if (!s) return mbh_fail(MBH_EINVAL, "null sampler");
-  HIP_TRY(hipSetDevice(s->ctx->device));
+static bool swap_in_lds(const mbh_sampler *s) { return s->K > 1 && s->K * s->W <= kSwapLdsMax; }
+
+// the exchanges of the iteration; `drawn`: their uniforms are already in
+// swap_logv, swap_shift
+static mbh_status smp_swap(mbh_sampler *s, bool drawn, hipStream_t st) {
   const int n = s->K * s->W;
-  if (s->K > 1 && n <= kSwapLdsMax) {
+  if (swap_in_lds(s)) {
     const size_t lds = (size_t)n * (sizeof(double) + sizeof(int)) + (size_t)s->K * (sizeof(double) + 2 * sizeof(int));
     const int np = (s->K - 1) * s->W;
-    hipLaunchKernelGGL(k_smp_swap_prep, dim3((np + 255) / 256), dim3(256), 0, st, s->p, (uint32_t)s->it, s->swap_logv,
-                       s->swap_shift);
+    if (!drawn)
+      hipLaunchKernelGGL(k_smp_swap_prep, dim3((np + 255) / 256), dim3(256), 0, st, s->p, (uint32_t)s->it,
+                         s->swap_logv, s->swap_shift);
     hipLaunchKernelGGL(k_smp_swap_lds, dim3(1), dim3(kSwapThreads), lds, st, s->p, s->swap_logv, s->swap_shift,
                        s->swap_perm, s->lnL, s->dhhh, s->swaps);
     hipLaunchKernelGGL(k_smp_permute, dim3((n * kDim + 255) / 256), dim3(256), 0, st, n, s->swap_perm, s->x, s->x_alt);
@@ -572,16 +680,45 @@ extern "C" mbh_status mbh_sampler_swap(mbh_sampler *s, hipStream_t st) {
   return MBH_OK;
 }
 
+extern "C" mbh_status mbh_sampler_swap(mbh_sampler *s, hipStream_t st) {
+  if (!s) return mbh_fail(MBH_EINVAL, "null sampler");
+  HIP_TRY(hipSetDevice(s->ctx->device));
+  return smp_swap(s, false, st);
+}
+
+// one half step with the heterodyned likelihood: proposals fused with the
+// half batch's setup, its main pass, totals fused with the decisions
+static mbh_status smp_half_het(mbh_sampler *s, const mbh_ref *ref, int half, hipStream_t st) {
+  MBH_TRY(smp_batches(s, ref));
+  const int nh = s->K * s->H;
+  const WorkItem *items = batch_device_items(s->half_batch);
+  const bool draw = half == 0 && swap_in_lds(s);
+  hipLaunchKernelGGL(k_smp_propose_setup, dim3((nh + 63) / 64), dim3(128), 0, st, s->p, half, (uint32_t)s->it, s->x,
+                     s->y, s->thy, s->kind, s->lz, items, s->half_n0, draw ? s->swap_logv : nullptr,
+                     draw ? s->swap_shift : nullptr);
+  MBH_TRY(mbh_batch_launch_stage(s->half_batch, MBH_STAGE_MAIN, st));
+  hipLaunchKernelGGL(k_smp_final_accept, dim3((nh + 255) / 256), dim3(256), 0, st, s->p, half, (uint32_t)s->it,
+                     items, s->half_n0, s->y, s->kind, s->lz, s->x, s->lnL, s->dhhh, s->counts);
+  HIP_TRY(hipGetLastError());
+  return MBH_OK;
+}
+
 extern "C" mbh_status mbh_sampler_step(mbh_sampler *s, const mbh_likelihood *like, int64_t n_iter, hipStream_t st) {
   if (!s || n_iter < 0) return mbh_fail(MBH_EINVAL, "bad argument");
   MBH_TRY(check_like(s, like));
+  HIP_TRY(hipSetDevice(s->ctx->device));
   for (int64_t i = 0; i < n_iter; ++i) {
+    if (like->ref) {
+      for (int half = 0; half < 2; ++half) MBH_TRY(smp_half_het(s, like->ref, half, st));
+      MBH_TRY(smp_swap(s, swap_in_lds(s), st));
+      continue;
+    }
     for (int half = 0; half < 2; ++half) {
       MBH_TRY(mbh_sampler_propose(s, half, st));
       MBH_TRY(smp_like(s, like, true, st));
       MBH_TRY(mbh_sampler_accept(s, half, s->lny, s->dhy, st));
     }
-    MBH_TRY(mbh_sampler_swap(s, st));
+    MBH_TRY(smp_swap(s, false, st));
   }
   return MBH_OK;
 }

@@ -399,6 +399,8 @@ extern "C" mbh_status mbh_batch_create(mbh_ctx *ctx, int n, const mbh_ref *const
   return mbh_batch_create_prec(ctx, n, refs, theta_dev, W, lnL_dev, dh_hh_dev, precs.data(), out);
 }
 
+const WorkItem *batch_device_items(const mbh_batch *b) { return b->items; }
+
 extern "C" mbh_status mbh_batch_launch(mbh_batch *b, hipStream_t st) {
   if (!b) return mbh_fail(MBH_EINVAL, "null batch");
   HIP_TRY(hipSetDevice(b->ctx->device));

@@ -156,6 +156,54 @@ def test_sampler_heterodyned_search_with_reference_updates(M, ctx, src):
     assert r1["reason"] in (M.STOP_CONVERGED, M.STOP_MAX_ITER)
 
 
+@pytest.mark.parametrize("prec,mixed_rungs", [("fp64", 0), ("mixed", 0), ("mixed", 2)])
+def test_sampler_step_equals_separate_calls(M, ctx, src, prec, mixed_rungs):
+    """mbh_sampler_step with the heterodyned likelihood fuses the proposals
+    with the batch's walker setup and the batch's totals with the decisions;
+    its states must equal, bit for bit, those of the separate calls
+    (propose, heterodyned calls over the proposals' theta, accept, swap)."""
+    import torch
+
+    K, W, n_it = 4, 32, 8
+    p = M.FP64 if prec == "fp64" else M.MIXED
+    lo, hi = OS.prior_box(src["g"].t_obs)
+    betas = 1.0 / 2.0 ** np.arange(K)
+    x0 = _start(src, K, W, 6)
+    gref = M.build_reference_coeffs(ctx, src["gd"], M.MODEL_IMR, M.MODE_22, src["th"], 64)
+    like = M.Sampler.likelihood(ref=gref)
+    a = M.Sampler(ctx, betas, W, lo, hi, seed=99, prec=p, mixed_rungs=mixed_rungs)
+    b = M.Sampler(ctx, betas, W, lo, hi, seed=99, prec=p, mixed_rungs=mixed_rungs)
+    a.set_walkers(x0.reshape(-1, 11), like)
+    b.set_walkers(x0.reshape(-1, 11), like)
+    a.step(like, n_it)
+    n = K * W // 2
+    # the half batch's items: the mixed rungs' proposals, then the rest in FP64
+    m = mixed_rungs if (p == M.MIXED and 0 < mixed_rungs < K) else K
+    parts = [(0, m * W // 2, p), (m * W // 2, n, M.FP64)] if m < K else [(0, n, p)]
+    for _ in range(n_it):
+        for half in (0, 1):
+            b.propose(half)
+            _, th, _ = b.proposals()
+            lnl = torch.empty(n, dtype=torch.float64, device="cuda")
+            dh = torch.empty((n, 2), dtype=torch.float64, device="cuda")
+            for lo_i, hi_i, pr in parts:
+                M.loglike_heterodyned(ctx, gref, _t(th[lo_i:hi_i]), pr, lnL=lnl[lo_i:hi_i], dh_hh=dh[lo_i:hi_i])
+            b.accept(half, lnl, dh)
+        b.swap()
+    sa, sb = a.get(), b.get()
+    for key in ("x", "lnL", "dh_hh"):
+        assert np.array_equal(sa[key], sb[key]), key
+    assert sa["iteration"] == sb["iteration"] == n_it
+    ta, tb = a.stats(), b.stats()
+    for key in ("accepted", "proposed", "swaps"):
+        assert np.array_equal(ta[key], tb[key]), key
+    print(f"[sampler] fused step == separate calls ({prec}, mixed_rungs={mixed_rungs}): {n_it} iterations, "
+          f"{int(ta['accepted'].sum())} moves accepted", flush=True)
+    a.close()
+    b.close()
+    gref.close()
+
+
 def test_sampler_mixed_rungs_split_precision(M, ctx, src):
     """mixed_rungs = m: the m coldest rungs are evaluated mixed, the others in
     FP64.  The cold rungs' lnL of the start is bit-identical to that of an
