@@ -512,6 +512,78 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def served_samplers(M, ctx, S5, refs, prec, n_iter=200, warm=5):
+    """Samplers as clients of the request server (Sec. 3's search with its
+    likelihood calls served, mbh_sampler_step_served): 16 tempered samplers on
+    the 4 resident sources (sampler i on source i mod 4), 8 rungs (T_k = 2^k)
+    of 8, 32, 128 or 512 walkers, so that each half step is one request of
+    32, 128, 512 or 2048 walkers; each sampler runs in a thread of its own on
+    its own stream, `warm` iterations, then n_iter timed."""
+    import torch
+
+    K, sizes, n_smp = 8, (8, 32, 128, 512), 16
+    lo = np.array([math.log(1e5), 0.05, -0.99, -0.99, 1e-2, 0.0, -1.0, 0.0, -1.0, 0.0, 0.0])
+    hi = np.array([math.log(1e8), 1.0, 0.99, 0.99, 1e3, 2 * math.pi, 1.0, 2 * math.pi, 1.0, math.pi,
+                   S5.items[0]["data"].t_obs])
+    betas = 1.0 / 2.0 ** np.arange(K)
+    sigs = []
+    for item in S5.items:
+        sigs.append(I.curvature_sigma(lambda x, r=item["ref"]: M.loglike_heterodyned(
+            ctx, r, torch.as_tensor(x, device="cuda"), M.FP64).cpu().numpy(), item["th"]))
+    srv = M.Server(ctx, refs, max_inflight=3, max_batch_walkers=65536, hbm_budget_bytes=2 << 30, prec=prec)
+    smps, Ws = [], []
+    for i in range(n_smp):
+        src, W = i % 4, sizes[(i // 4) % 4]
+        item = S5.items[src]
+        cloud = I.walker_cloud(item["th"], sigs[src], tuple(2.0 ** k for k in range(K)), W, I.rng_for(7, i))
+        x0 = cloud.copy()
+        x0[:, 0] = np.log(cloud[:, 0])
+        x0[:, 6] = np.cos(cloud[:, 6])
+        x0[:, 8] = np.sin(cloud[:, 8])
+        smp = M.Sampler(ctx, betas, W, lo, hi, seed=20211101 + i, prec=prec)
+        smp.set_walkers(np.clip(x0, lo, hi), M.Sampler.likelihood(ref=item["ref"]))
+        smps.append(smp)
+        Ws.append(W)
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream() for _ in range(n_smp)]
+    res = {}
+
+    def run(i, n):
+        t0 = time.perf_counter()
+        lat = smps[i].step_served(srv, i % 4, n, stream=streams[i])
+        res[i] = (lat, time.perf_counter() - t0)
+
+    def all_threads(n):
+        th = [threading.Thread(target=run, args=(i, n)) for i in range(n_smp)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        if len(res) != n_smp:
+            raise RuntimeError("a served sampler failed")
+
+    all_threads(warm)
+    res.clear()
+    b0 = srv.stats()
+    t0 = time.perf_counter()
+    all_threads(n_iter)
+    wall = time.perf_counter() - t0
+    b1 = srv.stats()
+    lat = np.concatenate([res[i][0] for i in range(n_smp)]) * 1e3
+    evals = sum(n_iter * K * W for W in Ws)
+    batches = b1["batches"] - b0["batches"]
+    out = {"samplers": n_smp, "rungs": K, "request_walkers": [K * w // 2 for w in sizes], "iterations_each": n_iter,
+           "wall_s": wall, "evals_per_s": evals / wall, "requests_per_s": 2 * n_iter * n_smp / wall,
+           "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+           "iteration_ms_median": float(np.median([res[i][1] / n_iter for i in range(n_smp)]) * 1e3),
+           "requests_per_batch": 2 * n_iter * n_smp / max(1, batches)}
+    for smp in smps:
+        smp.close()
+    srv.close()
+    log(f"[bench] samplers as server clients ({'fp64' if prec == M.FP64 else 'mixed'}): {out}")
+    return out
+
+
 def ingest_leg(M, ctx, reps=20):
     """TDI X, Y, Z -> A, E, T band (Sec. 2.1) on the step's data grid: one
     year of samples at dt = 10 s (N = 3 155 760), the band k = 1 .. N/2 that
@@ -815,6 +887,8 @@ def side_measurements(M, ctx, S, walkers, grid):
                   update=(datas, lnls, 100))
     serve["mixed_rho0.5_with_reference_updates"] = r
     log(f"[bench] serve mixed at 0.5 x capacity with a reference update every 100 requests: {r}")
+    for name, prec in (("mixed", M.MIXED), ("fp64", M.FP64)):
+        serve[f"samplers_as_clients_{name}"] = served_samplers(M, ctx, S5, refs, prec)
     out["serving"] = serve
     return out
 

@@ -567,8 +567,28 @@ mbh_status mbh_sampler_destroy(mbh_sampler *s);
  * under `like` on `stream`. */
 mbh_status mbh_sampler_set_walkers(mbh_sampler *s, const double *x_host, const double *lnL_host,
                                    const mbh_likelihood *like, hipStream_t stream);
-/* n_iter iterations on `stream` (asynchronous). */
+/* n_iter iterations on `stream` (asynchronous).  With the heterodyned
+ * likelihood a half step is three launches: the proposals fused with the
+ * walker setup of the sampler's batch, the batch's main pass, its per-walker
+ * totals fused with the decisions; the results equal those of the separate
+ * calls below bit for bit. */
 mbh_status mbh_sampler_step(mbh_sampler *s, const mbh_likelihood *like, int64_t n_iter, hipStream_t stream);
+/* n_iter iterations with the heterodyned likelihood of a request server's
+ * resident reference ref_index (Sec. 3's search as one of the server's
+ * clients): each half step's proposals are made on the device, copied to the
+ * host and submitted as one request of n_temps * walkers_per_temp / 2
+ * walkers; when it completes, its lnL and <d|h>, <h|h> go back to the device
+ * and the decisions are taken there.  Synchronous (the stream is
+ * synchronised at every half step; the sampler's pinned host staging is
+ * allocated on first use).  The states equal those of mbh_sampler_step under
+ * the same reference with the server's precision and mixed_rungs 0, bit for
+ * bit.  latency_s [2 n_iter] or NULL: each request's latency (completion
+ * minus submission).  Several samplers may be driven this way from separate
+ * threads, each on its own stream.
+ * Errors: MBH_EINVAL, MBH_EDEVICE and those of mbh_server_submit and
+ * mbh_server_wait. */
+mbh_status mbh_sampler_step_served(mbh_sampler *s, mbh_server *srv, int ref_index, int64_t n_iter,
+                                   hipStream_t stream, double *latency_s);
 /* The parts of one iteration, for callers that evaluate the likelihood
  * themselves: mbh_sampler_propose writes the proposals of half 0 or 1 of
  * every rung (mbh_sampler_proposals copies them out: x and theta

@@ -477,9 +477,14 @@ struct mbh_sampler {
   const mbh_ref *bref = nullptr;
   mbh_batch *half_batch = nullptr, *all_batch = nullptr;
   int half_n0 = 0;  // proposals in the half batch's first item
+  // pinned host staging of one half step's proposals and results for a
+  // request server (allocated on first use): theta [K W/2][11], lnL, <d|h> <h|h>
+  double *h_theta = nullptr, *h_lnl = nullptr, *h_dh = nullptr;
 };
 
 static void sampler_free(mbh_sampler *s) {
+  for (double *h : {s->h_theta, s->h_lnl, s->h_dh})
+    if (h) (void)hipHostFree(h);
   if (s->half_batch) mbh_batch_release(s->half_batch);
   if (s->all_batch) mbh_batch_release(s->all_batch);
   for (auto &a : s->allocs) ctx_free(s->ctx, a.first, a.second);
@@ -716,6 +721,35 @@ extern "C" mbh_status mbh_sampler_step(mbh_sampler *s, const mbh_likelihood *lik
     for (int half = 0; half < 2; ++half) {
       MBH_TRY(mbh_sampler_propose(s, half, st));
       MBH_TRY(smp_like(s, like, true, st));
+      MBH_TRY(mbh_sampler_accept(s, half, s->lny, s->dhy, st));
+    }
+    MBH_TRY(smp_swap(s, false, st));
+  }
+  return MBH_OK;
+}
+
+extern "C" mbh_status mbh_sampler_step_served(mbh_sampler *s, mbh_server *srv, int ref_index, int64_t n_iter,
+                                              hipStream_t st, double *latency_s) {
+  if (!s || !srv || n_iter < 0) return mbh_fail(MBH_EINVAL, "bad argument");
+  HIP_TRY(hipSetDevice(s->ctx->device));
+  const int64_t nh = (int64_t)s->K * s->H;
+  if (!s->h_theta) {
+    HIP_TRY(hipHostMalloc((void **)&s->h_theta, nh * kDim * sizeof(double), hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc((void **)&s->h_lnl, nh * sizeof(double), hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc((void **)&s->h_dh, 2 * nh * sizeof(double), hipHostMallocDefault));
+  }
+  for (int64_t i = 0; i < n_iter; ++i) {
+    for (int half = 0; half < 2; ++half) {
+      MBH_TRY(mbh_sampler_propose(s, half, st));
+      HIP_TRY(hipMemcpyAsync(s->h_theta, s->thy, nh * kDim * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      uint64_t id = 0;
+      MBH_TRY(mbh_server_submit(srv, ref_index, s->h_theta, nh, &id));
+      double lat = 0.0;
+      MBH_TRY(mbh_server_wait(srv, id, -1, s->h_lnl, s->h_dh, nh, &lat));
+      if (latency_s) latency_s[2 * i + half] = lat;
+      HIP_TRY(hipMemcpyAsync(s->lny, s->h_lnl, nh * sizeof(double), hipMemcpyHostToDevice, st));
+      HIP_TRY(hipMemcpyAsync(s->dhy, s->h_dh, 2 * nh * sizeof(double), hipMemcpyHostToDevice, st));
       MBH_TRY(mbh_sampler_accept(s, half, s->lny, s->dhy, st));
     }
     MBH_TRY(smp_swap(s, false, st));

@@ -141,6 +141,7 @@ _SIGS = {
     "mbh_sampler_destroy": [_vp],
     "mbh_sampler_set_walkers": [_vp, _dp, _dp, ct.POINTER(Likelihood), _vp],
     "mbh_sampler_step": [_vp, ct.POINTER(Likelihood), _i64, _vp],
+    "mbh_sampler_step_served": [_vp, _vp, _i32, _i64, _vp, _dp],
     "mbh_sampler_propose": [_vp, _i32, _vp],
     "mbh_sampler_proposals": [_vp, _dp, _dp, ct.POINTER(ct.c_int32)],
     "mbh_sampler_accept": [_vp, _i32, _vp, _vp, _vp],
@@ -682,6 +683,14 @@ class Sampler:
 
     def step(self, like: Likelihood, n_iter: int = 1, stream=None):
         _check(_L.mbh_sampler_step(self.h, ct.byref(like), n_iter, _stream(stream)), "mbh_sampler_step")
+
+    def step_served(self, server: "Server", ref_index: int, n_iter: int = 1, stream=None) -> np.ndarray:
+        """mbh_sampler_step_served: iterations whose likelihood calls are requests
+        to `server`; returns each request's latency in seconds ([2 n_iter])."""
+        lat = np.zeros(2 * n_iter)
+        _check(_L.mbh_sampler_step_served(self.h, server.h, ref_index, n_iter, _stream(stream),
+                                          lat.ctypes.data_as(_dp)), "mbh_sampler_step_served")
+        return lat
 
     def propose(self, half: int, stream=None):
         _check(_L.mbh_sampler_propose(self.h, half, _stream(stream)), "mbh_sampler_propose")

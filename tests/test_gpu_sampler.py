@@ -204,6 +204,63 @@ def test_sampler_step_equals_separate_calls(M, ctx, src, prec, mixed_rungs):
     gref.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_sampler_served_equals_batched(M, ctx, src, prec):
+    """mbh_sampler_step_served: the sampler as a client of a request server
+    (each half step's proposals one request) reaches the states of
+    mbh_sampler_step under the same reference and precision, bit for bit;
+    several samplers served from threads at once keep their own states."""
+    import threading
+
+    K, W, n_it = 4, 32, 6
+    p = M.FP64 if prec == "fp64" else M.MIXED
+    lo, hi = OS.prior_box(src["g"].t_obs)
+    betas = 1.0 / 2.0 ** np.arange(K)
+    gref = M.build_reference_coeffs(ctx, src["gd"], M.MODEL_IMR, M.MODE_22, src["th"], 64)
+    like = M.Sampler.likelihood(ref=gref)
+    srv = M.Server(ctx, [gref], prec=p)
+    seeds = [101, 202, 303]
+    ref_states, served = [], []
+    for sd in seeds:
+        x0 = _start(src, K, W, sd)
+        a = M.Sampler(ctx, betas, W, lo, hi, seed=sd, prec=p)
+        a.set_walkers(x0.reshape(-1, 11), like)
+        a.step(like, n_it)
+        ref_states.append(a.get())
+        a.close()
+        b = M.Sampler(ctx, betas, W, lo, hi, seed=sd, prec=p)
+        b.set_walkers(x0.reshape(-1, 11), like)
+        served.append(b)
+    import torch
+
+    torch.cuda.synchronize()  # the start's evaluations are done before other streams read them
+    # the first alone, the other two from threads at the same time
+    lats = [served[0].step_served(srv, 0, n_it)]
+    out = {}
+
+    def drive(i):
+        import torch
+
+        out[i] = served[i].step_served(srv, 0, n_it, stream=torch.cuda.Stream())
+
+    th = [threading.Thread(target=drive, args=(i,)) for i in (1, 2)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    lats += [out[1], out[2]]
+    for b, want, lat in zip(served, ref_states, lats):
+        got = b.get()
+        for key in ("x", "lnL", "dh_hh"):
+            assert np.array_equal(got[key], want[key]), key
+        assert lat.shape == (2 * n_it,) and np.all(np.isfinite(lat)) and np.all(lat > 0)
+        b.close()
+    print(f"[sampler] served ({prec}): 3 samplers x {n_it} iterations equal the batched runs; request latency "
+          f"median {np.median(np.concatenate(lats)) * 1e3:.3f} ms", flush=True)
+    srv.close()
+    gref.close()
+
+
 def test_sampler_mixed_rungs_split_precision(M, ctx, src):
     """mixed_rungs = m: the m coldest rungs are evaluated mixed, the others in
     FP64.  The cold rungs' lnL of the start is bit-identical to that of an
