@@ -373,6 +373,8 @@ def main():
     ap.add_argument("--full-grid-only", type=int, default=0, metavar="DRAWS",
                     help="time only the full-grid likelihood on this many prior draws of the first source "
                          "(default tile, FP64; for profiler runs) and exit")
+    ap.add_argument("--sampler-only", action="store_true",
+                    help="run only the sampler search on the loudest source and exit (for profiler runs)")
     ap.add_argument("--ingest-only", action="store_true",
                     help="time only the TDI ingest (X, Y, Z -> A, E, T band) and exit (for profiler runs)")
     ap.add_argument("--mixed-tol", type=float, default=None,
@@ -394,6 +396,10 @@ def main():
     grid = I.grid_lisa()
     if args.ingest_only:
         print(json.dumps(ingest_leg(M, ctx)))
+        return
+    if args.sampler_only:
+        S = Sources(M, ctx, grid, 2)
+        print(json.dumps(sampler_search(M, ctx, S.items[1]), default=float))
         return
     if args.full_grid_only:
         S = Sources(M, ctx, grid, 1)
