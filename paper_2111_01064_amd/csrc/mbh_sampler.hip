@@ -187,9 +187,8 @@ __device__ __forceinline__ int smp_accept_one(const SmpParams &p, int half, uint
 // pairs: each workgroup counts in LDS, then adds its nonzero counts.
 constexpr int kMaxCounters = 64 * 4;
 __device__ __forceinline__ void smp_count(unsigned *cnt, int code) {
-  if (code < 0) return;
-  atomicAdd(&cnt[code >> 1], 1u << 16);  // proposed: high half
-  if (code & 1) atomicAdd(&cnt[code >> 1], 1u);  // accepted: low half
+  // proposed in the high half, accepted in the low half: one LDS atomic
+  if (code >= 0) atomicAdd(&cnt[code >> 1], (1u << 16) + (unsigned)(code & 1));
 }
 __device__ __forceinline__ void smp_count_flush(const unsigned *cnt, int n_cnt, unsigned long long *counts) {
   for (int c = threadIdx.x; c < n_cnt; c += blockDim.x) {
@@ -399,10 +398,16 @@ __global__ __launch_bounds__(kSwapThreads) void k_smp_swap_lds(SmpParams p, cons
       perm[ob] = pa;
       ++mine;
     }
-    // one atomic add per wavefront
+    // one atomic add per wavefront: with one walker per thread a ballot
+    // counts the wavefront's exchanges, else a butterfly sum
+    if (one) {
+      const unsigned long long m = __ballot(mine != 0u);
+      if ((tid & 63) == 0 && m) atomicAdd(&cnt[k], (unsigned int)__popcll(m));
+    } else {
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) mine += __shfl_xor(mine, off, 64);
-    if ((tid & 63) == 0 && mine) atomicAdd(&cnt[k], mine);
+      for (int off = 32; off >= 1; off >>= 1) mine += __shfl_xor(mine, off, 64);
+      if ((tid & 63) == 0 && mine) atomicAdd(&cnt[k], mine);
+    }
     __syncthreads();
   }
   double dr[kSwapSlotsPerThread][2];
