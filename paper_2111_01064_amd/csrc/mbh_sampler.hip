@@ -216,56 +216,6 @@ __global__ __launch_bounds__(256) void k_smp_accept(SmpParams p, int half, uint3
   smp_count_flush(cnt, n_cnt, counts);
 }
 
-// Exchanges between adjacent rungs, k = 0, 1, ... in turn, in one workgroup:
-// walker i of rung k with walker (i + s) mod W of rung k + 1 (s uniform per
-// iteration and pair of rungs), accepted with probability
-// min(1, exp((beta_k - beta_k+1)(lnL_k+1 - lnL_k))).
-__global__ __launch_bounds__(1024) void k_smp_swap(SmpParams p, uint32_t it, double *__restrict__ x,
-                                                   double *__restrict__ lnL, double *__restrict__ dhhh,
-                                                   unsigned long long *__restrict__ swaps) {
-  const int W = p.W;
-  for (int k = 0; k + 1 < p.K; ++k) {
-    const U4 us = philox_uniforms(p.seed, it, (uint32_t)k, kStreamSwap, 0u);
-    const int s = min((int)floor(__dmul_rn(us.u[0], (double)W)), W - 1);
-    for (int i = threadIdx.x; i < W; i += blockDim.x) {
-      const int j = (i + s) % W;
-      const U4 v = philox_uniforms(p.seed, it, (uint32_t)(k * W + i), kStreamSwap, 1u);
-      const int64_t oa = (int64_t)k * W + i, ob = (int64_t)(k + 1) * W + j;
-      const double a = lnL[oa], b = lnL[ob];
-      const double la = __dmul_rn(__dadd_rn(p.betas[k], -p.betas[k + 1]), __dadd_rn(b, -a));
-      if (!(log(v.u[0]) < (isnan(la) ? -INFINITY : la))) continue;
-      for (int d = 0; d < kDim; ++d) {
-        const double t0 = x[oa * kDim + d];
-        x[oa * kDim + d] = x[ob * kDim + d];
-        x[ob * kDim + d] = t0;
-      }
-      lnL[oa] = b;
-      lnL[ob] = a;
-      for (int q = 0; q < 2; ++q) {
-        const double t0 = dhhh[2 * oa + q];
-        dhhh[2 * oa + q] = dhhh[2 * ob + q];
-        dhhh[2 * ob + q] = t0;
-      }
-      atomicAdd(&swaps[k], 1ull);
-    }
-    __syncthreads();
-  }
-}
-
-// The same exchanges for ensembles of at most kSwapLdsMax walkers in all,
-// decided in LDS: the lnL values and a slot permutation live in LDS while the
-// pairs of rungs are taken in turn (same uniforms, drawn beforehand by
-// k_smp_swap_prep, same arithmetic, same order, so the same decisions; the
-// exchange counts are summed per wavefront before one atomic add).  At the
-// end lnL is written from LDS and <d|h>, <h|h> are moved in place (each
-// thread reads the moved slots it owns into registers, then a barrier, then
-// writes them); the permutation goes out for k_smp_permute, which moves x.  Dynamic LDS: K W + K doubles (lnL, beta differences),
-// K W + 2 K ints (permutation, shifts, counters).
-constexpr int kSwapLdsMax = 4096;
-constexpr int kSwapThreads = 1024;
-constexpr int kSwapSlotsPerThread = kSwapLdsMax / kSwapThreads;
-constexpr int kSwapPrefetch = 16;  // pairs of rungs whose ln v a thread holds in registers
-
 // The uniforms of the exchanges do not depend on the walkers: ln v of every
 // (pair of rungs k, walker i) and the shift s of every pair, over the whole
 // chip, before the exchange kernel (logv [(K-1) W], shift [K-1]).
@@ -346,103 +296,108 @@ __global__ __launch_bounds__(256) void k_smp_final_accept(SmpParams p, int half,
   smp_count_flush(cnt, n_cnt, counts);
 }
 
-__global__ __launch_bounds__(kSwapThreads) void k_smp_swap_lds(SmpParams p, const double *__restrict__ logv,
+// Exchanges between adjacent rungs: pairs k = 0, 1, ... in turn, walker i of
+// rung k with walker (i + s_k) mod W of rung k + 1, accepted when
+// ln v < (beta_k - beta_k+1)(lnL_k+1 - lnL_k).  The slots p_0 = c,
+// p_k+1 = (p_k + s_k) mod W of rungs 0 .. K-1 form chain c, and every pair
+// of an iteration joins two slots of one chain: the W chains are independent,
+// so each is one thread's loop over the pairs, with the walker that moves up
+// the chain carried along (the decisions and their order are those of the
+// pairs taken in turn over all walkers).  A workgroup of kExchThreads
+// threads takes T chains (T <= 64, so that the deciding threads are one
+// wavefront): all its threads load the chains' lnL, <d|h>, <h|h> and ln v
+// into LDS, the T deciding threads take the decisions (counted per pair by a
+// ballot), then all threads write every slot of the chains: lnL and the
+// overlaps in place (from LDS), x into x_out.  Dynamic LDS: K (a double and
+// an int) + K T (4 doubles, an int and a byte).
+constexpr int kExchThreads = 1024;
+__global__ __launch_bounds__(kExchThreads) void k_smp_exchange(SmpParams p, int T, const double *__restrict__ logv,
                                                                const int32_t *__restrict__ shift,
-                                                               int32_t *__restrict__ perm_out,
-                                                               double *__restrict__ lnL, double *__restrict__ dhhh,
+                                                               const double *__restrict__ x_in,
+                                                               double *__restrict__ x_out, double *__restrict__ lnL,
+                                                               double *__restrict__ dhhh,
                                                                unsigned long long *__restrict__ swaps) {
   extern __shared__ double smem[];
-  const int W = p.W, n = p.K * W, np = p.K - 1, tid = threadIdx.x, nt = blockDim.x;
-  double *sl = smem;
-  double *sdb = sl + n;                // [K-1] beta_k - beta_k+1
-  int *perm = (int *)(sdb + p.K);      // [n]
-  int *ssh = perm + n;                 // [K-1] shifts
-  unsigned int *cnt = (unsigned int *)(ssh + p.K);
-  for (int t = tid; t < n; t += nt) {
-    sl[t] = lnL[t];
-    perm[t] = t;
+  const int K = p.K, W = p.W, tid = threadIdx.x, nt = blockDim.x;
+  const int c0 = blockIdx.x * T;            // first chain of the workgroup
+  const int Tc = min(T, W - c0);            // chains it holds
+  const int KT = K * T;
+  double *DB = smem;                        // [K] beta_k - beta_k+1
+  double *L = DB + K, *Dh = L + KT, *Hh = Dh + KT, *V = Hh + KT;  // [K][T]
+  int32_t *P = (int32_t *)(V + KT);         // [K][T] the chain's slot in rung k
+  int32_t *SH = P + KT;                     // [K] shifts
+  uint8_t *S = (uint8_t *)(SH + K);         // [K][T] rung whose walker ends in rung k
+  for (int k = tid; k + 1 < K; k += nt) {
+    DB[k] = __dadd_rn(p.betas[k], -p.betas[k + 1]);
+    SH[k] = shift[k];
   }
-  for (int k = tid; k < np; k += nt) {
-    sdb[k] = __dadd_rn(p.betas[k], -p.betas[k + 1]);
-    ssh[k] = shift[k];
-    cnt[k] = 0u;
-  }
-  // with one walker per thread and rung, its ln v of the first pairs in registers
-  const bool one = W <= nt;
-  double lv[kSwapPrefetch];
-#pragma unroll
-  for (int k = 0; k < kSwapPrefetch; ++k) lv[k] = (one && tid < W && k < np) ? logv[k * W + tid] : 0.0;
   __syncthreads();
-  for (int k = 0; k < np; ++k) {
-    const int s = ssh[k];
-    const double db = sdb[k];
-    unsigned int mine = 0u;
-    for (int i = tid; i < W; i += nt) {
-      const int j = i + s < W ? i + s : i + s - W;
-      const int oa = k * W + i, ob = (k + 1) * W + j;
-      double lu = 0.0;
-      if (one && k < kSwapPrefetch) {
-#pragma unroll
-        for (int q = 0; q < kSwapPrefetch; ++q)
-          if (q == k) lu = lv[q];
-      } else {
-        lu = logv[oa];
+  if (tid < Tc) {
+    int pk = c0 + tid;
+    for (int k = 0; k < K; ++k) {
+      P[k * T + tid] = pk;
+      if (k + 1 < K) {
+        pk += SH[k];
+        if (pk >= W) pk -= W;
       }
-      const double a = sl[oa], b = sl[ob];
-      const double la = __dmul_rn(db, __dadd_rn(b, -a));
-      if (!(lu < (isnan(la) ? -INFINITY : la))) continue;
-      sl[oa] = b;
-      sl[ob] = a;
-      const int pa = perm[oa];
-      perm[oa] = perm[ob];
-      perm[ob] = pa;
-      ++mine;
     }
-    // one atomic add per wavefront: with one walker per thread a ballot
-    // counts the wavefront's exchanges, else a butterfly sum
-    if (one) {
-      const unsigned long long m = __ballot(mine != 0u);
-      if ((tid & 63) == 0 && m) atomicAdd(&cnt[k], (unsigned int)__popcll(m));
-    } else {
-#pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) mine += __shfl_xor(mine, off, 64);
-      if ((tid & 63) == 0 && mine) atomicAdd(&cnt[k], mine);
-    }
-    __syncthreads();
-  }
-  double dr[kSwapSlotsPerThread][2];
-#pragma unroll
-  for (int q = 0; q < kSwapSlotsPerThread; ++q) {
-    const int t = tid + q * nt;
-    if (t >= n) continue;
-    perm_out[t] = perm[t];
-    if (perm[t] == t) continue;
-    const int64_t src = perm[t];
-    dr[q][0] = dhhh[2 * src];
-    dr[q][1] = dhhh[2 * src + 1];
   }
   __syncthreads();
-#pragma unroll
-  for (int q = 0; q < kSwapSlotsPerThread; ++q) {
-    const int t = tid + q * nt;
-    if (t >= n || perm[t] == t) continue;
-    dhhh[2 * (int64_t)t] = dr[q][0];
-    dhhh[2 * (int64_t)t + 1] = dr[q][1];
-    lnL[t] = sl[t];
+  for (int e = tid; e < KT; e += nt) {
+    const int k = e / T, j = e - k * T;
+    if (j >= Tc) continue;
+    const int64_t slot = (int64_t)k * W + P[e];
+    L[e] = lnL[slot];
+    Dh[e] = dhhh[2 * slot];
+    Hh[e] = dhhh[2 * slot + 1];
+    V[e] = k + 1 < K ? logv[(int64_t)k * W + P[e]] : 0.0;
   }
-  for (int k = tid; k < np; k += nt)
-    if (cnt[k]) atomicAdd(&swaps[k], (unsigned long long)cnt[k]);
+  __syncthreads();
+  if (tid < 64) {  // the deciding wavefront
+    const bool active = tid < Tc;
+    int carry = 0;  // the rung whose walker sits in rung k of the chain before pair k
+    for (int k = 0; k + 1 < K; ++k) {
+      bool sw = false;
+      if (active) {
+        const double a = L[carry * T + tid], b = L[(k + 1) * T + tid];
+        const double la = __dmul_rn(DB[k], __dadd_rn(b, -a));
+        sw = V[k * T + tid] < (isnan(la) ? -INFINITY : la);
+        S[k * T + tid] = (uint8_t)(sw ? k + 1 : carry);
+        if (!sw) carry = k + 1;
+      }
+      const unsigned long long m = __ballot(sw);
+      if (tid == 0 && m) atomicAdd(&swaps[k], (unsigned long long)__popcll(m));
+    }
+    if (active) S[(K - 1) * T + tid] = (uint8_t)carry;
+  }
+  __syncthreads();
+  for (int e = tid; e < KT; e += nt) {
+    const int k = e / T, j = e - k * T;
+    if (j >= Tc) continue;
+    const int r = S[e];
+    const int64_t slot = (int64_t)k * W + P[e];
+    lnL[slot] = L[r * T + j];
+    dhhh[2 * slot] = Dh[r * T + j];
+    dhhh[2 * slot + 1] = Hh[r * T + j];
+  }
+  for (int e = tid; e < KT * kDim; e += nt) {
+    const int q = e / kDim, d = e - q * kDim, k = q / T, j = q - k * T;
+    if (j >= Tc) continue;
+    const int r = S[q];
+    const int64_t slot = (int64_t)k * W + P[q], src = (int64_t)r * W + P[r * T + j];
+    x_out[slot * kDim + d] = x_in[src * kDim + d];
+  }
 }
 
-// x after the exchanges: x_out[t] = x_in[perm[t]], element by element over
-// the whole chip (consecutive threads take consecutive coordinates, so reads
-// and writes are coalesced); the sampler then uses x_out as its walkers.
-__global__ __launch_bounds__(256) void k_smp_permute(int n, const int32_t *__restrict__ perm,
-                                                     const double *__restrict__ x_in, double *__restrict__ x_out) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n * kDim) return;
-  const int t = e / kDim, d = e - t * kDim;
-  x_out[e] = x_in[(int64_t)perm[t] * kDim + d];
+// chains per workgroup of the exchange kernel: 64, or fewer so that its LDS
+// stays within 64 KB (K <= 64 rungs)
+size_t exchange_lds(int K, int T) {
+  return (size_t)K * (sizeof(double) + sizeof(int32_t)) + (size_t)K * T * (4 * sizeof(double) + sizeof(int32_t) + 1);
+}
+int exchange_chains(int K) {
+  int T = 64;
+  while (T > 16 && exchange_lds(K, T) > 65536) T /= 2;
+  return T;
 }
 
 // theta of every walker, and whether its x lies in the prior box
@@ -469,7 +424,6 @@ struct mbh_sampler {
   double *lo = nullptr, *hi = nullptr, *betas = nullptr;
   double *swap_logv = nullptr;  // [(K-1) W] ln v of the exchanges of one iteration
   int32_t *swap_shift = nullptr;  // [K-1]
-  int32_t *swap_perm = nullptr;   // [K W] slot permutation of one iteration's exchanges
   double *x_alt = nullptr;        // [K W][11] the other buffer of the walkers (swapped with x)
   double *x = nullptr, *lnL = nullptr, *dhhh = nullptr, *th = nullptr;
   double *y = nullptr, *thy = nullptr, *lny = nullptr, *dhy = nullptr, *lz = nullptr;
@@ -537,7 +491,7 @@ extern "C" mbh_status mbh_sampler_create(mbh_ctx *ctx, const mbh_sampler_config 
       (e = smp_alloc(s, &s->thy, nh * kDim)) || (e = smp_alloc(s, &s->lny, nh)) || (e = smp_alloc(s, &s->dhy, 2 * nh)) ||
       (e = smp_alloc(s, &s->lz, nh)) || (e = smp_alloc(s, &s->kind, nh)) || (e = smp_alloc(s, &s->counts, K * 8)) ||
       (e = smp_alloc(s, &s->swaps, K)) || (e = smp_alloc(s, &s->swap_logv, (size_t)std::max(K - 1, 1) * W)) ||
-      (e = smp_alloc(s, &s->swap_shift, std::max(K - 1, 1))) || (e = smp_alloc(s, &s->swap_perm, n)) ||
+      (e = smp_alloc(s, &s->swap_shift, std::max(K - 1, 1))) ||
       (e = smp_alloc(s, &s->x_alt, n * kDim))) {
     sampler_free(s);
     return e;
@@ -665,25 +619,18 @@ extern "C" mbh_status mbh_sampler_accept(mbh_sampler *s, int half, const double 
   return MBH_OK;
 }
 
-static bool swap_in_lds(const mbh_sampler *s) { return s->K > 1 && s->K * s->W <= kSwapLdsMax; }
-
 // the exchanges of the iteration; `drawn`: their uniforms are already in
 // swap_logv, swap_shift
 static mbh_status smp_swap(mbh_sampler *s, bool drawn, hipStream_t st) {
-  const int n = s->K * s->W;
-  if (swap_in_lds(s)) {
-    const size_t lds = (size_t)n * (sizeof(double) + sizeof(int)) + (size_t)s->K * (sizeof(double) + 2 * sizeof(int));
+  if (s->K > 1) {
     const int np = (s->K - 1) * s->W;
     if (!drawn)
       hipLaunchKernelGGL(k_smp_swap_prep, dim3((np + 255) / 256), dim3(256), 0, st, s->p, (uint32_t)s->it,
                          s->swap_logv, s->swap_shift);
-    hipLaunchKernelGGL(k_smp_swap_lds, dim3(1), dim3(kSwapThreads), lds, st, s->p, s->swap_logv, s->swap_shift,
-                       s->swap_perm, s->lnL, s->dhhh, s->swaps);
-    hipLaunchKernelGGL(k_smp_permute, dim3((n * kDim + 255) / 256), dim3(256), 0, st, n, s->swap_perm, s->x, s->x_alt);
+    const int T = exchange_chains(s->K);
+    hipLaunchKernelGGL(k_smp_exchange, dim3((s->W + T - 1) / T), dim3(kExchThreads), exchange_lds(s->K, T), st,
+                       s->p, T, s->swap_logv, s->swap_shift, s->x, s->x_alt, s->lnL, s->dhhh, s->swaps);
     std::swap(s->x, s->x_alt);
-  } else if (s->K > 1) {
-    hipLaunchKernelGGL(k_smp_swap, dim3(1), dim3(std::min(1024, s->W)), 0, st, s->p, (uint32_t)s->it, s->x, s->lnL,
-                       s->dhhh, s->swaps);
   }
   HIP_TRY(hipGetLastError());
   s->it += 1;
@@ -702,7 +649,7 @@ static mbh_status smp_half_het(mbh_sampler *s, const mbh_ref *ref, int half, hip
   MBH_TRY(smp_batches(s, ref));
   const int nh = s->K * s->H;
   const WorkItem *items = batch_device_items(s->half_batch);
-  const bool draw = half == 0 && swap_in_lds(s);
+  const bool draw = half == 0 && s->K > 1;
   hipLaunchKernelGGL(k_smp_propose_setup, dim3((nh + 63) / 64), dim3(128), 0, st, s->p, half, (uint32_t)s->it, s->x,
                      s->y, s->thy, s->kind, s->lz, items, s->half_n0, draw ? s->swap_logv : nullptr,
                      draw ? s->swap_shift : nullptr);
@@ -720,7 +667,7 @@ extern "C" mbh_status mbh_sampler_step(mbh_sampler *s, const mbh_likelihood *lik
   for (int64_t i = 0; i < n_iter; ++i) {
     if (like->ref) {
       for (int half = 0; half < 2; ++half) MBH_TRY(smp_half_het(s, like->ref, half, st));
-      MBH_TRY(smp_swap(s, swap_in_lds(s), st));
+      MBH_TRY(smp_swap(s, s->K > 1, st));
       continue;
     }
     for (int half = 0; half < 2; ++half) {

@@ -156,6 +156,56 @@ def test_sampler_heterodyned_search_with_reference_updates(M, ctx, src):
     assert r1["reason"] in (M.STOP_CONVERGED, M.STOP_MAX_ITER)
 
 
+@pytest.mark.parametrize("K,W", [(3, 16), (8, 1024), (33, 40), (64, 4), (2, 5000)])
+def test_sampler_exchanges_match_oracle(M, ctx, src, K, W):
+    """The exchanges (one chain of slots per thread on the device) against the
+    oracle's pairs taken in turn: walkers, lnL and exchange counts bit for bit
+    over two iterations, for 64, 32 and 16 chains per workgroup and for
+    ensembles above 4096 walkers; lnL of -inf included."""
+    lo, hi = OS.prior_box(src["g"].t_obs)
+    rng = np.random.default_rng(K * 1000 + W)
+    betas = 1.0 / 1.5 ** np.arange(K)
+    x0 = lo + (hi - lo) * rng.uniform(size=(K, W, 11))
+    l0 = rng.normal(scale=3.0, size=(K, W)) - 4.0 * np.arange(K)[:, None]
+    l0[rng.uniform(size=l0.shape) < 0.05] = -np.inf
+    o = OS.Sampler(betas, x0, l0, lo, hi, 77)
+    gs = M.Sampler(ctx, betas, W, lo, hi, seed=77, prec=M.FP64)
+    gs.set_walkers(x0.reshape(-1, 11), lnL=l0.ravel())
+    for it in range(2):
+        o.swap()
+        o.it += 1
+        gs.swap()
+        st = gs.get()
+        assert np.array_equal(st["x"].reshape(K, W, 11), o.x), it
+        assert np.array_equal(st["lnL"].reshape(K, W), o.lnL), it
+    sw = gs.stats()["swaps"].astype(np.int64)
+    assert np.array_equal(sw[:K - 1], o.n_swap_acc[:K - 1].astype(np.int64))
+    print(f"[sampler] exchanges K={K} W={W}: {int(sw[:K - 1].sum())} accepted, identical to the oracle", flush=True)
+    gs.close()
+
+
+def test_sampler_exchanges_move_overlaps(M, ctx, src):
+    """<d|h>, <h|h> move with their walker's lnL."""
+    K, W = 4, 32
+    lo, hi = OS.prior_box(src["g"].t_obs)
+    gref = M.build_reference_coeffs(ctx, src["gd"], M.MODEL_IMR, M.MODE_22, src["th"], 64)
+    like = M.Sampler.likelihood(ref=gref)
+    gs = M.Sampler(ctx, np.array([1.0, 0.9, 0.8, 0.7]), W, lo, hi, seed=5, prec=M.FP64)
+    gs.set_walkers(_start(src, K, W, 8).reshape(-1, 11), like)
+    before = gs.get()
+    pairs = {float(l): tuple(d) for l, d in zip(before["lnL"], before["dh_hh"])}
+    n_moved = 0
+    for _ in range(3):
+        gs.swap()
+    after = gs.get()
+    for l, d, x in zip(after["lnL"], after["dh_hh"], after["x"]):
+        assert pairs[float(l)] == tuple(d)
+    n_moved = int(np.sum(after["lnL"] != before["lnL"]))
+    assert n_moved > 0 and gs.stats()["swaps"].sum() > 0
+    gs.close()
+    gref.close()
+
+
 @pytest.mark.parametrize("prec,mixed_rungs", [("fp64", 0), ("mixed", 0), ("mixed", 2)])
 def test_sampler_step_equals_separate_calls(M, ctx, src, prec, mixed_rungs):
     """mbh_sampler_step with the heterodyned likelihood fuses the proposals
