@@ -152,33 +152,54 @@ __global__ __launch_bounds__(256) void k_smp_propose(SmpParams p, int half, uint
 // Metropolis decision of proposal t of one half: accept when
 // ln v < ln z^(d-1) + beta (lnL_y - lnL) inside the prior with a finite lnL_y
 // (a walker whose lnL is not finite takes any such proposal); an accepted
-// proposal replaces the walker, its lnL and overlaps.  Returns
-// 2 (4 k + kind) + 1 when the proposal was accepted, 2 (4 k + kind) if not.
-__device__ __forceinline__ int smp_accept_one(const SmpParams &p, int half, uint32_t it, int t,
-                                              const double *__restrict__ y, const int32_t *__restrict__ kind,
-                                              const double *__restrict__ lz, double ly, double dh, double hh,
-                                              bool has_dh, double *__restrict__ x, double *__restrict__ lnL,
-                                              double *__restrict__ dhhh) {
+// proposal replaces the walker, its lnL and overlaps.  The decision's inputs
+// other than lnL_y are read first (smp_accept_in), so that a caller can have
+// them in flight while it forms lnL_y.
+struct AcceptIn {
+  double yv[kDim];
+  double cur, lzt, logu;
+  int64_t o;
+  int k, kd;
+  bool in;
+};
+__device__ __forceinline__ AcceptIn smp_accept_in(const SmpParams &p, int half, uint32_t it, int t,
+                                                  const double *__restrict__ y, const int32_t *__restrict__ kind,
+                                                  const double *__restrict__ lz, const double *__restrict__ lnL) {
+  AcceptIn a;
   const int H = p.W / 2;
-  const int k = t / H, i = t - k * H, w = half * H + i;
-  const U4 v = philox_uniforms(p.seed, it, (uint32_t)(k * p.W + w), kStreamMove, (uint32_t)(half + 2));
+  a.k = t / H;
+  const int i = t - a.k * H, w = half * H + i;
+  const U4 v = philox_uniforms(p.seed, it, (uint32_t)(a.k * p.W + w), kStreamMove, (uint32_t)(half + 2));
   const double *yv = y + (int64_t)t * kDim;
-  bool in = true;
-  for (int d = 0; d < kDim; ++d) in = in && yv[d] >= p.lo[d] && yv[d] <= p.hi[d];
-  const int64_t o = (int64_t)k * p.W + w;
-  const double cur = lnL[o];
-  bool acc = false;
-  if (in && isfinite(ly)) {
-    const double la = isfinite(cur) ? __dadd_rn(lz[t], __dmul_rn(p.betas[k], __dadd_rn(ly, -cur))) : INFINITY;
-    acc = log(v.u[0]) < la;
+  a.in = true;
+  for (int d = 0; d < kDim; ++d) {
+    a.yv[d] = yv[d];
+    a.in = a.in && yv[d] >= p.lo[d] && yv[d] <= p.hi[d];
   }
-  const int c = 2 * (k * 4 + kind[t]);
+  a.o = (int64_t)a.k * p.W + w;
+  a.cur = lnL[a.o];
+  a.lzt = lz[t];
+  a.kd = kind[t];
+  a.logu = log(v.u[0]);
+  return a;
+}
+// Returns 2 (4 k + kind) + 1 when the proposal was accepted, 2 (4 k + kind)
+// if not.
+__device__ __forceinline__ int smp_accept_apply(const SmpParams &p, const AcceptIn &a, double ly, double dh,
+                                                double hh, bool has_dh, double *__restrict__ x,
+                                                double *__restrict__ lnL, double *__restrict__ dhhh) {
+  bool acc = false;
+  if (a.in && isfinite(ly)) {
+    const double la = isfinite(a.cur) ? __dadd_rn(a.lzt, __dmul_rn(p.betas[a.k], __dadd_rn(ly, -a.cur))) : INFINITY;
+    acc = a.logu < la;
+  }
+  const int c = 2 * (a.k * 4 + a.kd);
   if (!acc) return c;
-  for (int d = 0; d < kDim; ++d) x[o * kDim + d] = yv[d];
-  lnL[o] = ly;
+  for (int d = 0; d < kDim; ++d) x[a.o * kDim + d] = a.yv[d];
+  lnL[a.o] = ly;
   if (has_dh) {
-    dhhh[2 * o] = dh;
-    dhhh[2 * o + 1] = hh;
+    dhhh[2 * a.o] = dh;
+    dhhh[2 * a.o + 1] = hh;
   }
   return c + 1;
 }
@@ -209,9 +230,11 @@ __global__ __launch_bounds__(256) void k_smp_accept(SmpParams p, int half, uint3
   for (int c = threadIdx.x; c < n_cnt; c += blockDim.x) cnt[c] = 0u;
   __syncthreads();
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < p.K * (p.W / 2))
-    smp_count(cnt, smp_accept_one(p, half, it, t, y, kind, lz, lny[t], dhy ? dhy[2 * t] : 0.0,
-                                  dhy ? dhy[2 * t + 1] : 0.0, dhy != nullptr, x, lnL, dhhh));
+  if (t < p.K * (p.W / 2)) {
+    const AcceptIn a = smp_accept_in(p, half, it, t, y, kind, lz, lnL);
+    smp_count(cnt, smp_accept_apply(p, a, lny[t], dhy ? dhy[2 * t] : 0.0, dhy ? dhy[2 * t + 1] : 0.0,
+                                    dhy != nullptr, x, lnL, dhhh));
+  }
   __syncthreads();
   smp_count_flush(cnt, n_cnt, counts);
 }
@@ -243,39 +266,41 @@ __global__ __launch_bounds__(256) void k_smp_swap_prep(SmpParams p, uint32_t it,
 //  * proposals and the batch's walker constants: 64 proposals per workgroup
 //    of 128 threads; the first 64 threads propose (their theta kept in LDS),
 //    then the two threads of each proposal set its intrinsic and extrinsic
-//    constants in the batch item that holds it (items[0] holds proposals
-//    0 .. n0-1, items[1] the rest).  With logv set, the iteration's exchange
-//    uniforms are drawn too, over the grid.
-//  * totals and decisions: one thread per proposal adds its partial sums
-//    (as the batch's totals stage, writing the item's outputs) and takes the
-//    Metropolis decision from them.
-// Proposals, constants, totals and decisions are those of the separate
-// kernels bit for bit.
+//    constants in the batch item that holds it.  With logv set, the
+//    iteration's exchange uniforms are drawn too, over the grid.
+//  * totals and decisions: one thread per proposal reads the decision's
+//    inputs, adds its partial sums (as the batch's totals stage, writing the
+//    item's outputs) and takes the Metropolis decision.
+// items[0] holds proposals 0 .. n0-1, items[1] the rest; the first nb0
+// workgroups take items[0]'s proposals, the others items[1]'s, so that a
+// workgroup's item is uniform.  Proposals, constants, totals and decisions
+// are those of the separate kernels bit for bit.
 __global__ __launch_bounds__(128) void k_smp_propose_setup(SmpParams p, int half, uint32_t it,
                                                            const double *__restrict__ x, double *__restrict__ y,
                                                            double *__restrict__ thy, int32_t *__restrict__ kind,
                                                            double *__restrict__ lz, const WorkItem *__restrict__ items,
-                                                           int n0, double *__restrict__ logv,
+                                                           int n0, int nb0, double *__restrict__ logv,
                                                            int32_t *__restrict__ shift) {
   __shared__ double th_s[64][kDim];
   const int nh = p.K * (p.W / 2);
   const int j = threadIdx.x & 63;
-  const int t = blockIdx.x * 64 + j;
-  if (threadIdx.x < 64 && t < nh) smp_propose_one(p, half, it, t, x, y, thy, kind, lz, th_s[j]);
+  const bool second = (int)blockIdx.x >= nb0;
+  const int t0 = second ? n0 + ((int)blockIdx.x - nb0) * 64 : (int)blockIdx.x * 64;
+  const int t = t0 + j, t_end = second ? nh : n0;
+  const WorkItem &itm = items[second ? 1 : 0];
+  const int model = itm.model;
+  const uint32_t modes = itm.ref.modes;
+  WalkerC *wc = itm.wc;
+  if (threadIdx.x < 64 && t < t_end) smp_propose_one(p, half, it, t, x, y, thy, kind, lz, th_s[j]);
   __syncthreads();
-  if (t < nh) {
-    const int ii = t < n0 ? 0 : 1;
-    const WorkItem &itm = items[ii];
-    const int64_t w = ii ? t - n0 : t;
-    walker_setup(th_s[j], itm.model, itm.ref.modes, itm.wc[w], threadIdx.x < 64 ? 1 : 2);
-  }
+  if (t < t_end) walker_setup(th_s[j], model, modes, wc[second ? t - n0 : t], threadIdx.x < 64 ? 1 : 2);
   if (logv)
     for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < (p.K - 1) * p.W; u += gridDim.x * blockDim.x)
       smp_swap_uniforms(p, it, u, logv, shift);
 }
 
 __global__ __launch_bounds__(256) void k_smp_final_accept(SmpParams p, int half, uint32_t it,
-                                                          const WorkItem *__restrict__ items, int n0,
+                                                          const WorkItem *__restrict__ items, int n0, int nb0,
                                                           const double *__restrict__ y,
                                                           const int32_t *__restrict__ kind,
                                                           const double *__restrict__ lz, double *__restrict__ x,
@@ -285,12 +310,13 @@ __global__ __launch_bounds__(256) void k_smp_final_accept(SmpParams p, int half,
   const int n_cnt = p.K * 4;
   for (int c = threadIdx.x; c < n_cnt; c += blockDim.x) cnt[c] = 0u;
   __syncthreads();
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < p.K * (p.W / 2)) {
-    const int ii = t < n0 ? 0 : 1;
-    const WorkItem &itm = items[ii];
-    const WalkerTotals r = het_walker_totals(itm, ii ? t - n0 : t);
-    smp_count(cnt, smp_accept_one(p, half, it, t, y, kind, lz, r.lnL, r.dh, r.hh, itm.dhhh != nullptr, x, lnL, dhhh));
+  const bool second = (int)blockIdx.x >= nb0;
+  const int t = (second ? n0 + ((int)blockIdx.x - nb0) * 256 : (int)blockIdx.x * 256) + (int)threadIdx.x;
+  if (t < (second ? p.K * (p.W / 2) : n0)) {
+    const AcceptIn a = smp_accept_in(p, half, it, t, y, kind, lz, lnL);
+    const WorkItem &itm = items[second ? 1 : 0];
+    const WalkerTotals r = het_walker_totals(itm, second ? t - n0 : t);
+    smp_count(cnt, smp_accept_apply(p, a, r.lnL, r.dh, r.hh, itm.dhhh != nullptr, x, lnL, dhhh));
   }
   __syncthreads();
   smp_count_flush(cnt, n_cnt, counts);
@@ -650,12 +676,14 @@ static mbh_status smp_half_het(mbh_sampler *s, const mbh_ref *ref, int half, hip
   const int nh = s->K * s->H;
   const WorkItem *items = batch_device_items(s->half_batch);
   const bool draw = half == 0 && s->K > 1;
-  hipLaunchKernelGGL(k_smp_propose_setup, dim3((nh + 63) / 64), dim3(128), 0, st, s->p, half, (uint32_t)s->it, s->x,
-                     s->y, s->thy, s->kind, s->lz, items, s->half_n0, draw ? s->swap_logv : nullptr,
+  const int n0 = s->half_n0, nb0 = (n0 + 63) / 64, nb1 = (nh - n0 + 63) / 64;
+  hipLaunchKernelGGL(k_smp_propose_setup, dim3(nb0 + nb1), dim3(128), 0, st, s->p, half, (uint32_t)s->it, s->x, s->y,
+                     s->thy, s->kind, s->lz, items, n0, nb0, draw ? s->swap_logv : nullptr,
                      draw ? s->swap_shift : nullptr);
   MBH_TRY(mbh_batch_launch_stage(s->half_batch, MBH_STAGE_MAIN, st));
-  hipLaunchKernelGGL(k_smp_final_accept, dim3((nh + 255) / 256), dim3(256), 0, st, s->p, half, (uint32_t)s->it,
-                     items, s->half_n0, s->y, s->kind, s->lz, s->x, s->lnL, s->dhhh, s->counts);
+  const int fb0 = (n0 + 255) / 256, fb1 = (nh - n0 + 255) / 256;
+  hipLaunchKernelGGL(k_smp_final_accept, dim3(fb0 + fb1), dim3(256), 0, st, s->p, half, (uint32_t)s->it, items, n0,
+                     fb0, s->y, s->kind, s->lz, s->x, s->lnL, s->dhhh, s->counts);
   HIP_TRY(hipGetLastError());
   return MBH_OK;
 }
