@@ -239,35 +239,13 @@ __global__ __launch_bounds__(256) void k_smp_accept(SmpParams p, int half, uint3
   smp_count_flush(cnt, n_cnt, counts);
 }
 
-// The uniforms of the exchanges do not depend on the walkers: ln v of every
-// (pair of rungs k, walker i) and the shift s of every pair, over the whole
-// chip, before the exchange kernel (logv [(K-1) W], shift [K-1]).
-__device__ __forceinline__ void smp_swap_uniforms(const SmpParams &p, uint32_t it, int t, double *__restrict__ logv,
-                                                  int32_t *__restrict__ shift) {
-  const int W = p.W, np = (p.K - 1) * W;
-  if (t < np) {
-    const int k = t / W, i = t - k * W;
-    const U4 v = philox_uniforms(p.seed, it, (uint32_t)(k * W + i), kStreamSwap, 1u);
-    logv[t] = log(v.u[0]);
-  }
-  if (t < p.K - 1) {
-    const U4 us = philox_uniforms(p.seed, it, (uint32_t)t, kStreamSwap, 0u);
-    shift[t] = min((int)floor(__dmul_rn(us.u[0], (double)W)), W - 1);
-  }
-}
-__global__ __launch_bounds__(256) void k_smp_swap_prep(SmpParams p, uint32_t it, double *__restrict__ logv,
-                                                       int32_t *__restrict__ shift) {
-  smp_swap_uniforms(p, it, blockIdx.x * blockDim.x + threadIdx.x, logv, shift);
-}
-
 // A sampler step with the heterodyned likelihood runs the half batch's main
 // pass between two kernels of its own, each fused with the batch stage next
 // to it (so a half step is three launches, not five):
 //  * proposals and the batch's walker constants: 64 proposals per workgroup
 //    of 128 threads; the first 64 threads propose (their theta kept in LDS),
 //    then the two threads of each proposal set its intrinsic and extrinsic
-//    constants in the batch item that holds it.  With logv set, the
-//    iteration's exchange uniforms are drawn too, over the grid.
+//    constants in the batch item that holds it.
 //  * totals and decisions: one thread per proposal reads the decision's
 //    inputs, adds its partial sums (as the batch's totals stage, writing the
 //    item's outputs) and takes the Metropolis decision.
@@ -279,8 +257,7 @@ __global__ __launch_bounds__(128) void k_smp_propose_setup(SmpParams p, int half
                                                            const double *__restrict__ x, double *__restrict__ y,
                                                            double *__restrict__ thy, int32_t *__restrict__ kind,
                                                            double *__restrict__ lz, const WorkItem *__restrict__ items,
-                                                           int n0, int nb0, double *__restrict__ logv,
-                                                           int32_t *__restrict__ shift) {
+                                                           int n0, int nb0) {
   __shared__ double th_s[64][kDim];
   const int nh = p.K * (p.W / 2);
   const int j = threadIdx.x & 63;
@@ -294,9 +271,6 @@ __global__ __launch_bounds__(128) void k_smp_propose_setup(SmpParams p, int half
   if (threadIdx.x < 64 && t < t_end) smp_propose_one(p, half, it, t, x, y, thy, kind, lz, th_s[j]);
   __syncthreads();
   if (t < t_end) walker_setup(th_s[j], model, modes, wc[second ? t - n0 : t], threadIdx.x < 64 ? 1 : 2);
-  if (logv)
-    for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < (p.K - 1) * p.W; u += gridDim.x * blockDim.x)
-      smp_swap_uniforms(p, it, u, logv, shift);
 }
 
 __global__ __launch_bounds__(256) void k_smp_final_accept(SmpParams p, int half, uint32_t it,
@@ -323,22 +297,23 @@ __global__ __launch_bounds__(256) void k_smp_final_accept(SmpParams p, int half,
 }
 
 // Exchanges between adjacent rungs: pairs k = 0, 1, ... in turn, walker i of
-// rung k with walker (i + s_k) mod W of rung k + 1, accepted when
-// ln v < (beta_k - beta_k+1)(lnL_k+1 - lnL_k).  The slots p_0 = c,
-// p_k+1 = (p_k + s_k) mod W of rungs 0 .. K-1 form chain c, and every pair
-// of an iteration joins two slots of one chain: the W chains are independent,
-// so each is one thread's loop over the pairs, with the walker that moves up
-// the chain carried along (the decisions and their order are those of the
-// pairs taken in turn over all walkers).  A workgroup of kExchThreads
-// threads takes T chains (T <= 64, so that the deciding threads are one
-// wavefront): all its threads load the chains' lnL, <d|h>, <h|h> and ln v
-// into LDS, the T deciding threads take the decisions (counted per pair by a
-// ballot), then all threads write every slot of the chains: lnL and the
-// overlaps in place (from LDS), x into x_out.  Dynamic LDS: K (a double and
-// an int) + K T (4 doubles, an int and a byte).
+// rung k with walker (i + s_k) mod W of rung k + 1 (s_k uniform per pair),
+// accepted when ln v < (beta_k - beta_k+1)(lnL_k+1 - lnL_k) with v uniform
+// per (pair, walker i).  The slots p_0 = c, p_k+1 = (p_k + s_k) mod W of
+// rungs 0 .. K-1 form chain c, and every pair of an iteration joins two slots
+// of one chain: the W chains are independent, so each is one thread's loop
+// over the pairs, with the walker that moves up the chain carried along (the
+// decisions and their order are those of the pairs taken in turn over all
+// walkers).  A workgroup of kExchThreads threads takes T chains (T <= 64, so
+// that the deciding threads are one wavefront): the shifts are drawn, the
+// chains' slots found, then all threads load the chains' lnL, <d|h>, <h|h>
+// and x into LDS (one round of memory reads) and draw their ln v; the T
+// deciding threads take the decisions (counted per pair by a ballot); then all
+// threads write every slot of the chains from LDS: lnL and the overlaps in
+// place, x into x_out.  Dynamic LDS: K (two doubles and an int) + K T (15
+// doubles, an int and a byte).
 constexpr int kExchThreads = 1024;
-__global__ __launch_bounds__(kExchThreads) void k_smp_exchange(SmpParams p, int T, const double *__restrict__ logv,
-                                                               const int32_t *__restrict__ shift,
+__global__ __launch_bounds__(kExchThreads) void k_smp_exchange(SmpParams p, uint32_t it, int T,
                                                                const double *__restrict__ x_in,
                                                                double *__restrict__ x_out, double *__restrict__ lnL,
                                                                double *__restrict__ dhhh,
@@ -350,12 +325,13 @@ __global__ __launch_bounds__(kExchThreads) void k_smp_exchange(SmpParams p, int 
   const int KT = K * T;
   double *DB = smem;                        // [K] beta_k - beta_k+1
   double *L = DB + K, *Dh = L + KT, *Hh = Dh + KT, *V = Hh + KT;  // [K][T]
-  int32_t *P = (int32_t *)(V + KT);         // [K][T] the chain's slot in rung k
+  double *X = V + KT;                       // [K][T][11]
+  int32_t *P = (int32_t *)(X + KT * kDim);  // [K][T] the chain's slot in rung k
   int32_t *SH = P + KT;                     // [K] shifts
   uint8_t *S = (uint8_t *)(SH + K);         // [K][T] rung whose walker ends in rung k
   for (int k = tid; k + 1 < K; k += nt) {
-    DB[k] = __dadd_rn(p.betas[k], -p.betas[k + 1]);
-    SH[k] = shift[k];
+    const U4 us = philox_uniforms(p.seed, it, (uint32_t)k, kStreamSwap, 0u);
+    SH[k] = min((int)floor(__dmul_rn(us.u[0], (double)W)), W - 1);
   }
   __syncthreads();
   if (tid < Tc) {
@@ -369,6 +345,7 @@ __global__ __launch_bounds__(kExchThreads) void k_smp_exchange(SmpParams p, int 
     }
   }
   __syncthreads();
+  for (int k = tid; k + 1 < K; k += nt) DB[k] = __dadd_rn(p.betas[k], -p.betas[k + 1]);
   for (int e = tid; e < KT; e += nt) {
     const int k = e / T, j = e - k * T;
     if (j >= Tc) continue;
@@ -376,7 +353,17 @@ __global__ __launch_bounds__(kExchThreads) void k_smp_exchange(SmpParams p, int 
     L[e] = lnL[slot];
     Dh[e] = dhhh[2 * slot];
     Hh[e] = dhhh[2 * slot + 1];
-    V[e] = k + 1 < K ? logv[(int64_t)k * W + P[e]] : 0.0;
+    double lv = 0.0;
+    if (k + 1 < K) {
+      const U4 v = philox_uniforms(p.seed, it, (uint32_t)(k * W + P[e]), kStreamSwap, 1u);
+      lv = log(v.u[0]);
+    }
+    V[e] = lv;
+  }
+  for (int e = tid; e < KT * kDim; e += nt) {
+    const int q = e / kDim, d = e - q * kDim, k = q / T, j = q - k * T;
+    if (j >= Tc) continue;
+    X[e] = x_in[((int64_t)k * W + P[q]) * kDim + d];
   }
   __syncthreads();
   if (tid < 64) {  // the deciding wavefront
@@ -409,20 +396,19 @@ __global__ __launch_bounds__(kExchThreads) void k_smp_exchange(SmpParams p, int 
   for (int e = tid; e < KT * kDim; e += nt) {
     const int q = e / kDim, d = e - q * kDim, k = q / T, j = q - k * T;
     if (j >= Tc) continue;
-    const int r = S[q];
-    const int64_t slot = (int64_t)k * W + P[q], src = (int64_t)r * W + P[r * T + j];
-    x_out[slot * kDim + d] = x_in[src * kDim + d];
+    x_out[((int64_t)k * W + P[q]) * kDim + d] = X[((int)S[q] * T + j) * kDim + d];
   }
 }
 
 // chains per workgroup of the exchange kernel: 64, or fewer so that its LDS
 // stays within 64 KB (K <= 64 rungs)
 size_t exchange_lds(int K, int T) {
-  return (size_t)K * (sizeof(double) + sizeof(int32_t)) + (size_t)K * T * (4 * sizeof(double) + sizeof(int32_t) + 1);
+  return (size_t)K * (sizeof(double) + sizeof(int32_t)) +
+         (size_t)K * T * ((4 + kDim) * sizeof(double) + sizeof(int32_t) + 1);
 }
 int exchange_chains(int K) {
   int T = 64;
-  while (T > 16 && exchange_lds(K, T) > 65536) T /= 2;
+  while (T > 1 && exchange_lds(K, T) > 65536) T /= 2;
   return T;
 }
 
@@ -448,8 +434,6 @@ struct mbh_sampler {
   int K = 0, W = 0, H = 0;
   SmpParams p{};
   double *lo = nullptr, *hi = nullptr, *betas = nullptr;
-  double *swap_logv = nullptr;  // [(K-1) W] ln v of the exchanges of one iteration
-  int32_t *swap_shift = nullptr;  // [K-1]
   double *x_alt = nullptr;        // [K W][11] the other buffer of the walkers (swapped with x)
   double *x = nullptr, *lnL = nullptr, *dhhh = nullptr, *th = nullptr;
   double *y = nullptr, *thy = nullptr, *lny = nullptr, *dhy = nullptr, *lz = nullptr;
@@ -516,8 +500,7 @@ extern "C" mbh_status mbh_sampler_create(mbh_ctx *ctx, const mbh_sampler_config 
       (e = smp_alloc(s, &s->th, n * kDim)) || (e = smp_alloc(s, &s->y, nh * kDim)) ||
       (e = smp_alloc(s, &s->thy, nh * kDim)) || (e = smp_alloc(s, &s->lny, nh)) || (e = smp_alloc(s, &s->dhy, 2 * nh)) ||
       (e = smp_alloc(s, &s->lz, nh)) || (e = smp_alloc(s, &s->kind, nh)) || (e = smp_alloc(s, &s->counts, K * 8)) ||
-      (e = smp_alloc(s, &s->swaps, K)) || (e = smp_alloc(s, &s->swap_logv, (size_t)std::max(K - 1, 1) * W)) ||
-      (e = smp_alloc(s, &s->swap_shift, std::max(K - 1, 1))) ||
+      (e = smp_alloc(s, &s->swaps, K)) ||
       (e = smp_alloc(s, &s->x_alt, n * kDim))) {
     sampler_free(s);
     return e;
@@ -645,17 +628,12 @@ extern "C" mbh_status mbh_sampler_accept(mbh_sampler *s, int half, const double 
   return MBH_OK;
 }
 
-// the exchanges of the iteration; `drawn`: their uniforms are already in
-// swap_logv, swap_shift
-static mbh_status smp_swap(mbh_sampler *s, bool drawn, hipStream_t st) {
+// the exchanges of the iteration
+static mbh_status smp_swap(mbh_sampler *s, hipStream_t st) {
   if (s->K > 1) {
-    const int np = (s->K - 1) * s->W;
-    if (!drawn)
-      hipLaunchKernelGGL(k_smp_swap_prep, dim3((np + 255) / 256), dim3(256), 0, st, s->p, (uint32_t)s->it,
-                         s->swap_logv, s->swap_shift);
     const int T = exchange_chains(s->K);
     hipLaunchKernelGGL(k_smp_exchange, dim3((s->W + T - 1) / T), dim3(kExchThreads), exchange_lds(s->K, T), st,
-                       s->p, T, s->swap_logv, s->swap_shift, s->x, s->x_alt, s->lnL, s->dhhh, s->swaps);
+                       s->p, (uint32_t)s->it, T, s->x, s->x_alt, s->lnL, s->dhhh, s->swaps);
     std::swap(s->x, s->x_alt);
   }
   HIP_TRY(hipGetLastError());
@@ -666,7 +644,7 @@ static mbh_status smp_swap(mbh_sampler *s, bool drawn, hipStream_t st) {
 extern "C" mbh_status mbh_sampler_swap(mbh_sampler *s, hipStream_t st) {
   if (!s) return mbh_fail(MBH_EINVAL, "null sampler");
   HIP_TRY(hipSetDevice(s->ctx->device));
-  return smp_swap(s, false, st);
+  return smp_swap(s, st);
 }
 
 // one half step with the heterodyned likelihood: proposals fused with the
@@ -675,11 +653,9 @@ static mbh_status smp_half_het(mbh_sampler *s, const mbh_ref *ref, int half, hip
   MBH_TRY(smp_batches(s, ref));
   const int nh = s->K * s->H;
   const WorkItem *items = batch_device_items(s->half_batch);
-  const bool draw = half == 0 && s->K > 1;
   const int n0 = s->half_n0, nb0 = (n0 + 63) / 64, nb1 = (nh - n0 + 63) / 64;
   hipLaunchKernelGGL(k_smp_propose_setup, dim3(nb0 + nb1), dim3(128), 0, st, s->p, half, (uint32_t)s->it, s->x, s->y,
-                     s->thy, s->kind, s->lz, items, n0, nb0, draw ? s->swap_logv : nullptr,
-                     draw ? s->swap_shift : nullptr);
+                     s->thy, s->kind, s->lz, items, n0, nb0);
   MBH_TRY(mbh_batch_launch_stage(s->half_batch, MBH_STAGE_MAIN, st));
   const int fb0 = (n0 + 255) / 256, fb1 = (nh - n0 + 255) / 256;
   hipLaunchKernelGGL(k_smp_final_accept, dim3(fb0 + fb1), dim3(256), 0, st, s->p, half, (uint32_t)s->it, items, n0,
@@ -695,7 +671,7 @@ extern "C" mbh_status mbh_sampler_step(mbh_sampler *s, const mbh_likelihood *lik
   for (int64_t i = 0; i < n_iter; ++i) {
     if (like->ref) {
       for (int half = 0; half < 2; ++half) MBH_TRY(smp_half_het(s, like->ref, half, st));
-      MBH_TRY(smp_swap(s, s->K > 1, st));
+      MBH_TRY(smp_swap(s, st));
       continue;
     }
     for (int half = 0; half < 2; ++half) {
@@ -703,7 +679,7 @@ extern "C" mbh_status mbh_sampler_step(mbh_sampler *s, const mbh_likelihood *lik
       MBH_TRY(smp_like(s, like, true, st));
       MBH_TRY(mbh_sampler_accept(s, half, s->lny, s->dhy, st));
     }
-    MBH_TRY(smp_swap(s, false, st));
+    MBH_TRY(smp_swap(s, st));
   }
   return MBH_OK;
 }
@@ -732,7 +708,7 @@ extern "C" mbh_status mbh_sampler_step_served(mbh_sampler *s, mbh_server *srv, i
       HIP_TRY(hipMemcpyAsync(s->dhy, s->h_dh, 2 * nh * sizeof(double), hipMemcpyHostToDevice, st));
       MBH_TRY(mbh_sampler_accept(s, half, s->lny, s->dhy, st));
     }
-    MBH_TRY(smp_swap(s, false, st));
+    MBH_TRY(smp_swap(s, st));
   }
   return MBH_OK;
 }
