@@ -206,15 +206,16 @@ def test_sampler_exchanges_move_overlaps(M, ctx, src):
     gref.close()
 
 
-@pytest.mark.parametrize("prec,mixed_rungs", [("fp64", 0), ("mixed", 0), ("mixed", 2)])
-def test_sampler_step_equals_separate_calls(M, ctx, src, prec, mixed_rungs):
+@pytest.mark.parametrize("prec,mixed_rungs,K", [("fp64", 0, 4), ("mixed", 0, 4), ("mixed", 2, 4), ("mixed", 4, 4),
+                                                ("mixed", 9, 4), ("fp64", 0, 1), ("mixed", 1, 2)])
+def test_sampler_step_equals_separate_calls(M, ctx, src, prec, mixed_rungs, K):
     """mbh_sampler_step with the heterodyned likelihood fuses the proposals
     with the batch's walker setup and the batch's totals with the decisions;
     its states must equal, bit for bit, those of the separate calls
     (propose, heterodyned calls over the proposals' theta, accept, swap)."""
     import torch
 
-    K, W, n_it = 4, 32, 8
+    W, n_it = 32, 8
     p = M.FP64 if prec == "fp64" else M.MIXED
     lo, hi = OS.prior_box(src["g"].t_obs)
     betas = 1.0 / 2.0 ** np.arange(K)
@@ -247,7 +248,7 @@ def test_sampler_step_equals_separate_calls(M, ctx, src, prec, mixed_rungs):
     ta, tb = a.stats(), b.stats()
     for key in ("accepted", "proposed", "swaps"):
         assert np.array_equal(ta[key], tb[key]), key
-    print(f"[sampler] fused step == separate calls ({prec}, mixed_rungs={mixed_rungs}): {n_it} iterations, "
+    print(f"[sampler] fused step == separate calls ({prec}, mixed_rungs={mixed_rungs}, K={K}): {n_it} iterations, "
           f"{int(ta['accepted'].sum())} moves accepted", flush=True)
     a.close()
     b.close()
