@@ -689,11 +689,11 @@ extern "C" mbh_status mbh_sampler_step_served(mbh_sampler *s, mbh_server *srv, i
   if (!s || !srv || n_iter < 0) return mbh_fail(MBH_EINVAL, "bad argument");
   HIP_TRY(hipSetDevice(s->ctx->device));
   const int64_t nh = (int64_t)s->K * s->H;
-  if (!s->h_theta) {
-    HIP_TRY(hipHostMalloc((void **)&s->h_theta, nh * kDim * sizeof(double), hipHostMallocDefault));
-    HIP_TRY(hipHostMalloc((void **)&s->h_lnl, nh * sizeof(double), hipHostMallocDefault));
-    HIP_TRY(hipHostMalloc((void **)&s->h_dh, 2 * nh * sizeof(double), hipHostMallocDefault));
-  }
+  // staging allocated on first use (each buffer on its own, so a call after a
+  // failed allocation tries again)
+  if (!s->h_theta) HIP_TRY(hipHostMalloc((void **)&s->h_theta, nh * kDim * sizeof(double), hipHostMallocDefault));
+  if (!s->h_lnl) HIP_TRY(hipHostMalloc((void **)&s->h_lnl, nh * sizeof(double), hipHostMallocDefault));
+  if (!s->h_dh) HIP_TRY(hipHostMalloc((void **)&s->h_dh, 2 * nh * sizeof(double), hipHostMallocDefault));
   for (int64_t i = 0; i < n_iter; ++i) {
     for (int half = 0; half < 2; ++half) {
       MBH_TRY(mbh_sampler_propose(s, half, st));
