@@ -309,6 +309,15 @@ def test_sampler_served_equals_batched(M, ctx, src, prec):
     print(f"[sampler] served ({prec}): 3 samplers x {n_it} iterations equal the batched runs; request latency "
           f"median {np.median(np.concatenate(lats)) * 1e3:.3f} ms", flush=True)
     srv.close()
+    # a half step larger than the server's batch cap is refused, not truncated
+    small = M.Server(ctx, [gref], max_batch_walkers=K * W // 2 - 1, prec=p)
+    c = M.Sampler(ctx, betas, W, lo, hi, seed=1, prec=p)
+    c.set_walkers(_start(src, K, W, 1).reshape(-1, 11), like)
+    with pytest.raises(M.MbhError) as e:
+        c.step_served(small, 0, 1)
+    assert e.value.status == M.MBH_EAGAIN
+    c.close()
+    small.close()
     gref.close()
 
 
