@@ -3,9 +3,13 @@
 // proposals and three kinds of sky-mode hops; the extracted-SNR stopping rule
 // of the first search and the maximum-likelihood convergence rule of the
 // heterodyned search; the reference moved to the best walker every few
-// thousand iterations).  Walkers, proposals and decisions stay in HBM; the
-// likelihood of a half ensemble is one batch launch (heterodyned) or one
-// full-grid call.
+// thousand iterations).  Walkers, proposals and decisions stay in HBM.  With
+// the heterodyned likelihood a half step is the sampler's batch's main pass
+// between two kernels of the sampler's own (proposals fused with the batch's
+// walker setup, the batch's totals fused with the decisions); with the full
+// grid it is a full-grid call; a sampler can also send its proposals to a
+// request server as one of its clients.  The exchanges between rungs are one
+// kernel over all walkers.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
