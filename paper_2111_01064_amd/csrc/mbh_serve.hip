@@ -470,6 +470,12 @@ struct Slot {
   WorkItem *items_h = nullptr;
   WorkTile *tiles_h = nullptr;
   WalkerTile *wtiles_h = nullptr;
+  // the pinned buffers' device addresses, read and written by k_stage
+  const double *theta_hd = nullptr;
+  double *res_hd = nullptr;
+  const WorkItem *items_hd = nullptr;
+  const WorkTile *tiles_hd = nullptr;
+  const WalkerTile *wtiles_hd = nullptr;
   double *theta_d = nullptr, *res_d = nullptr;
   WorkItem *items_d = nullptr;
   WorkTile *tiles_d = nullptr;
@@ -590,20 +596,55 @@ static void server_build(mbh_server *s, Slot &sl) {
   *sl.hdr_h = WorkHeader{n_items, (int32_t)sl.tiles.size(), sl.walkers};
 }
 
+// Copies of up to four regions of 8-byte words, one grid row per region: a
+// batch's inputs from the slot's pinned host buffers into device memory
+// (parameters and work tables in one launch), or its results back.  The
+// kernel reads and writes the pinned buffers through their device addresses,
+// so serving never waits in the runtime's copy path: there a host-to-device
+// copy from pinned memory now and then held the scheduler for 6-7 ms.
+struct StageCopy {
+  const uint64_t *src[4];
+  uint64_t *dst[4];
+  int64_t words[4];
+};
+static __global__ __launch_bounds__(256) void k_stage(StageCopy c) {
+  const int r = blockIdx.y;
+  const uint64_t *__restrict__ src = c.src[r];
+  uint64_t *__restrict__ dst = c.dst[r];
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < c.words[r]; i += (int64_t)gridDim.x * 256)
+    dst[i] = src[i];
+}
+static void stage(const StageCopy &c, int n, hipStream_t st) {
+  int64_t most = 1;
+  for (int r = 0; r < n; ++r) most = std::max(most, c.words[r]);
+  const unsigned bx = (unsigned)std::min<int64_t>((most + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_stage, dim3(bx, (unsigned)n), dim3(256), 0, st, c);
+}
+template <typename T>
+static const uint64_t *words_of(const T *p) { return (const uint64_t *)p; }
+template <typename T>
+static uint64_t *words_of(T *p) { return (uint64_t *)p; }
+static_assert(sizeof(WorkItem) % 8 == 0 && sizeof(WorkTile) % 8 == 0 && sizeof(WalkerTile) % 8 == 0,
+              "staged tables are copied as 8-byte words");
+
 static bool server_launch(mbh_server *s, Slot &sl) {
   const WorkHeader &h = *sl.hdr_h;
   hipStream_t st = sl.st;
   if (s->updates_in_flight > 0 && hipStreamWaitEvent(st, s->barrier, 0) != hipSuccess) return false;
-  bool ok = hipMemcpyAsync(sl.theta_d, sl.theta_h, sl.walkers * 11 * sizeof(double), hipMemcpyHostToDevice, st) == hipSuccess &&
-            hipMemcpyAsync(sl.items_d, sl.items_h, h.n_items * sizeof(WorkItem), hipMemcpyHostToDevice, st) == hipSuccess &&
-            hipMemcpyAsync(sl.tiles_d, sl.tiles_h, h.n_tiles * sizeof(WorkTile), hipMemcpyHostToDevice, st) == hipSuccess &&
-            hipMemcpyAsync(sl.wtiles_d, sl.wtiles_h, sl.n_wtiles * sizeof(WalkerTile), hipMemcpyHostToDevice, st) == hipSuccess;
-  if (!ok) return false;
+  StageCopy in{};
+  in.src[0] = words_of(sl.theta_hd), in.dst[0] = words_of(sl.theta_d), in.words[0] = sl.walkers * 11;
+  in.src[1] = words_of(sl.items_hd), in.dst[1] = words_of(sl.items_d);
+  in.words[1] = (int64_t)h.n_items * (int64_t)(sizeof(WorkItem) / 8);
+  in.src[2] = words_of(sl.tiles_hd), in.dst[2] = words_of(sl.tiles_d);
+  in.words[2] = h.n_tiles * (int64_t)(sizeof(WorkTile) / 8);
+  in.src[3] = words_of(sl.wtiles_hd), in.dst[3] = words_of(sl.wtiles_d);
+  in.words[3] = sl.n_wtiles * (int64_t)(sizeof(WalkerTile) / 8);
+  stage(in, 4, st);
   launch_work(true, sl.n_wtiles, sl.groups, sl.wtiles_d, sl.items_d, sl.tiles_d, st);
-  ok = hipGetLastError() == hipSuccess &&
-       hipMemcpyAsync(sl.res_h, sl.res_d, sl.walkers * 3 * sizeof(double), hipMemcpyDeviceToHost, st) == hipSuccess &&
-       hipEventRecord(sl.ev, st) == hipSuccess;
-  return ok;
+  StageCopy out{};
+  out.src[0] = words_of(sl.res_d), out.dst[0] = words_of(sl.res_hd), out.words[0] = sl.walkers * 3;
+  stage(out, 1, st);
+  return hipGetLastError() == hipSuccess && hipEventRecord(sl.ev, st) == hipSuccess;
 }
 
 // results of a finished batch into its requests' buffers (sized at submit);
@@ -663,9 +704,11 @@ static bool server_issue_update(mbh_server *s, Slot &sl) {
   const int64_t W = r->W_update;
   std::memcpy(sl.theta_h, r->theta.data(), W * 11 * sizeof(double));
   std::memcpy(sl.res_h, r->lnL_in.data(), W * sizeof(double));
-  if (hipMemcpyAsync(sl.theta_d, sl.theta_h, W * 11 * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess ||
-      hipMemcpyAsync(sl.res_d, sl.res_h, W * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess)
-    return false;
+  StageCopy in{};
+  in.src[0] = words_of(sl.theta_hd), in.dst[0] = words_of(sl.theta_d), in.words[0] = W * 11;
+  in.src[1] = words_of(sl.res_hd), in.dst[1] = words_of(sl.res_d), in.words[1] = W;
+  stage(in, 2, st);
+  if (hipGetLastError() != hipSuccess) return false;
   mbh_ref *ref = const_cast<mbh_ref *>(s->refs[r->ref]);
   if (mbh_ref_refresh(s->ctx, r->data, ref, sl.theta_d, sl.res_d, W, st) != MBH_OK) return false;
   return hipEventRecord(s->barrier, st) == hipSuccess && hipEventRecord(sl.ev, st) == hipSuccess;
@@ -798,13 +841,18 @@ extern "C" mbh_status mbh_server_create(mbh_ctx *ctx, int n_refs, const mbh_ref 
     mbh_status st;
     if (hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming) != hipSuccess ||
-        hipHostMalloc((void **)&sl.theta_h, cap * 11 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&sl.res_h, cap * 3 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&sl.theta_h, cap * 11 * sizeof(double), hipHostMallocCoherent) != hipSuccess ||
+        hipHostMalloc((void **)&sl.res_h, cap * 3 * sizeof(double), hipHostMallocCoherent) != hipSuccess ||
         hipHostMalloc((void **)&sl.hdr_h, sizeof(WorkHeader), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&sl.items_h, s->max_items * sizeof(WorkItem), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&sl.tiles_h, s->max_tiles * sizeof(WorkTile), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&sl.items_h, s->max_items * sizeof(WorkItem), hipHostMallocCoherent) != hipSuccess ||
+        hipHostMalloc((void **)&sl.tiles_h, s->max_tiles * sizeof(WorkTile), hipHostMallocCoherent) != hipSuccess ||
         hipHostMalloc((void **)&sl.wtiles_h, (cap / kWalkerTile + s->max_items + 1) * sizeof(WalkerTile),
-                      hipHostMallocDefault) != hipSuccess) {
+                      hipHostMallocCoherent) != hipSuccess ||
+        hipHostGetDevicePointer((void **)&sl.theta_hd, sl.theta_h, 0) != hipSuccess ||
+        hipHostGetDevicePointer((void **)&sl.res_hd, sl.res_h, 0) != hipSuccess ||
+        hipHostGetDevicePointer((void **)&sl.items_hd, sl.items_h, 0) != hipSuccess ||
+        hipHostGetDevicePointer((void **)&sl.tiles_hd, sl.tiles_h, 0) != hipSuccess ||
+        hipHostGetDevicePointer((void **)&sl.wtiles_hd, sl.wtiles_h, 0) != hipSuccess) {
       server_free(s);
       return mbh_fail(MBH_EDEVICE, "server host resources");
     }
