@@ -575,11 +575,11 @@ mbh_status mbh_sampler_set_walkers(mbh_sampler *s, const double *x_host, const d
 mbh_status mbh_sampler_step(mbh_sampler *s, const mbh_likelihood *like, int64_t n_iter, hipStream_t stream);
 /* n_iter iterations with the heterodyned likelihood of a request server's
  * resident reference ref_index (Sec. 3's search as one of the server's
- * clients): each half step's proposals are made on the device, copied to the
- * host and submitted as one request of n_temps * walkers_per_temp / 2
- * walkers; when it completes, its lnL and <d|h>, <h|h> go back to the device
- * and the decisions are taken there.  Synchronous (the stream is
- * synchronised at every half step; the sampler's pinned host staging is
+ * clients): the proposal kernel writes each half step's proposals into the
+ * sampler's pinned host staging, they are submitted as one request of
+ * n_temps * walkers_per_temp / 2 walkers, and when it completes the decision
+ * kernel reads its lnL and <d|h>, <h|h> from the staging (no runtime copies).
+ * Synchronous (the stream is synchronised at every half step; the staging is
  * allocated on first use).  The states equal those of mbh_sampler_step under
  * the same reference with the server's precision and mixed_rungs 0, bit for
  * bit.  latency_s [2 n_iter] or NULL: each request's latency (completion

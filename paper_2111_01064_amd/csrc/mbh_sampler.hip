@@ -453,6 +453,10 @@ struct mbh_sampler {
   // pinned host staging of one half step's proposals and results for a
   // request server (allocated on first use): theta [K W/2][11], lnL, <d|h> <h|h>
   double *h_theta = nullptr, *h_lnl = nullptr, *h_dh = nullptr;
+  // their device addresses (coherent pinned memory): the proposal kernel
+  // writes theta there and the decision kernel reads lnL and the overlaps
+  // there, so a served half step makes no runtime copies
+  double *h_theta_d = nullptr, *h_lnl_d = nullptr, *h_dh_d = nullptr;
 };
 
 static void sampler_free(mbh_sampler *s) {
@@ -695,22 +699,25 @@ extern "C" mbh_status mbh_sampler_step_served(mbh_sampler *s, mbh_server *srv, i
   const int64_t nh = (int64_t)s->K * s->H;
   // staging allocated on first use (each buffer on its own, so a call after a
   // failed allocation tries again)
-  if (!s->h_theta) HIP_TRY(hipHostMalloc((void **)&s->h_theta, nh * kDim * sizeof(double), hipHostMallocDefault));
-  if (!s->h_lnl) HIP_TRY(hipHostMalloc((void **)&s->h_lnl, nh * sizeof(double), hipHostMallocDefault));
-  if (!s->h_dh) HIP_TRY(hipHostMalloc((void **)&s->h_dh, 2 * nh * sizeof(double), hipHostMallocDefault));
+  if (!s->h_theta) HIP_TRY(hipHostMalloc((void **)&s->h_theta, nh * kDim * sizeof(double), hipHostMallocCoherent));
+  if (!s->h_lnl) HIP_TRY(hipHostMalloc((void **)&s->h_lnl, nh * sizeof(double), hipHostMallocCoherent));
+  if (!s->h_dh) HIP_TRY(hipHostMalloc((void **)&s->h_dh, 2 * nh * sizeof(double), hipHostMallocCoherent));
+  HIP_TRY(hipHostGetDevicePointer((void **)&s->h_theta_d, s->h_theta, 0));
+  HIP_TRY(hipHostGetDevicePointer((void **)&s->h_lnl_d, s->h_lnl, 0));
+  HIP_TRY(hipHostGetDevicePointer((void **)&s->h_dh_d, s->h_dh, 0));
+  const int blocks = (int)((nh + 255) / 256);
   for (int64_t i = 0; i < n_iter; ++i) {
     for (int half = 0; half < 2; ++half) {
-      MBH_TRY(mbh_sampler_propose(s, half, st));
-      HIP_TRY(hipMemcpyAsync(s->h_theta, s->thy, nh * kDim * sizeof(double), hipMemcpyDeviceToHost, st));
+      hipLaunchKernelGGL(k_smp_propose, dim3(blocks), dim3(256), 0, st, s->p, half, (uint32_t)s->it, s->x, s->y,
+                         s->h_theta_d, s->kind, s->lz);
+      HIP_TRY(hipGetLastError());
       HIP_TRY(hipStreamSynchronize(st));
       uint64_t id = 0;
       MBH_TRY(mbh_server_submit(srv, ref_index, s->h_theta, nh, &id));
       double lat = 0.0;
       MBH_TRY(mbh_server_wait(srv, id, -1, s->h_lnl, s->h_dh, nh, &lat));
       if (latency_s) latency_s[2 * i + half] = lat;
-      HIP_TRY(hipMemcpyAsync(s->lny, s->h_lnl, nh * sizeof(double), hipMemcpyHostToDevice, st));
-      HIP_TRY(hipMemcpyAsync(s->dhy, s->h_dh, 2 * nh * sizeof(double), hipMemcpyHostToDevice, st));
-      MBH_TRY(mbh_sampler_accept(s, half, s->lny, s->dhy, st));
+      MBH_TRY(mbh_sampler_accept(s, half, s->h_lnl_d, s->h_dh_d, st));
     }
     MBH_TRY(smp_swap(s, st));
   }
