@@ -876,12 +876,6 @@ def side_measurements(M, ctx, S, walkers, grid):
         log(f"[bench] serving capacity {name}: {cap['requests_per_s']:.0f} req/s, {cap['throughput_evals_s']:.3g} evals/s")
     serve["capacity_req_per_s"] = serve["mixed_capacity_req_per_s"]
     serve["capacity_evals_per_s"] = serve["mixed_capacity_evals_per_s"]
-    # one unrecorded stream per precision first: the first stream after the
-    # capacity runs has shown a single ~12 ms stall (p99 ~7.7 ms where every
-    # repeat of the same stream gives 0.8-1.0 ms); the measured streams below
-    # are the steady state
-    for name, prec in (("mixed", M.MIXED), ("fp64", M.FP64)):
-        serve_run(M, ctx, refs, pools, prec, rate_hz=0.5 * caps[name], n_req=8000, warm=1000)
     for rho in (0.5, 0.8, 0.95):
         for name, prec in (("mixed", M.MIXED), ("fp64", M.FP64)):
             r = serve_run(M, ctx, refs, pools, prec, rate_hz=rho * caps[name], n_req=20000, warm=1000)
