@@ -38,3 +38,33 @@ def test_error_strings_without_a_device():
     assert lib.mbh_strerror(-3).decode().startswith("reference")
     lib.mbh_last_error.restype = ctypes.c_char_p
     assert isinstance(lib.mbh_last_error(), bytes)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libmbh.so not built")
+def test_binding_declares_every_entry_point():
+    """The Python binding gives every declared entry point an argument list
+    (the two string functions are typed where the errors are raised)."""
+    from paper_2111_01064_amd import mbh
+
+    missing = [n for n in declared_functions()
+               if n not in mbh._SIGS and n not in ("mbh_last_error", "mbh_strerror")]
+    assert not missing, missing
+    extra = [n for n in mbh._SIGS if n not in declared_functions()]
+    assert not extra, extra
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libmbh.so not built")
+def test_binding_argument_counts_match_the_header():
+    """Each binding's argument list has as many entries as the declaration
+    has parameters (a dropped or added argument would shift every later one)."""
+    from paper_2111_01064_amd import mbh
+
+    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    checked = 0
+    for m in re.finditer(r"\b(?:mbh_status|const char \*|void)\s+(mbh_\w+)\s*\(([^;{]*?)\)\s*;", src, re.S):
+        name, params = m.group(1), m.group(2).strip()
+        n = 0 if params in ("", "void") else params.count(",") + 1
+        if name in mbh._SIGS:
+            assert len(mbh._SIGS[name]) == n, (name, n, len(mbh._SIGS[name]))
+            checked += 1
+    assert checked >= 50
