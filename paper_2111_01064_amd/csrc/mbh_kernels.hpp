@@ -865,6 +865,9 @@ constexpr int kWalkerTile = 64;
 struct WalkerTile {
   int32_t item, pad;
   int64_t w_begin;
+  // the item's fields by value: a tile's workgroup reads them in the same
+  // round of loads as the tile, not in a second one through the item index
+  WorkItem it;
 };
 
 struct WalkerTotals {
@@ -900,19 +903,13 @@ __device__ inline WalkerTotals het_walker_totals(const WorkItem &it, int64_t w) 
 }
 
 // Per-walker totals of the main pass.  One workgroup of kWalkerTile threads
-// per walker tile (items, wtiles) or, for a single item passed by value in
-// `one` with items == nullptr, per kWalkerTile consecutive walkers.
+// per walker tile (batches: items != nullptr, the item's fields read from the
+// tile) or, for a single item passed by value in `one` with items == nullptr,
+// per kWalkerTile consecutive walkers.
 static __global__ __launch_bounds__(kWalkerTile) void k_het_final(const WorkItem *__restrict__ items, WorkItem one,
                                                                   const WalkerTile *__restrict__ wtiles) {
-  int64_t w0 = (int64_t)blockIdx.x * kWalkerTile;
-  int ii = 0;
-  if (items) {
-    const WalkerTile tl = wtiles[blockIdx.x];
-    ii = tl.item;
-    w0 = tl.w_begin;
-  }
-  const WorkItem &it = items ? items[ii] : one;
-  const int64_t w = w0 + threadIdx.x;
+  const WorkItem &it = items ? wtiles[blockIdx.x].it : one;
+  const int64_t w = (items ? wtiles[blockIdx.x].w_begin : (int64_t)blockIdx.x * kWalkerTile) + threadIdx.x;
   if (w < it.W) (void)het_walker_totals(it, w);
 }
 

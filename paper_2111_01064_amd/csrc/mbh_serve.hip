@@ -29,9 +29,16 @@ WorkItem make_item(const mbh_ctx *ctx, const mbh_ref *r, int G);
 void launch_finish(const WorkItem *items, const WorkItem &one, const WalkerTile *wtiles, int64_t n_wtiles,
                    hipStream_t st);
 
-// walker tiles of one item (kWalkerTile walkers each)
-static void append_wtiles(std::vector<WalkerTile> &wt, int item, int64_t W) {
-  for (int64_t w = 0; w < W; w += kWalkerTile) wt.push_back(WalkerTile{item, 0, w});
+// walker tiles of one item (kWalkerTile walkers each), each with a copy of
+// the item's fields
+static void append_wtiles(std::vector<WalkerTile> &wt, int item, const WorkItem &it) {
+  for (int64_t w = 0; w < it.W; w += kWalkerTile) {
+    WalkerTile t{};
+    t.item = item;
+    t.w_begin = w;
+    t.it = it;
+    wt.push_back(t);
+  }
 }
 
 #define HIP_TRY(x)                                                                          \
@@ -360,7 +367,7 @@ extern "C" mbh_status mbh_batch_create_prec(mbh_ctx *ctx, int n, const mbh_ref *
       dsc_off += (size_t)W[i] * refs[i]->pm_T1 * 3;
     }
     append_tiles(tiles, cost, i, refs[i], it.G, W[i]);
-    append_wtiles(wtiles, i, W[i]);
+    append_wtiles(wtiles, i, it);
     off += W[i];
   }
   b->groups = order_tiles(tiles, cost, items.data());
@@ -588,7 +595,7 @@ static void server_build(mbh_server *s, Slot &sl) {
     append_tiles(sl.tiles, sl.cost, i, ref, G, r.W);
   }
   sl.groups = order_tiles(sl.tiles, sl.cost, sl.items_h);
-  for (int i = 0; i < n_items; ++i) append_wtiles(sl.wtiles, i, sl.items_h[i].W);
+  for (int i = 0; i < n_items; ++i) append_wtiles(sl.wtiles, i, sl.items_h[i]);
   xcd_align(sl.tiles, sl.groups, sl.wtiles, sl.items_h, n_items);
   std::memcpy(sl.tiles_h, sl.tiles.data(), sl.tiles.size() * sizeof(WorkTile));
   std::memcpy(sl.wtiles_h, sl.wtiles.data(), sl.wtiles.size() * sizeof(WalkerTile));

@@ -30,8 +30,8 @@ struct WorkTile {
 // extrinsic ones, of the same walkers
 static __global__ __launch_bounds__(2 * kWalkerTile) void k_setup_work(const WorkItem *__restrict__ items,
                                                                        const WalkerTile *__restrict__ wtiles) {
-  const WalkerTile tl = wtiles[blockIdx.x];
-  const WorkItem &it = items[tl.item];
+  const WalkerTile &tl = wtiles[blockIdx.x];
+  const WorkItem &it = tl.it;
   const int64_t w = tl.w_begin + (threadIdx.x & (kWalkerTile - 1));
   const int part = threadIdx.x < kWalkerTile ? 1 : 2;
   if (w < it.W) walker_setup(it.theta + w * 11, it.model, it.ref.modes, it.wc[w], part);
