@@ -805,13 +805,14 @@ def side_measurements(M, ctx, S, walkers, grid):
         hm[f"{name}_autotuned_lanes"] = chosen
         ln4 = [torch.empty(len(t), dtype=torch.float64, device="cuda") for t in th4]
         b4 = M.Batch(ctx, [x["ref"] for x in S4.items], th4, ln4, prec=prec)
-        wall, mean_s = time_batch(M, ctx, b4, 50, 5, st)
-        hm[f"{name}_evals_per_s"] = W4 * 50 / wall
+        # 200 timed launches after 20 (steady state, as for the step)
+        wall, mean_s = time_batch(M, ctx, b4, 200, 20, st)
+        hm[f"{name}_evals_per_s"] = W4 * 200 / wall
         hm[f"{name}_us_per_launch"] = mean_s * 1e6
-        hm[f"{name}_fp64_segments_per_launch"] = b4.fp64_segments() / 55
+        hm[f"{name}_fp64_segments_per_launch"] = b4.fp64_segments() / 220
         lnl4[name] = np.concatenate([l.cpu().numpy() for l in ln4])
         b4.close()
-        log(f"[bench] HM batch {name}: {W4} walkers, {W4 * 50 / wall:.3g} evals/s")
+        log(f"[bench] HM batch {name}: {W4} walkers, {W4 * 200 / wall:.3g} evals/s")
     hm["mixed_speedup_vs_fp64"] = hm["mixed_evals_per_s"] / hm["fp64_evals_per_s"]
     ok = np.isfinite(lnl4["fp64"])
     hm["max_abs_dlnL_mixed_vs_fp64"] = float(np.max(np.abs(lnl4["mixed"][ok] - lnl4["fp64"][ok])))
@@ -823,8 +824,8 @@ def side_measurements(M, ctx, S, walkers, grid):
                for it4, nb in zip(S4.items, nbm)]
     lnp = [torch.empty(len(t), dtype=torch.float64, device="cuda") for t in th4]
     bp = M.Batch(ctx, pm_refs, th4, lnp, prec=M.FP64)
-    wall, mean_s = time_batch(M, ctx, bp, 50, 5, st)
-    hm["per_mode_fp64_evals_per_s"] = W4 * 50 / wall
+    wall, mean_s = time_batch(M, ctx, bp, 200, 20, st)
+    hm["per_mode_fp64_evals_per_s"] = W4 * 200 / wall
     hm["per_mode_fp64_us_per_launch"] = mean_s * 1e6
     hm["per_mode_bins"] = nbm
     bp.close()

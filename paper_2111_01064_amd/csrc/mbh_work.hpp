@@ -37,8 +37,14 @@ static __global__ __launch_bounds__(2 * kWalkerTile) void k_setup_work(const Wor
   if (w < it.W) walker_setup(it.theta + w * 11, it.model, it.ref.modes, it.wc[w], part);
 }
 
+// Occupancy: the (2,2)-only kernels need 94 VGPRs (5 wavefronts per SIMD);
+// the any-mode flattened kernels ~196, i.e. 2 per SIMD, and the mixed one is
+// held to 168 for 3 (80 B of spills per lane in its FP64 recomputation
+// branch; 4 % faster on a 16-source higher-mode batch, while the FP64 one
+// ran 1 % slower at 3, so it stays at 2).
 template <typename R, bool DH, int G, bool HM>
-__global__ __launch_bounds__(kBlock, 2) void k_het_tiles(const WorkItem *__restrict__ items,
+__global__ __launch_bounds__(kBlock, (HM && G == 0 && sizeof(R) == 4) ? 3 : 2) void k_het_tiles(
+    const WorkItem *__restrict__ items,
                                                          const WorkTile *__restrict__ tiles) {
   const WorkTile tl = tiles[blockIdx.x];
   // the item's fields are uniform: load them once, up front, into scalars
