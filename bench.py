@@ -381,6 +381,9 @@ def main():
                     help="run only the sampler search on the loudest source and exit (for profiler runs)")
     ap.add_argument("--ingest-only", action="store_true",
                     help="time only the TDI ingest (X, Y, Z -> A, E, T band) and exit (for profiler runs)")
+    ap.add_argument("--hm-only", action="store_true",
+                    help="time only the 16-source higher-mode batch (mode-summed and per-mode binning) and exit "
+                         "(for profiler runs; with --mapping, no autotuning)")
     ap.add_argument("--mixed-tol", type=float, default=None,
                     help="estimated-error tolerance of the mixed path (library default 9e-4; inf: no FP64 "
                          "recomputation, 0: everything in FP64)")
@@ -400,6 +403,9 @@ def main():
     grid = I.grid_lisa()
     if args.ingest_only:
         print(json.dumps(ingest_leg(M, ctx)))
+        return
+    if args.hm_only:
+        print(json.dumps(hm_batch_leg(M, ctx, grid, args.mapping, method_error=False), default=float))
         return
     if args.sampler_only:
         S = Sources(M, ctx, grid, 2)
@@ -688,6 +694,84 @@ def sampler_search(M, ctx, item, prec=None, mixed_rungs=0):
     return out
 
 
+def hm_batch_leg(M, ctx, grid, mapping=None, method_error=True):
+    """Ragged higher-mode batch: 16 sources, modes 1-6, N_b 64-512, W
+    128-4096, with the mode-summed ratio (both precisions) and with per-mode
+    binning (FP64).  ``mapping`` fixes the mapping of every item instead of
+    autotuning it (profiler runs); ``method_error`` adds the comparison with
+    the full-grid likelihood on a walker subset."""
+    import torch
+
+    shapes = I.batch_shapes(I.rng_for(4, 0), 16)
+    S4 = Sources(M, ctx, grid, 16, modes_list=[s[0] for s in shapes], n_bins_list=[s[1] for s in shapes], cfg=4)
+    th4 = []
+    for item, (_, _, W) in zip(S4.items, shapes):
+        th4.append(torch.as_tensor(S4.walkers(item, (1, 4, 16, 64), (W + 3) // 4)[:W], device="cuda"))
+    W4 = sum(len(t) for t in th4)
+    hm = {"sources": 16, "walkers": W4, "shapes": [[int(m), int(nb), int(w)] for (m, nb, w) in shapes]}
+    st = torch.cuda.Stream()
+    lnl4 = {}
+    for name, prec in (("fp64", M.FP64), ("mixed", M.MIXED)):
+        chosen = []
+        for it4, t4, sh in zip(S4.items, th4, shapes):
+            if mapping is None:
+                chosen.append(int(M.autotune_heterodyned(ctx, it4["ref"], t4, prec)))
+            else:
+                M.set_lanes(ctx, int(sh[1]), bin(int(sh[0])).count("1"), prec, mapping)
+                chosen.append(mapping)
+        # lanes per walker the autotuner picked per item (0 = flattened, one lane per walker and edge)
+        hm[f"{name}_autotuned_lanes"] = chosen
+        ln4 = [torch.empty(len(t), dtype=torch.float64, device="cuda") for t in th4]
+        b4 = M.Batch(ctx, [x["ref"] for x in S4.items], th4, ln4, prec=prec)
+        # 200 timed launches after 20 (steady state, as for the step)
+        wall, mean_s = time_batch(M, ctx, b4, 200, 20, st)
+        hm[f"{name}_evals_per_s"] = W4 * 200 / wall
+        hm[f"{name}_us_per_launch"] = mean_s * 1e6
+        hm[f"{name}_fp64_segments_per_launch"] = b4.fp64_segments() / 220
+        lnl4[name] = np.concatenate([l.cpu().numpy() for l in ln4])
+        b4.close()
+        log(f"[bench] HM batch {name}: {W4} walkers, {W4 * 200 / wall:.3g} evals/s")
+    hm["mixed_speedup_vs_fp64"] = hm["mixed_evals_per_s"] / hm["fp64_evals_per_s"]
+    ok = np.isfinite(lnl4["fp64"])
+    hm["max_abs_dlnL_mixed_vs_fp64"] = float(np.max(np.abs(lnl4["mixed"][ok] - lnl4["fp64"][ok])))
+    # the same sources and walkers with per-mode relative binning (each mode
+    # its own bins, log-uniform 64-512 per mode; FP64), and the method error
+    # of both schemes against the full-grid likelihood on a walker subset
+    nbm = [I.per_mode_bins(I.rng_for(4, 200 + k), sh[0]) for k, sh in enumerate(shapes)]
+    pm_refs = [M.build_reference_coeffs_pm(ctx, it4["data"], M.MODEL_IMR, it4["modes"], it4["th"], nb)
+               for it4, nb in zip(S4.items, nbm)]
+    lnp = [torch.empty(len(t), dtype=torch.float64, device="cuda") for t in th4]
+    bp = M.Batch(ctx, pm_refs, th4, lnp, prec=M.FP64)
+    wall, mean_s = time_batch(M, ctx, bp, 200, 20, st)
+    hm["per_mode_fp64_evals_per_s"] = W4 * 200 / wall
+    hm["per_mode_fp64_us_per_launch"] = mean_s * 1e6
+    hm["per_mode_bins"] = nbm
+    bp.close()
+    lnp = [l.cpu().numpy() for l in lnp]
+    if not method_error:
+        for r in pm_refs:
+            r.close()
+        return hm
+    err_sum, err_pm = [], []
+    for k, (it4, t4) in enumerate(zip(S4.items, th4)):
+        idx = np.arange(0, len(t4), max(1, len(t4) // 32))[:32]
+        sub = t4[torch.as_tensor(idx, device="cuda")].contiguous()
+        lf = M.loglike_full(ctx, it4["data"], M.MODEL_IMR, it4["modes"], sub, M.FP64).cpu().numpy()
+        off = sum(len(x) for x in th4[:k])
+        err_sum.append(np.abs(lnl4["fp64"][off + idx] - lf))
+        err_pm.append(np.abs(lnp[k][idx] - lf))
+    es, ep = np.concatenate(err_sum), np.concatenate(err_pm)
+    hm["method_error_vs_full_grid"] = {
+        "walkers": int(es.size),
+        "mode_summed": {"max": float(es.max()), "median": float(np.median(es))},
+        "per_mode": {"max": float(ep.max()), "median": float(np.median(ep))}}
+    for r in pm_refs:
+        r.close()
+    log(f"[bench] HM batch per-mode FP64: {hm['per_mode_fp64_evals_per_s']:.3g} evals/s; method error "
+        f"{hm['method_error_vs_full_grid']}")
+    return hm
+
+
 def side_measurements(M, ctx, S, walkers, grid):
     import torch
 
@@ -787,67 +871,7 @@ def side_measurements(M, ctx, S, walkers, grid):
     out["reference_update_step_latency"] = lat
     log(f"[bench] steps with a reference update every 10th step: {lat}")
     r.close()
-    # ragged higher-mode batch: 16 sources, modes 1-6, N_b 64-512, W 128-4096
-    shapes = I.batch_shapes(I.rng_for(4, 0), 16)
-    S4 = Sources(M, ctx, grid, 16, modes_list=[s[0] for s in shapes], n_bins_list=[s[1] for s in shapes], cfg=4)
-    th4 = []
-    for item, (_, _, W) in zip(S4.items, shapes):
-        th4.append(torch.as_tensor(S4.walkers(item, (1, 4, 16, 64), (W + 3) // 4)[:W], device="cuda"))
-    W4 = sum(len(t) for t in th4)
-    hm = {"sources": 16, "walkers": W4, "shapes": [[int(m), int(nb), int(w)] for (m, nb, w) in shapes]}
-    st = torch.cuda.Stream()
-    lnl4 = {}
-    for name, prec in (("fp64", M.FP64), ("mixed", M.MIXED)):
-        chosen = []
-        for it4, t4 in zip(S4.items, th4):
-            chosen.append(int(M.autotune_heterodyned(ctx, it4["ref"], t4, prec)))
-        # lanes per walker the autotuner picked per item (0 = flattened, one lane per walker and edge)
-        hm[f"{name}_autotuned_lanes"] = chosen
-        ln4 = [torch.empty(len(t), dtype=torch.float64, device="cuda") for t in th4]
-        b4 = M.Batch(ctx, [x["ref"] for x in S4.items], th4, ln4, prec=prec)
-        # 200 timed launches after 20 (steady state, as for the step)
-        wall, mean_s = time_batch(M, ctx, b4, 200, 20, st)
-        hm[f"{name}_evals_per_s"] = W4 * 200 / wall
-        hm[f"{name}_us_per_launch"] = mean_s * 1e6
-        hm[f"{name}_fp64_segments_per_launch"] = b4.fp64_segments() / 220
-        lnl4[name] = np.concatenate([l.cpu().numpy() for l in ln4])
-        b4.close()
-        log(f"[bench] HM batch {name}: {W4} walkers, {W4 * 200 / wall:.3g} evals/s")
-    hm["mixed_speedup_vs_fp64"] = hm["mixed_evals_per_s"] / hm["fp64_evals_per_s"]
-    ok = np.isfinite(lnl4["fp64"])
-    hm["max_abs_dlnL_mixed_vs_fp64"] = float(np.max(np.abs(lnl4["mixed"][ok] - lnl4["fp64"][ok])))
-    # the same sources and walkers with per-mode relative binning (each mode
-    # its own bins, log-uniform 64-512 per mode; FP64), and the method error
-    # of both schemes against the full-grid likelihood on a walker subset
-    nbm = [I.per_mode_bins(I.rng_for(4, 200 + k), sh[0]) for k, sh in enumerate(shapes)]
-    pm_refs = [M.build_reference_coeffs_pm(ctx, it4["data"], M.MODEL_IMR, it4["modes"], it4["th"], nb)
-               for it4, nb in zip(S4.items, nbm)]
-    lnp = [torch.empty(len(t), dtype=torch.float64, device="cuda") for t in th4]
-    bp = M.Batch(ctx, pm_refs, th4, lnp, prec=M.FP64)
-    wall, mean_s = time_batch(M, ctx, bp, 200, 20, st)
-    hm["per_mode_fp64_evals_per_s"] = W4 * 200 / wall
-    hm["per_mode_fp64_us_per_launch"] = mean_s * 1e6
-    hm["per_mode_bins"] = nbm
-    bp.close()
-    lnp = [l.cpu().numpy() for l in lnp]
-    err_sum, err_pm = [], []
-    for k, (it4, t4) in enumerate(zip(S4.items, th4)):
-        idx = np.arange(0, len(t4), max(1, len(t4) // 32))[:32]
-        sub = t4[torch.as_tensor(idx, device="cuda")].contiguous()
-        lf = M.loglike_full(ctx, it4["data"], M.MODEL_IMR, it4["modes"], sub, M.FP64).cpu().numpy()
-        off = sum(len(x) for x in th4[:k])
-        err_sum.append(np.abs(lnl4["fp64"][off + idx] - lf))
-        err_pm.append(np.abs(lnp[k][idx] - lf))
-    es, ep = np.concatenate(err_sum), np.concatenate(err_pm)
-    hm["method_error_vs_full_grid"] = {
-        "walkers": int(es.size),
-        "mode_summed": {"max": float(es.max()), "median": float(np.median(es))},
-        "per_mode": {"max": float(ep.max()), "median": float(np.median(ep))}}
-    for r in pm_refs:
-        r.close()
-    log(f"[bench] HM batch per-mode FP64: {hm['per_mode_fp64_evals_per_s']:.3g} evals/s; method error "
-        f"{hm['method_error_vs_full_grid']}")
-    out["hm_batch"] = hm
+    out["hm_batch"] = hm_batch_leg(M, ctx, grid)
     # a heterodyned search (Sec. 3's second module) on the loudest source of
     # the step: 10 rungs x 400 walkers from a wide cloud around the source,
     # the reference starting at a hot walker and moved to the best walker on

@@ -18,6 +18,10 @@ struct mbh_ctx {
   size_t budget = 0;
   std::atomic<size_t> in_use{0};
   int n_cu = 256;
+  // LDS one workgroup may take: a per-mode item's cross pass runs one
+  // workgroup per walker when the walker's deltas fit (else the chunked pass);
+  // MBH_PM_CROSS_LDS_MAX (bytes) lowers it, 0 forcing the chunked pass
+  size_t lds_max = 65536;
   std::string arch;
   mutable std::mutex mu;
   // lanes per walker of the heterodyned kernel, keyed by (n_bins, n_modes, precision)

@@ -559,6 +559,21 @@ constexpr double kMixedRouteTol = 9e-4;
 constexpr int kChunk = 63;
 constexpr int kWaves = kBlock / 64;
 
+// A pointer read from a work item is generic, so loads through it are flat
+// loads, which wait on the LDS counter as well; this view of it in the
+// global address space (where the work list's arrays live) gives global loads.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T *as_global(const T *p) {
+  return (const __attribute__((address_space(1))) T *)p;
+}
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *as_global(T *p) {
+  return (__attribute__((address_space(1))) T *)p;
+}
+// two doubles as a native vector: loads, stores and copies of it work in
+// every address space (unlike those of the double2 class)
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+
 // Per-mode relative binning (higher modes, each mode with its own bins and
 // ratio r_L = h_L / h0_L; Sec. 2.2 applied per mode).  The reference's edge
 // arrays (F, fq, psi0, is064) hold the edges of all its modes one mode after
@@ -578,6 +593,8 @@ struct PmView {
   const double *ccoef;     // [C][T2][4]: Re/Im C0, Re/Im C1 of the merged bins
   double2 *dsc;            // [W][T1][C] delta = r - 1 at every edge (per-call scratch)
   int32_t T1, T2;
+  int32_t cross_wg;        // 1: the cross pass runs one workgroup per walker, its deltas staged in LDS
+  int32_t pad;
 };
 
 // One heterodyned work item: a reference, a walker batch, its outputs and
@@ -885,8 +902,8 @@ __device__ inline WalkerTotals het_walker_totals(const WorkItem &it, int64_t w) 
   for (int k = 0; k < n_slot; ++k)
 #pragma unroll
     for (int q = 0; q < 3; ++q) s[q] += p[4 * k + q];
-  if (it.E2 > 1) {  // the cross pass of a per-mode reference
-    const int n2 = (int)((w * it.E2 + it.E2 - 2) / kChunk - (w * it.E2) / kChunk) + 1;
+  if (it.E2 > 1) {  // the cross pass of a per-mode reference (one slot when a workgroup took the walker)
+    const int n2 = it.pm.cross_wg ? 1 : (int)((w * it.E2 + it.E2 - 2) / kChunk - (w * it.E2) / kChunk) + 1;
     for (int k = 0; k < n2; ++k)
 #pragma unroll
       for (int q = 0; q < 3; ++q) s[q] += p[4 * (it.K1 + k) + q];
@@ -1254,13 +1271,13 @@ static __global__ __launch_bounds__(64) void k_pm_ref_edges(const WalkerC *__res
 // without cancellation, as het_edge (FP64)
 __device__ __forceinline__ void pm_edge(const WorkItem &it, const WalkerC &c, int tau, cx<double> dl[3]) {
   const HetRef &ref = it.ref;
-  const double *q = ref.fq + (int64_t)kFq * tau;
+  const auto *q = as_global(ref.fq + (int64_t)kFq * tau);
   const FreqC fc{q[0], q[1], q[2], ref.ns64};
   const FreqPow pw{q[3], q[4], q[5], q[6]};
   cx<double> s[3];
   double psi;
-  mode_point<double>(c, it.pm.mode_of[tau], ref.F[tau], pw, fc, ref.t_obs, s, psi);
-  const double dpsi = reduce_2pi(psi - ref.psi0[tau]);
+  mode_point<double>(c, *as_global(it.pm.mode_of + tau), *as_global(ref.F + tau), pw, fc, ref.t_obs, s, psi);
+  const double dpsi = reduce_2pi(psi - *as_global(ref.psi0 + tau));
   double hs, hc;
   sincos_red<double>(0.5 * dpsi, hs, hc);
   const cx<double> em1 = mk<double>(-2.0 * hs * hs, -2.0 * hs * hc);
@@ -1268,7 +1285,8 @@ __device__ __forceinline__ void pm_edge(const WorkItem &it, const WalkerC &c, in
   const int T1 = it.pm.T1;
 #pragma unroll
   for (int ch = 0; ch < 3; ++ch) {
-    const cx<double> is0 = mk<double>(ref.is064[2 * (ch * T1 + tau)], ref.is064[2 * (ch * T1 + tau) + 1]);
+    const auto *p = as_global(ref.is064 + 2 * (ch * T1 + tau));
+    const cx<double> is0 = mk<double>(p[0], p[1]);
     cx<double> r = s[ch] * is0;
     r.re -= 1.0;
     dl[ch] = r * e + em1;
@@ -1313,16 +1331,16 @@ __device__ __forceinline__ void pm_chunk_edges(const WorkItem &it, int64_t chunk
   const bool act = v < it.W;
   const WalkerC &c = it.wc[act ? v : 0];
   const bool valid = act && c.valid;
-  const int b = it.pm.bin_of[tau];
+  const int b = *as_global(it.pm.bin_of + tau);
   const bool is_bin = valid && lane < kChunk && b >= 0;
   cx<double> dl[3];
 #pragma unroll
   for (int ch = 0; ch < 3; ++ch) dl[ch] = mk<double>(0.0, 0.0);
   if (valid) pm_edge(it, c, tau, dl);
   if (act) {
-    double2 *o = it.pm.dsc + ((int64_t)v * E + tau) * 3;
+    auto *o = as_global((dvec2 *)(it.pm.dsc + ((int64_t)v * E + tau) * 3));
 #pragma unroll
-    for (int ch = 0; ch < 3; ++ch) o[ch] = make_double2(dl[ch].re, dl[ch].im);
+    for (int ch = 0; ch < 3; ++ch) o[ch] = dvec2{dl[ch].re, dl[ch].im};
   }
   cx<double> nb[3];
 #pragma unroll
@@ -1345,6 +1363,34 @@ __device__ __forceinline__ void pm_chunk_edges(const WorkItem &it, int64_t chunk
 // dA1, dB1 their slopes): the cross terms of <h|h> linearised about the
 // merged centre, and the parts of the data and <h|h> terms that involve the
 // other mode's reference.
+// Terms of merged bin mu from the deltas D of its walker (D: LDS or global)
+template <bool DH, typename DP>
+__device__ __forceinline__ void pm_cross_bin(const WorkItem &it, int mu, DP D, double val[4]) {
+  const int T2 = it.pm.T2;
+  const auto *xp = as_global(it.pm.cross + mu);
+  const PmCross x{xp->ea, xp->eb, xp->xa, xp->xb, xp->ia, xp->ib};
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) {
+    const dvec2 a0 = D[x.ea * 3 + ch], a1 = D[(x.ea + 1) * 3 + ch];
+    const dvec2 b0 = D[x.eb * 3 + ch], b1 = D[(x.eb + 1) * 3 + ch];
+    const cx<double> sA = mk<double>((a1.x - a0.x) * x.ia, (a1.y - a0.y) * x.ia);
+    const cx<double> sB = mk<double>((b1.x - b0.x) * x.ib, (b1.y - b0.y) * x.ib);
+    const cx<double> dA = mk<double>(0.5 * (a0.x + a1.x) + sA.re * x.xa, 0.5 * (a0.y + a1.y) + sA.im * x.xa);
+    const cx<double> dB = mk<double>(0.5 * (b0.x + b1.x) + sB.re * x.xb, 0.5 * (b0.y + b1.y) + sB.im * x.xb);
+    const cx<double> cB = mk<double>(dB.re, -dB.im), cSB = mk<double>(sB.re, -sB.im);
+    const cx<double> P0 = dA * cB;
+    const cx<double> P1 = sA * cB + dA * cSB;
+    const auto *k = as_global(it.pm.ccoef + ((int64_t)ch * T2 + mu) * 4);
+    const cx<double> C0 = mk<double>(k[0], k[1]), C1 = mk<double>(k[2], k[3]);
+    const double q = (C0 * P0).re + (C1 * P1).re;
+    val[0] -= 4.0 * q;
+    if constexpr (DH) {
+      val[1] += 4.0 * ((C0 * dA).re + (C1 * sA).re + (C0 * cB).re + (C1 * cSB).re);
+      val[2] += 8.0 * (q + (C0 * dA).re + (C0 * cB).re + (C1 * sA).re + (C1 * cSB).re);
+    }
+  }
+}
+
 template <bool DH>
 __device__ __forceinline__ void pm_chunk_cross(const WorkItem &it, int64_t chunk) {
   const int lane = threadIdx.x & 63;
@@ -1361,31 +1407,37 @@ __device__ __forceinline__ void pm_chunk_cross(const WorkItem &it, int64_t chunk
   const bool valid = act && it.wc[act ? v : 0].valid;
   const bool is_bin = valid && lane < kChunk && mu < T2;
   double val[4] = {0.0, 0.0, 0.0, 0.0};
-  if (is_bin) {
-    const PmCross x = it.pm.cross[mu];
-    const double2 *D = it.pm.dsc + (int64_t)v * T1 * 3;
-#pragma unroll
-    for (int ch = 0; ch < 3; ++ch) {
-      const double2 a0 = D[x.ea * 3 + ch], a1 = D[(x.ea + 1) * 3 + ch];
-      const double2 b0 = D[x.eb * 3 + ch], b1 = D[(x.eb + 1) * 3 + ch];
-      const cx<double> sA = mk<double>((a1.x - a0.x) * x.ia, (a1.y - a0.y) * x.ia);
-      const cx<double> sB = mk<double>((b1.x - b0.x) * x.ib, (b1.y - b0.y) * x.ib);
-      const cx<double> dA = mk<double>(0.5 * (a0.x + a1.x) + sA.re * x.xa, 0.5 * (a0.y + a1.y) + sA.im * x.xa);
-      const cx<double> dB = mk<double>(0.5 * (b0.x + b1.x) + sB.re * x.xb, 0.5 * (b0.y + b1.y) + sB.im * x.xb);
-      const cx<double> cB = mk<double>(dB.re, -dB.im), cSB = mk<double>(sB.re, -sB.im);
-      const cx<double> P0 = dA * cB;
-      const cx<double> P1 = sA * cB + dA * cSB;
-      const double *k = it.pm.ccoef + ((int64_t)ch * T2 + mu) * 4;
-      const cx<double> C0 = mk<double>(k[0], k[1]), C1 = mk<double>(k[2], k[3]);
-      const double q = (C0 * P0).re + (C1 * P1).re;
-      val[0] -= 4.0 * q;
-      if constexpr (DH) {
-        val[1] += 4.0 * ((C0 * dA).re + (C1 * sA).re + (C0 * cB).re + (C1 * cSB).re);
-        val[2] += 8.0 * (q + (C0 * dA).re + (C0 * cB).re + (C1 * sA).re + (C1 * cSB).re);
-      }
-    }
-  }
+  if (is_bin) pm_cross_bin<DH>(it, mu, as_global((const dvec2 *)(it.pm.dsc + (int64_t)v * T1 * 3)), val);
   pm_store_segments<DH>(it, chunk, E, v0, j0, v, is_bin, val, it.K1);
+}
+
+// Cross pass with one workgroup of kBlock threads per walker (pm.cross_wg):
+// the walker's deltas (T1 x C complex values, contiguous) are staged in LDS
+// by coalesced loads, and every merged bin reads them there instead of
+// through the caches; thread i takes merged bins i, i + kBlock, ... in turn,
+// and the workgroup's fixed-order sum goes to the walker's slot K1.  `sd`
+// is the dynamic LDS, T1 x C double2.
+template <bool DH>
+__device__ __forceinline__ void pm_walker_cross(const WorkItem &it, int64_t w, double2 *sd) {
+  __shared__ double sh[3 * kWaves];
+  double val[4] = {0.0, 0.0, 0.0, 0.0};
+  if (it.wc[w].valid) {  // uniform over the workgroup
+    const int n = it.pm.T1 * 3;
+    const auto *D = as_global((const dvec2 *)(it.pm.dsc + w * n));
+    dvec2 *S = (dvec2 *)sd;
+    for (int i = threadIdx.x; i < n; i += kBlock) S[i] = D[i];
+    __syncthreads();
+    const dvec2 *Sc = S;
+    for (int mu = threadIdx.x; mu < it.pm.T2; mu += kBlock) pm_cross_bin<DH>(it, mu, Sc, val);
+  }
+  block_sum<3>(val, sh);
+  if (threadIdx.x == 0) {
+    double *o = it.part + (w * it.K + it.K1) * 4;
+    o[0] = val[0];
+    o[1] = val[1];
+    o[2] = val[2];
+    o[3] = 0.0;
+  }
 }
 
 // single-item launches of the two passes
@@ -1399,6 +1451,12 @@ template <bool DH>
 __global__ __launch_bounds__(kBlock, 2) void k_pm_cross(WorkItem one, int64_t n_chunks) {
   const int64_t c = (int64_t)blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (c < n_chunks) pm_chunk_cross<DH>(one, c);
+}
+// one workgroup per walker (blockIdx.x); dynamic LDS of T1 x C double2
+template <bool DH>
+__global__ __launch_bounds__(kBlock) void k_pm_cross_wg(WorkItem one) {
+  extern __shared__ double2 pm_sd[];
+  pm_walker_cross<DH>(one, blockIdx.x, pm_sd);
 }
 
 }  // namespace mbh

@@ -71,7 +71,7 @@ static double tile_cost(double work, const mbh_ref *r) {
 }
 
 static void append_tiles(std::vector<WorkTile> &tiles, std::vector<double> &cost, int item, const mbh_ref *r,
-                         int G, int64_t W) {
+                         int G, int64_t W, bool cross_wg = false) {
   const int E = r->n_bins + 1;
   const int nm = popcount_modes(r->modes ? r->modes : 1u);
   if (W <= 0) return;
@@ -81,7 +81,12 @@ static void append_tiles(std::vector<WorkTile> &tiles, std::vector<double> &cost
       tiles.push_back(WorkTile{item, kPmEdgeTiles, c});
       cost.push_back(tile_cost(1.0, r));
     }
-    if (r->pm_T2 > 0) {
+    if (cross_wg) {  // one workgroup per walker
+      for (int64_t w = 0; w < W; ++w) {
+        tiles.push_back(WorkTile{item, kPmCrossWgTiles, w});
+        cost.push_back(tile_cost(1.0, r));
+      }
+    } else if (r->pm_T2 > 0) {
       const int64_t n2 = flat_chunks(W, r->pm_T2 + 1);
       for (int64_t c = 0; c < n2; c += kWaves) {
         tiles.push_back(WorkTile{item, kPmCrossTiles, c});
@@ -112,6 +117,7 @@ static void append_tiles(std::vector<WorkTile> &tiles, std::vector<double> &cost
 struct TileGroup {
   int G, hm, prec;
   int64_t begin, count;
+  size_t lds = 0;  // dynamic LDS of the group's kernel (per-walker cross pass: its largest item's deltas)
 };
 
 // The tiles arrive as runs (consecutive tiles of one item and one kernel,
@@ -148,6 +154,8 @@ static std::vector<TileGroup> order_tiles(std::vector<WorkTile> &tiles, const st
     if (groups.empty() || groups.back().G != tiles[i].G || groups.back().hm != h || groups.back().prec != p)
       groups.push_back(TileGroup{tiles[i].G, h, p, (int64_t)i, 0});
     groups.back().count += 1;
+    if (tiles[i].G == kPmCrossWgTiles)
+      groups.back().lds = std::max(groups.back().lds, (size_t)items[tiles[i].item].pm.T1 * 3 * sizeof(double2));
   }
   return groups;
 }
@@ -160,6 +168,8 @@ static std::vector<TileGroup> order_tiles(std::vector<WorkTile> &tiles, const st
 // carry similar work, spread over all XCDs), the walker-tile array deals
 // colours in turn, and the flattened main-pass tiles, kept in their order
 // within each XCD, are dealt to the XCD of their first walker's setup tile.
+// The tiles of both passes of a per-mode item follow the same rule, so that
+// a walker's cross-pass tiles share one L2 and read its deltas from HBM once.
 // Results do not depend on the order (each walker's partial slots are fixed).
 // Dealing: position p takes the next element of colour p mod 8, or of the
 // next colour (cyclically) that still has elements; the colour classes are
@@ -206,12 +216,16 @@ static void xcd_align(std::vector<WorkTile> &tiles, const std::vector<TileGroup>
   deal_by_colour(wtiles, colour, wt2.data(), &xcd_of);
   wtiles.swap(wt2);
   for (const auto &g : groups) {
-    if (g.G != 0) continue;
+    if (g.G != 0 && g.G != kPmEdgeTiles && g.G != kPmCrossTiles && g.G != kPmCrossWgTiles) continue;
     std::vector<WorkTile> in(tiles.begin() + g.begin, tiles.begin() + g.begin + g.count);
     std::vector<uint8_t> col((size_t)g.count);
     for (int64_t i = 0; i < g.count; ++i) {
       const WorkTile &t = in[(size_t)i];
-      const int64_t w = (t.begin * kChunk) / items[t.item].E;
+      // the tile's first walker: tasks per walker E (flattened main pass, per-mode edge pass) or E2
+      // (per-mode chunked cross pass); the per-walker cross pass names its walker
+      const int64_t w = g.G == kPmCrossWgTiles
+                            ? t.begin
+                            : (t.begin * kChunk) / (g.G == kPmCrossTiles ? items[t.item].E2 : items[t.item].E);
       col[(size_t)i] = (uint8_t)xcd_of[(size_t)(wt_first[t.item] + w / kWalkerTile)];
     }
     deal_by_colour(in, col, tiles.data() + g.begin);
@@ -236,11 +250,12 @@ static void launch_group_t(const TileGroup &g, const WorkItem *items, const Work
 
 template <typename R, bool DH>
 static void launch_group(const TileGroup &g, const WorkItem *items, const WorkTile *tiles, hipStream_t st) {
-  if (g.G == kPmEdgeTiles || g.G == kPmCrossTiles) {  // per-mode items (FP64 batches only)
+  if (g.G == kPmEdgeTiles || g.G == kPmCrossTiles || g.G == kPmCrossWgTiles) {  // per-mode items (FP64 only)
     const dim3 grid((unsigned)g.count), blk(kBlock);
     const WorkTile *t = tiles + g.begin;
     if (g.G == kPmEdgeTiles) hipLaunchKernelGGL((k_pm_tiles<DH, 1>), grid, blk, 0, st, items, t);
-    else hipLaunchKernelGGL((k_pm_tiles<DH, 2>), grid, blk, 0, st, items, t);
+    else if (g.G == kPmCrossTiles) hipLaunchKernelGGL((k_pm_tiles<DH, 2>), grid, blk, 0, st, items, t);
+    else hipLaunchKernelGGL((k_pm_cross_tiles<DH>), grid, blk, g.lds, st, items, t);
     return;
   }
   if (g.hm) launch_group_t<R, DH, true>(g, items, tiles, st);
@@ -366,7 +381,7 @@ extern "C" mbh_status mbh_batch_create_prec(mbh_ctx *ctx, int n, const mbh_ref *
       it.pm.dsc = dsc + dsc_off;
       dsc_off += (size_t)W[i] * refs[i]->pm_T1 * 3;
     }
-    append_tiles(tiles, cost, i, refs[i], it.G, W[i]);
+    append_tiles(tiles, cost, i, refs[i], it.G, W[i], it.pm.cross_wg != 0);
     append_wtiles(wtiles, i, it);
     off += W[i];
   }

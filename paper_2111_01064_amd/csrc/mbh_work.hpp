@@ -63,6 +63,9 @@ __global__ __launch_bounds__(kBlock, (HM && G == 0 && sizeof(R) == 4) ? 3 : 2) v
 // group is launched after every edge-pass group).
 constexpr int kPmEdgeTiles = 128;
 constexpr int kPmCrossTiles = 129;
+// and, for items whose cross pass takes one workgroup per walker, this, with
+// `begin` the walker
+constexpr int kPmCrossWgTiles = 130;
 
 template <bool DH, int PASS>
 __global__ __launch_bounds__(kBlock, 2) void k_pm_tiles(const WorkItem *__restrict__ items,
@@ -76,6 +79,14 @@ __global__ __launch_bounds__(kBlock, 2) void k_pm_tiles(const WorkItem *__restri
   } else {
     if (c < flat_chunks(it.W, it.E2)) pm_chunk_cross<DH>(it, c);
   }
+}
+
+template <bool DH>
+__global__ __launch_bounds__(kBlock) void k_pm_cross_tiles(const WorkItem *__restrict__ items,
+                                                           const WorkTile *__restrict__ tiles) {
+  extern __shared__ double2 pm_sd[];
+  const WorkTile tl = tiles[blockIdx.x];
+  pm_walker_cross<DH>(items[tl.item], tl.begin, pm_sd);
 }
 
 }  // namespace mbh

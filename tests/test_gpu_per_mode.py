@@ -191,3 +191,47 @@ def test_pm_edge_cases(M, ctx, case):
         gr.export()
     with pytest.raises(M.MbhError):
         M.Server(ctx, [gr], prec=M.FP64)
+
+
+def test_pm_cross_pass_both_forms(M, ctx, case, monkeypatch):
+    """The cross pass with one workgroup per walker (its deltas staged in
+    LDS, the default when they fit) and in chunks over the flattened
+    (walker, merged bin) tasks (taken when a walker's deltas exceed the LDS
+    of a workgroup; forced here for a second context by
+    MBH_PM_CROSS_LDS_MAX=0) both hold the FP64 bar against the oracle, single
+    calls and batches alike, and a batch equals its single calls bit for bit
+    in either form."""
+    import torch
+
+    g = case["g"]
+    monkeypatch.setenv("MBH_PM_CROSS_LDS_MAX", "0")
+    c2 = M.Context(0)
+    monkeypatch.delenv("MBH_PM_CROSS_LDS_MAX")
+    gd2 = M.data_create(c2, torch.as_tensor(case["d"], device="cuda"), torch.as_tensor(case["psd"], device="cuda"),
+                        g.f0, g.df, g.t_obs)
+    gr2 = M.build_reference_coeffs_pm(c2, gd2, M.MODEL_IMR, M.MODES_ALL, case["th"], NB_MODE)
+    w = case["walkers"]
+    rl, rdh, rhh = case["ref"].loglike(w)
+    bar = 1e-6 + 1e-12 * np.abs(rl)
+    res = {}
+    for name, cx, gr in (("per-walker", ctx, case["gr"]), ("chunked", c2, gr2)):
+        dh = torch.empty((len(w), 2), dtype=torch.float64, device="cuda")
+        got = M.loglike_heterodyned(cx, gr, _t(w), M.FP64, dh_hh=dh).cpu().numpy()
+        print(f"[pm] cross pass {name}: max|dlnL| vs oracle {np.abs(got - rl).max():.3e}", flush=True)
+        assert np.all(np.abs(got - rl) <= bar)
+        g2 = dh.cpu().numpy()
+        assert np.all(np.abs(g2[:, 0] - rdh) <= 1e-6 + 1e-12 * np.abs(rhh))
+        assert np.all(np.abs(g2[:, 1] - rhh) <= 1e-6 + 1e-12 * np.abs(rhh))
+        parts = [w[:29], w[29:]]
+        thetas = [_t(x) for x in parts]
+        lnls = [torch.empty(len(x), dtype=torch.float64, device="cuda") for x in parts]
+        b = M.Batch(cx, [gr, gr], thetas, lnls, prec=M.FP64)
+        b.launch_direct()
+        torch.cuda.synchronize()
+        assert np.array_equal(np.concatenate([l.cpu().numpy() for l in lnls]), got)
+        b.close()
+        res[name] = got
+    assert np.all(np.abs(res["per-walker"] - res["chunked"]) <= bar)
+    gr2.close()
+    gd2.close()
+    c2.close()
