@@ -187,7 +187,14 @@ mbh_status mbh_ref_export(const mbh_ref *ref, double *edges, int64_t *kb, double
  * only and return MBH_EINVAL for MBH_MIXED.  Not for the server, the
  * device reference update, mbh_loglike_heterodyned_noalloc, the autotuner or
  * mbh_ref_export (MBH_EINVAL); mbh_ref_get_info reports the total bin count
- * and the union of the bands.
+ * and the union of the bands.  A likelihood call over such a reference runs
+ * an edge pass (every mode edge of every walker) and a cross pass (every
+ * merged bin); the cross pass takes one workgroup per walker with the
+ * walker's edge values staged in LDS (48 B per mode edge) when they fit the
+ * LDS of one workgroup, else a chunked form; the environment variable
+ * MBH_PM_CROSS_LDS_MAX (bytes), read by mbh_create, lowers that limit for
+ * the context (0: always the chunked form).  Both forms give results within
+ * the FP64 rounding of each other.
  *   n_bins_mode [6] (host): bins of each mode in the mask, in the order of
  *   the MBH_MODE_* bits, each in [1, 4096].
  * Synchronises `stream`.  Device memory during the build: 16 B per grid
