@@ -632,16 +632,16 @@ template <typename R, bool HM>
 __device__ __forceinline__ void het_edge(const HetRef &ref, const WalkerC &c, int j, cx<double> dl[3]) {
   cx<double> s[3];
   double psi;
-  const double *q = ref.fq + (int64_t)kFq * j;
+  const auto *q = as_global(ref.fq + (int64_t)kFq * j);
   const FreqC fc{q[0], q[1], q[2], sizeof(R) == 8 ? ref.ns64 : ref.ns32};
   const FreqPow pw{q[3], q[4], q[5], q[6]};
-  template_point<R, HM>(c, ref.modes, ref.F[j], pw, fc, ref.t_obs, s, psi);
+  template_point<R, HM>(c, ref.modes, *as_global(ref.F + j), pw, fc, ref.t_obs, s, psi);
   // the carrier difference enters every channel of the edge at once: formed
   // and reduced to [-pi, pi] in FP64 in both paths; its sine and cosine in
   // the template precision (in FP32 they add an edge-to-edge random error of
   // the same size as the response's, which the error estimate's calibration
   // covers)
-  const double dpsi = reduce_2pi(psi - ref.psi0[j]);
+  const double dpsi = reduce_2pi(psi - *as_global(ref.psi0 + j));
   double hs, hc;
   if constexpr (sizeof(R) == 4) {
     float hs32, hc32;
@@ -658,7 +658,8 @@ __device__ __forceinline__ void het_edge(const HetRef &ref, const WalkerC &c, in
 #pragma unroll
   for (int ch = 0; ch < 3; ++ch) {
     if (ch >= ref.n_chan) break;
-    cx<double> is0 = mk<double>(ref.is064[2 * (ch * E + j)], ref.is064[2 * (ch * E + j) + 1]);
+    const auto *p = as_global(ref.is064 + 2 * (ch * E + j));
+    cx<double> is0 = mk<double>(p[0], p[1]);
     cx<double> q = s[ch] * is0;
     q.re -= 1.0;
     dl[ch] = q * e + em1;  // r - 1 without cancellation
@@ -675,7 +676,7 @@ __device__ __forceinline__ void bin_terms(const HetRef &ref, int b, const cx<dou
 #pragma unroll
   for (int ch = 0; ch < 3; ++ch) {
     if (ch >= ref.n_chan) break;
-    const double *k = ref.coef + ((int64_t)ch * Nb + b) * 6;
+    const auto *k = as_global(ref.coef + ((int64_t)ch * Nb + b) * 6);
     // delta_0 at the bin centre and the edge difference delta_1 dF_b
     const double d0r = 0.5 * (L[ch].re + Rt[ch].re), d0i = 0.5 * (L[ch].im + Rt[ch].im);
     const double d1r = Rt[ch].re - L[ch].re, d1i = Rt[ch].im - L[ch].im;
