@@ -593,7 +593,7 @@ struct PmView {
   const double *ccoef;     // [C][T2][4]: Re/Im C0, Re/Im C1 of the merged bins
   double2 *dsc;            // [W][T1][C] delta = r - 1 at every edge (per-call scratch)
   int32_t T1, T2;
-  int32_t cross_wg;        // 1: the cross pass runs one workgroup per walker, its deltas staged in LDS
+  int32_t cross_wg;        // > 0: the cross pass runs one workgroup per cross_wg walkers (1 or 2), deltas in LDS
   int32_t pad;
 };
 
@@ -1364,12 +1364,31 @@ __device__ __forceinline__ void pm_chunk_edges(const WorkItem &it, int64_t chunk
 // dA1, dB1 their slopes): the cross terms of <h|h> linearised about the
 // merged centre, and the parts of the data and <h|h> terms that involve the
 // other mode's reference.
-// Terms of merged bin mu from the deltas D of its walker (D: LDS or global)
-template <bool DH, typename DP>
-__device__ __forceinline__ void pm_cross_bin(const WorkItem &it, int mu, DP D, double val[4]) {
-  const int T2 = it.pm.T2;
+// Constants of merged bin mu: its edges, offsets and reciprocal widths, and
+// per channel C0, C1 (Re, Im)
+struct PmBinC {
+  PmCross x;
+  double k[12];
+};
+__device__ __forceinline__ PmBinC pm_bin_consts(const WorkItem &it, int mu) {
+  PmBinC b;
   const auto *xp = as_global(it.pm.cross + mu);
-  const PmCross x{xp->ea, xp->eb, xp->xa, xp->xb, xp->ia, xp->ib};
+  b.x = PmCross{xp->ea, xp->eb, xp->xa, xp->xb, xp->ia, xp->ib};
+  const int T2 = it.pm.T2;
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) {
+    const auto *k = as_global(it.pm.ccoef + ((int64_t)ch * T2 + mu) * 4);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) b.k[4 * ch + q] = k[q];
+  }
+  return b;
+}
+
+// Terms of a merged bin (constants b) from the deltas D of one walker (D:
+// LDS or global)
+template <bool DH, typename DP>
+__device__ __forceinline__ void pm_cross_terms(const PmBinC &b, DP D, double val[4]) {
+  const PmCross &x = b.x;
 #pragma unroll
   for (int ch = 0; ch < 3; ++ch) {
     const dvec2 a0 = D[x.ea * 3 + ch], a1 = D[(x.ea + 1) * 3 + ch];
@@ -1381,8 +1400,7 @@ __device__ __forceinline__ void pm_cross_bin(const WorkItem &it, int mu, DP D, d
     const cx<double> cB = mk<double>(dB.re, -dB.im), cSB = mk<double>(sB.re, -sB.im);
     const cx<double> P0 = dA * cB;
     const cx<double> P1 = sA * cB + dA * cSB;
-    const auto *k = as_global(it.pm.ccoef + ((int64_t)ch * T2 + mu) * 4);
-    const cx<double> C0 = mk<double>(k[0], k[1]), C1 = mk<double>(k[2], k[3]);
+    const cx<double> C0 = mk<double>(b.k[4 * ch], b.k[4 * ch + 1]), C1 = mk<double>(b.k[4 * ch + 2], b.k[4 * ch + 3]);
     const double q = (C0 * P0).re + (C1 * P1).re;
     val[0] -= 4.0 * q;
     if constexpr (DH) {
@@ -1408,36 +1426,53 @@ __device__ __forceinline__ void pm_chunk_cross(const WorkItem &it, int64_t chunk
   const bool valid = act && it.wc[act ? v : 0].valid;
   const bool is_bin = valid && lane < kChunk && mu < T2;
   double val[4] = {0.0, 0.0, 0.0, 0.0};
-  if (is_bin) pm_cross_bin<DH>(it, mu, as_global((const dvec2 *)(it.pm.dsc + (int64_t)v * T1 * 3)), val);
+  if (is_bin) pm_cross_terms<DH>(pm_bin_consts(it, mu), as_global((const dvec2 *)(it.pm.dsc + (int64_t)v * T1 * 3)), val);
   pm_store_segments<DH>(it, chunk, E, v0, j0, v, is_bin, val, it.K1);
 }
 
-// Cross pass with one workgroup of kBlock threads per walker (pm.cross_wg):
-// the walker's deltas (T1 x C complex values, contiguous) are staged in LDS
-// by coalesced loads, and every merged bin reads them there instead of
-// through the caches; thread i takes merged bins i, i + kBlock, ... in turn,
-// and the workgroup's fixed-order sum goes to the walker's slot K1.  `sd`
-// is the dynamic LDS, T1 x C double2.
+// Cross pass with one workgroup of kBlock threads per pm.cross_wg walkers
+// (1 or 2; 0 selects the chunked pass): each walker's deltas (T1 x C complex
+// values, contiguous) are staged in LDS by coalesced loads, and every merged
+// bin reads them there instead of through the caches, its constants loaded
+// once for the workgroup's walkers; thread i takes merged bins i,
+// i + kBlock, ... in turn, and each walker's fixed-order workgroup sum goes
+// to its slot K1.  `sd` is the dynamic LDS, cross_wg x T1 x C double2.
 template <bool DH>
-__device__ __forceinline__ void pm_walker_cross(const WorkItem &it, int64_t w, double2 *sd) {
+__device__ __forceinline__ void pm_walker_cross(const WorkItem &it, int64_t w0, double2 *sd) {
   __shared__ double sh[3 * kWaves];
-  double val[4] = {0.0, 0.0, 0.0, 0.0};
-  if (it.wc[w].valid) {  // uniform over the workgroup
-    const int n = it.pm.T1 * 3;
-    const auto *D = as_global((const dvec2 *)(it.pm.dsc + w * n));
-    dvec2 *S = (dvec2 *)sd;
-    for (int i = threadIdx.x; i < n; i += kBlock) S[i] = D[i];
-    __syncthreads();
-    const dvec2 *Sc = S;
-    for (int mu = threadIdx.x; mu < it.pm.T2; mu += kBlock) pm_cross_bin<DH>(it, mu, Sc, val);
+  const int nw = it.pm.cross_wg;
+  const int n = it.pm.T1 * 3;
+  bool on[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) on[k] = k < nw && w0 + k < it.W && it.wc[w0 + k].valid;  // uniform
+  dvec2 *S = (dvec2 *)sd;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    if (!on[k]) continue;
+    const auto *D = as_global((const dvec2 *)(it.pm.dsc + (w0 + k) * n));
+    for (int i = threadIdx.x; i < n; i += kBlock) S[k * n + i] = D[i];
   }
-  block_sum<3>(val, sh);
-  if (threadIdx.x == 0) {
-    double *o = it.part + (w * it.K + it.K1) * 4;
-    o[0] = val[0];
-    o[1] = val[1];
-    o[2] = val[2];
-    o[3] = 0.0;
+  __syncthreads();
+  double val[2][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+  if (on[0] || on[1]) {
+    const dvec2 *Sc = S;
+    for (int mu = threadIdx.x; mu < it.pm.T2; mu += kBlock) {
+      const PmBinC b = pm_bin_consts(it, mu);
+      if (on[0]) pm_cross_terms<DH>(b, Sc, val[0]);
+      if (on[1]) pm_cross_terms<DH>(b, Sc + n, val[1]);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    if (k >= nw || w0 + k >= it.W) break;  // uniform
+    block_sum<3>(val[k], sh);
+    if (threadIdx.x == 0) {
+      double *o = it.part + ((w0 + k) * it.K + it.K1) * 4;
+      o[0] = val[k][0];
+      o[1] = val[k][1];
+      o[2] = val[k][2];
+      o[3] = 0.0;
+    }
   }
 }
 
@@ -1453,11 +1488,12 @@ __global__ __launch_bounds__(kBlock, 2) void k_pm_cross(WorkItem one, int64_t n_
   const int64_t c = (int64_t)blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (c < n_chunks) pm_chunk_cross<DH>(one, c);
 }
-// one workgroup per walker (blockIdx.x); dynamic LDS of T1 x C double2
+// one workgroup per pm.cross_wg walkers (from blockIdx.x cross_wg); dynamic
+// LDS of cross_wg x T1 x C double2
 template <bool DH>
 __global__ __launch_bounds__(kBlock) void k_pm_cross_wg(WorkItem one) {
   extern __shared__ double2 pm_sd[];
-  pm_walker_cross<DH>(one, blockIdx.x, pm_sd);
+  pm_walker_cross<DH>(one, (int64_t)blockIdx.x * one.pm.cross_wg, pm_sd);
 }
 
 }  // namespace mbh

@@ -1302,9 +1302,9 @@ int lanes_lookup(const mbh_ctx *ctx, int n_bins, int n_modes, int prec) {
 // tol^2 / (8 kMixedErrScale^2), shared among its segments by bin count
 void set_error_limits(WorkItem &it, double tol) { it.est_lim = tol * tol / (8.0 * kMixedErrScale * kMixedErrScale); }
 
-// dynamic LDS of the per-walker cross pass of per-mode reference r: the
-// walker's deltas, T1 x C complex values; the kernel's static block-sum
-// array takes at most kPmCrossStaticLds beside it
+// dynamic LDS of the per-walker cross pass of per-mode reference r, per
+// walker: its deltas, T1 x C complex values; the kernel's static block-sum
+// array takes at most kPmCrossStaticLds beside them
 size_t pm_cross_lds(const mbh_ref *r) { return (size_t)r->pm_T1 * 3 * sizeof(double2); }
 constexpr size_t kPmCrossStaticLds = 256;
 
@@ -1323,7 +1323,10 @@ WorkItem make_item(const mbh_ctx *ctx, const mbh_ref *r, int G) {
     it.E = r->pm_T1;
     it.K1 = flat_slots(r->pm_T1);
     it.E2 = r->pm_T2 + 1;
-    it.pm.cross_wg = r->pm_T2 > 0 && pm_cross_lds(r) + kPmCrossStaticLds <= ctx->lds_max ? 1 : 0;
+    // two walkers per workgroup while their deltas stay within 64 KB of LDS
+    // (the merged-bin constants then load once for both), else one if it fits
+    if (r->pm_T2 > 0 && pm_cross_lds(r) + kPmCrossStaticLds <= ctx->lds_max)
+      it.pm.cross_wg = 2 * pm_cross_lds(r) + kPmCrossStaticLds <= std::min(ctx->lds_max, (size_t)65536) ? 2 : 1;
     it.K = it.K1 + (it.pm.cross_wg ? 1 : flat_slots(it.E2));
     it.pm.mode_of = r->pm_mode_of;
     it.pm.bin_of = r->pm_bin_of;
@@ -1423,8 +1426,9 @@ static mbh_status pm_launch(const WorkItem &it, hipStream_t st) {
   hipLaunchKernelGGL(k_setup_one, dim3((unsigned)((it.W + 63) / 64)), dim3(128), 0, st, it);
   const int64_t n1 = flat_chunks(it.W, it.E), n2 = flat_chunks(it.W, it.E2);
   const dim3 g1((unsigned)((n1 + kWaves - 1) / kWaves)), g2((unsigned)((n2 + kWaves - 1) / kWaves));
-  const dim3 gw((unsigned)it.W);
-  const size_t lds = (size_t)it.pm.T1 * 3 * sizeof(double2);
+  const int nw = std::max(it.pm.cross_wg, 1);
+  const dim3 gw((unsigned)((it.W + nw - 1) / nw));
+  const size_t lds = (size_t)nw * it.pm.T1 * 3 * sizeof(double2);
   if (it.dhhh) {
     hipLaunchKernelGGL(k_pm_edges<true>, g1, dim3(kBlock), 0, st, it, n1);
     if (it.pm.cross_wg) hipLaunchKernelGGL(k_pm_cross_wg<true>, gw, dim3(kBlock), lds, st, it);

@@ -71,7 +71,7 @@ static double tile_cost(double work, const mbh_ref *r) {
 }
 
 static void append_tiles(std::vector<WorkTile> &tiles, std::vector<double> &cost, int item, const mbh_ref *r,
-                         int G, int64_t W, bool cross_wg = false) {
+                         int G, int64_t W, int cross_wg = 0) {
   const int E = r->n_bins + 1;
   const int nm = popcount_modes(r->modes ? r->modes : 1u);
   if (W <= 0) return;
@@ -81,8 +81,8 @@ static void append_tiles(std::vector<WorkTile> &tiles, std::vector<double> &cost
       tiles.push_back(WorkTile{item, kPmEdgeTiles, c});
       cost.push_back(tile_cost(1.0, r));
     }
-    if (cross_wg) {  // one workgroup per walker
-      for (int64_t w = 0; w < W; ++w) {
+    if (cross_wg > 0) {  // one workgroup per cross_wg walkers
+      for (int64_t w = 0; w < W; w += cross_wg) {
         tiles.push_back(WorkTile{item, kPmCrossWgTiles, w});
         cost.push_back(tile_cost(1.0, r));
       }
@@ -155,7 +155,8 @@ static std::vector<TileGroup> order_tiles(std::vector<WorkTile> &tiles, const st
       groups.push_back(TileGroup{tiles[i].G, h, p, (int64_t)i, 0});
     groups.back().count += 1;
     if (tiles[i].G == kPmCrossWgTiles)
-      groups.back().lds = std::max(groups.back().lds, (size_t)items[tiles[i].item].pm.T1 * 3 * sizeof(double2));
+      groups.back().lds = std::max(groups.back().lds, (size_t)items[tiles[i].item].pm.cross_wg *
+                                                          items[tiles[i].item].pm.T1 * 3 * sizeof(double2));
   }
   return groups;
 }
@@ -381,7 +382,7 @@ extern "C" mbh_status mbh_batch_create_prec(mbh_ctx *ctx, int n, const mbh_ref *
       it.pm.dsc = dsc + dsc_off;
       dsc_off += (size_t)W[i] * refs[i]->pm_T1 * 3;
     }
-    append_tiles(tiles, cost, i, refs[i], it.G, W[i], it.pm.cross_wg != 0);
+    append_tiles(tiles, cost, i, refs[i], it.G, W[i], it.pm.cross_wg);
     append_wtiles(wtiles, i, it);
     off += W[i];
   }
