@@ -58,7 +58,7 @@ ALGO_FULL_FLOPS_PER_POINT = 250.0
 # their reading for a 64 MiB device copy: factors 0.5002 and 1.000).  Valid
 # only for the kernel sources they were measured on (sha256 over
 # KERNEL_SOURCES); reported as null otherwise.
-COUNTERS = {"src_sha256": "4aeaf217a9a090466d51ab493a6d53bbb0c36353b77daeaa200f185a93d7acd8",
+COUNTERS = {"src_sha256": "17bbbc549db901cc88ac28f6f2325a6d2a5d878639a571fba0855cc90e2ce08d",
             "valu_flops_per_edge": 850.7, "full_valu_flops_per_point": 504.7, "bytes_per_launch": 5.495e6}
 
 

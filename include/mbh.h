@@ -189,9 +189,10 @@ mbh_status mbh_ref_export(const mbh_ref *ref, double *edges, int64_t *kb, double
  * mbh_ref_export (MBH_EINVAL); mbh_ref_get_info reports the total bin count
  * and the union of the bands.  A likelihood call over such a reference runs
  * an edge pass (every mode edge of every walker) and a cross pass (every
- * merged bin); the cross pass takes one workgroup per walker with the
- * walker's edge values staged in LDS (48 B per mode edge) when they fit the
- * LDS of one workgroup, else a chunked form; the environment variable
+ * merged bin); the cross pass takes one workgroup per walker, or per two
+ * walkers while their values stay within 64 KB, with the edge values staged
+ * in LDS (48 B per mode edge and walker) when they fit the LDS of one
+ * workgroup, else a chunked form; the environment variable
  * MBH_PM_CROSS_LDS_MAX (bytes), read by mbh_create, lowers that limit for
  * the context (0: always the chunked form).  Both forms give results within
  * the FP64 rounding of each other.

@@ -63,8 +63,8 @@ __global__ __launch_bounds__(kBlock, (HM && G == 0 && sizeof(R) == 4) ? 3 : 2) v
 // group is launched after every edge-pass group).
 constexpr int kPmEdgeTiles = 128;
 constexpr int kPmCrossTiles = 129;
-// and, for items whose cross pass takes one workgroup per walker, this, with
-// `begin` the walker
+// and, for items whose cross pass takes one workgroup per one or two walkers,
+// this, with `begin` the first of them
 constexpr int kPmCrossWgTiles = 130;
 
 template <bool DH, int PASS>

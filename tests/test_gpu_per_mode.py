@@ -194,7 +194,7 @@ def test_pm_edge_cases(M, ctx, case):
 
 
 def test_pm_cross_pass_both_forms(M, ctx, case, monkeypatch):
-    """The cross pass with one workgroup per walker (its deltas staged in
+    """The cross pass with one workgroup per one or two walkers (deltas staged in
     LDS, the default when they fit) and in chunks over the flattened
     (walker, merged bin) tasks (taken when a walker's deltas exceed the LDS
     of a workgroup; forced here for a second context by
